@@ -1,0 +1,220 @@
+"""One-dimensional operators of the DGSEM and the FV sub-cell maps (oracle).
+
+Test infrastructure: a plain, slow reference.  Only the tests, the smoke check
+and the benchmark's CPU-baseline leg use it.
+
+Everything here is computed in 40-digit arithmetic (mpmath) and rounded once
+to float64.
+
+* Legendre-Gauss-Lobatto nodes and weights, the Lagrange basis and its
+  nodal derivative matrix ``D_ij = l_j'(xi_i)`` (Section 3.1.1, the collocated
+  tensor-product DGSEM, eq. dgsem_abbrev).
+* The orthonormal Legendre Vandermonde ``V_Leg`` used by the modal indicator
+  (Section 3.4, eq. solution_expansion).
+* ``V^{N->M}``: interpolation to a higher degree; ``V^{M->N}``: the modal L2
+  projection to a lower degree (Section 3.2, the degree-change maps).
+* ``V^{DG->FV}``: sub-cell integral means of the Lagrange basis on an
+  equidistant ``N_FV`` grid, and ``V^{FV->DG}`` its pseudo-inverse
+  (Section 3.2, the DG/FV switching maps).
+* ``I^{face}``: the Lagrange basis evaluated at the ``N_FV + 1`` sub-cell
+  interfaces (used for sub-cell face normals).
+"""
+from __future__ import annotations
+
+import functools
+
+import mpmath as mp
+import numpy as np
+
+mp.mp.dps = 40
+
+
+def _legendre(n: int, x):
+    """P_n(x) and P_n'(x) by the three-term recurrence."""
+    if n == 0:
+        return mp.mpf(1), mp.mpf(0)
+    p0, p1 = mp.mpf(1), x
+    for k in range(2, n + 1):
+        p0, p1 = p1, ((2 * k - 1) * x * p1 - (k - 1) * p0) / k
+    # derivative from (x^2 - 1) P_n' = n (x P_n - P_{n-1})
+    if abs(x) == 1:
+        dp = mp.mpf(n * (n + 1)) / 2 * (x ** (n + 1))
+    else:
+        dp = n * (x * p1 - p0) / (x * x - 1)
+    return p1, dp
+
+
+@functools.lru_cache(maxsize=None)
+def lgl_mp(N: int):
+    """LGL nodes (ascending) and weights in mp precision."""
+    if N < 1:
+        raise ValueError("N >= 1")
+    x = [mp.mpf(-1)]
+    for j in range(1, N):
+        # interior nodes are the roots of P_N'; Newton from Chebyshev-Lobatto guesses
+        z = -mp.cos(mp.pi * j / N)
+        for _ in range(100):
+            p, dp = _legendre(N, z)
+            ddp = (2 * z * dp - N * (N + 1) * p) / (1 - z * z)
+            dz = dp / ddp
+            z -= dz
+            if abs(dz) < mp.mpf(10) ** (-38):
+                break
+        x.append(z)
+    x.append(mp.mpf(1))
+    w = []
+    for xi in x:
+        p, _ = _legendre(N, xi)
+        w.append(mp.mpf(2) / (N * (N + 1) * p * p))
+    return x, w
+
+
+def _bary_weights(x):
+    n = len(x)
+    return [1 / mp.fprod(x[j] - x[k] for k in range(n) if k != j) for j in range(n)]
+
+
+def _lagrange_row(x, t):
+    """[l_0(t), ..., l_N(t)] for nodes x."""
+    n = len(x)
+    row = []
+    for j in range(n):
+        v = mp.mpf(1)
+        for k in range(n):
+            if k != j:
+                v *= (t - x[k]) / (x[j] - x[k])
+        row.append(v)
+    return row
+
+
+def _f64(rows) -> np.ndarray:
+    return np.array([[float(v) for v in r] for r in rows], dtype=np.float64)
+
+
+@functools.lru_cache(maxsize=None)
+def lgl(N: int):
+    """(nodes, weights) as float64 arrays."""
+    x, w = lgl_mp(N)
+    return np.array([float(v) for v in x]), np.array([float(v) for v in w])
+
+
+@functools.lru_cache(maxsize=None)
+def dmat_mp(N: int):
+    x, _ = lgl_mp(N)
+    bw = _bary_weights(x)
+    n = N + 1
+    D = [[mp.mpf(0)] * n for _ in range(n)]
+    for i in range(n):
+        for j in range(n):
+            if i != j:
+                D[i][j] = (bw[j] / bw[i]) / (x[i] - x[j])
+        D[i][i] = -mp.fsum(D[i][j] for j in range(n) if j != i)
+    return D
+
+
+@functools.lru_cache(maxsize=None)
+def dmat(N: int) -> np.ndarray:
+    """Nodal derivative matrix D_ij = l_j'(xi_i) (eq. dgsem_abbrev)."""
+    return _f64(dmat_mp(N))
+
+
+@functools.lru_cache(maxsize=None)
+def vleg_mp(N: int):
+    x, _ = lgl_mp(N)
+    rows = []
+    for xi in x:
+        r = []
+        for j in range(N + 1):
+            p, _ = _legendre(j, xi)
+            r.append(mp.sqrt(mp.mpf(2 * j + 1) / 2) * p)
+        rows.append(r)
+    return mp.matrix(rows)
+
+
+@functools.lru_cache(maxsize=None)
+def vleg(N: int) -> np.ndarray:
+    """V_Leg[i, j] = orthonormal Legendre polynomial j at LGL node i."""
+    m = vleg_mp(N)
+    return _f64(m.tolist())
+
+
+@functools.lru_cache(maxsize=None)
+def vleg_inv(N: int) -> np.ndarray:
+    """Nodal -> modal map (inverse of V_Leg)."""
+    return _f64((vleg_mp(N) ** -1).tolist())
+
+
+@functools.lru_cache(maxsize=None)
+def interp(N: int, M: int) -> np.ndarray:
+    """V^{N->M}[i, j] = l^N_j(xi^M_i): evaluate a degree-N nodal polynomial at degree-M nodes."""
+    xN, _ = lgl_mp(N)
+    xM, _ = lgl_mp(M)
+    return _f64([_lagrange_row(xN, t) for t in xM])
+
+
+@functools.lru_cache(maxsize=None)
+def project(M: int, N: int) -> np.ndarray:
+    """V^{M->N} for M > N: modal L2 truncation of a degree-M nodal polynomial to degree N."""
+    if M < N:
+        raise ValueError("projection needs M >= N")
+    trunc = mp.zeros(N + 1, M + 1)
+    for i in range(N + 1):
+        trunc[i, i] = 1
+    P = vleg_mp(N) * trunc * (vleg_mp(M) ** -1)
+    return _f64(P.tolist())
+
+
+def _poly_from_roots(roots):
+    """Monomial coefficients (ascending) of prod (t - r)."""
+    c = [mp.mpf(1)]
+    for r in roots:
+        nc = [mp.mpf(0)] * (len(c) + 1)
+        for k, ck in enumerate(c):
+            nc[k + 1] += ck
+            nc[k] -= r * ck
+        c = nc
+    return c
+
+
+def _integral(coef, a, b):
+    return mp.fsum(ck * (b ** (k + 1) - a ** (k + 1)) / (k + 1) for k, ck in enumerate(coef))
+
+
+@functools.lru_cache(maxsize=None)
+def dg2fv_mp(N: int, NFV: int):
+    x, _ = lgl_mp(N)
+    h = mp.mpf(2) / NFV
+    rows = []
+    for s in range(NFV):
+        a, b = -1 + s * h, -1 + (s + 1) * h
+        r = []
+        for j in range(N + 1):
+            others = [x[k] for k in range(N + 1) if k != j]
+            scale = mp.fprod(x[j] - xk for xk in others)
+            r.append(_integral(_poly_from_roots(others), a, b) / scale / h)
+        rows.append(r)
+    return mp.matrix(rows)
+
+
+@functools.lru_cache(maxsize=None)
+def dg2fv(N: int, NFV: int) -> np.ndarray:
+    """V^{DG->FV}[s, j]: mean of l_j over sub-cell s of width h = 2/NFV."""
+    return _f64(dg2fv_mp(N, NFV).tolist())
+
+
+@functools.lru_cache(maxsize=None)
+def fv2dg(N: int, NFV: int) -> np.ndarray:
+    """V^{FV->DG}: Moore-Penrose pseudo-inverse of V^{DG->FV} (NFV >= N+1)."""
+    if NFV < N + 1:
+        raise ValueError("NFV >= N+1 required")
+    V = dg2fv_mp(N, NFV)
+    P = ((V.T * V) ** -1) * V.T
+    return _f64(P.tolist())
+
+
+@functools.lru_cache(maxsize=None)
+def face_interp(N: int, NFV: int) -> np.ndarray:
+    """I[q, j] = l_j(-1 + q h), q = 0..NFV: basis values at the sub-cell interfaces."""
+    x, _ = lgl_mp(N)
+    h = mp.mpf(2) / NFV
+    return _f64([_lagrange_row(x, -1 + q * h) for q in range(NFV + 1)])
