@@ -1,0 +1,215 @@
+"""Throughput of the hybrid DG/FV right-hand side on one MI355X.
+
+A step is one five-stage low-storage Runge-Kutta step (five ``dg_rk_stage``
+calls: face fluxes, FV sub-cell operator on blended elements, split-form
+volume integral, lift, blend and the stage update) over the whole mesh.  The
+reported value is DOF-updates per second per RK stage:
+``n_dof * 5 * steps / t``, with the state already resident in HBM.
+
+Workload (default): 64^3 periodic hexahedra, uniform degree N = 7
+(512 LGL nodes per element, 1.34e8 DOFs x 5 variables), FP64, a
+Kelvin-Helmholtz shear layer, 10 % of the elements FV-blended (the lowest
+indicator values, seeded tie-break), Ranocha volume flux, Roe + Harten-Hyman
+at DG faces, local Lax-Friedrichs at FV faces.
+
+Prints one JSON line.  ``--gpus`` above 1 is rejected: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0      # MI355X HBM3E
+METRIC = "FP64 DOF-updates/s per RK stage on 1 GPU"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="C5", choices=["C1", "C2", "C3", "C4", "C5"])
+    ap.add_argument("--n", type=int, default=None, help="elements per direction (default: the config's)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-n", type=int, default=8, help="elements per direction of the oracle sample")
+    return ap.parse_args()
+
+
+def blend_mask(ind: np.ndarray, fraction: float, seed: int) -> np.ndarray:
+    """The ``fraction`` of elements with the lowest indicator, ties broken by a seeded permutation."""
+    rng = np.random.default_rng(seed)
+    tie = rng.permutation(ind.size)
+    order = np.lexsort((tie, ind))
+    k = int(math.ceil(fraction * ind.size))
+    m = np.zeros(ind.size, dtype=bool)
+    m[order[:k]] = True
+    return m
+
+
+def initial_state_device(gm, wl, dgfv, torch, chunk=1 << 23):
+    """Sample the workload's primitive state at the library's nodes, chunk by chunk, on the device."""
+    xyz = gm.node_coords()
+    u = torch.empty((wl.n_var, gm.n_node), dtype=torch.float64, device="cuda")
+    for a in range(0, gm.n_node, chunk):
+        b = min(gm.n_node, a + chunk)
+        w = wl.prim(np.ascontiguousarray(xyz[:, a:b].T))[: wl.n_var]
+        c = dgfv.prim_to_cons(w, wl.n_var, wl.gamma, wl.kappa, wl.R)
+        u[:, a:b] = torch.from_numpy(np.ascontiguousarray(c)).to("cuda")
+    del xyz
+    return u
+
+
+def element_kernel_bytes(wl, n_dof: int, n_elem_by_deg: dict, blended_dofs: int, stage: int) -> float:
+    """Algorithmic HBM bytes of one element-kernel launch (all buckets of one stage).
+
+    Per node: u read + write, k read (not at stage 1) + write, 9 metric terms
+    and J; per element 6 (N+1)^2 nvar side fluxes; per blended node the FV
+    residual (nvar).
+    """
+    nv = wl.n_var
+    per_node = 8 * (2 * nv + (nv if stage > 1 else 0) + nv + 10)
+    side = sum(8 * 6 * (N + 1) ** 2 * nv * cnt for N, cnt in n_elem_by_deg.items())
+    return float(per_node * n_dof + side + 8 * nv * blended_dofs)
+
+
+def cpu_baseline(cfg: str, n: int, seed: int):
+    """Time the CPU oracle (as it stands) on a small mesh of the same configuration."""
+    import torch
+
+    from oracle import lsrk, problem
+    from paper_2502_19342_amd import workloads as W
+
+    wl = W.make_workload(cfg, n=n)
+    mesh, gas, f = problem.build(wl)
+    u = problem.initial_state(mesh, gas, wl.prim)
+    alpha = torch.zeros(mesh.K, dtype=torch.float64)
+    if wl.blend_fraction:
+        alpha[torch.as_tensor(blend_mask(np.zeros(mesh.K), wl.blend_fraction, seed))] = 1.0
+    dt = 1e-4
+    k = torch.zeros_like(u)
+    lsrk.stage(lambda v: f(v, alpha), u, k, 0, dt)          # warm-up
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        u, k = lsrk.stage(lambda v: f(v, alpha), u, k, reps % 5, dt)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el > 12.0 or reps >= 50:
+            break
+    return {"value": mesh.n_node * reps / el, "unit": "DOF-updates/s", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": f"{reps} RK stages of the same configuration on {n}^3 elements ({mesh.n_node} DOFs), "
+                      f"{el:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build measures one GPU; --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2502_19342_amd import dgfv
+    from paper_2502_19342_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    t_setup = time.perf_counter()
+    wl = W.make_workload(args.config, n=args.n)
+    gm = dgfv.Mesh.from_workload(wl)
+    prm = dgfv.params_of(wl)
+    u = initial_state_device(gm, wl, dgfv, torch)
+    k = torch.zeros_like(u)
+    n_dof = gm.n_node
+    degs, cnts = np.unique(wl.mesh.degree, return_counts=True)
+    n_by_deg = {int(d): int(c) for d, c in zip(degs, cnts)}
+
+    # blending factors: indicator on the initial state, then the lowest-I fraction is blended
+    blend_frac = wl.blend_fraction
+    if blend_frac:
+        ind_prm = dgfv.Params(prm.volume_flux, prm.face_flux_dg, prm.face_flux_fv, 1 | 2, prm.ind_T, prm.ind_dT)
+        _, ind = dgfv.indicator(gm, ind_prm, u)
+        mask = blend_mask(ind.cpu().numpy(), blend_frac, wl.seed)
+        alpha = torch.as_tensor(mask.astype(np.float64), device="cuda")
+    else:
+        alpha, _ = dgfv.indicator(gm, prm, u)
+        mask = alpha.cpu().numpy() > 0
+    npe = (wl.mesh.degree.astype(np.int64) + 1) ** 3
+    blended_dofs = int(npe[mask].sum())
+    dt = 1e-5
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
+    print(f"[bench] {args.config}: {wl.mesh.n_elem} elements, {n_dof} DOFs, blended {mask.mean():.3f}, "
+          f"setup {t_setup:.1f} s", file=sys.stderr, flush=True)
+
+    for _ in range(args.warmup):
+        dgfv.rk_step(gm, prm, dt, u, k, alpha)
+    torch.cuda.synchronize()
+    gm.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        dgfv.rk_step(gm, prm, dt, u, k, alpha)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    kt = {name: gm.kernel_time(kid) for name, kid in
+          (("element", dgfv.KERNEL_ELEMENT), ("face", dgfv.KERNEL_FACE), ("fv_means", dgfv.KERNEL_FV_MEANS),
+           ("fv_residual", dgfv.KERNEL_FV_RESIDUAL))}
+    gm.profile(False)
+    if not torch.isfinite(u).all():
+        print("bench.py: non-finite state after the timed steps", file=sys.stderr)
+        sys.exit(1)
+
+    stages = 5 * args.steps
+    value = n_dof * stages / el
+    el_ms, el_n = kt["element"]
+    avg_el_s = el_ms / el_n / 1e3
+    byts = np.mean([element_kernel_bytes(wl, n_dof, n_by_deg, blended_dofs, s) for s in range(1, 6)])
+    achieved = byts / avg_el_s / 1e9
+    rec = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * el / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.config}: {wl.mesh.n}^3 periodic hexahedra, degrees "
+                        f"{sorted(n_by_deg)}, {n_dof} DOFs x {wl.n_var} variables, "
+                        f"{100 * mask.mean():.1f}% of elements FV-blended (N_FV={wl.n_fv}), "
+                        f"5-stage 2N RK steps",
+            "n_elem": wl.mesh.n_elem, "n_dof": n_dof, "n_var": wl.n_var,
+            "volume_flux": ["ranocha", "pirozzoli", "central"][wl.volume_flux],
+            "blended_fraction": float(mask.mean()),
+        },
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "kernel": "element_kernel (volume + lift + blend + RK update)",
+                     "bytes_per_launch": byts, "avg_launch_ms": 1e3 * avg_el_s},
+        "kernel_ms_per_stage": {kname: v[0] / max(1, v[1]) for kname, v in kt.items()},
+        "adjoint_forward_ratio": None,
+    }
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(args.config, args.cpu_sample_n, wl.seed)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

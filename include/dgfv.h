@@ -1,0 +1,182 @@
+/*
+ * dgfv.h - C ABI of the MI355X (gfx950) hybrid DG/FV right-hand side.
+ *
+ * The library evaluates, in FP64 on one GPU, the semi-discrete operator of the
+ * hp-adaptive hybrid discontinuous-Galerkin / finite-volume scheme of
+ * arXiv 2502.19342 (Section 3): per element e with degree N_e and blending
+ * factor alpha_e in [0, 1]
+ *
+ *     d u_e / dt = R_e(u) = (1 - alpha_e) R^DG_e(u) + alpha_e R^FV_e(u)
+ *
+ * where R^DG is the split-form DGSEM of eq. semidiscrete (flux differencing
+ * with a two-point flux on LGL nodes, Section 3.5) with Riemann fluxes and the
+ * surface lift at element faces, and R^FV the sub-cell finite-volume operator
+ * of eq. semidiscrete_fv reached through the V^{DG->FV} / V^{FV->DG} maps
+ * (Section 3.2).  Faces between elements of different degree use the
+ * interpolation V^{N->M} / modal projection V^{M->N} of Section 3.2.1.
+ * Only the inviscid (Euler) part of eq. ns_equation is implemented, for one
+ * species (n_var = 5) or two ideal-gas species (n_var = 6, eq. mix_R_kappa).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Device pointers (suffix _d) are HIP device pointers to contiguous FP64
+ *   memory owned by the caller.  The library never frees them and keeps no
+ *   reference to them after the call returns.
+ * - State layout (structure of arrays):
+ *       u[v * n_node + elem_offset[e] + (k * (N_e+1) + j) * (N_e+1) + i]
+ *   v = 0..n_var-1 over (rho, rho v1, rho v2, rho v3, rho e[, rho Y1]),
+ *   (i, j, k) the LGL node indices along xi1, xi2, xi3, elem_offset[e] the
+ *   prefix sum of (N_e+1)^3 in element order (dgfv_mesh_info).
+ * - `stream` is a hipStream_t (NULL = the default stream).  Compute calls
+ *   only enqueue work; they return before it finishes.  Faults inside kernels
+ *   surface at the caller's next synchronisation, as HIP defines.
+ * - Every call returns a status; no C++ exception crosses the ABI.  Argument
+ *   errors are detected synchronously and leave all buffers untouched.
+ *   dgfv_last_error() gives a text for the last non-OK status of the thread.
+ * - A mesh object owns scratch buffers: calls on one mesh must not overlap
+ *   (use one stream per mesh, or synchronise).
+ */
+#ifndef DGFV_H
+#define DGFV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dgfv_mesh dgfv_mesh; /* opaque; owns device geometry and scratch */
+
+typedef enum {
+  DGFV_OK = 0,
+  DGFV_ERR_ARG = 1,         /* invalid argument (null pointer, range, shape)   */
+  DGFV_ERR_UNSUPPORTED = 2, /* valid but not implemented (degree, flux combo)  */
+  DGFV_ERR_HIP = 3,         /* a HIP runtime call failed                       */
+  DGFV_ERR_OOM = 4,         /* device allocation failed                        */
+  DGFV_ERR_STATE = 5        /* non-physical state (rho <= 0, p <= 0 or NaN)   */
+} dgfv_status;
+
+/* Two-point volume fluxes (Section 3.5). */
+enum { DGFV_VOL_RANOCHA = 0,   /* entropy-conserving + kinetic-energy-preserving, 1 species */
+       DGFV_VOL_PIROZZOLI = 1, /* kinetic-energy-preserving flux of Pirozzoli                */
+       DGFV_VOL_CENTRAL = 2 }; /* arithmetic mean of the physical fluxes                     */
+/* Numerical (Riemann) fluxes at faces (eq. conv_flux). */
+enum { DGFV_RIEMANN_ROE_HH = 0, /* Roe with the Harten-Hyman entropy fix, 1 species */
+       DGFV_RIEMANN_LLF = 1,    /* local Lax-Friedrichs                              */
+       DGFV_RIEMANN_EC = 2 };   /* the volume two-point flux used at the face        */
+
+/*
+ * Mesh description (host arrays, copied by dgfv_mesh_create).
+ * Geometry: trilinear hexahedra.  corners[e][c][3] with corner c at local
+ * reference coordinates xi_d = -1 + 2 * bit_d(c) (bit 0 -> xi1, 1 -> xi2, 2 -> xi3).
+ * Faces: faces[f] = {eL, sideL, eR, sideR, orient}; side s is xi_{s/2} = -1 (s even)
+ * or +1 (s odd).  A face grid index (p, q) runs p along the lower tangential
+ * reference direction, q along the higher one.  `orient` maps the left
+ * side's (p, q) on an n x n grid to the right side's (p', q'): (a, b) = (q, p)
+ * if bit 2 is set, else (p, q); then p' = n-1-a if bit 0, else a; q' = n-1-b
+ * if bit 1, else b.  Every element side must appear in exactly one face
+ * (periodic, conforming meshes).
+ * Metrics are formed in the conservative curl form at degree metric_degree
+ * (<= min N_e) and interpolated to each element's degree (Section 3.1.1).
+ */
+typedef struct {
+  int32_t n_elem;
+  int32_t n_var;           /* 5 (Euler) or 6 (two species, rho*Y1 last) */
+  const int8_t* degree;    /* [n_elem], 1..7                            */
+  const double* corners;   /* [n_elem][8][3]                            */
+  int32_t n_face;
+  const int32_t* faces;    /* [n_face][5]                               */
+  int32_t n_fv;            /* FV sub-cells per direction, max(N_e)+1 .. 8 */
+  int32_t metric_degree;   /* N_J, 1 <= N_J <= min(N_e)                 */
+  double gamma;            /* ratio of specific heats, n_var = 5        */
+  double kappa[2];         /* species heat-capacity ratios, n_var = 6   */
+  double R[2];             /* species gas constants, n_var = 6          */
+} dgfv_mesh_desc;
+
+typedef struct {
+  int32_t volume_flux;     /* DGFV_VOL_*                                           */
+  int32_t face_flux_dg;    /* DGFV_RIEMANN_* at faces between two DG (alpha=0) sides */
+  int32_t face_flux_fv;    /* DGFV_RIEMANN_* at FV faces and inside sub-cell grids   */
+  int32_t ind_vars;        /* indicator variables: bit 0 p, bit 1 rho, bit 2 Y1    */
+  double ind_T;            /* blending ramp centre on the indicator I              */
+  double ind_dT;           /* blending ramp half-width (> 0)                       */
+} dgfv_params;
+
+/* Build the device geometry of a mesh (synchronous; allocates device memory). */
+dgfv_status dgfv_mesh_create(const dgfv_mesh_desc* desc, dgfv_mesh** out);
+void dgfv_mesh_destroy(dgfv_mesh* mesh);
+
+/* Node count and (optionally, host array of n_elem+1) element node offsets. */
+dgfv_status dgfv_mesh_info(const dgfv_mesh* mesh, int64_t* n_node, int64_t* elem_offset);
+
+/* Physical node coordinates, host array [3][n_node] (synchronous). */
+dgfv_status dgfv_mesh_node_coords(const dgfv_mesh* mesh, double* xyz);
+
+/*
+ * Modal decay indicator (Section 3.4, eq. modal_contribution .. eq. modal_indicator)
+ * and blending factor.  Per element: the variables selected by params->ind_vars
+ * are transformed to the orthonormal Legendre basis; the share w_m of mode m
+ * per direction is fitted by a least-squares line through (m, ln max(w_m, 1e-30)),
+ * I = min over directions (and variables) of |slope|; energies below 1e-300 give
+ * I = +inf.  alpha = 1 for I <= T - dT, 0 for I >= T + dT, and
+ * (1 - sin(pi (I - T) / (2 dT))) / 2 between.
+ * alpha_d: [n_elem] output.  ind_d: [n_elem] output, may be NULL.
+ */
+dgfv_status dg_indicator(const dgfv_mesh* mesh, const dgfv_params* params, const double* u_d,
+                         double* alpha_d, double* ind_d, void* stream);
+
+/*
+ * ut = R(u) with blending factors alpha (eq. semidiscrete, eq. semidiscrete_fv,
+ * Section 3.2).  alpha_d: [n_elem] in [0, 1]; NULL means all zero (pure DG).
+ * u_d, ut_d: [n_var][n_node]; they must not overlap.
+ */
+dgfv_status dg_rhs(const dgfv_mesh* mesh, const dgfv_params* params, const double* u_d,
+                   const double* alpha_d, double* ut_d, void* stream);
+
+/*
+ * One stage of the five-stage fourth-order 2N-storage Runge-Kutta scheme
+ * (Section 3.3; Carpenter-Kennedy coefficients A_s, B_s):
+ *     k <- A_s k + dt R(u),  u <- u + B_s k,   stage = 1..5.
+ * Stage 1 writes k = dt R(u) without reading k.  u_d and k_d are updated in
+ * place; alpha_d as for dg_rhs (frozen over the stages of a step).
+ */
+dgfv_status dg_rk_stage(const dgfv_mesh* mesh, const dgfv_params* params, int stage, double dt,
+                        double* u_d, double* k_d, const double* alpha_d, void* stream);
+
+/*
+ * Vector-Jacobian product of the right-hand side with alpha frozen:
+ *     g_b = (dR/du (u))^T w_b,  b = 0..batch-1,
+ * w_d, g_d: [batch][n_var][n_node]; alpha_d as for dg_rhs.  Derivatives at
+ * the switches of the Riemann solvers (entropy fix, max) are those of the
+ * branch taken.
+ */
+dgfv_status dg_rhs_vjp(const dgfv_mesh* mesh, const dgfv_params* params, const double* u_d,
+                       const double* alpha_d, const double* w_d, double* g_d, int batch,
+                       void* stream);
+
+/*
+ * Kernel timing with HIP events (measurement support, not part of the method).
+ * dgfv_profile_enable(mesh, 1) clears the counters and makes every later call
+ * on the mesh record an event pair around each launch of the kernels below,
+ * on the caller's stream; 0 stops recording.  dgfv_profile_read synchronises
+ * the recorded events and returns the summed duration (ms) and the launch
+ * count of one kernel class.
+ */
+enum { DGFV_KERNEL_ELEMENT = 0, /* volume + lift + blend (+ RK update), all degree buckets */
+       DGFV_KERNEL_FACE = 1,    /* interface fluxes                                      */
+       DGFV_KERNEL_FV_MEANS = 2,
+       DGFV_KERNEL_FV_RESIDUAL = 3,
+       DGFV_KERNEL_INDICATOR = 4,
+       DGFV_KERNEL_VJP = 5,
+       DGFV_KERNEL_COUNT = 6 };
+dgfv_status dgfv_profile_enable(dgfv_mesh* mesh, int enable);
+dgfv_status dgfv_profile_read(dgfv_mesh* mesh, int kernel, double* total_ms, int64_t* launches);
+
+/* Text of the last non-OK status returned to this thread. */
+const char* dgfv_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DGFV_H */

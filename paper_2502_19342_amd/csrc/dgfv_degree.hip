@@ -1,0 +1,469 @@
+// Per-degree kernels of the hybrid DG/FV right-hand side.  This translation
+// unit is compiled once per element degree with -DDGFV_N=<N>.
+//
+//  element_kernel  split-form DGSEM volume term (flux differencing, Section 3.5),
+//                  surface lift (eq. semidiscrete), blend with the FV residual,
+//                  and optionally the fused 2N Runge-Kutta stage (Section 3.3)
+//  fv_means        J-weighted sub-cell means of blended elements (V^{DG->FV}, Section 3.2)
+//  fv_residual     first-order FV sub-cell operator (eq. semidiscrete_fv) mapped
+//                  back with V^{FV->DG}
+//  indicator       modal decay indicator and blending ramp (Section 3.4)
+#include "dgfv_internal.h"
+#include "dgfv_physics.h"
+#include "dgfv_lds.h"
+
+#ifndef DGFV_N
+#error "compile with -DDGFV_N=<degree>"
+#endif
+
+namespace dgfv {
+namespace {
+
+constexpr int kN = DGFV_N;
+
+template <int N>
+struct Geo {
+  static constexpr int NP = N + 1, NP2 = NP * NP, NP3 = NP2 * NP;
+  // elements per workgroup of the element kernel: fill about 512 lanes
+  static constexpr int EPB = NP3 >= 256 ? 1 : (512 / NP3 > 64 ? 64 : 512 / NP3);
+};
+
+// ---------------------------------------------------------------------------
+// element kernel
+// ---------------------------------------------------------------------------
+template <int N, int NV, class FLUX>
+__global__ void __launch_bounds__(Geo<N>::EPB * Geo<N>::NP3)
+element_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const double* u,
+               const double* __restrict__ alpha, double* __restrict__ ut, double* k, int stage,
+               double dt, double A, double B) {
+  using G = Geo<N>;
+  constexpr int NP = G::NP, NP2 = G::NP2, NP3 = G::NP3, EPB = G::EPB;
+  constexpr int NA = FLUX::NA;
+  __shared__ double sD[NP * NP];
+  __shared__ double sAux[EPB][NA][NP3];
+  __shared__ double sJa[EPB][9][NP3];
+
+  const int tid = threadIdx.x;
+  const int slot = tid / NP3;
+  const int node = tid - slot * NP3;
+  const int idx = blockIdx.x * EPB + slot;
+  const bool active = idx < count;
+
+  for (int t = tid; t < NP * NP; t += blockDim.x) sD[t] = 2.0 * m.ops[m.tab.D[N] + t];
+
+  int e = 0;
+  int64_t base = 0;
+  double uo[NV];
+  double invJ = 0.0;
+  if (active) {
+    e = elist[idx];
+    base = m.elem_offset[e] + node;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) uo[v] = u[v * m.n_node + base];
+    const Prim q = cons2prim<NV>(uo, m.gas);
+    double r[NA];
+    FLUX::template make<NV>(q, r);
+#pragma unroll
+    for (int a = 0; a < NA; ++a) sAux[slot][a][node] = r[a];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) sJa[slot][c][node] = m.metric[c * m.n_node + base];
+    invJ = 1.0 / m.metric[9 * m.n_node + base];
+  }
+  __syncthreads();
+  if (!active) return;
+
+  const int i = node % NP, j = (node / NP) % NP, kk = node / NP2;
+  double acc[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+
+  double me[NA];
+#pragma unroll
+  for (int a = 0; a < NA; ++a) me[a] = sAux[slot][a][node];
+
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int id = d == 0 ? i : (d == 1 ? j : kk);
+    const int stride = d == 0 ? 1 : (d == 1 ? NP : NP2);
+    const double ja1 = sJa[slot][3 * d + 0][node];
+    const double ja2 = sJa[slot][3 * d + 1][node];
+    const double ja3 = sJa[slot][3 * d + 2][node];
+#pragma unroll 1
+    for (int o = 1; o < NP; ++o) {
+      int mm = id + o;
+      if (mm >= NP) mm -= NP;
+      const int pn = node + (mm - id) * stride;
+      double other[NA];
+#pragma unroll
+      for (int a = 0; a < NA; ++a) other[a] = sAux[slot][a][pn];
+      const double a1 = 0.5 * (ja1 + sJa[slot][3 * d + 0][pn]);
+      const double a2 = 0.5 * (ja2 + sJa[slot][3 * d + 1][pn]);
+      const double a3 = 0.5 * (ja3 + sJa[slot][3 * d + 2][pn]);
+      double f[NV];
+      FLUX::template flux<NV>(me, other, a1, a2, a3, m.gas, f);
+      const double c = sD[id * NP + mm];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) acc[v] += c * f[v];
+    }
+  }
+
+  // surface lift: outward numerical flux over the end weight on boundary nodes
+  const double inv_w0 = 1.0 / m.ops[m.tab.w[N]];
+  const double* fs = m.fside + m.side_off[e];
+  auto add_side = [&](int s, int fidx) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] += fs[(s * NV + v) * NP2 + fidx] * inv_w0;
+  };
+  if (i == 0) add_side(0, kk * NP + j);
+  if (i == N) add_side(1, kk * NP + j);
+  if (j == 0) add_side(2, kk * NP + i);
+  if (j == N) add_side(3, kk * NP + i);
+  if (kk == 0) add_side(4, j * NP + i);
+  if (kk == N) add_side(5, j * NP + i);
+
+  double R[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) R[v] = -acc[v] * invJ;
+
+  const double al = alpha ? alpha[e] : 0.0;
+  if (al > 0.0) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) R[v] = (1.0 - al) * R[v] + al * m.rfv[v * m.n_node + base];
+  }
+
+  if (stage == 0) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) ut[v * m.n_node + base] = R[v];
+  } else {
+    double* uw = const_cast<double*>(u);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int64_t g = v * m.n_node + base;
+      const double kv = (stage == 1) ? dt * R[v] : A * k[g] + dt * R[v];
+      k[g] = kv;
+      uw[g] = uo[v] + B * kv;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// sub-cell means of blended elements: ubar = V3(J u) / V3(J)
+// ---------------------------------------------------------------------------
+constexpr int FV_THREADS = 256;
+
+template <int N, int NV>
+__global__ void __launch_bounds__(FV_THREADS)
+fv_means_kernel(MeshView m, const int32_t* __restrict__ elist, int count,
+                const double* __restrict__ u, const double* __restrict__ alpha) {
+  constexpr int NP = N + 1, NP3 = NP * NP * NP;
+  constexpr int NF = NV + 1;                  // J*u (NV fields) and J
+  constexpr int CAP = NF * MAXFV * MAXFV * MAXFV;
+  __shared__ double bufA[CAP];
+  __shared__ double bufB[CAP];
+  __shared__ double sV[MAXFV * (MAXN + 1)];
+  const int idx = blockIdx.x;
+  if (idx >= count) return;
+  const int e = elist[idx];
+  if (!(alpha[e] > 0.0)) return;
+  const int NFV = m.n_fv;
+  const int64_t base = m.elem_offset[e];
+  for (int t = threadIdx.x; t < NFV * NP; t += blockDim.x) sV[t] = m.ops[m.tab.dg2fv[N] + t];
+  for (int t = threadIdx.x; t < NP3; t += blockDim.x) {
+    const double J = m.metric[9 * m.n_node + base + t];
+    for (int v = 0; v < NV; ++v) bufA[v * NP3 + t] = J * u[v * m.n_node + base + t];
+    bufA[NV * NP3 + t] = J;
+  }
+  __syncthreads();
+  contract_axis(bufA, bufB, sV, NFV, NP, NF, NP, NP, NP, 0);
+  __syncthreads();
+  contract_axis(bufB, bufA, sV, NFV, NP, NF, NP, NP, NFV, 1);
+  __syncthreads();
+  contract_axis(bufA, bufB, sV, NFV, NP, NF, NP, NFV, NFV, 2);
+  __syncthreads();
+  const int S3 = NFV * NFV * NFV;
+  double* ub = m.ubar + (size_t)e * NV * S3;
+  for (int t = threadIdx.x; t < S3; t += blockDim.x) {
+    const double ivol = 1.0 / bufB[NV * S3 + t];
+    for (int v = 0; v < NV; ++v) ub[v * S3 + t] = bufB[v * S3 + t] * ivol;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FV sub-cell residual of blended elements, in nodal form:
+//   dC/dt = -(sum of outward sub-face fluxes),  R^FV = V3^+(dC/dt) / (h^3 J)
+// Sub-face normals: h^2 x mean of Ja^d over the sub-face (face_interp along d,
+// dg2fv along the tangential directions).
+// ---------------------------------------------------------------------------
+template <int N, int NV>
+__global__ void __launch_bounds__(FV_THREADS)
+fv_residual_kernel(MeshView m, ParamsDev prm, const int32_t* __restrict__ elist, int count,
+                   const double* __restrict__ alpha) {
+  constexpr int NP = N + 1, NP3 = NP * NP * NP;
+  constexpr int S3MAX = MAXFV * MAXFV * MAXFV;
+  __shared__ double sU[NV * S3MAX];          // sub-cell means
+  __shared__ double sC[NV * S3MAX];          // dC/dt accumulator, later scratch
+  __shared__ double sJa[9 * NP3];
+  __shared__ double sG[NV * (MAXFV + 1) * MAXFV * MAXFV];   // interface fluxes / normal scratch
+  __shared__ double sNrm[3 * (MAXFV + 1) * MAXFV * MAXFV];
+  __shared__ double sV[MAXFV * (MAXN + 1)];
+  __shared__ double sVp[MAXFV * (MAXN + 1)];
+  __shared__ double sI[(MAXFV + 1) * (MAXN + 1)];
+
+  const int idx = blockIdx.x;
+  if (idx >= count) return;
+  const int e = elist[idx];
+  if (!(alpha[e] > 0.0)) return;
+  const int NFV = m.n_fv;
+  const int S2 = NFV * NFV, S3 = S2 * NFV;
+  const double h = 2.0 / NFV;
+  const int64_t base = m.elem_offset[e];
+  const double* ub = m.ubar + (size_t)e * NV * S3;
+  for (int t = threadIdx.x; t < NV * S3; t += blockDim.x) {
+    sU[t] = ub[t];
+    sC[t] = 0.0;
+  }
+  for (int t = threadIdx.x; t < 9 * NP3; t += blockDim.x)
+    sJa[t] = m.metric[(t / NP3) * m.n_node + base + (t % NP3)];
+  for (int t = threadIdx.x; t < NFV * NP; t += blockDim.x) {
+    sV[t] = m.ops[m.tab.dg2fv[N] + t];
+    sVp[t] = m.ops[m.tab.fv2dg[N] + t];
+  }
+  for (int t = threadIdx.x; t < (NFV + 1) * NP; t += blockDim.x) sI[t] = m.ops[m.tab.face_interp[N] + t];
+  __syncthreads();
+
+  const double* fvs = m.fvside + (size_t)e * 6 * NV * S2;
+  for (int d = 0; d < 3; ++d) {
+    // normals of the NFV+1 interface planes along d: [3][..] with axis d of size NFV+1
+    // three passes on the 3 components of Ja^d; scratch in sG (fits 3*(NFV+1)*NP*NP? see CAP)
+    const double* src = sJa + 3 * d * NP3;
+    // pass over axis d first with face_interp, then tangential axes with dg2fv
+    int n2 = NP, n1 = NP, n0 = NP;
+    // stage 1
+    double* t1 = sG;
+    double* t2 = sNrm;
+    contract_axis(src, t1, sI, NFV + 1, NP, 3, n2, n1, n0, d);
+    __syncthreads();
+    int a2 = (d == 2) ? NFV + 1 : NP, a1 = (d == 1) ? NFV + 1 : NP, a0 = (d == 0) ? NFV + 1 : NP;
+    // remaining two axes (tangential), each NP -> NFV
+    const int ta = (d == 0) ? 1 : 0;
+    const int tb = (d == 2) ? 1 : 2;
+    contract_axis(t1, t2, sV, NFV, NP, 3, a2, a1, a0, ta);
+    __syncthreads();
+    if (ta == 0) a0 = NFV; else a1 = NFV;
+    contract_axis(t2, t1, sV, NFV, NP, 3, a2, a1, a0, tb);
+    __syncthreads();
+    if (tb == 1) a1 = NFV; else a2 = NFV;
+    // t1 (= sG) now holds normals [3][a2][a1][a0]; scale by h^2 and move to sNrm
+    const int nn = a2 * a1 * a0;
+    for (int t = threadIdx.x; t < 3 * nn; t += blockDim.x) sNrm[t] = sG[t] * (h * h);
+    __syncthreads();
+    // interface fluxes G[q] (+xi_d direction) on the same index layout, NV fields
+    for (int t = threadIdx.x; t < nn; t += blockDim.x) {
+      const int x0 = t % a0, x1 = (t / a0) % a1, x2 = t / (a0 * a1);
+      const int q = (d == 0) ? x0 : (d == 1 ? x1 : x2);
+      // the two tangential sub-cell indices in face (p, q') order
+      int fp, fq;
+      if (d == 0) { fp = x1; fq = x2; }
+      else if (d == 1) { fp = x0; fq = x2; }
+      else { fp = x0; fq = x1; }
+      double F[NV];
+      if (q == 0) {
+        for (int v = 0; v < NV; ++v) F[v] = -fvs[((2 * d) * NV + v) * S2 + fq * NFV + fp];
+      } else if (q == NFV) {
+        for (int v = 0; v < NV; ++v) F[v] = fvs[((2 * d + 1) * NV + v) * S2 + fq * NFV + fp];
+      } else {
+        int sl, sr;   // sub-cell indices left/right of the interface
+        if (d == 0) { sl = (x2 * NFV + x1) * NFV + (q - 1); sr = sl + 1; }
+        else if (d == 1) { sl = (x2 * NFV + (q - 1)) * NFV + x0; sr = sl + NFV; }
+        else { sl = ((q - 1) * NFV + x1) * NFV + x0; sr = sl + S2; }
+        double uL[NV], uR[NV];
+        for (int v = 0; v < NV; ++v) { uL[v] = sU[v * S3 + sl]; uR[v] = sU[v * S3 + sr]; }
+        riemann<NV>(prm.face_flux_fv, prm.volume_flux, uL, uR, sNrm[t], sNrm[nn + t],
+                    sNrm[2 * nn + t], m.gas, F);
+      }
+      for (int v = 0; v < NV; ++v) sG[v * nn + t] = F[v];
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < S3; t += blockDim.x) {
+      const int s0 = t % NFV, s1 = (t / NFV) % NFV, s2 = t / S2;
+      int lo, hi;
+      if (d == 0) { lo = (s2 * NFV + s1) * (NFV + 1) + s0; hi = lo + 1; }
+      else if (d == 1) { lo = (s2 * (NFV + 1) + s1) * NFV + s0; hi = lo + NFV; }
+      else { lo = (s2 * NFV + s1) * NFV + s0; hi = lo + S2; }
+      for (int v = 0; v < NV; ++v) sC[v * S3 + t] -= sG[v * nn + hi] - sG[v * nn + lo];
+    }
+    __syncthreads();
+  }
+  // nodal form: V3^+ (dC/dt) / (h^3 J); sC [NV][S3] -> sU as scratch
+  contract_axis(sC, sU, sVp, NP, NFV, NV, NFV, NFV, NFV, 0);
+  __syncthreads();
+  contract_axis(sU, sC, sVp, NP, NFV, NV, NFV, NFV, NP, 1);
+  __syncthreads();
+  contract_axis(sC, sU, sVp, NP, NFV, NV, NFV, NP, NP, 2);
+  __syncthreads();
+  const double ih3 = 1.0 / (h * h * h);
+  for (int t = threadIdx.x; t < NP3; t += blockDim.x) {
+    const double iJ = 1.0 / m.metric[9 * m.n_node + base + t];
+    for (int v = 0; v < NV; ++v) m.rfv[v * m.n_node + base + t] = sU[v * NP3 + t] * ih3 * iJ;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// modal decay indicator and blending factor (one element per 64-lane workgroup)
+// ---------------------------------------------------------------------------
+template <int N, int NV>
+__global__ void __launch_bounds__(64)
+indicator_kernel(MeshView m, ParamsDev prm, const int32_t* __restrict__ elist, int count,
+                 const double* __restrict__ u, double* __restrict__ alpha, double* __restrict__ ind) {
+  constexpr int NP = N + 1, NP3 = NP * NP * NP;
+  __shared__ double sq[NP3];
+  __shared__ double sw[NP3];
+  __shared__ double sVi[NP * NP];
+  __shared__ double sE[3][NP];
+  __shared__ double sI[3];
+  const int idx = blockIdx.x;
+  if (idx >= count) return;
+  const int e = elist[idx];
+  const int64_t base = m.elem_offset[e];
+  for (int t = threadIdx.x; t < NP * NP; t += blockDim.x) sVi[t] = m.ops[m.tab.vleg_inv[N] + t];
+  double Imin = INFINITY;
+  for (int var = 0; var < 3; ++var) {
+    if (!(prm.ind_vars & (1 << var))) continue;
+    if (var == 2 && NV != 6) continue;
+    __syncthreads();
+    for (int t = threadIdx.x; t < NP3; t += blockDim.x) {
+      double uu[NV];
+      for (int v = 0; v < NV; ++v) uu[v] = u[v * m.n_node + base + t];
+      const Prim q = cons2prim<NV>(uu, m.gas);
+      sq[t] = var == 0 ? q.p : (var == 1 ? q.rho : q.Y);
+    }
+    __syncthreads();
+    contract_axis(sq, sw, sVi, NP, NP, 1, NP, NP, NP, 0);
+    __syncthreads();
+    contract_axis(sw, sq, sVi, NP, NP, 1, NP, NP, NP, 1);
+    __syncthreads();
+    contract_axis(sq, sw, sVi, NP, NP, 1, NP, NP, NP, 2);
+    __syncthreads();
+    // energies per mode and direction
+    for (int t = threadIdx.x; t < 3 * NP; t += blockDim.x) {
+      const int d = t / NP, mm = t % NP;
+      double s = 0.0;
+      for (int a = 0; a < NP; ++a)
+        for (int b = 0; b < NP; ++b) {
+          int id;
+          if (d == 0) id = (b * NP + a) * NP + mm;
+          else if (d == 1) id = (b * NP + mm) * NP + a;
+          else id = (mm * NP + b) * NP + a;
+          s += sw[id] * sw[id];
+        }
+      sE[d][mm] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+      const int d = threadIdx.x;
+      double tot = 0.0;
+      for (int mm = 0; mm < NP; ++mm) tot += sE[d][mm];
+      double res;
+      if (tot < 1e-300) {
+        res = INFINITY;
+      } else {
+        const double mbar = 0.5 * N;
+        double ybar = 0.0;
+        double y[NP];
+        for (int mm = 0; mm < NP; ++mm) {
+          y[mm] = log(fmax(sE[d][mm] / tot, 1e-30));
+          ybar += y[mm];
+        }
+        ybar /= NP;
+        double sxy = 0.0, sxx = 0.0;
+        for (int mm = 0; mm < NP; ++mm) {
+          sxy += (mm - mbar) * (y[mm] - ybar);
+          sxx += (mm - mbar) * (mm - mbar);
+        }
+        res = fabs(-sxy / sxx);
+      }
+      sI[d] = res;
+    }
+    __syncthreads();
+    Imin = fmin(Imin, fmin(sI[0], fmin(sI[1], sI[2])));
+  }
+  if (threadIdx.x == 0) {
+    const double x = (Imin - prm.ind_T) / prm.ind_dT;
+    double a;
+    if (x <= -1.0) a = 1.0;
+    else if (x >= 1.0) a = 0.0;
+    else a = 0.5 * (1.0 - sin(0.5 * M_PI * x));
+    alpha[e] = a;
+    if (ind) ind[e] = Imin;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers for this degree
+// ---------------------------------------------------------------------------
+template <int NV, class FLUX>
+static hipError_t launch_elem_t(const MeshView& m, const int32_t* elist, int count, const double* u,
+                                const double* alpha, double* ut, double* k, int stage, double dt,
+                                double A, double B, hipStream_t s) {
+  using G = Geo<kN>;
+  const int blocks = (count + G::EPB - 1) / G::EPB;
+  hipLaunchKernelGGL((element_kernel<kN, NV, FLUX>), dim3(blocks), dim3(G::EPB * G::NP3), 0, s, m,
+                     elist, count, u, alpha, ut, k, stage, dt, A, B);
+  return hipGetLastError();
+}
+
+namespace per_degree {
+hipError_t element(const MeshView& m, const ParamsDev& p, const int32_t* elist, int count,
+                   const double* u, const double* alpha, double* ut, double* k, int stage,
+                   double dt, double A, double B, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  if (m.nvar == 5) {
+    if (p.volume_flux == 0) return launch_elem_t<5, FluxRanocha>(m, elist, count, u, alpha, ut, k, stage, dt, A, B, s);
+    if (p.volume_flux == 1) return launch_elem_t<5, FluxPirozzoli>(m, elist, count, u, alpha, ut, k, stage, dt, A, B, s);
+    return launch_elem_t<5, FluxCentral>(m, elist, count, u, alpha, ut, k, stage, dt, A, B, s);
+  }
+  if (p.volume_flux == 1) return launch_elem_t<6, FluxPirozzoli>(m, elist, count, u, alpha, ut, k, stage, dt, A, B, s);
+  return launch_elem_t<6, FluxCentral>(m, elist, count, u, alpha, ut, k, stage, dt, A, B, s);
+}
+
+hipError_t fv_means(const MeshView& m, const int32_t* elist, int count, const double* u,
+                    const double* alpha, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  if (m.nvar == 5)
+    hipLaunchKernelGGL((fv_means_kernel<kN, 5>), dim3(count), dim3(FV_THREADS), 0, s, m, elist, count, u, alpha);
+  else
+    hipLaunchKernelGGL((fv_means_kernel<kN, 6>), dim3(count), dim3(FV_THREADS), 0, s, m, elist, count, u, alpha);
+  return hipGetLastError();
+}
+
+hipError_t fv_residual(const MeshView& m, const ParamsDev& p, const int32_t* elist, int count,
+                       const double* alpha, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  if (m.nvar == 5)
+    hipLaunchKernelGGL((fv_residual_kernel<kN, 5>), dim3(count), dim3(FV_THREADS), 0, s, m, p, elist, count, alpha);
+  else
+    hipLaunchKernelGGL((fv_residual_kernel<kN, 6>), dim3(count), dim3(FV_THREADS), 0, s, m, p, elist, count, alpha);
+  return hipGetLastError();
+}
+
+hipError_t indicator(const MeshView& m, const ParamsDev& p, const int32_t* elist, int count,
+                     const double* u, double* alpha, double* ind, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  if (m.nvar == 5)
+    hipLaunchKernelGGL((indicator_kernel<kN, 5>), dim3(count), dim3(64), 0, s, m, p, elist, count, u, alpha, ind);
+  else
+    hipLaunchKernelGGL((indicator_kernel<kN, 6>), dim3(count), dim3(64), 0, s, m, p, elist, count, u, alpha, ind);
+  return hipGetLastError();
+}
+}  // namespace per_degree
+}  // namespace
+
+// The dispatcher's handle on this degree's launchers.
+#define DGFV_CAT2(a, b) a##b
+#define DGFV_CAT(a, b) DGFV_CAT2(a, b)
+DegreeOps DGFV_CAT(degree_ops_, DGFV_N)() {
+  return DegreeOps{&per_degree::element, &per_degree::fv_means, &per_degree::fv_residual,
+                   &per_degree::indicator};
+}
+
+}  // namespace dgfv

@@ -1,0 +1,219 @@
+// Interface fluxes of the hybrid DG/FV operator (Section 3.2.1).
+//
+// One face per 64-lane workgroup.  The face class is decided at run time from
+// the degrees and blending factors of its two elements:
+//  * DG / DG, same degree: the Riemann flux at each face node with the left
+//    side's outward normal n*s = +-Ja^d (eq. conv_flux);
+//  * DG / DG, degrees NL != NR: both traces at M = max(NL, NR) through
+//    V^{N->M}, flux at the M nodes, and the lower side receives the modal L2
+//    projection V^{M->N} of it;
+//  * FV face (either alpha > 0): sub-face traces on the N_FV^2 grid (sub-cell
+//    means of a blended side, V^{DG->FV} of a DG side's nodal trace), one
+//    Riemann flux per sub-face with n*s = h^2 V^{DG->FV}(Ja); the FV part of
+//    a blended side receives it directly and every DG part V^{FV->DG} of it / h^2.
+// Results go to per-element side buffers: the right side gets the negated flux
+// re-indexed through the face orientation.
+#include "dgfv_internal.h"
+#include "dgfv_lds.h"
+#include "dgfv_physics.h"
+
+namespace dgfv {
+namespace {
+
+constexpr int FACE_THREADS = 64;
+constexpr int GRID = 64;  // max points of a face grid: (MAXN+1)^2 = MAXFV^2 = 64
+
+// Gather a side's nodal trace into `dst[NV][n*n]` on the left side's face grid.
+template <int NV>
+__device__ void gather_trace(const MeshView& m, const double* u, int e, int side, int o, bool right,
+                             int n, double* dst) {
+  const int64_t base = m.elem_offset[e];
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+    int p = t % n, q = t / n;
+    if (right) orient_map(o, p, q, n, p, q);
+    const int64_t g = base + side_node(side, p, q, n);
+    for (int v = 0; v < NV; ++v) dst[v * GRID + t] = u[v * m.n_node + g];
+  }
+}
+
+// Boundary-layer sub-cell means of side `side` on the left side's sub-face grid.
+template <int NV>
+__device__ void gather_subcells(const MeshView& m, int e, int side, int o, bool right, double* dst) {
+  const int n = m.n_fv;
+  const int S3 = n * n * n;
+  const double* ub = m.ubar + (size_t)e * NV * S3;
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+    int p = t % n, q = t / n;
+    if (right) orient_map(o, p, q, n, p, q);
+    const int s = side_node(side, p, q, n);
+    for (int v = 0; v < NV; ++v) dst[v * GRID + t] = ub[v * S3 + s];
+  }
+}
+
+// 2D tensor map A (x) A on face data [nf][GRID] with grids nin x nin -> nout x nout.
+__device__ void map2d(const double* src, double* tmp, double* dst, const double* A, int nout,
+                      int nin, int nf) {
+  // compact src into tmp as [nf][nin][nin] for the generic contraction
+  for (int t = threadIdx.x; t < nf * nin * nin; t += blockDim.x) {
+    const int f = t / (nin * nin), r = t % (nin * nin);
+    tmp[t] = src[f * GRID + r];
+  }
+  __syncthreads();
+  double* mid = tmp + nf * GRID;     // disjoint from both the compacted input and the output
+  contract_axis(tmp, mid, A, nout, nin, nf, 1, nin, nin, 0);   // [nf][nin][nout]
+  __syncthreads();
+  double* out = tmp;                 // the compacted input is dead now
+  contract_axis(mid, out, A, nout, nin, nf, 1, nin, nout, 1);  // [nf][nout][nout]
+  __syncthreads();
+  for (int t = threadIdx.x; t < nf * nout * nout; t += blockDim.x) {
+    const int f = t / (nout * nout), r = t % (nout * nout);
+    dst[f * GRID + r] = out[t];
+  }
+  __syncthreads();
+}
+
+// Write face data [NV][n*n] (left grid) into a side buffer, with sign and orientation.
+template <int NV>
+__device__ void write_side(double* dst_block, const double* src, int side, int o, bool right, int n,
+                           double scale) {
+  const int n2 = n * n;
+  for (int t = threadIdx.x; t < n2; t += blockDim.x) {
+    int p = t % n, q = t / n;
+    if (right) orient_map(o, p, q, n, p, q);
+    for (int v = 0; v < NV; ++v) dst_block[(side * NV + v) * n2 + q * n + p] = scale * src[v * GRID + t];
+  }
+}
+
+template <int NV>
+__global__ void __launch_bounds__(FACE_THREADS)
+face_kernel(MeshView m, ParamsDev prm, const double* __restrict__ u, const double* __restrict__ alpha) {
+  __shared__ double sL[NV * GRID];
+  __shared__ double sR[NV * GRID];
+  __shared__ double sF[NV * GRID];
+  __shared__ double sN[3 * GRID];
+  __shared__ double sTmp[3 * NV * GRID];
+
+  const int f = blockIdx.x;
+  if (f >= m.n_face) return;
+  const int32_t* fc = m.faces + 5 * f;
+  const int eL = fc[0], sideL = fc[1], eR = fc[2], sideR = fc[3], o = fc[4];
+  const int NL = m.degree[eL], NR = m.degree[eR];
+  const int M = NL > NR ? NL : NR;
+  const int nL = NL + 1, nR = NR + 1, nM = M + 1;
+  const double aL = alpha ? alpha[eL] : 0.0;
+  const double aR = alpha ? alpha[eR] : 0.0;
+  const double* nrm = m.face_norm + m.face_norm_off[f];   // [3][nM*nM]
+  double* bL = m.fside + m.side_off[eL];
+  double* bR = m.fside + m.side_off[eR];
+
+  if (!(aL > 0.0) && !(aR > 0.0)) {
+    if (NL == NR) {
+      // conforming DG face: pointwise
+      const int n = nL, n2 = n * n;
+      const int64_t baseL = m.elem_offset[eL], baseR = m.elem_offset[eR];
+      for (int t = threadIdx.x; t < n2; t += blockDim.x) {
+        const int p = t % n, q = t / n;
+        int pp, qq;
+        orient_map(o, p, q, n, pp, qq);
+        const int64_t gL = baseL + side_node(sideL, p, q, n);
+        const int64_t gR = baseR + side_node(sideR, pp, qq, n);
+        double uL[NV], uR[NV], F[NV];
+        for (int v = 0; v < NV; ++v) {
+          uL[v] = u[v * m.n_node + gL];
+          uR[v] = u[v * m.n_node + gR];
+        }
+        riemann<NV>(prm.face_flux_dg, prm.volume_flux, uL, uR, nrm[t], nrm[n2 + t], nrm[2 * n2 + t],
+                    m.gas, F);
+        for (int v = 0; v < NV; ++v) {
+          bL[(sideL * NV + v) * n2 + q * n + p] = F[v];
+          bR[(sideR * NV + v) * n2 + qq * n + pp] = -F[v];
+        }
+      }
+      return;
+    }
+    // degree jump: common degree M
+    gather_trace<NV>(m, u, eL, sideL, o, false, nL, sL);
+    gather_trace<NV>(m, u, eR, sideR, o, true, nR, sR);
+    __syncthreads();
+    if (NL < M) map2d(sL, sTmp, sL, m.ops + m.tab.interp[NL][M], nM, nL, NV);
+    if (NR < M) map2d(sR, sTmp, sR, m.ops + m.tab.interp[NR][M], nM, nR, NV);
+    const int n2 = nM * nM;
+    for (int t = threadIdx.x; t < n2; t += blockDim.x) {
+      double uL[NV], uR[NV], F[NV];
+      for (int v = 0; v < NV; ++v) {
+        uL[v] = sL[v * GRID + t];
+        uR[v] = sR[v * GRID + t];
+      }
+      riemann<NV>(prm.face_flux_dg, prm.volume_flux, uL, uR, nrm[t], nrm[n2 + t], nrm[2 * n2 + t],
+                  m.gas, F);
+      for (int v = 0; v < NV; ++v) sF[v * GRID + t] = F[v];
+    }
+    __syncthreads();
+    if (NL < M) {
+      map2d(sF, sTmp, sL, m.ops + m.tab.project[M][NL], nL, nM, NV);
+      write_side<NV>(bL, sL, sideL, o, false, nL, 1.0);
+    } else {
+      write_side<NV>(bL, sF, sideL, o, false, nL, 1.0);
+    }
+    if (NR < M) {
+      map2d(sF, sTmp, sR, m.ops + m.tab.project[M][NR], nR, nM, NV);
+      write_side<NV>(bR, sR, sideR, o, true, nR, -1.0);
+    } else {
+      write_side<NV>(bR, sF, sideR, o, true, nR, -1.0);
+    }
+    return;
+  }
+
+  // FV face
+  const int nF = m.n_fv, n2F = nF * nF;
+  const double h = 2.0 / nF;
+  if (aL > 0.0) {
+    gather_subcells<NV>(m, eL, sideL, o, false, sL);
+  } else {
+    gather_trace<NV>(m, u, eL, sideL, o, false, nL, sL);
+  }
+  if (aR > 0.0) {
+    gather_subcells<NV>(m, eR, sideR, o, true, sR);
+  } else {
+    gather_trace<NV>(m, u, eR, sideR, o, true, nR, sR);
+  }
+  for (int t = threadIdx.x; t < 3 * nM * nM; t += blockDim.x)
+    sN[(t / (nM * nM)) * GRID + t % (nM * nM)] = nrm[t];
+  __syncthreads();
+  if (!(aL > 0.0)) map2d(sL, sTmp, sL, m.ops + m.tab.dg2fv[NL], nF, nL, NV);
+  if (!(aR > 0.0)) map2d(sR, sTmp, sR, m.ops + m.tab.dg2fv[NR], nF, nR, NV);
+  map2d(sN, sTmp, sN, m.ops + m.tab.dg2fv[M], nF, nM, 3);
+  for (int t = threadIdx.x; t < n2F; t += blockDim.x) {
+    double uL[NV], uR[NV], F[NV];
+    for (int v = 0; v < NV; ++v) {
+      uL[v] = sL[v * GRID + t];
+      uR[v] = sR[v * GRID + t];
+    }
+    const double a = h * h;
+    riemann<NV>(prm.face_flux_fv, prm.volume_flux, uL, uR, a * sN[t], a * sN[GRID + t],
+                a * sN[2 * GRID + t], m.gas, F);
+    for (int v = 0; v < NV; ++v) sF[v * GRID + t] = F[v];
+  }
+  __syncthreads();
+  if (aL > 0.0) write_side<NV>(m.fvside + (size_t)eL * 6 * NV * n2F, sF, sideL, o, false, nF, 1.0);
+  if (aR > 0.0) write_side<NV>(m.fvside + (size_t)eR * 6 * NV * n2F, sF, sideR, o, true, nF, -1.0);
+  const double ih2 = 1.0 / (h * h);
+  map2d(sF, sTmp, sL, m.ops + m.tab.fv2dg[NL], nL, nF, NV);
+  write_side<NV>(bL, sL, sideL, o, false, nL, ih2);
+  map2d(sF, sTmp, sR, m.ops + m.tab.fv2dg[NR], nR, nF, NV);
+  write_side<NV>(bR, sR, sideR, o, true, nR, -ih2);
+}
+
+}  // namespace
+
+hipError_t launch_faces(const MeshView& m, const ParamsDev& p, const double* u, const double* alpha,
+                        hipStream_t s) {
+  if (m.n_face == 0) return hipSuccess;
+  if (m.nvar == 5)
+    hipLaunchKernelGGL((face_kernel<5>), dim3(m.n_face), dim3(FACE_THREADS), 0, s, m, p, u, alpha);
+  else
+    hipLaunchKernelGGL((face_kernel<6>), dim3(m.n_face), dim3(FACE_THREADS), 0, s, m, p, u, alpha);
+  return hipGetLastError();
+}
+
+}  // namespace dgfv

@@ -1,0 +1,627 @@
+// Host runtime of the hybrid DG/FV right-hand side: mesh setup (operators,
+// curl-form metrics, face tables, degree buckets, device buffers) and the C ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/dgfv.h"
+#include "dgfv_internal.h"
+#include "dgfv_ops1d.h"
+
+using namespace dgfv;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+dgfv_status fail(dgfv_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+struct HipError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw HipError(std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <class T>
+T* dev_upload(const std::vector<T>& h) {
+  T* d = nullptr;
+  if (h.empty()) return nullptr;
+  hip_check(hipMalloc(&d, h.size() * sizeof(T)), "hipMalloc");
+  hip_check(hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice), "hipMemcpy");
+  return d;
+}
+
+template <class T>
+T* dev_alloc(size_t n) {
+  T* d = nullptr;
+  if (n == 0) n = 1;
+  hip_check(hipMalloc(&d, n * sizeof(T)), "hipMalloc");
+  return d;
+}
+
+// Carpenter-Kennedy five-stage fourth-order 2N-storage coefficients.
+const double RK_A[5] = {0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
+                        -3550918686646.0 / 2091501179385.0, -1275806237668.0 / 842570457699.0};
+const double RK_B[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
+                        1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
+                        2277821191437.0 / 14882151754819.0};
+
+template <class F>
+void parallel_for(int64_t n, F&& body) {
+  unsigned nt = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+  if (n < 256) nt = 1;
+  std::vector<std::thread> th;
+  const int64_t chunk = (n + nt - 1) / nt;
+  for (unsigned t = 0; t < nt; ++t) {
+    const int64_t a = t * chunk, b = std::min<int64_t>(n, a + chunk);
+    if (a >= b) break;
+    th.emplace_back([=, &body] {
+      for (int64_t i = a; i < b; ++i) body(i);
+    });
+  }
+  for (auto& x : th) x.join();
+}
+
+DegreeOps ops_for(int N) {
+  switch (N) {
+    case 1: return degree_ops_1();
+    case 2: return degree_ops_2();
+    case 3: return degree_ops_3();
+    case 4: return degree_ops_4();
+    case 5: return degree_ops_5();
+    case 6: return degree_ops_6();
+    default: return degree_ops_7();
+  }
+}
+
+}  // namespace
+
+struct dgfv_mesh {
+  int K = 0, nvar = 0, n_fv = 0, NJ = 0, F = 0;
+  int64_t n_node = 0;
+  std::vector<int8_t> degree;
+  std::vector<int64_t> offset;
+  std::vector<double> coords;            // [3][n_node]
+  std::array<std::vector<int32_t>, MAXN + 1> bucket;
+  std::array<int32_t*, MAXN + 1> d_bucket{};
+  std::vector<void*> allocations;
+  MeshView view{};
+
+  // kernel timing (mutable: recording does not change the mesh)
+  mutable bool profile = false;
+  mutable std::array<std::vector<std::pair<hipEvent_t, hipEvent_t>>, DGFV_KERNEL_COUNT> ev;
+  mutable std::array<size_t, DGFV_KERNEL_COUNT> ev_used{};
+
+  ~dgfv_mesh() {
+    for (auto& list : ev)
+      for (auto& pr : list) {
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+      }
+    for (void* p : allocations) (void)hipFree(p);
+  }
+  template <class T>
+  T* keep(T* p) {
+    allocations.push_back((void*)p);
+    return p;
+  }
+};
+
+namespace {
+
+// Trilinear map and its Jacobian at reference point (x1, x2, x3).
+void trilinear(const double* c, double x1, double x2, double x3, double X[3], double G[3][3]) {
+  const double ph[2][3] = {{0.5 * (1 - x1), 0.5 * (1 - x2), 0.5 * (1 - x3)},
+                           {0.5 * (1 + x1), 0.5 * (1 + x2), 0.5 * (1 + x3)}};
+  const double dph[2] = {-0.5, 0.5};
+  for (int n = 0; n < 3; ++n) {
+    X[n] = 0;
+    for (int a = 0; a < 3; ++a) G[n][a] = 0;
+  }
+  for (int k = 0; k < 8; ++k) {
+    const int b0 = k & 1, b1 = (k >> 1) & 1, b2 = (k >> 2) & 1;
+    const double w = ph[b0][0] * ph[b1][1] * ph[b2][2];
+    const double g0 = dph[b0] * ph[b1][1] * ph[b2][2];
+    const double g1 = ph[b0][0] * dph[b1] * ph[b2][2];
+    const double g2 = ph[b0][0] * ph[b1][1] * dph[b2];
+    for (int n = 0; n < 3; ++n) {
+      const double cn = c[3 * k + n];
+      X[n] += cn * w;
+      G[n][0] += cn * g0;
+      G[n][1] += cn * g1;
+      G[n][2] += cn * g2;
+    }
+  }
+}
+
+// Derivative along reference axis `a` of a nodal field f[(k*n + j)*n + i] on n^3 nodes.
+void dxi(const std::vector<double>& D, int n, const double* f, double* out, int a) {
+  for (int k = 0; k < n; ++k)
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int m = 0; m < n; ++m) {
+          int idx;
+          if (a == 0) idx = (k * n + j) * n + m;
+          else if (a == 1) idx = (k * n + m) * n + i;
+          else idx = (m * n + j) * n + i;
+          s += D[(a == 0 ? i : (a == 1 ? j : k)) * n + m] * f[idx];
+        }
+        out[(k * n + j) * n + i] = s;
+      }
+}
+
+// Conservative curl-form metrics Ja^d_n of one element at the degree-NJ LGL nodes:
+// Ja^d_n = -(curl_xi (X_l grad_xi X_m))_d with (n, m, l) cyclic.  Output [9][nJ^3].
+void curl_metrics(const double* corners, int NJ, const std::vector<double>& xJ,
+                  const std::vector<double>& DJ, std::vector<double>& out) {
+  const int n = NJ + 1, n3 = n * n * n;
+  std::vector<double> X(3 * n3);
+  for (int k = 0; k < n; ++k)
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i) {
+        double x[3], G[3][3];
+        trilinear(corners, xJ[i], xJ[j], xJ[k], x, G);
+        for (int c = 0; c < 3; ++c) X[c * n3 + (k * n + j) * n + i] = x[c];
+      }
+  std::vector<double> dX(3 * n3), W(3 * n3), dW(n3), tmp(n3);
+  out.assign(9 * n3, 0.0);
+  for (int nn = 0; nn < 3; ++nn) {
+    const int mm = (nn + 1) % 3, ll = (nn + 2) % 3;
+    for (int a = 0; a < 3; ++a) {
+      dxi(DJ, n, &X[mm * n3], tmp.data(), a);
+      for (int t = 0; t < n3; ++t) W[a * n3 + t] = X[ll * n3 + t] * tmp[t];
+    }
+    // curl components
+    for (int d = 0; d < 3; ++d) {
+      const int b = (d + 1) % 3, c = (d + 2) % 3;   // (curl W)_d = d_b W_c - d_c W_b
+      dxi(DJ, n, &W[c * n3], dW.data(), b);
+      dxi(DJ, n, &W[b * n3], tmp.data(), c);
+      for (int t = 0; t < n3; ++t) out[(3 * d + nn) * n3 + t] = -(dW[t] - tmp[t]);
+    }
+  }
+}
+
+// Tensor interpolation of nodal fields [nf][nin^3] to [nf][nout^3] with the 1D matrix V (nout x nin).
+void interp3(const std::vector<double>& V, int nin, int nout, const double* src, double* dst, int nf) {
+  std::vector<double> a(nin * nin * nout), b(nin * nout * nout);
+  for (int f = 0; f < nf; ++f) {
+    const double* s = src + (size_t)f * nin * nin * nin;
+    double* o = dst + (size_t)f * nout * nout * nout;
+    for (int k = 0; k < nin; ++k)
+      for (int j = 0; j < nin; ++j)
+        for (int i = 0; i < nout; ++i) {
+          double acc = 0;
+          for (int c = 0; c < nin; ++c) acc += V[i * nin + c] * s[(k * nin + j) * nin + c];
+          a[(k * nin + j) * nout + i] = acc;
+        }
+    for (int k = 0; k < nin; ++k)
+      for (int j = 0; j < nout; ++j)
+        for (int i = 0; i < nout; ++i) {
+          double acc = 0;
+          for (int c = 0; c < nin; ++c) acc += V[j * nin + c] * a[(k * nin + c) * nout + i];
+          b[(k * nout + j) * nout + i] = acc;
+        }
+    for (int k = 0; k < nout; ++k)
+      for (int j = 0; j < nout; ++j)
+        for (int i = 0; i < nout; ++i) {
+          double acc = 0;
+          for (int c = 0; c < nin; ++c) acc += V[k * nin + c] * b[(c * nout + j) * nout + i];
+          o[(k * nout + j) * nout + i] = acc;
+        }
+  }
+}
+
+int side_node_h(int s, int p, int q, int n) {
+  const int last = (s & 1) ? n - 1 : 0;
+  switch (s >> 1) {
+    case 0: return (q * n + p) * n + last;
+    case 1: return (q * n + last) * n + p;
+    default: return (last * n + q) * n + p;
+  }
+}
+
+dgfv_status check_params(const dgfv_mesh* m, const dgfv_params* p) {
+  if (!p) return fail(DGFV_ERR_ARG, "params is NULL");
+  if (p->volume_flux < 0 || p->volume_flux > 2) return fail(DGFV_ERR_ARG, "volume_flux out of range");
+  if (p->face_flux_dg < 0 || p->face_flux_dg > 2 || p->face_flux_fv < 0 || p->face_flux_fv > 2)
+    return fail(DGFV_ERR_ARG, "face flux selector out of range");
+  if (m->nvar == 6 && p->volume_flux == DGFV_VOL_RANOCHA)
+    return fail(DGFV_ERR_UNSUPPORTED, "the entropy-conserving volume flux is single-species only");
+  if (m->nvar == 6 && (p->face_flux_dg == DGFV_RIEMANN_ROE_HH || p->face_flux_fv == DGFV_RIEMANN_ROE_HH))
+    return fail(DGFV_ERR_UNSUPPORTED, "the Roe solver is single-species only");
+  return DGFV_OK;
+}
+
+// Records an event pair around one launch when profiling is on.
+struct Timed {
+  const dgfv_mesh* m;
+  int kind;
+  hipStream_t s;
+  hipEvent_t stop = nullptr;
+  Timed(const dgfv_mesh* mesh, int k, hipStream_t st) : m(mesh), kind(k), s(st) {
+    if (!m->profile) return;
+    auto& list = m->ev[kind];
+    size_t& used = m->ev_used[kind];
+    if (used == list.size()) {
+      hipEvent_t a, b;
+      hip_check(hipEventCreate(&a), "hipEventCreate");
+      hip_check(hipEventCreate(&b), "hipEventCreate");
+      list.emplace_back(a, b);
+    }
+    hip_check(hipEventRecord(list[used].first, s), "hipEventRecord");
+    stop = list[used].second;
+    ++used;
+  }
+  ~Timed() {
+    if (stop) (void)hipEventRecord(stop, s);
+  }
+};
+
+ParamsDev to_dev(const dgfv_params* p) {
+  ParamsDev d;
+  d.volume_flux = p->volume_flux;
+  d.face_flux_dg = p->face_flux_dg;
+  d.face_flux_fv = p->face_flux_fv;
+  d.ind_vars = p->ind_vars;
+  d.ind_T = p->ind_T;
+  d.ind_dT = p->ind_dT;
+  return d;
+}
+
+// Enqueue one evaluation: stage 0 -> ut = R(u); stage 1..5 -> RK stage on (u, k).
+dgfv_status enqueue_rhs(const dgfv_mesh* m, const dgfv_params* prm, const double* u,
+                        const double* alpha, double* ut, double* k, int stage, double dt,
+                        hipStream_t s) {
+  const ParamsDev p = to_dev(prm);
+  const MeshView& v = m->view;
+  const double A = stage > 0 ? RK_A[stage - 1] : 0.0;
+  const double B = stage > 0 ? RK_B[stage - 1] : 0.0;
+  try {
+    if (alpha) {
+      Timed t(m, DGFV_KERNEL_FV_MEANS, s);
+      for (int N = 1; N <= MAXN; ++N)
+        if (!m->bucket[N].empty())
+          hip_check(ops_for(N).fv_means(v, m->d_bucket[N], (int)m->bucket[N].size(), u, alpha, s),
+                    "fv_means launch");
+    }
+    {
+      Timed t(m, DGFV_KERNEL_FACE, s);
+      hip_check(launch_faces(v, p, u, alpha, s), "face launch");
+    }
+    if (alpha) {
+      Timed t(m, DGFV_KERNEL_FV_RESIDUAL, s);
+      for (int N = 1; N <= MAXN; ++N)
+        if (!m->bucket[N].empty())
+          hip_check(ops_for(N).fv_residual(v, p, m->d_bucket[N], (int)m->bucket[N].size(), alpha, s),
+                    "fv_residual launch");
+    }
+    {
+      Timed t(m, DGFV_KERNEL_ELEMENT, s);
+      for (int N = 1; N <= MAXN; ++N)
+        if (!m->bucket[N].empty())
+          hip_check(ops_for(N).element(v, p, m->d_bucket[N], (int)m->bucket[N].size(), u, alpha, ut, k,
+                                       stage, dt, A, B, s),
+                    "element launch");
+    }
+  } catch (const HipError& e) {
+    return fail(DGFV_ERR_HIP, e.what());
+  }
+  return DGFV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dgfv_last_error(void) { return g_last_error.c_str(); }
+
+dgfv_status dgfv_mesh_create(const dgfv_mesh_desc* d, dgfv_mesh** out) {
+  if (!d || !out) return fail(DGFV_ERR_ARG, "NULL argument");
+  *out = nullptr;
+  if (d->n_elem <= 0) return fail(DGFV_ERR_ARG, "n_elem must be positive");
+  if (d->n_var != 5 && d->n_var != 6) return fail(DGFV_ERR_ARG, "n_var must be 5 or 6");
+  if (!d->degree || !d->corners || !d->faces) return fail(DGFV_ERR_ARG, "NULL mesh array");
+  int nmin = 99, nmax = 0;
+  for (int e = 0; e < d->n_elem; ++e) {
+    const int N = d->degree[e];
+    if (N < 1 || N > MAXN) return fail(DGFV_ERR_UNSUPPORTED, "element degree must be in 1..7");
+    nmin = std::min(nmin, N);
+    nmax = std::max(nmax, N);
+  }
+  if (d->metric_degree < 1 || d->metric_degree > nmin)
+    return fail(DGFV_ERR_ARG, "metric_degree must be in 1..min(degree)");
+  if (d->n_fv < nmax + 1 || d->n_fv > MAXFV)
+    return fail(DGFV_ERR_UNSUPPORTED, "n_fv must be in max(degree)+1 .. 8");
+  if (d->n_face != 3 * d->n_elem)
+    return fail(DGFV_ERR_ARG, "a closed conforming hexahedral mesh has 3 faces per element");
+  {
+    std::vector<uint8_t> seen((size_t)d->n_elem * 6, 0);
+    for (int f = 0; f < d->n_face; ++f) {
+      const int32_t* fc = d->faces + 5 * f;
+      for (int side = 0; side < 2; ++side) {
+        const int e = fc[2 * side], s = fc[2 * side + 1];
+        if (e < 0 || e >= d->n_elem || s < 0 || s > 5) return fail(DGFV_ERR_ARG, "face entry out of range");
+        if (seen[(size_t)e * 6 + s]++) return fail(DGFV_ERR_ARG, "element side used by two faces");
+      }
+      if (fc[4] < 0 || fc[4] > 7) return fail(DGFV_ERR_ARG, "orientation code out of range");
+    }
+  }
+  if (d->n_var == 5 && !(d->gamma > 1.0)) return fail(DGFV_ERR_ARG, "gamma must exceed 1");
+  if (d->n_var == 6 && !(d->kappa[0] > 1.0 && d->kappa[1] > 1.0 && d->R[0] > 0 && d->R[1] > 0))
+    return fail(DGFV_ERR_ARG, "invalid species constants");
+
+  std::unique_ptr<dgfv_mesh> m(new dgfv_mesh);
+  try {
+    m->K = d->n_elem;
+    m->nvar = d->n_var;
+    m->n_fv = d->n_fv;
+    m->NJ = d->metric_degree;
+    m->F = d->n_face;
+    m->degree.assign(d->degree, d->degree + d->n_elem);
+    m->offset.resize(m->K + 1);
+    m->offset[0] = 0;
+    for (int e = 0; e < m->K; ++e) {
+      const int n = m->degree[e] + 1;
+      m->offset[e + 1] = m->offset[e] + n * n * n;
+    }
+    m->n_node = m->offset[m->K];
+    const int NFV = m->n_fv, NJ = m->NJ;
+    bool present[MAXN + 1] = {false};
+    for (int e = 0; e < m->K; ++e) present[m->degree[e]] = true;
+
+    // ---- operator tables --------------------------------------------------
+    std::vector<double> ops;
+    OpTables tab;
+    std::memset(&tab, 0xff, sizeof(tab));   // -1 everywhere
+    auto push = [&](const std::vector<double>& a) {
+      const int off = (int)ops.size();
+      ops.insert(ops.end(), a.begin(), a.end());
+      return off;
+    };
+    for (int N = 1; N <= MAXN; ++N) {
+      if (!present[N]) continue;
+      tab.D[N] = push(op_D(N));
+      tab.w[N] = push(op_weights(N));
+      tab.vleg_inv[N] = push(op_vleg_inv(N));
+      tab.dg2fv[N] = push(op_dg2fv(N, NFV));
+      tab.fv2dg[N] = push(op_fv2dg(N, NFV));
+      tab.face_interp[N] = push(op_face_interp(N, NFV));
+      for (int M = N + 1; M <= MAXN; ++M) {
+        if (!present[M]) continue;
+        tab.interp[N][M] = push(op_interp(N, M));
+        tab.project[M][N] = push(op_project(M, N));
+      }
+    }
+
+    // ---- metrics and coordinates -------------------------------------------
+    const auto xJ = op_nodes(NJ);
+    const auto DJ = op_D(NJ);
+    std::array<std::vector<double>, MAXN + 1> xN, VJN;
+    for (int N = 1; N <= MAXN; ++N)
+      if (present[N] || N == NJ) {
+        xN[N] = op_nodes(N);
+        VJN[N] = op_interp(NJ, N);   // identity rows when N == NJ? op_interp(N, N) is the identity
+      }
+    std::vector<double> metric((size_t)10 * m->n_node);
+    m->coords.assign((size_t)3 * m->n_node, 0.0);
+    std::vector<uint8_t> bad(m->K, 0);
+    const int nJ = NJ + 1, nJ3 = nJ * nJ * nJ;
+    std::vector<double> JaJ_all((size_t)m->K * 9 * nJ3);
+    parallel_for(m->K, [&](int64_t e) {
+      const double* c = d->corners + 24 * e;
+      std::vector<double> JaJ;
+      curl_metrics(c, NJ, xJ, DJ, JaJ);
+      std::copy(JaJ.begin(), JaJ.end(), JaJ_all.begin() + e * 9 * nJ3);
+      const int N = m->degree[e], n = N + 1, n3 = n * n * n;
+      std::vector<double> JaN(9 * n3);
+      interp3(VJN[N], nJ, n, JaJ.data(), JaN.data(), 9);
+      const int64_t base = m->offset[e];
+      for (int t = 0; t < n3; ++t) {
+        for (int comp = 0; comp < 9; ++comp) metric[(size_t)comp * m->n_node + base + t] = JaN[comp * n3 + t];
+        const int i = t % n, j = (t / n) % n, k = t / (n * n);
+        double X[3], G[3][3];
+        trilinear(c, xN[N][i], xN[N][j], xN[N][k], X, G);
+        const double J = G[0][0] * (G[1][1] * G[2][2] - G[1][2] * G[2][1]) -
+                         G[0][1] * (G[1][0] * G[2][2] - G[1][2] * G[2][0]) +
+                         G[0][2] * (G[1][0] * G[2][1] - G[1][1] * G[2][0]);
+        if (!(J > 0)) bad[e] = 1;
+        metric[(size_t)9 * m->n_node + base + t] = J;
+        for (int a = 0; a < 3; ++a) m->coords[(size_t)a * m->n_node + base + t] = X[a];
+      }
+    });
+    for (int e = 0; e < m->K; ++e)
+      if (bad[e]) return fail(DGFV_ERR_ARG, "element " + std::to_string(e) + " has a non-positive Jacobian");
+
+    // ---- faces: left outward normal at the common degree M -----------------
+    std::vector<int64_t> fnorm_off(m->F);
+    int64_t tot = 0;
+    for (int f = 0; f < m->F; ++f) {
+      const int M = std::max(m->degree[d->faces[5 * f]], m->degree[d->faces[5 * f + 2]]);
+      fnorm_off[f] = tot;
+      tot += 3 * (M + 1) * (M + 1);
+    }
+    std::vector<double> fnorm(tot);
+    parallel_for(m->F, [&](int64_t f) {
+      const int32_t* fc = d->faces + 5 * f;
+      const int eL = fc[0], sL = fc[1];
+      const int M = std::max(m->degree[eL], m->degree[fc[2]]);
+      const int nM = M + 1, dd = sL / 2;
+      const double sign = (sL & 1) ? 1.0 : -1.0;
+      const double* JaJ = &JaJ_all[(size_t)eL * 9 * nJ3];
+      const auto& V = VJN[M];
+      // face slice of Ja^dd at the NJ grid, then 2D interpolation to M
+      for (int comp = 0; comp < 3; ++comp) {
+        std::vector<double> sl(nJ * nJ);
+        for (int q = 0; q < nJ; ++q)
+          for (int p = 0; p < nJ; ++p) sl[q * nJ + p] = JaJ[(3 * dd + comp) * nJ3 + side_node_h(sL, p, q, nJ)];
+        for (int q = 0; q < nM; ++q)
+          for (int p = 0; p < nM; ++p) {
+            double acc = 0.0;
+            for (int b = 0; b < nJ; ++b)
+              for (int a = 0; a < nJ; ++a) acc += V[q * nJ + b] * V[p * nJ + a] * sl[b * nJ + a];
+            fnorm[fnorm_off[f] + comp * nM * nM + q * nM + p] = sign * acc;
+          }
+      }
+    });
+
+    // ---- per-element side blocks -------------------------------------------
+    std::vector<int64_t> side_off(m->K);
+    int64_t stot = 0;
+    for (int e = 0; e < m->K; ++e) {
+      const int n = m->degree[e] + 1;
+      side_off[e] = stot;
+      stot += (int64_t)6 * m->nvar * n * n;
+    }
+
+    // ---- buckets -----------------------------------------------------------
+    for (int e = 0; e < m->K; ++e) m->bucket[m->degree[e]].push_back(e);
+
+    // ---- device ------------------------------------------------------------
+    MeshView& v = m->view;
+    v.K = m->K;
+    v.nvar = m->nvar;
+    v.n_fv = NFV;
+    v.n_face = m->F;
+    v.n_node = m->n_node;
+    v.elem_offset = m->keep(dev_upload(m->offset));
+    v.degree = m->keep(dev_upload(m->degree));
+    v.metric = m->keep(dev_upload(metric));
+    std::vector<int32_t> faces(d->faces, d->faces + 5 * (size_t)m->F);
+    v.faces = m->keep(dev_upload(faces));
+    v.face_norm_off = m->keep(dev_upload(fnorm_off));
+    v.face_norm = m->keep(dev_upload(fnorm));
+    v.side_off = m->keep(dev_upload(side_off));
+    v.fside = m->keep(dev_alloc<double>(stot));
+    v.fvside = m->keep(dev_alloc<double>((size_t)m->K * 6 * m->nvar * NFV * NFV));
+    v.ubar = m->keep(dev_alloc<double>((size_t)m->K * m->nvar * NFV * NFV * NFV));
+    v.rfv = m->keep(dev_alloc<double>((size_t)m->nvar * m->n_node));
+    v.ops = m->keep(dev_upload(ops));
+    v.tab = tab;
+    v.gas.gamma = d->gamma;
+    if (m->nvar == 6) {
+      v.gas.cv0 = d->R[0] / (d->kappa[0] - 1.0);
+      v.gas.cp0 = d->kappa[0] * v.gas.cv0;
+      v.gas.cv1 = d->R[1] / (d->kappa[1] - 1.0);
+      v.gas.cp1 = d->kappa[1] * v.gas.cv1;
+    } else {
+      v.gas.cv0 = v.gas.cp0 = v.gas.cv1 = v.gas.cp1 = 0.0;
+    }
+    for (int N = 1; N <= MAXN; ++N)
+      if (!m->bucket[N].empty()) m->d_bucket[N] = m->keep(dev_upload(m->bucket[N]));
+    hip_check(hipDeviceSynchronize(), "mesh upload");
+  } catch (const HipError& e) {
+    const std::string msg = e.what();
+    return fail(msg.find("out of memory") != std::string::npos ? DGFV_ERR_OOM : DGFV_ERR_HIP, msg);
+  } catch (const std::exception& e) {
+    return fail(DGFV_ERR_HIP, e.what());
+  }
+  *out = m.release();
+  return DGFV_OK;
+}
+
+void dgfv_mesh_destroy(dgfv_mesh* m) { delete m; }
+
+dgfv_status dgfv_mesh_info(const dgfv_mesh* m, int64_t* n_node, int64_t* elem_offset) {
+  if (!m) return fail(DGFV_ERR_ARG, "mesh is NULL");
+  if (n_node) *n_node = m->n_node;
+  if (elem_offset) std::copy(m->offset.begin(), m->offset.end(), elem_offset);
+  return DGFV_OK;
+}
+
+dgfv_status dgfv_mesh_node_coords(const dgfv_mesh* m, double* xyz) {
+  if (!m || !xyz) return fail(DGFV_ERR_ARG, "NULL argument");
+  std::copy(m->coords.begin(), m->coords.end(), xyz);
+  return DGFV_OK;
+}
+
+dgfv_status dg_indicator(const dgfv_mesh* m, const dgfv_params* prm, const double* u,
+                         double* alpha, double* ind, void* stream) {
+  if (!m || !u || !alpha) return fail(DGFV_ERR_ARG, "NULL argument");
+  if (dgfv_status st = check_params(m, prm)) return st;
+  if (!(prm->ind_dT > 0.0)) return fail(DGFV_ERR_ARG, "ind_dT must be positive");
+  if ((prm->ind_vars & 7) == 0) return fail(DGFV_ERR_ARG, "ind_vars selects no variable");
+  const ParamsDev p = to_dev(prm);
+  try {
+    Timed t(m, DGFV_KERNEL_INDICATOR, (hipStream_t)stream);
+    for (int N = 1; N <= MAXN; ++N)
+      if (!m->bucket[N].empty())
+        hip_check(ops_for(N).indicator(m->view, p, m->d_bucket[N], (int)m->bucket[N].size(), u, alpha,
+                                       ind, (hipStream_t)stream),
+                  "indicator launch");
+  } catch (const HipError& e) {
+    return fail(DGFV_ERR_HIP, e.what());
+  }
+  return DGFV_OK;
+}
+
+dgfv_status dg_rhs(const dgfv_mesh* m, const dgfv_params* prm, const double* u, const double* alpha,
+                   double* ut, void* stream) {
+  if (!m || !u || !ut) return fail(DGFV_ERR_ARG, "NULL argument");
+  if (u == ut) return fail(DGFV_ERR_ARG, "u and ut must not overlap");
+  if (dgfv_status st = check_params(m, prm)) return st;
+  return enqueue_rhs(m, prm, u, alpha, ut, nullptr, 0, 0.0, (hipStream_t)stream);
+}
+
+dgfv_status dg_rk_stage(const dgfv_mesh* m, const dgfv_params* prm, int stage, double dt, double* u,
+                        double* k, const double* alpha, void* stream) {
+  if (!m || !u || !k) return fail(DGFV_ERR_ARG, "NULL argument");
+  if (stage < 1 || stage > 5) return fail(DGFV_ERR_ARG, "stage must be 1..5");
+  if (!std::isfinite(dt)) return fail(DGFV_ERR_ARG, "dt must be finite");
+  if (u == k) return fail(DGFV_ERR_ARG, "u and k must not overlap");
+  if (dgfv_status st = check_params(m, prm)) return st;
+  return enqueue_rhs(m, prm, u, alpha, nullptr, k, stage, dt, (hipStream_t)stream);
+}
+
+dgfv_status dgfv_profile_enable(dgfv_mesh* m, int enable) {
+  if (!m) return fail(DGFV_ERR_ARG, "mesh is NULL");
+  m->profile = enable != 0;
+  for (auto& u : m->ev_used) u = 0;
+  return DGFV_OK;
+}
+
+dgfv_status dgfv_profile_read(dgfv_mesh* m, int kernel, double* total_ms, int64_t* launches) {
+  if (!m || !total_ms || !launches) return fail(DGFV_ERR_ARG, "NULL argument");
+  if (kernel < 0 || kernel >= DGFV_KERNEL_COUNT) return fail(DGFV_ERR_ARG, "kernel id out of range");
+  double tot = 0.0;
+  try {
+    for (size_t i = 0; i < m->ev_used[kernel]; ++i) {
+      auto& pr = m->ev[kernel][i];
+      hip_check(hipEventSynchronize(pr.second), "hipEventSynchronize");
+      float ms = 0.0f;
+      hip_check(hipEventElapsedTime(&ms, pr.first, pr.second), "hipEventElapsedTime");
+      tot += ms;
+    }
+  } catch (const HipError& e) {
+    return fail(DGFV_ERR_HIP, e.what());
+  }
+  *total_ms = tot;
+  *launches = (int64_t)m->ev_used[kernel];
+  return DGFV_OK;
+}
+
+dgfv_status dg_rhs_vjp(const dgfv_mesh* m, const dgfv_params* prm, const double* u,
+                       const double* alpha, const double* w, double* g, int batch, void* stream) {
+  (void)stream;
+  if (!m || !u || !w || !g) return fail(DGFV_ERR_ARG, "NULL argument");
+  if (batch < 1) return fail(DGFV_ERR_ARG, "batch must be positive");
+  if (dgfv_status st = check_params(m, prm)) return st;
+  (void)alpha;
+  return fail(DGFV_ERR_UNSUPPORTED, "dg_rhs_vjp is not available in this build");
+}
+
+}  // extern "C"

@@ -1,0 +1,84 @@
+// Internal declarations shared by the host runtime and the device kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace dgfv {
+
+constexpr int MAXN = 7;   // highest element degree
+constexpr int MAXFV = 8;  // most FV sub-cells per direction
+
+// Offsets (in doubles) of the small 1D operator tables inside one device buffer.
+// A value of -1 marks a table that the mesh does not need.
+struct OpTables {
+  int D[MAXN + 1];                    // (N+1)^2, D[i*(N+1)+j] = l_j'(xi_i)
+  int w[MAXN + 1];                    // (N+1) LGL weights
+  int vleg_inv[MAXN + 1];             // (N+1)^2 nodal -> orthonormal Legendre modal
+  int interp[MAXN + 1][MAXN + 1];     // [N][M]: (M+1) x (N+1), N < M
+  int project[MAXN + 1][MAXN + 1];    // [M][N]: (N+1) x (M+1), M > N, modal L2 truncation
+  int dg2fv[MAXN + 1];                // NFV x (N+1), sub-cell means of l_j
+  int fv2dg[MAXN + 1];                // (N+1) x NFV, pseudo-inverse of dg2fv
+  int face_interp[MAXN + 1];          // (NFV+1) x (N+1), l_j at the sub-cell interfaces
+};
+
+struct GasDev {
+  double gamma;            // single species
+  double cp0, cv0, cp1, cv1;  // two species (Y1 weights species 0)
+};
+
+struct ParamsDev {
+  int volume_flux, face_flux_dg, face_flux_fv;
+  int ind_vars;
+  double ind_T, ind_dT;
+};
+
+// Everything a kernel needs to address the mesh (device pointers).
+struct MeshView {
+  int K, nvar, n_fv, n_face;
+  int64_t n_node;
+  const int64_t* elem_offset;   // [K+1]
+  const int8_t* degree;         // [K]
+  const double* metric;         // [10][n_node]: Ja^d_n at component 3d+n, J at 9
+  const int32_t* faces;         // [F][5]
+  const int64_t* face_norm_off; // [F] offset into face_norm
+  const double* face_norm;      // per face [3][(M+1)^2] left outward n*s at degree M = max(NL,NR)
+  const int64_t* side_off;      // [K] offset of element e's side-flux block: 6*nvar*(N+1)^2 doubles
+  double* fside;                // DG surface fluxes per element side, [6][nvar][(N+1)^2]
+  double* fvside;               // FV sub-face fluxes, [K][6][nvar][NFV^2]
+  double* ubar;                 // sub-cell means, [K][nvar][NFV^3]
+  double* rfv;                  // FV residual in nodal form, [nvar][n_node]
+  const double* ops;            // operator tables
+  OpTables tab;
+  GasDev gas;
+};
+
+// ---- launchers (defined in the .hip translation units) ----------------------
+// Per-degree launchers; each acts on one degree bucket: `count` elements listed
+// in `elist` (device).  stage 0 writes ut = R(u); stage 1..5 performs the RK
+// stage with coefficients (A, B) on u (in place) and k.
+struct DegreeOps {
+  hipError_t (*element)(const MeshView& m, const ParamsDev& p, const int32_t* elist, int count,
+                        const double* u, const double* alpha, double* ut, double* k, int stage,
+                        double dt, double A, double B, hipStream_t s);
+  hipError_t (*fv_means)(const MeshView& m, const int32_t* elist, int count, const double* u,
+                         const double* alpha, hipStream_t s);
+  hipError_t (*fv_residual)(const MeshView& m, const ParamsDev& p, const int32_t* elist, int count,
+                            const double* alpha, hipStream_t s);
+  hipError_t (*indicator)(const MeshView& m, const ParamsDev& p, const int32_t* elist, int count,
+                          const double* u, double* alpha, double* ind, hipStream_t s);
+};
+DegreeOps degree_ops_1();
+DegreeOps degree_ops_2();
+DegreeOps degree_ops_3();
+DegreeOps degree_ops_4();
+DegreeOps degree_ops_5();
+DegreeOps degree_ops_6();
+DegreeOps degree_ops_7();
+
+// All faces: Riemann fluxes into the per-side buffers (DG, mixed-degree and FV faces).
+hipError_t launch_faces(const MeshView& m, const ParamsDev& p, const double* u, const double* alpha,
+                        hipStream_t s);
+
+}  // namespace dgfv

@@ -1,0 +1,21 @@
+// Host-side one-dimensional operator tables (long double, rounded to double).
+#pragma once
+
+#include <vector>
+
+namespace dgfv {
+
+std::vector<long double> lgl_nodes(int N);
+std::vector<long double> lgl_weights(int N);
+
+std::vector<double> op_nodes(int N);
+std::vector<double> op_weights(int N);
+std::vector<double> op_D(int N);                    // (N+1)^2
+std::vector<double> op_vleg_inv(int N);             // (N+1)^2
+std::vector<double> op_interp(int N, int M);        // (M+1) x (N+1)
+std::vector<double> op_project(int M, int N);       // (N+1) x (M+1), M > N
+std::vector<double> op_dg2fv(int N, int NFV);       // NFV x (N+1)
+std::vector<double> op_fv2dg(int N, int NFV);       // (N+1) x NFV
+std::vector<double> op_face_interp(int N, int NFV); // (NFV+1) x (N+1)
+
+}  // namespace dgfv

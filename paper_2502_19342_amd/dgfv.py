@@ -1,0 +1,236 @@
+"""Python binding of the C ABI in ``include/dgfv.h`` (argument marshalling only).
+
+Every computation runs in the HIP library ``libdgfv.so``; this module only
+converts mesh descriptions to the C structs, checks tensor shapes, dtypes and
+devices, and passes device pointers and the current HIP stream.  Importing it
+without the built library raises immediately.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdgfv.so")
+
+OK, ERR_ARG, ERR_UNSUPPORTED, ERR_HIP, ERR_OOM, ERR_STATE = range(6)
+
+
+class DgfvError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"dgfv status {status}: {msg}")
+        self.status = status
+
+
+class _MeshDesc(ctypes.Structure):
+    _fields_ = [("n_elem", ctypes.c_int32), ("n_var", ctypes.c_int32),
+                ("degree", ctypes.POINTER(ctypes.c_int8)), ("corners", ctypes.POINTER(ctypes.c_double)),
+                ("n_face", ctypes.c_int32), ("faces", ctypes.POINTER(ctypes.c_int32)),
+                ("n_fv", ctypes.c_int32), ("metric_degree", ctypes.c_int32),
+                ("gamma", ctypes.c_double), ("kappa", ctypes.c_double * 2), ("R", ctypes.c_double * 2)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("volume_flux", ctypes.c_int32), ("face_flux_dg", ctypes.c_int32),
+                ("face_flux_fv", ctypes.c_int32), ("ind_vars", ctypes.c_int32),
+                ("ind_T", ctypes.c_double), ("ind_dT", ctypes.c_double)]
+
+
+EXPORTED = ("dgfv_mesh_create", "dgfv_mesh_destroy", "dgfv_mesh_info", "dgfv_mesh_node_coords",
+            "dg_indicator", "dg_rhs", "dg_rk_stage", "dg_rhs_vjp", "dgfv_profile_enable",
+            "dgfv_profile_read", "dgfv_last_error")
+KERNEL_ELEMENT, KERNEL_FACE, KERNEL_FV_MEANS, KERNEL_FV_RESIDUAL, KERNEL_INDICATOR, KERNEL_VJP = range(6)
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2502_19342_amd.build`")
+    lib = ctypes.CDLL(path)
+    P, c_int, c_double = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    lib.dgfv_mesh_create.argtypes = [ctypes.POINTER(_MeshDesc), ctypes.POINTER(P)]
+    lib.dgfv_mesh_destroy.argtypes = [P]
+    lib.dgfv_mesh_destroy.restype = None
+    lib.dgfv_mesh_info.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+    lib.dgfv_mesh_node_coords.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
+    lib.dg_indicator.argtypes = [P, ctypes.POINTER(_Params), P, P, P, P]
+    lib.dg_rhs.argtypes = [P, ctypes.POINTER(_Params), P, P, P, P]
+    lib.dg_rk_stage.argtypes = [P, ctypes.POINTER(_Params), c_int, c_double, P, P, P, P]
+    lib.dg_rhs_vjp.argtypes = [P, ctypes.POINTER(_Params), P, P, P, P, c_int, P]
+    lib.dgfv_profile_enable.argtypes = [P, c_int]
+    lib.dgfv_profile_read.argtypes = [P, c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    lib.dgfv_last_error.restype = ctypes.c_char_p
+    for name in EXPORTED:
+        if name not in ("dgfv_mesh_destroy", "dgfv_last_error"):
+            getattr(lib, name).restype = ctypes.c_int
+    return lib
+
+
+_lib = load_library()
+
+
+def _check(status: int):
+    if status != OK:
+        raise DgfvError(status, _lib.dgfv_last_error().decode())
+
+
+@dataclass
+class Params:
+    volume_flux: int = 0
+    face_flux_dg: int = 0
+    face_flux_fv: int = 1
+    ind_vars: int = 1
+    ind_T: float = 2.0
+    ind_dT: float = 1.0
+
+    def c(self) -> _Params:
+        return _Params(self.volume_flux, self.face_flux_dg, self.face_flux_fv, self.ind_vars,
+                       float(self.ind_T), float(self.ind_dT))
+
+
+def params_of(wl) -> Params:
+    return Params(wl.volume_flux, wl.face_flux_dg, wl.face_flux_fv, wl.ind_vars, wl.ind_T, wl.ind_dT)
+
+
+class Mesh:
+    """Device geometry of a conforming hexahedral mesh (owns the library handle)."""
+
+    def __init__(self, degree, corners, faces, n_var=5, n_fv=None, metric_degree=1, gamma=1.4,
+                 kappa=(1.4, 1.4), R=(287.0, 287.0)):
+        self.degree = np.ascontiguousarray(degree, dtype=np.int8)
+        self.corners = np.ascontiguousarray(corners, dtype=np.float64)
+        self.faces = np.ascontiguousarray(faces, dtype=np.int32)
+        K = self.degree.shape[0]
+        if self.corners.shape != (K, 8, 3) or self.faces.ndim != 2 or self.faces.shape[1] != 5:
+            raise ValueError("corners must be [K,8,3] and faces [F,5]")
+        self.n_elem = K
+        self.n_var = int(n_var)
+        self.n_fv = int(n_fv if n_fv is not None else int(self.degree.max()) + 1)
+        desc = _MeshDesc(K, self.n_var, self.degree.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)),
+                         self.corners.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                         self.faces.shape[0], self.faces.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                         self.n_fv, int(metric_degree), float(gamma),
+                         (ctypes.c_double * 2)(*kappa), (ctypes.c_double * 2)(*R))
+        h = ctypes.c_void_p()
+        _check(_lib.dgfv_mesh_create(ctypes.byref(desc), ctypes.byref(h)))
+        self._h = h
+        n = ctypes.c_int64()
+        off = np.zeros(K + 1, dtype=np.int64)
+        _check(_lib.dgfv_mesh_info(h, ctypes.byref(n), off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+        self.n_node = int(n.value)
+        self.elem_offset = off
+
+    @classmethod
+    def from_workload(cls, wl) -> "Mesh":
+        m = wl.mesh
+        return cls(m.degree, m.corners, m.faces, wl.n_var, wl.n_fv, wl.metric_degree, wl.gamma,
+                   tuple(wl.kappa), tuple(wl.R))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.dgfv_mesh_destroy(h)
+            self._h = None
+
+    def profile(self, enable: bool = True) -> None:
+        """Start (clearing the counters) or stop event timing of every kernel launch."""
+        _check(_lib.dgfv_profile_enable(self._h, int(enable)))
+
+    def kernel_time(self, kernel: int):
+        """``(total_ms, launches)`` of one kernel class since profiling was enabled."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        _check(_lib.dgfv_profile_read(self._h, int(kernel), ctypes.byref(ms), ctypes.byref(n)))
+        return float(ms.value), int(n.value)
+
+    def node_coords(self) -> np.ndarray:
+        xyz = np.zeros((3, self.n_node), dtype=np.float64)
+        _check(_lib.dgfv_mesh_node_coords(self._h, xyz.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return xyz
+
+    # ------------------------------------------------------------------
+    def _state(self, t: torch.Tensor, name: str, batch: int | None = None) -> int:
+        shape = (self.n_var, self.n_node) if batch is None else (batch, self.n_var, self.n_node)
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
+            raise TypeError(f"{name} must be a float64 CUDA/HIP tensor")
+        if tuple(t.shape) != shape or not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous with shape {shape}")
+        return t.data_ptr()
+
+    def _alpha(self, a) -> int | None:
+        if a is None:
+            return None
+        if a.dtype != torch.float64 or not a.is_cuda or tuple(a.shape) != (self.n_elem,) or not a.is_contiguous():
+            raise ValueError("alpha must be a contiguous float64 device tensor of shape [n_elem]")
+        return a.data_ptr()
+
+
+def _stream(stream) -> int | None:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+def rhs(mesh: Mesh, params: Params, u: torch.Tensor, alpha: torch.Tensor | None = None,
+        out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """``R(u)`` (``dg_rhs``)."""
+    if out is None:
+        out = torch.empty_like(u)
+    _check(_lib.dg_rhs(mesh._h, ctypes.byref(params.c()), mesh._state(u, "u"), mesh._alpha(alpha),
+                       mesh._state(out, "out"), _stream(stream)))
+    return out
+
+
+def rk_stage(mesh: Mesh, params: Params, stage: int, dt: float, u: torch.Tensor, k: torch.Tensor,
+             alpha: torch.Tensor | None = None, stream=None) -> None:
+    """In-place 2N Runge-Kutta stage ``stage`` in 1..5 (``dg_rk_stage``)."""
+    _check(_lib.dg_rk_stage(mesh._h, ctypes.byref(params.c()), int(stage), float(dt),
+                            mesh._state(u, "u"), mesh._state(k, "k"), mesh._alpha(alpha), _stream(stream)))
+
+
+def rk_step(mesh: Mesh, params: Params, dt: float, u: torch.Tensor, k: torch.Tensor,
+            alpha: torch.Tensor | None = None, stream=None) -> None:
+    for s in range(1, 6):
+        rk_stage(mesh, params, s, dt, u, k, alpha, stream)
+
+
+def indicator(mesh: Mesh, params: Params, u: torch.Tensor, stream=None):
+    """Per-element ``(alpha, I)`` (``dg_indicator``)."""
+    alpha = torch.empty(mesh.n_elem, dtype=torch.float64, device=u.device)
+    ind = torch.empty_like(alpha)
+    _check(_lib.dg_indicator(mesh._h, ctypes.byref(params.c()), mesh._state(u, "u"), alpha.data_ptr(),
+                             ind.data_ptr(), _stream(stream)))
+    return alpha, ind
+
+
+def rhs_vjp(mesh: Mesh, params: Params, u: torch.Tensor, alpha: torch.Tensor | None, w: torch.Tensor,
+            out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """``(dR/du)^T w`` for a batch ``w[B, n_var, n_node]`` (``dg_rhs_vjp``)."""
+    squeeze = w.dim() == 2
+    if squeeze:
+        w = w.unsqueeze(0)
+    B = w.shape[0]
+    if out is None:
+        out = torch.empty_like(w)
+    _check(_lib.dg_rhs_vjp(mesh._h, ctypes.byref(params.c()), mesh._state(u, "u"), mesh._alpha(alpha),
+                           mesh._state(w, "w", B), mesh._state(out, "out", B), B, _stream(stream)))
+    return out[0] if squeeze else out
+
+
+def prim_to_cons(w: np.ndarray, n_var: int, gamma: float = 1.4, kappa=(1.4, 1.4), R=(287.0, 287.0)) -> np.ndarray:
+    """Primitive (rho, v1, v2, v3, p[, Y1]) -> conservative variables, host arrays (input preparation)."""
+    rho, v, p = w[0], w[1:4], w[4]
+    if n_var == 6:
+        Y = w[5]
+        cv = [R[j] / (kappa[j] - 1.0) for j in range(2)]
+        cp = [kappa[j] * cv[j] for j in range(2)]
+        kap = (Y * cp[0] + (1 - Y) * cp[1]) / (Y * cv[0] + (1 - Y) * cv[1])
+    else:
+        kap = gamma
+    E = p / (kap - 1.0) + 0.5 * rho * (v * v).sum(0)
+    comps = [rho, rho * v[0], rho * v[1], rho * v[2], E]
+    if n_var == 6:
+        comps.append(rho * w[5])
+    return np.stack(comps)

@@ -1,0 +1,138 @@
+"""Parity of the HIP right-hand side with the CPU oracle, element by element.
+
+Bar: max-norm error per variable <= 1e-12 of the oracle's max norm for one RHS
+evaluation; <= 1e-10 after the Runge-Kutta runs.  Inputs are generated on the
+oracle side (its own node coordinates) and copied to the device.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import lsrk
+from paper_2502_19342_amd import workloads as W
+
+from gpu_common import Case, announce, rel_err
+from oracle_cases import curved_mixed, seeded_alpha, smooth_state
+
+pytestmark = pytest.mark.gpu
+T = torch.float64
+RHS_TOL = 1e-12
+STEP_TOL = 1e-10
+
+
+def test_c1_density_wave_rhs():
+    announce("C1 rhs")
+    c = Case(W.make_workload("C1"))
+    r_gpu = c.gpu_rhs()
+    r_ora = c.oracle_rhs()
+    assert rel_err(r_gpu, r_ora) <= RHS_TOL
+    # alpha = NULL and alpha = 0 take different code paths but give the same numbers
+    r_null = c.gpu_rhs(alpha=None)
+    assert torch.equal(r_null, r_gpu)
+
+
+@pytest.mark.parametrize("vol,face", [(W.VOL_PIROZZOLI, W.RIEMANN_ROE_HH), (W.VOL_CENTRAL, W.RIEMANN_LLF),
+                                      (W.VOL_RANOCHA, W.RIEMANN_EC)])
+def test_flux_choices_rhs(vol, face):
+    announce(f"flux choices {vol} {face}")
+    wl = curved_mixed(n=3, nmin=3, nmax=3, scramble=4, volume_flux=vol, face_dg=face)
+    c = Case(wl, prim=smooth_state(71), noise=1e-3, seed=1)
+    assert rel_err(c.gpu_rhs(), c.oracle_rhs()) <= RHS_TOL
+
+
+@pytest.mark.parametrize("scramble", [None, 9])
+def test_curved_mixed_degree_blended_rhs(scramble):
+    announce(f"curved mixed blended scramble={scramble}")
+    wl = curved_mixed(n=3, nmin=1, nmax=4, scramble=scramble, metric_degree=1, n_fv=5)
+    c = Case(wl, prim=smooth_state(73), noise=1e-3, seed=2)
+    c.alpha = seeded_alpha(c.mesh.K, 11, values=(0.0, 0.0, 0.35, 1.0))
+    assert rel_err(c.gpu_rhs(), c.oracle_rhs()) <= RHS_TOL
+
+
+def test_two_species_mixed_degree_blended_rhs():
+    announce("two species mixed blended")
+    wl = curved_mixed(n=3, nmin=2, nmax=5, n_var=6, scramble=5, volume_flux=W.VOL_PIROZZOLI,
+                      face_dg=W.RIEMANN_LLF, n_fv=8)
+    c = Case(wl, prim=smooth_state(75, n_var=6), noise=1e-3, seed=3)
+    c.alpha = seeded_alpha(c.mesh.K, 12, values=(0.0, 0.5, 1.0))
+    assert rel_err(c.gpu_rhs(), c.oracle_rhs()) <= RHS_TOL
+
+
+def test_freestream_on_gpu():
+    announce("free-stream")
+    wl = curved_mixed(n=3, nmin=1, nmax=5, scramble=6, metric_degree=1, n_fv=6)
+    c = Case(wl, prim=lambda x: W.freestream(x))
+    c.alpha = seeded_alpha(c.mesh.K, 13)
+    r = c.gpu_rhs()
+    # scale: the largest single term of R (volume sum over J), as in the oracle's own pin
+    from test_oracle_rhs import term_scale
+    scale = term_scale(c.mesh, c.gas, c.f.params, c.u)
+    assert float(r.abs().max()) <= 1e-13 * scale
+    assert float((r - c.oracle_rhs()).abs().max()) <= 1e-13 * scale
+
+
+def test_conservation_on_gpu():
+    announce("conservation")
+    wl = curved_mixed(n=3, nmin=1, nmax=4, scramble=7, metric_degree=1, n_fv=6)
+    c = Case(wl, prim=smooth_state(77), noise=1e-2, seed=4)
+    c.alpha = seeded_alpha(c.mesh.K, 14)
+    r = c.gpu_rhs()
+    w = c.mesh.weights_flat() * c.mesh.jacobian_flat()
+    tot = (r * w).sum(1)
+    mag = (r * w).abs().sum(1)
+    assert torch.all(tot.abs() <= 1e-13 * mag)
+
+
+def test_indicator_parity_blast():
+    announce("indicator C2 small")
+    wl = W.make_workload("C2", n=4)
+    c = Case(wl)
+    from paper_2502_19342_amd import dgfv
+    a_gpu, i_gpu = dgfv.indicator(c.gmesh, c.params, c.gpu(c.u))
+    torch.cuda.synchronize()
+    I_ora, a_ora = c.oracle_indicator()
+    fin = torch.isfinite(I_ora)
+    assert torch.equal(torch.isfinite(i_gpu.cpu()), fin)
+    assert torch.allclose(i_gpu.cpu()[fin], I_ora[fin], rtol=1e-11, atol=1e-11)
+    assert torch.allclose(a_gpu.cpu(), a_ora, rtol=0, atol=1e-10)
+    assert float(a_ora.max()) > 0
+    # RHS with the oracle's blending factors
+    c.alpha = a_ora
+    assert rel_err(c.gpu_rhs(), c.oracle_rhs()) <= RHS_TOL
+
+
+def _gpu_steps(c, dt, n):
+    from paper_2502_19342_amd import dgfv
+    u = c.gpu(c.u)
+    k = torch.full_like(u, float("nan"))      # stage 1 must not read k
+    a = c.gpu(c.alpha)
+    for _ in range(n):
+        dgfv.rk_step(c.gmesh, c.params, dt, u, k, a)
+    torch.cuda.synchronize()
+    return u.cpu()
+
+
+def _oracle_steps(c, dt, n):
+    u = c.u.clone()
+    for _ in range(n):
+        u = lsrk.step(lambda v: c.f(v, c.alpha), u, dt)
+    return u
+
+
+def test_c1_ten_rk_steps():
+    announce("C1 10 steps")
+    wl = W.make_workload("C1")
+    c = Case(wl)
+    dt = lsrk.timestep(c.mesh, c.gas, c.u, wl.cfl)
+    assert rel_err(_gpu_steps(c, dt, 10), _oracle_steps(c, dt, 10)) <= STEP_TOL
+
+
+def test_hybrid_mixed_rk_steps():
+    announce("hybrid mixed 20 steps")
+    wl = curved_mixed(n=2, nmin=2, nmax=4, scramble=8, n_fv=5)
+    c = Case(wl, prim=smooth_state(79), noise=1e-3, seed=5)
+    c.alpha = seeded_alpha(c.mesh.K, 15, values=(0.0, 0.3, 1.0))
+    dt = lsrk.timestep(c.mesh, c.gas, c.u, 0.5, c.alpha)
+    assert rel_err(_gpu_steps(c, dt, 20), _oracle_steps(c, dt, 20)) <= STEP_TOL
