@@ -399,6 +399,336 @@ indicator_kernel(MeshView m, ParamsDev prm, const int32_t* __restrict__ elist, i
 }
 
 // ---------------------------------------------------------------------------
+// adjoint (vector-Jacobian product) with alpha frozen.
+// Forward: R = (1 - alpha) R^DG + alpha R^FV with
+//   R^DG_i = -(1/J_i) [ sum_d sum_{m != i} 2 D_im F#d(u_i, u_m) + lift_i(F_side) ].
+// With a_i = -(1 - alpha) w_i / J_i and the symmetry of F#,
+//   g_j = sum_d sum_{m != j} (d F#d(u_j, u_m) / d u_j)^T (2 D_jm a_j + 2 D_mj a_m),
+// evaluated per node through the flux record: the record adjoint is summed
+// over the pairs and mapped to u once (make_adj).  The lift gives the side
+// cotangents a_i / w_0 at the boundary nodes.
+// ---------------------------------------------------------------------------
+template <int N, int NV, class FLUX>
+__global__ void __launch_bounds__(Geo<N>::EPB * Geo<N>::NP3)
+vjp_volume_kernel(MeshView m, const int32_t* __restrict__ elist, int count,
+                  const double* __restrict__ u, const double* __restrict__ alpha,
+                  const double* __restrict__ w, double* __restrict__ g) {
+  using G = Geo<N>;
+  constexpr int NP = G::NP, NP2 = G::NP2, NP3 = G::NP3, EPB = G::EPB;
+  constexpr int NA = FLUX::NA;
+  __shared__ double sD[NP * NP];
+  __shared__ double sAux[EPB][NA][NP3];
+  __shared__ double sJa[EPB][9][NP3];
+  __shared__ double sA[EPB][NV][NP3];
+
+  const int tid = threadIdx.x;
+  const int slot = tid / NP3;
+  const int node = tid - slot * NP3;
+  const int idx = blockIdx.x * EPB + slot;
+  const bool active = idx < count;
+  for (int t = tid; t < NP * NP; t += blockDim.x) sD[t] = 2.0 * m.ops[m.tab.D[N] + t];
+
+  int e = 0;
+  int64_t base = 0;
+  double uo[NV], ame[NV];
+  if (active) {
+    e = elist[idx];
+    base = m.elem_offset[e] + node;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) uo[v] = u[v * m.n_node + base];
+    const Prim q = cons2prim<NV>(uo, m.gas);
+    double r[NA];
+    FLUX::template make<NV>(q, r);
+#pragma unroll
+    for (int a = 0; a < NA; ++a) sAux[slot][a][node] = r[a];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) sJa[slot][c][node] = m.metric[c * m.n_node + base];
+    const double al = alpha ? alpha[e] : 0.0;
+    const double sc = -(1.0 - al) / m.metric[9 * m.n_node + base];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      ame[v] = sc * w[v * m.n_node + base];
+      sA[slot][v][node] = ame[v];
+    }
+  }
+  __syncthreads();
+  if (!active) return;
+
+  const int i = node % NP, j = (node / NP) % NP, kk = node / NP2;
+  double me[NA], ab[NA];
+#pragma unroll
+  for (int a = 0; a < NA; ++a) {
+    me[a] = sAux[slot][a][node];
+    ab[a] = 0.0;
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int id = d == 0 ? i : (d == 1 ? j : kk);
+    const int stride = d == 0 ? 1 : (d == 1 ? NP : NP2);
+    const double ja1 = sJa[slot][3 * d + 0][node];
+    const double ja2 = sJa[slot][3 * d + 1][node];
+    const double ja3 = sJa[slot][3 * d + 2][node];
+#pragma unroll 1
+    for (int o = 1; o < NP; ++o) {
+      int mm = id + o;
+      if (mm >= NP) mm -= NP;
+      const int pn = node + (mm - id) * stride;
+      double other[NA], c[NV];
+#pragma unroll
+      for (int a = 0; a < NA; ++a) other[a] = sAux[slot][a][pn];
+      const double cme = sD[id * NP + mm], cot = sD[mm * NP + id];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) c[v] = cme * ame[v] + cot * sA[slot][v][pn];
+      const double a1 = 0.5 * (ja1 + sJa[slot][3 * d + 0][pn]);
+      const double a2 = 0.5 * (ja2 + sJa[slot][3 * d + 1][pn]);
+      const double a3 = 0.5 * (ja3 + sJa[slot][3 * d + 2][pn]);
+      FLUX::template flux_adj_a<NV>(me, other, a1, a2, a3, m.gas, c, ab);
+    }
+  }
+  double ub[NV];
+  FLUX::template make_adj<NV>(uo, m.gas, ab, ub);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) g[v * m.n_node + base] = ub[v];
+
+  // cotangents of the side fluxes through the lift
+  const double inv_w0 = 1.0 / m.ops[m.tab.w[N]];
+  double* fs = m.fside + m.side_off[e];
+  auto put_side = [&](int s, int fidx) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) fs[(s * NV + v) * NP2 + fidx] = ame[v] * inv_w0;
+  };
+  if (i == 0) put_side(0, kk * NP + j);
+  if (i == N) put_side(1, kk * NP + j);
+  if (j == 0) put_side(2, kk * NP + i);
+  if (j == N) put_side(3, kk * NP + i);
+  if (kk == 0) put_side(4, j * NP + i);
+  if (kk == N) put_side(5, j * NP + i);
+}
+
+// Adjoint of the FV residual of a blended element: from w to the cotangents of
+// its sub-cell means (internal sub-faces) and of its boundary sub-face fluxes.
+//   R^FV = V3^+(dC) / (h^3 J)           ->  dCb = V3^+^T (alpha w / (h^3 J))
+//   dC[s] -= G[s+1] - G[s] along each d  ->  Gb[q] = dCb[q] - dCb[q-1]
+//   internal G = Riemann(ubar_l, ubar_r) ->  ubar_bar via the Riemann VJP
+//   G[0] = -F_fv(side 2d), G[NFV] = F_fv(side 2d+1)
+template <int N, int NV>
+__global__ void __launch_bounds__(FV_THREADS)
+vjp_fv_kernel(MeshView m, ParamsDev prm, const int32_t* __restrict__ elist, int count,
+              const double* __restrict__ alpha, const double* __restrict__ w) {
+  constexpr int NP = N + 1, NP3 = NP * NP * NP;
+  constexpr int S3MAX = MAXFV * MAXFV * MAXFV;
+  constexpr int NRM = 3 * (MAXFV + 1) * MAXFV * MAXFV;
+  __shared__ double sU[NV * S3MAX];
+  __shared__ double sC[NV * S3MAX];
+  __shared__ double sUb[NV * S3MAX];
+  __shared__ double sJa[9 * NP3];
+  __shared__ double sNrm[NRM];
+  __shared__ double sScr[NRM];
+  __shared__ double sV[MAXFV * (MAXN + 1)];
+  __shared__ double sVpT[MAXFV * (MAXN + 1)];
+  __shared__ double sI[(MAXFV + 1) * (MAXN + 1)];
+
+  const int idx = blockIdx.x;
+  if (idx >= count) return;
+  const int e = elist[idx];
+  const double al = alpha[e];
+  if (!(al > 0.0)) return;
+  const int NFV = m.n_fv;
+  const int S2 = NFV * NFV, S3 = S2 * NFV;
+  const double h = 2.0 / NFV;
+  const int64_t base = m.elem_offset[e];
+  const double* ub = m.ubar + (size_t)e * NV * S3;
+  for (int t = threadIdx.x; t < NV * S3; t += blockDim.x) sU[t] = ub[t];
+  for (int t = threadIdx.x; t < 9 * NP3; t += blockDim.x)
+    sJa[t] = m.metric[(t / NP3) * m.n_node + base + (t % NP3)];
+  for (int t = threadIdx.x; t < NFV * NP; t += blockDim.x) {
+    sV[t] = m.ops[m.tab.dg2fv[N] + t];
+    sVpT[t] = m.ops[m.tab.fv2dgT[N] + t];
+  }
+  for (int t = threadIdx.x; t < (NFV + 1) * NP; t += blockDim.x) sI[t] = m.ops[m.tab.face_interp[N] + t];
+  const double ih3 = 1.0 / (h * h * h);
+  for (int t = threadIdx.x; t < NP3; t += blockDim.x) {
+    const double sc = al * ih3 / m.metric[9 * m.n_node + base + t];
+    for (int v = 0; v < NV; ++v) sUb[v * NP3 + t] = sc * w[v * m.n_node + base + t];
+  }
+  __syncthreads();
+  // dCb = (V^+)^T (x) (V^+)^T (x) (V^+)^T q
+  contract_axis(sUb, sC, sVpT, NFV, NP, NV, NP, NP, NP, 0);
+  __syncthreads();
+  contract_axis(sC, sUb, sVpT, NFV, NP, NV, NP, NP, NFV, 1);
+  __syncthreads();
+  contract_axis(sUb, sC, sVpT, NFV, NP, NV, NP, NFV, NFV, 2);
+  __syncthreads();
+  for (int t = threadIdx.x; t < NV * S3; t += blockDim.x) sUb[t] = 0.0;
+
+  double* fvs = m.fvside + (size_t)e * 6 * NV * S2;
+  for (int d = 0; d < 3; ++d) {
+    __syncthreads();
+    // sub-face normals, exactly as in the forward residual
+    const double* src = sJa + 3 * d * NP3;
+    contract_axis(src, sScr, sI, NFV + 1, NP, 3, NP, NP, NP, d);
+    __syncthreads();
+    int a2 = (d == 2) ? NFV + 1 : NP, a1 = (d == 1) ? NFV + 1 : NP, a0 = (d == 0) ? NFV + 1 : NP;
+    const int ta = (d == 0) ? 1 : 0;
+    const int tb = (d == 2) ? 1 : 2;
+    contract_axis(sScr, sNrm, sV, NFV, NP, 3, a2, a1, a0, ta);
+    __syncthreads();
+    if (ta == 0) a0 = NFV; else a1 = NFV;
+    contract_axis(sNrm, sScr, sV, NFV, NP, 3, a2, a1, a0, tb);
+    __syncthreads();
+    if (tb == 1) a1 = NFV; else a2 = NFV;
+    const int nn = a2 * a1 * a0;
+    for (int t = threadIdx.x; t < 3 * nn; t += blockDim.x) sNrm[t] = sScr[t] * (h * h);
+    __syncthreads();
+    const int stride = d == 0 ? 1 : (d == 1 ? NFV : S2);
+    for (int t = threadIdx.x; t < S3; t += blockDim.x) {
+      const int s0 = t % NFV, s1 = (t / NFV) % NFV, s2 = t / S2;
+      const int sd = d == 0 ? s0 : (d == 1 ? s1 : s2);
+      int lo;
+      if (d == 0) lo = (s2 * NFV + s1) * (NFV + 1) + s0;
+      else if (d == 1) lo = (s2 * (NFV + 1) + s1) * NFV + s0;
+      else lo = (s2 * NFV + s1) * NFV + s0;
+      const int istr = d == 0 ? 1 : (d == 1 ? NFV : S2);   // interface stride along d
+      const int hi = lo + istr;
+      double acc[NV];
+      for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+      double uc[NV];
+      for (int v = 0; v < NV; ++v) uc[v] = sU[v * S3 + t];
+      if (sd + 1 <= NFV - 1) {   // internal interface on the +d side: this cell is its left state
+        double un[NV], Gb[NV], r[NV];
+        for (int v = 0; v < NV; ++v) {
+          un[v] = sU[v * S3 + t + stride];
+          Gb[v] = sC[v * S3 + t + stride] - sC[v * S3 + t];
+        }
+        riemann_vjp_side<NV>(0, prm.face_flux_fv, prm.volume_flux, uc, un, sNrm[hi], sNrm[nn + hi],
+                             sNrm[2 * nn + hi], m.gas, Gb, r);
+        for (int v = 0; v < NV; ++v) acc[v] += r[v];
+      }
+      if (sd >= 1) {             // internal interface on the -d side: this cell is its right state
+        double un[NV], Gb[NV], r[NV];
+        for (int v = 0; v < NV; ++v) {
+          un[v] = sU[v * S3 + t - stride];
+          Gb[v] = sC[v * S3 + t] - sC[v * S3 + t - stride];
+        }
+        riemann_vjp_side<NV>(1, prm.face_flux_fv, prm.volume_flux, un, uc, sNrm[lo], sNrm[nn + lo],
+                             sNrm[2 * nn + lo], m.gas, Gb, r);
+        for (int v = 0; v < NV; ++v) acc[v] += r[v];
+      }
+      for (int v = 0; v < NV; ++v) sUb[v * S3 + t] += acc[v];
+      // boundary sub-face flux cotangents
+      int fp, fq;
+      if (d == 0) { fp = s1; fq = s2; }
+      else if (d == 1) { fp = s0; fq = s2; }
+      else { fp = s0; fq = s1; }
+      if (sd == 0)
+        for (int v = 0; v < NV; ++v) fvs[((2 * d) * NV + v) * S2 + fq * NFV + fp] = -sC[v * S3 + t];
+      if (sd == NFV - 1)
+        for (int v = 0; v < NV; ++v) fvs[((2 * d + 1) * NV + v) * S2 + fq * NFV + fp] = -sC[v * S3 + t];
+    }
+  }
+  __syncthreads();
+  double* out = m.ubar_bar + (size_t)e * NV * S3;
+  for (int t = threadIdx.x; t < NV * S3; t += blockDim.x) out[t] = sUb[t];
+}
+
+// Gather of the trace cotangents (left in fside by the face adjoint) into g,
+// one thread per node.
+template <int N, int NV>
+__global__ void __launch_bounds__(Geo<N>::EPB * Geo<N>::NP3)
+vjp_trace_kernel(MeshView m, const int32_t* __restrict__ elist, int count, double* __restrict__ g) {
+  using G = Geo<N>;
+  constexpr int NP = G::NP, NP2 = G::NP2, NP3 = G::NP3, EPB = G::EPB;
+  const int tid = threadIdx.x;
+  const int slot = tid / NP3;
+  const int node = tid - slot * NP3;
+  const int idx = blockIdx.x * EPB + slot;
+  if (idx >= count) return;
+  const int e = elist[idx];
+  const int i = node % NP, j = (node / NP) % NP, kk = node / NP2;
+  if (!(i == 0 || i == N || j == 0 || j == N || kk == 0 || kk == N)) return;
+  const int64_t base = m.elem_offset[e] + node;
+  const double* fs = m.fside + m.side_off[e];
+  double acc[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+  auto add_side = [&](int s, int fidx) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] += fs[(s * NV + v) * NP2 + fidx];
+  };
+  if (i == 0) add_side(0, kk * NP + j);
+  if (i == N) add_side(1, kk * NP + j);
+  if (j == 0) add_side(2, kk * NP + i);
+  if (j == N) add_side(3, kk * NP + i);
+  if (kk == 0) add_side(4, j * NP + i);
+  if (kk == N) add_side(5, j * NP + i);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) g[v * m.n_node + base] += acc[v];
+}
+
+// Adjoint of the sub-cell means of a blended element:
+//   ubar = V3(J u) / V3(J)  ->  g += J (V^T (x) V^T (x) V^T)(ubar_bar / V3(J)),
+// where ubar_bar collects the internal part (vjp_fv) and the boundary-layer
+// trace cotangents of the six sides (left in fvside by the face adjoint).
+template <int N, int NV>
+__global__ void __launch_bounds__(FV_THREADS)
+vjp_fv_gather_kernel(MeshView m, const int32_t* __restrict__ elist, int count,
+                     const double* __restrict__ alpha, double* __restrict__ g) {
+  constexpr int NP = N + 1, NP3 = NP * NP * NP;
+  constexpr int CAP = (NV + 1) * MAXFV * MAXFV * MAXFV;
+  __shared__ double bufA[CAP];
+  __shared__ double bufB[CAP];
+  __shared__ double sV[MAXFV * (MAXN + 1)];
+  __shared__ double sVT[MAXFV * (MAXN + 1)];
+  const int idx = blockIdx.x;
+  if (idx >= count) return;
+  const int e = elist[idx];
+  if (!(alpha[e] > 0.0)) return;
+  const int NFV = m.n_fv;
+  const int S2 = NFV * NFV, S3 = S2 * NFV;
+  const int64_t base = m.elem_offset[e];
+  for (int t = threadIdx.x; t < NFV * NP; t += blockDim.x) {
+    sV[t] = m.ops[m.tab.dg2fv[N] + t];
+    sVT[t] = m.ops[m.tab.dg2fvT[N] + t];
+  }
+  for (int t = threadIdx.x; t < NP3; t += blockDim.x) bufA[t] = m.metric[9 * m.n_node + base + t];
+  __syncthreads();
+  // V3(J)
+  contract_axis(bufA, bufB, sV, NFV, NP, 1, NP, NP, NP, 0);
+  __syncthreads();
+  contract_axis(bufB, bufA, sV, NFV, NP, 1, NP, NP, NFV, 1);
+  __syncthreads();
+  contract_axis(bufA, bufB, sV, NFV, NP, 1, NP, NFV, NFV, 2);   // bufB[0..S3) = V3(J)
+  __syncthreads();
+  const double* ubb = m.ubar_bar + (size_t)e * NV * S3;
+  const double* fvs = m.fvside + (size_t)e * 6 * NV * S2;
+  for (int t = threadIdx.x; t < S3; t += blockDim.x) {
+    const int s0 = t % NFV, s1 = (t / NFV) % NFV, s2 = t / S2;
+    const double ivol = 1.0 / bufB[t];
+    for (int v = 0; v < NV; ++v) {
+      double x = ubb[v * S3 + t];
+      if (s0 == 0) x += fvs[(0 * NV + v) * S2 + s2 * NFV + s1];
+      if (s0 == NFV - 1) x += fvs[(1 * NV + v) * S2 + s2 * NFV + s1];
+      if (s1 == 0) x += fvs[(2 * NV + v) * S2 + s2 * NFV + s0];
+      if (s1 == NFV - 1) x += fvs[(3 * NV + v) * S2 + s2 * NFV + s0];
+      if (s2 == 0) x += fvs[(4 * NV + v) * S2 + s1 * NFV + s0];
+      if (s2 == NFV - 1) x += fvs[(5 * NV + v) * S2 + s1 * NFV + s0];
+      bufA[v * S3 + t] = x * ivol;
+    }
+  }
+  __syncthreads();
+  contract_axis(bufA, bufB, sVT, NP, NFV, NV, NFV, NFV, NFV, 0);
+  __syncthreads();
+  contract_axis(bufB, bufA, sVT, NP, NFV, NV, NFV, NFV, NP, 1);
+  __syncthreads();
+  contract_axis(bufA, bufB, sVT, NP, NFV, NV, NFV, NP, NP, 2);
+  __syncthreads();
+  for (int t = threadIdx.x; t < NP3; t += blockDim.x) {
+    const double J = m.metric[9 * m.n_node + base + t];
+    for (int v = 0; v < NV; ++v) g[v * m.n_node + base + t] += J * bufB[v * NP3 + t];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // launchers for this degree
 // ---------------------------------------------------------------------------
 template <int NV, class FLUX>
@@ -455,6 +785,56 @@ hipError_t indicator(const MeshView& m, const ParamsDev& p, const int32_t* elist
     hipLaunchKernelGGL((indicator_kernel<kN, 6>), dim3(count), dim3(64), 0, s, m, p, elist, count, u, alpha, ind);
   return hipGetLastError();
 }
+
+template <int NV, class FLUX>
+hipError_t launch_vjp_volume_t(const MeshView& m, const int32_t* elist, int count, const double* u,
+                               const double* alpha, const double* w, double* g, hipStream_t s) {
+  using G = Geo<kN>;
+  const int blocks = (count + G::EPB - 1) / G::EPB;
+  hipLaunchKernelGGL((vjp_volume_kernel<kN, NV, FLUX>), dim3(blocks), dim3(G::EPB * G::NP3), 0, s, m,
+                     elist, count, u, alpha, w, g);
+  return hipGetLastError();
+}
+
+hipError_t vjp_volume(const MeshView& m, const ParamsDev& p, const int32_t* elist, int count,
+                      const double* u, const double* alpha, const double* w, double* g, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  if (m.nvar == 5) {
+    if (p.volume_flux == 0) return launch_vjp_volume_t<5, FluxRanocha>(m, elist, count, u, alpha, w, g, s);
+    if (p.volume_flux == 1) return launch_vjp_volume_t<5, FluxPirozzoli>(m, elist, count, u, alpha, w, g, s);
+    return launch_vjp_volume_t<5, FluxCentral>(m, elist, count, u, alpha, w, g, s);
+  }
+  if (p.volume_flux == 1) return launch_vjp_volume_t<6, FluxPirozzoli>(m, elist, count, u, alpha, w, g, s);
+  return launch_vjp_volume_t<6, FluxCentral>(m, elist, count, u, alpha, w, g, s);
+}
+
+hipError_t vjp_fv(const MeshView& m, const ParamsDev& p, const int32_t* elist, int count,
+                  const double* alpha, const double* w, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  if (m.nvar == 5)
+    hipLaunchKernelGGL((vjp_fv_kernel<kN, 5>), dim3(count), dim3(FV_THREADS), 0, s, m, p, elist, count, alpha, w);
+  else
+    hipLaunchKernelGGL((vjp_fv_kernel<kN, 6>), dim3(count), dim3(FV_THREADS), 0, s, m, p, elist, count, alpha, w);
+  return hipGetLastError();
+}
+
+hipError_t vjp_gather(const MeshView& m, const int32_t* elist, int count, const double* alpha,
+                      double* g, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  using G = Geo<kN>;
+  const int blocks = (count + G::EPB - 1) / G::EPB;
+  if (m.nvar == 5)
+    hipLaunchKernelGGL((vjp_trace_kernel<kN, 5>), dim3(blocks), dim3(G::EPB * G::NP3), 0, s, m, elist, count, g);
+  else
+    hipLaunchKernelGGL((vjp_trace_kernel<kN, 6>), dim3(blocks), dim3(G::EPB * G::NP3), 0, s, m, elist, count, g);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess || !alpha) return err;
+  if (m.nvar == 5)
+    hipLaunchKernelGGL((vjp_fv_gather_kernel<kN, 5>), dim3(count), dim3(FV_THREADS), 0, s, m, elist, count, alpha, g);
+  else
+    hipLaunchKernelGGL((vjp_fv_gather_kernel<kN, 6>), dim3(count), dim3(FV_THREADS), 0, s, m, elist, count, alpha, g);
+  return hipGetLastError();
+}
 }  // namespace per_degree
 }  // namespace
 
@@ -462,8 +842,9 @@ hipError_t indicator(const MeshView& m, const ParamsDev& p, const int32_t* elist
 #define DGFV_CAT2(a, b) a##b
 #define DGFV_CAT(a, b) DGFV_CAT2(a, b)
 DegreeOps DGFV_CAT(degree_ops_, DGFV_N)() {
-  return DegreeOps{&per_degree::element, &per_degree::fv_means, &per_degree::fv_residual,
-                   &per_degree::indicator};
+  return DegreeOps{&per_degree::element,    &per_degree::fv_means, &per_degree::fv_residual,
+                   &per_degree::indicator,  &per_degree::vjp_volume, &per_degree::vjp_fv,
+                   &per_degree::vjp_gather};
 }
 
 }  // namespace dgfv

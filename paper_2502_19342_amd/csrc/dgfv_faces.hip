@@ -204,7 +204,185 @@ face_kernel(MeshView m, ParamsDev prm, const double* __restrict__ u, const doubl
   write_side<NV>(bR, sR, sideR, o, true, nR, -ih2);
 }
 
+// Gather side data [NV][n*n] from a side block (`right` re-indexes onto the left grid).
+template <int NV>
+__device__ void gather_side(const double* blk, int side, int o, bool right, int n, double* dst) {
+  const int n2 = n * n;
+  for (int t = threadIdx.x; t < n2; t += blockDim.x) {
+    int p = t % n, q = t / n;
+    if (right) orient_map(o, p, q, n, p, q);
+    for (int v = 0; v < NV; ++v) dst[v * GRID + t] = blk[(side * NV + v) * n2 + q * n + p];
+  }
+}
+
+// Adjoint of face_kernel.  On entry fside holds, per element side, the
+// cotangent of the side flux it received; fvside holds the cotangents of the
+// FV side fluxes of blended elements.  On exit fside holds the cotangents of
+// each side's nodal trace, and fvside (blended sides of FV faces) those of the
+// boundary sub-cell means.  Each element side belongs to one face, so the
+// in-place update has no cross-workgroup hazard.
+template <int NV>
+__global__ void __launch_bounds__(FACE_THREADS)
+face_vjp_kernel(MeshView m, ParamsDev prm, const double* __restrict__ u, const double* __restrict__ alpha) {
+  __shared__ double sL[NV * GRID];
+  __shared__ double sR[NV * GRID];
+  __shared__ double sF[NV * GRID];
+  __shared__ double sN[3 * GRID];
+  __shared__ double sTmp[3 * NV * GRID];
+
+  const int f = blockIdx.x;
+  if (f >= m.n_face) return;
+  const int32_t* fc = m.faces + 5 * f;
+  const int eL = fc[0], sideL = fc[1], eR = fc[2], sideR = fc[3], o = fc[4];
+  const int NL = m.degree[eL], NR = m.degree[eR];
+  const int M = NL > NR ? NL : NR;
+  const int nL = NL + 1, nR = NR + 1, nM = M + 1;
+  const double aL = alpha ? alpha[eL] : 0.0;
+  const double aR = alpha ? alpha[eR] : 0.0;
+  const double* nrm = m.face_norm + m.face_norm_off[f];
+  double* bL = m.fside + m.side_off[eL];
+  double* bR = m.fside + m.side_off[eR];
+
+  if (!(aL > 0.0) && !(aR > 0.0)) {
+    if (NL == NR) {
+      const int n = nL, n2 = n * n;
+      const int64_t baseL = m.elem_offset[eL], baseR = m.elem_offset[eR];
+      for (int t = threadIdx.x; t < n2; t += blockDim.x) {
+        const int p = t % n, q = t / n;
+        int pp, qq;
+        orient_map(o, p, q, n, pp, qq);
+        const int64_t gL = baseL + side_node(sideL, p, q, n);
+        const int64_t gR = baseR + side_node(sideR, pp, qq, n);
+        double uL[NV], uR[NV], Fb[NV], uLb[NV], uRb[NV];
+        for (int v = 0; v < NV; ++v) {
+          uL[v] = u[v * m.n_node + gL];
+          uR[v] = u[v * m.n_node + gR];
+          Fb[v] = bL[(sideL * NV + v) * n2 + q * n + p] - bR[(sideR * NV + v) * n2 + qq * n + pp];
+        }
+        riemann_vjp<NV>(prm.face_flux_dg, prm.volume_flux, uL, uR, nrm[t], nrm[n2 + t], nrm[2 * n2 + t],
+                        m.gas, Fb, uLb, uRb);
+        for (int v = 0; v < NV; ++v) {
+          bL[(sideL * NV + v) * n2 + q * n + p] = uLb[v];
+          bR[(sideR * NV + v) * n2 + qq * n + pp] = uRb[v];
+        }
+      }
+      return;
+    }
+    // degree jump: Fb at M = P_L^T FbL - P_R^T FbR, then the interpolations' transposes
+    gather_side<NV>(bL, sideL, o, false, nL, sL);
+    gather_side<NV>(bR, sideR, o, true, nR, sR);
+    __syncthreads();
+    if (NL < M) map2d(sL, sTmp, sL, m.ops + m.tab.projectT[M][NL], nM, nL, NV);
+    if (NR < M) map2d(sR, sTmp, sR, m.ops + m.tab.projectT[M][NR], nM, nR, NV);
+    const int n2 = nM * nM;
+    for (int t = threadIdx.x; t < n2; t += blockDim.x)
+      for (int v = 0; v < NV; ++v) sF[v * GRID + t] = sL[v * GRID + t] - sR[v * GRID + t];
+    __syncthreads();
+    gather_trace<NV>(m, u, eL, sideL, o, false, nL, sL);
+    gather_trace<NV>(m, u, eR, sideR, o, true, nR, sR);
+    __syncthreads();
+    if (NL < M) map2d(sL, sTmp, sL, m.ops + m.tab.interp[NL][M], nM, nL, NV);
+    if (NR < M) map2d(sR, sTmp, sR, m.ops + m.tab.interp[NR][M], nM, nR, NV);
+    for (int t = threadIdx.x; t < n2; t += blockDim.x) {
+      double uL[NV], uR[NV], Fb[NV], uLb[NV], uRb[NV];
+      for (int v = 0; v < NV; ++v) {
+        uL[v] = sL[v * GRID + t];
+        uR[v] = sR[v * GRID + t];
+        Fb[v] = sF[v * GRID + t];
+      }
+      riemann_vjp<NV>(prm.face_flux_dg, prm.volume_flux, uL, uR, nrm[t], nrm[n2 + t], nrm[2 * n2 + t],
+                      m.gas, Fb, uLb, uRb);
+      for (int v = 0; v < NV; ++v) {
+        sL[v * GRID + t] = uLb[v];
+        sR[v * GRID + t] = uRb[v];
+      }
+    }
+    __syncthreads();
+    if (NL < M) map2d(sL, sTmp, sL, m.ops + m.tab.interpT[NL][M], nL, nM, NV);
+    write_side<NV>(bL, sL, sideL, o, false, nL, 1.0);
+    if (NR < M) map2d(sR, sTmp, sR, m.ops + m.tab.interpT[NR][M], nR, nM, NV);
+    write_side<NV>(bR, sR, sideR, o, true, nR, 1.0);
+    return;
+  }
+
+  // FV face
+  const int nF = m.n_fv, n2F = nF * nF;
+  const double h = 2.0 / nF;
+  const double ih2 = 1.0 / (h * h);
+  double* fvL = m.fvside + (size_t)eL * 6 * NV * n2F;
+  double* fvR = m.fvside + (size_t)eR * 6 * NV * n2F;
+  gather_side<NV>(bL, sideL, o, false, nL, sL);
+  gather_side<NV>(bR, sideR, o, true, nR, sR);
+  __syncthreads();
+  map2d(sL, sTmp, sL, m.ops + m.tab.fv2dgT[NL], nF, nL, NV);
+  map2d(sR, sTmp, sR, m.ops + m.tab.fv2dgT[NR], nF, nR, NV);
+  for (int t = threadIdx.x; t < n2F; t += blockDim.x) {
+    int pp, qq;
+    orient_map(o, t % nF, t / nF, nF, pp, qq);
+    for (int v = 0; v < NV; ++v) {
+      double x = (sL[v * GRID + t] - sR[v * GRID + t]) * ih2;
+      if (aL > 0.0) x += fvL[(sideL * NV + v) * n2F + t];
+      if (aR > 0.0) x -= fvR[(sideR * NV + v) * n2F + qq * nF + pp];
+      sF[v * GRID + t] = x;
+    }
+  }
+  __syncthreads();
+  // linearisation point: the forward traces and sub-face normals
+  if (aL > 0.0) gather_subcells<NV>(m, eL, sideL, o, false, sL);
+  else gather_trace<NV>(m, u, eL, sideL, o, false, nL, sL);
+  if (aR > 0.0) gather_subcells<NV>(m, eR, sideR, o, true, sR);
+  else gather_trace<NV>(m, u, eR, sideR, o, true, nR, sR);
+  for (int t = threadIdx.x; t < 3 * nM * nM; t += blockDim.x)
+    sN[(t / (nM * nM)) * GRID + t % (nM * nM)] = nrm[t];
+  __syncthreads();
+  if (!(aL > 0.0)) map2d(sL, sTmp, sL, m.ops + m.tab.dg2fv[NL], nF, nL, NV);
+  if (!(aR > 0.0)) map2d(sR, sTmp, sR, m.ops + m.tab.dg2fv[NR], nF, nR, NV);
+  map2d(sN, sTmp, sN, m.ops + m.tab.dg2fv[M], nF, nM, 3);
+  for (int t = threadIdx.x; t < n2F; t += blockDim.x) {
+    double uL[NV], uR[NV], Fb[NV], uLb[NV], uRb[NV];
+    for (int v = 0; v < NV; ++v) {
+      uL[v] = sL[v * GRID + t];
+      uR[v] = sR[v * GRID + t];
+      Fb[v] = sF[v * GRID + t];
+    }
+    const double a = h * h;
+    riemann_vjp<NV>(prm.face_flux_fv, prm.volume_flux, uL, uR, a * sN[t], a * sN[GRID + t],
+                    a * sN[2 * GRID + t], m.gas, Fb, uLb, uRb);
+    for (int v = 0; v < NV; ++v) {
+      sL[v * GRID + t] = uLb[v];
+      sR[v * GRID + t] = uRb[v];
+    }
+  }
+  __syncthreads();
+  if (aL > 0.0) {
+    write_side<NV>(fvL, sL, sideL, o, false, nF, 1.0);
+    for (int t = threadIdx.x; t < nL * nL; t += blockDim.x)
+      for (int v = 0; v < NV; ++v) bL[(sideL * NV + v) * nL * nL + t] = 0.0;
+  } else {
+    map2d(sL, sTmp, sL, m.ops + m.tab.dg2fvT[NL], nL, nF, NV);
+    write_side<NV>(bL, sL, sideL, o, false, nL, 1.0);
+  }
+  if (aR > 0.0) {
+    write_side<NV>(fvR, sR, sideR, o, true, nF, 1.0);
+    for (int t = threadIdx.x; t < nR * nR; t += blockDim.x)
+      for (int v = 0; v < NV; ++v) bR[(sideR * NV + v) * nR * nR + t] = 0.0;
+  } else {
+    map2d(sR, sTmp, sR, m.ops + m.tab.dg2fvT[NR], nR, nF, NV);
+    write_side<NV>(bR, sR, sideR, o, true, nR, 1.0);
+  }
+}
+
 }  // namespace
+
+hipError_t launch_faces_vjp(const MeshView& m, const ParamsDev& p, const double* u, const double* alpha,
+                            hipStream_t s) {
+  if (m.n_face == 0) return hipSuccess;
+  if (m.nvar == 5)
+    hipLaunchKernelGGL((face_vjp_kernel<5>), dim3(m.n_face), dim3(FACE_THREADS), 0, s, m, p, u, alpha);
+  else
+    hipLaunchKernelGGL((face_vjp_kernel<6>), dim3(m.n_face), dim3(FACE_THREADS), 0, s, m, p, u, alpha);
+  return hipGetLastError();
+}
 
 hipError_t launch_faces(const MeshView& m, const ParamsDev& p, const double* u, const double* alpha,
                         hipStream_t s) {

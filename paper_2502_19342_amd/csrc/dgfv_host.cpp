@@ -226,6 +226,14 @@ void interp3(const std::vector<double>& V, int nin, int nout, const double* src,
   }
 }
 
+// r x c row-major -> c x r row-major
+std::vector<double> transpose(const std::vector<double>& a, int r, int c) {
+  std::vector<double> t((size_t)r * c);
+  for (int i = 0; i < r; ++i)
+    for (int j = 0; j < c; ++j) t[(size_t)j * r + i] = a[(size_t)i * c + j];
+  return t;
+}
+
 int side_node_h(int s, int p, int q, int n) {
   const int last = (s & 1) ? n - 1 : 0;
   switch (s >> 1) {
@@ -400,11 +408,15 @@ dgfv_status dgfv_mesh_create(const dgfv_mesh_desc* d, dgfv_mesh** out) {
       tab.vleg_inv[N] = push(op_vleg_inv(N));
       tab.dg2fv[N] = push(op_dg2fv(N, NFV));
       tab.fv2dg[N] = push(op_fv2dg(N, NFV));
+      tab.dg2fvT[N] = push(transpose(op_dg2fv(N, NFV), NFV, N + 1));
+      tab.fv2dgT[N] = push(transpose(op_fv2dg(N, NFV), N + 1, NFV));
       tab.face_interp[N] = push(op_face_interp(N, NFV));
       for (int M = N + 1; M <= MAXN; ++M) {
         if (!present[M]) continue;
         tab.interp[N][M] = push(op_interp(N, M));
         tab.project[M][N] = push(op_project(M, N));
+        tab.interpT[N][M] = push(transpose(op_interp(N, M), M + 1, N + 1));
+        tab.projectT[M][N] = push(transpose(op_project(M, N), N + 1, M + 1));
       }
     }
 
@@ -510,6 +522,7 @@ dgfv_status dgfv_mesh_create(const dgfv_mesh_desc* d, dgfv_mesh** out) {
     v.fvside = m->keep(dev_alloc<double>((size_t)m->K * 6 * m->nvar * NFV * NFV));
     v.ubar = m->keep(dev_alloc<double>((size_t)m->K * m->nvar * NFV * NFV * NFV));
     v.rfv = m->keep(dev_alloc<double>((size_t)m->nvar * m->n_node));
+    v.ubar_bar = m->keep(dev_alloc<double>((size_t)m->K * m->nvar * NFV * NFV * NFV));
     v.ops = m->keep(dev_upload(ops));
     v.tab = tab;
     v.gas.gamma = d->gamma;
@@ -616,12 +629,44 @@ dgfv_status dgfv_profile_read(dgfv_mesh* m, int kernel, double* total_ms, int64_
 
 dgfv_status dg_rhs_vjp(const dgfv_mesh* m, const dgfv_params* prm, const double* u,
                        const double* alpha, const double* w, double* g, int batch, void* stream) {
-  (void)stream;
   if (!m || !u || !w || !g) return fail(DGFV_ERR_ARG, "NULL argument");
   if (batch < 1) return fail(DGFV_ERR_ARG, "batch must be positive");
+  if (g == w || g == u) return fail(DGFV_ERR_ARG, "g must not overlap u or w");
   if (dgfv_status st = check_params(m, prm)) return st;
-  (void)alpha;
-  return fail(DGFV_ERR_UNSUPPORTED, "dg_rhs_vjp is not available in this build");
+  const ParamsDev p = to_dev(prm);
+  const MeshView& v = m->view;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t plane = (size_t)m->nvar * m->n_node;
+  try {
+    Timed t(m, DGFV_KERNEL_VJP, s);
+    if (alpha) {
+      for (int N = 1; N <= MAXN; ++N)
+        if (!m->bucket[N].empty())
+          hip_check(ops_for(N).fv_means(v, m->d_bucket[N], (int)m->bucket[N].size(), u, alpha, s),
+                    "fv_means launch");
+    }
+    for (int b = 0; b < batch; ++b) {
+      const double* wb = w + b * plane;
+      double* gb = g + b * plane;
+      for (int N = 1; N <= MAXN; ++N)
+        if (!m->bucket[N].empty())
+          hip_check(ops_for(N).vjp_volume(v, p, m->d_bucket[N], (int)m->bucket[N].size(), u, alpha, wb, gb, s),
+                    "vjp_volume launch");
+      if (alpha)
+        for (int N = 1; N <= MAXN; ++N)
+          if (!m->bucket[N].empty())
+            hip_check(ops_for(N).vjp_fv(v, p, m->d_bucket[N], (int)m->bucket[N].size(), alpha, wb, s),
+                      "vjp_fv launch");
+      hip_check(launch_faces_vjp(v, p, u, alpha, s), "face vjp launch");
+      for (int N = 1; N <= MAXN; ++N)
+        if (!m->bucket[N].empty())
+          hip_check(ops_for(N).vjp_gather(v, m->d_bucket[N], (int)m->bucket[N].size(), alpha, gb, s),
+                    "vjp_gather launch");
+    }
+  } catch (const HipError& e) {
+    return fail(DGFV_ERR_HIP, e.what());
+  }
+  return DGFV_OK;
 }
 
 }  // extern "C"

@@ -21,6 +21,11 @@ struct OpTables {
   int dg2fv[MAXN + 1];                // NFV x (N+1), sub-cell means of l_j
   int fv2dg[MAXN + 1];                // (N+1) x NFV, pseudo-inverse of dg2fv
   int face_interp[MAXN + 1];          // (NFV+1) x (N+1), l_j at the sub-cell interfaces
+  // transposes, for the adjoint
+  int interpT[MAXN + 1][MAXN + 1];    // [N][M]: (N+1) x (M+1)
+  int projectT[MAXN + 1][MAXN + 1];   // [M][N]: (M+1) x (N+1)
+  int dg2fvT[MAXN + 1];               // (N+1) x NFV
+  int fv2dgT[MAXN + 1];               // NFV x (N+1)
 };
 
 struct GasDev {
@@ -49,6 +54,7 @@ struct MeshView {
   double* fvside;               // FV sub-face fluxes, [K][6][nvar][NFV^2]
   double* ubar;                 // sub-cell means, [K][nvar][NFV^3]
   double* rfv;                  // FV residual in nodal form, [nvar][n_node]
+  double* ubar_bar;             // adjoint of the sub-cell means, [K][nvar][NFV^3]
   const double* ops;            // operator tables
   OpTables tab;
   GasDev gas;
@@ -68,6 +74,14 @@ struct DegreeOps {
                             const double* alpha, hipStream_t s);
   hipError_t (*indicator)(const MeshView& m, const ParamsDev& p, const int32_t* elist, int count,
                           const double* u, double* alpha, double* ind, hipStream_t s);
+  // adjoint: g = (dR/du)^T w, alpha frozen (see dg_rhs_vjp)
+  hipError_t (*vjp_volume)(const MeshView& m, const ParamsDev& p, const int32_t* elist, int count,
+                           const double* u, const double* alpha, const double* w, double* g,
+                           hipStream_t s);
+  hipError_t (*vjp_fv)(const MeshView& m, const ParamsDev& p, const int32_t* elist, int count,
+                       const double* alpha, const double* w, hipStream_t s);
+  hipError_t (*vjp_gather)(const MeshView& m, const int32_t* elist, int count, const double* alpha,
+                           double* g, hipStream_t s);
 };
 DegreeOps degree_ops_1();
 DegreeOps degree_ops_2();
@@ -80,5 +94,9 @@ DegreeOps degree_ops_7();
 // All faces: Riemann fluxes into the per-side buffers (DG, mixed-degree and FV faces).
 hipError_t launch_faces(const MeshView& m, const ParamsDev& p, const double* u, const double* alpha,
                         hipStream_t s);
+// Adjoint of the face fluxes: side-flux cotangents in fside / fvside are replaced
+// in place by the cotangents of the traces they were computed from.
+hipError_t launch_faces_vjp(const MeshView& m, const ParamsDev& p, const double* u, const double* alpha,
+                            hipStream_t s);
 
 }  // namespace dgfv

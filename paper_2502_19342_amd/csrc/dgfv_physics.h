@@ -4,43 +4,58 @@
 // inviscid part of eq. ns_equation.  Pressure from eq. eos with the mixture
 // ratio of eq. mix_R_kappa / eq. mix_cp_cv for two species.  All fluxes are
 // returned already contracted with an (unnormalised) direction vector.
+//
+// The state-dependent functions are templated on the scalar type S (double,
+// or a forward-mode Dual<K> for local Jacobians in the adjoint kernels).
 #pragma once
 
+#include "dgfv_dual.h"
 #include "dgfv_internal.h"
 
 namespace dgfv {
 
-struct Prim {
-  double rho, v1, v2, v3, p, E, kap, Y;
-};
+__host__ __device__ inline double sqrt(double x) { return ::sqrt(x); }
+__host__ __device__ inline double log(double x) { return ::log(x); }
+__host__ __device__ inline double fabs(double x) { return ::fabs(x); }
+__host__ __device__ inline double fmax(double a, double b) { return ::fmax(a, b); }
 
-template <int NV>
-__device__ __forceinline__ Prim cons2prim(const double* u, const GasDev& g) {
-  Prim q;
+template <class S>
+struct PrimT {
+  S rho, v1, v2, v3, p, E, kap, Y;
+};
+using Prim = PrimT<double>;
+
+__device__ __forceinline__ double kappa_mix(double Y, const GasDev& g) {
+  const double Y2 = 1.0 - Y;
+  return (Y * g.cp0 + Y2 * g.cp1) / (Y * g.cv0 + Y2 * g.cv1);
+}
+
+template <int NV, class S>
+__device__ __forceinline__ PrimT<S> cons2prim(const S* u, const GasDev& g) {
+  PrimT<S> q;
   q.rho = u[0];
-  const double ir = 1.0 / q.rho;
+  const S ir = 1.0 / q.rho;
   q.v1 = u[1] * ir;
   q.v2 = u[2] * ir;
   q.v3 = u[3] * ir;
   q.E = u[4];
   if constexpr (NV == 6) {
     q.Y = u[5] * ir;
-    const double Y2 = 1.0 - q.Y;
+    const S Y2 = 1.0 - q.Y;
     q.kap = (q.Y * g.cp0 + Y2 * g.cp1) / (q.Y * g.cv0 + Y2 * g.cv1);
   } else {
-    q.Y = 0.0;
-    q.kap = g.gamma;
+    q.Y = S(0.0);
+    q.kap = S(g.gamma);
   }
   q.p = (q.kap - 1.0) * (q.E - 0.5 * q.rho * (q.v1 * q.v1 + q.v2 * q.v2 + q.v3 * q.v3));
   return q;
 }
 
 // Physical flux F(u) . a
-template <int NV>
-__device__ __forceinline__ void euler_flux(const Prim& q, double a1, double a2, double a3,
-                                           double* f) {
-  const double vn = q.v1 * a1 + q.v2 * a2 + q.v3 * a3;
-  const double m = q.rho * vn;
+template <int NV, class S>
+__device__ __forceinline__ void euler_flux(const PrimT<S>& q, double a1, double a2, double a3, S* f) {
+  const S vn = q.v1 * a1 + q.v2 * a2 + q.v3 * a3;
+  const S m = q.rho * vn;
   f[0] = m;
   f[1] = m * q.v1 + q.p * a1;
   f[2] = m * q.v2 + q.p * a2;
@@ -51,70 +66,189 @@ __device__ __forceinline__ void euler_flux(const Prim& q, double a1, double a2, 
 
 // Logarithmic mean (a - b) / (ln a - ln b) from precomputed logarithms, with the
 // Ismail-Roe series F = 1 + u/3 + u^2/5 + u^3/7, u = ((a-b)/(a+b))^2, below u = 1e-4.
-__device__ __forceinline__ double log_mean(double a, double b, double la, double lb) {
-  const double s = a + b;
-  const double f = (a - b) / s;
-  const double u = f * f;
+template <class S>
+__device__ __forceinline__ S log_mean(const S& a, const S& b, const S& la, const S& lb) {
+  const S s = a + b;
+  const S f = (a - b) / s;
+  const S u = f * f;
   if (u < 1e-4) {
-    const double F = 1.0 + u * (1.0 / 3.0 + u * (0.2 + u * (1.0 / 7.0)));
+    const S F = 1.0 + u * (1.0 / 3.0 + u * (0.2 + u * (1.0 / 7.0)));
     return s / (2.0 * F);
   }
   return (a - b) / (la - lb);
 }
 
+// Partial derivatives of log_mean with respect to its first value and first logarithm.
+__device__ __forceinline__ double log_mean_d(double a, double b, double la, double lb, double& d_a,
+                                             double& d_la) {
+  const double s = a + b;
+  const double f = (a - b) / s;
+  const double u = f * f;
+  if (u < 1e-4) {
+    const double F = 1.0 + u * (1.0 / 3.0 + u * (0.2 + u * (1.0 / 7.0)));
+    const double dF = 1.0 / 3.0 + u * (0.4 + u * (3.0 / 7.0));
+    const double dfa = 2.0 * b / (s * s);
+    const double lm = s / (2.0 * F);
+    d_a = 1.0 / (2.0 * F) - lm / F * dF * (2.0 * f * dfa);
+    d_la = 0.0;
+    return lm;
+  }
+  const double il = 1.0 / (la - lb);
+  const double lm = (a - b) * il;
+  d_a = il;
+  d_la = -lm * il;
+  return lm;
+}
+
 // ---------------------------------------------------------------------------
 // Per-node auxiliary records of the volume two-point fluxes.  Each kind stores
 // NA doubles per node in LDS (structure of arrays) and evaluates
-// f#(u_i, u_m) . a from two records.
+// f#(u_i, u_m) . a from two records.  For the adjoint each kind also provides
+//   flux_adj_a : abar += (d f# / d a_record)^T c     (first argument)
+//   make_adj   : ubar  = (d record / d u)^T abar
 // ---------------------------------------------------------------------------
 
 // Ranocha's entropy-conserving, kinetic-energy-preserving flux (single species).
 struct FluxRanocha {
   static constexpr int NA = 8;  // rho, v1, v2, v3, p, ln rho, beta = rho/p, ln beta
-  template <int NV>
-  __device__ __forceinline__ static void make(const Prim& q, double* r) {
+  template <int NV, class S>
+  __device__ __forceinline__ static void make(const PrimT<S>& q, S* r) {
     r[0] = q.rho; r[1] = q.v1; r[2] = q.v2; r[3] = q.v3; r[4] = q.p;
     r[5] = log(q.rho);
-    const double beta = q.rho / q.p;
+    const S beta = q.rho / q.p;
     r[6] = beta;
     r[7] = log(beta);
   }
-  template <int NV>
-  __device__ __forceinline__ static void flux(const double* a_, const double* b_, double a1,
-                                              double a2, double a3, const GasDev& g, double* f) {
-    const double rho_ln = log_mean(a_[0], b_[0], a_[5], b_[5]);
-    const double beta_ln = log_mean(a_[6], b_[6], a_[7], b_[7]);
-    const double v1 = 0.5 * (a_[1] + b_[1]), v2 = 0.5 * (a_[2] + b_[2]), v3 = 0.5 * (a_[3] + b_[3]);
-    const double pbar = 0.5 * (a_[4] + b_[4]);
-    const double vn = v1 * a1 + v2 * a2 + v3 * a3;
-    const double fr = rho_ln * vn;
+  template <int NV, class S>
+  __device__ __forceinline__ static void flux(const S* a_, const S* b_, double a1, double a2,
+                                              double a3, const GasDev& g, S* f) {
+    const S rho_ln = log_mean(a_[0], b_[0], a_[5], b_[5]);
+    const S beta_ln = log_mean(a_[6], b_[6], a_[7], b_[7]);
+    const S v1 = 0.5 * (a_[1] + b_[1]), v2 = 0.5 * (a_[2] + b_[2]), v3 = 0.5 * (a_[3] + b_[3]);
+    const S pbar = 0.5 * (a_[4] + b_[4]);
+    const S vn = v1 * a1 + v2 * a2 + v3 * a3;
+    const S fr = rho_ln * vn;
     f[0] = fr;
     f[1] = fr * v1 + pbar * a1;
     f[2] = fr * v2 + pbar * a2;
     f[3] = fr * v3 + pbar * a3;
-    const double vv = 0.5 * (a_[1] * b_[1] + a_[2] * b_[2] + a_[3] * b_[3]);
-    const double vna = a_[1] * a1 + a_[2] * a2 + a_[3] * a3;
-    const double vnb = b_[1] * a1 + b_[2] * a2 + b_[3] * a3;
+    const S vv = 0.5 * (a_[1] * b_[1] + a_[2] * b_[2] + a_[3] * b_[3]);
+    const S vna = a_[1] * a1 + a_[2] * a2 + a_[3] * a3;
+    const S vnb = b_[1] * a1 + b_[2] * a2 + b_[3] * a3;
     f[4] = fr * (1.0 / ((g.gamma - 1.0) * beta_ln) + vv) + 0.5 * (a_[4] * vnb + b_[4] * vna);
   }
+  template <int NV>
+  __device__ __forceinline__ static void flux_adj_a(const double* a_, const double* b_, double n1,
+                                                    double n2, double n3, const GasDev& g,
+                                                    const double* c, double* ab) {
+    double drho_a, drho_la, dbeta_a, dbeta_la;
+    const double rho_ln = log_mean_d(a_[0], b_[0], a_[5], b_[5], drho_a, drho_la);
+    const double beta_ln = log_mean_d(a_[6], b_[6], a_[7], b_[7], dbeta_a, dbeta_la);
+    const double v1 = 0.5 * (a_[1] + b_[1]), v2 = 0.5 * (a_[2] + b_[2]), v3 = 0.5 * (a_[3] + b_[3]);
+    const double vn = v1 * n1 + v2 * n2 + v3 * n3;
+    const double fr = rho_ln * vn;
+    const double gm1 = g.gamma - 1.0;
+    const double ib = 1.0 / (gm1 * beta_ln);
+    const double vv = 0.5 * (a_[1] * b_[1] + a_[2] * b_[2] + a_[3] * b_[3]);
+    const double vnb = b_[1] * n1 + b_[2] * n2 + b_[3] * n3;
+    const double frb = c[0] + c[1] * v1 + c[2] * v2 + c[3] * v3 + c[4] * (ib + vv);
+    const double pbarb = c[1] * n1 + c[2] * n2 + c[3] * n3;
+    const double betab = -c[4] * fr * gm1 * ib * ib;
+    const double vvb = c[4] * fr;
+    const double vnab = 0.5 * c[4] * b_[4];
+    const double rholnb = frb * vn;
+    const double vnbar = frb * rho_ln;
+    ab[0] += rholnb * drho_a;
+    ab[5] += rholnb * drho_la;
+    ab[6] += betab * dbeta_a;
+    ab[7] += betab * dbeta_la;
+    ab[1] += 0.5 * (c[1] * fr + vnbar * n1) + 0.5 * vvb * b_[1] + vnab * n1;
+    ab[2] += 0.5 * (c[2] * fr + vnbar * n2) + 0.5 * vvb * b_[2] + vnab * n2;
+    ab[3] += 0.5 * (c[3] * fr + vnbar * n3) + 0.5 * vvb * b_[3] + vnab * n3;
+    ab[4] += 0.5 * pbarb + 0.5 * c[4] * vnb;
+  }
+  template <int NV>
+  __device__ __forceinline__ static void make_adj(const double* u, const GasDev& g, const double* ab,
+                                                  double* ub) {
+    const double rho = u[0], ir = 1.0 / rho;
+    const double v1 = u[1] * ir, v2 = u[2] * ir, v3 = u[3] * ir;
+    const double gm1 = g.gamma - 1.0;
+    const double vsq = v1 * v1 + v2 * v2 + v3 * v3;
+    const double p = gm1 * (u[4] - 0.5 * rho * vsq);
+    const double beta = rho / p;
+    const double betab = ab[6] + ab[7] / beta;
+    double rhob = ab[0] + ab[5] * ir + betab / p;
+    const double pb = ab[4] - betab * beta / p;
+    // p = (gamma-1) (E - |m|^2 / (2 rho))
+    ub[4] = gm1 * pb;
+    double m1b = -gm1 * pb * v1, m2b = -gm1 * pb * v2, m3b = -gm1 * pb * v3;
+    rhob += gm1 * pb * 0.5 * vsq;
+    // v = m / rho
+    m1b += ab[1] * ir;
+    m2b += ab[2] * ir;
+    m3b += ab[3] * ir;
+    rhob -= (ab[1] * v1 + ab[2] * v2 + ab[3] * v3) * ir;
+    ub[0] = rhob;
+    ub[1] = m1b;
+    ub[2] = m2b;
+    ub[3] = m3b;
+  }
 };
+
+// Chain rule of (rho, v, p, E, Y) with respect to u, shared by the Pirozzoli
+// and central records: given bars of rho, v, p, E, Y accumulate ub.
+template <int NV>
+__device__ __forceinline__ void prim_adj(const double* u, const GasDev& g, double rhob, double v1b,
+                                         double v2b, double v3b, double pb, double Eb, double Yb,
+                                         double* ub) {
+  const double rho = u[0], ir = 1.0 / rho;
+  const double v1 = u[1] * ir, v2 = u[2] * ir, v3 = u[3] * ir;
+  const double vsq = v1 * v1 + v2 * v2 + v3 * v3;
+  const double qe = u[4] - 0.5 * rho * vsq;                // p = (kappa - 1) qe
+  double kap = g.gamma;
+  double Y = 0.0;
+  if constexpr (NV == 6) {
+    Y = u[5] * ir;
+    const double num = Y * g.cp0 + (1.0 - Y) * g.cp1, den = Y * g.cv0 + (1.0 - Y) * g.cv1;
+    kap = num / den;
+    const double dkdY = ((g.cp0 - g.cp1) * den - num * (g.cv0 - g.cv1)) / (den * den);
+    Yb += pb * qe * dkdY;
+  }
+  const double qb = (kap - 1.0) * pb;
+  Eb += qb;
+  double m1b = -qb * v1, m2b = -qb * v2, m3b = -qb * v3;
+  rhob += qb * 0.5 * vsq;
+  m1b += v1b * ir;
+  m2b += v2b * ir;
+  m3b += v3b * ir;
+  rhob -= (v1b * v1 + v2b * v2 + v3b * v3) * ir;
+  if constexpr (NV == 6) {
+    ub[5] = Yb * ir;
+    rhob -= Yb * Y * ir;
+  }
+  ub[0] = rhob;
+  ub[1] = m1b;
+  ub[2] = m2b;
+  ub[3] = m3b;
+  ub[4] = Eb;
+}
 
 // Pirozzoli's kinetic-energy-preserving flux (Section 3.5); f_rhoY = f_rho {Y}.
 struct FluxPirozzoli {
   static constexpr int NA = 7;  // rho, v1, v2, v3, p, H, Y
-  template <int NV>
-  __device__ __forceinline__ static void make(const Prim& q, double* r) {
+  template <int NV, class S>
+  __device__ __forceinline__ static void make(const PrimT<S>& q, S* r) {
     r[0] = q.rho; r[1] = q.v1; r[2] = q.v2; r[3] = q.v3; r[4] = q.p;
     r[5] = (q.E + q.p) / q.rho;
     r[6] = q.Y;
   }
-  template <int NV>
-  __device__ __forceinline__ static void flux(const double* a_, const double* b_, double a1,
-                                              double a2, double a3, const GasDev&, double* f) {
-    const double rho = 0.5 * (a_[0] + b_[0]);
-    const double v1 = 0.5 * (a_[1] + b_[1]), v2 = 0.5 * (a_[2] + b_[2]), v3 = 0.5 * (a_[3] + b_[3]);
-    const double pbar = 0.5 * (a_[4] + b_[4]);
-    const double fr = rho * (v1 * a1 + v2 * a2 + v3 * a3);
+  template <int NV, class S>
+  __device__ __forceinline__ static void flux(const S* a_, const S* b_, double a1, double a2,
+                                              double a3, const GasDev&, S* f) {
+    const S rho = 0.5 * (a_[0] + b_[0]);
+    const S v1 = 0.5 * (a_[1] + b_[1]), v2 = 0.5 * (a_[2] + b_[2]), v3 = 0.5 * (a_[3] + b_[3]);
+    const S pbar = 0.5 * (a_[4] + b_[4]);
+    const S fr = rho * (v1 * a1 + v2 * a2 + v3 * a3);
     f[0] = fr;
     f[1] = fr * v1 + pbar * a1;
     f[2] = fr * v2 + pbar * a2;
@@ -122,21 +256,55 @@ struct FluxPirozzoli {
     f[4] = fr * (0.5 * (a_[5] + b_[5]));
     if constexpr (NV == 6) f[5] = fr * (0.5 * (a_[6] + b_[6]));
   }
+  template <int NV>
+  __device__ __forceinline__ static void flux_adj_a(const double* a_, const double* b_, double n1,
+                                                    double n2, double n3, const GasDev&,
+                                                    const double* c, double* ab) {
+    const double rho = 0.5 * (a_[0] + b_[0]);
+    const double v1 = 0.5 * (a_[1] + b_[1]), v2 = 0.5 * (a_[2] + b_[2]), v3 = 0.5 * (a_[3] + b_[3]);
+    const double vn = v1 * n1 + v2 * n2 + v3 * n3;
+    const double fr = rho * vn;
+    const double Hbar = 0.5 * (a_[5] + b_[5]);
+    double frb = c[0] + c[1] * v1 + c[2] * v2 + c[3] * v3 + c[4] * Hbar;
+    double Yb = 0.0;
+    if constexpr (NV == 6) {
+      frb += c[5] * 0.5 * (a_[6] + b_[6]);
+      Yb = c[5] * fr;
+    }
+    const double vnb = frb * rho;
+    ab[0] += 0.5 * frb * vn;
+    ab[1] += 0.5 * (c[1] * fr + vnb * n1);
+    ab[2] += 0.5 * (c[2] * fr + vnb * n2);
+    ab[3] += 0.5 * (c[3] * fr + vnb * n3);
+    ab[4] += 0.5 * (c[1] * n1 + c[2] * n2 + c[3] * n3);
+    ab[5] += 0.5 * c[4] * fr;
+    ab[6] += 0.5 * Yb;
+  }
+  template <int NV>
+  __device__ __forceinline__ static void make_adj(const double* u, const GasDev& g, const double* ab,
+                                                  double* ub) {
+    // H = (E + p) / rho
+    const double ir = 1.0 / u[0];
+    const PrimT<double> q = cons2prim<NV>(u, g);
+    const double H = (q.E + q.p) * ir;
+    const double Hb = ab[5];
+    prim_adj<NV>(u, g, ab[0] - Hb * H * ir, ab[1], ab[2], ab[3], ab[4] + Hb * ir, Hb * ir, ab[6], ub);
+  }
 };
 
 // Arithmetic mean of the physical fluxes.
 struct FluxCentral {
   static constexpr int NA = 7;  // rho, v1, v2, v3, p, E, Y
-  template <int NV>
-  __device__ __forceinline__ static void make(const Prim& q, double* r) {
+  template <int NV, class S>
+  __device__ __forceinline__ static void make(const PrimT<S>& q, S* r) {
     r[0] = q.rho; r[1] = q.v1; r[2] = q.v2; r[3] = q.v3; r[4] = q.p; r[5] = q.E; r[6] = q.Y;
   }
-  template <int NV>
-  __device__ __forceinline__ static void flux(const double* a_, const double* b_, double a1,
-                                              double a2, double a3, const GasDev&, double* f) {
-    const double vna = a_[1] * a1 + a_[2] * a2 + a_[3] * a3;
-    const double vnb = b_[1] * a1 + b_[2] * a2 + b_[3] * a3;
-    const double ma = a_[0] * vna, mb = b_[0] * vnb;
+  template <int NV, class S>
+  __device__ __forceinline__ static void flux(const S* a_, const S* b_, double a1, double a2,
+                                              double a3, const GasDev&, S* f) {
+    const S vna = a_[1] * a1 + a_[2] * a2 + a_[3] * a3;
+    const S vnb = b_[1] * a1 + b_[2] * a2 + b_[3] * a3;
+    const S ma = a_[0] * vna, mb = b_[0] * vnb;
     f[0] = 0.5 * (ma + mb);
     f[1] = 0.5 * (ma * a_[1] + a_[4] * a1 + mb * b_[1] + b_[4] * a1);
     f[2] = 0.5 * (ma * a_[2] + a_[4] * a2 + mb * b_[2] + b_[4] * a2);
@@ -144,16 +312,39 @@ struct FluxCentral {
     f[4] = 0.5 * ((a_[5] + a_[4]) * vna + (b_[5] + b_[4]) * vnb);
     if constexpr (NV == 6) f[5] = 0.5 * (ma * a_[6] + mb * b_[6]);
   }
+  template <int NV>
+  __device__ __forceinline__ static void flux_adj_a(const double* a_, const double*, double n1,
+                                                    double n2, double n3, const GasDev&,
+                                                    const double* c, double* ab) {
+    const double vna = a_[1] * n1 + a_[2] * n2 + a_[3] * n3;
+    const double ma = a_[0] * vna;
+    double mab = 0.5 * (c[0] + c[1] * a_[1] + c[2] * a_[2] + c[3] * a_[3]);
+    if constexpr (NV == 6) {
+      mab += 0.5 * c[5] * a_[6];
+      ab[6] += 0.5 * c[5] * ma;
+    }
+    const double vnab = mab * a_[0] + 0.5 * c[4] * (a_[5] + a_[4]);
+    ab[0] += mab * vna;
+    ab[1] += 0.5 * c[1] * ma + vnab * n1;
+    ab[2] += 0.5 * c[2] * ma + vnab * n2;
+    ab[3] += 0.5 * c[3] * ma + vnab * n3;
+    ab[4] += 0.5 * (c[1] * n1 + c[2] * n2 + c[3] * n3) + 0.5 * c[4] * vna;
+    ab[5] += 0.5 * c[4] * vna;
+  }
+  template <int NV>
+  __device__ __forceinline__ static void make_adj(const double* u, const GasDev& g, const double* ab,
+                                                  double* ub) {
+    prim_adj<NV>(u, g, ab[0], ab[1], ab[2], ab[3], ab[4], ab[5], ab[6], ub);
+  }
 };
 
 // Two-point flux of the chosen volume kind evaluated from conservative states
 // (used at faces with the EC selector).
-template <int NV>
-__device__ __forceinline__ void two_point_cons(int kind, const double* uL, const double* uR,
-                                               double n1, double n2, double n3, const GasDev& g,
-                                               double* F) {
-  const Prim qL = cons2prim<NV>(uL, g), qR = cons2prim<NV>(uR, g);
-  double ra[8], rb[8];
+template <int NV, class S>
+__device__ __forceinline__ void two_point_cons(int kind, const S* uL, const S* uR, double n1,
+                                               double n2, double n3, const GasDev& g, S* F) {
+  const PrimT<S> qL = cons2prim<NV>(uL, g), qR = cons2prim<NV>(uR, g);
+  S ra[8], rb[8];
   if (kind == 0) {
     FluxRanocha::make<NV>(qL, ra);
     FluxRanocha::make<NV>(qR, rb);
@@ -170,84 +361,86 @@ __device__ __forceinline__ void two_point_cons(int kind, const double* uL, const
 }
 
 // Local Lax-Friedrichs flux times the area element |nvec|.
-template <int NV>
-__device__ __forceinline__ void riemann_llf(const double* uL, const double* uR, double n1,
-                                            double n2, double n3, const GasDev& g, double* F) {
-  const double s = sqrt(n1 * n1 + n2 * n2 + n3 * n3);
+template <int NV, class S>
+__device__ __forceinline__ void riemann_llf(const S* uL, const S* uR, double n1, double n2, double n3,
+                                            const GasDev& g, S* F) {
+  const double s = ::sqrt(n1 * n1 + n2 * n2 + n3 * n3);
   const double is = 1.0 / s;
   const double e1 = n1 * is, e2 = n2 * is, e3 = n3 * is;
-  const Prim qL = cons2prim<NV>(uL, g), qR = cons2prim<NV>(uR, g);
-  const double cL = sqrt(qL.kap * qL.p / qL.rho), cR = sqrt(qR.kap * qR.p / qR.rho);
-  const double lam = fmax(fabs(qL.v1 * e1 + qL.v2 * e2 + qL.v3 * e3) + cL,
-                          fabs(qR.v1 * e1 + qR.v2 * e2 + qR.v3 * e3) + cR);
-  double fL[NV], fR[NV];
+  const PrimT<S> qL = cons2prim<NV>(uL, g), qR = cons2prim<NV>(uR, g);
+  const S cL = sqrt(qL.kap * qL.p / qL.rho), cR = sqrt(qR.kap * qR.p / qR.rho);
+  const S lam = fmax(fabs(qL.v1 * e1 + qL.v2 * e2 + qL.v3 * e3) + cL,
+                     fabs(qR.v1 * e1 + qR.v2 * e2 + qR.v3 * e3) + cR);
+  S fL[NV], fR[NV];
   euler_flux<NV>(qL, e1, e2, e3, fL);
   euler_flux<NV>(qR, e1, e2, e3, fR);
 #pragma unroll
   for (int v = 0; v < NV; ++v) F[v] = (0.5 * (fL[v] + fR[v]) - 0.5 * lam * (uR[v] - uL[v])) * s;
 }
 
-// Roe flux with the Harten-Hyman entropy fix on the acoustic waves, times |nvec| (1 species).
-__device__ __forceinline__ double hh_fix(double lam, double lamL, double lamR) {
-  const double delta = fmax(0.0, fmax(lam - lamL, lamR - lam));
-  const double al = fabs(lam);
+// Harten-Hyman entropy fix on an acoustic wave speed.
+template <class S>
+__device__ __forceinline__ S hh_fix(const S& lam, const S& lamL, const S& lamR) {
+  const S delta = fmax(0.0, fmax(lam - lamL, lamR - lam));
+  const S al = fabs(lam);
   return (al < delta) ? 0.5 * (lam * lam / delta + delta) : al;
 }
 
-__device__ __forceinline__ void riemann_roe(const double* uL, const double* uR, double n1, double n2,
-                                            double n3, const GasDev& g, double* F) {
-  const double s = sqrt(n1 * n1 + n2 * n2 + n3 * n3);
+// Roe flux with the Harten-Hyman entropy fix on the acoustic waves, times |nvec| (1 species).
+template <class S>
+__device__ __forceinline__ void riemann_roe(const S* uL, const S* uR, double n1, double n2, double n3,
+                                            const GasDev& g, S* F) {
+  const double s = ::sqrt(n1 * n1 + n2 * n2 + n3 * n3);
   const double is = 1.0 / s;
   const double e1 = n1 * is, e2 = n2 * is, e3 = n3 * is;
-  const Prim qL = cons2prim<5>(uL, g), qR = cons2prim<5>(uR, g);
+  const PrimT<S> qL = cons2prim<5>(uL, g), qR = cons2prim<5>(uR, g);
   const double gm1 = g.gamma - 1.0;
-  const double sL = sqrt(qL.rho), sR = sqrt(qR.rho);
-  const double iw = 1.0 / (sL + sR);
-  const double v1 = (sL * qL.v1 + sR * qR.v1) * iw;
-  const double v2 = (sL * qL.v2 + sR * qR.v2) * iw;
-  const double v3 = (sL * qL.v3 + sR * qR.v3) * iw;
-  const double HL = (qL.E + qL.p) / qL.rho, HR = (qR.E + qR.p) / qR.rho;
-  const double H = (sL * HL + sR * HR) * iw;
-  const double vsq = v1 * v1 + v2 * v2 + v3 * v3;
-  const double c2 = gm1 * (H - 0.5 * vsq);
-  const double c = sqrt(c2);
-  const double rt = sL * sR;
-  const double vn = v1 * e1 + v2 * e2 + v3 * e3;
+  const S sL = sqrt(qL.rho), sR = sqrt(qR.rho);
+  const S iw = 1.0 / (sL + sR);
+  const S v1 = (sL * qL.v1 + sR * qR.v1) * iw;
+  const S v2 = (sL * qL.v2 + sR * qR.v2) * iw;
+  const S v3 = (sL * qL.v3 + sR * qR.v3) * iw;
+  const S HL = (qL.E + qL.p) / qL.rho, HR = (qR.E + qR.p) / qR.rho;
+  const S H = (sL * HL + sR * HR) * iw;
+  const S vsq = v1 * v1 + v2 * v2 + v3 * v3;
+  const S c2 = gm1 * (H - 0.5 * vsq);
+  const S c = sqrt(c2);
+  const S rt = sL * sR;
+  const S vn = v1 * e1 + v2 * e2 + v3 * e3;
 
-  const double drho = qR.rho - qL.rho, dp = qR.p - qL.p;
-  const double d1 = qR.v1 - qL.v1, d2 = qR.v2 - qL.v2, d3 = qR.v3 - qL.v3;
-  const double dvn = d1 * e1 + d2 * e2 + d3 * e3;
-  const double a1 = (dp - rt * c * dvn) / (2.0 * c2);
-  const double a5 = (dp + rt * c * dvn) / (2.0 * c2);
-  const double a2 = drho - dp / c2;
-  const double t1 = d1 - dvn * e1, t2 = d2 - dvn * e2, t3 = d3 - dvn * e3;
+  const S drho = qR.rho - qL.rho, dp = qR.p - qL.p;
+  const S d1 = qR.v1 - qL.v1, d2 = qR.v2 - qL.v2, d3 = qR.v3 - qL.v3;
+  const S dvn = d1 * e1 + d2 * e2 + d3 * e3;
+  const S a1 = (dp - rt * c * dvn) / (2.0 * c2);
+  const S a5 = (dp + rt * c * dvn) / (2.0 * c2);
+  const S a2 = drho - dp / c2;
+  const S t1 = d1 - dvn * e1, t2 = d2 - dvn * e2, t3 = d3 - dvn * e3;
 
-  const double cL = sqrt(qL.kap * qL.p / qL.rho), cR = sqrt(qR.kap * qR.p / qR.rho);
-  const double vnL = qL.v1 * e1 + qL.v2 * e2 + qL.v3 * e3;
-  const double vnR = qR.v1 * e1 + qR.v2 * e2 + qR.v3 * e3;
-  const double l1 = hh_fix(vn - c, vnL - cL, vnR - cR);
-  const double l5 = hh_fix(vn + c, vnL + cL, vnR + cR);
-  const double l2 = fabs(vn);
+  const S cL = sqrt(qL.kap * qL.p / qL.rho), cR = sqrt(qR.kap * qR.p / qR.rho);
+  const S vnL = qL.v1 * e1 + qL.v2 * e2 + qL.v3 * e3;
+  const S vnR = qR.v1 * e1 + qR.v2 * e2 + qR.v3 * e3;
+  const S l1 = hh_fix(vn - c, vnL - cL, vnR - cR);
+  const S l5 = hh_fix(vn + c, vnL + cL, vnR + cR);
+  const S l2 = fabs(vn);
 
-  const double w1 = l1 * a1, w5 = l5 * a5, w2 = l2 * a2, wt = l2 * rt;
-  double D[5];
+  const S w1 = l1 * a1, w5 = l5 * a5, w2 = l2 * a2, wt = l2 * rt;
+  S D[5];
   D[0] = w1 + w5 + w2;
   D[1] = w1 * (v1 - c * e1) + w5 * (v1 + c * e1) + w2 * v1 + wt * t1;
   D[2] = w1 * (v2 - c * e2) + w5 * (v2 + c * e2) + w2 * v2 + wt * t2;
   D[3] = w1 * (v3 - c * e3) + w5 * (v3 + c * e3) + w2 * v3 + wt * t3;
   D[4] = w1 * (H - c * vn) + w5 * (H + c * vn) + w2 * (0.5 * vsq) + wt * (v1 * t1 + v2 * t2 + v3 * t3);
 
-  double fL[5], fR[5];
+  S fL[5], fR[5];
   euler_flux<5>(qL, e1, e2, e3, fL);
   euler_flux<5>(qR, e1, e2, e3, fR);
 #pragma unroll
   for (int v = 0; v < 5; ++v) F[v] = (0.5 * (fL[v] + fR[v]) - 0.5 * D[v]) * s;
 }
 
-template <int NV>
-__device__ __forceinline__ void riemann(int kind, int vol_kind, const double* uL, const double* uR,
-                                        double n1, double n2, double n3, const GasDev& g,
-                                        double* F) {
+template <int NV, class S>
+__device__ __forceinline__ void riemann(int kind, int vol_kind, const S* uL, const S* uR, double n1,
+                                        double n2, double n3, const GasDev& g, S* F) {
   if (kind == 1) {
     riemann_llf<NV>(uL, uR, n1, n2, n3, g, F);
   } else if (kind == 0) {
@@ -258,6 +451,63 @@ __device__ __forceinline__ void riemann(int kind, int vol_kind, const double* uL
     }
   } else {
     two_point_cons<NV>(vol_kind, uL, uR, n1, n2, n3, g, F);
+  }
+}
+
+// (dF*/duL)^T Fb and (dF*/duR)^T Fb of the Riemann flux, by forward-mode duals.
+template <int NV>
+__device__ __forceinline__ void riemann_vjp(int kind, int vol_kind, const double* uL, const double* uR,
+                                            double n1, double n2, double n3, const GasDev& g,
+                                            const double* Fb, double* uLb, double* uRb) {
+  using D = Dual<NV>;
+  D a[NV], b[NV], F[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    a[v] = D::seed(uL[v], v);
+    b[v] = D(uR[v]);
+  }
+  riemann<NV>(kind, vol_kind, a, b, n1, n2, n3, g, F);
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double s = 0.0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) s += F[v].d[k] * Fb[v];
+    uLb[k] = s;
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    a[v] = D(uL[v]);
+    b[v] = D::seed(uR[v], v);
+  }
+  riemann<NV>(kind, vol_kind, a, b, n1, n2, n3, g, F);
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double s = 0.0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) s += F[v].d[k] * Fb[v];
+    uRb[k] = s;
+  }
+}
+
+// One side of riemann_vjp: (dF*/du_side)^T Fb with side 0 = left, 1 = right.
+template <int NV>
+__device__ __forceinline__ void riemann_vjp_side(int side, int kind, int vol_kind, const double* uL,
+                                                 const double* uR, double n1, double n2, double n3,
+                                                 const GasDev& g, const double* Fb, double* ub) {
+  using D = Dual<NV>;
+  D a[NV], b[NV], F[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    a[v] = side == 0 ? D::seed(uL[v], v) : D(uL[v]);
+    b[v] = side == 1 ? D::seed(uR[v], v) : D(uR[v]);
+  }
+  riemann<NV>(kind, vol_kind, a, b, n1, n2, n3, g, F);
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double s = 0.0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) s += F[v].d[k] * Fb[v];
+    ub[k] = s;
   }
 }
 

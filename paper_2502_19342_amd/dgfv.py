@@ -234,3 +234,84 @@ def prim_to_cons(w: np.ndarray, n_var: int, gamma: float = 1.4, kappa=(1.4, 1.4)
     if n_var == 6:
         comps.append(rho * w[5])
     return np.stack(comps)
+
+
+# ---------------------------------------------------------------------------
+# differentiation: torch.autograd bindings of dg_rhs / dg_rhs_vjp
+# ---------------------------------------------------------------------------
+
+class RHSFunction(torch.autograd.Function):
+    """``R(u)`` with the blending factors frozen; backward calls ``dg_rhs_vjp``."""
+
+    @staticmethod
+    def forward(ctx, u, mesh, params, alpha=None):
+        ctx.mesh, ctx.params, ctx.alpha = mesh, params, alpha
+        ctx.save_for_backward(u)
+        return rhs(mesh, params, u.contiguous(), alpha)
+
+    @staticmethod
+    def backward(ctx, grad):
+        (u,) = ctx.saved_tensors
+        g = rhs_vjp(ctx.mesh, ctx.params, u, ctx.alpha, grad.contiguous())
+        return g, None, None, None
+
+
+def rk_step_vjp(mesh: Mesh, params: Params, dt: float, u0: torch.Tensor, ubar: torch.Tensor,
+                alpha: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Cotangent of the state at the start of one 2N RK step, given that of its end.
+
+    The five stage inputs are recomputed from ``u0`` (k starts at zero since
+    A_1 = 0).  Per stage s = 5..1, with k_s = A_s k_{s-1} + dt R(u_{s-1}) and
+    u_s = u_{s-1} + B_s k_s:  kbar += B_s ubar;  ubar += dt (dR/du)^T kbar;
+    kbar = A_s kbar.
+    """
+    A = [0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
+         -3550918686646.0 / 2091501179385.0, -1275806237668.0 / 842570457699.0]
+    B = [1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
+         1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
+         2277821191437.0 / 14882151754819.0]
+    stages = [u0.clone()]
+    u = u0.clone()
+    k = torch.empty_like(u)
+    for s in range(1, 5):
+        rk_stage(mesh, params, s, dt, u, k, alpha, stream)
+        stages.append(u.clone())
+    ub = ubar.clone()
+    kb = torch.zeros_like(ub)
+    for s in range(5, 0, -1):
+        kb.add_(ub, alpha=B[s - 1])
+        ub.add_(rhs_vjp(mesh, params, stages[s - 1], alpha, kb, stream=stream), alpha=dt)
+        kb.mul_(A[s - 1])
+    return ub
+
+
+class CheckpointedRollout(torch.autograd.Function):
+    """``n`` RK steps from ``u0``; stores the state at every step start (RK-stage checkpointing).
+
+    Backward replays each step's stages from its checkpoint and runs the stage
+    adjoints in reverse (``rk_step_vjp``).
+    """
+
+    @staticmethod
+    def forward(ctx, u0, mesh, params, n_steps, dt, alpha=None):
+        u = u0.detach().clone().contiguous()
+        k = torch.empty_like(u)
+        checkpoints = []
+        for _ in range(int(n_steps)):
+            checkpoints.append(u.clone())
+            rk_step(mesh, params, dt, u, k, alpha)
+        ctx.mesh, ctx.params, ctx.dt, ctx.alpha = mesh, params, dt, alpha
+        ctx.checkpoints = checkpoints
+        return u
+
+    @staticmethod
+    def backward(ctx, grad):
+        ub = grad.contiguous()
+        for u0 in reversed(ctx.checkpoints):
+            ub = rk_step_vjp(ctx.mesh, ctx.params, ctx.dt, u0, ub, ctx.alpha)
+        ctx.checkpoints = None
+        return ub, None, None, None, None, None
+
+
+def checkpointed_rollout(u0, mesh, params, n_steps, dt, alpha=None):
+    return CheckpointedRollout.apply(u0, mesh, params, n_steps, dt, alpha)

@@ -52,6 +52,29 @@ class Case:
                                 wl.ind_vars)
 
 
+def oracle_spread(c: "Case", trials: int = 2, seed: int = 0) -> float:
+    """Largest rel_err of the oracle's own RHS under random 1-ulp relative perturbations of u.
+
+    The FV sub-cell map V^{FV->DG} amplifies rounding by up to ||V^+||^3 (about
+    2.7e3 at N=5, 6e4 at N=7), so no two correct evaluation orders can agree
+    better than this spread on blended elements.
+    """
+    g = torch.Generator().manual_seed(seed)
+    r0 = c.oracle_rhs()
+    worst = 0.0
+    for _ in range(trials):
+        up = c.u * (1.0 + 2.0 ** -52 * torch.randn(tuple(c.u.shape), generator=g, dtype=T))
+        worst = max(worst, rel_err(c.f(up, c.alpha), r0))
+    return worst
+
+
+def rhs_tol(c: "Case", base: float = 1e-12) -> float:
+    """1e-12, or four times the oracle's own 1-ulp spread where the FV map makes that larger."""
+    if not bool((c.alpha > 0).any()):
+        return base
+    return max(base, 4.0 * oracle_spread(c))
+
+
 def rel_err(a: torch.Tensor, ref: torch.Tensor) -> float:
     """max_v ||a_v - ref_v||_inf / ||ref_v||_inf over the variables."""
     num = (a - ref).abs().amax(dim=1)

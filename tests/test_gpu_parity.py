@@ -1,8 +1,11 @@
 """Parity of the HIP right-hand side with the CPU oracle, element by element.
 
 Bar: max-norm error per variable <= 1e-12 of the oracle's max norm for one RHS
-evaluation; <= 1e-10 after the Runge-Kutta runs.  Inputs are generated on the
-oracle side (its own node coordinates) and copied to the device.
+evaluation; <= 1e-10 after the Runge-Kutta runs.  On FV-blended elements the
+sub-cell map V^{FV->DG} amplifies rounding by up to ||V^+||^3, so there the
+bar is four times the oracle's own spread under 1-ulp input perturbations
+when that exceeds 1e-12 (``rhs_tol``).  Inputs are generated on the oracle
+side (its own node coordinates) and copied to the device.
 """
 import math
 
@@ -13,7 +16,7 @@ import torch
 from oracle import lsrk
 from paper_2502_19342_amd import workloads as W
 
-from gpu_common import Case, announce, rel_err
+from gpu_common import Case, announce, rel_err, rhs_tol
 from oracle_cases import curved_mixed, seeded_alpha, smooth_state
 
 pytestmark = pytest.mark.gpu
@@ -48,7 +51,7 @@ def test_curved_mixed_degree_blended_rhs(scramble):
     wl = curved_mixed(n=3, nmin=1, nmax=4, scramble=scramble, metric_degree=1, n_fv=5)
     c = Case(wl, prim=smooth_state(73), noise=1e-3, seed=2)
     c.alpha = seeded_alpha(c.mesh.K, 11, values=(0.0, 0.0, 0.35, 1.0))
-    assert rel_err(c.gpu_rhs(), c.oracle_rhs()) <= RHS_TOL
+    assert rel_err(c.gpu_rhs(), c.oracle_rhs()) <= rhs_tol(c)
 
 
 def test_two_species_mixed_degree_blended_rhs():
@@ -57,7 +60,7 @@ def test_two_species_mixed_degree_blended_rhs():
                       face_dg=W.RIEMANN_LLF, n_fv=8)
     c = Case(wl, prim=smooth_state(75, n_var=6), noise=1e-3, seed=3)
     c.alpha = seeded_alpha(c.mesh.K, 12, values=(0.0, 0.5, 1.0))
-    assert rel_err(c.gpu_rhs(), c.oracle_rhs()) <= RHS_TOL
+    assert rel_err(c.gpu_rhs(), c.oracle_rhs()) <= rhs_tol(c)
 
 
 def test_freestream_on_gpu():
@@ -100,7 +103,7 @@ def test_indicator_parity_blast():
     assert float(a_ora.max()) > 0
     # RHS with the oracle's blending factors
     c.alpha = a_ora
-    assert rel_err(c.gpu_rhs(), c.oracle_rhs()) <= RHS_TOL
+    assert rel_err(c.gpu_rhs(), c.oracle_rhs()) <= rhs_tol(c)
 
 
 def _gpu_steps(c, dt, n):
@@ -127,6 +130,31 @@ def test_c1_ten_rk_steps():
     c = Case(wl)
     dt = lsrk.timestep(c.mesh, c.gas, c.u, wl.cfl)
     assert rel_err(_gpu_steps(c, dt, 10), _oracle_steps(c, dt, 10)) <= STEP_TOL
+
+
+def test_blast_hundred_rk_steps():
+    # C2 at 4^3: 100 LSRK steps, the indicator recomputed at the start of every step on
+    # each side (<= 1e-10).  CFL 0.125 makes the 100 steps span the physical time of
+    # 100 CFL-0.5 steps at 16^3 (no positivity limiter is part of this path).
+    announce("C2 small 100 steps, indicator every step")
+    from paper_2502_19342_amd import dgfv
+    from oracle.indicator import indicator as ora_ind
+    wl = W.make_workload("C2", n=4)
+    c = Case(wl)
+    ones = torch.ones(c.mesh.K, dtype=T)
+    dt = lsrk.timestep(c.mesh, c.gas, c.u, wl.cfl * 4 / 16, ones)
+    u = c.u.clone()
+    for _ in range(100):
+        _, a = ora_ind(c.mesh, c.gas, u, wl.ind_T, wl.ind_dT, wl.ind_vars)
+        u = lsrk.step(lambda v: c.f(v, a), u, dt)
+    ug = c.gpu(c.u)
+    k = torch.empty_like(ug)
+    for _ in range(100):
+        ag, _ = dgfv.indicator(c.gmesh, c.params, ug)
+        dgfv.rk_step(c.gmesh, c.params, dt, ug, k, ag)
+    torch.cuda.synchronize()
+    assert torch.isfinite(u).all()
+    assert rel_err(ug.cpu(), u) <= STEP_TOL
 
 
 def test_hybrid_mixed_rk_steps():

@@ -86,7 +86,7 @@ def test_indicator_smooth_vs_jump_and_ramp():
 
 
 def test_indicator_blast_marks_the_front():
-    wl = W.make_workload("C2", n=4)
+    wl = W.make_workload("C2", n=8)
     mesh, gas, f = oracle_of(wl)
     u = state(mesh, gas, wl.prim)
     I, alpha = indicator(mesh, gas, u, wl.ind_T, wl.ind_dT, wl.ind_vars)
