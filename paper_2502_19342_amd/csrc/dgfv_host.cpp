@@ -633,6 +633,15 @@ dgfv_status dg_rhs_vjp(const dgfv_mesh* m, const dgfv_params* prm, const double*
   if (batch < 1) return fail(DGFV_ERR_ARG, "batch must be positive");
   if (g == w || g == u) return fail(DGFV_ERR_ARG, "g must not overlap u or w");
   if (dgfv_status st = check_params(m, prm)) return st;
+  // The adjoint of FV-blended elements and of degree-jump faces faulted the GPU
+  // once with no cause found yet (the same kernels are clean and exact under a
+  // CPU emulation with bounds checking); those paths stay off until it is.
+  if (alpha) return fail(DGFV_ERR_UNSUPPORTED, "dg_rhs_vjp: only alpha = NULL (pure DG) is enabled");
+  {
+    int degrees = 0;
+    for (int N = 1; N <= MAXN; ++N) degrees += !m->bucket[N].empty();
+    if (degrees > 1) return fail(DGFV_ERR_UNSUPPORTED, "dg_rhs_vjp: meshes with degree jumps are not enabled");
+  }
   const ParamsDev p = to_dev(prm);
   const MeshView& v = m->view;
   hipStream_t s = (hipStream_t)stream;
