@@ -39,73 +39,101 @@ element_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const d
   using G = Geo<N>;
   constexpr int NP = G::NP, NP2 = G::NP2, NP3 = G::NP3, EPB = G::EPB;
   constexpr int NA = FLUX::NA;
+  // Each pair (i, m) of a line is evaluated once: offsets o = 1..NOFF send the
+  // partner's share 2 D_mi f# through sInc; for even NP the pairs at offset
+  // NP/2 are evaluated from both ends (no exchange).
+  constexpr int NOFF = (NP - 1) / 2;
+  constexpr bool HALF = (NP % 2) == 0;
   __shared__ double sD[NP * NP];
   __shared__ double sAux[EPB][NA][NP3];
-  __shared__ double sJa[EPB][9][NP3];
+  __shared__ double sJa[EPB][3][NP3];          // Ja^d of the current direction
+  __shared__ double sInc[NOFF > 0 ? EPB : 1][NV][NOFF > 0 ? NP3 : 1];
 
   const int tid = threadIdx.x;
   const int slot = tid / NP3;
   const int node = tid - slot * NP3;
   const int idx = blockIdx.x * EPB + slot;
-  const bool active = idx < count;
+  const bool active = idx < count;          // inactive lanes mirror element 0 and write nothing
 
   for (int t = tid; t < NP * NP; t += blockDim.x) sD[t] = 2.0 * m.ops[m.tab.D[N] + t];
 
-  int e = 0;
-  int64_t base = 0;
+  const int e = elist[active ? idx : 0];
+  const int64_t base = m.elem_offset[e] + node;
   double uo[NV];
-  double invJ = 0.0;
-  if (active) {
-    e = elist[idx];
-    base = m.elem_offset[e] + node;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) uo[v] = u[v * m.n_node + base];
+  for (int v = 0; v < NV; ++v) uo[v] = u[v * m.n_node + base];
+  {
     const Prim q = cons2prim<NV>(uo, m.gas);
     double r[NA];
     FLUX::template make<NV>(q, r);
 #pragma unroll
     for (int a = 0; a < NA; ++a) sAux[slot][a][node] = r[a];
-#pragma unroll
-    for (int c = 0; c < 9; ++c) sJa[slot][c][node] = m.metric[c * m.n_node + base];
-    invJ = 1.0 / m.metric[9 * m.n_node + base];
   }
-  __syncthreads();
-  if (!active) return;
+  const double invJ = 1.0 / m.metric[9 * m.n_node + base];
 
   const int i = node % NP, j = (node / NP) % NP, kk = node / NP2;
   double acc[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) acc[v] = 0.0;
-
   double me[NA];
-#pragma unroll
-  for (int a = 0; a < NA; ++a) me[a] = sAux[slot][a][node];
 
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
+    const double ja1 = m.metric[(3 * d + 0) * m.n_node + base];
+    const double ja2 = m.metric[(3 * d + 1) * m.n_node + base];
+    const double ja3 = m.metric[(3 * d + 2) * m.n_node + base];
+    if (d > 0) __syncthreads();               // previous direction done with sJa and sInc
+    sJa[slot][0][node] = ja1;
+    sJa[slot][1][node] = ja2;
+    sJa[slot][2][node] = ja3;
+    __syncthreads();
+    if (d == 0) {
+#pragma unroll
+      for (int a = 0; a < NA; ++a) me[a] = sAux[slot][a][node];
+    }
     const int id = d == 0 ? i : (d == 1 ? j : kk);
     const int stride = d == 0 ? 1 : (d == 1 ? NP : NP2);
-    const double ja1 = sJa[slot][3 * d + 0][node];
-    const double ja2 = sJa[slot][3 * d + 1][node];
-    const double ja3 = sJa[slot][3 * d + 2][node];
 #pragma unroll 1
-    for (int o = 1; o < NP; ++o) {
+    for (int o = 1; o <= NOFF; ++o) {
       int mm = id + o;
       if (mm >= NP) mm -= NP;
       const int pn = node + (mm - id) * stride;
       double other[NA];
 #pragma unroll
       for (int a = 0; a < NA; ++a) other[a] = sAux[slot][a][pn];
-      const double a1 = 0.5 * (ja1 + sJa[slot][3 * d + 0][pn]);
-      const double a2 = 0.5 * (ja2 + sJa[slot][3 * d + 1][pn]);
-      const double a3 = 0.5 * (ja3 + sJa[slot][3 * d + 2][pn]);
+      const double a1 = 0.5 * (ja1 + sJa[slot][0][pn]);
+      const double a2 = 0.5 * (ja2 + sJa[slot][1][pn]);
+      const double a3 = 0.5 * (ja3 + sJa[slot][2][pn]);
       double f[NV];
-      FLUX::template flux<NV>(me, other, a1, a2, a3, m.gas, f);
-      const double c = sD[id * NP + mm];
+      FLUX::template flux_fast<NV>(me, other, a1, a2, a3, m.gas, f);
+      const double c1 = sD[id * NP + mm], c2 = sD[mm * NP + id];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) acc[v] += c * f[v];
+      for (int v = 0; v < NV; ++v) acc[v] += c1 * f[v];
+      if (o > 1) __syncthreads();             // partner has read the previous round's share
+#pragma unroll
+      for (int v = 0; v < NV; ++v) sInc[slot][v][pn] = c2 * f[v];
+      __syncthreads();
+#pragma unroll
+      for (int v = 0; v < NV; ++v) acc[v] += sInc[slot][v][node];
+    }
+    if constexpr (HALF) {
+      int mm = id + NP / 2;
+      if (mm >= NP) mm -= NP;
+      const int pn = node + (mm - id) * stride;
+      double other[NA];
+#pragma unroll
+      for (int a = 0; a < NA; ++a) other[a] = sAux[slot][a][pn];
+      const double a1 = 0.5 * (ja1 + sJa[slot][0][pn]);
+      const double a2 = 0.5 * (ja2 + sJa[slot][1][pn]);
+      const double a3 = 0.5 * (ja3 + sJa[slot][2][pn]);
+      double f[NV];
+      FLUX::template flux_fast<NV>(me, other, a1, a2, a3, m.gas, f);
+      const double c1 = sD[id * NP + mm];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) acc[v] += c1 * f[v];
     }
   }
+  if (!active) return;
 
   // surface lift: outward numerical flux over the end weight on boundary nodes
   const double inv_w0 = 1.0 / m.ops[m.tab.w[N]];
@@ -147,164 +175,220 @@ element_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const d
 }
 
 // ---------------------------------------------------------------------------
-// sub-cell means of blended elements: ubar = V3(J u) / V3(J)
+// FV sub-cell operator of blended elements.
+//   means:    ubar = V3(J u) / V3(J)                         (V^{DG->FV}, Section 3.2)
+//   residual: dC/dt = -(sum of outward sub-face fluxes),
+//             R^FV = V3^+(dC/dt) / (h^3 J)                    (eq. semidiscrete_fv, V^{FV->DG})
+// Sub-face normals n*s = h^2 x mean of Ja^d over the sub-face (face_interp along
+// d, dg2fv along the tangential directions) depend on geometry only; they are
+// formed once per mesh (fv_normals_kernel) for the NFV-1 internal planes of
+// each direction: fvnorm[e][d][c][q][a][b], q = 0..NFV-2 the plane between
+// sub-cells q and q+1, (a, b) the tangential sub-cell indices (slower, faster).
 // ---------------------------------------------------------------------------
 constexpr int FV_THREADS = 256;
 
-template <int N, int NV>
+template <int N>
 __global__ void __launch_bounds__(FV_THREADS)
-fv_means_kernel(MeshView m, const int32_t* __restrict__ elist, int count,
-                const double* __restrict__ u, const double* __restrict__ alpha) {
+fv_normals_kernel(MeshView m, const int32_t* __restrict__ elist, int count) {
   constexpr int NP = N + 1, NP3 = NP * NP * NP;
-  constexpr int NF = NV + 1;                  // J*u (NV fields) and J
-  constexpr int CAP = NF * MAXFV * MAXFV * MAXFV;
-  __shared__ double bufA[CAP];
-  __shared__ double bufB[CAP];
+  constexpr int NRM = 3 * (MAXFV + 1) * MAXFV * MAXFV;
+  __shared__ double sJa[9 * NP3];
+  __shared__ double sA[NRM];
+  __shared__ double sB[NRM];
   __shared__ double sV[MAXFV * (MAXN + 1)];
+  __shared__ double sI[(MAXFV + 1) * (MAXN + 1)];
   const int idx = blockIdx.x;
   if (idx >= count) return;
   const int e = elist[idx];
-  if (!(alpha[e] > 0.0)) return;
   const int NFV = m.n_fv;
+  const int S2 = NFV * NFV, NIF = (NFV - 1) * S2;
+  const double h = 2.0 / NFV;
   const int64_t base = m.elem_offset[e];
+  for (int t = threadIdx.x; t < 9 * NP3; t += blockDim.x)
+    sJa[t] = m.metric[(t / NP3) * m.n_node + base + (t % NP3)];
   for (int t = threadIdx.x; t < NFV * NP; t += blockDim.x) sV[t] = m.ops[m.tab.dg2fv[N] + t];
-  for (int t = threadIdx.x; t < NP3; t += blockDim.x) {
-    const double J = m.metric[9 * m.n_node + base + t];
-    for (int v = 0; v < NV; ++v) bufA[v * NP3 + t] = J * u[v * m.n_node + base + t];
-    bufA[NV * NP3 + t] = J;
-  }
+  for (int t = threadIdx.x; t < (NFV + 1) * NP; t += blockDim.x) sI[t] = m.ops[m.tab.face_interp[N] + t];
   __syncthreads();
-  contract_axis(bufA, bufB, sV, NFV, NP, NF, NP, NP, NP, 0);
-  __syncthreads();
-  contract_axis(bufB, bufA, sV, NFV, NP, NF, NP, NP, NFV, 1);
-  __syncthreads();
-  contract_axis(bufA, bufB, sV, NFV, NP, NF, NP, NFV, NFV, 2);
-  __syncthreads();
-  const int S3 = NFV * NFV * NFV;
-  double* ub = m.ubar + (size_t)e * NV * S3;
-  for (int t = threadIdx.x; t < S3; t += blockDim.x) {
-    const double ivol = 1.0 / bufB[NV * S3 + t];
-    for (int v = 0; v < NV; ++v) ub[v * S3 + t] = bufB[v * S3 + t] * ivol;
+  double* out = m.fvnorm + (size_t)e * 9 * NIF;
+  for (int d = 0; d < 3; ++d) {
+    contract_axis(sJa + 3 * d * NP3, sA, sI, NFV + 1, NP, 3, NP, NP, NP, d);
+    __syncthreads();
+    int a2 = (d == 2) ? NFV + 1 : NP, a1 = (d == 1) ? NFV + 1 : NP, a0 = (d == 0) ? NFV + 1 : NP;
+    const int ta = (d == 0) ? 1 : 0;
+    const int tb = (d == 2) ? 1 : 2;
+    contract_axis(sA, sB, sV, NFV, NP, 3, a2, a1, a0, ta);
+    __syncthreads();
+    if (ta == 0) a0 = NFV; else a1 = NFV;
+    contract_axis(sB, sA, sV, NFV, NP, 3, a2, a1, a0, tb);
+    __syncthreads();
+    if (tb == 1) a1 = NFV; else a2 = NFV;
+    const int nn = a2 * a1 * a0;
+    for (int t = threadIdx.x; t < 3 * nn; t += blockDim.x) {
+      const int c = t / nn, r = t % nn;
+      const int x0 = r % a0, x1 = (r / a0) % a1, x2 = r / (a0 * a1);
+      int q, a, b;
+      if (d == 0) { q = x0; a = x2; b = x1; }
+      else if (d == 1) { q = x1; a = x2; b = x0; }
+      else { q = x2; a = x1; b = x0; }
+      if (q == 0 || q == NFV) continue;
+      out[(d * 3 + c) * NIF + ((q - 1) * NFV + a) * NFV + b] = sA[t] * (h * h);
+    }
+    __syncthreads();
   }
 }
 
-// ---------------------------------------------------------------------------
-// FV sub-cell residual of blended elements, in nodal form:
-//   dC/dt = -(sum of outward sub-face fluxes),  R^FV = V3^+(dC/dt) / (h^3 J)
-// Sub-face normals: h^2 x mean of Ja^d over the sub-face (face_interp along d,
-// dg2fv along the tangential directions).
-// ---------------------------------------------------------------------------
-template <int N, int NV>
-__global__ void __launch_bounds__(FV_THREADS)
-fv_residual_kernel(MeshView m, ParamsDev prm, const int32_t* __restrict__ elist, int count,
-                   const double* __restrict__ alpha) {
-  constexpr int NP = N + 1, NP3 = NP * NP * NP;
-  constexpr int S3MAX = MAXFV * MAXFV * MAXFV;
-  __shared__ double sU[NV * S3MAX];          // sub-cell means
-  __shared__ double sC[NV * S3MAX];          // dC/dt accumulator, later scratch
-  __shared__ double sJa[9 * NP3];
-  __shared__ double sG[NV * (MAXFV + 1) * MAXFV * MAXFV];   // interface fluxes / normal scratch
-  __shared__ double sNrm[3 * (MAXFV + 1) * MAXFV * MAXFV];
-  __shared__ double sV[MAXFV * (MAXN + 1)];
-  __shared__ double sVp[MAXFV * (MAXN + 1)];
-  __shared__ double sI[(MAXFV + 1) * (MAXN + 1)];
+constexpr int FV2_THREADS = 512;
 
+template <int N, int NFV, int NV>
+__global__ void __launch_bounds__(FV2_THREADS)
+fv_means_kernel(MeshView m, const int32_t* __restrict__ elist, int count,
+                const double* __restrict__ u, const double* __restrict__ alpha) {
+  constexpr int NP = N + 1, NP3 = NP * NP * NP, S3 = NFV * NFV * NFV;
+  constexpr int NF = NV + 1;                  // J*u (NV fields) and J
+  __shared__ double bufA[NF * S3];
+  __shared__ double bufB[NF * S3];
+  __shared__ double sV[NFV * NP];
   const int idx = blockIdx.x;
   if (idx >= count) return;
   const int e = elist[idx];
   if (!(alpha[e] > 0.0)) return;
-  const int NFV = m.n_fv;
-  const int S2 = NFV * NFV, S3 = S2 * NFV;
-  const double h = 2.0 / NFV;
+  const int t = threadIdx.x;
   const int64_t base = m.elem_offset[e];
-  const double* ub = m.ubar + (size_t)e * NV * S3;
-  for (int t = threadIdx.x; t < NV * S3; t += blockDim.x) {
-    sU[t] = ub[t];
-    sC[t] = 0.0;
+  if (t < NFV * NP) sV[t] = m.ops[m.tab.dg2fv[N] + t];
+  for (int r = t; r < NP3; r += FV2_THREADS) {
+    const double J = m.metric[9 * m.n_node + base + r];
+    for (int v = 0; v < NV; ++v) bufA[v * NP3 + r] = J * u[v * m.n_node + base + r];
+    bufA[NV * NP3 + r] = J;
   }
-  for (int t = threadIdx.x; t < 9 * NP3; t += blockDim.x)
-    sJa[t] = m.metric[(t / NP3) * m.n_node + base + (t % NP3)];
-  for (int t = threadIdx.x; t < NFV * NP; t += blockDim.x) {
-    sV[t] = m.ops[m.tab.dg2fv[N] + t];
-    sVp[t] = m.ops[m.tab.fv2dg[N] + t];
-  }
-  for (int t = threadIdx.x; t < (NFV + 1) * NP; t += blockDim.x) sI[t] = m.ops[m.tab.face_interp[N] + t];
   __syncthreads();
+  // axis 0: [f][k][j][c] -> [f][k][j][s0]
+  for (int r = t; r < NF * NP * NP * NFV; r += FV2_THREADS) {
+    const int s0 = r % NFV, jk = (r / NFV) % (NP * NP), f = r / (NFV * NP * NP);
+    const double* src = bufA + f * NP3 + jk * NP;
+    double acc = 0.0;
+#pragma unroll
+    for (int c = 0; c < NP; ++c) acc += sV[s0 * NP + c] * src[c];
+    bufB[r] = acc;
+  }
+  __syncthreads();
+  // axis 1: [f][k][c][s0] -> [f][k][s1][s0]
+  for (int r = t; r < NF * NP * NFV * NFV; r += FV2_THREADS) {
+    const int s0 = r % NFV, s1 = (r / NFV) % NFV, kf = r / (NFV * NFV);   // kf = f*NP + k
+    const double* src = bufB + kf * NP * NFV + s0;
+    double acc = 0.0;
+#pragma unroll
+    for (int c = 0; c < NP; ++c) acc += sV[s1 * NP + c] * src[c * NFV];
+    bufA[r] = acc;
+  }
+  __syncthreads();
+  // axis 2: [f][c][s1][s0] -> [f][s2][s1][s0]
+  for (int r = t; r < NF * S3; r += FV2_THREADS) {
+    const int s01 = r % (NFV * NFV), s2 = (r / (NFV * NFV)) % NFV, f = r / S3;
+    const double* src = bufA + f * NP * NFV * NFV + s01;
+    double acc = 0.0;
+#pragma unroll
+    for (int c = 0; c < NP; ++c) acc += sV[s2 * NP + c] * src[c * NFV * NFV];
+    bufB[r] = acc;
+  }
+  __syncthreads();
+  double* ub = m.ubar + (size_t)e * NV * S3;
+  for (int r = t; r < S3; r += FV2_THREADS) {
+    const double ivol = 1.0 / bufB[NV * S3 + r];
+    for (int v = 0; v < NV; ++v) ub[v * S3 + r] = bufB[v * S3 + r] * ivol;
+  }
+}
 
+template <int N, int NFV, int NV>
+__global__ void __launch_bounds__(FV2_THREADS)
+fv_residual_kernel(MeshView m, ParamsDev prm, const int32_t* __restrict__ elist, int count,
+                   const double* __restrict__ alpha) {
+  constexpr int NP = N + 1, NP3 = NP * NP * NP;
+  constexpr int S2 = NFV * NFV, S3 = S2 * NFV, NIF = (NFV - 1) * S2;
+  static_assert(S3 <= FV2_THREADS, "one thread per sub-cell");
+  __shared__ double sU[NV * S3];
+  __shared__ double sG[NV * S3];
+  __shared__ double sVp[NP * NFV];
+  const int idx = blockIdx.x;
+  if (idx >= count) return;
+  const int e = elist[idx];
+  if (!(alpha[e] > 0.0)) return;
+  const int t = threadIdx.x;
+  const int64_t base = m.elem_offset[e];
+  const double h = 2.0 / NFV;
+  const double* ub = m.ubar + (size_t)e * NV * S3;
+  for (int r = t; r < NV * S3; r += FV2_THREADS) sU[r] = ub[r];
+  if (t < NP * NFV) sVp[t] = m.ops[m.tab.fv2dg[N] + t];
+  const double* nrm = m.fvnorm + (size_t)e * 9 * NIF;
   const double* fvs = m.fvside + (size_t)e * 6 * NV * S2;
+  const bool active = t < S3;
+  const int s0 = t % NFV, s1 = (t / NFV) % NFV, s2 = t / S2;
+  double dC[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) dC[v] = 0.0;
+  __syncthreads();
+#pragma unroll
   for (int d = 0; d < 3; ++d) {
-    // normals of the NFV+1 interface planes along d: [3][..] with axis d of size NFV+1
-    // three passes on the 3 components of Ja^d; scratch in sG (fits 3*(NFV+1)*NP*NP? see CAP)
-    const double* src = sJa + 3 * d * NP3;
-    // pass over axis d first with face_interp, then tangential axes with dg2fv
-    int n2 = NP, n1 = NP, n0 = NP;
-    // stage 1
-    double* t1 = sG;
-    double* t2 = sNrm;
-    contract_axis(src, t1, sI, NFV + 1, NP, 3, n2, n1, n0, d);
-    __syncthreads();
-    int a2 = (d == 2) ? NFV + 1 : NP, a1 = (d == 1) ? NFV + 1 : NP, a0 = (d == 0) ? NFV + 1 : NP;
-    // remaining two axes (tangential), each NP -> NFV
-    const int ta = (d == 0) ? 1 : 0;
-    const int tb = (d == 2) ? 1 : 2;
-    contract_axis(t1, t2, sV, NFV, NP, 3, a2, a1, a0, ta);
-    __syncthreads();
-    if (ta == 0) a0 = NFV; else a1 = NFV;
-    contract_axis(t2, t1, sV, NFV, NP, 3, a2, a1, a0, tb);
-    __syncthreads();
-    if (tb == 1) a1 = NFV; else a2 = NFV;
-    // t1 (= sG) now holds normals [3][a2][a1][a0]; scale by h^2 and move to sNrm
-    const int nn = a2 * a1 * a0;
-    for (int t = threadIdx.x; t < 3 * nn; t += blockDim.x) sNrm[t] = sG[t] * (h * h);
-    __syncthreads();
-    // interface fluxes G[q] (+xi_d direction) on the same index layout, NV fields
-    for (int t = threadIdx.x; t < nn; t += blockDim.x) {
-      const int x0 = t % a0, x1 = (t / a0) % a1, x2 = t / (a0 * a1);
-      const int q = (d == 0) ? x0 : (d == 1 ? x1 : x2);
-      // the two tangential sub-cell indices in face (p, q') order
-      int fp, fq;
-      if (d == 0) { fp = x1; fq = x2; }
-      else if (d == 1) { fp = x0; fq = x2; }
-      else { fp = x0; fq = x1; }
-      double F[NV];
-      if (q == 0) {
-        for (int v = 0; v < NV; ++v) F[v] = -fvs[((2 * d) * NV + v) * S2 + fq * NFV + fp];
-      } else if (q == NFV) {
-        for (int v = 0; v < NV; ++v) F[v] = fvs[((2 * d + 1) * NV + v) * S2 + fq * NFV + fp];
-      } else {
-        int sl, sr;   // sub-cell indices left/right of the interface
-        if (d == 0) { sl = (x2 * NFV + x1) * NFV + (q - 1); sr = sl + 1; }
-        else if (d == 1) { sl = (x2 * NFV + (q - 1)) * NFV + x0; sr = sl + NFV; }
-        else { sl = ((q - 1) * NFV + x1) * NFV + x0; sr = sl + S2; }
-        double uL[NV], uR[NV];
-        for (int v = 0; v < NV; ++v) { uL[v] = sU[v * S3 + sl]; uR[v] = sU[v * S3 + sr]; }
-        riemann<NV>(prm.face_flux_fv, prm.volume_flux, uL, uR, sNrm[t], sNrm[nn + t],
-                    sNrm[2 * nn + t], m.gas, F);
+    const int sd = d == 0 ? s0 : (d == 1 ? s1 : s2);
+    const int stride = d == 0 ? 1 : (d == 1 ? NFV : S2);
+    const int ta = d == 2 ? s1 : s2, tb = d == 0 ? s1 : s0;     // tangential (slower, faster)
+    const int fidx = ta * NFV + tb;                            // face-grid index on the sides
+    if (active && sd < NFV - 1) {
+      double uL[NV], uR[NV], F[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        uL[v] = sU[v * S3 + t];
+        uR[v] = sU[v * S3 + t + stride];
       }
-      for (int v = 0; v < NV; ++v) sG[v * nn + t] = F[v];
+      const int k = (sd * NFV + ta) * NFV + tb;
+      riemann<NV>(prm.face_flux_fv, prm.volume_flux, uL, uR, nrm[(d * 3 + 0) * NIF + k],
+                  nrm[(d * 3 + 1) * NIF + k], nrm[(d * 3 + 2) * NIF + k], m.gas, F);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) sG[v * S3 + t] = F[v];
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < S3; t += blockDim.x) {
-      const int s0 = t % NFV, s1 = (t / NFV) % NFV, s2 = t / S2;
-      int lo, hi;
-      if (d == 0) { lo = (s2 * NFV + s1) * (NFV + 1) + s0; hi = lo + 1; }
-      else if (d == 1) { lo = (s2 * (NFV + 1) + s1) * NFV + s0; hi = lo + NFV; }
-      else { lo = (s2 * NFV + s1) * NFV + s0; hi = lo + S2; }
-      for (int v = 0; v < NV; ++v) sC[v * S3 + t] -= sG[v * nn + hi] - sG[v * nn + lo];
+    if (active) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const double hi = sd < NFV - 1 ? sG[v * S3 + t] : fvs[((2 * d + 1) * NV + v) * S2 + fidx];
+        const double lo = sd > 0 ? sG[v * S3 + t - stride] : -fvs[((2 * d) * NV + v) * S2 + fidx];
+        dC[v] -= hi - lo;
+      }
     }
     __syncthreads();
   }
-  // nodal form: V3^+ (dC/dt) / (h^3 J); sC [NV][S3] -> sU as scratch
-  contract_axis(sC, sU, sVp, NP, NFV, NV, NFV, NFV, NFV, 0);
+  // nodal form: V3^+(dC) / (h^3 J)
+  if (active) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sG[v * S3 + t] = dC[v];
+  }
   __syncthreads();
-  contract_axis(sU, sC, sVp, NP, NFV, NV, NFV, NFV, NP, 1);
+  for (int r = t; r < NV * S2 * NP; r += FV2_THREADS) {        // [v][s2][s1][i]
+    const int i = r % NP, q = r / NP;                        // q = v*S2 + s2*NFV + s1
+    const double* src = sG + q * NFV;
+    double acc = 0.0;
+#pragma unroll
+    for (int c = 0; c < NFV; ++c) acc += sVp[i * NFV + c] * src[c];
+    sU[r] = acc;
+  }
   __syncthreads();
-  contract_axis(sC, sU, sVp, NP, NFV, NV, NFV, NP, NP, 2);
+  for (int r = t; r < NV * NFV * NP * NP; r += FV2_THREADS) {  // [v][s2][j][i]
+    const int i = r % NP, j = (r / NP) % NP, q = r / (NP * NP); // q = v*NFV + s2
+    const double* src = sU + q * NFV * NP + i;
+    double acc = 0.0;
+#pragma unroll
+    for (int c = 0; c < NFV; ++c) acc += sVp[j * NFV + c] * src[c * NP];
+    sG[r] = acc;
+  }
   __syncthreads();
   const double ih3 = 1.0 / (h * h * h);
-  for (int t = threadIdx.x; t < NP3; t += blockDim.x) {
-    const double iJ = 1.0 / m.metric[9 * m.n_node + base + t];
-    for (int v = 0; v < NV; ++v) m.rfv[v * m.n_node + base + t] = sU[v * NP3 + t] * ih3 * iJ;
+  for (int r = t; r < NV * NP3; r += FV2_THREADS) {          // [v][k][j][i]
+    const int ij = r % (NP * NP), k = (r / (NP * NP)) % NP, v = r / NP3;
+    const double* src = sG + v * NFV * NP * NP + ij;
+    double acc = 0.0;
+#pragma unroll
+    for (int c = 0; c < NFV; ++c) acc += sVp[k * NFV + c] * src[c * NP * NP];
+    const int node = k * NP * NP + ij;
+    m.rfv[v * m.n_node + base + node] = acc * ih3 / m.metric[9 * m.n_node + base + node];
   }
 }
 
@@ -756,23 +840,65 @@ hipError_t element(const MeshView& m, const ParamsDev& p, const int32_t* elist, 
   return launch_elem_t<6, FluxCentral>(m, elist, count, u, alpha, ut, k, stage, dt, A, B, s);
 }
 
+template <int NFV>
+hipError_t fv_means_t(const MeshView& m, const int32_t* elist, int count, const double* u,
+                      const double* alpha, hipStream_t s) {
+  if constexpr (NFV >= kN + 1) {
+    if (m.nvar == 5)
+      hipLaunchKernelGGL((fv_means_kernel<kN, NFV, 5>), dim3(count), dim3(FV2_THREADS), 0, s, m, elist, count, u, alpha);
+    else
+      hipLaunchKernelGGL((fv_means_kernel<kN, NFV, 6>), dim3(count), dim3(FV2_THREADS), 0, s, m, elist, count, u, alpha);
+    return hipGetLastError();
+  }
+  return hipErrorInvalidValue;
+}
+
 hipError_t fv_means(const MeshView& m, const int32_t* elist, int count, const double* u,
                     const double* alpha, hipStream_t s) {
   if (count == 0) return hipSuccess;
-  if (m.nvar == 5)
-    hipLaunchKernelGGL((fv_means_kernel<kN, 5>), dim3(count), dim3(FV_THREADS), 0, s, m, elist, count, u, alpha);
-  else
-    hipLaunchKernelGGL((fv_means_kernel<kN, 6>), dim3(count), dim3(FV_THREADS), 0, s, m, elist, count, u, alpha);
-  return hipGetLastError();
+  switch (m.n_fv) {
+    case 2: return fv_means_t<2>(m, elist, count, u, alpha, s);
+    case 3: return fv_means_t<3>(m, elist, count, u, alpha, s);
+    case 4: return fv_means_t<4>(m, elist, count, u, alpha, s);
+    case 5: return fv_means_t<5>(m, elist, count, u, alpha, s);
+    case 6: return fv_means_t<6>(m, elist, count, u, alpha, s);
+    case 7: return fv_means_t<7>(m, elist, count, u, alpha, s);
+    case 8: return fv_means_t<8>(m, elist, count, u, alpha, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int NFV>
+hipError_t fv_residual_t(const MeshView& m, const ParamsDev& p, const int32_t* elist, int count,
+                         const double* alpha, hipStream_t s) {
+  if constexpr (NFV >= kN + 1) {
+    if (m.nvar == 5)
+      hipLaunchKernelGGL((fv_residual_kernel<kN, NFV, 5>), dim3(count), dim3(FV2_THREADS), 0, s, m, p, elist, count, alpha);
+    else
+      hipLaunchKernelGGL((fv_residual_kernel<kN, NFV, 6>), dim3(count), dim3(FV2_THREADS), 0, s, m, p, elist, count, alpha);
+    return hipGetLastError();
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t fv_residual(const MeshView& m, const ParamsDev& p, const int32_t* elist, int count,
                        const double* alpha, hipStream_t s) {
   if (count == 0) return hipSuccess;
-  if (m.nvar == 5)
-    hipLaunchKernelGGL((fv_residual_kernel<kN, 5>), dim3(count), dim3(FV_THREADS), 0, s, m, p, elist, count, alpha);
-  else
-    hipLaunchKernelGGL((fv_residual_kernel<kN, 6>), dim3(count), dim3(FV_THREADS), 0, s, m, p, elist, count, alpha);
+  switch (m.n_fv) {
+    case 2: return fv_residual_t<2>(m, p, elist, count, alpha, s);
+    case 3: return fv_residual_t<3>(m, p, elist, count, alpha, s);
+    case 4: return fv_residual_t<4>(m, p, elist, count, alpha, s);
+    case 5: return fv_residual_t<5>(m, p, elist, count, alpha, s);
+    case 6: return fv_residual_t<6>(m, p, elist, count, alpha, s);
+    case 7: return fv_residual_t<7>(m, p, elist, count, alpha, s);
+    case 8: return fv_residual_t<8>(m, p, elist, count, alpha, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t fv_normals(const MeshView& m, const int32_t* elist, int count, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL((fv_normals_kernel<kN>), dim3(count), dim3(FV_THREADS), 0, s, m, elist, count);
   return hipGetLastError();
 }
 
@@ -844,7 +970,7 @@ hipError_t vjp_gather(const MeshView& m, const int32_t* elist, int count, const 
 DegreeOps DGFV_CAT(degree_ops_, DGFV_N)() {
   return DegreeOps{&per_degree::element,    &per_degree::fv_means, &per_degree::fv_residual,
                    &per_degree::indicator,  &per_degree::vjp_volume, &per_degree::vjp_fv,
-                   &per_degree::vjp_gather};
+                   &per_degree::vjp_gather, &per_degree::fv_normals};
 }
 
 }  // namespace dgfv

@@ -523,6 +523,7 @@ dgfv_status dgfv_mesh_create(const dgfv_mesh_desc* d, dgfv_mesh** out) {
     v.ubar = m->keep(dev_alloc<double>((size_t)m->K * m->nvar * NFV * NFV * NFV));
     v.rfv = m->keep(dev_alloc<double>((size_t)m->nvar * m->n_node));
     v.ubar_bar = m->keep(dev_alloc<double>((size_t)m->K * m->nvar * NFV * NFV * NFV));
+    v.fvnorm = m->keep(dev_alloc<double>((size_t)m->K * 9 * (NFV - 1) * NFV * NFV));
     v.ops = m->keep(dev_upload(ops));
     v.tab = tab;
     v.gas.gamma = d->gamma;
@@ -536,6 +537,10 @@ dgfv_status dgfv_mesh_create(const dgfv_mesh_desc* d, dgfv_mesh** out) {
     }
     for (int N = 1; N <= MAXN; ++N)
       if (!m->bucket[N].empty()) m->d_bucket[N] = m->keep(dev_upload(m->bucket[N]));
+    for (int N = 1; N <= MAXN; ++N)
+      if (!m->bucket[N].empty())
+        hip_check(ops_for(N).fv_normals(v, m->d_bucket[N], (int)m->bucket[N].size(), nullptr),
+                  "fv_normals launch");
     hip_check(hipDeviceSynchronize(), "mesh upload");
   } catch (const HipError& e) {
     const std::string msg = e.what();

@@ -55,6 +55,7 @@ struct MeshView {
   double* ubar;                 // sub-cell means, [K][nvar][NFV^3]
   double* rfv;                  // FV residual in nodal form, [nvar][n_node]
   double* ubar_bar;             // adjoint of the sub-cell means, [K][nvar][NFV^3]
+  double* fvnorm;               // sub-face normals of internal planes, [K][3][3][(NFV-1) NFV^2]
   const double* ops;            // operator tables
   OpTables tab;
   GasDev gas;
@@ -82,6 +83,8 @@ struct DegreeOps {
                        const double* alpha, const double* w, hipStream_t s);
   hipError_t (*vjp_gather)(const MeshView& m, const int32_t* elist, int count, const double* alpha,
                            double* g, hipStream_t s);
+  // setup: sub-face normals of the FV sub-cell grid (geometry only)
+  hipError_t (*fv_normals)(const MeshView& m, const int32_t* elist, int count, hipStream_t s);
 };
 DegreeOps degree_ops_1();
 DegreeOps degree_ops_2();
