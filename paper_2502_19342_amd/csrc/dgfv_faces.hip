@@ -1,7 +1,7 @@
 // Interface fluxes of the hybrid DG/FV operator (Section 3.2.1).
 //
-// One face per 64-lane workgroup.  The face class is decided at run time from
-// the degrees and blending factors of its two elements:
+// Three kernels per call, by face class (the class is fixed by the degrees and
+// blending factors of the two elements):
 //  * DG / DG, same degree: the Riemann flux at each face node with the left
 //    side's outward normal n*s = +-Ja^d (eq. conv_flux);
 //  * DG / DG, degrees NL != NR: both traces at M = max(NL, NR) through
@@ -11,6 +11,9 @@
 //    means of a blended side, V^{DG->FV} of a DG side's nodal trace), one
 //    Riemann flux per sub-face with n*s = h^2 V^{DG->FV}(Ja); the FV part of
 //    a blended side receives it directly and every DG part V^{FV->DG} of it / h^2.
+// The first class runs one lane per face node over static per-degree face
+// lists; the second runs one face per 64-lane workgroup over a static list;
+// FV faces are found per call from alpha, one blended element per workgroup.
 // Results go to per-element side buffers: the right side gets the negated flux
 // re-indexed through the face orientation.
 #include "dgfv_internal.h"
@@ -84,17 +87,69 @@ __device__ void write_side(double* dst_block, const double* src, int side, int o
   }
 }
 
-template <int NV>
-__global__ void __launch_bounds__(FACE_THREADS)
-face_kernel(MeshView m, ParamsDev prm, const double* __restrict__ u, const double* __restrict__ alpha) {
-  __shared__ double sL[NV * GRID];
-  __shared__ double sR[NV * GRID];
-  __shared__ double sF[NV * GRID];
-  __shared__ double sN[3 * GRID];
-  __shared__ double sTmp[3 * NV * GRID];
+// Rows pp and qq of A ([nout][nin] row-major, nin <= MAXN + 1) in registers,
+// zero-padded.
+struct MapRows {
+  double ap[MAXN + 1], aq[MAXN + 1];
+  __device__ MapRows(const double* A, int nin, int pp, int qq) {
+#pragma unroll
+    for (int k = 0; k <= MAXN; ++k) {
+      ap[k] = k < nin ? A[pp * nin + k] : 0.0;
+      aq[k] = k < nin ? A[qq * nin + k] : 0.0;
+    }
+  }
+  // one output point of the 2D tensor map A (x) A of a [nin][nin] grid (p fastest)
+  __device__ double apply(const double* src, int nin) const {
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q <= MAXN; ++q) {
+      if (q < nin) {
+        double r = 0.0;
+#pragma unroll
+        for (int p = 0; p <= MAXN; ++p)
+          if (p < nin) r += ap[p] * src[q * nin + p];
+        acc += aq[q] * r;
+      }
+    }
+    return acc;
+  }
+};
 
-  const int f = blockIdx.x;
-  if (f >= m.n_face) return;
+// dst[v][nout^2] = (A (x) A) src[v][nin^2] in LDS, one output point per lane;
+// dst must not alias src, and the caller synchronises before reading dst.
+template <int NF>
+__device__ void map2d_to(const double* src, double* dst, const double* A, int nout, int nin) {
+  for (int t = threadIdx.x; t < nout * nout; t += blockDim.x) {
+    const int pp = t % nout, qq = t / nout;
+    const MapRows rows(A, nin, pp, qq);
+    for (int v = 0; v < NF; ++v) dst[v * GRID + t] = rows.apply(src + v * GRID, nin);
+  }
+}
+
+// The same map written straight into a side buffer (orientation and scale as
+// in write_side).
+template <int NV>
+__device__ void map2d_side(double* dst_block, const double* src, const double* A, int nout, int nin,
+                           int side, int o, bool right, double scale) {
+  const int n2 = nout * nout;
+  for (int t = threadIdx.x; t < n2; t += blockDim.x) {
+    const int pp = t % nout, qq = t / nout;
+    int p = pp, q = qq;
+    if (right) orient_map(o, pp, qq, nout, p, q);
+    const MapRows rows(A, nin, pp, qq);
+    for (int v = 0; v < NV; ++v)
+      dst_block[(side * NV + v) * n2 + q * nout + p] = scale * rows.apply(src + v * GRID, nin);
+  }
+}
+
+// One face, any class, by the whole (64-lane) workgroup, with three
+// workgroup barriers; B0..B3 are [NV][GRID] and sN, sNF [3][GRID] LDS arrays
+// of the caller.  Degree-jump and FV faces need them; conforming DG faces
+// take the pointwise branch.  The caller synchronises before reusing them.
+template <int NV>
+__device__ void face_body(const MeshView& m, const ParamsDev& prm, const double* __restrict__ u,
+                          const double* __restrict__ alpha, int f, double* B0, double* B1, double* B2,
+                          double* B3, double* sN, double* sNF) {
   const int32_t* fc = m.faces + 5 * f;
   const int eL = fc[0], sideL = fc[1], eR = fc[2], sideR = fc[3], o = fc[4];
   const int NL = m.degree[eL], NR = m.degree[eR];
@@ -131,77 +186,162 @@ face_kernel(MeshView m, ParamsDev prm, const double* __restrict__ u, const doubl
       }
       return;
     }
-    // degree jump: common degree M
-    gather_trace<NV>(m, u, eL, sideL, o, false, nL, sL);
-    gather_trace<NV>(m, u, eR, sideR, o, true, nR, sR);
+    // degree jump: both traces at the common degree M, flux there, the lower
+    // side receives the L2 projection
+    gather_trace<NV>(m, u, eL, sideL, o, false, nL, B0);
+    gather_trace<NV>(m, u, eR, sideR, o, true, nR, B1);
     __syncthreads();
-    if (NL < M) map2d(sL, sTmp, sL, m.ops + m.tab.interp[NL][M], nM, nL, NV);
-    if (NR < M) map2d(sR, sTmp, sR, m.ops + m.tab.interp[NR][M], nM, nR, NV);
+    const double* LM = B0;
+    const double* RM = B1;
+    if (NL < M) { map2d_to<NV>(B0, B2, m.ops + m.tab.interp[NL][M], nM, nL); LM = B2; }
+    if (NR < M) { map2d_to<NV>(B1, B3, m.ops + m.tab.interp[NR][M], nM, nR); RM = B3; }
+    __syncthreads();
+    double* F = NL < M ? B0 : B2;
     const int n2 = nM * nM;
     for (int t = threadIdx.x; t < n2; t += blockDim.x) {
-      double uL[NV], uR[NV], F[NV];
+      double uL[NV], uR[NV], Fl[NV];
       for (int v = 0; v < NV; ++v) {
-        uL[v] = sL[v * GRID + t];
-        uR[v] = sR[v * GRID + t];
+        uL[v] = LM[v * GRID + t];
+        uR[v] = RM[v * GRID + t];
       }
       riemann<NV>(prm.face_flux_dg, prm.volume_flux, uL, uR, nrm[t], nrm[n2 + t], nrm[2 * n2 + t],
-                  m.gas, F);
-      for (int v = 0; v < NV; ++v) sF[v * GRID + t] = F[v];
+                  m.gas, Fl);
+      for (int v = 0; v < NV; ++v) F[v * GRID + t] = Fl[v];
+      const int p = t % nM, q = t / nM;
+      if (NL == M)
+        for (int v = 0; v < NV; ++v) bL[(sideL * NV + v) * n2 + q * nM + p] = Fl[v];
+      if (NR == M) {
+        int pp, qq;
+        orient_map(o, p, q, nM, pp, qq);
+        for (int v = 0; v < NV; ++v) bR[(sideR * NV + v) * n2 + qq * nM + pp] = -Fl[v];
+      }
     }
     __syncthreads();
-    if (NL < M) {
-      map2d(sF, sTmp, sL, m.ops + m.tab.project[M][NL], nL, nM, NV);
-      write_side<NV>(bL, sL, sideL, o, false, nL, 1.0);
-    } else {
-      write_side<NV>(bL, sF, sideL, o, false, nL, 1.0);
-    }
-    if (NR < M) {
-      map2d(sF, sTmp, sR, m.ops + m.tab.project[M][NR], nR, nM, NV);
-      write_side<NV>(bR, sR, sideR, o, true, nR, -1.0);
-    } else {
-      write_side<NV>(bR, sF, sideR, o, true, nR, -1.0);
-    }
+    if (NL < M) map2d_side<NV>(bL, F, m.ops + m.tab.project[M][NL], nL, nM, sideL, o, false, 1.0);
+    if (NR < M) map2d_side<NV>(bR, F, m.ops + m.tab.project[M][NR], nR, nM, sideR, o, true, -1.0);
     return;
   }
 
-  // FV face
+  // FV face: sub-face traces, one flux per sub-face
   const int nF = m.n_fv, n2F = nF * nF;
   const double h = 2.0 / nF;
-  if (aL > 0.0) {
-    gather_subcells<NV>(m, eL, sideL, o, false, sL);
-  } else {
-    gather_trace<NV>(m, u, eL, sideL, o, false, nL, sL);
-  }
-  if (aR > 0.0) {
-    gather_subcells<NV>(m, eR, sideR, o, true, sR);
-  } else {
-    gather_trace<NV>(m, u, eR, sideR, o, true, nR, sR);
-  }
+  if (aL > 0.0) gather_subcells<NV>(m, eL, sideL, o, false, B0);
+  else gather_trace<NV>(m, u, eL, sideL, o, false, nL, B0);
+  if (aR > 0.0) gather_subcells<NV>(m, eR, sideR, o, true, B1);
+  else gather_trace<NV>(m, u, eR, sideR, o, true, nR, B1);
   for (int t = threadIdx.x; t < 3 * nM * nM; t += blockDim.x)
     sN[(t / (nM * nM)) * GRID + t % (nM * nM)] = nrm[t];
   __syncthreads();
-  if (!(aL > 0.0)) map2d(sL, sTmp, sL, m.ops + m.tab.dg2fv[NL], nF, nL, NV);
-  if (!(aR > 0.0)) map2d(sR, sTmp, sR, m.ops + m.tab.dg2fv[NR], nF, nR, NV);
-  map2d(sN, sTmp, sN, m.ops + m.tab.dg2fv[M], nF, nM, 3);
+  const double* LF = B0;
+  const double* RF = B1;
+  if (!(aL > 0.0)) { map2d_to<NV>(B0, B2, m.ops + m.tab.dg2fv[NL], nF, nL); LF = B2; }
+  if (!(aR > 0.0)) { map2d_to<NV>(B1, B3, m.ops + m.tab.dg2fv[NR], nF, nR); RF = B3; }
+  map2d_to<3>(sN, sNF, m.ops + m.tab.dg2fv[M], nF, nM);
+  __syncthreads();
+  double* F = LF == B2 ? B0 : B2;
+  double* fvL = m.fvside + (size_t)eL * 6 * NV * n2F;
+  double* fvR = m.fvside + (size_t)eR * 6 * NV * n2F;
+  const double a = h * h;
   for (int t = threadIdx.x; t < n2F; t += blockDim.x) {
-    double uL[NV], uR[NV], F[NV];
+    double uL[NV], uR[NV], Fl[NV];
     for (int v = 0; v < NV; ++v) {
-      uL[v] = sL[v * GRID + t];
-      uR[v] = sR[v * GRID + t];
+      uL[v] = LF[v * GRID + t];
+      uR[v] = RF[v * GRID + t];
     }
-    const double a = h * h;
-    riemann<NV>(prm.face_flux_fv, prm.volume_flux, uL, uR, a * sN[t], a * sN[GRID + t],
-                a * sN[2 * GRID + t], m.gas, F);
-    for (int v = 0; v < NV; ++v) sF[v * GRID + t] = F[v];
+    riemann<NV>(prm.face_flux_fv, prm.volume_flux, uL, uR, a * sNF[t], a * sNF[GRID + t],
+                a * sNF[2 * GRID + t], m.gas, Fl);
+    for (int v = 0; v < NV; ++v) F[v * GRID + t] = Fl[v];
+    const int p = t % nF, q = t / nF;
+    if (aL > 0.0)
+      for (int v = 0; v < NV; ++v) fvL[(sideL * NV + v) * n2F + q * nF + p] = Fl[v];
+    if (aR > 0.0) {
+      int pp, qq;
+      orient_map(o, p, q, nF, pp, qq);
+      for (int v = 0; v < NV; ++v) fvR[(sideR * NV + v) * n2F + qq * nF + pp] = -Fl[v];
+    }
   }
   __syncthreads();
-  if (aL > 0.0) write_side<NV>(m.fvside + (size_t)eL * 6 * NV * n2F, sF, sideL, o, false, nF, 1.0);
-  if (aR > 0.0) write_side<NV>(m.fvside + (size_t)eR * 6 * NV * n2F, sF, sideR, o, true, nF, -1.0);
   const double ih2 = 1.0 / (h * h);
-  map2d(sF, sTmp, sL, m.ops + m.tab.fv2dg[NL], nL, nF, NV);
-  write_side<NV>(bL, sL, sideL, o, false, nL, ih2);
-  map2d(sF, sTmp, sR, m.ops + m.tab.fv2dg[NR], nR, nF, NV);
-  write_side<NV>(bR, sR, sideR, o, true, nR, -ih2);
+  map2d_side<NV>(bL, F, m.ops + m.tab.fv2dg[NL], nL, nF, sideL, o, false, ih2);
+  map2d_side<NV>(bR, F, m.ops + m.tab.fv2dg[NR], nR, nF, sideR, o, true, -ih2);
+}
+
+// Conforming same-degree faces whose two elements are both pure DG: one thread
+// per face node, several faces per workgroup, no LDS.  FV faces are skipped
+// here (face_fv_kernel handles them).
+constexpr int CONF_THREADS = 256;
+
+template <int N, int NV>
+__global__ void __launch_bounds__(CONF_THREADS)
+face_conforming_kernel(MeshView m, ParamsDev prm, const int32_t* __restrict__ flist, int fcount,
+                       const double* __restrict__ u, const double* __restrict__ alpha) {
+  constexpr int NP = N + 1, NP2 = NP * NP, FPB = CONF_THREADS / NP2;
+  const int t = threadIdx.x;
+  const int slot = t / NP2, r = t - slot * NP2;
+  if (slot >= FPB) return;
+  const int fi = blockIdx.x * FPB + slot;
+  if (fi >= fcount) return;
+  const int f = flist[fi];
+  const int32_t* fc = m.faces + 5 * f;
+  const int eL = fc[0], sideL = fc[1], eR = fc[2], sideR = fc[3], o = fc[4];
+  if (alpha && (alpha[eL] > 0.0 || alpha[eR] > 0.0)) return;
+  const int p = r % NP, q = r / NP;
+  int pp, qq;
+  orient_map(o, p, q, NP, pp, qq);
+  const int64_t gL = m.elem_offset[eL] + side_node(sideL, p, q, NP);
+  const int64_t gR = m.elem_offset[eR] + side_node(sideR, pp, qq, NP);
+  const double* nrm = m.face_norm + m.face_norm_off[f];
+  double uL[NV], uR[NV], F[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    uL[v] = u[v * m.n_node + gL];
+    uR[v] = u[v * m.n_node + gR];
+  }
+  riemann<NV>(prm.face_flux_dg, prm.volume_flux, uL, uR, nrm[r], nrm[NP2 + r], nrm[2 * NP2 + r], m.gas, F);
+  double* bL = m.fside + m.side_off[eL];
+  double* bR = m.fside + m.side_off[eR];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    bL[(sideL * NV + v) * NP2 + q * NP + p] = F[v];
+    bR[(sideR * NV + v) * NP2 + qq * NP + pp] = -F[v];
+  }
+}
+
+// Degree-jump faces between two pure DG elements (static list); FV faces are
+// skipped here.  Grid-stride loop, one face per workgroup at a time.
+template <int NV>
+__global__ void __launch_bounds__(FACE_THREADS)
+face_mixed_kernel(MeshView m, ParamsDev prm, const int32_t* __restrict__ flist, int fcount,
+                  const double* __restrict__ u, const double* __restrict__ alpha) {
+  __shared__ double B0[NV * GRID], B1[NV * GRID], B2[NV * GRID], B3[NV * GRID], sN[3 * GRID], sNF[3 * GRID];
+  for (int fi = blockIdx.x; fi < fcount; fi += gridDim.x) {
+    const int f = flist[fi];
+    const int32_t* fc = m.faces + 5 * f;
+    if (alpha && (alpha[fc[0]] > 0.0 || alpha[fc[2]] > 0.0)) continue;
+    face_body<NV>(m, prm, u, alpha, f, B0, B1, B2, B3, sN, sNF);
+    __syncthreads();
+  }
+}
+
+// FV faces: one workgroup per element; a pure DG element leaves at once, a
+// blended one processes the faces it owns (the left element owns a face when
+// it is blended, otherwise the right one).  Blended elements cluster along
+// flow features, so one element per workgroup lets the dispatcher balance the
+// load.
+template <int NV>
+__global__ void __launch_bounds__(FACE_THREADS)
+face_fv_kernel(MeshView m, ParamsDev prm, const double* __restrict__ u, const double* __restrict__ alpha) {
+  __shared__ double B0[NV * GRID], B1[NV * GRID], B2[NV * GRID], B3[NV * GRID], sN[3 * GRID], sNF[3 * GRID];
+  const int e = blockIdx.x;
+  if (e >= m.K || !(alpha[e] > 0.0)) return;
+  for (int side = 0; side < 6; ++side) {
+    const int f = m.elem_face[6 * e + side];
+    const int32_t* fc = m.faces + 5 * f;
+    const bool left = fc[0] == e && fc[1] == side;
+    if (!left && alpha[fc[0]] > 0.0) continue;      // the blended left element owns it
+    face_body<NV>(m, prm, u, alpha, f, B0, B1, B2, B3, sN, sNF);
+    __syncthreads();
+  }
 }
 
 // Gather side data [NV][n*n] from a side block (`right` re-indexes onto the left grid).
@@ -384,14 +524,44 @@ hipError_t launch_faces_vjp(const MeshView& m, const ParamsDev& p, const double*
   return hipGetLastError();
 }
 
+template <int NV>
+static hipError_t launch_faces_t(const MeshView& m, const ParamsDev& p, const double* u,
+                                 const double* alpha, hipStream_t s) {
+  for (int N = 1; N <= MAXN; ++N) {
+    const int cnt = m.face_conf_count[N];
+    if (cnt == 0) continue;
+    const int np2 = (N + 1) * (N + 1), fpb = CONF_THREADS / np2;
+    const dim3 grid((cnt + fpb - 1) / fpb), block(CONF_THREADS);
+    const int32_t* fl = m.face_conf[N];
+    switch (N) {
+      case 1: hipLaunchKernelGGL((face_conforming_kernel<1, NV>), grid, block, 0, s, m, p, fl, cnt, u, alpha); break;
+      case 2: hipLaunchKernelGGL((face_conforming_kernel<2, NV>), grid, block, 0, s, m, p, fl, cnt, u, alpha); break;
+      case 3: hipLaunchKernelGGL((face_conforming_kernel<3, NV>), grid, block, 0, s, m, p, fl, cnt, u, alpha); break;
+      case 4: hipLaunchKernelGGL((face_conforming_kernel<4, NV>), grid, block, 0, s, m, p, fl, cnt, u, alpha); break;
+      case 5: hipLaunchKernelGGL((face_conforming_kernel<5, NV>), grid, block, 0, s, m, p, fl, cnt, u, alpha); break;
+      case 6: hipLaunchKernelGGL((face_conforming_kernel<6, NV>), grid, block, 0, s, m, p, fl, cnt, u, alpha); break;
+      default: hipLaunchKernelGGL((face_conforming_kernel<7, NV>), grid, block, 0, s, m, p, fl, cnt, u, alpha); break;
+    }
+    if (hipError_t e = hipGetLastError()) return e;
+  }
+  if (m.face_mixed_count > 0) {
+    const int grid = m.face_mixed_count < 65536 ? m.face_mixed_count : 65536;
+    hipLaunchKernelGGL((face_mixed_kernel<NV>), dim3(grid), dim3(FACE_THREADS), 0, s, m, p, m.face_mixed,
+                       m.face_mixed_count, u, alpha);
+    if (hipError_t e = hipGetLastError()) return e;
+  }
+  if (alpha) {
+    hipLaunchKernelGGL((face_fv_kernel<NV>), dim3(m.K), dim3(FACE_THREADS),
+                       0, s, m, p, u, alpha);
+    if (hipError_t e = hipGetLastError()) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_faces(const MeshView& m, const ParamsDev& p, const double* u, const double* alpha,
                         hipStream_t s) {
   if (m.n_face == 0) return hipSuccess;
-  if (m.nvar == 5)
-    hipLaunchKernelGGL((face_kernel<5>), dim3(m.n_face), dim3(FACE_THREADS), 0, s, m, p, u, alpha);
-  else
-    hipLaunchKernelGGL((face_kernel<6>), dim3(m.n_face), dim3(FACE_THREADS), 0, s, m, p, u, alpha);
-  return hipGetLastError();
+  return m.nvar == 5 ? launch_faces_t<5>(m, p, u, alpha, s) : launch_faces_t<6>(m, p, u, alpha, s);
 }
 
 }  // namespace dgfv

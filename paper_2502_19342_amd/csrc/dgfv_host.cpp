@@ -537,6 +537,26 @@ dgfv_status dgfv_mesh_create(const dgfv_mesh_desc* d, dgfv_mesh** out) {
     }
     for (int N = 1; N <= MAXN; ++N)
       if (!m->bucket[N].empty()) m->d_bucket[N] = m->keep(dev_upload(m->bucket[N]));
+    // face classes: conforming lists per degree, degree-jump list, element -> face map
+    {
+      std::array<std::vector<int32_t>, MAXN + 1> conf;
+      std::vector<int32_t> mixed, elem_face((size_t)m->K * 6, -1);
+      for (int f = 0; f < m->F; ++f) {
+        const int32_t* fc = d->faces + 5 * f;
+        const int NL = m->degree[fc[0]], NR = m->degree[fc[2]];
+        if (NL == NR) conf[NL].push_back(f);
+        else mixed.push_back(f);
+        elem_face[(size_t)fc[0] * 6 + fc[1]] = f;
+        elem_face[(size_t)fc[2] * 6 + fc[3]] = f;
+      }
+      for (int N = 0; N <= MAXN; ++N) {
+        v.face_conf[N] = conf[N].empty() ? nullptr : m->keep(dev_upload(conf[N]));
+        v.face_conf_count[N] = (int)conf[N].size();
+      }
+      v.face_mixed = mixed.empty() ? nullptr : m->keep(dev_upload(mixed));
+      v.face_mixed_count = (int)mixed.size();
+      v.elem_face = m->keep(dev_upload(elem_face));
+    }
     for (int N = 1; N <= MAXN; ++N)
       if (!m->bucket[N].empty())
         hip_check(ops_for(N).fv_normals(v, m->d_bucket[N], (int)m->bucket[N].size(), nullptr),

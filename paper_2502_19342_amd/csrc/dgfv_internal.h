@@ -56,6 +56,11 @@ struct MeshView {
   double* rfv;                  // FV residual in nodal form, [nvar][n_node]
   double* ubar_bar;             // adjoint of the sub-cell means, [K][nvar][NFV^3]
   double* fvnorm;               // sub-face normals of internal planes, [K][3][3][(NFV-1) NFV^2]
+  const int32_t* elem_face;     // [K][6] face of each element side
+  const int32_t* face_conf[MAXN + 1];   // faces with NL = NR = N
+  int face_conf_count[MAXN + 1];
+  const int32_t* face_mixed;    // faces with NL != NR
+  int face_mixed_count;
   const double* ops;            // operator tables
   OpTables tab;
   GasDev gas;
