@@ -2,7 +2,8 @@
 import numpy as np
 import torch
 
-from oracle import problem
+from oracle import ops1d, problem
+from oracle.physics import prim_to_cons
 from paper_2502_19342_amd import workloads as W
 
 T = torch.float64
@@ -51,3 +52,57 @@ def smooth_state(seed, n_var=5):
 def operator_scale(mesh, rhs_fn, u):
     """Magnitude of the individual terms of R: max |R| of the state with the flux scale of u."""
     return float(rhs_fn(u, torch.zeros(mesh.K, dtype=T)).abs().max())
+
+
+# ---------------------------------------------------------------------------
+# full-size inputs and sampled patches
+# ---------------------------------------------------------------------------
+
+def trilinear_nodes(corners: np.ndarray, N: int) -> np.ndarray:
+    """Physical coordinates [E, (N+1)^3, 3] of the LGL nodes (i fastest) of trilinear elements."""
+    x, _ = ops1d.lgl(N)
+    s = 0.5 * (1.0 + np.asarray(x, dtype=np.float64))
+    one = np.stack([1.0 - s, s], axis=1)                        # [n, 2]
+    wts = np.einsum("kz,jy,ix->kjizyx", one, one, one).reshape(-1, 8)   # corner z*4 + y*2 + x
+    return np.einsum("nc,ecd->end", wts, corners)
+
+
+def c5_state(wl, chunk=8192):
+    spec = wl.mesh
+    N = int(spec.degree[0])
+    gas = problem.gas_of(wl)
+    n3 = (N + 1) ** 3
+    u = torch.empty(wl.n_var, spec.n_elem * n3, dtype=T)
+    for a in range(0, spec.n_elem, chunk):
+        b = min(spec.n_elem, a + chunk)
+        X = trilinear_nodes(spec.corners[a:b], N).reshape(-1, 3)
+        w = torch.as_tensor(np.asarray(wl.prim(X))[: wl.n_var], dtype=T)
+        u[:, a * n3:b * n3] = prim_to_cons(w, gas)
+    return u
+
+
+def patch(spec, centres):
+    """Sub-mesh of the centres and their face neighbours; uncovered sides get self-faces."""
+    faces = np.asarray(spec.faces, dtype=np.int64)
+    touch = np.isin(faces[:, 0], centres) | np.isin(faces[:, 2], centres)
+    elems = np.unique(np.concatenate([centres, faces[touch, 0], faces[touch, 2]]))
+    local = {int(e): i for i, e in enumerate(elems)}
+    inside = np.isin(faces[:, 0], elems) & np.isin(faces[:, 2], elems)
+    sub = faces[inside].copy()
+    sub[:, 0] = [local[int(e)] for e in sub[:, 0]]
+    sub[:, 2] = [local[int(e)] for e in sub[:, 2]]
+    covered = np.zeros((len(elems), 6), dtype=bool)
+    covered[sub[:, 0], sub[:, 1]] = True
+    covered[sub[:, 2], sub[:, 3]] = True
+    for i in range(len(elems)):
+        for s in range(6):
+            if not covered[i, s]:
+                assert int(elems[i]) not in set(centres.tolist())
+                sub = np.vstack([sub, [i, s, i, s, 0]])
+    pspec = W.MeshSpec(n=spec.n, lo=spec.lo, hi=spec.hi, corners=spec.corners[elems],
+                       faces=sub.astype(np.int32), degree=spec.degree[elems])
+    return elems, local, pspec
+
+
+def node_index(offsets, elems):
+    return np.concatenate([np.arange(offsets[e], offsets[e + 1]) for e in elems])

@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 import torch
 
-from oracle import ops1d
+from oracle import ops1d, problem
 from oracle.physics import entropy_vars, euler_flux, riemann, to_prim
 from oracle.rhs import volume_term
 from paper_2502_19342_amd import workloads as W
@@ -223,3 +223,32 @@ def test_full_fv_equals_textbook_first_order_fv(N):
         Fp = riemann(W.RIEMANN_LLF, ub, uR, nvec.view(3, 1, 1, 1), gas)
         ref = ref - (Fp - torch.roll(Fp, 1, dims=dim)) / dx
     assert torch.allclose(rb, ref, rtol=0, atol=1e-12 * float(ref.abs().max()))
+
+
+@pytest.mark.parametrize("cfg,n", [("C5", 4), ("C3", 4)])
+def test_patch_evaluation_matches_whole_mesh(cfg, n):
+    # sampled elements with their face neighbours (the full-size GPU checks at 64^3 rely on it)
+    from oracle.geometry import OracleMesh
+    from oracle.rhs import Rhs
+    from oracle_cases import node_index, patch, trilinear_nodes
+    wl = W.make_workload(cfg, n=n)
+    mesh, gas, f = oracle_of(wl)
+    spec = wl.mesh
+    if cfg == "C5":
+        # the host-side node generator used for the 64^3 state agrees with the oracle's nodes
+        X = torch.as_tensor(trilinear_nodes(spec.corners, int(spec.degree[0])).reshape(-1, 3).T)
+        assert float((X - mesh.node_coords()).abs().max()) <= 1e-15
+    u = state(mesh, gas, wl.prim)
+    rng = np.random.default_rng(3)
+    alpha = torch.as_tensor(np.where(rng.random(mesh.K) < 0.3, rng.choice([0.5, 1.0], mesh.K), 0.0))
+    r_full = f(u, alpha)
+    centres = np.sort(rng.choice(mesh.K, size=5, replace=False))
+    elems, local, pspec = patch(spec, centres)
+    pm = OracleMesh(pspec, wl.n_fv, wl.metric_degree)
+    fp = Rhs(pm, gas, problem.params_of(wl))
+    off = spec.elem_offset()
+    rp = fp(u[:, torch.as_tensor(node_index(off, elems))], alpha[torch.as_tensor(elems)])
+    lidx = torch.as_tensor(node_index(pspec.elem_offset(), [local[int(e)] for e in centres]))
+    ref = r_full[:, torch.as_tensor(node_index(off, centres))]
+    err = ((rp[:, lidx] - ref).abs().amax(1) / ref.abs().amax(1)).max()
+    assert float(err) <= 1e-13
