@@ -144,6 +144,32 @@ dgfv_status dg_rk_stage(const dgfv_mesh* mesh, const dgfv_params* params, int st
                         double* u_d, double* k_d, const double* alpha_d, void* stream);
 
 /*
+ * One whole Runge-Kutta step: stages 1..5 of dg_rk_stage in order, with the
+ * same arguments and in-place updates (k need not be initialised).
+ */
+dgfv_status dg_rk_step(const dgfv_mesh* mesh, const dgfv_params* params, double dt, double* u_d,
+                       double* k_d, const double* alpha_d, void* stream);
+
+/*
+ * Launch batching (not part of the method).  Within each phase of an
+ * evaluation (sub-cell means, face fluxes, FV residuals, element kernels) the
+ * launches of the different degree buckets and face classes are independent.
+ *   DGFV_LAUNCH_SERIAL:   all launches in order on the caller's stream;
+ *   DGFV_LAUNCH_BRANCHES: (default) the launches of a phase fork from the
+ *                         caller's stream onto streams owned by the mesh and
+ *                         join back, so that small buckets run side by side;
+ *   DGFV_LAUNCH_GRAPH:    as BRANCHES, but dg_rk_step and dg_rk_stage capture
+ *                         their launches into a hipGraph once per argument set
+ *                         (params, stage, dt and the u, k, alpha pointers) and
+ *                         replay it on later calls.  Up to 16 graphs are cached
+ *                         per mesh (the oldest is dropped); leaving this mode
+ *                         frees them.  Graphs are not used while profiling is on.
+ * Capture and instantiation errors are reported as DGFV_ERR_HIP.
+ */
+enum { DGFV_LAUNCH_SERIAL = 0, DGFV_LAUNCH_BRANCHES = 1, DGFV_LAUNCH_GRAPH = 2 };
+dgfv_status dgfv_set_launch_mode(dgfv_mesh* mesh, int mode);
+
+/*
  * Vector-Jacobian product of the right-hand side with alpha frozen:
  *     g_b = (dR/du (u))^T w_b,  b = 0..batch-1,
  * w_d, g_d: [batch][n_var][n_node]; alpha_d as for dg_rhs.  Derivatives at

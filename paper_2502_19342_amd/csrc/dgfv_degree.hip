@@ -241,20 +241,18 @@ constexpr int FV2_THREADS = 512;
 
 template <int N, int NFV, int NV>
 __global__ void __launch_bounds__(FV2_THREADS)
-fv_means_kernel(MeshView m, const int32_t* __restrict__ elist, int count,
-                const double* __restrict__ u, const double* __restrict__ alpha) {
+fv_means_kernel(MeshView m, const double* __restrict__ u) {
   constexpr int NP = N + 1, NP3 = NP * NP * NP, S3 = NFV * NFV * NFV;
   constexpr int NF = NV + 1;                  // J*u (NV fields) and J
   __shared__ double bufA[NF * S3];
   __shared__ double bufB[NF * S3];
   __shared__ double sV[NFV * NP];
-  const int idx = blockIdx.x;
-  if (idx >= count) return;
-  const int e = elist[idx];
-  if (!(alpha[e] > 0.0)) return;
   const int t = threadIdx.x;
-  const int64_t base = m.elem_offset[e];
   if (t < NFV * NP) sV[t] = m.ops[m.tab.dg2fv[N] + t];
+  const int end = m.blend_start[N + 1];
+  for (int w = m.blend_start[N] + blockIdx.x; w < end; w += gridDim.x) {
+  const int e = m.blend_list[w];
+  const int64_t base = m.elem_offset[e];
   for (int r = t; r < NP3; r += FV2_THREADS) {
     const double J = m.metric[9 * m.n_node + base + r];
     for (int v = 0; v < NV; ++v) bufA[v * NP3 + r] = J * u[v * m.n_node + base + r];
@@ -296,28 +294,28 @@ fv_means_kernel(MeshView m, const int32_t* __restrict__ elist, int count,
     const double ivol = 1.0 / bufB[NV * S3 + r];
     for (int v = 0; v < NV; ++v) ub[v * S3 + r] = bufB[v * S3 + r] * ivol;
   }
+  __syncthreads();                            // bufB is reused by the next element
+  }
 }
 
 template <int N, int NFV, int NV>
 __global__ void __launch_bounds__(FV2_THREADS)
-fv_residual_kernel(MeshView m, ParamsDev prm, const int32_t* __restrict__ elist, int count,
-                   const double* __restrict__ alpha) {
+fv_residual_kernel(MeshView m, ParamsDev prm) {
   constexpr int NP = N + 1, NP3 = NP * NP * NP;
   constexpr int S2 = NFV * NFV, S3 = S2 * NFV, NIF = (NFV - 1) * S2;
   static_assert(S3 <= FV2_THREADS, "one thread per sub-cell");
   __shared__ double sU[NV * S3];
   __shared__ double sG[NV * S3];
   __shared__ double sVp[NP * NFV];
-  const int idx = blockIdx.x;
-  if (idx >= count) return;
-  const int e = elist[idx];
-  if (!(alpha[e] > 0.0)) return;
   const int t = threadIdx.x;
-  const int64_t base = m.elem_offset[e];
   const double h = 2.0 / NFV;
+  if (t < NP * NFV) sVp[t] = m.ops[m.tab.fv2dg[N] + t];
+  const int w = m.blend_start[N] + blockIdx.x;
+  if (w >= m.blend_start[N + 1]) return;
+  const int e = m.blend_list[w];
+  const int64_t base = m.elem_offset[e];
   const double* ub = m.ubar + (size_t)e * NV * S3;
   for (int r = t; r < NV * S3; r += FV2_THREADS) sU[r] = ub[r];
-  if (t < NP * NFV) sVp[t] = m.ops[m.tab.fv2dg[N] + t];
   const double* nrm = m.fvnorm + (size_t)e * 9 * NIF;
   const double* fvs = m.fvside + (size_t)e * 6 * NV * S2;
   const bool active = t < S3;
@@ -840,58 +838,74 @@ hipError_t element(const MeshView& m, const ParamsDev& p, const int32_t* elist, 
   return launch_elem_t<6, FluxCentral>(m, elist, count, u, alpha, ut, k, stage, dt, A, B, s);
 }
 
+// fv_means is persistent: as many workgroups as fit on the device at once (at
+// most `count`, the bucket size) walk this degree's range of the blended-element
+// list built for the call.  fv_residual runs one workgroup per list entry over
+// a grid of the bucket size, the workgroups past the range leaving at once:
+// its register footprint grows by half in the persistent loop form.
+template <auto KERNEL>
+int persistent_grid(int block, const MeshView& m, int count) {
+  static const int per_cu = resident_per_cu(reinterpret_cast<const void*>(KERNEL), block);
+  const int g = per_cu * m.n_cu;
+  return count < g ? count : g;
+}
+
 template <int NFV>
-hipError_t fv_means_t(const MeshView& m, const int32_t* elist, int count, const double* u,
-                      const double* alpha, hipStream_t s) {
+hipError_t fv_means_t(const MeshView& m, int count, const double* u, hipStream_t s) {
   if constexpr (NFV >= kN + 1) {
     if (m.nvar == 5)
-      hipLaunchKernelGGL((fv_means_kernel<kN, NFV, 5>), dim3(count), dim3(FV2_THREADS), 0, s, m, elist, count, u, alpha);
+      hipLaunchKernelGGL((fv_means_kernel<kN, NFV, 5>),
+                         dim3(persistent_grid<fv_means_kernel<kN, NFV, 5>>(FV2_THREADS, m, count)),
+                         dim3(FV2_THREADS), 0, s, m, u);
     else
-      hipLaunchKernelGGL((fv_means_kernel<kN, NFV, 6>), dim3(count), dim3(FV2_THREADS), 0, s, m, elist, count, u, alpha);
+      hipLaunchKernelGGL((fv_means_kernel<kN, NFV, 6>),
+                         dim3(persistent_grid<fv_means_kernel<kN, NFV, 6>>(FV2_THREADS, m, count)),
+                         dim3(FV2_THREADS), 0, s, m, u);
     return hipGetLastError();
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t fv_means(const MeshView& m, const int32_t* elist, int count, const double* u,
-                    const double* alpha, hipStream_t s) {
+hipError_t fv_means(const MeshView& m, int count, const double* u, hipStream_t s) {
   if (count == 0) return hipSuccess;
   switch (m.n_fv) {
-    case 2: return fv_means_t<2>(m, elist, count, u, alpha, s);
-    case 3: return fv_means_t<3>(m, elist, count, u, alpha, s);
-    case 4: return fv_means_t<4>(m, elist, count, u, alpha, s);
-    case 5: return fv_means_t<5>(m, elist, count, u, alpha, s);
-    case 6: return fv_means_t<6>(m, elist, count, u, alpha, s);
-    case 7: return fv_means_t<7>(m, elist, count, u, alpha, s);
-    case 8: return fv_means_t<8>(m, elist, count, u, alpha, s);
+    case 2: return fv_means_t<2>(m, count, u, s);
+    case 3: return fv_means_t<3>(m, count, u, s);
+    case 4: return fv_means_t<4>(m, count, u, s);
+    case 5: return fv_means_t<5>(m, count, u, s);
+    case 6: return fv_means_t<6>(m, count, u, s);
+    case 7: return fv_means_t<7>(m, count, u, s);
+    case 8: return fv_means_t<8>(m, count, u, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <int NFV>
-hipError_t fv_residual_t(const MeshView& m, const ParamsDev& p, const int32_t* elist, int count,
-                         const double* alpha, hipStream_t s) {
+hipError_t fv_residual_t(const MeshView& m, const ParamsDev& p, int count, hipStream_t s) {
   if constexpr (NFV >= kN + 1) {
     if (m.nvar == 5)
-      hipLaunchKernelGGL((fv_residual_kernel<kN, NFV, 5>), dim3(count), dim3(FV2_THREADS), 0, s, m, p, elist, count, alpha);
+      hipLaunchKernelGGL((fv_residual_kernel<kN, NFV, 5>),
+                         dim3(count),
+                         dim3(FV2_THREADS), 0, s, m, p);
     else
-      hipLaunchKernelGGL((fv_residual_kernel<kN, NFV, 6>), dim3(count), dim3(FV2_THREADS), 0, s, m, p, elist, count, alpha);
+      hipLaunchKernelGGL((fv_residual_kernel<kN, NFV, 6>),
+                         dim3(count),
+                         dim3(FV2_THREADS), 0, s, m, p);
     return hipGetLastError();
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t fv_residual(const MeshView& m, const ParamsDev& p, const int32_t* elist, int count,
-                       const double* alpha, hipStream_t s) {
+hipError_t fv_residual(const MeshView& m, const ParamsDev& p, int count, hipStream_t s) {
   if (count == 0) return hipSuccess;
   switch (m.n_fv) {
-    case 2: return fv_residual_t<2>(m, p, elist, count, alpha, s);
-    case 3: return fv_residual_t<3>(m, p, elist, count, alpha, s);
-    case 4: return fv_residual_t<4>(m, p, elist, count, alpha, s);
-    case 5: return fv_residual_t<5>(m, p, elist, count, alpha, s);
-    case 6: return fv_residual_t<6>(m, p, elist, count, alpha, s);
-    case 7: return fv_residual_t<7>(m, p, elist, count, alpha, s);
-    case 8: return fv_residual_t<8>(m, p, elist, count, alpha, s);
+    case 2: return fv_residual_t<2>(m, p, count, s);
+    case 3: return fv_residual_t<3>(m, p, count, s);
+    case 4: return fv_residual_t<4>(m, p, count, s);
+    case 5: return fv_residual_t<5>(m, p, count, s);
+    case 6: return fv_residual_t<6>(m, p, count, s);
+    case 7: return fv_residual_t<7>(m, p, count, s);
+    case 8: return fv_residual_t<8>(m, p, count, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -13,7 +13,7 @@
 //    a blended side receives it directly and every DG part V^{FV->DG} of it / h^2.
 // The first class runs one lane per face node over static per-degree face
 // lists; the second runs one face per 64-lane workgroup over a static list;
-// FV faces are found per call from alpha, one blended element per workgroup.
+// FV faces come from the blended-element list of the call.
 // Results go to per-element side buffers: the right side gets the negated flux
 // re-indexed through the face orientation.
 #include "dgfv_internal.h"
@@ -323,17 +323,17 @@ face_mixed_kernel(MeshView m, ParamsDev prm, const int32_t* __restrict__ flist, 
   }
 }
 
-// FV faces: one workgroup per element; a pure DG element leaves at once, a
-// blended one processes the faces it owns (the left element owns a face when
-// it is blended, otherwise the right one).  Blended elements cluster along
-// flow features, so one element per workgroup lets the dispatcher balance the
-// load.
+// FV faces: one workgroup per entry of the blended-element list of the call
+// (a grid of K, the workgroups past the list leaving at once); each blended
+// element processes the faces it owns (the left element owns a
+// face when it is blended, otherwise the right one).
+
 template <int NV>
 __global__ void __launch_bounds__(FACE_THREADS)
 face_fv_kernel(MeshView m, ParamsDev prm, const double* __restrict__ u, const double* __restrict__ alpha) {
   __shared__ double B0[NV * GRID], B1[NV * GRID], B2[NV * GRID], B3[NV * GRID], sN[3 * GRID], sNF[3 * GRID];
-  const int e = blockIdx.x;
-  if (e >= m.K || !(alpha[e] > 0.0)) return;
+  if ((int)blockIdx.x >= m.blend_start[MAXN + 1]) return;
+  const int e = m.blend_list[blockIdx.x];
   for (int side = 0; side < 6; ++side) {
     const int f = m.elem_face[6 * e + side];
     const int32_t* fc = m.faces + 5 * f;
@@ -525,11 +525,11 @@ hipError_t launch_faces_vjp(const MeshView& m, const ParamsDev& p, const double*
 }
 
 template <int NV>
-static hipError_t launch_faces_t(const MeshView& m, const ParamsDev& p, const double* u,
-                                 const double* alpha, hipStream_t s) {
-  for (int N = 1; N <= MAXN; ++N) {
-    const int cnt = m.face_conf_count[N];
-    if (cnt == 0) continue;
+static hipError_t launch_face_class_t(const MeshView& m, const ParamsDev& p, const double* u,
+                                      const double* alpha, int cls, hipStream_t s) {
+  if (cls >= 1 && cls <= MAXN) {
+    const int N = cls, cnt = m.face_conf_count[N];
+    if (cnt == 0) return hipSuccess;
     const int np2 = (N + 1) * (N + 1), fpb = CONF_THREADS / np2;
     const dim3 grid((cnt + fpb - 1) / fpb), block(CONF_THREADS);
     const int32_t* fl = m.face_conf[N];
@@ -542,26 +542,35 @@ static hipError_t launch_faces_t(const MeshView& m, const ParamsDev& p, const do
       case 6: hipLaunchKernelGGL((face_conforming_kernel<6, NV>), grid, block, 0, s, m, p, fl, cnt, u, alpha); break;
       default: hipLaunchKernelGGL((face_conforming_kernel<7, NV>), grid, block, 0, s, m, p, fl, cnt, u, alpha); break;
     }
-    if (hipError_t e = hipGetLastError()) return e;
+    return hipGetLastError();
   }
-  if (m.face_mixed_count > 0) {
+  if (cls == FACE_CLASS_MIXED) {
+    if (m.face_mixed_count == 0) return hipSuccess;
     const int grid = m.face_mixed_count < 65536 ? m.face_mixed_count : 65536;
     hipLaunchKernelGGL((face_mixed_kernel<NV>), dim3(grid), dim3(FACE_THREADS), 0, s, m, p, m.face_mixed,
                        m.face_mixed_count, u, alpha);
-    if (hipError_t e = hipGetLastError()) return e;
+    return hipGetLastError();
   }
-  if (alpha) {
-    hipLaunchKernelGGL((face_fv_kernel<NV>), dim3(m.K), dim3(FACE_THREADS),
-                       0, s, m, p, u, alpha);
-    if (hipError_t e = hipGetLastError()) return e;
+  if (cls == FACE_CLASS_FV) {
+    if (!alpha) return hipSuccess;
+    hipLaunchKernelGGL((face_fv_kernel<NV>), dim3(m.K), dim3(FACE_THREADS), 0, s, m, p, u, alpha);
+    return hipGetLastError();
   }
-  return hipSuccess;
+  return hipErrorInvalidValue;
 }
 
-hipError_t launch_faces(const MeshView& m, const ParamsDev& p, const double* u, const double* alpha,
-                        hipStream_t s) {
+bool face_class_present(const MeshView& m, const double* alpha, int cls) {
+  if (cls >= 1 && cls <= MAXN) return m.face_conf_count[cls] > 0;
+  if (cls == FACE_CLASS_MIXED) return m.face_mixed_count > 0;
+  if (cls == FACE_CLASS_FV) return alpha != nullptr && m.n_face > 0;
+  return false;
+}
+
+hipError_t launch_face_class(const MeshView& m, const ParamsDev& p, const double* u, const double* alpha,
+                             int cls, hipStream_t s) {
   if (m.n_face == 0) return hipSuccess;
-  return m.nvar == 5 ? launch_faces_t<5>(m, p, u, alpha, s) : launch_faces_t<6>(m, p, u, alpha, s);
+  return m.nvar == 5 ? launch_face_class_t<5>(m, p, u, alpha, cls, s)
+                     : launch_face_class_t<6>(m, p, u, alpha, cls, s);
 }
 
 }  // namespace dgfv

@@ -101,12 +101,45 @@ struct dgfv_mesh {
   std::vector<void*> allocations;
   MeshView view{};
 
+  // concurrent branches: per-degree launches of one phase fork from the
+  // caller's stream onto side streams and join back (graph branches when captured)
+  std::array<hipStream_t, FACE_CLASS_COUNT> side{};
+  hipEvent_t fork_ev = nullptr;
+  std::array<hipEvent_t, FACE_CLASS_COUNT> join_ev{};
+
+  // hipGraph cache of dg_rk_step / dg_rk_stage, keyed on the full argument set
+  struct GraphKey {
+    int kind, stage;
+    const void *u, *k, *alpha;
+    double dt;
+    dgfv_params prm;
+    bool operator==(const GraphKey& o) const {
+      return kind == o.kind && stage == o.stage && u == o.u && k == o.k && alpha == o.alpha &&
+             std::memcmp(&dt, &o.dt, sizeof dt) == 0 && std::memcmp(&prm, &o.prm, sizeof prm) == 0;
+    }
+  };
+  static constexpr size_t GRAPH_CACHE = 16;
+  int launch_mode = DGFV_LAUNCH_BRANCHES;
+  hipStream_t cap_stream = nullptr;
+  mutable std::vector<std::pair<GraphKey, hipGraphExec_t>> graph_cache;
+
   // kernel timing (mutable: recording does not change the mesh)
   mutable bool profile = false;
   mutable std::array<std::vector<std::pair<hipEvent_t, hipEvent_t>>, DGFV_KERNEL_COUNT> ev;
   mutable std::array<size_t, DGFV_KERNEL_COUNT> ev_used{};
 
+  void drop_graphs() const {
+    for (auto& pr : graph_cache) (void)hipGraphExecDestroy(pr.second);
+    graph_cache.clear();
+  }
   ~dgfv_mesh() {
+    drop_graphs();
+    for (hipStream_t st : side)
+      if (st) (void)hipStreamDestroy(st);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (fork_ev) (void)hipEventDestroy(fork_ev);
+    for (hipEvent_t e : join_ev)
+      if (e) (void)hipEventDestroy(e);
     for (auto& list : ev)
       for (auto& pr : list) {
         (void)hipEventDestroy(pr.first);
@@ -291,41 +324,135 @@ ParamsDev to_dev(const dgfv_params* p) {
   return d;
 }
 
+// Runs launch(item, stream) for every item in `items`; with more than one, as
+// parallel branches on the mesh's side streams that fork from and join back
+// into s (parallel graph branches when s is being captured).
+template <class F>
+void fork_join(const dgfv_mesh* m, hipStream_t s, const std::vector<int>& items, F&& launch) {
+  if (items.size() <= 1 || m->launch_mode == DGFV_LAUNCH_SERIAL) {
+    for (int it : items) launch(it, s);
+    return;
+  }
+  hip_check(hipEventRecord(m->fork_ev, s), "hipEventRecord");
+  for (size_t b = 0; b < items.size(); ++b) {
+    hipStream_t ss = m->side[b];
+    hip_check(hipStreamWaitEvent(ss, m->fork_ev, 0), "hipStreamWaitEvent");
+    launch(items[b], ss);
+    hip_check(hipEventRecord(m->join_ev[b], ss), "hipEventRecord");
+  }
+  for (size_t b = 0; b < items.size(); ++b)
+    hip_check(hipStreamWaitEvent(s, m->join_ev[b], 0), "hipStreamWaitEvent");
+}
+
+std::vector<int> degrees_present(const dgfv_mesh* m) {
+  std::vector<int> d;
+  for (int N = 1; N <= MAXN; ++N)
+    if (!m->bucket[N].empty()) d.push_back(N);
+  return d;
+}
+
 // Enqueue one evaluation: stage 0 -> ut = R(u); stage 1..5 -> RK stage on (u, k).
-dgfv_status enqueue_rhs(const dgfv_mesh* m, const dgfv_params* prm, const double* u,
-                        const double* alpha, double* ut, double* k, int stage, double dt,
-                        hipStream_t s) {
-  const ParamsDev p = to_dev(prm);
+// Phases: blended list + sub-cell means, face fluxes, FV residuals, element
+// kernels (volume, lift, blend, RK update); the per-degree (per face class)
+// launches of a phase are independent branches.
+void enqueue_rhs_impl(const dgfv_mesh* m, const ParamsDev& p, const double* u, const double* alpha,
+                      double* ut, double* k, int stage, double dt, hipStream_t s) {
   const MeshView& v = m->view;
   const double A = stage > 0 ? RK_A[stage - 1] : 0.0;
   const double B = stage > 0 ? RK_B[stage - 1] : 0.0;
+  const std::vector<int> degs = degrees_present(m);
+  if (alpha) {
+    Timed t(m, DGFV_KERNEL_FV_MEANS, s);
+    hip_check(launch_blend_list(v, alpha, s), "blended list launch");
+    fork_join(m, s, degs, [&](int N, hipStream_t ss) {
+      hip_check(ops_for(N).fv_means(v, (int)m->bucket[N].size(), u, ss), "fv_means launch");
+    });
+  }
+  {
+    Timed t(m, DGFV_KERNEL_FACE, s);
+    std::vector<int> classes;
+    for (int c = 1; c < FACE_CLASS_COUNT; ++c)
+      if (face_class_present(v, alpha, c)) classes.push_back(c);
+    fork_join(m, s, classes, [&](int c, hipStream_t ss) {
+      hip_check(launch_face_class(v, p, u, alpha, c, ss), "face launch");
+    });
+  }
+  if (alpha) {
+    Timed t(m, DGFV_KERNEL_FV_RESIDUAL, s);
+    fork_join(m, s, degs, [&](int N, hipStream_t ss) {
+      hip_check(ops_for(N).fv_residual(v, p, (int)m->bucket[N].size(), ss), "fv_residual launch");
+    });
+  }
+  {
+    Timed t(m, DGFV_KERNEL_ELEMENT, s);
+    fork_join(m, s, degs, [&](int N, hipStream_t ss) {
+      hip_check(ops_for(N).element(v, p, m->d_bucket[N], (int)m->bucket[N].size(), u, alpha, ut, k, stage,
+                                   dt, A, B, ss),
+                "element launch");
+    });
+  }
+}
+
+dgfv_status enqueue_rhs(const dgfv_mesh* m, const dgfv_params* prm, const double* u,
+                        const double* alpha, double* ut, double* k, int stage, double dt,
+                        hipStream_t s) {
   try {
-    if (alpha) {
-      Timed t(m, DGFV_KERNEL_FV_MEANS, s);
-      for (int N = 1; N <= MAXN; ++N)
-        if (!m->bucket[N].empty())
-          hip_check(ops_for(N).fv_means(v, m->d_bucket[N], (int)m->bucket[N].size(), u, alpha, s),
-                    "fv_means launch");
+    enqueue_rhs_impl(m, to_dev(prm), u, alpha, ut, k, stage, dt, s);
+  } catch (const HipError& e) {
+    return fail(DGFV_ERR_HIP, e.what());
+  }
+  return DGFV_OK;
+}
+
+// Stages first..last of an RK step, replayed from a cached hipGraph when the
+// mesh has graphs on (and profiling off), else enqueued directly.
+dgfv_status run_stages(const dgfv_mesh* m, const dgfv_params* prm, int kind, int first, int last, double dt,
+                       double* u, double* k, const double* alpha, hipStream_t s) {
+  try {
+    if (m->launch_mode != DGFV_LAUNCH_GRAPH || m->profile) {
+      const ParamsDev p = to_dev(prm);
+      for (int st = first; st <= last; ++st) enqueue_rhs_impl(m, p, u, alpha, nullptr, k, st, dt, s);
+      return DGFV_OK;
     }
-    {
-      Timed t(m, DGFV_KERNEL_FACE, s);
-      hip_check(launch_faces(v, p, u, alpha, s), "face launch");
+    dgfv_mesh::GraphKey key;
+    std::memset(&key, 0, sizeof key);             // padding too: the key is compared bytewise in part
+    key.kind = kind;
+    key.stage = first;
+    key.u = u;
+    key.k = k;
+    key.alpha = alpha;
+    key.dt = dt;
+    key.prm.volume_flux = prm->volume_flux;
+    key.prm.face_flux_dg = prm->face_flux_dg;
+    key.prm.face_flux_fv = prm->face_flux_fv;
+    key.prm.ind_vars = prm->ind_vars;
+    key.prm.ind_T = prm->ind_T;
+    key.prm.ind_dT = prm->ind_dT;
+    hipGraphExec_t exec = nullptr;
+    for (auto& pr : m->graph_cache)
+      if (pr.first == key) exec = pr.second;
+    if (!exec) {
+      const ParamsDev p = to_dev(prm);
+      hipGraph_t graph = nullptr;
+      hip_check(hipStreamBeginCapture(m->cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+      try {
+        for (int st = first; st <= last; ++st) enqueue_rhs_impl(m, p, u, alpha, nullptr, k, st, dt, m->cap_stream);
+      } catch (...) {
+        (void)hipStreamEndCapture(m->cap_stream, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        throw;
+      }
+      hip_check(hipStreamEndCapture(m->cap_stream, &graph), "hipStreamEndCapture");
+      const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      hip_check(ie, "hipGraphInstantiate");
+      if (m->graph_cache.size() >= dgfv_mesh::GRAPH_CACHE) {
+        (void)hipGraphExecDestroy(m->graph_cache.front().second);
+        m->graph_cache.erase(m->graph_cache.begin());
+      }
+      m->graph_cache.emplace_back(key, exec);
     }
-    if (alpha) {
-      Timed t(m, DGFV_KERNEL_FV_RESIDUAL, s);
-      for (int N = 1; N <= MAXN; ++N)
-        if (!m->bucket[N].empty())
-          hip_check(ops_for(N).fv_residual(v, p, m->d_bucket[N], (int)m->bucket[N].size(), alpha, s),
-                    "fv_residual launch");
-    }
-    {
-      Timed t(m, DGFV_KERNEL_ELEMENT, s);
-      for (int N = 1; N <= MAXN; ++N)
-        if (!m->bucket[N].empty())
-          hip_check(ops_for(N).element(v, p, m->d_bucket[N], (int)m->bucket[N].size(), u, alpha, ut, k,
-                                       stage, dt, A, B, s),
-                    "element launch");
-    }
+    hip_check(hipGraphLaunch(exec, s), "hipGraphLaunch");
   } catch (const HipError& e) {
     return fail(DGFV_ERR_HIP, e.what());
   }
@@ -557,6 +684,31 @@ dgfv_status dgfv_mesh_create(const dgfv_mesh_desc* d, dgfv_mesh** out) {
       v.face_mixed_count = (int)mixed.size();
       v.elem_face = m->keep(dev_upload(elem_face));
     }
+    // blended-element work list: buckets concatenated in ascending degree
+    {
+      std::vector<int32_t> order;
+      order.reserve(m->K);
+      for (int N = 0; N <= MAXN + 1; ++N) v.bucket_pos[N] = 0;
+      for (int N = 1; N <= MAXN; ++N) {
+        v.bucket_pos[N] = (int)order.size();
+        order.insert(order.end(), m->bucket[N].begin(), m->bucket[N].end());
+      }
+      v.bucket_pos[MAXN + 1] = (int)order.size();
+      v.order = m->keep(dev_upload(order));
+      v.n_chunk = (m->K + LIST_CHUNK - 1) / LIST_CHUNK;
+      v.chunk_cnt = m->keep(dev_alloc<int32_t>(v.n_chunk));
+      v.chunk_off = m->keep(dev_alloc<int32_t>(v.n_chunk));
+      v.blend_list = m->keep(dev_alloc<int32_t>(m->K));
+      v.blend_start = m->keep(dev_alloc<int32_t>(MAXN + 2));
+      int dev = 0, cus = 0;
+      hip_check(hipGetDevice(&dev), "hipGetDevice");
+      hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
+      v.n_cu = cus > 0 ? cus : 1;
+    }
+    for (auto& st : m->side) hip_check(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "hipStreamCreate");
+    hip_check(hipStreamCreateWithFlags(&m->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
+    hip_check(hipEventCreateWithFlags(&m->fork_ev, hipEventDisableTiming), "hipEventCreate");
+    for (auto& e : m->join_ev) hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
     for (int N = 1; N <= MAXN; ++N)
       if (!m->bucket[N].empty())
         hip_check(ops_for(N).fv_normals(v, m->d_bucket[N], (int)m->bucket[N].size(), nullptr),
@@ -622,7 +774,25 @@ dgfv_status dg_rk_stage(const dgfv_mesh* m, const dgfv_params* prm, int stage, d
   if (!std::isfinite(dt)) return fail(DGFV_ERR_ARG, "dt must be finite");
   if (u == k) return fail(DGFV_ERR_ARG, "u and k must not overlap");
   if (dgfv_status st = check_params(m, prm)) return st;
-  return enqueue_rhs(m, prm, u, alpha, nullptr, k, stage, dt, (hipStream_t)stream);
+  return run_stages(m, prm, 0, stage, stage, dt, u, k, alpha, (hipStream_t)stream);
+}
+
+dgfv_status dg_rk_step(const dgfv_mesh* m, const dgfv_params* prm, double dt, double* u, double* k,
+                       const double* alpha, void* stream) {
+  if (!m || !u || !k) return fail(DGFV_ERR_ARG, "NULL argument");
+  if (!std::isfinite(dt)) return fail(DGFV_ERR_ARG, "dt must be finite");
+  if (u == k) return fail(DGFV_ERR_ARG, "u and k must not overlap");
+  if (dgfv_status st = check_params(m, prm)) return st;
+  return run_stages(m, prm, 1, 1, 5, dt, u, k, alpha, (hipStream_t)stream);
+}
+
+dgfv_status dgfv_set_launch_mode(dgfv_mesh* m, int mode) {
+  if (!m) return fail(DGFV_ERR_ARG, "mesh is NULL");
+  if (mode != DGFV_LAUNCH_SERIAL && mode != DGFV_LAUNCH_BRANCHES && mode != DGFV_LAUNCH_GRAPH)
+    return fail(DGFV_ERR_ARG, "unknown launch mode");
+  m->launch_mode = mode;
+  if (mode != DGFV_LAUNCH_GRAPH) m->drop_graphs();
+  return DGFV_OK;
 }
 
 dgfv_status dgfv_profile_enable(dgfv_mesh* m, int enable) {
@@ -674,10 +844,10 @@ dgfv_status dg_rhs_vjp(const dgfv_mesh* m, const dgfv_params* prm, const double*
   try {
     Timed t(m, DGFV_KERNEL_VJP, s);
     if (alpha) {
+      hip_check(launch_blend_list(v, alpha, s), "blended list launch");
       for (int N = 1; N <= MAXN; ++N)
         if (!m->bucket[N].empty())
-          hip_check(ops_for(N).fv_means(v, m->d_bucket[N], (int)m->bucket[N].size(), u, alpha, s),
-                    "fv_means launch");
+          hip_check(ops_for(N).fv_means(v, (int)m->bucket[N].size(), u, s), "fv_means launch");
     }
     for (int b = 0; b < batch; ++b) {
       const double* wb = w + b * plane;

@@ -61,6 +61,15 @@ struct MeshView {
   int face_conf_count[MAXN + 1];
   const int32_t* face_mixed;    // faces with NL != NR
   int face_mixed_count;
+  // blended-element work list, rebuilt from alpha by every call that has alpha
+  const int32_t* order;         // [K] all elements, degree buckets in ascending degree
+  int bucket_pos[MAXN + 2];     // start of degree N's bucket in `order`; [MAXN + 1] = K
+  int n_chunk;                  // ceil(K / LIST_CHUNK)
+  int32_t* chunk_cnt;           // [n_chunk] blended elements per chunk of `order`
+  int32_t* chunk_off;           // [n_chunk] exclusive prefix sum of chunk_cnt
+  int32_t* blend_list;          // [K] blended elements, in `order` order
+  int32_t* blend_start;         // [MAXN + 2] blend_list range of degree N: [start[N], start[N + 1])
+  int n_cu;                     // compute units of the device (persistent grid sizes)
   const double* ops;            // operator tables
   OpTables tab;
   GasDev gas;
@@ -74,10 +83,10 @@ struct DegreeOps {
   hipError_t (*element)(const MeshView& m, const ParamsDev& p, const int32_t* elist, int count,
                         const double* u, const double* alpha, double* ut, double* k, int stage,
                         double dt, double A, double B, hipStream_t s);
-  hipError_t (*fv_means)(const MeshView& m, const int32_t* elist, int count, const double* u,
-                         const double* alpha, hipStream_t s);
-  hipError_t (*fv_residual)(const MeshView& m, const ParamsDev& p, const int32_t* elist, int count,
-                            const double* alpha, hipStream_t s);
+  // FV kernels walk this degree's range of the blended-element list (m.blend_list,
+  // m.blend_start) with `count` persistent workgroups; `count` bounds the range size
+  hipError_t (*fv_means)(const MeshView& m, int count, const double* u, hipStream_t s);
+  hipError_t (*fv_residual)(const MeshView& m, const ParamsDev& p, int count, hipStream_t s);
   hipError_t (*indicator)(const MeshView& m, const ParamsDev& p, const int32_t* elist, int count,
                           const double* u, double* alpha, double* ind, hipStream_t s);
   // adjoint: g = (dR/du)^T w, alpha frozen (see dg_rhs_vjp)
@@ -99,11 +108,29 @@ DegreeOps degree_ops_5();
 DegreeOps degree_ops_6();
 DegreeOps degree_ops_7();
 
-// All faces: Riemann fluxes into the per-side buffers (DG, mixed-degree and FV faces).
-hipError_t launch_faces(const MeshView& m, const ParamsDev& p, const double* u, const double* alpha,
-                        hipStream_t s);
-// Adjoint of the face fluxes: side-flux cotangents in fside / fvside are replaced
-// in place by the cotangents of the traces they were computed from.
+// Workgroups of `kernel` (block size `block`) resident on one compute unit at
+// once; a persistent launch uses this times the compute units, so that every
+// workgroup starts at once and the static round-robin split stays balanced.
+inline int resident_per_cu(const void* kernel, int block) {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, block, 0) != hipSuccess || n < 1) n = 1;
+  return n;
+}
+
+// Blended-element work list of one call: m.blend_list and m.blend_start from alpha.
+constexpr int LIST_CHUNK = 1024;
+hipError_t launch_blend_list(const MeshView& m, const double* alpha, hipStream_t s);
+
+// Interface fluxes into the per-side buffers, one launch per face class:
+// 1..MAXN conforming DG faces of that degree, FACE_CLASS_MIXED degree jumps
+// between DG elements, FACE_CLASS_FV faces with a blended side (needs the
+// blended-element list of the call).  The classes write disjoint sides and
+// may run concurrently.
+constexpr int FACE_CLASS_MIXED = MAXN + 1, FACE_CLASS_FV = MAXN + 2, FACE_CLASS_COUNT = MAXN + 3;
+bool face_class_present(const MeshView& m, const double* alpha, int cls);
+hipError_t launch_face_class(const MeshView& m, const ParamsDev& p, const double* u, const double* alpha,
+                             int cls, hipStream_t s);
+
 hipError_t launch_faces_vjp(const MeshView& m, const ParamsDev& p, const double* u, const double* alpha,
                             hipStream_t s);
 

@@ -41,9 +41,10 @@ class _Params(ctypes.Structure):
 
 
 EXPORTED = ("dgfv_mesh_create", "dgfv_mesh_destroy", "dgfv_mesh_info", "dgfv_mesh_node_coords",
-            "dg_indicator", "dg_rhs", "dg_rk_stage", "dg_rhs_vjp", "dgfv_profile_enable",
-            "dgfv_profile_read", "dgfv_last_error")
+            "dg_indicator", "dg_rhs", "dg_rk_stage", "dg_rk_step", "dg_rhs_vjp", "dgfv_set_launch_mode",
+            "dgfv_profile_enable", "dgfv_profile_read", "dgfv_last_error")
 KERNEL_ELEMENT, KERNEL_FACE, KERNEL_FV_MEANS, KERNEL_FV_RESIDUAL, KERNEL_INDICATOR, KERNEL_VJP = range(6)
+LAUNCH_SERIAL, LAUNCH_BRANCHES, LAUNCH_GRAPH = range(3)
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -59,7 +60,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dg_indicator.argtypes = [P, ctypes.POINTER(_Params), P, P, P, P]
     lib.dg_rhs.argtypes = [P, ctypes.POINTER(_Params), P, P, P, P]
     lib.dg_rk_stage.argtypes = [P, ctypes.POINTER(_Params), c_int, c_double, P, P, P, P]
+    lib.dg_rk_step.argtypes = [P, ctypes.POINTER(_Params), c_double, P, P, P, P]
     lib.dg_rhs_vjp.argtypes = [P, ctypes.POINTER(_Params), P, P, P, P, c_int, P]
+    lib.dgfv_set_launch_mode.argtypes = [P, c_int]
     lib.dgfv_profile_enable.argtypes = [P, c_int]
     lib.dgfv_profile_read.argtypes = [P, c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.dgfv_last_error.restype = ctypes.c_char_p
@@ -135,6 +138,14 @@ class Mesh:
             _lib.dgfv_mesh_destroy(h)
             self._h = None
 
+    def launch_mode(self, mode: int) -> None:
+        """LAUNCH_SERIAL, LAUNCH_BRANCHES (default) or LAUNCH_GRAPH (``dgfv_set_launch_mode``)."""
+        _check(_lib.dgfv_set_launch_mode(self._h, int(mode)))
+
+    def graphs(self, enable: bool = True) -> None:
+        """Capture and replay RK steps and stages as hipGraphs, or go back to branch launches."""
+        self.launch_mode(LAUNCH_GRAPH if enable else LAUNCH_BRANCHES)
+
     def profile(self, enable: bool = True) -> None:
         """Start (clearing the counters) or stop event timing of every kernel launch."""
         _check(_lib.dgfv_profile_enable(self._h, int(enable)))
@@ -192,8 +203,9 @@ def rk_stage(mesh: Mesh, params: Params, stage: int, dt: float, u: torch.Tensor,
 
 def rk_step(mesh: Mesh, params: Params, dt: float, u: torch.Tensor, k: torch.Tensor,
             alpha: torch.Tensor | None = None, stream=None) -> None:
-    for s in range(1, 6):
-        rk_stage(mesh, params, s, dt, u, k, alpha, stream)
+    """In-place five-stage 2N Runge-Kutta step (``dg_rk_step``)."""
+    _check(_lib.dg_rk_step(mesh._h, ctypes.byref(params.c()), float(dt), mesh._state(u, "u"),
+                           mesh._state(k, "k"), mesh._alpha(alpha), _stream(stream)))
 
 
 def indicator(mesh: Mesh, params: Params, u: torch.Tensor, stream=None):
