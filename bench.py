@@ -147,6 +147,7 @@ def main():
     else:
         alpha, _ = dgfv.indicator(gm, prm, u)
         mask = alpha.cpu().numpy() > 0
+    tune = gm.autotune(prm, u, alpha)            # element-kernel tile shape per degree
     npe = (wl.mesh.degree.astype(np.int64) + 1) ** 3
     blended_dofs = int(npe[mask].sum())
     dt = 1e-5
@@ -210,6 +211,7 @@ def main():
             "n_elem": wl.mesh.n_elem, "n_dof": n_dof, "n_var": wl.n_var,
             "volume_flux": ["ranocha", "pirozzoli", "central"][wl.volume_flux],
             "launch": args.launch,
+            "autotune_ms": {str(N): [round(a, 4), round(b, 4)] for N, (a, b) in tune.items()},
             "blended_fraction": float(mask.mean()),
         },
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",

@@ -170,6 +170,24 @@ enum { DGFV_LAUNCH_SERIAL = 0, DGFV_LAUNCH_BRANCHES = 1, DGFV_LAUNCH_GRAPH = 2 }
 dgfv_status dgfv_set_launch_mode(dgfv_mesh* mesh, int mode);
 
 /*
+ * Autotuning (not part of the method).  The element kernel has two tile
+ * shapes at degrees N <= 5: about 512 or about 256 lanes per workgroup (the
+ * number of elements per workgroup).  dgfv_autotune evaluates the RHS once on
+ * (u_d, alpha_d), then times each shape of every degree bucket over 5 launches
+ * after one warm-up (HIP events on `stream`) and keeps the faster shape per
+ * degree for all later calls on the mesh; cached graphs are dropped.
+ * Synchronous; allocates and frees one state-sized scratch buffer.
+ * ms_out (nullable): host array [8][2], the average launch time (ms) per
+ * degree and shape, 0 where not timed.
+ */
+dgfv_status dgfv_autotune(dgfv_mesh* mesh, const dgfv_params* params, const double* u_d,
+                          const double* alpha_d, double* ms_out, void* stream);
+
+/* Sets the element-kernel shape of one degree by hand (0, or 1 where
+ * available); DGFV_ERR_ARG for a shape the degree does not have. */
+dgfv_status dgfv_set_element_shape(dgfv_mesh* mesh, int degree, int shape);
+
+/*
  * Vector-Jacobian product of the right-hand side with alpha frozen:
  *     g_b = (dR/du (u))^T w_b,  b = 0..batch-1,
  * w_d, g_d: [batch][n_var][n_node]; alpha_d as for dg_rhs.  Derivatives at

@@ -28,16 +28,23 @@ struct Geo {
   static constexpr int EPB = NP3 >= 256 ? 1 : (512 / NP3 > 64 ? 64 : 512 / NP3);
 };
 
+// Tile shapes of the element kernel, chosen per degree by the autotuner:
+// variant 0 fills about 512 lanes per workgroup, variant 1 about 256 (only
+// where a workgroup holds more than one element).
+template <int N, int V>
+constexpr int elem_epb() { return V == 0 || Geo<N>::EPB == 1 ? Geo<N>::EPB : Geo<N>::EPB / 2; }
+constexpr int elem_variants(int N) { return (N + 1) * (N + 1) * (N + 1) >= 256 ? 1 : 2; }
+
 // ---------------------------------------------------------------------------
 // element kernel
 // ---------------------------------------------------------------------------
-template <int N, int NV, class FLUX>
-__global__ void __launch_bounds__(Geo<N>::EPB * Geo<N>::NP3)
+template <int N, int NV, class FLUX, int EPB>
+__global__ void __launch_bounds__(EPB * Geo<N>::NP3)
 element_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const double* u,
                const double* __restrict__ alpha, double* __restrict__ ut, double* k, int stage,
                double dt, double A, double B) {
   using G = Geo<N>;
-  constexpr int NP = G::NP, NP2 = G::NP2, NP3 = G::NP3, EPB = G::EPB;
+  constexpr int NP = G::NP, NP2 = G::NP2, NP3 = G::NP3;
   constexpr int NA = FLUX::NA;
   // Each pair (i, m) of a line is evaluated once: offsets o = 1..NOFF send the
   // partner's share 2 D_mi f# through sInc; for even NP the pairs at offset
@@ -813,29 +820,39 @@ vjp_fv_gather_kernel(MeshView m, const int32_t* __restrict__ elist, int count,
 // ---------------------------------------------------------------------------
 // launchers for this degree
 // ---------------------------------------------------------------------------
+template <int NV, class FLUX, int V>
+static hipError_t launch_elem_v(const MeshView& m, const int32_t* elist, int count, const double* u,
+                                const double* alpha, double* ut, double* k, int stage, double dt,
+                                double A, double B, hipStream_t s) {
+  constexpr int EPB = elem_epb<kN, V>();
+  const int blocks = (count + EPB - 1) / EPB;
+  hipLaunchKernelGGL((element_kernel<kN, NV, FLUX, EPB>), dim3(blocks), dim3(EPB * Geo<kN>::NP3), 0, s, m,
+                     elist, count, u, alpha, ut, k, stage, dt, A, B);
+  return hipGetLastError();
+}
+
 template <int NV, class FLUX>
 static hipError_t launch_elem_t(const MeshView& m, const int32_t* elist, int count, const double* u,
                                 const double* alpha, double* ut, double* k, int stage, double dt,
-                                double A, double B, hipStream_t s) {
-  using G = Geo<kN>;
-  const int blocks = (count + G::EPB - 1) / G::EPB;
-  hipLaunchKernelGGL((element_kernel<kN, NV, FLUX>), dim3(blocks), dim3(G::EPB * G::NP3), 0, s, m,
-                     elist, count, u, alpha, ut, k, stage, dt, A, B);
-  return hipGetLastError();
+                                double A, double B, int variant, hipStream_t s) {
+  if (variant == 1 && elem_variants(kN) > 1)
+    return launch_elem_v<NV, FLUX, 1>(m, elist, count, u, alpha, ut, k, stage, dt, A, B, s);
+  return launch_elem_v<NV, FLUX, 0>(m, elist, count, u, alpha, ut, k, stage, dt, A, B, s);
 }
 
 namespace per_degree {
 hipError_t element(const MeshView& m, const ParamsDev& p, const int32_t* elist, int count,
                    const double* u, const double* alpha, double* ut, double* k, int stage,
-                   double dt, double A, double B, hipStream_t s) {
+                   double dt, double A, double B, int variant, hipStream_t s) {
   if (count == 0) return hipSuccess;
+  const int v = variant;
   if (m.nvar == 5) {
-    if (p.volume_flux == 0) return launch_elem_t<5, FluxRanocha>(m, elist, count, u, alpha, ut, k, stage, dt, A, B, s);
-    if (p.volume_flux == 1) return launch_elem_t<5, FluxPirozzoli>(m, elist, count, u, alpha, ut, k, stage, dt, A, B, s);
-    return launch_elem_t<5, FluxCentral>(m, elist, count, u, alpha, ut, k, stage, dt, A, B, s);
+    if (p.volume_flux == 0) return launch_elem_t<5, FluxRanocha>(m, elist, count, u, alpha, ut, k, stage, dt, A, B, v, s);
+    if (p.volume_flux == 1) return launch_elem_t<5, FluxPirozzoli>(m, elist, count, u, alpha, ut, k, stage, dt, A, B, v, s);
+    return launch_elem_t<5, FluxCentral>(m, elist, count, u, alpha, ut, k, stage, dt, A, B, v, s);
   }
-  if (p.volume_flux == 1) return launch_elem_t<6, FluxPirozzoli>(m, elist, count, u, alpha, ut, k, stage, dt, A, B, s);
-  return launch_elem_t<6, FluxCentral>(m, elist, count, u, alpha, ut, k, stage, dt, A, B, s);
+  if (p.volume_flux == 1) return launch_elem_t<6, FluxPirozzoli>(m, elist, count, u, alpha, ut, k, stage, dt, A, B, v, s);
+  return launch_elem_t<6, FluxCentral>(m, elist, count, u, alpha, ut, k, stage, dt, A, B, v, s);
 }
 
 // fv_means is persistent: as many workgroups as fit on the device at once (at
@@ -984,7 +1001,7 @@ hipError_t vjp_gather(const MeshView& m, const int32_t* elist, int count, const 
 DegreeOps DGFV_CAT(degree_ops_, DGFV_N)() {
   return DegreeOps{&per_degree::element,    &per_degree::fv_means, &per_degree::fv_residual,
                    &per_degree::indicator,  &per_degree::vjp_volume, &per_degree::vjp_fv,
-                   &per_degree::vjp_gather, &per_degree::fv_normals};
+                   &per_degree::vjp_gather, &per_degree::fv_normals, elem_variants(kN)};
 }
 
 }  // namespace dgfv

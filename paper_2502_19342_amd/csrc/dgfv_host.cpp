@@ -120,6 +120,7 @@ struct dgfv_mesh {
   };
   static constexpr size_t GRAPH_CACHE = 16;
   int launch_mode = DGFV_LAUNCH_BRANCHES;
+  std::array<int, MAXN + 1> elem_variant{};    // element-kernel tile shape per degree (autotuned)
   hipStream_t cap_stream = nullptr;
   mutable std::vector<std::pair<GraphKey, hipGraphExec_t>> graph_cache;
 
@@ -387,7 +388,7 @@ void enqueue_rhs_impl(const dgfv_mesh* m, const ParamsDev& p, const double* u, c
     Timed t(m, DGFV_KERNEL_ELEMENT, s);
     fork_join(m, s, degs, [&](int N, hipStream_t ss) {
       hip_check(ops_for(N).element(v, p, m->d_bucket[N], (int)m->bucket[N].size(), u, alpha, ut, k, stage,
-                                   dt, A, B, ss),
+                                   dt, A, B, m->elem_variant[N], ss),
                 "element launch");
     });
   }
@@ -784,6 +785,76 @@ dgfv_status dg_rk_step(const dgfv_mesh* m, const dgfv_params* prm, double dt, do
   if (u == k) return fail(DGFV_ERR_ARG, "u and k must not overlap");
   if (dgfv_status st = check_params(m, prm)) return st;
   return run_stages(m, prm, 1, 1, 5, dt, u, k, alpha, (hipStream_t)stream);
+}
+
+dgfv_status dgfv_autotune(dgfv_mesh* m, const dgfv_params* prm, const double* u, const double* alpha,
+                          double* ms_out, void* stream) {
+  if (!m || !u) return fail(DGFV_ERR_ARG, "NULL argument");
+  if (dgfv_status st = check_params(m, prm)) return st;
+  if (ms_out) std::fill(ms_out, ms_out + 2 * (MAXN + 1), 0.0);
+  hipStream_t s = (hipStream_t)stream;
+  double* scratch = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const bool prof = m->profile;
+  m->profile = false;
+  try {
+    scratch = dev_alloc<double>((size_t)m->nvar * m->n_node);
+    hip_check(hipEventCreate(&e0), "hipEventCreate");
+    hip_check(hipEventCreate(&e1), "hipEventCreate");
+    const ParamsDev p = to_dev(prm);
+    // one full evaluation fills the side-flux and FV buffers that the element kernel reads
+    enqueue_rhs_impl(m, p, u, alpha, scratch, nullptr, 0, 0.0, s);
+    const MeshView& v = m->view;
+    constexpr int REPS = 5;
+    for (int N = 1; N <= MAXN; ++N) {
+      const DegreeOps ops = ops_for(N);
+      if (m->bucket[N].empty() || ops.element_variants < 2) continue;
+      const int cnt = (int)m->bucket[N].size();
+      double best = 0.0;
+      int choice = 0;
+      for (int var = 0; var < ops.element_variants; ++var) {
+        hip_check(ops.element(v, p, m->d_bucket[N], cnt, u, alpha, scratch, nullptr, 0, 0.0, 0.0, 0.0, var, s),
+                  "element launch");
+        hip_check(hipEventRecord(e0, s), "hipEventRecord");
+        for (int r = 0; r < REPS; ++r)
+          hip_check(ops.element(v, p, m->d_bucket[N], cnt, u, alpha, scratch, nullptr, 0, 0.0, 0.0, 0.0, var, s),
+                    "element launch");
+        hip_check(hipEventRecord(e1, s), "hipEventRecord");
+        hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+        float ms = 0.0f;
+        hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+        const double avg = ms / REPS;
+        if (ms_out) ms_out[2 * N + var] = avg;
+        if (var == 0 || avg < best) {
+          best = avg;
+          choice = var;
+        }
+      }
+      m->elem_variant[N] = choice;
+    }
+    m->drop_graphs();
+  } catch (const HipError& e) {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (scratch) (void)hipFree(scratch);
+    m->profile = prof;
+    return fail(DGFV_ERR_HIP, e.what());
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(scratch);
+  m->profile = prof;
+  return DGFV_OK;
+}
+
+dgfv_status dgfv_set_element_shape(dgfv_mesh* m, int degree, int shape) {
+  if (!m) return fail(DGFV_ERR_ARG, "mesh is NULL");
+  if (degree < 1 || degree > MAXN) return fail(DGFV_ERR_ARG, "degree must be in 1..7");
+  if (shape < 0 || shape >= ops_for(degree).element_variants)
+    return fail(DGFV_ERR_ARG, "no such element-kernel shape at this degree");
+  m->elem_variant[degree] = shape;
+  m->drop_graphs();
+  return DGFV_OK;
 }
 
 dgfv_status dgfv_set_launch_mode(dgfv_mesh* m, int mode) {

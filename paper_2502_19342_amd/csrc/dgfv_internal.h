@@ -80,9 +80,10 @@ struct MeshView {
 // in `elist` (device).  stage 0 writes ut = R(u); stage 1..5 performs the RK
 // stage with coefficients (A, B) on u (in place) and k.
 struct DegreeOps {
+  // element kernel in tile shape `variant` (0 .. element_variants - 1)
   hipError_t (*element)(const MeshView& m, const ParamsDev& p, const int32_t* elist, int count,
                         const double* u, const double* alpha, double* ut, double* k, int stage,
-                        double dt, double A, double B, hipStream_t s);
+                        double dt, double A, double B, int variant, hipStream_t s);
   // FV kernels walk this degree's range of the blended-element list (m.blend_list,
   // m.blend_start) with `count` persistent workgroups; `count` bounds the range size
   hipError_t (*fv_means)(const MeshView& m, int count, const double* u, hipStream_t s);
@@ -99,6 +100,7 @@ struct DegreeOps {
                            double* g, hipStream_t s);
   // setup: sub-face normals of the FV sub-cell grid (geometry only)
   hipError_t (*fv_normals)(const MeshView& m, const int32_t* elist, int count, hipStream_t s);
+  int element_variants;   // tile shapes of the element kernel at this degree
 };
 DegreeOps degree_ops_1();
 DegreeOps degree_ops_2();

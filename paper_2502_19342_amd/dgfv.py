@@ -41,7 +41,8 @@ class _Params(ctypes.Structure):
 
 
 EXPORTED = ("dgfv_mesh_create", "dgfv_mesh_destroy", "dgfv_mesh_info", "dgfv_mesh_node_coords",
-            "dg_indicator", "dg_rhs", "dg_rk_stage", "dg_rk_step", "dg_rhs_vjp", "dgfv_set_launch_mode",
+            "dg_indicator", "dg_rhs", "dg_rk_stage", "dg_rk_step", "dg_rhs_vjp", "dgfv_set_launch_mode", "dgfv_autotune",
+            "dgfv_set_element_shape",
             "dgfv_profile_enable", "dgfv_profile_read", "dgfv_last_error")
 KERNEL_ELEMENT, KERNEL_FACE, KERNEL_FV_MEANS, KERNEL_FV_RESIDUAL, KERNEL_INDICATOR, KERNEL_VJP = range(6)
 LAUNCH_SERIAL, LAUNCH_BRANCHES, LAUNCH_GRAPH = range(3)
@@ -63,6 +64,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dg_rk_step.argtypes = [P, ctypes.POINTER(_Params), c_double, P, P, P, P]
     lib.dg_rhs_vjp.argtypes = [P, ctypes.POINTER(_Params), P, P, P, P, c_int, P]
     lib.dgfv_set_launch_mode.argtypes = [P, c_int]
+    lib.dgfv_set_element_shape.argtypes = [P, c_int, c_int]
+    lib.dgfv_autotune.argtypes = [P, ctypes.POINTER(_Params), P, P, ctypes.POINTER(ctypes.c_double), P]
     lib.dgfv_profile_enable.argtypes = [P, c_int]
     lib.dgfv_profile_read.argtypes = [P, c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.dgfv_last_error.restype = ctypes.c_char_p
@@ -141,6 +144,21 @@ class Mesh:
     def launch_mode(self, mode: int) -> None:
         """LAUNCH_SERIAL, LAUNCH_BRANCHES (default) or LAUNCH_GRAPH (``dgfv_set_launch_mode``)."""
         _check(_lib.dgfv_set_launch_mode(self._h, int(mode)))
+
+    def autotune(self, params: "Params", u: torch.Tensor, alpha: torch.Tensor | None = None,
+                 stream=None) -> dict:
+        """Pick the element kernel's tile shape per degree (``dgfv_autotune``).
+
+        Returns ``{N: (ms_shape0, ms_shape1)}`` for the degrees that were timed.
+        """
+        ms = (ctypes.c_double * 16)()
+        _check(_lib.dgfv_autotune(self._h, ctypes.byref(params.c()), self._state(u, "u"), self._alpha(alpha),
+                                  ms, _stream(stream)))
+        return {N: (ms[2 * N], ms[2 * N + 1]) for N in range(1, 8) if ms[2 * N] > 0}
+
+    def set_element_shape(self, degree: int, shape: int) -> None:
+        """Element-kernel tile shape of one degree by hand (``dgfv_set_element_shape``)."""
+        _check(_lib.dgfv_set_element_shape(self._h, int(degree), int(shape)))
 
     def graphs(self, enable: bool = True) -> None:
         """Capture and replay RK steps and stages as hipGraphs, or go back to branch launches."""

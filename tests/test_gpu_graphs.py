@@ -78,3 +78,25 @@ def test_graph_recaptures_on_new_alpha_pointer():
         torch.cuda.synchronize()
         assert torch.equal(u, r)
     c.gmesh.graphs(False)
+
+
+def test_element_shapes_and_autotune():
+    announce("element shapes + autotune")
+    from paper_2502_19342_amd import dgfv
+    from gpu_common import rel_err, rhs_tol
+    wl = curved_mixed(n=3, nmin=1, nmax=5, scramble=47, metric_degree=1, n_fv=6)
+    c = Case(wl, prim=smooth_state(101), noise=1e-3, seed=14)
+    c.alpha = seeded_alpha(c.mesh.K, 48, values=(0.0, 0.0, 0.5, 1.0))
+    out = []
+    for shape in (0, 1):
+        for N in range(1, 6):
+            c.gmesh.set_element_shape(N, shape)
+        out.append(c.gpu_rhs())
+    # the shape only changes how many elements share a workgroup: identical arithmetic
+    assert torch.equal(out[0], out[1])
+    assert rel_err(out[1], c.oracle_rhs()) <= rhs_tol(c)
+    with pytest.raises(dgfv.DgfvError):
+        c.gmesh.set_element_shape(7, 1)          # one shape only at N = 7
+    ms = c.gmesh.autotune(c.params, c.gpu(c.u), c.gpu(c.alpha))
+    assert set(ms) <= {1, 2, 3, 4, 5} and all(a > 0 and b > 0 for a, b in ms.values())
+    assert torch.equal(c.gpu_rhs(), out[0])
