@@ -44,6 +44,9 @@ def parse():
     ap.add_argument("--launch", default="branches", choices=["serial", "branches", "graph"],
                     help="serial launches, concurrent degree-bucket branches, or replayed hipGraphs")
     ap.add_argument("--cpu-sample-n", type=int, default=8, help="elements per direction of the oracle sample")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward timing ratio")
+    ap.add_argument("--copy-gib", type=float, default=0.0,
+                    help="before the steps, one plain device copy of this many GiB (counter calibration)")
     return ap.parse_args()
 
 
@@ -114,6 +117,35 @@ def cpu_baseline(cfg: str, n: int, seed: int):
                       f"{el:.1f} s"}
 
 
+def adjoint_ratio(gm, prm, u, dgfv, torch, reps: int = 5):
+    """t(dg_rhs_vjp, batch 1) / t(dg_rhs) on the same state, pure DG (alpha = NULL), events on one stream."""
+    w = torch.randn_like(u)
+    ut = torch.empty_like(u)
+    g = torch.empty_like(u)
+
+    def timed(fn, reps=reps):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        b.synchronize()
+        return a.elapsed_time(b) / reps
+
+    t_rhs = timed(lambda: dgfv.rhs(gm, prm, u, None, out=ut))
+    t_vjp = timed(lambda: dgfv.rhs_vjp(gm, prm, u, None, w, out=g))
+    rec = {"rhs_ms": t_rhs, "vjp_ms": t_vjp, "ratio": t_vjp / t_rhs, "batch": 1, "alpha": "none (pure DG)"}
+    if 2 * 32 * u.numel() * 8 <= (8 << 30):          # a batch of 32 cotangents where it fits in 8 GiB
+        w32 = torch.randn((32,) + tuple(u.shape), dtype=u.dtype, device=u.device)
+        g32 = torch.empty_like(w32)
+        t32 = timed(lambda: dgfv.rhs_vjp(gm, prm, u, None, w32, out=g32), reps=2)
+        rec["vjp_batch32_ms"] = t32
+        rec["batch32_ratio"] = t32 / (32 * t_rhs)
+    return rec
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -158,6 +190,13 @@ def main():
 
     gm.launch_mode({"serial": dgfv.LAUNCH_SERIAL, "branches": dgfv.LAUNCH_BRANCHES,
                     "graph": dgfv.LAUNCH_GRAPH}[args.launch])
+    if args.copy_gib > 0:
+        n = int(args.copy_gib * (1 << 30)) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         dgfv.rk_step(gm, prm, dt, u, k, alpha)
     torch.cuda.synchronize()
@@ -183,6 +222,7 @@ def main():
     if not torch.isfinite(u).all():
         print("bench.py: non-finite state after the timed steps", file=sys.stderr)
         sys.exit(1)
+    adjoint = None if args.no_adjoint else adjoint_ratio(gm, prm, u, dgfv, torch)
 
     stages = 5 * args.steps
     value = n_dof * stages / el
@@ -220,7 +260,7 @@ def main():
                      "bytes_per_launch": byts, "avg_launch_ms": 1e3 * avg_el_s},
         "kernel_ms_per_stage": {kname: v[0] / max(1, v[1]) for kname, v in kt.items()},
         "kernel_ms_source": "live events over the timed steps" if live else "profiled steps after the timed region",
-        "adjoint_forward_ratio": None,
+        "adjoint_forward_ratio": adjoint,
     }
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(args.config, args.cpu_sample_n, wl.seed)
