@@ -239,13 +239,18 @@ def rhs_vjp(mesh: Mesh, params: Params, u: torch.Tensor, alpha: torch.Tensor | N
             out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     """``(dR/du)^T w`` for a batch ``w[B, n_var, n_node]`` (``dg_rhs_vjp``)."""
     squeeze = w.dim() == 2
+    given = out
     if squeeze:
         w = w.unsqueeze(0)
+        if out is not None:
+            out = out.unsqueeze(0)
     B = w.shape[0]
     if out is None:
         out = torch.empty_like(w)
     _check(_lib.dg_rhs_vjp(mesh._h, ctypes.byref(params.c()), mesh._state(u, "u"), mesh._alpha(alpha),
                            mesh._state(w, "w", B), mesh._state(out, "out", B), B, _stream(stream)))
+    if given is not None:
+        return given
     return out[0] if squeeze else out
 
 

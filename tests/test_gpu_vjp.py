@@ -98,6 +98,9 @@ def test_vjp_batch_equals_single_calls():
     for b in range(3):
         g1 = dgfv.rhs_vjp(c.gmesh, c.params, c.gpu(c.u), None, ws[b].contiguous())
         assert torch.equal(gb[b], g1)
+    out = torch.empty_like(ws[0])                     # a single cotangent into a given output
+    assert dgfv.rhs_vjp(c.gmesh, c.params, c.gpu(c.u), None, ws[0].contiguous(), out=out) is out
+    assert torch.equal(out, gb[0])
 
 
 def test_vjp_against_central_differences_c4():
