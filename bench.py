@@ -117,6 +117,27 @@ def cpu_baseline(cfg: str, n: int, seed: int):
                       f"{el:.1f} s"}
 
 
+def counter_traffic(cfg: str):
+    """HBM bytes per element-kernel launch from the committed rocprofv3 counter runs.
+
+    FETCH_SIZE and WRITE_SIZE per dispatch (two --pmc runs), each scaled by what
+    the same counter reads for a plain 4 GiB device copy in the same run.  The
+    figure holds only for the kernel sources it was measured on (sha256 of the
+    files listed with it) and for the C5 workload; otherwise None.
+    """
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "element_kernel_C5_hbm_traffic.json")
+    if cfg != "C5" or not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    h = hashlib.sha256()
+    for f in rec["source_files"]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return rec["traffic_bytes_per_launch"] if h.hexdigest() == rec["source_sha256"] else None
+
+
 def adjoint_ratio(gm, prm, u, dgfv, torch, reps: int = 5):
     """t(dg_rhs_vjp, batch 1) / t(dg_rhs) on the same state, pure DG (alpha = NULL), events on one stream."""
     w = torch.randn_like(u)
@@ -255,7 +276,7 @@ def main():
             "blended_fraction": float(mask.mean()),
         },
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": counter_traffic(args.config),
                      "kernel": "element_kernel (volume + lift + blend + RK update)",
                      "bytes_per_launch": byts, "avg_launch_ms": 1e3 * avg_el_s},
         "kernel_ms_per_stage": {kname: v[0] / max(1, v[1]) for kname, v in kt.items()},
