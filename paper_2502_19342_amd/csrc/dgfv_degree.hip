@@ -8,6 +8,8 @@
 //  fv_residual     first-order FV sub-cell operator (eq. semidiscrete_fv) mapped
 //                  back with V^{FV->DG}
 //  indicator       modal decay indicator and blending ramp (Section 3.4)
+#include <type_traits>
+
 #include "dgfv_internal.h"
 #include "dgfv_physics.h"
 #include "dgfv_lds.h"
@@ -47,7 +49,7 @@ element_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const d
   constexpr int NP = G::NP, NP2 = G::NP2, NP3 = G::NP3;
   constexpr int NA = FLUX::NA;
   // Each pair (i, m) of a line is evaluated once: offsets o = 1..NOFF send the
-  // partner's share 2 D_mi f# through sInc; for even NP the pairs at offset
+  // partner's share D_mi f# through sInc; for even NP the pairs at offset
   // NP/2 are evaluated from both ends (no exchange).
   constexpr int NOFF = (NP - 1) / 2;
   constexpr bool HALF = (NP % 2) == 0;
@@ -62,7 +64,10 @@ element_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const d
   const int idx = blockIdx.x * EPB + slot;
   const bool active = idx < count;          // inactive lanes mirror element 0 and write nothing
 
-  for (int t = tid; t < NP * NP; t += blockDim.x) sD[t] = 2.0 * m.ops[m.tab.D[N] + t];
+  // The two-point fluxes are linear in the metric direction: they are evaluated
+  // with the sum Ja_i + Ja_m instead of the mean, so the weights are D_im
+  // instead of 2 D_im.
+  for (int t = tid; t < NP * NP; t += blockDim.x) sD[t] = m.ops[m.tab.D[N] + t];
 
   const int e = elist[active ? idx : 0];
   const int64_t base = m.elem_offset[e] + node;
@@ -79,27 +84,46 @@ element_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const d
   const double invJ = 1.0 / m.metric[9 * m.n_node + base];
 
   const int i = node % NP, j = (node / NP) % NP, kk = node / NP2;
+  const int lane = tid & 63;
   double acc[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+  __syncthreads();                            // sAux complete
   double me[NA];
-
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
+  for (int a = 0; a < NA; ++a) me[a] = sAux[slot][a][node];
+
+  // One direction of the flux differencing.  Where every line of direction d
+  // lies inside one 64-lane wave (N+1 dividing 64 for d = 0, 1; (N+1)^3
+  // dividing 64 for d = 2), the partner's metric and the partner's share move
+  // by cross-lane shuffles and need no workgroup barrier; otherwise through LDS.
+  auto direction = [&](auto dtag, bool lds_was_used) {
+    constexpr int d = decltype(dtag)::value;
+    constexpr bool in_wave = d < 2 ? (64 % NP == 0) : (64 % NP3 == 0);
+    constexpr int stride = d == 0 ? 1 : (d == 1 ? NP : NP2);
+    const int id = d == 0 ? i : (d == 1 ? j : kk);
     const double ja1 = m.metric[(3 * d + 0) * m.n_node + base];
     const double ja2 = m.metric[(3 * d + 1) * m.n_node + base];
     const double ja3 = m.metric[(3 * d + 2) * m.n_node + base];
-    if (d > 0) __syncthreads();               // previous direction done with sJa and sInc
-    sJa[slot][0][node] = ja1;
-    sJa[slot][1][node] = ja2;
-    sJa[slot][2][node] = ja3;
-    __syncthreads();
-    if (d == 0) {
-#pragma unroll
-      for (int a = 0; a < NA; ++a) me[a] = sAux[slot][a][node];
+    if constexpr (!in_wave) {
+      if (lds_was_used) __syncthreads();      // previous direction done with sJa and sInc
+      sJa[slot][0][node] = ja1;
+      sJa[slot][1][node] = ja2;
+      sJa[slot][2][node] = ja3;
+      __syncthreads();
     }
-    const int id = d == 0 ? i : (d == 1 ? j : kk);
-    const int stride = d == 0 ? 1 : (d == 1 ? NP : NP2);
+    auto partner_metric = [&](int pn, double& b1, double& b2, double& b3) {
+      if constexpr (in_wave) {
+        const int sl = (lane + pn - node) & 63;
+        b1 = __shfl(ja1, sl);
+        b2 = __shfl(ja2, sl);
+        b3 = __shfl(ja3, sl);
+      } else {
+        b1 = sJa[slot][0][pn];
+        b2 = sJa[slot][1][pn];
+        b3 = sJa[slot][2][pn];
+      }
+    };
 #pragma unroll 1
     for (int o = 1; o <= NOFF; ++o) {
       int mm = id + o;
@@ -108,20 +132,28 @@ element_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const d
       double other[NA];
 #pragma unroll
       for (int a = 0; a < NA; ++a) other[a] = sAux[slot][a][pn];
-      const double a1 = 0.5 * (ja1 + sJa[slot][0][pn]);
-      const double a2 = 0.5 * (ja2 + sJa[slot][1][pn]);
-      const double a3 = 0.5 * (ja3 + sJa[slot][2][pn]);
+      double b1, b2, b3;
+      partner_metric(pn, b1, b2, b3);
       double f[NV];
-      FLUX::template flux_fast<NV>(me, other, a1, a2, a3, m.gas, f);
+      FLUX::template flux_fast<NV>(me, other, ja1 + b1, ja2 + b2, ja3 + b3, m.gas, f);
       const double c1 = sD[id * NP + mm], c2 = sD[mm * NP + id];
 #pragma unroll
       for (int v = 0; v < NV; ++v) acc[v] += c1 * f[v];
-      if (o > 1) __syncthreads();             // partner has read the previous round's share
+      if constexpr (in_wave) {
+        // the share for this node comes from the node at offset -o on the line
+        int mr = id - o;
+        if (mr < 0) mr += NP;
+        const int sl = (lane + (mr - id) * stride) & 63;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) sInc[slot][v][pn] = c2 * f[v];
-      __syncthreads();
+        for (int v = 0; v < NV; ++v) acc[v] += __shfl(c2 * f[v], sl);
+      } else {
+        if (o > 1) __syncthreads();           // partner has read the previous round's share
 #pragma unroll
-      for (int v = 0; v < NV; ++v) acc[v] += sInc[slot][v][node];
+        for (int v = 0; v < NV; ++v) sInc[slot][v][pn] = c2 * f[v];
+        __syncthreads();
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[v] += sInc[slot][v][node];
+      }
     }
     if constexpr (HALF) {
       int mm = id + NP / 2;
@@ -130,16 +162,19 @@ element_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const d
       double other[NA];
 #pragma unroll
       for (int a = 0; a < NA; ++a) other[a] = sAux[slot][a][pn];
-      const double a1 = 0.5 * (ja1 + sJa[slot][0][pn]);
-      const double a2 = 0.5 * (ja2 + sJa[slot][1][pn]);
-      const double a3 = 0.5 * (ja3 + sJa[slot][2][pn]);
+      double b1, b2, b3;
+      partner_metric(pn, b1, b2, b3);
       double f[NV];
-      FLUX::template flux_fast<NV>(me, other, a1, a2, a3, m.gas, f);
+      FLUX::template flux_fast<NV>(me, other, ja1 + b1, ja2 + b2, ja3 + b3, m.gas, f);
       const double c1 = sD[id * NP + mm];
 #pragma unroll
       for (int v = 0; v < NV; ++v) acc[v] += c1 * f[v];
     }
-  }
+    return lds_was_used || !in_wave;
+  };
+  bool lds_used = direction(std::integral_constant<int, 0>{}, false);
+  lds_used = direction(std::integral_constant<int, 1>{}, lds_used);
+  direction(std::integral_constant<int, 2>{}, lds_used);
   if (!active) return;
 
   // surface lift: outward numerical flux over the end weight on boundary nodes

@@ -109,6 +109,17 @@ __device__ __forceinline__ double log_mean_d(double a, double b, double la, doub
 // ---------------------------------------------------------------------------
 
 // Ranocha's entropy-conserving, kinetic-energy-preserving flux (single species).
+// 1/x from the hardware estimate (v_rcp_f64) refined by two Newton-Raphson
+// steps, e = 1 - x r, r <- r + r e: within about one ulp, not correctly rounded.
+// x must be finite and nonzero.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+
 struct FluxRanocha {
   static constexpr int NA = 8;  // rho, v1, v2, v3, p, ln rho, beta = rho/p, ln beta
   template <int NV, class S>
@@ -119,7 +130,7 @@ struct FluxRanocha {
     r[6] = beta;
     r[7] = log(beta);
   }
-  // Double-precision evaluation with one division per logarithmic mean.
+  // Double-precision evaluation with one reciprocal (rcp_nr) per logarithmic mean.
   // rho_ln: near-equal arguments use (a+b)/2 times the reciprocal of the
   // Ismail-Roe series, 1/F(u) = 1 - u/3 - 4u^2/45 - 44u^3/945 + O(u^4), with
   // u = ((a-b)/(a+b))^2; otherwise (a-b)/(ln a - ln b).  The energy flux needs
@@ -131,7 +142,7 @@ struct FluxRanocha {
     {
       const double s = a_[0] + b_[0], d = a_[0] - b_[0], dl = a_[5] - b_[5];
       const bool small = d * d < 1e-4 * s * s;
-      const double r = 1.0 / (small ? s : dl);
+      const double r = rcp_nr(small ? s : dl);
       const double u = (d * r) * (d * r);
       const double iF = 1.0 - u * (1.0 / 3.0 + u * (4.0 / 45.0 + u * (44.0 / 945.0)));
       rho_ln = small ? 0.5 * s * iF : d * r;
@@ -139,7 +150,7 @@ struct FluxRanocha {
     {
       const double s = a_[6] + b_[6], d = a_[6] - b_[6], dl = a_[7] - b_[7];
       const bool small = d * d < 1e-4 * s * s;
-      const double r = 1.0 / (small ? s : d);
+      const double r = rcp_nr(small ? s : d);
       const double u = (d * r) * (d * r);
       const double F = 1.0 + u * (1.0 / 3.0 + u * (0.2 + u * (1.0 / 7.0)));
       ibeta_ln = small ? 2.0 * F * r : dl * r;
