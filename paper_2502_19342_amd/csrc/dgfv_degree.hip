@@ -97,14 +97,12 @@ element_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const d
   // lies inside one 64-lane wave (N+1 dividing 64 for d = 0, 1; (N+1)^3
   // dividing 64 for d = 2), the partner's metric and the partner's share move
   // by cross-lane shuffles and need no workgroup barrier; otherwise through LDS.
-  auto direction = [&](auto dtag, bool lds_was_used) {
+  auto direction = [&](auto dtag, bool lds_was_used, const double* ja) {
     constexpr int d = decltype(dtag)::value;
     constexpr bool in_wave = d < 2 ? (64 % NP == 0) : (64 % NP3 == 0);
     constexpr int stride = d == 0 ? 1 : (d == 1 ? NP : NP2);
     const int id = d == 0 ? i : (d == 1 ? j : kk);
-    const double ja1 = m.metric[(3 * d + 0) * m.n_node + base];
-    const double ja2 = m.metric[(3 * d + 1) * m.n_node + base];
-    const double ja3 = m.metric[(3 * d + 2) * m.n_node + base];
+    const double ja1 = ja[0], ja2 = ja[1], ja3 = ja[2];
     if constexpr (!in_wave) {
       if (lds_was_used) __syncthreads();      // previous direction done with sJa and sInc
       sJa[slot][0][node] = ja1;
@@ -172,9 +170,21 @@ element_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const d
     }
     return lds_was_used || !in_wave;
   };
-  bool lds_used = direction(std::integral_constant<int, 0>{}, false);
-  lds_used = direction(std::integral_constant<int, 1>{}, lds_used);
-  direction(std::integral_constant<int, 2>{}, lds_used);
+  // Ja^d of the next direction is loaded while the current one is computed
+  auto load_ja = [&](int d, double* ja) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) ja[c] = m.metric[(3 * d + c) * m.n_node + base];
+  };
+  double jaA[3], jaB[3];
+  load_ja(0, jaA);
+  load_ja(1, jaB);
+  bool lds_used = direction(std::integral_constant<int, 0>{}, false, jaA);
+  load_ja(2, jaA);
+  lds_used = direction(std::integral_constant<int, 1>{}, lds_used, jaB);
+  double k_old[NV];                            // the RK register, loaded while xi_3 is computed
+#pragma unroll
+  for (int v = 0; v < NV; ++v) k_old[v] = stage > 1 ? k[v * m.n_node + base] : 0.0;
+  direction(std::integral_constant<int, 2>{}, lds_used, jaA);
   if (!active) return;
 
   // surface lift: outward numerical flux over the end weight on boundary nodes
@@ -209,7 +219,7 @@ element_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const d
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       const int64_t g = v * m.n_node + base;
-      const double kv = (stage == 1) ? dt * R[v] : A * k[g] + dt * R[v];
+      const double kv = (stage == 1) ? dt * R[v] : A * k_old[v] + dt * R[v];
       k[g] = kv;
       uw[g] = uo[v] + B * kv;
     }
