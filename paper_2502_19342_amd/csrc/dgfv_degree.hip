@@ -179,12 +179,81 @@ element_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const d
   load_ja(0, jaA);
   load_ja(1, jaB);
   bool lds_used = direction(std::integral_constant<int, 0>{}, false, jaA);
-  load_ja(2, jaA);
+  // At N = 7 with one element per workgroup (an 8 x 8 plane per wave) the
+  // xi_3 lines cross waves.  There the xi_3 pairs are computed under a
+  // transposed ownership instead, wave w taking the plane j = w and lane l the
+  // node (i, k) = (l mod 8, l div 8), so that every xi_3 line lies in one wave
+  // and moves by shuffles; one LDS pass hands the sums back to the owners.
+  constexpr bool XI3_TRANSPOSED = NP == 8 && EPB == 1;
+  if constexpr (XI3_TRANSPOSED) {
+    const int nt = (lane % NP) + NP * (tid >> 6) + NP2 * (lane / NP);
+    const int64_t bt = m.elem_offset[e] + nt;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) jaA[c] = m.metric[(6 + c) * m.n_node + bt];
+  } else {
+    load_ja(2, jaA);
+  }
   lds_used = direction(std::integral_constant<int, 1>{}, lds_used, jaB);
   double k_old[NV];                            // the RK register, loaded while xi_3 is computed
+  if constexpr (!XI3_TRANSPOSED) {
 #pragma unroll
-  for (int v = 0; v < NV; ++v) k_old[v] = stage > 1 ? k[v * m.n_node + base] : 0.0;
-  direction(std::integral_constant<int, 2>{}, lds_used, jaA);
+    for (int v = 0; v < NV; ++v) k_old[v] = stage > 1 ? k[v * m.n_node + base] : 0.0;
+  }
+  if constexpr (XI3_TRANSPOSED) {
+    // the owners park their xi_1, xi_2 sums in LDS, which frees their registers
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sInc[0][v][node] = acc[v];
+    const int it = lane % NP, kt = lane / NP;
+    const int nt = it + NP * (tid >> 6) + NP2 * kt;
+    double mt[NA], at[NV];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) mt[a] = sAux[0][a][nt];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) at[v] = 0.0;
+    const double ja1 = jaA[0], ja2 = jaA[1], ja3 = jaA[2];
+    auto pair = [&](int mm, bool exchange, int o) {
+      const int pn = nt + (mm - kt) * NP2;
+      const int sl = (lane + (mm - kt) * NP) & 63;
+      double other[NA];
+#pragma unroll
+      for (int a = 0; a < NA; ++a) other[a] = sAux[0][a][pn];
+      const double b1 = __shfl(ja1, sl), b2 = __shfl(ja2, sl), b3 = __shfl(ja3, sl);
+      double f[NV];
+      FLUX::template flux_fast<NV>(mt, other, ja1 + b1, ja2 + b2, ja3 + b3, m.gas, f);
+      const double c1 = sD[kt * NP + mm];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) at[v] += c1 * f[v];
+      if (exchange) {
+        const double c2 = sD[mm * NP + kt];
+        int mr = kt - o;
+        if (mr < 0) mr += NP;
+        const int sr = (lane + (mr - kt) * NP) & 63;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) at[v] += __shfl(c2 * f[v], sr);
+      }
+    };
+#pragma unroll 1
+    for (int o = 1; o <= NOFF; ++o) {
+      int mm = kt + o;
+      if (mm >= NP) mm -= NP;
+      pair(mm, true, o);
+    }
+    {
+      int mm = kt + NP / 2;
+      if (mm >= NP) mm -= NP;
+      pair(mm, false, 0);
+    }
+    __syncthreads();                           // every owner has parked its sums
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sInc[0][v][nt] += at[v];
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = sInc[0][v][node];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) k_old[v] = stage > 1 ? k[v * m.n_node + base] : 0.0;
+  } else {
+    direction(std::integral_constant<int, 2>{}, lds_used, jaA);
+  }
   if (!active) return;
 
   // surface lift: outward numerical flux over the end weight on boundary nodes
