@@ -612,16 +612,21 @@ indicator_kernel(MeshView m, ParamsDev prm, const int32_t* __restrict__ elist, i
 // cotangents a_i / w_0 at the boundary nodes.
 // ---------------------------------------------------------------------------
 template <int N, int NV, class FLUX>
-__global__ void __launch_bounds__(Geo<N>::EPB * Geo<N>::NP3)
+__global__ void __launch_bounds__(Geo<N>::EPB * Geo<N>::NP3, 4)   // 4 waves per SIMD: two workgroups per CU
 vjp_volume_kernel(MeshView m, const int32_t* __restrict__ elist, int count,
                   const double* __restrict__ u, const double* __restrict__ alpha,
                   const double* __restrict__ w, double* __restrict__ g) {
   using G = Geo<N>;
   constexpr int NP = G::NP, NP2 = G::NP2, NP3 = G::NP3, EPB = G::EPB;
   constexpr int NA = FLUX::NA;
+  // The partners' metric moves by wave shuffles where the lines lie inside one
+  // wave (xi_1, xi_2 when N+1 divides 64; xi_3 when (N+1)^3 does); only the
+  // other components are kept in LDS.
+  constexpr bool SH01 = 64 % NP == 0, SH2 = 64 % NP3 == 0;
+  constexpr int JL = SH01 ? (SH2 ? 1 : 3) : 9;
   __shared__ double sD[NP * NP];
   __shared__ double sAux[EPB][NA][NP3];
-  __shared__ double sJa[EPB][9][NP3];
+  __shared__ double sJa[EPB][JL][NP3];
   __shared__ double sA[EPB][NV][NP3];
 
   const int tid = threadIdx.x;
@@ -629,7 +634,8 @@ vjp_volume_kernel(MeshView m, const int32_t* __restrict__ elist, int count,
   const int node = tid - slot * NP3;
   const int idx = blockIdx.x * EPB + slot;
   const bool active = idx < count;
-  for (int t = tid; t < NP * NP; t += blockDim.x) sD[t] = 2.0 * m.ops[m.tab.D[N] + t];
+  // metric sums with weights D_im, as in the forward kernel
+  for (int t = tid; t < NP * NP; t += blockDim.x) sD[t] = m.ops[m.tab.D[N] + t];
 
   int e = 0;
   int64_t base = 0;
@@ -644,8 +650,13 @@ vjp_volume_kernel(MeshView m, const int32_t* __restrict__ elist, int count,
     FLUX::template make<NV>(q, r);
 #pragma unroll
     for (int a = 0; a < NA; ++a) sAux[slot][a][node] = r[a];
+    if constexpr (JL == 9) {
 #pragma unroll
-    for (int c = 0; c < 9; ++c) sJa[slot][c][node] = m.metric[c * m.n_node + base];
+      for (int c = 0; c < 9; ++c) sJa[slot][c][node] = m.metric[c * m.n_node + base];
+    } else if constexpr (JL == 3) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) sJa[slot][c][node] = m.metric[(6 + c) * m.n_node + base];
+    }
     const double al = alpha ? alpha[e] : 0.0;
     const double sc = -(1.0 - al) / m.metric[9 * m.n_node + base];
 #pragma unroll
@@ -664,13 +675,15 @@ vjp_volume_kernel(MeshView m, const int32_t* __restrict__ elist, int count,
     me[a] = sAux[slot][a][node];
     ab[a] = 0.0;
   }
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
+  const int lane = tid & 63;
+  auto direction = [&](auto dtag) {
+    constexpr int d = decltype(dtag)::value;
+    constexpr bool sh = d < 2 ? SH01 : SH2;
+    constexpr int stride = d == 0 ? 1 : (d == 1 ? NP : NP2);
     const int id = d == 0 ? i : (d == 1 ? j : kk);
-    const int stride = d == 0 ? 1 : (d == 1 ? NP : NP2);
-    const double ja1 = sJa[slot][3 * d + 0][node];
-    const double ja2 = sJa[slot][3 * d + 1][node];
-    const double ja3 = sJa[slot][3 * d + 2][node];
+    const double ja1 = m.metric[(3 * d + 0) * m.n_node + base];
+    const double ja2 = m.metric[(3 * d + 1) * m.n_node + base];
+    const double ja3 = m.metric[(3 * d + 2) * m.n_node + base];
 #pragma unroll 1
     for (int o = 1; o < NP; ++o) {
       int mm = id + o;
@@ -682,12 +695,27 @@ vjp_volume_kernel(MeshView m, const int32_t* __restrict__ elist, int count,
       const double cme = sD[id * NP + mm], cot = sD[mm * NP + id];
 #pragma unroll
       for (int v = 0; v < NV; ++v) c[v] = cme * ame[v] + cot * sA[slot][v][pn];
-      const double a1 = 0.5 * (ja1 + sJa[slot][3 * d + 0][pn]);
-      const double a2 = 0.5 * (ja2 + sJa[slot][3 * d + 1][pn]);
-      const double a3 = 0.5 * (ja3 + sJa[slot][3 * d + 2][pn]);
-      FLUX::template flux_adj_a<NV>(me, other, a1, a2, a3, m.gas, c, ab);
+      double b1, b2, b3;
+      if constexpr (sh) {
+        const int sl = (lane + pn - node) & 63;
+        b1 = __shfl(ja1, sl);
+        b2 = __shfl(ja2, sl);
+        b3 = __shfl(ja3, sl);
+      } else if constexpr (JL == 9) {
+        b1 = sJa[slot][3 * d + 0][pn];
+        b2 = sJa[slot][3 * d + 1][pn];
+        b3 = sJa[slot][3 * d + 2][pn];
+      } else {                                 // JL == 3: only xi_3 is kept in LDS
+        b1 = sJa[slot][0][pn];
+        b2 = sJa[slot][1][pn];
+        b3 = sJa[slot][2][pn];
+      }
+      FLUX::template flux_adj_a<NV>(me, other, ja1 + b1, ja2 + b2, ja3 + b3, m.gas, c, ab);
     }
-  }
+  };
+  direction(std::integral_constant<int, 0>{});
+  direction(std::integral_constant<int, 1>{});
+  direction(std::integral_constant<int, 2>{});
   double ub[NV];
   FLUX::template make_adj<NV>(uo, m.gas, ab, ub);
 #pragma unroll

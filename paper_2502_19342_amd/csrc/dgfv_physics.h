@@ -79,21 +79,34 @@ __device__ __forceinline__ S log_mean(const S& a, const S& b, const S& la, const
 }
 
 // Partial derivatives of log_mean with respect to its first value and first logarithm.
+// 1/x from the hardware estimate (v_rcp_f64) refined by two Newton-Raphson
+// steps, e = 1 - x r, r <- r + r e: within about one ulp, not correctly rounded.
+// x must be finite and nonzero.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+
 __device__ __forceinline__ double log_mean_d(double a, double b, double la, double lb, double& d_a,
                                              double& d_la) {
   const double s = a + b;
-  const double f = (a - b) / s;
+  const double is = rcp_nr(s);
+  const double f = (a - b) * is;
   const double u = f * f;
   if (u < 1e-4) {
     const double F = 1.0 + u * (1.0 / 3.0 + u * (0.2 + u * (1.0 / 7.0)));
     const double dF = 1.0 / 3.0 + u * (0.4 + u * (3.0 / 7.0));
-    const double dfa = 2.0 * b / (s * s);
-    const double lm = s / (2.0 * F);
-    d_a = 1.0 / (2.0 * F) - lm / F * dF * (2.0 * f * dfa);
+    const double iF = rcp_nr(F);
+    const double dfa = 2.0 * b * is * is;
+    const double lm = 0.5 * s * iF;
+    d_a = 0.5 * iF - lm * iF * dF * (2.0 * f * dfa);
     d_la = 0.0;
     return lm;
   }
-  const double il = 1.0 / (la - lb);
+  const double il = rcp_nr(la - lb);
   const double lm = (a - b) * il;
   d_a = il;
   d_la = -lm * il;
@@ -109,17 +122,6 @@ __device__ __forceinline__ double log_mean_d(double a, double b, double la, doub
 // ---------------------------------------------------------------------------
 
 // Ranocha's entropy-conserving, kinetic-energy-preserving flux (single species).
-// 1/x from the hardware estimate (v_rcp_f64) refined by two Newton-Raphson
-// steps, e = 1 - x r, r <- r + r e: within about one ulp, not correctly rounded.
-// x must be finite and nonzero.
-__device__ __forceinline__ double rcp_nr(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = __builtin_fma(-x, r, 1.0);
-  r = __builtin_fma(r, e, r);
-  e = __builtin_fma(-x, r, 1.0);
-  return __builtin_fma(r, e, r);
-}
-
 struct FluxRanocha {
   static constexpr int NA = 8;  // rho, v1, v2, v3, p, ln rho, beta = rho/p, ln beta
   template <int NV, class S>
@@ -198,7 +200,7 @@ struct FluxRanocha {
     const double vn = v1 * n1 + v2 * n2 + v3 * n3;
     const double fr = rho_ln * vn;
     const double gm1 = g.gamma - 1.0;
-    const double ib = 1.0 / (gm1 * beta_ln);
+    const double ib = rcp_nr(gm1 * beta_ln);
     const double vv = 0.5 * (a_[1] * b_[1] + a_[2] * b_[2] + a_[3] * b_[3]);
     const double vnb = b_[1] * n1 + b_[2] * n2 + b_[3] * n3;
     const double frb = c[0] + c[1] * v1 + c[2] * v2 + c[3] * v3 + c[4] * (ib + vv);
