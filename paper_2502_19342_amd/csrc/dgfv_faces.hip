@@ -363,7 +363,8 @@ __device__ void gather_side(const double* blk, int side, int o, bool right, int 
 // in-place update has no cross-workgroup hazard.
 template <int NV>
 __global__ void __launch_bounds__(FACE_THREADS)
-face_vjp_kernel(MeshView m, ParamsDev prm, const double* __restrict__ u, const double* __restrict__ alpha) {
+face_vjp_kernel(MeshView m, ParamsDev prm, const double* __restrict__ u, const double* __restrict__ alpha,
+                bool skip_conforming) {
   __shared__ double sL[NV * GRID];
   __shared__ double sR[NV * GRID];
   __shared__ double sF[NV * GRID];
@@ -385,6 +386,7 @@ face_vjp_kernel(MeshView m, ParamsDev prm, const double* __restrict__ u, const d
 
   if (!(aL > 0.0) && !(aR > 0.0)) {
     if (NL == NR) {
+      if (skip_conforming) return;              // done by face_vjp_conforming_kernel
       const int n = nL, n2 = n * n;
       const int64_t baseL = m.elem_offset[eL], baseR = m.elem_offset[eR];
       for (int t = threadIdx.x; t < n2; t += blockDim.x) {
@@ -512,16 +514,81 @@ face_vjp_kernel(MeshView m, ParamsDev prm, const double* __restrict__ u, const d
   }
 }
 
+// Adjoint of face_conforming_kernel: same-degree faces between pure DG
+// elements, one lane per face node, several faces per workgroup.  In place:
+// the side-flux cotangents become the trace cotangents of both sides.
+template <int N, int NV>
+__global__ void __launch_bounds__(CONF_THREADS)
+face_vjp_conforming_kernel(MeshView m, ParamsDev prm, const int32_t* __restrict__ flist, int fcount,
+                           const double* __restrict__ u, const double* __restrict__ alpha) {
+  constexpr int NP = N + 1, NP2 = NP * NP, FPB = CONF_THREADS / NP2;
+  const int t = threadIdx.x;
+  const int slot = t / NP2, r = t - slot * NP2;
+  if (slot >= FPB) return;
+  const int fi = blockIdx.x * FPB + slot;
+  if (fi >= fcount) return;
+  const int f = flist[fi];
+  const int32_t* fc = m.faces + 5 * f;
+  const int eL = fc[0], sideL = fc[1], eR = fc[2], sideR = fc[3], o = fc[4];
+  if (alpha && (alpha[eL] > 0.0 || alpha[eR] > 0.0)) return;
+  const int p = r % NP, q = r / NP;
+  int pp, qq;
+  orient_map(o, p, q, NP, pp, qq);
+  const int64_t gL = m.elem_offset[eL] + side_node(sideL, p, q, NP);
+  const int64_t gR = m.elem_offset[eR] + side_node(sideR, pp, qq, NP);
+  const double* nrm = m.face_norm + m.face_norm_off[f];
+  double* bL = m.fside + m.side_off[eL];
+  double* bR = m.fside + m.side_off[eR];
+  double uL[NV], uR[NV], Fb[NV], uLb[NV], uRb[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    uL[v] = u[v * m.n_node + gL];
+    uR[v] = u[v * m.n_node + gR];
+    Fb[v] = bL[(sideL * NV + v) * NP2 + q * NP + p] - bR[(sideR * NV + v) * NP2 + qq * NP + pp];
+  }
+  riemann_vjp<NV>(prm.face_flux_dg, prm.volume_flux, uL, uR, nrm[r], nrm[NP2 + r], nrm[2 * NP2 + r], m.gas,
+                  Fb, uLb, uRb);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    bL[(sideL * NV + v) * NP2 + q * NP + p] = uLb[v];
+    bR[(sideR * NV + v) * NP2 + qq * NP + pp] = uRb[v];
+  }
+}
+
 }  // namespace
+
+template <int NV>
+static hipError_t launch_faces_vjp_t(const MeshView& m, const ParamsDev& p, const double* u,
+                                     const double* alpha, hipStream_t s) {
+  for (int N = 1; N <= MAXN; ++N) {
+    const int cnt = m.face_conf_count[N];
+    if (cnt == 0) continue;
+    const int np2 = (N + 1) * (N + 1), fpb = CONF_THREADS / np2;
+    const dim3 grid((cnt + fpb - 1) / fpb), block(CONF_THREADS);
+    const int32_t* fl = m.face_conf[N];
+    switch (N) {
+      case 1: hipLaunchKernelGGL((face_vjp_conforming_kernel<1, NV>), grid, block, 0, s, m, p, fl, cnt, u, alpha); break;
+      case 2: hipLaunchKernelGGL((face_vjp_conforming_kernel<2, NV>), grid, block, 0, s, m, p, fl, cnt, u, alpha); break;
+      case 3: hipLaunchKernelGGL((face_vjp_conforming_kernel<3, NV>), grid, block, 0, s, m, p, fl, cnt, u, alpha); break;
+      case 4: hipLaunchKernelGGL((face_vjp_conforming_kernel<4, NV>), grid, block, 0, s, m, p, fl, cnt, u, alpha); break;
+      case 5: hipLaunchKernelGGL((face_vjp_conforming_kernel<5, NV>), grid, block, 0, s, m, p, fl, cnt, u, alpha); break;
+      case 6: hipLaunchKernelGGL((face_vjp_conforming_kernel<6, NV>), grid, block, 0, s, m, p, fl, cnt, u, alpha); break;
+      default: hipLaunchKernelGGL((face_vjp_conforming_kernel<7, NV>), grid, block, 0, s, m, p, fl, cnt, u, alpha); break;
+    }
+    if (hipError_t e = hipGetLastError()) return e;
+  }
+  // degree jumps and FV faces, one face per workgroup
+  if (m.face_mixed_count > 0 || alpha) {
+    hipLaunchKernelGGL((face_vjp_kernel<NV>), dim3(m.n_face), dim3(FACE_THREADS), 0, s, m, p, u, alpha, true);
+    if (hipError_t e = hipGetLastError()) return e;
+  }
+  return hipSuccess;
+}
 
 hipError_t launch_faces_vjp(const MeshView& m, const ParamsDev& p, const double* u, const double* alpha,
                             hipStream_t s) {
   if (m.n_face == 0) return hipSuccess;
-  if (m.nvar == 5)
-    hipLaunchKernelGGL((face_vjp_kernel<5>), dim3(m.n_face), dim3(FACE_THREADS), 0, s, m, p, u, alpha);
-  else
-    hipLaunchKernelGGL((face_vjp_kernel<6>), dim3(m.n_face), dim3(FACE_THREADS), 0, s, m, p, u, alpha);
-  return hipGetLastError();
+  return m.nvar == 5 ? launch_faces_vjp_t<5>(m, p, u, alpha, s) : launch_faces_vjp_t<6>(m, p, u, alpha, s);
 }
 
 template <int NV>
