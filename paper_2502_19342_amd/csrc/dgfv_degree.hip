@@ -1003,38 +1003,38 @@ hipError_t element(const MeshView& m, const ParamsDev& p, const int32_t* elist, 
 // a grid of the bucket size, the workgroups past the range leaving at once:
 // its register footprint grows by half in the persistent loop form.
 template <auto KERNEL>
-int persistent_grid(int block, const MeshView& m, int count) {
+int persistent_grid(int block, const MeshView& m, int count, int share) {
   static const int per_cu = resident_per_cu(reinterpret_cast<const void*>(KERNEL), block);
-  const int g = per_cu * m.n_cu;
+  const int g = (per_cu * m.n_cu + share - 1) / share;   // the device is shared by `share` branches
   return count < g ? count : g;
 }
 
 template <int NFV>
-hipError_t fv_means_t(const MeshView& m, int count, const double* u, hipStream_t s) {
+hipError_t fv_means_t(const MeshView& m, int count, int share, const double* u, hipStream_t s) {
   if constexpr (NFV >= kN + 1) {
     if (m.nvar == 5)
       hipLaunchKernelGGL((fv_means_kernel<kN, NFV, 5>),
-                         dim3(persistent_grid<fv_means_kernel<kN, NFV, 5>>(FV2_THREADS, m, count)),
+                         dim3(persistent_grid<fv_means_kernel<kN, NFV, 5>>(FV2_THREADS, m, count, share)),
                          dim3(FV2_THREADS), 0, s, m, u);
     else
       hipLaunchKernelGGL((fv_means_kernel<kN, NFV, 6>),
-                         dim3(persistent_grid<fv_means_kernel<kN, NFV, 6>>(FV2_THREADS, m, count)),
+                         dim3(persistent_grid<fv_means_kernel<kN, NFV, 6>>(FV2_THREADS, m, count, share)),
                          dim3(FV2_THREADS), 0, s, m, u);
     return hipGetLastError();
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t fv_means(const MeshView& m, int count, const double* u, hipStream_t s) {
+hipError_t fv_means(const MeshView& m, int count, int share, const double* u, hipStream_t s) {
   if (count == 0) return hipSuccess;
   switch (m.n_fv) {
-    case 2: return fv_means_t<2>(m, count, u, s);
-    case 3: return fv_means_t<3>(m, count, u, s);
-    case 4: return fv_means_t<4>(m, count, u, s);
-    case 5: return fv_means_t<5>(m, count, u, s);
-    case 6: return fv_means_t<6>(m, count, u, s);
-    case 7: return fv_means_t<7>(m, count, u, s);
-    case 8: return fv_means_t<8>(m, count, u, s);
+    case 2: return fv_means_t<2>(m, count, share, u, s);
+    case 3: return fv_means_t<3>(m, count, share, u, s);
+    case 4: return fv_means_t<4>(m, count, share, u, s);
+    case 5: return fv_means_t<5>(m, count, share, u, s);
+    case 6: return fv_means_t<6>(m, count, share, u, s);
+    case 7: return fv_means_t<7>(m, count, share, u, s);
+    case 8: return fv_means_t<8>(m, count, share, u, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -365,8 +365,9 @@ void enqueue_rhs_impl(const dgfv_mesh* m, const ParamsDev& p, const double* u, c
   if (alpha) {
     Timed t(m, DGFV_KERNEL_FV_MEANS, s);
     hip_check(launch_blend_list(v, alpha, s), "blended list launch");
+    const int share = m->launch_mode == DGFV_LAUNCH_SERIAL ? 1 : (int)degs.size();
     fork_join(m, s, degs, [&](int N, hipStream_t ss) {
-      hip_check(ops_for(N).fv_means(v, (int)m->bucket[N].size(), u, ss), "fv_means launch");
+      hip_check(ops_for(N).fv_means(v, (int)m->bucket[N].size(), share, u, ss), "fv_means launch");
     });
   }
   {
@@ -918,7 +919,7 @@ dgfv_status dg_rhs_vjp(const dgfv_mesh* m, const dgfv_params* prm, const double*
       hip_check(launch_blend_list(v, alpha, s), "blended list launch");
       for (int N = 1; N <= MAXN; ++N)
         if (!m->bucket[N].empty())
-          hip_check(ops_for(N).fv_means(v, (int)m->bucket[N].size(), u, s), "fv_means launch");
+          hip_check(ops_for(N).fv_means(v, (int)m->bucket[N].size(), 1, u, s), "fv_means launch");
     }
     for (int b = 0; b < batch; ++b) {
       const double* wb = w + b * plane;

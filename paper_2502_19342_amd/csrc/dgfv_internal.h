@@ -85,8 +85,9 @@ struct DegreeOps {
                         const double* u, const double* alpha, double* ut, double* k, int stage,
                         double dt, double A, double B, int variant, hipStream_t s);
   // FV kernels walk this degree's range of the blended-element list (m.blend_list,
-  // m.blend_start) with `count` persistent workgroups; `count` bounds the range size
-  hipError_t (*fv_means)(const MeshView& m, int count, const double* u, hipStream_t s);
+  // m.blend_start); `count` bounds the range size.  fv_means runs persistent
+  // workgroups, a 1/share part of the device (share = concurrent degree branches)
+  hipError_t (*fv_means)(const MeshView& m, int count, int share, const double* u, hipStream_t s);
   hipError_t (*fv_residual)(const MeshView& m, const ParamsDev& p, int count, hipStream_t s);
   hipError_t (*indicator)(const MeshView& m, const ParamsDev& p, const int32_t* elist, int count,
                           const double* u, double* alpha, double* ind, hipStream_t s);

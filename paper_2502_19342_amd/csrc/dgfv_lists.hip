@@ -56,14 +56,24 @@ __global__ void __launch_bounds__(LIST_CHUNK) blend_scan_kernel(MeshView m, cons
     if (t == LIST_CHUNK - 1) carry += s[t];
     __syncthreads();
   }
-  // blended elements before the first position of each degree bucket
-  if (t >= 1 && t <= MAXN + 1) {
-    const int P = m.bucket_pos[t];
+  // blended elements before the first position of each degree bucket: the
+  // chunks before its chunk plus the part of its chunk, summed by the whole
+  // workgroup
+  for (int N = 1; N <= MAXN + 1; ++N) {
+    const int P = m.bucket_pos[N];
     const int c = P / LIST_CHUNK;
-    int before = 0;
-    for (int j = 0; j < c; ++j) before += m.chunk_cnt[j];
-    for (int i = c * LIST_CHUNK; i < P; ++i) before += blended_at(m, alpha, i) ? 1 : 0;
-    m.blend_start[t] = before;
+    int part = 0;
+    for (int j = t; j < c; j += LIST_CHUNK) part += m.chunk_cnt[j];
+    const int i = c * LIST_CHUNK + t;
+    if (i < P && blended_at(m, alpha, i)) part += 1;
+    s[t] = part;
+    __syncthreads();
+    for (int half = LIST_CHUNK / 2; half > 0; half >>= 1) {
+      if (t < half) s[t] += s[t + half];
+      __syncthreads();
+    }
+    if (t == 0) m.blend_start[N] = s[0];
+    __syncthreads();
   }
   if (t == 0) m.blend_start[0] = 0;
 }
