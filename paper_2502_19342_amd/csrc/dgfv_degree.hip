@@ -134,17 +134,20 @@ element_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const d
       partner_metric(pn, b1, b2, b3);
       double f[NV];
       FLUX::template flux_fast<NV>(me, other, ja1 + b1, ja2 + b2, ja3 + b3, m.gas, f);
-      const double c1 = sD[id * NP + mm], c2 = sD[mm * NP + id];
+      const double c1 = sD[id * NP + mm];
 #pragma unroll
       for (int v = 0; v < NV; ++v) acc[v] += c1 * f[v];
       if constexpr (in_wave) {
-        // the share for this node comes from the node at offset -o on the line
+        // the share for this node comes from the node at offset -o on the line:
+        // its flux, weighted here by D[id][mr]
         int mr = id - o;
         if (mr < 0) mr += NP;
         const int sl = (lane + (mr - id) * stride) & 63;
+        const double cr = sD[id * NP + mr];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) acc[v] += __shfl(c2 * f[v], sl);
+        for (int v = 0; v < NV; ++v) acc[v] += cr * __shfl(f[v], sl);
       } else {
+        const double c2 = sD[mm * NP + id];
         if (o > 1) __syncthreads();           // partner has read the previous round's share
 #pragma unroll
         for (int v = 0; v < NV; ++v) sInc[slot][v][pn] = c2 * f[v];
@@ -224,12 +227,12 @@ element_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const d
 #pragma unroll
       for (int v = 0; v < NV; ++v) at[v] += c1 * f[v];
       if (exchange) {
-        const double c2 = sD[mm * NP + kt];
         int mr = kt - o;
         if (mr < 0) mr += NP;
         const int sr = (lane + (mr - kt) * NP) & 63;
+        const double cr = sD[kt * NP + mr];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) at[v] += __shfl(c2 * f[v], sr);
+        for (int v = 0; v < NV; ++v) at[v] += cr * __shfl(f[v], sr);
       }
     };
 #pragma unroll 1
