@@ -611,8 +611,10 @@ indicator_kernel(MeshView m, ParamsDev prm, const int32_t* __restrict__ elist, i
 // With a_i = -(1 - alpha) w_i / J_i and the symmetry of F#,
 //   g_j = sum_d sum_{m != j} (d F#d(u_j, u_m) / d u_j)^T (2 D_jm a_j + 2 D_mj a_m),
 // evaluated per node through the flux record: the record adjoint is summed
-// over the pairs and mapped to u once (make_adj).  The lift gives the side
-// cotangents a_i / w_0 at the boundary nodes.
+// over the pairs and mapped to u once (make_adj).  As in the forward kernel the
+// pair terms use the metric sum Ja_i + Ja_m with weights D instead of the mean
+// with weights 2 D.  The lift gives the side cotangents a_i / w_0 at the
+// boundary nodes.
 // ---------------------------------------------------------------------------
 template <int N, int NV, class FLUX>
 __global__ void __launch_bounds__(Geo<N>::EPB * Geo<N>::NP3, 4)   // 4 waves per SIMD: two workgroups per CU

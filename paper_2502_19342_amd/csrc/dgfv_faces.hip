@@ -355,7 +355,8 @@ __device__ void gather_side(const double* blk, int side, int o, bool right, int 
   }
 }
 
-// Adjoint of face_kernel.  On entry fside holds, per element side, the
+// Adjoint of the face fluxes (face_body: degree-jump and FV faces; conforming
+// DG faces go to face_vjp_conforming_kernel).  On entry fside holds, per element side, the
 // cotangent of the side flux it received; fvside holds the cotangents of the
 // FV side fluxes of blended elements.  On exit fside holds the cotangents of
 // each side's nodal trace, and fvside (blended sides of FV faces) those of the
