@@ -139,7 +139,12 @@ def counter_traffic(cfg: str):
 
 
 def adjoint_ratio(gm, prm, u, dgfv, torch, reps: int = 5):
-    """t(dg_rhs_vjp, batch 1) / t(dg_rhs) on the same state, pure DG (alpha = NULL), events on one stream."""
+    """Adjoint cost against the forward, pure DG (alpha = NULL), events on one stream.
+
+    t(dg_rhs_vjp, batch 1) / t(dg_rhs); where memory allows, a batch of 32
+    cotangents per cotangent, and the reverse of a 50-step checkpointed
+    rollout (stage recompute + stage adjoints) against its forward.
+    """
     w = torch.randn_like(u)
     ut = torch.empty_like(u)
     g = torch.empty_like(u)
@@ -164,6 +169,23 @@ def adjoint_ratio(gm, prm, u, dgfv, torch, reps: int = 5):
         t32 = timed(lambda: dgfv.rhs_vjp(gm, prm, u, None, w32, out=g32), reps=2)
         rec["vjp_batch32_ms"] = t32
         rec["batch32_ratio"] = t32 / (32 * t_rhs)
+    steps = 50
+    if steps * u.numel() * 8 <= (16 << 30):           # 50 checkpointed states where they fit in 16 GiB
+        dt = 1e-4
+        u0 = u.clone().requires_grad_(True)
+        dgfv.checkpointed_rollout(u0, gm, prm, 2, dt, None).backward(w)   # warm-up (autograd, allocator)
+        torch.cuda.synchronize()
+        a, b, c = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        a.record()
+        out = dgfv.checkpointed_rollout(u0, gm, prm, steps, dt, None)
+        b.record()
+        out.backward(w)
+        c.record()
+        c.synchronize()
+        rec["rollout_steps"] = steps
+        rec["rollout_forward_ms"] = a.elapsed_time(b)
+        rec["rollout_reverse_ms"] = b.elapsed_time(c)
+        rec["rollout_ratio"] = b.elapsed_time(c) / a.elapsed_time(b)
     return rec
 
 
