@@ -100,3 +100,29 @@ def test_element_shapes_and_autotune():
     ms = c.gmesh.autotune(c.params, c.gpu(c.u), c.gpu(c.alpha))
     assert set(ms) <= {1, 2, 3, 4, 5} and all(a > 0 and b > 0 for a, b in ms.values())
     assert torch.equal(c.gpu_rhs(), out[0])
+
+
+def test_launch_mode_and_shape_arguments_are_checked():
+    announce("launch mode / shape argument checks")
+    from paper_2502_19342_amd import dgfv
+    wl = curved_mixed(n=2, nmin=2, nmax=3, scramble=49)
+    c = Case(wl, prim=smooth_state(103))
+    with pytest.raises(dgfv.DgfvError) as e:
+        c.gmesh.launch_mode(3)
+    assert e.value.status == dgfv.ERR_ARG
+    with pytest.raises(dgfv.DgfvError):
+        c.gmesh.set_element_shape(0, 0)
+    with pytest.raises(dgfv.DgfvError):
+        c.gmesh.set_element_shape(2, 2)
+    # every mode gives the same step
+    out = []
+    for mode in (dgfv.LAUNCH_SERIAL, dgfv.LAUNCH_BRANCHES, dgfv.LAUNCH_GRAPH):
+        c.gmesh.launch_mode(mode)
+        u = c.gpu(c.u)
+        k = torch.zeros_like(u)
+        for _ in range(2):
+            dgfv.rk_step(c.gmesh, c.params, 1e-4, u, k)
+        torch.cuda.synchronize()
+        out.append(u)
+    assert torch.equal(out[0], out[1]) and torch.equal(out[0], out[2])
+    c.gmesh.launch_mode(dgfv.LAUNCH_BRANCHES)
