@@ -66,8 +66,9 @@ element_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const d
 
   // The two-point fluxes are linear in the metric direction: they are evaluated
   // with the sum Ja_i + Ja_m instead of the mean, so the weights are D_im
-  // instead of 2 D_im.
-  for (int t = tid; t < NP * NP; t += blockDim.x) sD[t] = m.ops[m.tab.D[N] + t];
+  // instead of 2 D_im (times FAST_WEIGHT, where flux_fast returns a multiple
+  // of the flux).
+  for (int t = tid; t < NP * NP; t += blockDim.x) sD[t] = FLUX::FAST_WEIGHT * m.ops[m.tab.D[N] + t];
 
   const int e = elist[active ? idx : 0];
   const int64_t base = m.elem_offset[e] + node;

@@ -136,14 +136,18 @@ struct FluxRanocha {
   // rho_ln: near-equal arguments use (a+b)/2 times the reciprocal of the
   // Ismail-Roe series, 1/F(u) = 1 - u/3 - 4u^2/45 - 44u^3/945 + O(u^4), with
   // u = ((a-b)/(a+b))^2; otherwise (a-b)/(ln a - ln b).  The energy flux needs
-  // 1/beta_ln, formed directly as 2F(u)/(a+b) or (ln a - ln b)/(a-b).
+  // 1/beta_ln, formed directly as 2F(u)/(a+b) or (ln a - ln b)/(a-b).  Both
+  // arguments are positive, so u < 1e-4 is tested as |a-b| < 0.01 (a+b).
+  // flux_fast returns TWICE the flux: the arithmetic means then cost one add
+  // each, and the caller's weights carry the factor 1/2 (FAST_WEIGHT).
+  static constexpr double FAST_WEIGHT = 0.5;
   template <int NV>
   __device__ __forceinline__ static void flux_fast(const double* a_, const double* b_, double a1,
                                                    double a2, double a3, const GasDev& g, double* f) {
     double rho_ln, ibeta_ln;
     {
       const double s = a_[0] + b_[0], d = a_[0] - b_[0], dl = a_[5] - b_[5];
-      const bool small = d * d < 1e-4 * s * s;
+      const bool small = fabs(d) < 1e-2 * s;
       const double r = rcp_nr(small ? s : dl);
       const double u = (d * r) * (d * r);
       const double iF = 1.0 - u * (1.0 / 3.0 + u * (4.0 / 45.0 + u * (44.0 / 945.0)));
@@ -151,25 +155,26 @@ struct FluxRanocha {
     }
     {
       const double s = a_[6] + b_[6], d = a_[6] - b_[6], dl = a_[7] - b_[7];
-      const bool small = d * d < 1e-4 * s * s;
+      const bool small = fabs(d) < 1e-2 * s;
       const double r = rcp_nr(small ? s : d);
       const double u = (d * r) * (d * r);
       const double F = 1.0 + u * (1.0 / 3.0 + u * (0.2 + u * (1.0 / 7.0)));
       ibeta_ln = small ? 2.0 * F * r : dl * r;
     }
-    const double v1 = 0.5 * (a_[1] + b_[1]), v2 = 0.5 * (a_[2] + b_[2]), v3 = 0.5 * (a_[3] + b_[3]);
-    const double pbar = 0.5 * (a_[4] + b_[4]);
-    const double vn = v1 * a1 + v2 * a2 + v3 * a3;
-    const double fr = rho_ln * vn;
-    f[0] = fr;
-    f[1] = fr * v1 + pbar * a1;
-    f[2] = fr * v2 + pbar * a2;
-    f[3] = fr * v3 + pbar * a3;
-    const double vv = 0.5 * (a_[1] * b_[1] + a_[2] * b_[2] + a_[3] * b_[3]);
+    // normal velocities of both states; 2 vn = vna + vnb
     const double vna = a_[1] * a1 + a_[2] * a2 + a_[3] * a3;
     const double vnb = b_[1] * a1 + b_[2] * a2 + b_[3] * a3;
+    const double f0 = rho_ln * (vna + vnb);      // 2 rho_ln vn
+    const double fr = 0.5 * f0;                   // rho_ln vn
+    const double sp = a_[4] + b_[4];              // 2 pbar
+    f[0] = f0;
+    f[1] = fr * (a_[1] + b_[1]) + sp * a1;        // 2 (rho_ln vn v1 + pbar a1)
+    f[2] = fr * (a_[2] + b_[2]) + sp * a2;
+    f[3] = fr * (a_[3] + b_[3]) + sp * a3;
+    const double vab = a_[1] * b_[1] + a_[2] * b_[2] + a_[3] * b_[3];
     const double igm1 = 1.0 / (g.gamma - 1.0);
-    f[4] = fr * (ibeta_ln * igm1 + vv) + 0.5 * (a_[4] * vnb + b_[4] * vna);
+    // 2 [rho_ln vn (1/((gamma-1) beta_ln) + vab/2) + (p_a vnb + p_b vna)/2]
+    f[4] = f0 * (ibeta_ln * igm1) + fr * vab + (a_[4] * vnb + b_[4] * vna);
   }
   template <int NV, class S>
   __device__ __forceinline__ static void flux(const S* a_, const S* b_, double a1, double a2,
@@ -288,6 +293,7 @@ __device__ __forceinline__ void prim_adj(const double* u, const GasDev& g, doubl
 // Pirozzoli's kinetic-energy-preserving flux (Section 3.5); f_rhoY = f_rho {Y}.
 struct FluxPirozzoli {
   static constexpr int NA = 7;  // rho, v1, v2, v3, p, H, Y
+  static constexpr double FAST_WEIGHT = 1.0;   // flux_fast is the flux itself
   template <int NV>
   __device__ __forceinline__ static void flux_fast(const double* a_, const double* b_, double a1,
                                                    double a2, double a3, const GasDev& g, double* f) {
@@ -352,6 +358,7 @@ struct FluxPirozzoli {
 // Arithmetic mean of the physical fluxes.
 struct FluxCentral {
   static constexpr int NA = 7;  // rho, v1, v2, v3, p, E, Y
+  static constexpr double FAST_WEIGHT = 1.0;   // flux_fast is the flux itself
   template <int NV>
   __device__ __forceinline__ static void flux_fast(const double* a_, const double* b_, double a1,
                                                    double a2, double a3, const GasDev& g, double* f) {
