@@ -260,7 +260,7 @@ def main():
         torch.cuda.synchronize()
     kt = {name: gm.kernel_time(kid) for name, kid in
           (("element", dgfv.KERNEL_ELEMENT), ("face", dgfv.KERNEL_FACE), ("fv_means", dgfv.KERNEL_FV_MEANS),
-           ("fv_residual", dgfv.KERNEL_FV_RESIDUAL))}
+           ("fv_face", dgfv.KERNEL_FV_FACE), ("fv_residual", dgfv.KERNEL_FV_RESIDUAL))}
     gm.profile(False)
     if not torch.isfinite(u).all():
         print("bench.py: non-finite state after the timed steps", file=sys.stderr)
@@ -303,6 +303,8 @@ def main():
                      "bytes_per_launch": byts, "avg_launch_ms": 1e3 * avg_el_s},
         "kernel_ms_per_stage": {kname: v[0] / max(1, v[1]) for kname, v in kt.items()},
         "kernel_ms_source": "live events over the timed steps" if live else "profiled steps after the timed region",
+        "kernel_ms_note": "phases in order: fv_means, face, fv_residual, element; fv_face lies inside face "
+                          "(beside the DG face fluxes outside --launch serial)",
         "adjoint_forward_ratio": adjoint,
     }
     if not args.no_cpu_baseline:

@@ -201,18 +201,20 @@ dgfv_status dg_rhs_vjp(const dgfv_mesh* mesh, const dgfv_params* params, const d
 /*
  * Kernel timing with HIP events (measurement support, not part of the method).
  * dgfv_profile_enable(mesh, 1) clears the counters and makes every later call
- * on the mesh record an event pair around each launch of the kernels below,
- * on the caller's stream; 0 stops recording.  dgfv_profile_read synchronises
- * the recorded events and returns the summed duration (ms) and the launch
- * count of one kernel class.
+ * on the mesh record an event pair around each phase below, on the stream the
+ * phase runs on; 0 stops recording.  dgfv_profile_read synchronises the
+ * recorded events and returns the summed duration (ms) and the count of one
+ * class.  FV_FACE lies inside the FACE interval (in the concurrent launch
+ * modes it runs beside the DG face fluxes).
  */
-enum { DGFV_KERNEL_ELEMENT = 0, /* volume + lift + blend (+ RK update), all degree buckets */
-       DGFV_KERNEL_FACE = 1,    /* interface fluxes                                      */
-       DGFV_KERNEL_FV_MEANS = 2,
-       DGFV_KERNEL_FV_RESIDUAL = 3,
+enum { DGFV_KERNEL_ELEMENT = 0,     /* volume + lift + blend (+ RK update), all degree buckets   */
+       DGFV_KERNEL_FACE = 1,        /* face phase: every interface flux                          */
+       DGFV_KERNEL_FV_MEANS = 2,    /* blended list + sub-cell means                             */
+       DGFV_KERNEL_FV_RESIDUAL = 3, /* FV sub-cell residuals                                     */
        DGFV_KERNEL_INDICATOR = 4,
        DGFV_KERNEL_VJP = 5,
-       DGFV_KERNEL_COUNT = 6 };
+       DGFV_KERNEL_FV_FACE = 6,     /* fluxes of the faces with a blended side                   */
+       DGFV_KERNEL_COUNT = 7 };
 dgfv_status dgfv_profile_enable(dgfv_mesh* mesh, int enable);
 dgfv_status dgfv_profile_read(dgfv_mesh* mesh, int kernel, double* total_ms, int64_t* launches);
 

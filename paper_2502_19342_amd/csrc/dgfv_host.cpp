@@ -296,7 +296,7 @@ struct Timed {
   hipStream_t s;
   hipEvent_t stop = nullptr;
   Timed(const dgfv_mesh* mesh, int k, hipStream_t st) : m(mesh), kind(k), s(st) {
-    if (!m->profile) return;
+    if (!m->profile || k < 0) return;             // k < 0: not timed
     auto& list = m->ev[kind];
     size_t& used = m->ev_used[kind];
     if (used == list.size()) {
@@ -376,6 +376,7 @@ void enqueue_rhs_impl(const dgfv_mesh* m, const ParamsDev& p, const double* u, c
     for (int c = 1; c < FACE_CLASS_COUNT; ++c)
       if (face_class_present(v, alpha, c)) classes.push_back(c);
     fork_join(m, s, classes, [&](int c, hipStream_t ss) {
+      Timed tf(m, c == FACE_CLASS_FV ? DGFV_KERNEL_FV_FACE : -1, ss);
       hip_check(launch_face_class(v, p, u, alpha, c, ss), "face launch");
     });
   }
