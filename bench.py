@@ -74,17 +74,25 @@ def initial_state_device(gm, wl, dgfv, torch, chunk=1 << 23):
     return u
 
 
-def element_kernel_bytes(wl, n_dof: int, n_elem_by_deg: dict, blended_dofs: int, stage: int) -> float:
+def element_kernel_bytes(wl, degree: np.ndarray, alpha: np.ndarray, stage: int) -> float:
     """Algorithmic HBM bytes of one element-kernel launch (all buckets of one stage).
 
-    Per node: u read + write, k read (not at stage 1) + write, 9 metric terms
-    and J; per element 6 (N+1)^2 nvar side fluxes; per blended node the FV
-    residual (nvar).
+    Per node: u read + write, k read (not at stage 1) + write; per blended node
+    (alpha > 0) the FV residual (nvar).  Except on pure FV elements (alpha = 1
+    at degrees with one element per workgroup, N >= 6, whose DG part is not
+    evaluated): per node the 9 metric terms and J, per element the 6 (N+1)^2
+    nvar side fluxes.
     """
     nv = wl.n_var
-    per_node = 8 * (2 * nv + (nv if stage > 1 else 0) + nv + 10)
-    side = sum(8 * 6 * (N + 1) ** 2 * nv * cnt for N, cnt in n_elem_by_deg.items())
-    return float(per_node * n_dof + side + 8 * nv * blended_dofs)
+    npe = (degree.astype(np.int64) + 1) ** 3
+    fv_only = (alpha >= 1.0) & (degree >= 6)
+    dg = ~fv_only
+    per_node = 8 * (2 * nv + (nv if stage > 1 else 0) + nv)
+    total = per_node * npe.sum()
+    total += 8 * 10 * npe[dg].sum()
+    total += 8 * 6 * ((degree[dg].astype(np.int64) + 1) ** 2).sum() * nv
+    total += 8 * nv * npe[alpha > 0].sum()
+    return float(total)
 
 
 def cpu_baseline(cfg: str, n: int, seed: int):
@@ -223,8 +231,6 @@ def main():
         alpha, _ = dgfv.indicator(gm, prm, u)
         mask = alpha.cpu().numpy() > 0
     tune = gm.autotune(prm, u, alpha)            # element-kernel tile shape per degree
-    npe = (wl.mesh.degree.astype(np.int64) + 1) ** 3
-    blended_dofs = int(npe[mask].sum())
     dt = 1e-5
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup
@@ -271,7 +277,8 @@ def main():
     value = n_dof * stages / el
     el_ms, el_n = kt["element"]
     avg_el_s = el_ms / el_n / 1e3
-    byts = np.mean([element_kernel_bytes(wl, n_dof, n_by_deg, blended_dofs, s) for s in range(1, 6)])
+    alpha_h = alpha.cpu().numpy()
+    byts = np.mean([element_kernel_bytes(wl, np.asarray(wl.mesh.degree), alpha_h, s) for s in range(1, 6)])
     achieved = byts / avg_el_s / 1e9
     rec = {
         "metric": METRIC,

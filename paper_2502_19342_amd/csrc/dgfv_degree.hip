@@ -75,6 +75,40 @@ element_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const d
   double uo[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) uo[v] = u[v * m.n_node + base];
+
+  // stage 0: ut = R; stage s: k <- A k + dt R (k not read at stage 1), u <- u + B k
+  auto store = [&](const double* R, const double* k_old) {
+    if (stage == 0) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) ut[v * m.n_node + base] = R[v];
+    } else {
+      double* uw = const_cast<double*>(u);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const int64_t g = v * m.n_node + base;
+        const double kv = (stage == 1) ? dt * R[v] : A * k_old[v] + dt * R[v];
+        k[g] = kv;
+        uw[g] = uo[v] + B * kv;
+      }
+    }
+  };
+  const double al = alpha ? alpha[e] : 0.0;
+  if constexpr (EPB == 1) {
+    // alpha = 1: a pure FV element.  The DG part has weight 0, so R = R^FV
+    // exactly and none of it is evaluated (one element per workgroup: the
+    // branch is uniform and comes before every barrier).
+    if (al >= 1.0) {
+      if (!active) return;
+      double R[NV], k_old[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        R[v] = m.rfv[v * m.n_node + base];
+        k_old[v] = stage > 1 ? k[v * m.n_node + base] : 0.0;
+      }
+      store(R, k_old);
+      return;
+    }
+  }
   {
     const Prim q = cons2prim<NV>(uo, m.gas);
     double r[NA];
@@ -278,25 +312,11 @@ element_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const d
 #pragma unroll
   for (int v = 0; v < NV; ++v) R[v] = -acc[v] * invJ;
 
-  const double al = alpha ? alpha[e] : 0.0;
   if (al > 0.0) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) R[v] = (1.0 - al) * R[v] + al * m.rfv[v * m.n_node + base];
   }
-
-  if (stage == 0) {
-#pragma unroll
-    for (int v = 0; v < NV; ++v) ut[v * m.n_node + base] = R[v];
-  } else {
-    double* uw = const_cast<double*>(u);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const int64_t g = v * m.n_node + base;
-      const double kv = (stage == 1) ? dt * R[v] : A * k_old[v] + dt * R[v];
-      k[g] = kv;
-      uw[g] = uo[v] + B * kv;
-    }
-  }
+  store(R, k_old);
 }
 
 // ---------------------------------------------------------------------------
