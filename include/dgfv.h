@@ -151,6 +151,21 @@ dgfv_status dg_rk_step(const dgfv_mesh* mesh, const dgfv_params* params, double 
                        double* k_d, const double* alpha_d, void* stream);
 
 /*
+ * Non-physical states (failure detection, not part of the method).  The
+ * element kernels of dg_rhs, dg_rk_stage and dg_rk_step set a flag of the mesh
+ * when a node of the state they read has rho <= 0, p <= 0 or a NaN in either
+ * (the RK stages read the previous stage's output, so a bad step shows in the
+ * next call).  Each of these calls then copies the flag to pinned host memory
+ * behind an event on its stream, without waiting.  A later call on the mesh
+ * whose predecessor's copy has completed returns DGFV_ERR_STATE, clears the
+ * flag, and enqueues nothing; the caller decides (e.g. a smaller dt from a
+ * stored state).  Nothing is copied while the caller captures the stream.
+ * dgfv_check_state synchronises `stream`, returns DGFV_ERR_STATE if the flag
+ * is set (and clears it), else DGFV_OK.
+ */
+dgfv_status dgfv_check_state(dgfv_mesh* mesh, void* stream);
+
+/*
  * Launch batching (not part of the method).  Within each phase of an
  * evaluation (sub-cell means, face fluxes, FV residuals, element kernels) the
  * launches of the different degree buckets and face classes are independent.

@@ -99,6 +99,8 @@ element_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const d
     // branch is uniform and comes before every barrier).
     if (al >= 1.0) {
       if (!active) return;
+      const Prim q = cons2prim<NV>(uo, m.gas);
+      if (!(q.rho > 0.0) || !(q.p > 0.0)) m.state_flag[0] = 1;   // rho <= 0, p <= 0 or NaN
       double R[NV], k_old[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
@@ -111,6 +113,7 @@ element_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const d
   }
   {
     const Prim q = cons2prim<NV>(uo, m.gas);
+    if (!(q.rho > 0.0) || !(q.p > 0.0)) m.state_flag[0] = 1;     // rho <= 0, p <= 0 or NaN
     double r[NA];
     FLUX::template make<NV>(q, r);
 #pragma unroll

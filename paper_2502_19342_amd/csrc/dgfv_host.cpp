@@ -124,6 +124,13 @@ struct dgfv_mesh {
   hipStream_t cap_stream = nullptr;
   mutable std::vector<std::pair<GraphKey, hipGraphExec_t>> graph_cache;
 
+  // non-physical state: the element kernels set view.state_flag; each RHS or RK
+  // call copies it to pinned host memory behind an event, and a later call
+  // reports it once that copy has landed (mutable: bookkeeping only)
+  int32_t* flag_host = nullptr;
+  hipEvent_t flag_ev = nullptr;
+  mutable bool flag_pending = false;
+
   // kernel timing (mutable: recording does not change the mesh)
   mutable bool profile = false;
   mutable std::array<std::vector<std::pair<hipEvent_t, hipEvent_t>>, DGFV_KERNEL_COUNT> ev;
@@ -139,6 +146,8 @@ struct dgfv_mesh {
       if (st) (void)hipStreamDestroy(st);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     if (fork_ev) (void)hipEventDestroy(fork_ev);
+    if (flag_ev) (void)hipEventDestroy(flag_ev);
+    if (flag_host) (void)hipHostFree(flag_host);
     for (hipEvent_t e : join_ev)
       if (e) (void)hipEventDestroy(e);
     for (auto& list : ev)
@@ -462,11 +471,62 @@ dgfv_status run_stages(const dgfv_mesh* m, const dgfv_params* prm, int kind, int
   return DGFV_OK;
 }
 
+bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone;
+}
+
+// A non-physical state seen by an earlier call whose flag copy has landed:
+// DGFV_ERR_STATE, reported once (the flag is cleared).  Never blocks; a copy
+// still in flight is looked at by a later call.
+dgfv_status state_seen(const dgfv_mesh* m, hipStream_t s) {
+  if (!m->flag_pending || capturing(s)) return DGFV_OK;
+  if (hipEventQuery(m->flag_ev) != hipSuccess) return DGFV_OK;
+  m->flag_pending = false;
+  if (*m->flag_host == 0) return DGFV_OK;
+  *m->flag_host = 0;
+  if (hipMemsetAsync(m->view.state_flag, 0, sizeof(int32_t), s) != hipSuccess)
+    return fail(DGFV_ERR_HIP, "hipMemsetAsync of the state flag");
+  return fail(DGFV_ERR_STATE, "an earlier call read a state with rho <= 0, p <= 0 or NaN");
+}
+
+// After a call: copy the flag to pinned host memory behind an event (not
+// while the caller captures the stream; dgfv_check_state covers that case).
+dgfv_status state_post(const dgfv_mesh* m, hipStream_t s) {
+  if (capturing(s)) return DGFV_OK;
+  if (hipMemcpyAsync(m->flag_host, m->view.state_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipEventRecord(m->flag_ev, s) != hipSuccess)
+    return fail(DGFV_ERR_HIP, "copy of the state flag");
+  m->flag_pending = true;
+  return DGFV_OK;
+}
+
+// state check, the call, then the flag copy
+template <class F>
+dgfv_status guarded(const dgfv_mesh* m, hipStream_t s, F&& call) {
+  if (dgfv_status st = state_seen(m, s)) return st;
+  if (dgfv_status st = call()) return st;
+  return state_post(m, s);
+}
+
 }  // namespace
 
 extern "C" {
 
 const char* dgfv_last_error(void) { return g_last_error.c_str(); }
+
+dgfv_status dgfv_check_state(dgfv_mesh* m, void* stream) {
+  if (!m) return fail(DGFV_ERR_ARG, "NULL argument");
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return fail(DGFV_ERR_HIP, "hipStreamSynchronize");
+  int32_t h = 0;
+  if (hipMemcpy(&h, m->view.state_flag, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(DGFV_ERR_HIP, "hipMemcpy of the state flag");
+  m->flag_pending = false;
+  *m->flag_host = 0;
+  if (h == 0) return DGFV_OK;
+  if (hipMemset(m->view.state_flag, 0, sizeof(int32_t)) != hipSuccess) return fail(DGFV_ERR_HIP, "hipMemset");
+  return fail(DGFV_ERR_STATE, "a state with rho <= 0, p <= 0 or NaN was read since the last check");
+}
 
 dgfv_status dgfv_mesh_create(const dgfv_mesh_desc* d, dgfv_mesh** out) {
   if (!d || !out) return fail(DGFV_ERR_ARG, "NULL argument");
@@ -703,6 +763,11 @@ dgfv_status dgfv_mesh_create(const dgfv_mesh_desc* d, dgfv_mesh** out) {
       v.chunk_off = m->keep(dev_alloc<int32_t>(v.n_chunk));
       v.blend_list = m->keep(dev_alloc<int32_t>(m->K));
       v.blend_start = m->keep(dev_alloc<int32_t>(MAXN + 2));
+      v.state_flag = m->keep(dev_alloc<int32_t>(1));
+      hip_check(hipMemset(v.state_flag, 0, sizeof(int32_t)), "hipMemset");
+      hip_check(hipHostMalloc((void**)&m->flag_host, sizeof(int32_t), hipHostMallocDefault), "hipHostMalloc");
+      *m->flag_host = 0;
+      hip_check(hipEventCreateWithFlags(&m->flag_ev, hipEventDisableTiming), "hipEventCreate");
       int dev = 0, cus = 0;
       hip_check(hipGetDevice(&dev), "hipGetDevice");
       hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
@@ -767,7 +832,8 @@ dgfv_status dg_rhs(const dgfv_mesh* m, const dgfv_params* prm, const double* u, 
   if (!m || !u || !ut) return fail(DGFV_ERR_ARG, "NULL argument");
   if (u == ut) return fail(DGFV_ERR_ARG, "u and ut must not overlap");
   if (dgfv_status st = check_params(m, prm)) return st;
-  return enqueue_rhs(m, prm, u, alpha, ut, nullptr, 0, 0.0, (hipStream_t)stream);
+  hipStream_t s = (hipStream_t)stream;
+  return guarded(m, s, [&] { return enqueue_rhs(m, prm, u, alpha, ut, nullptr, 0, 0.0, s); });
 }
 
 dgfv_status dg_rk_stage(const dgfv_mesh* m, const dgfv_params* prm, int stage, double dt, double* u,
@@ -777,7 +843,8 @@ dgfv_status dg_rk_stage(const dgfv_mesh* m, const dgfv_params* prm, int stage, d
   if (!std::isfinite(dt)) return fail(DGFV_ERR_ARG, "dt must be finite");
   if (u == k) return fail(DGFV_ERR_ARG, "u and k must not overlap");
   if (dgfv_status st = check_params(m, prm)) return st;
-  return run_stages(m, prm, 0, stage, stage, dt, u, k, alpha, (hipStream_t)stream);
+  hipStream_t s = (hipStream_t)stream;
+  return guarded(m, s, [&] { return run_stages(m, prm, 0, stage, stage, dt, u, k, alpha, s); });
 }
 
 dgfv_status dg_rk_step(const dgfv_mesh* m, const dgfv_params* prm, double dt, double* u, double* k,
@@ -786,7 +853,8 @@ dgfv_status dg_rk_step(const dgfv_mesh* m, const dgfv_params* prm, double dt, do
   if (!std::isfinite(dt)) return fail(DGFV_ERR_ARG, "dt must be finite");
   if (u == k) return fail(DGFV_ERR_ARG, "u and k must not overlap");
   if (dgfv_status st = check_params(m, prm)) return st;
-  return run_stages(m, prm, 1, 1, 5, dt, u, k, alpha, (hipStream_t)stream);
+  hipStream_t s = (hipStream_t)stream;
+  return guarded(m, s, [&] { return run_stages(m, prm, 1, 1, 5, dt, u, k, alpha, s); });
 }
 
 dgfv_status dgfv_autotune(dgfv_mesh* m, const dgfv_params* prm, const double* u, const double* alpha,

@@ -70,6 +70,7 @@ struct MeshView {
   int32_t* blend_list;          // [K] blended elements, in `order` order
   int32_t* blend_start;         // [MAXN + 2] blend_list range of degree N: [start[N], start[N + 1])
   int n_cu;                     // compute units of the device (persistent grid sizes)
+  int32_t* state_flag;          // [1] set to 1 by an element kernel that reads rho <= 0, p <= 0 or NaN
   const double* ops;            // operator tables
   OpTables tab;
   GasDev gas;

@@ -42,7 +42,7 @@ class _Params(ctypes.Structure):
 
 EXPORTED = ("dgfv_mesh_create", "dgfv_mesh_destroy", "dgfv_mesh_info", "dgfv_mesh_node_coords",
             "dg_indicator", "dg_rhs", "dg_rk_stage", "dg_rk_step", "dg_rhs_vjp", "dgfv_set_launch_mode", "dgfv_autotune",
-            "dgfv_set_element_shape",
+            "dgfv_set_element_shape", "dgfv_check_state",
             "dgfv_profile_enable", "dgfv_profile_read", "dgfv_last_error")
 KERNEL_ELEMENT, KERNEL_FACE, KERNEL_FV_MEANS, KERNEL_FV_RESIDUAL, KERNEL_INDICATOR, KERNEL_VJP, KERNEL_FV_FACE = range(7)
 LAUNCH_SERIAL, LAUNCH_BRANCHES, LAUNCH_GRAPH = range(3)
@@ -224,6 +224,12 @@ def rk_step(mesh: Mesh, params: Params, dt: float, u: torch.Tensor, k: torch.Ten
     """In-place five-stage 2N Runge-Kutta step (``dg_rk_step``)."""
     _check(_lib.dg_rk_step(mesh._h, ctypes.byref(params.c()), float(dt), mesh._state(u, "u"),
                            mesh._state(k, "k"), mesh._alpha(alpha), _stream(stream)))
+
+
+def check_state(mesh: Mesh, stream=None) -> None:
+    """Raise DgfvError(ERR_STATE) if a state with rho <= 0, p <= 0 or NaN was read
+    since the last report (``dgfv_check_state``; synchronises the stream)."""
+    _check(_lib.dgfv_check_state(mesh._h, _stream(stream)))
 
 
 def indicator(mesh: Mesh, params: Params, u: torch.Tensor, stream=None):

@@ -73,3 +73,38 @@ def test_ragged_degree_buckets():
     assert (counts > 0).sum() >= 5                 # several buckets, most far from a full workgroup
     c.alpha = seeded_alpha(c.mesh.K, 36, values=(0.0, 0.0, 1.0))
     assert rel_err(c.gpu_rhs(), c.oracle_rhs()) <= rhs_tol(c)
+
+
+def test_nonphysical_state_is_reported():
+    """rho <= 0 in the state read by an RK stage: DGFV_ERR_STATE from the next call once the
+    flag copy has landed (DG elements and pure FV elements at N >= 6), and from dgfv_check_state."""
+    announce("non-physical state flag")
+    from paper_2502_19342_amd import dgfv
+    wl = curved_mixed(n=2, nmin=6, nmax=7, scramble=37, metric_degree=1, n_fv=8)
+    c = Case(wl, prim=smooth_state(95), noise=1e-3, seed=15)
+    dt = 1e-5
+    u, k = c.gpu(c.u), torch.zeros_like(c.gpu(c.u))
+    dgfv.rk_step(c.gmesh, c.params, dt, u, k, None)
+    torch.cuda.synchronize()
+    dgfv.rk_step(c.gmesh, c.params, dt, u, k, None)     # sees the first step's copy: clean
+    dgfv.check_state(c.gmesh)
+    node = int(c.gmesh.elem_offset[3]) + 5               # a node of element 3
+    for alpha in (None, torch.ones(c.mesh.K, dtype=T, device="cuda")):
+        u, k = c.gpu(c.u), torch.zeros_like(c.gpu(c.u))
+        u[0, node] = -1.0
+        dgfv.rk_stage(c.gmesh, c.params, 1, dt, u, k, alpha)
+        torch.cuda.synchronize()
+        with pytest.raises(dgfv.DgfvError) as err:
+            dgfv.rk_stage(c.gmesh, c.params, 2, dt, u, k, alpha)
+        assert err.value.status == dgfv.ERR_STATE
+        dgfv.check_state(c.gmesh)                        # reported once, then cleared
+    u = c.gpu(c.u)
+    u[4, node] = float("nan")
+    dgfv.rhs(c.gmesh, c.params, u, None)
+    with pytest.raises(dgfv.DgfvError) as err:
+        dgfv.check_state(c.gmesh)
+    assert err.value.status == dgfv.ERR_STATE
+    dgfv.check_state(c.gmesh)
+    r = dgfv.rhs(c.gmesh, c.params, c.gpu(c.u), None)   # a good state again: no report
+    dgfv.check_state(c.gmesh)
+    assert rel_err(r.cpu(), c.oracle_rhs()) <= 1e-12
