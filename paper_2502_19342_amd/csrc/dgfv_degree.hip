@@ -454,6 +454,7 @@ fv_residual_kernel(MeshView m, ParamsDev prm) {
   static_assert(S3 <= FV2_THREADS, "one thread per sub-cell");
   __shared__ double sU[NV * S3];
   __shared__ double sG[NV * S3];
+  __shared__ double sF[6 * NV * S2];           // the six sides' FV fluxes
   __shared__ double sVp[NP * NFV];
   const int t = threadIdx.x;
   const double h = 2.0 / NFV;
@@ -462,12 +463,27 @@ fv_residual_kernel(MeshView m, ParamsDev prm) {
   if (w >= m.blend_start[N + 1]) return;
   const int e = m.blend_list[w];
   const int64_t base = m.elem_offset[e];
+  // every global read of the element is issued here, ahead of the first barrier:
+  // the sub-cell means and side fluxes into LDS, this thread's sub-face normals
+  // and J into registers
   const double* ub = m.ubar + (size_t)e * NV * S3;
   for (int r = t; r < NV * S3; r += FV2_THREADS) sU[r] = ub[r];
-  const double* nrm = m.fvnorm + (size_t)e * 9 * NIF;
   const double* fvs = m.fvside + (size_t)e * 6 * NV * S2;
+  for (int r = t; r < 6 * NV * S2; r += FV2_THREADS) sF[r] = fvs[r];
+  const double* nrm = m.fvnorm + (size_t)e * 9 * NIF;
   const bool active = t < S3;
   const int s0 = t % NFV, s1 = (t / NFV) % NFV, s2 = t / S2;
+  double nd[3][3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int sd = d == 0 ? s0 : (d == 1 ? s1 : s2);
+    const int ta = d == 2 ? s1 : s2, tb = d == 0 ? s1 : s0;
+    const int k = (sd * NFV + ta) * NFV + tb;
+    const bool has = active && sd < NFV - 1;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) nd[d][c] = has ? nrm[(d * 3 + c) * NIF + k] : 0.0;
+  }
+  const double Jn = t < NP3 ? m.metric[9 * m.n_node + base + t] : 1.0;
   double dC[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) dC[v] = 0.0;
@@ -485,9 +501,7 @@ fv_residual_kernel(MeshView m, ParamsDev prm) {
         uL[v] = sU[v * S3 + t];
         uR[v] = sU[v * S3 + t + stride];
       }
-      const int k = (sd * NFV + ta) * NFV + tb;
-      riemann<NV>(prm.face_flux_fv, prm.volume_flux, uL, uR, nrm[(d * 3 + 0) * NIF + k],
-                  nrm[(d * 3 + 1) * NIF + k], nrm[(d * 3 + 2) * NIF + k], m.gas, F);
+      riemann<NV>(prm.face_flux_fv, prm.volume_flux, uL, uR, nd[d][0], nd[d][1], nd[d][2], m.gas, F);
 #pragma unroll
       for (int v = 0; v < NV; ++v) sG[v * S3 + t] = F[v];
     }
@@ -495,8 +509,8 @@ fv_residual_kernel(MeshView m, ParamsDev prm) {
     if (active) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        const double hi = sd < NFV - 1 ? sG[v * S3 + t] : fvs[((2 * d + 1) * NV + v) * S2 + fidx];
-        const double lo = sd > 0 ? sG[v * S3 + t - stride] : -fvs[((2 * d) * NV + v) * S2 + fidx];
+        const double hi = sd < NFV - 1 ? sG[v * S3 + t] : sF[((2 * d + 1) * NV + v) * S2 + fidx];
+        const double lo = sd > 0 ? sG[v * S3 + t - stride] : -sF[((2 * d) * NV + v) * S2 + fidx];
         dC[v] -= hi - lo;
       }
     }
@@ -534,7 +548,8 @@ fv_residual_kernel(MeshView m, ParamsDev prm) {
 #pragma unroll
     for (int c = 0; c < NFV; ++c) acc += sVp[k * NFV + c] * src[c * NP * NP];
     const int node = k * NP * NP + ij;
-    m.rfv[v * m.n_node + base + node] = acc * ih3 / m.metric[9 * m.n_node + base + node];
+    const double J = node == t ? Jn : m.metric[9 * m.n_node + base + node];
+    m.rfv[v * m.n_node + base + node] = acc * ih3 / J;
   }
 }
 
