@@ -142,6 +142,77 @@ __device__ void map2d_side(double* dst_block, const double* src, const double* A
   }
 }
 
+// Separable (two-pass) forms of the same maps, for one-wave workgroups whose
+// barriers are free: pass 1 contracts p into T[f][q][pp] (nin rows of nout),
+// pass 2 contracts q.  The sums are those of MapRows::apply in the same order
+// (inner over p, outer over q), at nin + nout instead of nin^2 + nin products
+// per output point and field.  T must alias neither src nor dst; one workgroup
+// barrier inside, the caller synchronises around the call.
+template <int NF>
+__device__ void map2d_pass1(const double* src, double* T, const double* A, int nout, int nin) {
+  for (int t = threadIdx.x; t < nin * nout; t += blockDim.x) {
+    const int pp = t % nout, q = t / nout;
+    double a[MAXN + 1];
+#pragma unroll
+    for (int p = 0; p <= MAXN; ++p) a[p] = p < nin ? A[pp * nin + p] : 0.0;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const double* row = src + f * GRID + q * nin;
+      double acc = 0.0;
+#pragma unroll
+      for (int p = 0; p <= MAXN; ++p)
+        if (p < nin) acc += a[p] * row[p];
+      T[f * GRID + t] = acc;
+    }
+  }
+}
+
+template <int NF>
+__device__ void map2d_sep_to(const double* src, double* T, double* dst, const double* A, int nout, int nin) {
+  map2d_pass1<NF>(src, T, A, nout, nin);
+  __syncthreads();
+  for (int t = threadIdx.x; t < nout * nout; t += blockDim.x) {
+    const int pp = t % nout, qq = t / nout;
+    double a[MAXN + 1];
+#pragma unroll
+    for (int q = 0; q <= MAXN; ++q) a[q] = q < nin ? A[qq * nin + q] : 0.0;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const double* col = T + f * GRID + pp;
+      double acc = 0.0;
+#pragma unroll
+      for (int q = 0; q <= MAXN; ++q)
+        if (q < nin) acc += a[q] * col[q * nout];
+      dst[f * GRID + t] = acc;
+    }
+  }
+}
+
+template <int NV>
+__device__ void map2d_sep_side(double* dst_block, const double* src, double* T, const double* A, int nout,
+                               int nin, int side, int o, bool right, double scale) {
+  map2d_pass1<NV>(src, T, A, nout, nin);
+  __syncthreads();
+  const int n2 = nout * nout;
+  for (int t = threadIdx.x; t < n2; t += blockDim.x) {
+    const int pp = t % nout, qq = t / nout;
+    int p = pp, q = qq;
+    if (right) orient_map(o, pp, qq, nout, p, q);
+    double a[MAXN + 1];
+#pragma unroll
+    for (int c = 0; c <= MAXN; ++c) a[c] = c < nin ? A[qq * nin + c] : 0.0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const double* col = T + v * GRID + pp;
+      double acc = 0.0;
+#pragma unroll
+      for (int c = 0; c <= MAXN; ++c)
+        if (c < nin) acc += a[c] * col[c * nout];
+      dst_block[(side * NV + v) * n2 + q * nout + p] = scale * acc;
+    }
+  }
+}
+
 // One face, any class, by the whole (64-lane) workgroup, with three
 // workgroup barriers; B0..B3 are [NV][GRID] and sN, sNF [3][GRID] LDS arrays
 // of the caller.  Degree-jump and FV faces need them; conforming DG faces
@@ -187,14 +258,15 @@ __device__ void face_body(const MeshView& m, const ParamsDev& prm, const double*
       return;
     }
     // degree jump: both traces at the common degree M, flux there, the lower
-    // side receives the L2 projection
+    // side receives the L2 projection (two-pass maps; exactly one side is lower,
+    // and the buffers the other side leaves free serve as their scratch)
     gather_trace<NV>(m, u, eL, sideL, o, false, nL, B0);
     gather_trace<NV>(m, u, eR, sideR, o, true, nR, B1);
     __syncthreads();
     const double* LM = B0;
     const double* RM = B1;
-    if (NL < M) { map2d_to<NV>(B0, B2, m.ops + m.tab.interp[NL][M], nM, nL); LM = B2; }
-    if (NR < M) { map2d_to<NV>(B1, B3, m.ops + m.tab.interp[NR][M], nM, nR); RM = B3; }
+    if (NL < M) { map2d_sep_to<NV>(B0, B3, B2, m.ops + m.tab.interp[NL][M], nM, nL); LM = B2; }
+    if (NR < M) { map2d_sep_to<NV>(B1, B2, B3, m.ops + m.tab.interp[NR][M], nM, nR); RM = B3; }
     __syncthreads();
     double* F = NL < M ? B0 : B2;
     const int n2 = nM * nM;
@@ -217,8 +289,8 @@ __device__ void face_body(const MeshView& m, const ParamsDev& prm, const double*
       }
     }
     __syncthreads();
-    if (NL < M) map2d_side<NV>(bL, F, m.ops + m.tab.project[M][NL], nL, nM, sideL, o, false, 1.0);
-    if (NR < M) map2d_side<NV>(bR, F, m.ops + m.tab.project[M][NR], nR, nM, sideR, o, true, -1.0);
+    if (NL < M) map2d_sep_side<NV>(bL, F, B3, m.ops + m.tab.project[M][NL], nL, nM, sideL, o, false, 1.0);
+    if (NR < M) map2d_sep_side<NV>(bR, F, B1, m.ops + m.tab.project[M][NR], nR, nM, sideR, o, true, -1.0);
     return;
   }
 
