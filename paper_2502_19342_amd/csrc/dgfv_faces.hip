@@ -126,22 +126,6 @@ __device__ void map2d_to(const double* src, double* dst, const double* A, int no
   }
 }
 
-// The same map written straight into a side buffer (orientation and scale as
-// in write_side).
-template <int NV>
-__device__ void map2d_side(double* dst_block, const double* src, const double* A, int nout, int nin,
-                           int side, int o, bool right, double scale) {
-  const int n2 = nout * nout;
-  for (int t = threadIdx.x; t < n2; t += blockDim.x) {
-    const int pp = t % nout, qq = t / nout;
-    int p = pp, q = qq;
-    if (right) orient_map(o, pp, qq, nout, p, q);
-    const MapRows rows(A, nin, pp, qq);
-    for (int v = 0; v < NV; ++v)
-      dst_block[(side * NV + v) * n2 + q * nout + p] = scale * rows.apply(src + v * GRID, nin);
-  }
-}
-
 // Separable (two-pass) forms of the same maps, for one-wave workgroups whose
 // barriers are free: pass 1 contracts p into T[f][q][pp] (nin rows of nout),
 // pass 2 contracts q.  The sums are those of MapRows::apply in the same order
@@ -188,11 +172,11 @@ __device__ void map2d_sep_to(const double* src, double* T, double* dst, const do
   }
 }
 
+// pass 2 of the map from T written straight into a side buffer (orientation
+// and scale as in write_side)
 template <int NV>
-__device__ void map2d_sep_side(double* dst_block, const double* src, double* T, const double* A, int nout,
-                               int nin, int side, int o, bool right, double scale) {
-  map2d_pass1<NV>(src, T, A, nout, nin);
-  __syncthreads();
+__device__ void map2d_pass2_side(double* dst_block, const double* T, const double* A, int nout, int nin,
+                                 int side, int o, bool right, double scale) {
   const int n2 = nout * nout;
   for (int t = threadIdx.x; t < n2; t += blockDim.x) {
     const int pp = t % nout, qq = t / nout;
@@ -211,6 +195,14 @@ __device__ void map2d_sep_side(double* dst_block, const double* src, double* T, 
       dst_block[(side * NV + v) * n2 + q * nout + p] = scale * acc;
     }
   }
+}
+
+template <int NV>
+__device__ void map2d_sep_side(double* dst_block, const double* src, double* T, const double* A, int nout,
+                               int nin, int side, int o, bool right, double scale) {
+  map2d_pass1<NV>(src, T, A, nout, nin);
+  __syncthreads();
+  map2d_pass2_side<NV>(dst_block, T, A, nout, nin, side, o, right, scale);
 }
 
 // One face, any class, by the whole (64-lane) workgroup, with three
@@ -304,11 +296,13 @@ __device__ void face_body(const MeshView& m, const ParamsDev& prm, const double*
   for (int t = threadIdx.x; t < 3 * nM * nM; t += blockDim.x)
     sN[(t / (nM * nM)) * GRID + t % (nM * nM)] = nrm[t];
   __syncthreads();
+  // at most one side is pure DG; its trace goes to the sub-face grid by the
+  // two-pass map, with the buffer the blended side leaves free as scratch
   const double* LF = B0;
   const double* RF = B1;
-  if (!(aL > 0.0)) { map2d_to<NV>(B0, B2, m.ops + m.tab.dg2fv[NL], nF, nL); LF = B2; }
-  if (!(aR > 0.0)) { map2d_to<NV>(B1, B3, m.ops + m.tab.dg2fv[NR], nF, nR); RF = B3; }
   map2d_to<3>(sN, sNF, m.ops + m.tab.dg2fv[M], nF, nM);
+  if (!(aL > 0.0)) { map2d_sep_to<NV>(B0, B3, B2, m.ops + m.tab.dg2fv[NL], nF, nL); LF = B2; }
+  if (!(aR > 0.0)) { map2d_sep_to<NV>(B1, B2, B3, m.ops + m.tab.dg2fv[NR], nF, nR); RF = B3; }
   __syncthreads();
   double* F = LF == B2 ? B0 : B2;
   double* fvL = m.fvside + (size_t)eL * 6 * NV * n2F;
@@ -333,9 +327,16 @@ __device__ void face_body(const MeshView& m, const ParamsDev& prm, const double*
     }
   }
   __syncthreads();
+  // both DG parts receive V^{FV->DG} F: first passes into two of the buffers
+  // other than F (all dead now), one barrier, second passes into the sides
   const double ih2 = 1.0 / (h * h);
-  map2d_side<NV>(bL, F, m.ops + m.tab.fv2dg[NL], nL, nF, sideL, o, false, ih2);
-  map2d_side<NV>(bR, F, m.ops + m.tab.fv2dg[NR], nR, nF, sideR, o, true, -ih2);
+  double* TL = F == B0 ? B1 : B0;
+  double* TR = F == B2 ? B3 : B2;
+  map2d_pass1<NV>(F, TL, m.ops + m.tab.fv2dg[NL], nL, nF);
+  map2d_pass1<NV>(F, TR, m.ops + m.tab.fv2dg[NR], nR, nF);
+  __syncthreads();
+  map2d_pass2_side<NV>(bL, TL, m.ops + m.tab.fv2dg[NL], nL, nF, sideL, o, false, ih2);
+  map2d_pass2_side<NV>(bR, TR, m.ops + m.tab.fv2dg[NR], nR, nF, sideR, o, true, -ih2);
 }
 
 // Conforming same-degree faces whose two elements are both pure DG: one thread
