@@ -130,6 +130,13 @@ class Mesh:
         self.elem_offset = off
 
     @classmethod
+    def from_config(cls, cfg: str, **kw) -> "Mesh":
+        """Mesh of a named seeded workload (C1..C5; keyword arguments as for
+        ``workloads.make_workload``)."""
+        from . import workloads as W
+        return cls.from_workload(W.make_workload(cfg, **kw))
+
+    @classmethod
     def from_workload(cls, wl) -> "Mesh":
         m = wl.mesh
         return cls(m.degree, m.corners, m.faces, wl.n_var, wl.n_fv, wl.metric_degree, wl.gamma,
