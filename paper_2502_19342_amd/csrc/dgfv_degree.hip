@@ -407,34 +407,55 @@ fv_means_kernel(MeshView m, const double* __restrict__ u) {
     bufA[NV * NP3 + r] = J;
   }
   __syncthreads();
+  // Three one-dimensional contractions with V (NFV x NP).  Each thread keeps one
+  // input line in registers and forms all NFV outputs along the contracted
+  // axis, so every LDS word is read once per pass; V is read at uniform
+  // addresses.
   // axis 0: [f][k][j][c] -> [f][k][j][s0]
-  for (int r = t; r < NF * NP * NP * NFV; r += FV2_THREADS) {
-    const int s0 = r % NFV, jk = (r / NFV) % (NP * NP), f = r / (NFV * NP * NP);
-    const double* src = bufA + f * NP3 + jk * NP;
-    double acc = 0.0;
+  for (int r = t; r < NF * NP * NP; r += FV2_THREADS) {
+    const double* src = bufA + r * NP;
+    double x[NP];
 #pragma unroll
-    for (int c = 0; c < NP; ++c) acc += sV[s0 * NP + c] * src[c];
-    bufB[r] = acc;
+    for (int c = 0; c < NP; ++c) x[c] = src[c];
+#pragma unroll
+    for (int s0 = 0; s0 < NFV; ++s0) {
+      double acc = 0.0;
+#pragma unroll
+      for (int c = 0; c < NP; ++c) acc += sV[s0 * NP + c] * x[c];
+      bufB[r * NFV + s0] = acc;
+    }
   }
   __syncthreads();
   // axis 1: [f][k][c][s0] -> [f][k][s1][s0]
-  for (int r = t; r < NF * NP * NFV * NFV; r += FV2_THREADS) {
-    const int s0 = r % NFV, s1 = (r / NFV) % NFV, kf = r / (NFV * NFV);   // kf = f*NP + k
+  for (int r = t; r < NF * NP * NFV; r += FV2_THREADS) {
+    const int s0 = r % NFV, kf = r / NFV;                                   // kf = f*NP + k
     const double* src = bufB + kf * NP * NFV + s0;
-    double acc = 0.0;
+    double x[NP];
 #pragma unroll
-    for (int c = 0; c < NP; ++c) acc += sV[s1 * NP + c] * src[c * NFV];
-    bufA[r] = acc;
+    for (int c = 0; c < NP; ++c) x[c] = src[c * NFV];
+#pragma unroll
+    for (int s1 = 0; s1 < NFV; ++s1) {
+      double acc = 0.0;
+#pragma unroll
+      for (int c = 0; c < NP; ++c) acc += sV[s1 * NP + c] * x[c];
+      bufA[(kf * NFV + s1) * NFV + s0] = acc;
+    }
   }
   __syncthreads();
   // axis 2: [f][c][s1][s0] -> [f][s2][s1][s0]
-  for (int r = t; r < NF * S3; r += FV2_THREADS) {
-    const int s01 = r % (NFV * NFV), s2 = (r / (NFV * NFV)) % NFV, f = r / S3;
+  for (int r = t; r < NF * NFV * NFV; r += FV2_THREADS) {
+    const int s01 = r % (NFV * NFV), f = r / (NFV * NFV);
     const double* src = bufA + f * NP * NFV * NFV + s01;
-    double acc = 0.0;
+    double x[NP];
 #pragma unroll
-    for (int c = 0; c < NP; ++c) acc += sV[s2 * NP + c] * src[c * NFV * NFV];
-    bufB[r] = acc;
+    for (int c = 0; c < NP; ++c) x[c] = src[c * NFV * NFV];
+#pragma unroll
+    for (int s2 = 0; s2 < NFV; ++s2) {
+      double acc = 0.0;
+#pragma unroll
+      for (int c = 0; c < NP; ++c) acc += sV[s2 * NP + c] * x[c];
+      bufB[f * S3 + s2 * NFV * NFV + s01] = acc;
+    }
   }
   __syncthreads();
   double* ub = m.ubar + (size_t)e * NV * S3;
@@ -455,6 +476,7 @@ fv_residual_kernel(MeshView m, ParamsDev prm) {
   __shared__ double sU[NV * S3];
   __shared__ double sG[NV * S3];
   __shared__ double sF[6 * NV * S2];           // the six sides' FV fluxes
+  __shared__ double sJ[NP3];
   __shared__ double sVp[NP * NFV];
   const int t = threadIdx.x;
   const double h = 2.0 / NFV;
@@ -464,8 +486,8 @@ fv_residual_kernel(MeshView m, ParamsDev prm) {
   const int e = m.blend_list[w];
   const int64_t base = m.elem_offset[e];
   // every global read of the element is issued here, ahead of the first barrier:
-  // the sub-cell means and side fluxes into LDS, this thread's sub-face normals
-  // and J into registers
+  // the sub-cell means, side fluxes and J into LDS, this thread's sub-face
+  // normals into registers
   const double* ub = m.ubar + (size_t)e * NV * S3;
   for (int r = t; r < NV * S3; r += FV2_THREADS) sU[r] = ub[r];
   const double* fvs = m.fvside + (size_t)e * 6 * NV * S2;
@@ -483,7 +505,7 @@ fv_residual_kernel(MeshView m, ParamsDev prm) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) nd[d][c] = has ? nrm[(d * 3 + c) * NIF + k] : 0.0;
   }
-  const double Jn = t < NP3 ? m.metric[9 * m.n_node + base + t] : 1.0;
+  for (int r = t; r < NP3; r += FV2_THREADS) sJ[r] = m.metric[9 * m.n_node + base + r];
   double dC[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) dC[v] = 0.0;
@@ -516,40 +538,55 @@ fv_residual_kernel(MeshView m, ParamsDev prm) {
     }
     __syncthreads();
   }
-  // nodal form: V3^+(dC) / (h^3 J)
+  // nodal form: V3^+(dC) / (h^3 J), three one-dimensional contractions; each
+  // thread keeps one input line in registers and forms all NP outputs along
+  // the contracted axis
   if (active) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) sG[v * S3 + t] = dC[v];
   }
   __syncthreads();
-  for (int r = t; r < NV * S2 * NP; r += FV2_THREADS) {        // [v][s2][s1][i]
-    const int i = r % NP, q = r / NP;                        // q = v*S2 + s2*NFV + s1
-    const double* src = sG + q * NFV;
-    double acc = 0.0;
+  for (int q = t; q < NV * S2; q += FV2_THREADS) {              // [v][s2][s1][c] -> [v][s2][s1][i]
+    double x[NFV];
 #pragma unroll
-    for (int c = 0; c < NFV; ++c) acc += sVp[i * NFV + c] * src[c];
-    sU[r] = acc;
+    for (int c = 0; c < NFV; ++c) x[c] = sG[q * NFV + c];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      double acc = 0.0;
+#pragma unroll
+      for (int c = 0; c < NFV; ++c) acc += sVp[i * NFV + c] * x[c];
+      sU[q * NP + i] = acc;
+    }
   }
   __syncthreads();
-  for (int r = t; r < NV * NFV * NP * NP; r += FV2_THREADS) {  // [v][s2][j][i]
-    const int i = r % NP, j = (r / NP) % NP, q = r / (NP * NP); // q = v*NFV + s2
-    const double* src = sU + q * NFV * NP + i;
-    double acc = 0.0;
+  for (int r = t; r < NV * NFV * NP; r += FV2_THREADS) {       // [v][s2][c][i] -> [v][s2][j][i]
+    const int i = r % NP, q = r / NP;                          // q = v*NFV + s2
+    double x[NFV];
 #pragma unroll
-    for (int c = 0; c < NFV; ++c) acc += sVp[j * NFV + c] * src[c * NP];
-    sG[r] = acc;
+    for (int c = 0; c < NFV; ++c) x[c] = sU[(q * NFV + c) * NP + i];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      double acc = 0.0;
+#pragma unroll
+      for (int c = 0; c < NFV; ++c) acc += sVp[j * NFV + c] * x[c];
+      sG[(q * NP + j) * NP + i] = acc;
+    }
   }
   __syncthreads();
   const double ih3 = 1.0 / (h * h * h);
-  for (int r = t; r < NV * NP3; r += FV2_THREADS) {          // [v][k][j][i]
-    const int ij = r % (NP * NP), k = (r / (NP * NP)) % NP, v = r / NP3;
-    const double* src = sG + v * NFV * NP * NP + ij;
-    double acc = 0.0;
+  for (int r = t; r < NV * NP * NP; r += FV2_THREADS) {       // [v][c][j][i] -> [v][k][j][i]
+    const int ij = r % (NP * NP), v = r / (NP * NP);
+    double x[NFV];
 #pragma unroll
-    for (int c = 0; c < NFV; ++c) acc += sVp[k * NFV + c] * src[c * NP * NP];
-    const int node = k * NP * NP + ij;
-    const double J = node == t ? Jn : m.metric[9 * m.n_node + base + node];
-    m.rfv[v * m.n_node + base + node] = acc * ih3 / J;
+    for (int c = 0; c < NFV; ++c) x[c] = sG[(v * NFV + c) * NP * NP + ij];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      double acc = 0.0;
+#pragma unroll
+      for (int c = 0; c < NFV; ++c) acc += sVp[k * NFV + c] * x[c];
+      const int node = k * NP * NP + ij;
+      m.rfv[v * m.n_node + base + node] = acc * ih3 / sJ[node];
+    }
   }
 }
 
