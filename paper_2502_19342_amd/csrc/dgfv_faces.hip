@@ -350,7 +350,22 @@ face_conforming_kernel(MeshView m, ParamsDev prm, const int32_t* __restrict__ fl
                        const double* __restrict__ u, const double* __restrict__ alpha) {
   constexpr int NP = N + 1, NP2 = NP * NP, FPB = CONF_THREADS / NP2;
   const int t = threadIdx.x;
-  const int slot = t / NP2, r = t - slot * NP2;
+  // At N = 7 a face has 64 nodes.  Each wave takes half the nodes of two
+  // consecutive faces of the list (lanes 0-31 the even slot, 32-63 the odd
+  // one), and the odd slot loads its right side first: on a structured mesh
+  // the even face's right element is the odd face's left element, so one load
+  // instruction reads both opposite sides of that element, which share their
+  // cache lines along xi_1.
+  constexpr bool PAIRED = NP2 == 64;
+  int slot, r;
+  if constexpr (PAIRED) {
+    const int w = t >> 6, l = t & 63;
+    slot = (w & ~1) + (l >> 5);
+    r = (l & 31) + ((w & 1) << 5);
+  } else {
+    slot = t / NP2;
+    r = t - slot * NP2;
+  }
   if (slot >= FPB) return;
   const int fi = blockIdx.x * FPB + slot;
   if (fi >= fcount) return;
@@ -364,11 +379,18 @@ face_conforming_kernel(MeshView m, ParamsDev prm, const int32_t* __restrict__ fl
   const int64_t gL = m.elem_offset[eL] + side_node(sideL, p, q, NP);
   const int64_t gR = m.elem_offset[eR] + side_node(sideR, pp, qq, NP);
   const double* nrm = m.face_norm + m.face_norm_off[f];
+  const bool flip = PAIRED && (slot & 1);
+  const int64_t gA = flip ? gR : gL, gB = flip ? gL : gR;
+  double a[NV], b[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) a[v] = u[v * m.n_node + gA];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) b[v] = u[v * m.n_node + gB];
   double uL[NV], uR[NV], F[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
-    uL[v] = u[v * m.n_node + gL];
-    uR[v] = u[v * m.n_node + gR];
+    uL[v] = flip ? b[v] : a[v];
+    uR[v] = flip ? a[v] : b[v];
   }
   riemann<NV>(prm.face_flux_dg, prm.volume_flux, uL, uR, nrm[r], nrm[NP2 + r], nrm[2 * NP2 + r], m.gas, F);
   double* bL = m.fside + m.side_off[eL];
