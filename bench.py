@@ -75,13 +75,14 @@ def initial_state_device(gm, wl, dgfv, torch, chunk=1 << 23):
 
 
 def element_kernel_bytes(wl, degree: np.ndarray, alpha: np.ndarray, stage: int) -> float:
-    """Algorithmic HBM bytes of one element-kernel launch (all buckets of one stage).
+    """Algorithmic HBM bytes of one element-kernel launch (all buckets of one stage of an RK step).
 
     Per node: u read + write, k read (not at stage 1) + write; per blended node
     (alpha > 0) the FV residual (nvar).  Except on pure FV elements (alpha = 1
     at degrees with one element per workgroup, N >= 6, whose DG part is not
     evaluated): per node the 9 metric terms and J, per element the 6 (N+1)^2
-    nvar side fluxes.
+    nvar side fluxes.  Stages 1..4 also write the new state of sides 0 and 1
+    (2 (N+1)^2 nvar per element of degree >= 6) for the next stage's face fluxes.
     """
     nv = wl.n_var
     npe = (degree.astype(np.int64) + 1) ** 3
@@ -92,6 +93,8 @@ def element_kernel_bytes(wl, degree: np.ndarray, alpha: np.ndarray, stage: int) 
     total += 8 * 10 * npe[dg].sum()
     total += 8 * 6 * ((degree[dg].astype(np.int64) + 1) ** 2).sum() * nv
     total += 8 * nv * npe[alpha > 0].sum()
+    if stage < 5:
+        total += 8 * 2 * ((degree[degree >= 6].astype(np.int64) + 1) ** 2).sum() * nv
     return float(total)
 
 

@@ -44,7 +44,7 @@ template <int N, int NV, class FLUX, int EPB>
 __global__ void __launch_bounds__(EPB * Geo<N>::NP3)
 element_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const double* u,
                const double* __restrict__ alpha, double* __restrict__ ut, double* k, int stage,
-               double dt, double A, double B) {
+               double dt, double A, double B, bool write_trace) {
   using G = Geo<N>;
   constexpr int NP = G::NP, NP2 = G::NP2, NP3 = G::NP3;
   constexpr int NA = FLUX::NA;
@@ -76,19 +76,30 @@ element_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const d
 #pragma unroll
   for (int v = 0; v < NV; ++v) uo[v] = u[v * m.n_node + base];
 
-  // stage 0: ut = R; stage s: k <- A k + dt R (k not read at stage 1), u <- u + B k
+  const int i = node % NP, j = (node / NP) % NP, kk = node / NP2;
+  // stage 0: ut = R; stage s: k <- A k + dt R (k not read at stage 1), u <- u + B k,
+  // and with write_trace the new state of the xi_1 ends (sides 0 and 1) also in
+  // m.trace, contiguous per side for the next stage's face fluxes.  Only at
+  // N >= TRACE_MIN_N, where the N+1 stride of those sides in u costs the face
+  // kernels most; below it the extra stores cost more than they save.
+  constexpr bool TRACE = N >= TRACE_MIN_N;
   auto store = [&](const double* R, const double* k_old) {
     if (stage == 0) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) ut[v * m.n_node + base] = R[v];
     } else {
       double* uw = const_cast<double*>(u);
+      double* tr = nullptr;
+      if (TRACE && write_trace && (i == 0 || i == N))
+        tr = m.trace + m.side_off[e] / 3 + ((i == 0 ? 0 : 1) * NV) * NP2 + kk * NP + j;
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         const int64_t g = v * m.n_node + base;
         const double kv = (stage == 1) ? dt * R[v] : A * k_old[v] + dt * R[v];
+        const double un = uo[v] + B * kv;
         k[g] = kv;
-        uw[g] = uo[v] + B * kv;
+        uw[g] = un;
+        if (tr) tr[v * NP2] = un;
       }
     }
   };
@@ -121,7 +132,6 @@ element_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const d
   }
   const double invJ = 1.0 / m.metric[9 * m.n_node + base];
 
-  const int i = node % NP, j = (node / NP) % NP, kk = node / NP2;
   const int lane = tid & 63;
   double acc[NV];
 #pragma unroll
@@ -1046,36 +1056,36 @@ vjp_fv_gather_kernel(MeshView m, const int32_t* __restrict__ elist, int count,
 template <int NV, class FLUX, int V>
 static hipError_t launch_elem_v(const MeshView& m, const int32_t* elist, int count, const double* u,
                                 const double* alpha, double* ut, double* k, int stage, double dt,
-                                double A, double B, hipStream_t s) {
+                                double A, double B, bool tr, hipStream_t s) {
   constexpr int EPB = elem_epb<kN, V>();
   const int blocks = (count + EPB - 1) / EPB;
   hipLaunchKernelGGL((element_kernel<kN, NV, FLUX, EPB>), dim3(blocks), dim3(EPB * Geo<kN>::NP3), 0, s, m,
-                     elist, count, u, alpha, ut, k, stage, dt, A, B);
+                     elist, count, u, alpha, ut, k, stage, dt, A, B, tr);
   return hipGetLastError();
 }
 
 template <int NV, class FLUX>
 static hipError_t launch_elem_t(const MeshView& m, const int32_t* elist, int count, const double* u,
                                 const double* alpha, double* ut, double* k, int stage, double dt,
-                                double A, double B, int variant, hipStream_t s) {
+                                double A, double B, int variant, bool tr, hipStream_t s) {
   if (variant == 1 && elem_variants(kN) > 1)
-    return launch_elem_v<NV, FLUX, 1>(m, elist, count, u, alpha, ut, k, stage, dt, A, B, s);
-  return launch_elem_v<NV, FLUX, 0>(m, elist, count, u, alpha, ut, k, stage, dt, A, B, s);
+    return launch_elem_v<NV, FLUX, 1>(m, elist, count, u, alpha, ut, k, stage, dt, A, B, tr, s);
+  return launch_elem_v<NV, FLUX, 0>(m, elist, count, u, alpha, ut, k, stage, dt, A, B, tr, s);
 }
 
 namespace per_degree {
 hipError_t element(const MeshView& m, const ParamsDev& p, const int32_t* elist, int count,
                    const double* u, const double* alpha, double* ut, double* k, int stage,
-                   double dt, double A, double B, int variant, hipStream_t s) {
+                   double dt, double A, double B, int variant, bool tr, hipStream_t s) {
   if (count == 0) return hipSuccess;
   const int v = variant;
   if (m.nvar == 5) {
-    if (p.volume_flux == 0) return launch_elem_t<5, FluxRanocha>(m, elist, count, u, alpha, ut, k, stage, dt, A, B, v, s);
-    if (p.volume_flux == 1) return launch_elem_t<5, FluxPirozzoli>(m, elist, count, u, alpha, ut, k, stage, dt, A, B, v, s);
-    return launch_elem_t<5, FluxCentral>(m, elist, count, u, alpha, ut, k, stage, dt, A, B, v, s);
+    if (p.volume_flux == 0) return launch_elem_t<5, FluxRanocha>(m, elist, count, u, alpha, ut, k, stage, dt, A, B, v, tr, s);
+    if (p.volume_flux == 1) return launch_elem_t<5, FluxPirozzoli>(m, elist, count, u, alpha, ut, k, stage, dt, A, B, v, tr, s);
+    return launch_elem_t<5, FluxCentral>(m, elist, count, u, alpha, ut, k, stage, dt, A, B, v, tr, s);
   }
-  if (p.volume_flux == 1) return launch_elem_t<6, FluxPirozzoli>(m, elist, count, u, alpha, ut, k, stage, dt, A, B, v, s);
-  return launch_elem_t<6, FluxCentral>(m, elist, count, u, alpha, ut, k, stage, dt, A, B, v, s);
+  if (p.volume_flux == 1) return launch_elem_t<6, FluxPirozzoli>(m, elist, count, u, alpha, ut, k, stage, dt, A, B, v, tr, s);
+  return launch_elem_t<6, FluxCentral>(m, elist, count, u, alpha, ut, k, stage, dt, A, B, v, tr, s);
 }
 
 // fv_means is persistent: as many workgroups as fit on the device at once (at

@@ -347,7 +347,8 @@ constexpr int CONF_THREADS = 256;
 template <int N, int NV>
 __global__ void __launch_bounds__(CONF_THREADS)
 face_conforming_kernel(MeshView m, ParamsDev prm, const int32_t* __restrict__ flist, int fcount,
-                       const double* __restrict__ u, const double* __restrict__ alpha) {
+                       const double* __restrict__ u, const double* __restrict__ alpha,
+                       const double* __restrict__ trace) {
   constexpr int NP = N + 1, NP2 = NP * NP, FPB = CONF_THREADS / NP2;
   const int t = threadIdx.x;
   // At N = 7 a face has 64 nodes.  Each wave takes half the nodes of two
@@ -376,16 +377,31 @@ face_conforming_kernel(MeshView m, ParamsDev prm, const int32_t* __restrict__ fl
   const int p = r % NP, q = r / NP;
   int pp, qq;
   orient_map(o, p, q, NP, pp, qq);
-  const int64_t gL = m.elem_offset[eL] + side_node(sideL, p, q, NP);
-  const int64_t gR = m.elem_offset[eR] + side_node(sideR, pp, qq, NP);
+  // where each side's state comes from: u, or for sides 0 and 1 (strided by
+  // N+1 in u) the trace the previous stage wrote, contiguous per side
+  auto source = [&](int e, int side, int sp, int sq, const double*& src, int64_t& vstride) {
+    if (trace && side < 2) {
+      src = trace + m.side_off[e] / 3 + side * NV * NP2 + sq * NP + sp;
+      vstride = NP2;
+    } else {
+      src = u + m.elem_offset[e] + side_node(side, sp, sq, NP);
+      vstride = m.n_node;
+    }
+  };
+  const double *sL, *sR;
+  int64_t vL, vR;
+  source(eL, sideL, p, q, sL, vL);
+  source(eR, sideR, pp, qq, sR, vR);
   const double* nrm = m.face_norm + m.face_norm_off[f];
   const bool flip = PAIRED && (slot & 1);
-  const int64_t gA = flip ? gR : gL, gB = flip ? gL : gR;
+  const double* sA = flip ? sR : sL;
+  const double* sB = flip ? sL : sR;
+  const int64_t vA = flip ? vR : vL, vB = flip ? vL : vR;
   double a[NV], b[NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) a[v] = u[v * m.n_node + gA];
+  for (int v = 0; v < NV; ++v) a[v] = sA[v * vA];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) b[v] = u[v * m.n_node + gB];
+  for (int v = 0; v < NV; ++v) b[v] = sB[v * vB];
   double uL[NV], uR[NV], F[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
@@ -689,7 +705,8 @@ hipError_t launch_faces_vjp(const MeshView& m, const ParamsDev& p, const double*
 
 template <int NV>
 static hipError_t launch_face_class_t(const MeshView& m, const ParamsDev& p, const double* u,
-                                      const double* alpha, int cls, hipStream_t s) {
+                                      const double* alpha, int cls, bool read_trace, hipStream_t s) {
+  const double* tr = read_trace && cls >= TRACE_MIN_N && cls <= MAXN ? m.trace : nullptr;
   if (cls >= 1 && cls <= MAXN) {
     const int N = cls, cnt = m.face_conf_count[N];
     if (cnt == 0) return hipSuccess;
@@ -697,13 +714,13 @@ static hipError_t launch_face_class_t(const MeshView& m, const ParamsDev& p, con
     const dim3 grid((cnt + fpb - 1) / fpb), block(CONF_THREADS);
     const int32_t* fl = m.face_conf[N];
     switch (N) {
-      case 1: hipLaunchKernelGGL((face_conforming_kernel<1, NV>), grid, block, 0, s, m, p, fl, cnt, u, alpha); break;
-      case 2: hipLaunchKernelGGL((face_conforming_kernel<2, NV>), grid, block, 0, s, m, p, fl, cnt, u, alpha); break;
-      case 3: hipLaunchKernelGGL((face_conforming_kernel<3, NV>), grid, block, 0, s, m, p, fl, cnt, u, alpha); break;
-      case 4: hipLaunchKernelGGL((face_conforming_kernel<4, NV>), grid, block, 0, s, m, p, fl, cnt, u, alpha); break;
-      case 5: hipLaunchKernelGGL((face_conforming_kernel<5, NV>), grid, block, 0, s, m, p, fl, cnt, u, alpha); break;
-      case 6: hipLaunchKernelGGL((face_conforming_kernel<6, NV>), grid, block, 0, s, m, p, fl, cnt, u, alpha); break;
-      default: hipLaunchKernelGGL((face_conforming_kernel<7, NV>), grid, block, 0, s, m, p, fl, cnt, u, alpha); break;
+      case 1: hipLaunchKernelGGL((face_conforming_kernel<1, NV>), grid, block, 0, s, m, p, fl, cnt, u, alpha, tr); break;
+      case 2: hipLaunchKernelGGL((face_conforming_kernel<2, NV>), grid, block, 0, s, m, p, fl, cnt, u, alpha, tr); break;
+      case 3: hipLaunchKernelGGL((face_conforming_kernel<3, NV>), grid, block, 0, s, m, p, fl, cnt, u, alpha, tr); break;
+      case 4: hipLaunchKernelGGL((face_conforming_kernel<4, NV>), grid, block, 0, s, m, p, fl, cnt, u, alpha, tr); break;
+      case 5: hipLaunchKernelGGL((face_conforming_kernel<5, NV>), grid, block, 0, s, m, p, fl, cnt, u, alpha, tr); break;
+      case 6: hipLaunchKernelGGL((face_conforming_kernel<6, NV>), grid, block, 0, s, m, p, fl, cnt, u, alpha, tr); break;
+      default: hipLaunchKernelGGL((face_conforming_kernel<7, NV>), grid, block, 0, s, m, p, fl, cnt, u, alpha, tr); break;
     }
     return hipGetLastError();
   }
@@ -730,10 +747,10 @@ bool face_class_present(const MeshView& m, const double* alpha, int cls) {
 }
 
 hipError_t launch_face_class(const MeshView& m, const ParamsDev& p, const double* u, const double* alpha,
-                             int cls, hipStream_t s) {
+                             int cls, bool read_trace, hipStream_t s) {
   if (m.n_face == 0) return hipSuccess;
-  return m.nvar == 5 ? launch_face_class_t<5>(m, p, u, alpha, cls, s)
-                     : launch_face_class_t<6>(m, p, u, alpha, cls, s);
+  return m.nvar == 5 ? launch_face_class_t<5>(m, p, u, alpha, cls, read_trace, s)
+                     : launch_face_class_t<6>(m, p, u, alpha, cls, read_trace, s);
 }
 
 }  // namespace dgfv

@@ -365,8 +365,12 @@ std::vector<int> degrees_present(const dgfv_mesh* m) {
 // Phases: blended list + sub-cell means, face fluxes, FV residuals, element
 // kernels (volume, lift, blend, RK update); the per-degree (per face class)
 // launches of a phase are independent branches.
+// trace_in: the conforming faces read sides 0 and 1 from m->view.trace, which
+// the previous stage of the same step wrote (trace_out) from the state it left
+// in u; only dg_rk_step sets them, as within one call nothing else writes u.
 void enqueue_rhs_impl(const dgfv_mesh* m, const ParamsDev& p, const double* u, const double* alpha,
-                      double* ut, double* k, int stage, double dt, hipStream_t s) {
+                      double* ut, double* k, int stage, double dt, hipStream_t s, bool trace_in = false,
+                      bool trace_out = false) {
   const MeshView& v = m->view;
   const double A = stage > 0 ? RK_A[stage - 1] : 0.0;
   const double B = stage > 0 ? RK_B[stage - 1] : 0.0;
@@ -386,7 +390,7 @@ void enqueue_rhs_impl(const dgfv_mesh* m, const ParamsDev& p, const double* u, c
       if (face_class_present(v, alpha, c)) classes.push_back(c);
     fork_join(m, s, classes, [&](int c, hipStream_t ss) {
       Timed tf(m, c == FACE_CLASS_FV ? DGFV_KERNEL_FV_FACE : -1, ss);
-      hip_check(launch_face_class(v, p, u, alpha, c, ss), "face launch");
+      hip_check(launch_face_class(v, p, u, alpha, c, trace_in, ss), "face launch");
     });
   }
   if (alpha) {
@@ -399,7 +403,7 @@ void enqueue_rhs_impl(const dgfv_mesh* m, const ParamsDev& p, const double* u, c
     Timed t(m, DGFV_KERNEL_ELEMENT, s);
     fork_join(m, s, degs, [&](int N, hipStream_t ss) {
       hip_check(ops_for(N).element(v, p, m->d_bucket[N], (int)m->bucket[N].size(), u, alpha, ut, k, stage,
-                                   dt, A, B, m->elem_variant[N], ss),
+                                   dt, A, B, m->elem_variant[N], trace_out, ss),
                 "element launch");
     });
   }
@@ -423,7 +427,8 @@ dgfv_status run_stages(const dgfv_mesh* m, const dgfv_params* prm, int kind, int
   try {
     if (m->launch_mode != DGFV_LAUNCH_GRAPH || m->profile) {
       const ParamsDev p = to_dev(prm);
-      for (int st = first; st <= last; ++st) enqueue_rhs_impl(m, p, u, alpha, nullptr, k, st, dt, s);
+      for (int st = first; st <= last; ++st)
+        enqueue_rhs_impl(m, p, u, alpha, nullptr, k, st, dt, s, st > first, st < last);
       return DGFV_OK;
     }
     dgfv_mesh::GraphKey key;
@@ -448,7 +453,8 @@ dgfv_status run_stages(const dgfv_mesh* m, const dgfv_params* prm, int kind, int
       hipGraph_t graph = nullptr;
       hip_check(hipStreamBeginCapture(m->cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
       try {
-        for (int st = first; st <= last; ++st) enqueue_rhs_impl(m, p, u, alpha, nullptr, k, st, dt, m->cap_stream);
+        for (int st = first; st <= last; ++st)
+          enqueue_rhs_impl(m, p, u, alpha, nullptr, k, st, dt, m->cap_stream, st > first, st < last);
       } catch (...) {
         (void)hipStreamEndCapture(m->cap_stream, &graph);
         if (graph) (void)hipGraphDestroy(graph);
@@ -709,6 +715,7 @@ dgfv_status dgfv_mesh_create(const dgfv_mesh_desc* d, dgfv_mesh** out) {
     v.face_norm = m->keep(dev_upload(fnorm));
     v.side_off = m->keep(dev_upload(side_off));
     v.fside = m->keep(dev_alloc<double>(stot));
+    v.trace = m->keep(dev_alloc<double>(stot / 3));    // sides 0 and 1 of every element
     v.fvside = m->keep(dev_alloc<double>((size_t)m->K * 6 * m->nvar * NFV * NFV));
     v.ubar = m->keep(dev_alloc<double>((size_t)m->K * m->nvar * NFV * NFV * NFV));
     v.rfv = m->keep(dev_alloc<double>((size_t)m->nvar * m->n_node));
@@ -883,11 +890,11 @@ dgfv_status dgfv_autotune(dgfv_mesh* m, const dgfv_params* prm, const double* u,
       double best = 0.0;
       int choice = 0;
       for (int var = 0; var < ops.element_variants; ++var) {
-        hip_check(ops.element(v, p, m->d_bucket[N], cnt, u, alpha, scratch, nullptr, 0, 0.0, 0.0, 0.0, var, s),
+        hip_check(ops.element(v, p, m->d_bucket[N], cnt, u, alpha, scratch, nullptr, 0, 0.0, 0.0, 0.0, var, false, s),
                   "element launch");
         hip_check(hipEventRecord(e0, s), "hipEventRecord");
         for (int r = 0; r < REPS; ++r)
-          hip_check(ops.element(v, p, m->d_bucket[N], cnt, u, alpha, scratch, nullptr, 0, 0.0, 0.0, 0.0, var, s),
+          hip_check(ops.element(v, p, m->d_bucket[N], cnt, u, alpha, scratch, nullptr, 0, 0.0, 0.0, 0.0, var, false, s),
                     "element launch");
         hip_check(hipEventRecord(e1, s), "hipEventRecord");
         hip_check(hipEventSynchronize(e1), "hipEventSynchronize");

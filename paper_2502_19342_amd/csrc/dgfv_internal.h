@@ -51,6 +51,9 @@ struct MeshView {
   const double* face_norm;      // per face [3][(M+1)^2] left outward n*s at degree M = max(NL,NR)
   const int64_t* side_off;      // [K] offset of element e's side-flux block: 6*nvar*(N+1)^2 doubles
   double* fside;                // DG surface fluxes per element side, [6][nvar][(N+1)^2]
+  double* trace;                // state on element sides 0 and 1 (the xi_1 ends), [2][nvar][(N+1)^2]
+                                // at offset side_off[e] / 3, written by one RK stage for the next
+                                // (elements of degree >= TRACE_MIN_N)
   double* fvside;               // FV sub-face fluxes, [K][6][nvar][NFV^2]
   double* ubar;                 // sub-cell means, [K][nvar][NFV^3]
   double* rfv;                  // FV residual in nodal form, [nvar][n_node]
@@ -82,9 +85,10 @@ struct MeshView {
 // stage with coefficients (A, B) on u (in place) and k.
 struct DegreeOps {
   // element kernel in tile shape `variant` (0 .. element_variants - 1)
+  // With write_trace the kernel also stores the new state of sides 0 and 1 in m.trace.
   hipError_t (*element)(const MeshView& m, const ParamsDev& p, const int32_t* elist, int count,
                         const double* u, const double* alpha, double* ut, double* k, int stage,
-                        double dt, double A, double B, int variant, hipStream_t s);
+                        double dt, double A, double B, int variant, bool write_trace, hipStream_t s);
   // FV kernels walk this degree's range of the blended-element list (m.blend_list,
   // m.blend_start); `count` bounds the range size.  fv_means runs persistent
   // workgroups, a 1/share part of the device (share = concurrent degree branches)
@@ -129,11 +133,14 @@ hipError_t launch_blend_list(const MeshView& m, const double* alpha, hipStream_t
 // 1..MAXN conforming DG faces of that degree, FACE_CLASS_MIXED degree jumps
 // between DG elements, FACE_CLASS_FV faces with a blended side (needs the
 // blended-element list of the call).  The classes write disjoint sides and
-// may run concurrently.
+// may run concurrently.  With read_trace the conforming classes take the
+// state on sides 0 and 1 from m.trace (written by the previous RK stage of
+// the same step) instead of u.
 constexpr int FACE_CLASS_MIXED = MAXN + 1, FACE_CLASS_FV = MAXN + 2, FACE_CLASS_COUNT = MAXN + 3;
+constexpr int TRACE_MIN_N = 6;   // lowest degree whose sides 0 and 1 go through m.trace
 bool face_class_present(const MeshView& m, const double* alpha, int cls);
 hipError_t launch_face_class(const MeshView& m, const ParamsDev& p, const double* u, const double* alpha,
-                             int cls, hipStream_t s);
+                             int cls, bool read_trace, hipStream_t s);
 
 hipError_t launch_faces_vjp(const MeshView& m, const ParamsDev& p, const double* u, const double* alpha,
                             hipStream_t s);

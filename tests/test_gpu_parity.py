@@ -157,6 +157,18 @@ def test_blast_hundred_rk_steps():
     assert rel_err(ug.cpu(), u) <= STEP_TOL
 
 
+@pytest.mark.parametrize("scramble", [None, 41])
+def test_n7_rk_steps(scramble):
+    # dg_rk_step at N = 7: from stage 2 on the conforming faces read the xi_1 ends
+    # from the traces the previous stage wrote (paired faces on the structured mesh)
+    announce(f"N=7 5 steps scramble={scramble}")
+    wl = curved_mixed(n=3, nmin=7, nmax=7, scramble=scramble, n_fv=8)
+    c = Case(wl, prim=smooth_state(97), noise=1e-3, seed=17)
+    c.alpha = seeded_alpha(c.mesh.K, 42, values=(0.0, 0.0, 0.0, 1.0))
+    dt = lsrk.timestep(c.mesh, c.gas, c.u, 0.5, c.alpha)
+    assert rel_err(_gpu_steps(c, dt, 5), _oracle_steps(c, dt, 5)) <= STEP_TOL
+
+
 def test_hybrid_mixed_rk_steps():
     announce("hybrid mixed 20 steps")
     wl = curved_mixed(n=2, nmin=2, nmax=4, scramble=8, n_fv=5)
