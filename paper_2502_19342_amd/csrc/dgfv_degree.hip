@@ -603,83 +603,93 @@ fv_residual_kernel(MeshView m, ParamsDev prm) {
 // ---------------------------------------------------------------------------
 // modal decay indicator and blending factor (one element per 64-lane workgroup)
 // ---------------------------------------------------------------------------
+// Lanes per element of the indicator: one wave up to N = 4, four waves above.
+template <int N>
+constexpr int ind_threads() { return (N + 1) * (N + 1) * (N + 1) >= 216 ? 256 : 64; }
+
 template <int N, int NV>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(ind_threads<N>())
 indicator_kernel(MeshView m, ParamsDev prm, const int32_t* __restrict__ elist, int count,
                  const double* __restrict__ u, double* __restrict__ alpha, double* __restrict__ ind) {
   constexpr int NP = N + 1, NP3 = NP * NP * NP;
-  __shared__ double sq[NP3];
-  __shared__ double sw[NP3];
+  constexpr int NFMAX = NV == 6 ? 3 : 2;       // p, rho (and Y)
+  __shared__ double sq[NFMAX * NP3];
+  __shared__ double sw[NFMAX * NP3];
   __shared__ double sVi[NP * NP];
-  __shared__ double sE[3][NP];
-  __shared__ double sI[3];
+  __shared__ double sE[NFMAX * 3 * NP];
+  __shared__ double sI[NFMAX * 3];
   const int idx = blockIdx.x;
   if (idx >= count) return;
   const int e = elist[idx];
   const int64_t base = m.elem_offset[e];
   for (int t = threadIdx.x; t < NP * NP; t += blockDim.x) sVi[t] = m.ops[m.tab.vleg_inv[N] + t];
-  double Imin = INFINITY;
-  for (int var = 0; var < 3; ++var) {
-    if (!(prm.ind_vars & (1 << var))) continue;
-    if (var == 2 && NV != 6) continue;
-    __syncthreads();
-    for (int t = threadIdx.x; t < NP3; t += blockDim.x) {
-      double uu[NV];
-      for (int v = 0; v < NV; ++v) uu[v] = u[v * m.n_node + base + t];
-      const Prim q = cons2prim<NV>(uu, m.gas);
-      sq[t] = var == 0 ? q.p : (var == 1 ? q.rho : q.Y);
-    }
-    __syncthreads();
-    contract_axis(sq, sw, sVi, NP, NP, 1, NP, NP, NP, 0);
-    __syncthreads();
-    contract_axis(sw, sq, sVi, NP, NP, 1, NP, NP, NP, 1);
-    __syncthreads();
-    contract_axis(sq, sw, sVi, NP, NP, 1, NP, NP, NP, 2);
-    __syncthreads();
-    // energies per mode and direction
-    for (int t = threadIdx.x; t < 3 * NP; t += blockDim.x) {
-      const int d = t / NP, mm = t % NP;
-      double s = 0.0;
-      for (int a = 0; a < NP; ++a)
-        for (int b = 0; b < NP; ++b) {
-          int id;
-          if (d == 0) id = (b * NP + a) * NP + mm;
-          else if (d == 1) id = (b * NP + mm) * NP + a;
-          else id = (mm * NP + b) * NP + a;
-          s += sw[id] * sw[id];
-        }
-      sE[d][mm] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x < 3) {
-      const int d = threadIdx.x;
-      double tot = 0.0;
-      for (int mm = 0; mm < NP; ++mm) tot += sE[d][mm];
-      double res;
-      if (tot < 1e-300) {
-        res = INFINITY;
-      } else {
-        const double mbar = 0.5 * N;
-        double ybar = 0.0;
-        double y[NP];
-        for (int mm = 0; mm < NP; ++mm) {
-          y[mm] = log(fmax(sE[d][mm] / tot, 1e-30));
-          ybar += y[mm];
-        }
-        ybar /= NP;
-        double sxy = 0.0, sxx = 0.0;
-        for (int mm = 0; mm < NP; ++mm) {
-          sxy += (mm - mbar) * (y[mm] - ybar);
-          sxx += (mm - mbar) * (mm - mbar);
-        }
-        res = fabs(-sxy / sxx);
-      }
-      sI[d] = res;
-    }
-    __syncthreads();
-    Imin = fmin(Imin, fmin(sI[0], fmin(sI[1], sI[2])));
+  // the state is read once; every selected variable (in the order p, rho, Y)
+  // goes to its own field and the three transforms act on all fields at once
+  const bool use_p = prm.ind_vars & 1, use_r = prm.ind_vars & 2, use_y = NV == 6 && (prm.ind_vars & 4);
+  const int nf = (use_p ? 1 : 0) + (use_r ? 1 : 0) + (use_y ? 1 : 0);
+  for (int t = threadIdx.x; t < NP3; t += blockDim.x) {
+    double uu[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) uu[v] = u[v * m.n_node + base + t];
+    const Prim q = cons2prim<NV>(uu, m.gas);
+    int f = 0;
+    if (use_p) sq[(f++) * NP3 + t] = q.p;
+    if (use_r) sq[(f++) * NP3 + t] = q.rho;
+    if (use_y) sq[f * NP3 + t] = q.Y;
   }
+  __syncthreads();
+  contract_axis(sq, sw, sVi, NP, NP, nf, NP, NP, NP, 0);
+  __syncthreads();
+  contract_axis(sw, sq, sVi, NP, NP, nf, NP, NP, NP, 1);
+  __syncthreads();
+  contract_axis(sq, sw, sVi, NP, NP, nf, NP, NP, NP, 2);
+  __syncthreads();
+  // energies per field, direction and mode
+  for (int t = threadIdx.x; t < nf * 3 * NP; t += blockDim.x) {
+    const int mm = t % NP, d = (t / NP) % 3, f = t / (3 * NP);
+    const double* w = sw + f * NP3;
+    double s = 0.0;
+    for (int a = 0; a < NP; ++a)
+      for (int b = 0; b < NP; ++b) {
+        int id;
+        if (d == 0) id = (b * NP + a) * NP + mm;
+        else if (d == 1) id = (b * NP + mm) * NP + a;
+        else id = (mm * NP + b) * NP + a;
+        s += w[id] * w[id];
+      }
+    sE[t] = s;
+  }
+  __syncthreads();
+  // decay slope per field and direction
+  for (int t = threadIdx.x; t < nf * 3; t += blockDim.x) {
+    const double* E = sE + t * NP;
+    double tot = 0.0;
+    for (int mm = 0; mm < NP; ++mm) tot += E[mm];
+    double res;
+    if (tot < 1e-300) {
+      res = INFINITY;
+    } else {
+      const double mbar = 0.5 * N;
+      double ybar = 0.0;
+      double y[NP];
+      for (int mm = 0; mm < NP; ++mm) {
+        y[mm] = log(fmax(E[mm] / tot, 1e-30));
+        ybar += y[mm];
+      }
+      ybar /= NP;
+      double sxy = 0.0, sxx = 0.0;
+      for (int mm = 0; mm < NP; ++mm) {
+        sxy += (mm - mbar) * (y[mm] - ybar);
+        sxx += (mm - mbar) * (mm - mbar);
+      }
+      res = fabs(-sxy / sxx);
+    }
+    sI[t] = res;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
+    double Imin = INFINITY;
+    for (int t = 0; t < nf * 3; ++t) Imin = fmin(Imin, sI[t]);
     const double x = (Imin - prm.ind_T) / prm.ind_dT;
     double a;
     if (x <= -1.0) a = 1.0;
@@ -1170,9 +1180,11 @@ hipError_t indicator(const MeshView& m, const ParamsDev& p, const int32_t* elist
                      const double* u, double* alpha, double* ind, hipStream_t s) {
   if (count == 0) return hipSuccess;
   if (m.nvar == 5)
-    hipLaunchKernelGGL((indicator_kernel<kN, 5>), dim3(count), dim3(64), 0, s, m, p, elist, count, u, alpha, ind);
+    hipLaunchKernelGGL((indicator_kernel<kN, 5>), dim3(count), dim3(ind_threads<kN>()), 0, s, m, p, elist, count,
+                       u, alpha, ind);
   else
-    hipLaunchKernelGGL((indicator_kernel<kN, 6>), dim3(count), dim3(64), 0, s, m, p, elist, count, u, alpha, ind);
+    hipLaunchKernelGGL((indicator_kernel<kN, 6>), dim3(count), dim3(ind_threads<kN>()), 0, s, m, p, elist, count,
+                       u, alpha, ind);
   return hipGetLastError();
 }
 
