@@ -638,44 +638,83 @@ indicator_kernel(MeshView m, ParamsDev prm, const int32_t* __restrict__ elist, i
     if (use_y) sq[f * NP3 + t] = q.Y;
   }
   __syncthreads();
-  contract_axis(sq, sw, sVi, NP, NP, nf, NP, NP, NP, 0);
+  // modal coefficients: V_Leg^{-1} along each axis, one input line per thread
+  // forming all NP outputs along it
+  for (int r = threadIdx.x; r < nf * NP * NP; r += blockDim.x) {        // [f][k][j][c] -> [f][k][j][m0]
+    double x[NP];
+#pragma unroll
+    for (int c = 0; c < NP; ++c) x[c] = sq[r * NP + c];
+#pragma unroll
+    for (int o = 0; o < NP; ++o) {
+      double acc = 0.0;
+#pragma unroll
+      for (int c = 0; c < NP; ++c) acc += sVi[o * NP + c] * x[c];
+      sw[r * NP + o] = acc;
+    }
+  }
   __syncthreads();
-  contract_axis(sw, sq, sVi, NP, NP, nf, NP, NP, NP, 1);
+  for (int r = threadIdx.x; r < nf * NP * NP; r += blockDim.x) {        // [f][k][c][m0] -> [f][k][m1][m0]
+    const int m0 = r % NP, kf = r / NP;
+    double x[NP];
+#pragma unroll
+    for (int c = 0; c < NP; ++c) x[c] = sw[(kf * NP + c) * NP + m0];
+#pragma unroll
+    for (int o = 0; o < NP; ++o) {
+      double acc = 0.0;
+#pragma unroll
+      for (int c = 0; c < NP; ++c) acc += sVi[o * NP + c] * x[c];
+      sq[(kf * NP + o) * NP + m0] = acc;
+    }
+  }
   __syncthreads();
-  contract_axis(sq, sw, sVi, NP, NP, nf, NP, NP, NP, 2);
+  for (int r = threadIdx.x; r < nf * NP * NP; r += blockDim.x) {        // [f][c][m1][m0] -> [f][m2][m1][m0]
+    const int m01 = r % (NP * NP), f = r / (NP * NP);
+    double x[NP];
+#pragma unroll
+    for (int c = 0; c < NP; ++c) x[c] = sq[f * NP3 + c * NP * NP + m01];
+#pragma unroll
+    for (int o = 0; o < NP; ++o) {
+      double acc = 0.0;
+#pragma unroll
+      for (int c = 0; c < NP; ++c) acc += sVi[o * NP + c] * x[c];
+      sw[f * NP3 + o * NP * NP + m01] = acc;
+    }
+  }
   __syncthreads();
-  // energies per field, direction and mode
+  // energies per field, direction and mode (one lane each; the index is base +
+  // a sa + b sb with the strides of the two directions summed over)
   for (int t = threadIdx.x; t < nf * 3 * NP; t += blockDim.x) {
     const int mm = t % NP, d = (t / NP) % 3, f = t / (3 * NP);
-    const double* w = sw + f * NP3;
+    const int base = d == 0 ? mm : (d == 1 ? mm * NP : mm * NP * NP);
+    const int sa = d == 0 ? NP : 1, sb = d == 2 ? NP : NP * NP;
+    const double* w = sw + f * NP3 + base;
     double s = 0.0;
     for (int a = 0; a < NP; ++a)
       for (int b = 0; b < NP; ++b) {
-        int id;
-        if (d == 0) id = (b * NP + a) * NP + mm;
-        else if (d == 1) id = (b * NP + mm) * NP + a;
-        else id = (mm * NP + b) * NP + a;
-        s += w[id] * w[id];
+        const double x = w[a * sa + b * sb];
+        s += x * x;
       }
     sE[t] = s;
   }
   __syncthreads();
-  // decay slope per field and direction
-  for (int t = threadIdx.x; t < nf * 3; t += blockDim.x) {
-    const double* E = sE + t * NP;
+  // ln of the energy shares, one lane per entry
+  for (int t = threadIdx.x; t < nf * 3 * NP; t += blockDim.x) {
+    const double* E = sE + (t / NP) * NP;
     double tot = 0.0;
     for (int mm = 0; mm < NP; ++mm) tot += E[mm];
+    sq[t] = tot < 1e-300 ? INFINITY : log(fmax(sE[t] / tot, 1e-30));
+  }
+  __syncthreads();
+  // decay slope per field and direction: least-squares line through (m, y_m)
+  for (int t = threadIdx.x; t < nf * 3; t += blockDim.x) {
+    const double* y = sq + t * NP;
     double res;
-    if (tot < 1e-300) {
+    if (y[0] == INFINITY) {                    // no energy at all
       res = INFINITY;
     } else {
       const double mbar = 0.5 * N;
       double ybar = 0.0;
-      double y[NP];
-      for (int mm = 0; mm < NP; ++mm) {
-        y[mm] = log(fmax(E[mm] / tot, 1e-30));
-        ybar += y[mm];
-      }
+      for (int mm = 0; mm < NP; ++mm) ybar += y[mm];
       ybar /= NP;
       double sxy = 0.0, sxx = 0.0;
       for (int mm = 0; mm < NP; ++mm) {
