@@ -25,6 +25,17 @@ namespace {
 
 constexpr int FACE_THREADS = 64;
 constexpr int GRID = 64;  // max points of a face grid: (MAXN+1)^2 = MAXFV^2 = 64
+static_assert(FACE_THREADS == 64, "the face workgroups are one wavefront");
+
+// Synchronisation of the one-wavefront face workgroups through LDS.  The LDS
+// operations of a wavefront are performed in program order, so a fence at
+// wavefront scope (no wait instruction; it only keeps the compiler from
+// moving memory accesses across it) is enough.  A workgroup barrier would in
+// addition wait for every global store still in flight.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
 
 // Gather a side's nodal trace into `dst[NV][n*n]` on the left side's face grid.
 template <int NV>
@@ -87,88 +98,56 @@ __device__ void write_side(double* dst_block, const double* src, int side, int o
   }
 }
 
-// Rows pp and qq of A ([nout][nin] row-major, nin <= MAXN + 1) in registers,
-// zero-padded.
-struct MapRows {
-  double ap[MAXN + 1], aq[MAXN + 1];
-  __device__ MapRows(const double* A, int nin, int pp, int qq) {
-#pragma unroll
-    for (int k = 0; k <= MAXN; ++k) {
-      ap[k] = k < nin ? A[pp * nin + k] : 0.0;
-      aq[k] = k < nin ? A[qq * nin + k] : 0.0;
-    }
-  }
-  // one output point of the 2D tensor map A (x) A of a [nin][nin] grid (p fastest)
-  __device__ double apply(const double* src, int nin) const {
-    double acc = 0.0;
-#pragma unroll
-    for (int q = 0; q <= MAXN; ++q) {
-      if (q < nin) {
-        double r = 0.0;
-#pragma unroll
-        for (int p = 0; p <= MAXN; ++p)
-          if (p < nin) r += ap[p] * src[q * nin + p];
-        acc += aq[q] * r;
-      }
-    }
-    return acc;
-  }
-};
+// The maps below take their sizes at run time but unroll over MAXN + 1 terms
+// without a branch per term: a coefficient past nin is zero, and the operand
+// index is clamped to nin - 1, so the extra terms add exact zeros to the sums
+// (a branch per term would make each one wait for its own LDS read).
+__device__ __forceinline__ int clamp_last(int k, int n) { return k < n ? k : n - 1; }
 
-// dst[v][nout^2] = (A (x) A) src[v][nin^2] in LDS, one output point per lane;
-// dst must not alias src, and the caller synchronises before reading dst.
-template <int NF>
-__device__ void map2d_to(const double* src, double* dst, const double* A, int nout, int nin) {
-  for (int t = threadIdx.x; t < nout * nout; t += blockDim.x) {
-    const int pp = t % nout, qq = t / nout;
-    const MapRows rows(A, nin, pp, qq);
-    for (int v = 0; v < NF; ++v) dst[v * GRID + t] = rows.apply(src + v * GRID, nin);
+// Row r of A ([nout][nin] row-major, nin <= MAXN + 1) in registers, zero-padded.
+__device__ __forceinline__ void load_row(const double* A, int nin, int r, double (&a)[MAXN + 1]) {
+#pragma unroll
+  for (int k = 0; k <= MAXN; ++k) {
+    const double x = A[r * nin + clamp_last(k, nin)];
+    a[k] = k < nin ? x : 0.0;
   }
 }
 
-// Separable (two-pass) forms of the same maps, for one-wave workgroups whose
-// barriers are free: pass 1 contracts p into T[f][q][pp] (nin rows of nout),
-// pass 2 contracts q.  The sums are those of MapRows::apply in the same order
-// (inner over p, outer over q), at nin + nout instead of nin^2 + nin products
-// per output point and field.  T must alias neither src nor dst; one workgroup
-// barrier inside, the caller synchronises around the call.
+// sum_k a[k] src[k * stride] over k < nin, in order of k
+__device__ __forceinline__ double dot_row(const double (&a)[MAXN + 1], const double* src, int stride, int nin) {
+  double acc = 0.0;
+#pragma unroll
+  for (int k = 0; k <= MAXN; ++k) acc += a[k] * src[clamp_last(k, nin) * stride];
+  return acc;
+}
+
+// 2D tensor maps A (x) A of face data [NF][GRID] on [nin][nin] grids (p
+// fastest) to [nout][nout] grids, in two passes, for the one-wavefront face
+// workgroups: pass 1 contracts p into T[f][q][pp] (nin rows of nout), pass 2
+// contracts q, so each output is the sum over q of A[qq][q] times the sum over
+// p of A[pp][p] src[q][p], at nin + nout products per output point and field.  T must alias neither src nor dst; one wave_sync
+// inside, the caller synchronises around the call.
 template <int NF>
 __device__ void map2d_pass1(const double* src, double* T, const double* A, int nout, int nin) {
   for (int t = threadIdx.x; t < nin * nout; t += blockDim.x) {
     const int pp = t % nout, q = t / nout;
     double a[MAXN + 1];
+    load_row(A, nin, pp, a);
 #pragma unroll
-    for (int p = 0; p <= MAXN; ++p) a[p] = p < nin ? A[pp * nin + p] : 0.0;
-#pragma unroll
-    for (int f = 0; f < NF; ++f) {
-      const double* row = src + f * GRID + q * nin;
-      double acc = 0.0;
-#pragma unroll
-      for (int p = 0; p <= MAXN; ++p)
-        if (p < nin) acc += a[p] * row[p];
-      T[f * GRID + t] = acc;
-    }
+    for (int f = 0; f < NF; ++f) T[f * GRID + t] = dot_row(a, src + f * GRID + q * nin, 1, nin);
   }
 }
 
 template <int NF>
 __device__ void map2d_sep_to(const double* src, double* T, double* dst, const double* A, int nout, int nin) {
   map2d_pass1<NF>(src, T, A, nout, nin);
-  __syncthreads();
+  wave_sync();
   for (int t = threadIdx.x; t < nout * nout; t += blockDim.x) {
     const int pp = t % nout, qq = t / nout;
     double a[MAXN + 1];
+    load_row(A, nin, qq, a);
 #pragma unroll
-    for (int q = 0; q <= MAXN; ++q) a[q] = q < nin ? A[qq * nin + q] : 0.0;
-#pragma unroll
-    for (int f = 0; f < NF; ++f) {
-      const double* col = T + f * GRID + pp;
-      double acc = 0.0;
-#pragma unroll
-      for (int q = 0; q <= MAXN; ++q)
-        if (q < nin) acc += a[q] * col[q * nout];
-      dst[f * GRID + t] = acc;
-    }
+    for (int f = 0; f < NF; ++f) dst[f * GRID + t] = dot_row(a, T + f * GRID + pp, nout, nin);
   }
 }
 
@@ -183,17 +162,10 @@ __device__ void map2d_pass2_side(double* dst_block, const double* T, const doubl
     int p = pp, q = qq;
     if (right) orient_map(o, pp, qq, nout, p, q);
     double a[MAXN + 1];
+    load_row(A, nin, qq, a);
 #pragma unroll
-    for (int c = 0; c <= MAXN; ++c) a[c] = c < nin ? A[qq * nin + c] : 0.0;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const double* col = T + v * GRID + pp;
-      double acc = 0.0;
-#pragma unroll
-      for (int c = 0; c <= MAXN; ++c)
-        if (c < nin) acc += a[c] * col[c * nout];
-      dst_block[(side * NV + v) * n2 + q * nout + p] = scale * acc;
-    }
+    for (int v = 0; v < NV; ++v)
+      dst_block[(side * NV + v) * n2 + q * nout + p] = scale * dot_row(a, T + v * GRID + pp, nout, nin);
   }
 }
 
@@ -201,12 +173,12 @@ template <int NV>
 __device__ void map2d_sep_side(double* dst_block, const double* src, double* T, const double* A, int nout,
                                int nin, int side, int o, bool right, double scale) {
   map2d_pass1<NV>(src, T, A, nout, nin);
-  __syncthreads();
+  wave_sync();
   map2d_pass2_side<NV>(dst_block, T, A, nout, nin, side, o, right, scale);
 }
 
-// One face, any class, by the whole (64-lane) workgroup, with three
-// workgroup barriers; B0..B3 are [NV][GRID] and sN, sNF [3][GRID] LDS arrays
+// One face, any class, by the whole (64-lane) workgroup, with a few
+// wave_syncs; B0..B3 are [NV][GRID] and sN, sNF [3][GRID] LDS arrays
 // of the caller.  Degree-jump and FV faces need them; conforming DG faces
 // take the pointwise branch.  The caller synchronises before reusing them.
 template <int NV>
@@ -254,12 +226,12 @@ __device__ void face_body(const MeshView& m, const ParamsDev& prm, const double*
     // and the buffers the other side leaves free serve as their scratch)
     gather_trace<NV>(m, u, eL, sideL, o, false, nL, B0);
     gather_trace<NV>(m, u, eR, sideR, o, true, nR, B1);
-    __syncthreads();
+    wave_sync();
     const double* LM = B0;
     const double* RM = B1;
     if (NL < M) { map2d_sep_to<NV>(B0, B3, B2, m.ops + m.tab.interp[NL][M], nM, nL); LM = B2; }
     if (NR < M) { map2d_sep_to<NV>(B1, B2, B3, m.ops + m.tab.interp[NR][M], nM, nR); RM = B3; }
-    __syncthreads();
+    wave_sync();
     double* F = NL < M ? B0 : B2;
     const int n2 = nM * nM;
     for (int t = threadIdx.x; t < n2; t += blockDim.x) {
@@ -280,7 +252,7 @@ __device__ void face_body(const MeshView& m, const ParamsDev& prm, const double*
         for (int v = 0; v < NV; ++v) bR[(sideR * NV + v) * n2 + qq * nM + pp] = -Fl[v];
       }
     }
-    __syncthreads();
+    wave_sync();
     if (NL < M) map2d_sep_side<NV>(bL, F, B3, m.ops + m.tab.project[M][NL], nL, nM, sideL, o, false, 1.0);
     if (NR < M) map2d_sep_side<NV>(bR, F, B1, m.ops + m.tab.project[M][NR], nR, nM, sideR, o, true, -1.0);
     return;
@@ -295,15 +267,17 @@ __device__ void face_body(const MeshView& m, const ParamsDev& prm, const double*
   else gather_trace<NV>(m, u, eR, sideR, o, true, nR, B1);
   for (int t = threadIdx.x; t < 3 * nM * nM; t += blockDim.x)
     sN[(t / (nM * nM)) * GRID + t % (nM * nM)] = nrm[t];
-  __syncthreads();
-  // at most one side is pure DG; its trace goes to the sub-face grid by the
-  // two-pass map, with the buffer the blended side leaves free as scratch
+  wave_sync();
+  // the normals go to the sub-face grid first (B2 as scratch); at most one
+  // side is pure DG, and its trace follows by the two-pass map, with the
+  // buffer the blended side leaves free as scratch
   const double* LF = B0;
   const double* RF = B1;
-  map2d_to<3>(sN, sNF, m.ops + m.tab.dg2fv[M], nF, nM);
+  map2d_sep_to<3>(sN, B2, sNF, m.ops + m.tab.dg2fv[M], nF, nM);
+  wave_sync();
   if (!(aL > 0.0)) { map2d_sep_to<NV>(B0, B3, B2, m.ops + m.tab.dg2fv[NL], nF, nL); LF = B2; }
   if (!(aR > 0.0)) { map2d_sep_to<NV>(B1, B2, B3, m.ops + m.tab.dg2fv[NR], nF, nR); RF = B3; }
-  __syncthreads();
+  wave_sync();
   double* F = LF == B2 ? B0 : B2;
   double* fvL = m.fvside + (size_t)eL * 6 * NV * n2F;
   double* fvR = m.fvside + (size_t)eR * 6 * NV * n2F;
@@ -326,15 +300,15 @@ __device__ void face_body(const MeshView& m, const ParamsDev& prm, const double*
       for (int v = 0; v < NV; ++v) fvR[(sideR * NV + v) * n2F + qq * nF + pp] = -Fl[v];
     }
   }
-  __syncthreads();
+  wave_sync();
   // both DG parts receive V^{FV->DG} F: first passes into two of the buffers
-  // other than F (all dead now), one barrier, second passes into the sides
+  // other than F (all dead now), one wave_sync, second passes into the sides
   const double ih2 = 1.0 / (h * h);
   double* TL = F == B0 ? B1 : B0;
   double* TR = F == B2 ? B3 : B2;
   map2d_pass1<NV>(F, TL, m.ops + m.tab.fv2dg[NL], nL, nF);
   map2d_pass1<NV>(F, TR, m.ops + m.tab.fv2dg[NR], nR, nF);
-  __syncthreads();
+  wave_sync();
   map2d_pass2_side<NV>(bL, TL, m.ops + m.tab.fv2dg[NL], nL, nF, sideL, o, false, ih2);
   map2d_pass2_side<NV>(bR, TR, m.ops + m.tab.fv2dg[NR], nR, nF, sideR, o, true, -ih2);
 }
@@ -430,7 +404,7 @@ face_mixed_kernel(MeshView m, ParamsDev prm, const int32_t* __restrict__ flist, 
     const int32_t* fc = m.faces + 5 * f;
     if (alpha && (alpha[fc[0]] > 0.0 || alpha[fc[2]] > 0.0)) continue;
     face_body<NV>(m, prm, u, alpha, f, B0, B1, B2, B3, sN, sNF);
-    __syncthreads();
+    wave_sync();
   }
 }
 
@@ -451,7 +425,7 @@ face_fv_kernel(MeshView m, ParamsDev prm, const double* __restrict__ u, const do
     const bool left = fc[0] == e && fc[1] == side;
     if (!left && alpha[fc[0]] > 0.0) continue;      // the blended left element owns it
     face_body<NV>(m, prm, u, alpha, f, B0, B1, B2, B3, sN, sNF);
-    __syncthreads();
+    wave_sync();
   }
 }
 
