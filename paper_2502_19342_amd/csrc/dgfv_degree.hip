@@ -490,9 +490,11 @@ fv_residual_kernel(MeshView m, ParamsDev prm) {
   __shared__ double sVp[NP * NFV];
   const int t = threadIdx.x;
   const double h = 2.0 / NFV;
-  if (t < NP * NFV) sVp[t] = m.ops[m.tab.fv2dg[N] + t];
+  // the grid spans the whole degree bucket: workgroups past the blended range
+  // leave before touching memory other than the range bounds
   const int w = m.blend_start[N] + blockIdx.x;
   if (w >= m.blend_start[N + 1]) return;
+  if (t < NP * NFV) sVp[t] = m.ops[m.tab.fv2dg[N] + t];
   const int e = m.blend_list[w];
   const int64_t base = m.elem_offset[e];
   // every global read of the element is issued here, ahead of the first barrier:
