@@ -239,10 +239,15 @@ def check_state(mesh: Mesh, stream=None) -> None:
     _check(_lib.dgfv_check_state(mesh._h, _stream(stream)))
 
 
-def indicator(mesh: Mesh, params: Params, u: torch.Tensor, stream=None):
-    """Per-element ``(alpha, I)`` (``dg_indicator``)."""
-    alpha = torch.empty(mesh.n_elem, dtype=torch.float64, device=u.device)
-    ind = torch.empty_like(alpha)
+def indicator(mesh: Mesh, params: Params, u: torch.Tensor, stream=None,
+              alpha: torch.Tensor | None = None, ind: torch.Tensor | None = None):
+    """Per-element ``(alpha, I)`` (``dg_indicator``), into ``alpha`` and ``ind`` when given."""
+    if alpha is None:
+        alpha = torch.empty(mesh.n_elem, dtype=torch.float64, device=u.device)
+    if ind is None:
+        ind = torch.empty_like(alpha)
+    mesh._alpha(alpha)
+    mesh._alpha(ind)
     _check(_lib.dg_indicator(mesh._h, ctypes.byref(params.c()), mesh._state(u, "u"), alpha.data_ptr(),
                              ind.data_ptr(), _stream(stream)))
     return alpha, ind

@@ -101,6 +101,13 @@ def test_indicator_parity_blast():
     assert torch.allclose(i_gpu.cpu()[fin], I_ora[fin], rtol=1e-11, atol=1e-11)
     assert torch.allclose(a_gpu.cpu(), a_ora, rtol=0, atol=1e-10)
     assert float(a_ora.max()) > 0
+    # into given buffers: the same values, and the buffers are the ones returned
+    a_out = torch.full_like(a_gpu, float("nan"))
+    i_out = torch.full_like(i_gpu, float("nan"))
+    a2, i2 = dgfv.indicator(c.gmesh, c.params, c.gpu(c.u), alpha=a_out, ind=i_out)
+    assert a2 is a_out and i2 is i_out
+    assert torch.equal(a_out, a_gpu) and torch.equal(torch.isfinite(i_out), torch.isfinite(i_gpu))
+    assert torch.equal(i_out[torch.isfinite(i_gpu)], i_gpu[torch.isfinite(i_gpu)])
     # RHS with the oracle's blending factors
     c.alpha = a_ora
     assert rel_err(c.gpu_rhs(), c.oracle_rhs()) <= rhs_tol(c)
