@@ -605,9 +605,14 @@ fv_residual_kernel(MeshView m, ParamsDev prm) {
 // ---------------------------------------------------------------------------
 // modal decay indicator and blending factor (one element per 64-lane workgroup)
 // ---------------------------------------------------------------------------
-// Lanes per element of the indicator: one wave up to N = 4, four waves above.
+// Lanes per element of the indicator: one wave up to N = 4, two waves above.
 template <int N>
-constexpr int ind_threads() { return (N + 1) * (N + 1) * (N + 1) >= 216 ? 256 : 64; }
+constexpr int ind_threads() { return (N + 1) * (N + 1) * (N + 1) >= 216 ? 128 : 64; }
+
+// An empty asm statement with a memory clobber: LDS values read after it are
+// read there, so the operator rows of the modal transforms are not hoisted
+// out of their line loops and held in registers (64 doubles at N = 7).
+__device__ __forceinline__ void lds_reload() { asm volatile("" ::: "memory"); }
 
 template <int N, int NV>
 __global__ void __launch_bounds__(ind_threads<N>())
@@ -643,6 +648,7 @@ indicator_kernel(MeshView m, ParamsDev prm, const int32_t* __restrict__ elist, i
   // modal coefficients: V_Leg^{-1} along each axis, one input line per thread
   // forming all NP outputs along it
   for (int r = threadIdx.x; r < nf * NP * NP; r += blockDim.x) {        // [f][k][j][c] -> [f][k][j][m0]
+    lds_reload();
     double x[NP];
 #pragma unroll
     for (int c = 0; c < NP; ++c) x[c] = sq[r * NP + c];
@@ -657,6 +663,7 @@ indicator_kernel(MeshView m, ParamsDev prm, const int32_t* __restrict__ elist, i
   __syncthreads();
   for (int r = threadIdx.x; r < nf * NP * NP; r += blockDim.x) {        // [f][k][c][m0] -> [f][k][m1][m0]
     const int m0 = r % NP, kf = r / NP;
+    lds_reload();
     double x[NP];
 #pragma unroll
     for (int c = 0; c < NP; ++c) x[c] = sw[(kf * NP + c) * NP + m0];
@@ -671,6 +678,7 @@ indicator_kernel(MeshView m, ParamsDev prm, const int32_t* __restrict__ elist, i
   __syncthreads();
   for (int r = threadIdx.x; r < nf * NP * NP; r += blockDim.x) {        // [f][c][m1][m0] -> [f][m2][m1][m0]
     const int m01 = r % (NP * NP), f = r / (NP * NP);
+    lds_reload();
     double x[NP];
 #pragma unroll
     for (int c = 0; c < NP; ++c) x[c] = sq[f * NP3 + c * NP * NP + m01];
