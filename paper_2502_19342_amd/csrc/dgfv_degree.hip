@@ -57,6 +57,14 @@ element_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const d
   __shared__ double sAux[EPB][NA][NP3];
   __shared__ double sJa[EPB][3][NP3];          // Ja^d of the current direction
   __shared__ double sInc[NOFF > 0 ? EPB : 1][NV][NOFF > 0 ? NP3 : 1];
+  // One element per workgroup: the element's side fluxes (one contiguous block
+  // of 6 NV (N+1)^2 values) are loaded beside the state and parked in LDS before
+  // the first barrier, so the lift reads LDS instead of waiting on global loads
+  // at the end of the kernel.
+  constexpr bool STAGE_SIDES = EPB == 1;
+  constexpr int NSIDE = 6 * NV * NP2;
+  constexpr int SIDE_PER = STAGE_SIDES ? (NSIDE + NP3 - 1) / NP3 : 1;
+  __shared__ double sSide[STAGE_SIDES ? NSIDE : 1];
 
   const int tid = threadIdx.x;
   const int slot = tid / NP3;
@@ -75,6 +83,18 @@ element_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const d
   double uo[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) uo[v] = u[v * m.n_node + base];
+  const double al = alpha ? alpha[e] : 0.0;
+  const double* fs = m.fside + m.side_off[e];
+  double sv[SIDE_PER];
+  if constexpr (STAGE_SIDES) {
+    if (al < 1.0) {        // a pure FV element needs no side fluxes
+#pragma unroll
+      for (int r = 0; r < SIDE_PER; ++r) {
+        const int q = tid + r * NP3;
+        sv[r] = q < NSIDE ? fs[q] : 0.0;
+      }
+    }
+  }
 
   const int i = node % NP, j = (node / NP) % NP, kk = node / NP2;
   // stage 0: ut = R; stage s: k <- A k + dt R (k not read at stage 1), u <- u + B k,
@@ -103,7 +123,6 @@ element_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const d
       }
     }
   };
-  const double al = alpha ? alpha[e] : 0.0;
   if constexpr (EPB == 1) {
     // alpha = 1: a pure FV element.  The DG part has weight 0, so R = R^FV
     // exactly and none of it is evaluated (one element per workgroup: the
@@ -129,6 +148,13 @@ element_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const d
     FLUX::template make<NV>(q, r);
 #pragma unroll
     for (int a = 0; a < NA; ++a) sAux[slot][a][node] = r[a];
+  }
+  if constexpr (STAGE_SIDES) {
+#pragma unroll
+    for (int r = 0; r < SIDE_PER; ++r) {
+      const int q = tid + r * NP3;
+      if (q < NSIDE) sSide[q] = sv[r];
+    }
   }
   const double invJ = 1.0 / m.metric[9 * m.n_node + base];
 
@@ -309,10 +335,10 @@ element_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const d
 
   // surface lift: outward numerical flux over the end weight on boundary nodes
   const double inv_w0 = 1.0 / m.ops[m.tab.w[N]];
-  const double* fs = m.fside + m.side_off[e];
+  const double* side = STAGE_SIDES ? static_cast<const double*>(sSide) : fs;
   auto add_side = [&](int s, int fidx) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) acc[v] += fs[(s * NV + v) * NP2 + fidx] * inv_w0;
+    for (int v = 0; v < NV; ++v) acc[v] += side[(s * NV + v) * NP2 + fidx] * inv_w0;
   };
   if (i == 0) add_side(0, kk * NP + j);
   if (i == N) add_side(1, kk * NP + j);
