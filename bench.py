@@ -211,7 +211,7 @@ def adjoint_ratio(gm, prm, u, dgfv, torch, reps: int = 5):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build measures one GPU; --gpus must be 1", file=sys.stderr)
+        print("bench.py: the benchmark measures one GPU; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
     import torch
 
