@@ -320,7 +320,7 @@ constexpr int CONF_THREADS = 256;
 
 template <int N, int NV>
 __global__ void __launch_bounds__(CONF_THREADS)
-face_conforming_kernel(MeshView m, ParamsDev prm, const int32_t* __restrict__ flist, int fcount,
+face_conforming_kernel(MeshView m, ParamsDev prm, const ConfRec* __restrict__ rec, int fcount,
                        const double* __restrict__ u, const double* __restrict__ alpha,
                        const double* __restrict__ trace) {
   constexpr int NP = N + 1, NP2 = NP * NP, FPB = CONF_THREADS / NP2;
@@ -344,29 +344,29 @@ face_conforming_kernel(MeshView m, ParamsDev prm, const int32_t* __restrict__ fl
   if (slot >= FPB) return;
   const int fi = blockIdx.x * FPB + slot;
   if (fi >= fcount) return;
-  const int f = flist[fi];
-  const int32_t* fc = m.faces + 5 * f;
-  const int eL = fc[0], sideL = fc[1], eR = fc[2], sideR = fc[3], o = fc[4];
-  if (alpha && (alpha[eL] > 0.0 || alpha[eR] > 0.0)) return;
+  const ConfRec rc = rec[fi];
+  const int sideL = rc.code & 7, sideR = (rc.code >> 3) & 7, o = rc.code >> 6;
+  if (alpha && (alpha[rc.eL] > 0.0 || alpha[rc.eR] > 0.0)) return;
   const int p = r % NP, q = r / NP;
   int pp, qq;
   orient_map(o, p, q, NP, pp, qq);
   // where each side's state comes from: u, or for sides 0 and 1 (strided by
   // N+1 in u) the trace the previous stage wrote, contiguous per side
-  auto source = [&](int e, int side, int sp, int sq, const double*& src, int64_t& vstride) {
+  auto source = [&](int64_t base, int64_t sblk, int side, int sp, int sq, const double*& src,
+                    int64_t& vstride) {
     if (trace && side < 2) {
-      src = trace + m.side_off[e] / 3 + side * NV * NP2 + sq * NP + sp;
+      src = trace + sblk / 3 + side * NV * NP2 + sq * NP + sp;
       vstride = NP2;
     } else {
-      src = u + m.elem_offset[e] + side_node(side, sp, sq, NP);
+      src = u + base + side_node(side, sp, sq, NP);
       vstride = m.n_node;
     }
   };
   const double *sL, *sR;
   int64_t vL, vR;
-  source(eL, sideL, p, q, sL, vL);
-  source(eR, sideR, pp, qq, sR, vR);
-  const double* nrm = m.face_norm + m.face_norm_off[f];
+  source(rc.baseL, rc.sideL, sideL, p, q, sL, vL);
+  source(rc.baseR, rc.sideR, sideR, pp, qq, sR, vR);
+  const double* nrm = m.face_norm + rc.nrm;
   const bool flip = PAIRED && (slot & 1);
   const double* sA = flip ? sR : sL;
   const double* sB = flip ? sL : sR;
@@ -383,8 +383,8 @@ face_conforming_kernel(MeshView m, ParamsDev prm, const int32_t* __restrict__ fl
     uR[v] = flip ? a[v] : b[v];
   }
   riemann<NV>(prm.face_flux_dg, prm.volume_flux, uL, uR, nrm[r], nrm[NP2 + r], nrm[2 * NP2 + r], m.gas, F);
-  double* bL = m.fside + m.side_off[eL];
-  double* bR = m.fside + m.side_off[eR];
+  double* bL = m.fside + rc.sideL;
+  double* bR = m.fside + rc.sideR;
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     bL[(sideL * NV + v) * NP2 + q * NP + p] = F[v];
@@ -686,7 +686,7 @@ static hipError_t launch_face_class_t(const MeshView& m, const ParamsDev& p, con
     if (cnt == 0) return hipSuccess;
     const int np2 = (N + 1) * (N + 1), fpb = CONF_THREADS / np2;
     const dim3 grid((cnt + fpb - 1) / fpb), block(CONF_THREADS);
-    const int32_t* fl = m.face_conf[N];
+    const ConfRec* fl = m.face_conf_rec[N];
     switch (N) {
       case 1: hipLaunchKernelGGL((face_conforming_kernel<1, NV>), grid, block, 0, s, m, p, fl, cnt, u, alpha, tr); break;
       case 2: hipLaunchKernelGGL((face_conforming_kernel<2, NV>), grid, block, 0, s, m, p, fl, cnt, u, alpha, tr); break;

@@ -749,6 +749,21 @@ dgfv_status dgfv_mesh_create(const dgfv_mesh_desc* d, dgfv_mesh** out) {
       for (int N = 0; N <= MAXN; ++N) {
         v.face_conf[N] = conf[N].empty() ? nullptr : m->keep(dev_upload(conf[N]));
         v.face_conf_count[N] = (int)conf[N].size();
+        std::vector<ConfRec> rec(conf[N].size());
+        for (size_t i = 0; i < conf[N].size(); ++i) {
+          const int32_t* fc = d->faces + 5 * (size_t)conf[N][i];
+          ConfRec& r = rec[i];
+          r.baseL = m->offset[fc[0]];
+          r.baseR = m->offset[fc[2]];
+          r.sideL = side_off[fc[0]];
+          r.sideR = side_off[fc[2]];
+          r.nrm = fnorm_off[conf[N][i]];
+          r.eL = fc[0];
+          r.eR = fc[2];
+          r.code = fc[1] | (fc[3] << 3) | (fc[4] << 6);
+          r.pad = 0;
+        }
+        v.face_conf_rec[N] = rec.empty() ? nullptr : m->keep(dev_upload(rec));
       }
       v.face_mixed = mixed.empty() ? nullptr : m->keep(dev_upload(mixed));
       v.face_mixed_count = (int)mixed.size();

@@ -39,6 +39,18 @@ struct ParamsDev {
   double ind_T, ind_dT;
 };
 
+// One entry of a per-degree conforming face list with everything the face
+// kernel addresses, gathered at set-up: one load replaces the dependent chain
+// list -> face -> element offsets.
+struct alignas(16) ConfRec {
+  int64_t baseL, baseR;   // elem_offset of the left and right elements
+  int64_t sideL, sideR;   // side_off of the left and right elements
+  int64_t nrm;            // face_norm_off of the face
+  int32_t eL, eR;         // the elements
+  int32_t code;           // left side | right side << 3 | orientation << 6
+  int32_t pad;
+};
+
 // Everything a kernel needs to address the mesh (device pointers).
 struct MeshView {
   int K, nvar, n_fv, n_face;
@@ -61,6 +73,7 @@ struct MeshView {
   double* fvnorm;               // sub-face normals of internal planes, [K][3][3][(NFV-1) NFV^2]
   const int32_t* elem_face;     // [K][6] face of each element side
   const int32_t* face_conf[MAXN + 1];   // faces with NL = NR = N
+  const ConfRec* face_conf_rec[MAXN + 1];   // the same lists as records
   int face_conf_count[MAXN + 1];
   const int32_t* face_mixed;    // faces with NL != NR
   int face_mixed_count;
