@@ -78,8 +78,13 @@ element_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const d
   // of the flux).
   for (int t = tid; t < NP * NP; t += blockDim.x) sD[t] = FLUX::FAST_WEIGHT * m.ops[m.tab.D[N] + t];
 
-  const int e = elist[active ? idx : 0];
+  // with one element per workgroup the element index is wave-uniform: kept in
+  // a scalar register, its per-element records (offsets, alpha, side block)
+  // are scalar loads held in scalar registers for the whole kernel
+  int e = elist[active ? idx : 0];
+  if constexpr (EPB == 1) e = __builtin_amdgcn_readfirstlane(e);
   const int64_t base = m.elem_offset[e] + node;
+  const double inv_w0 = 1.0 / m.ops[m.tab.w[N]];    // lift weight, loaded early
   double uo[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) uo[v] = u[v * m.n_node + base];
@@ -334,7 +339,6 @@ element_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const d
   if (!active) return;
 
   // surface lift: outward numerical flux over the end weight on boundary nodes
-  const double inv_w0 = 1.0 / m.ops[m.tab.w[N]];
   const double* side = STAGE_SIDES ? static_cast<const double*>(sSide) : fs;
   auto add_side = [&](int s, int fidx) {
 #pragma unroll
