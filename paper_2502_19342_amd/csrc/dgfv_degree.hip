@@ -527,13 +527,32 @@ fv_residual_kernel(MeshView m, ParamsDev prm) {
   if (t < NP * NFV) sVp[t] = m.ops[m.tab.fv2dg[N] + t];
   const int e = m.blend_list[w];
   const int64_t base = m.elem_offset[e];
-  // every global read of the element is issued here, ahead of the first barrier:
-  // the sub-cell means, side fluxes and J into LDS, this thread's sub-face
-  // normals into registers
-  const double* ub = m.ubar + (size_t)e * NV * S3;
-  for (int r = t; r < NV * S3; r += FV2_THREADS) sU[r] = ub[r];
-  const double* fvs = m.fvside + (size_t)e * 6 * NV * S2;
-  for (int r = t; r < 6 * NV * S2; r += FV2_THREADS) sF[r] = fvs[r];
+  // every global read of the element is issued here, ahead of the first barrier
+  // and before any of them is used: the sub-cell means, side fluxes and J go to
+  // LDS, this thread's sub-face normals stay in registers.  The copy loops have
+  // compile-time trip counts and unroll, so the loads do not wait on each other.
+  constexpr int NUB = NV * S3, NFS = 6 * NV * S2;
+  constexpr int PU = (NUB + FV2_THREADS - 1) / FV2_THREADS;
+  constexpr int PF = (NFS + FV2_THREADS - 1) / FV2_THREADS;
+  constexpr int PJ = (NP3 + FV2_THREADS - 1) / FV2_THREADS;
+  const double* ub = m.ubar + (size_t)e * NUB;
+  const double* fvs = m.fvside + (size_t)e * NFS;
+  double xu[PU], xf[PF], xj[PJ];
+#pragma unroll
+  for (int i = 0; i < PU; ++i) {
+    const int r = t + i * FV2_THREADS;
+    xu[i] = ub[r < NUB ? r : NUB - 1];
+  }
+#pragma unroll
+  for (int i = 0; i < PF; ++i) {
+    const int r = t + i * FV2_THREADS;
+    xf[i] = fvs[r < NFS ? r : NFS - 1];
+  }
+#pragma unroll
+  for (int i = 0; i < PJ; ++i) {
+    const int r = t + i * FV2_THREADS;
+    xj[i] = m.metric[9 * m.n_node + base + (r < NP3 ? r : NP3 - 1)];
+  }
   const double* nrm = m.fvnorm + (size_t)e * 9 * NIF;
   const bool active = t < S3;
   const int s0 = t % NFV, s1 = (t / NFV) % NFV, s2 = t / S2;
@@ -542,12 +561,29 @@ fv_residual_kernel(MeshView m, ParamsDev prm) {
   for (int d = 0; d < 3; ++d) {
     const int sd = d == 0 ? s0 : (d == 1 ? s1 : s2);
     const int ta = d == 2 ? s1 : s2, tb = d == 0 ? s1 : s0;
-    const int k = (sd * NFV + ta) * NFV + tb;
     const bool has = active && sd < NFV - 1;
+    const int k = has ? (sd * NFV + ta) * NFV + tb : 0;     // an in-range index either way
 #pragma unroll
-    for (int c = 0; c < 3; ++c) nd[d][c] = has ? nrm[(d * 3 + c) * NIF + k] : 0.0;
+    for (int c = 0; c < 3; ++c) {
+      const double x = nrm[(d * 3 + c) * NIF + k];
+      nd[d][c] = has ? x : 0.0;
+    }
   }
-  for (int r = t; r < NP3; r += FV2_THREADS) sJ[r] = m.metric[9 * m.n_node + base + r];
+#pragma unroll
+  for (int i = 0; i < PU; ++i) {
+    const int r = t + i * FV2_THREADS;
+    if (r < NUB) sU[r] = xu[i];
+  }
+#pragma unroll
+  for (int i = 0; i < PF; ++i) {
+    const int r = t + i * FV2_THREADS;
+    if (r < NFS) sF[r] = xf[i];
+  }
+#pragma unroll
+  for (int i = 0; i < PJ; ++i) {
+    const int r = t + i * FV2_THREADS;
+    if (r < NP3) sJ[r] = xj[i];
+  }
   double dC[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) dC[v] = 0.0;
