@@ -261,12 +261,47 @@ __device__ void face_body(const MeshView& m, const ParamsDev& prm, const double*
   // FV face: sub-face traces, one flux per sub-face
   const int nF = m.n_fv, n2F = nF * nF;
   const double h = 2.0 / nF;
-  if (aL > 0.0) gather_subcells<NV>(m, eL, sideL, o, false, B0);
-  else gather_trace<NV>(m, u, eL, sideL, o, false, nL, B0);
-  if (aR > 0.0) gather_subcells<NV>(m, eR, sideR, o, true, B1);
-  else gather_trace<NV>(m, u, eR, sideR, o, true, nR, B1);
-  for (int t = threadIdx.x; t < 3 * nM * nM; t += blockDim.x)
-    sN[(t / (nM * nM)) * GRID + t % (nM * nM)] = nrm[t];
+  {
+    // both sides' data (sub-cell means of a blended side, the nodal trace of a
+    // DG side, the right side re-indexed onto the left grid) and the normals:
+    // one point of each grid per lane, every load issued before the first store
+    // (separate copy loops would wait for each other's loads)
+    static_assert(GRID == FACE_THREADS, "one point per lane");
+    const int t = threadIdx.x;
+    const int nl = aL > 0.0 ? nF : nL, nr = aR > 0.0 ? nF : nR, nn = nM * nM;
+    const int S3 = nF * nF * nF;
+    auto source = [&](int e, int side, double a, int n, bool right, const double*& src, int64_t& vs) {
+      const int tc = t < n * n ? t : 0;          // in-range index for idle lanes
+      int p = tc % n, q = tc / n;
+      if (right) orient_map(o, p, q, n, p, q);
+      if (a > 0.0) {
+        src = m.ubar + (size_t)e * NV * S3 + side_node(side, p, q, n);
+        vs = S3;
+      } else {
+        src = u + m.elem_offset[e] + side_node(side, p, q, n);
+        vs = m.n_node;
+      }
+    };
+    const double *srcL, *srcR;
+    int64_t vL, vR;
+    source(eL, sideL, aL, nl, false, srcL, vL);
+    source(eR, sideR, aR, nr, true, srcR, vR);
+    const int tn = t < nn ? t : 0;
+    double xl[NV], xr[NV], xn[3];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      xl[v] = srcL[v * vL];
+      xr[v] = srcR[v * vR];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) xn[c] = nrm[c * nn + tn];
+    if (t < nl * nl)
+      for (int v = 0; v < NV; ++v) B0[v * GRID + t] = xl[v];
+    if (t < nr * nr)
+      for (int v = 0; v < NV; ++v) B1[v * GRID + t] = xr[v];
+    if (t < nn)
+      for (int c = 0; c < 3; ++c) sN[c * GRID + t] = xn[c];
+  }
   wave_sync();
   // the normals go to the sub-face grid first (B2 as scratch); at most one
   // side is pure DG, and its trace follows by the two-pass map, with the
