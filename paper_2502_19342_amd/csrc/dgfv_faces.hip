@@ -224,8 +224,32 @@ __device__ void face_body(const MeshView& m, const ParamsDev& prm, const double*
     // degree jump: both traces at the common degree M, flux there, the lower
     // side receives the L2 projection (two-pass maps; exactly one side is lower,
     // and the buffers the other side leaves free serve as their scratch)
-    gather_trace<NV>(m, u, eL, sideL, o, false, nL, B0);
-    gather_trace<NV>(m, u, eR, sideR, o, true, nR, B1);
+    // both traces and this lane's normal at the common degree are loaded
+    // before the first store (separate copy loops would wait for each other's
+    // loads); the flux loop below visits at most one point per lane, that of
+    // threadIdx.x, as a face grid has at most GRID = FACE_THREADS points
+    static_assert(GRID == FACE_THREADS, "one point per lane");
+    const int n2 = nM * nM;
+    {
+      const int t = threadIdx.x;
+      const int tl = t < nL * nL ? t : 0, tr = t < nR * nR ? t : 0;
+      int pr = tr % nR, qr = tr / nR;
+      orient_map(o, pr, qr, nR, pr, qr);
+      const double* srcL = u + m.elem_offset[eL] + side_node(sideL, tl % nL, tl / nL, nL);
+      const double* srcR = u + m.elem_offset[eR] + side_node(sideR, pr, qr, nR);
+      double xl[NV], xr[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        xl[v] = srcL[v * m.n_node];
+        xr[v] = srcR[v * m.n_node];
+      }
+      if (t < nL * nL)
+        for (int v = 0; v < NV; ++v) B0[v * GRID + t] = xl[v];
+      if (t < nR * nR)
+        for (int v = 0; v < NV; ++v) B1[v * GRID + t] = xr[v];
+    }
+    const int tn = (int)threadIdx.x < n2 ? (int)threadIdx.x : 0;
+    const double xn0 = nrm[tn], xn1 = nrm[n2 + tn], xn2 = nrm[2 * n2 + tn];
     wave_sync();
     const double* LM = B0;
     const double* RM = B1;
@@ -233,15 +257,13 @@ __device__ void face_body(const MeshView& m, const ParamsDev& prm, const double*
     if (NR < M) { map2d_sep_to<NV>(B1, B2, B3, m.ops + m.tab.interp[NR][M], nM, nR); RM = B3; }
     wave_sync();
     double* F = NL < M ? B0 : B2;
-    const int n2 = nM * nM;
     for (int t = threadIdx.x; t < n2; t += blockDim.x) {
       double uL[NV], uR[NV], Fl[NV];
       for (int v = 0; v < NV; ++v) {
         uL[v] = LM[v * GRID + t];
         uR[v] = RM[v * GRID + t];
       }
-      riemann<NV>(prm.face_flux_dg, prm.volume_flux, uL, uR, nrm[t], nrm[n2 + t], nrm[2 * n2 + t],
-                  m.gas, Fl);
+      riemann<NV>(prm.face_flux_dg, prm.volume_flux, uL, uR, xn0, xn1, xn2, m.gas, Fl);
       for (int v = 0; v < NV; ++v) F[v * GRID + t] = Fl[v];
       const int p = t % nM, q = t / nM;
       if (NL == M)
