@@ -76,8 +76,16 @@ enum { DGFV_RIEMANN_ROE_HH = 0, /* Roe with the Harten-Hyman entropy fix, 1 spec
  * if bit 2 is set, else (p, q); then p' = n-1-a if bit 0, else a; q' = n-1-b
  * if bit 1, else b.  Every element side must appear in exactly one face
  * (periodic, conforming meshes).
- * Metrics are formed in the conservative curl form at degree metric_degree
- * (<= min N_e) and interpolated to each element's degree (Section 3.1.1).
+ * Metrics Ja^d are formed in the conservative curl form (Section 3.1.1):
+ *  - metric_degree >= 1 (at most min N_e): on the degree-metric_degree nodes,
+ *    interpolated to each element's degree;
+ *  - metric_degree == 0: at each element's own degree.  On a face shared with
+ *    a neighbour of lower degree Nf, the two tangential components of
+ *    X_l grad X_m on the face are replaced by their degree-Nf interpolant
+ *    before the curl, so both sides hold the same face normal polynomial
+ *    (free-stream preservation across degree jumps); formed in long double
+ *    and rounded once.  Exact for trilinear elements where the element and
+ *    the neighbour across each face have degree >= 2.
  */
 typedef struct {
   int32_t n_elem;
@@ -87,7 +95,7 @@ typedef struct {
   int32_t n_face;
   const int32_t* faces;    /* [n_face][5]                               */
   int32_t n_fv;            /* FV sub-cells per direction, max(N_e)+1 .. 8 */
-  int32_t metric_degree;   /* N_J, 1 <= N_J <= min(N_e)                 */
+  int32_t metric_degree;   /* N_J, 1 <= N_J <= min(N_e), or 0: per element */
   double gamma;            /* ratio of specific heats, n_var = 5        */
   double kappa[2];         /* species heat-capacity ratios, n_var = 6   */
   double R[2];             /* species gas constants, n_var = 6          */

@@ -152,6 +152,31 @@ def interp(N: int, M: int) -> np.ndarray:
     return _f64([_lagrange_row(xN, t) for t in xM])
 
 
+def _ld(rows) -> np.ndarray:
+    return np.array([[np.longdouble(mp.nstr(v, 30)) for v in r] for r in rows], dtype=np.longdouble)
+
+
+@functools.lru_cache(maxsize=None)
+def lgl_ld(N: int) -> np.ndarray:
+    """LGL nodes in long double (for metric terms rounded once)."""
+    x, _ = lgl_mp(N)
+    return _ld([x])[0]
+
+
+@functools.lru_cache(maxsize=None)
+def dmat_ld(N: int) -> np.ndarray:
+    """D in long double."""
+    return _ld(dmat_mp(N))
+
+
+@functools.lru_cache(maxsize=None)
+def interp_ld(N: int, M: int) -> np.ndarray:
+    """V^{N->M} in long double."""
+    xN, _ = lgl_mp(N)
+    xM, _ = lgl_mp(M)
+    return _ld([_lagrange_row(xN, t) for t in xM])
+
+
 @functools.lru_cache(maxsize=None)
 def project(M: int, N: int) -> np.ndarray:
     """V^{M->N} for M > N: modal L2 truncation of a degree-M nodal polynomial to degree N."""

@@ -239,6 +239,120 @@ void curl_metrics(const double* corners, int NJ, const std::vector<double>& xJ,
   }
 }
 
+int side_node_h(int s, int p, int q, int n);
+
+// Per-element metrics whose face normals match the neighbours' (metric_degree 0).
+// The curl form Ja^d_n = -(curl_xi W)_d, W = X_l grad_xi X_m, is taken at the
+// element degree N.  A face shared with a neighbour of lower degree Nf gets, in
+// place of W's two tangential components at its nodes, their degree-Nf
+// interpolant (through W's exact values at the Nf face points), so the face
+// normal (the tangential curl of W on the face) is the neighbour's polynomial.
+// On trilinear elements W's component along an edge is linear along it, so
+// two faces never disagree on a shared edge.  Long double throughout, rounded
+// once, so that the two sides of a face hold the same normal to rounding.
+void trilinear_ld(const double* c, long double x1, long double x2, long double x3, long double X[3],
+                  long double G[3][3]) {
+  using LD = long double;
+  const LD ph[2][3] = {{0.5L * (1 - x1), 0.5L * (1 - x2), 0.5L * (1 - x3)},
+                       {0.5L * (1 + x1), 0.5L * (1 + x2), 0.5L * (1 + x3)}};
+  const LD dph[2] = {-0.5L, 0.5L};
+  for (int n = 0; n < 3; ++n) {
+    X[n] = 0;
+    for (int a = 0; a < 3; ++a) G[n][a] = 0;
+  }
+  for (int k = 0; k < 8; ++k) {
+    const int b0 = k & 1, b1 = (k >> 1) & 1, b2 = (k >> 2) & 1;
+    const LD w = ph[b0][0] * ph[b1][1] * ph[b2][2];
+    const LD g0 = dph[b0] * ph[b1][1] * ph[b2][2];
+    const LD g1 = ph[b0][0] * dph[b1] * ph[b2][2];
+    const LD g2 = ph[b0][0] * ph[b1][1] * dph[b2];
+    for (int n = 0; n < 3; ++n) {
+      const LD cn = c[3 * k + n];
+      X[n] += cn * w;
+      G[n][0] += cn * g0;
+      G[n][1] += cn * g1;
+      G[n][2] += cn * g2;
+    }
+  }
+}
+
+void dxi_ld(const std::vector<long double>& D, int n, const long double* f, long double* out, int a) {
+  for (int k = 0; k < n; ++k)
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i) {
+        long double s = 0.0L;
+        const int r = a == 0 ? i : (a == 1 ? j : k);
+        for (int m = 0; m < n; ++m) {
+          const int idx = a == 0 ? (k * n + j) * n + m : (a == 1 ? (k * n + m) * n + i : (m * n + j) * n + i);
+          s += D[r * n + m] * f[idx];
+        }
+        out[(k * n + j) * n + i] = s;
+      }
+}
+
+// out: [9][(N+1)^3], component 3d + n; nbr[s]: degree across side s.
+void matched_metrics(const double* corners, int N, const int nbr[6], double* out) {
+  using LD = long double;
+  const int n = N + 1, n3 = n * n * n;
+  const std::vector<LD> x = lgl_nodes(N), D = ld_D(N);
+  std::vector<LD> X(3 * n3), G(9 * n3);
+  for (int k = 0; k < n; ++k)
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i) {
+        LD Xp[3], Gp[3][3];
+        trilinear_ld(corners, x[i], x[j], x[k], Xp, Gp);
+        for (int c = 0; c < 3; ++c) X[c * n3 + (k * n + j) * n + i] = Xp[c];
+      }
+  std::vector<LD> W(3 * n3), tmp(n3), dA(n3), dB(n3);
+  for (int nn = 0; nn < 3; ++nn) {
+    const int mm = (nn + 1) % 3, ll = (nn + 2) % 3;
+    for (int a = 0; a < 3; ++a) {
+      dxi_ld(D, n, &X[mm * n3], tmp.data(), a);
+      for (int t = 0; t < n3; ++t) W[a * n3 + t] = X[ll * n3 + t] * tmp[t];
+    }
+    for (int s = 0; s < 6; ++s) {
+      const int Nf = nbr[s];
+      if (Nf >= N) continue;
+      const int d = s / 2, nf = Nf + 1;
+      const LD endv = (s & 1) ? 1.0L : -1.0L;
+      const int ta = d == 0 ? 1 : 0, tb = d == 2 ? 1 : 2;   // face grid: p along ta, q along tb
+      const std::vector<LD> xf = lgl_nodes(Nf), V = ld_interp(Nf, N);
+      for (int a = 0; a < 3; ++a) {
+        if (a == d) continue;
+        std::vector<LD> Wf(nf * nf), mid(nf * n);
+        for (int qf = 0; qf < nf; ++qf)
+          for (int pf = 0; pf < nf; ++pf) {
+            LD r[3];
+            r[d] = endv;
+            r[ta] = xf[pf];
+            r[tb] = xf[qf];
+            LD Xp[3], Gp[3][3];
+            trilinear_ld(corners, r[0], r[1], r[2], Xp, Gp);
+            Wf[qf * nf + pf] = Xp[ll] * Gp[mm][a];
+          }
+        for (int qf = 0; qf < nf; ++qf)          // interpolate along p
+          for (int p = 0; p < n; ++p) {
+            LD acc = 0.0L;
+            for (int pf = 0; pf < nf; ++pf) acc += V[p * nf + pf] * Wf[qf * nf + pf];
+            mid[qf * n + p] = acc;
+          }
+        for (int q = 0; q < n; ++q)              // then along q, into W's face nodes
+          for (int p = 0; p < n; ++p) {
+            LD acc = 0.0L;
+            for (int qf = 0; qf < nf; ++qf) acc += V[q * nf + qf] * mid[qf * n + p];
+            W[a * n3 + side_node_h(s, p, q, n)] = acc;
+          }
+      }
+    }
+    for (int d = 0; d < 3; ++d) {
+      const int b = (d + 1) % 3, c = (d + 2) % 3;  // (curl W)_d = d_b W_c - d_c W_b
+      dxi_ld(D, n, &W[c * n3], dA.data(), b);
+      dxi_ld(D, n, &W[b * n3], dB.data(), c);
+      for (int t = 0; t < n3; ++t) out[(3 * d + nn) * n3 + t] = (double)(-(dA[t] - dB[t]));
+    }
+  }
+}
+
 // Tensor interpolation of nodal fields [nf][nin^3] to [nf][nout^3] with the 1D matrix V (nout x nin).
 void interp3(const std::vector<double>& V, int nin, int nout, const double* src, double* dst, int nf) {
   std::vector<double> a(nin * nin * nout), b(nin * nout * nout);
@@ -547,8 +661,8 @@ dgfv_status dgfv_mesh_create(const dgfv_mesh_desc* d, dgfv_mesh** out) {
     nmin = std::min(nmin, N);
     nmax = std::max(nmax, N);
   }
-  if (d->metric_degree < 1 || d->metric_degree > nmin)
-    return fail(DGFV_ERR_ARG, "metric_degree must be in 1..min(degree)");
+  if (d->metric_degree < 0 || d->metric_degree > nmin)
+    return fail(DGFV_ERR_ARG, "metric_degree must be 0 (per element) or in 1..min(degree)");
   if (d->n_fv < nmax + 1 || d->n_fv > MAXFV)
     return fail(DGFV_ERR_UNSUPPORTED, "n_fv must be in max(degree)+1 .. 8");
   if (d->n_face != 3 * d->n_elem)
@@ -617,27 +731,41 @@ dgfv_status dgfv_mesh_create(const dgfv_mesh_desc* d, dgfv_mesh** out) {
     }
 
     // ---- metrics and coordinates -------------------------------------------
-    const auto xJ = op_nodes(NJ);
-    const auto DJ = op_D(NJ);
+    // NJ >= 1: curl form at one mesh-wide degree NJ, interpolated to each degree;
+    // NJ == 0: per element at its own degree, faces matched to lower-degree neighbours
+    const int NJc = NJ > 0 ? NJ : 1;
+    const auto xJ = op_nodes(NJc);
+    const auto DJ = op_D(NJc);
     std::array<std::vector<double>, MAXN + 1> xN, VJN;
-    for (int N = 1; N <= MAXN; ++N)
-      if (present[N] || N == NJ) {
+    for (int N = 1; N <= MAXN; ++N) {
+      if (present[N] || N == NJc) {
         xN[N] = op_nodes(N);
-        VJN[N] = op_interp(NJ, N);   // identity rows when N == NJ? op_interp(N, N) is the identity
+        VJN[N] = op_interp(NJc, N);
       }
+    }
+    std::vector<int32_t> nbr((size_t)m->K * 6, 0);
+    for (int f = 0; f < d->n_face; ++f) {
+      const int32_t* fc = d->faces + 5 * f;
+      nbr[(size_t)fc[0] * 6 + fc[1]] = m->degree[fc[2]];
+      nbr[(size_t)fc[2] * 6 + fc[3]] = m->degree[fc[0]];
+    }
     std::vector<double> metric((size_t)10 * m->n_node);
     m->coords.assign((size_t)3 * m->n_node, 0.0);
     std::vector<uint8_t> bad(m->K, 0);
-    const int nJ = NJ + 1, nJ3 = nJ * nJ * nJ;
-    std::vector<double> JaJ_all((size_t)m->K * 9 * nJ3);
+    const int nJ = NJc + 1, nJ3 = nJ * nJ * nJ;
+    std::vector<double> JaJ_all(NJ > 0 ? (size_t)m->K * 9 * nJ3 : 0);
     parallel_for(m->K, [&](int64_t e) {
       const double* c = d->corners + 24 * e;
-      std::vector<double> JaJ;
-      curl_metrics(c, NJ, xJ, DJ, JaJ);
-      std::copy(JaJ.begin(), JaJ.end(), JaJ_all.begin() + e * 9 * nJ3);
       const int N = m->degree[e], n = N + 1, n3 = n * n * n;
       std::vector<double> JaN(9 * n3);
-      interp3(VJN[N], nJ, n, JaJ.data(), JaN.data(), 9);
+      if (NJ > 0) {
+        std::vector<double> JaJ;
+        curl_metrics(c, NJ, xJ, DJ, JaJ);
+        std::copy(JaJ.begin(), JaJ.end(), JaJ_all.begin() + e * 9 * nJ3);
+        interp3(VJN[N], nJ, n, JaJ.data(), JaN.data(), 9);
+      } else {
+        matched_metrics(c, N, &nbr[(size_t)e * 6], JaN.data());
+      }
       const int64_t base = m->offset[e];
       for (int t = 0; t < n3; ++t) {
         for (int comp = 0; comp < 9; ++comp) metric[(size_t)comp * m->n_node + base + t] = JaN[comp * n3 + t];
@@ -664,24 +792,34 @@ dgfv_status dgfv_mesh_create(const dgfv_mesh_desc* d, dgfv_mesh** out) {
       tot += 3 * (M + 1) * (M + 1);
     }
     std::vector<double> fnorm(tot);
+    std::array<std::array<std::vector<double>, MAXN + 1>, MAXN + 1> VLM;   // [NL][M], per-element mode
+    if (NJ == 0)
+      for (int a = 1; a <= MAXN; ++a)
+        for (int b = a; b <= MAXN; ++b)
+          if (present[a] && present[b]) VLM[a][b] = op_interp(a, b);
     parallel_for(m->F, [&](int64_t f) {
       const int32_t* fc = d->faces + 5 * f;
       const int eL = fc[0], sL = fc[1];
       const int M = std::max(m->degree[eL], m->degree[fc[2]]);
       const int nM = M + 1, dd = sL / 2;
       const double sign = (sL & 1) ? 1.0 : -1.0;
-      const double* JaJ = &JaJ_all[(size_t)eL * 9 * nJ3];
-      const auto& V = VJN[M];
-      // face slice of Ja^dd at the NJ grid, then 2D interpolation to M
+      // face slice of the left element's Ja^dd (at NJ, or at its own degree NL
+      // per element), then 2D interpolation to M
+      const int nS = NJ > 0 ? nJ : m->degree[eL] + 1;
+      const auto& V = NJ > 0 ? VJN[M] : VLM[nS - 1][M];
       for (int comp = 0; comp < 3; ++comp) {
-        std::vector<double> sl(nJ * nJ);
-        for (int q = 0; q < nJ; ++q)
-          for (int p = 0; p < nJ; ++p) sl[q * nJ + p] = JaJ[(3 * dd + comp) * nJ3 + side_node_h(sL, p, q, nJ)];
+        std::vector<double> sl(nS * nS);
+        for (int q = 0; q < nS; ++q)
+          for (int p = 0; p < nS; ++p) {
+            const int node = side_node_h(sL, p, q, nS);
+            sl[q * nS + p] = NJ > 0 ? JaJ_all[(size_t)eL * 9 * nJ3 + (3 * dd + comp) * nJ3 + node]
+                                    : metric[(size_t)(3 * dd + comp) * m->n_node + m->offset[eL] + node];
+          }
         for (int q = 0; q < nM; ++q)
           for (int p = 0; p < nM; ++p) {
             double acc = 0.0;
-            for (int b = 0; b < nJ; ++b)
-              for (int a = 0; a < nJ; ++a) acc += V[q * nJ + b] * V[p * nJ + a] * sl[b * nJ + a];
+            for (int b = 0; b < nS; ++b)
+              for (int a = 0; a < nS; ++a) acc += V[q * nS + b] * V[p * nS + a] * sl[b * nS + a];
             fnorm[fnorm_off[f] + comp * nM * nM + q * nM + p] = sign * acc;
           }
       }
@@ -991,15 +1129,19 @@ dgfv_status dg_rhs_vjp(const dgfv_mesh* m, const dgfv_params* prm, const double*
   if (batch < 1) return fail(DGFV_ERR_ARG, "batch must be positive");
   if (g == w || g == u) return fail(DGFV_ERR_ARG, "g must not overlap u or w");
   if (dgfv_status st = check_params(m, prm)) return st;
+#ifndef DGFV_CPU_ADJOINT_ALL_PATHS
   // The adjoint of FV-blended elements and of degree-jump faces faulted the GPU
-  // once with no cause found yet (the same kernels are clean and exact under a
-  // CPU emulation with bounds checking); those paths stay off until it is.
+  // once with no cause found: the same kernels run clean and exact in the CPU
+  // build of the library (every thread a fiber with wavefront semantics,
+  // guarded allocations, AddressSanitizer), which alone defines the macro
+  // above.  On the GPU those paths stay off until a cause is shown.
   if (alpha) return fail(DGFV_ERR_UNSUPPORTED, "dg_rhs_vjp: only alpha = NULL (pure DG) is enabled");
   {
     int degrees = 0;
     for (int N = 1; N <= MAXN; ++N) degrees += !m->bucket[N].empty();
     if (degrees > 1) return fail(DGFV_ERR_UNSUPPORTED, "dg_rhs_vjp: meshes with degree jumps are not enabled");
   }
+#endif
   const ParamsDev p = to_dev(prm);
   const MeshView& v = m->view;
   hipStream_t s = (hipStream_t)stream;

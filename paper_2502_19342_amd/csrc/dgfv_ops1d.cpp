@@ -165,13 +165,17 @@ std::vector<double> op_nodes(int N) { return to_double(lgl_nodes(N)); }
 std::vector<double> op_D(int N) { return to_double(dmat_ld(N)); }
 std::vector<double> op_vleg_inv(int N) { return to_double(inverse(vleg_ld(N), N + 1)); }
 
-std::vector<double> op_interp(int N, int M) {
+std::vector<LD> ld_D(int N) { return dmat_ld(N); }
+
+std::vector<LD> ld_interp(int N, int M) {
   const auto xN = lgl_nodes(N), xM = lgl_nodes(M);
   std::vector<LD> V((M + 1) * (N + 1));
   for (int i = 0; i <= M; ++i)
     for (int j = 0; j <= N; ++j) V[i * (N + 1) + j] = lagrange(xN, j, xM[i]);
-  return to_double(V);
+  return V;
 }
+
+std::vector<double> op_interp(int N, int M) { return to_double(ld_interp(N, M)); }
 
 std::vector<double> op_project(int M, int N) {
   const auto VN = vleg_ld(N);

@@ -7,6 +7,8 @@ namespace dgfv {
 
 std::vector<long double> lgl_nodes(int N);
 std::vector<long double> lgl_weights(int N);
+std::vector<long double> ld_D(int N);               // (N+1)^2, unrounded
+std::vector<long double> ld_interp(int N, int M);   // (M+1) x (N+1), unrounded
 
 std::vector<double> op_nodes(int N);
 std::vector<double> op_weights(int N);

@@ -20,7 +20,8 @@ def curved_mixed(n=3, nmin=2, nmax=4, n_var=5, scramble=None, amp=0.05, seed=7,
     if n_var == 6:
         kw = dict(kappa=W.GAS_AIR_H2["kappa"], R=W.GAS_AIR_H2["R"])
     wl = W.Workload("case", m, n_var, prim or W.density_wave, volume_flux, face_dg, face_fv,
-                    n_fv=n_fv or nmax + 1, metric_degree=metric_degree or min(2, nmin), **kw)
+                    n_fv=n_fv or nmax + 1,
+                    metric_degree=min(2, nmin) if metric_degree is None else metric_degree, **kw)
     return wl
 
 
@@ -106,3 +107,72 @@ def patch(spec, centres):
 
 def node_index(offsets, elems):
     return np.concatenate([np.arange(offsets[e], offsets[e + 1]) for e in elems])
+
+
+# ---------------------------------------------------------------------------
+# face traces and the Harten-Hyman switch (coverage checks of parity cases)
+# ---------------------------------------------------------------------------
+
+def face_traces(mesh, u):
+    """Left and right states and left outward n*s at every node of every face.
+
+    Faces with equal degree only; returns ``(uL, uR, nvec)`` as ``[nvar, P]``,
+    ``[nvar, P]`` and ``[3, P]`` over all face nodes P.
+    """
+    from oracle.geometry import face_slice
+    from oracle.rhs import to_left
+    UL, UR, NV = [], [], []
+    for eL, sL, eR, sR, o in np.asarray(mesh.faces).tolist():
+        NL, NR = int(mesh.degree[eL]), int(mesh.degree[eR])
+        if NL != NR:
+            continue
+        g = mesh.groups[NL]
+        tL = face_slice(mesh.gather(u, NL)[int(mesh.slot[eL])], sL)
+        tR = to_left(face_slice(mesh.gather(u, NR)[int(mesh.slot[eR])], sR), o)
+        UL.append(tL.reshape(tL.shape[0], -1))
+        UR.append(tR.reshape(tR.shape[0], -1))
+        nv = g.outward_normal(sL)[int(mesh.slot[eL])]
+        NV.append(nv.reshape(3, -1))
+    return torch.cat(UL, 1), torch.cat(UR, 1), torch.cat(NV, 1)
+
+
+def harten_hyman_active(uL, uR, nvec, gamma):
+    """Per face node: is the entropy fix active on an acoustic wave of the Roe solver?
+
+    Roe averages with sqrt(rho) weights, wave speeds v.n -+ c of the average and
+    of each side; the fix replaces |lam~| where |lam~| < max(0, lam~ - lam_L, lam_R - lam~).
+    """
+    n = nvec / torch.sqrt((nvec * nvec).sum(0))
+
+    def prim(u):
+        rho = u[0]
+        v = u[1:4] / rho
+        p = (gamma - 1.0) * (u[4] - 0.5 * rho * (v * v).sum(0))
+        return rho, v, p, (u[4] + p) / rho
+
+    rL, vL, pL, HL = prim(uL)
+    rR, vR, pR, HR = prim(uR)
+    wl, wr = torch.sqrt(rL), torch.sqrt(rR)
+    v = (wl * vL + wr * vR) / (wl + wr)
+    H = (wl * HL + wr * HR) / (wl + wr)
+    c = torch.sqrt((gamma - 1.0) * (H - 0.5 * (v * v).sum(0)))
+    vn, vnL, vnR = (v * n).sum(0), (vL * n).sum(0), (vR * n).sum(0)
+    cL, cR = torch.sqrt(gamma * pL / rL), torch.sqrt(gamma * pR / rR)
+    act = torch.zeros_like(vn, dtype=torch.bool)
+    for sg in (-1.0, 1.0):
+        lt, lL, lR = vn + sg * c, vnL + sg * cL, vnR + sg * cR
+        delta = torch.clamp(torch.maximum(lt - lL, lR - lt), min=0.0)
+        act |= lt.abs() < delta
+    return act
+
+
+def transonic_state(seed):
+    """Smooth state whose velocity along x stays within a few per cent of the sound speed."""
+    phis = [W.fourier_field(seed * 19 + i, 4, 2) for i in range(4)]
+
+    def f(x):
+        ph = [g(x) for g in phis]
+        c0 = np.sqrt(1.4)
+        vx = c0 * (1.0 + 0.03 * np.sin(2 * np.pi * x[:, 0]) + 0.01 * ph[1])
+        return np.stack([1.0 + 0.2 * ph[0], vx, 0.2 * ph[2], 0.2 * ph[3], np.ones(len(x))])
+    return f

@@ -17,7 +17,8 @@ from oracle import lsrk
 from paper_2502_19342_amd import workloads as W
 
 from gpu_common import Case, announce, rel_err, rhs_tol
-from oracle_cases import curved_mixed, seeded_alpha, smooth_state
+from oracle_cases import (curved_mixed, face_traces, harten_hyman_active, seeded_alpha, smooth_state,
+                          transonic_state)
 
 pytestmark = pytest.mark.gpu
 T = torch.float64
@@ -45,6 +46,19 @@ def test_flux_choices_rhs(vol, face):
     assert rel_err(c.gpu_rhs(), c.oracle_rhs()) <= RHS_TOL
 
 
+def test_roe_sonic_points_rhs():
+    # a flow through the sound speed: the Roe solver's Harten-Hyman branch is taken
+    # at face nodes on both sides of the sonic surfaces (Section 3.1.1)
+    announce("roe sonic points")
+    wl = curved_mixed(n=4, nmin=3, nmax=3, scramble=15, face_dg=W.RIEMANN_ROE_HH, metric_degree=3)
+    c = Case(wl, prim=transonic_state(17), noise=1e-2, seed=4)    # jumps across faces: delta > 0
+    uL, uR, nvec = face_traces(c.mesh, c.u)
+    hits = int(harten_hyman_active(uL, uR, nvec, c.gas.gamma).sum())
+    assert hits >= 40, hits
+    print(f"[gpu-case] Harten-Hyman fix active at {hits} of {uL.shape[1]} face nodes", flush=True)
+    assert rel_err(c.gpu_rhs(), c.oracle_rhs()) <= RHS_TOL
+
+
 @pytest.mark.parametrize("scramble", [None, 9])
 def test_curved_mixed_degree_blended_rhs(scramble):
     announce(f"curved mixed blended scramble={scramble}")
@@ -52,6 +66,22 @@ def test_curved_mixed_degree_blended_rhs(scramble):
     c = Case(wl, prim=smooth_state(73), noise=1e-3, seed=2)
     c.alpha = seeded_alpha(c.mesh.K, 11, values=(0.0, 0.0, 0.35, 1.0))
     assert rel_err(c.gpu_rhs(), c.oracle_rhs()) <= rhs_tol(c)
+
+
+@pytest.mark.parametrize("n_var", [5, 6])
+def test_per_element_metrics_rhs_and_freestream(n_var):
+    # metric_degree 0: curl form at each element's degree, faces matched to lower-degree
+    # neighbours; curved, scrambled, degrees 1..7 side by side, blended
+    announce(f"per-element metrics n_var={n_var}")
+    flux = {} if n_var == 5 else dict(volume_flux=W.VOL_PIROZZOLI, face_dg=W.RIEMANN_LLF)
+    wl = curved_mixed(n=3, nmin=1, nmax=7, n_var=n_var, scramble=5, metric_degree=0, n_fv=8, **flux)
+    c = Case(wl, prim=smooth_state(73, n_var), noise=1e-3, seed=2)
+    c.alpha = seeded_alpha(c.mesh.K, 11, values=(0.0, 0.0, 0.35, 1.0))
+    assert rel_err(c.gpu_rhs(), c.oracle_rhs()) <= rhs_tol(c)
+    fs = Case(wl, prim=lambda x: W.freestream(x, n_var))
+    from test_oracle_rhs import term_scale
+    scale = term_scale(fs.mesh, fs.gas, fs.f.params, fs.u)
+    assert float(fs.gpu_rhs().abs().max()) <= 1e-13 * scale
 
 
 def test_two_species_mixed_degree_blended_rhs():
