@@ -1,0 +1,98 @@
+"""Run C-ABI calls of the CPU build of the library (child process; test infrastructure).
+
+Usage: ``python drive.py in.npz out.npz`` with libasan preloaded.  ``in.npz``
+holds the mesh description, the parameters, the state and the list of calls;
+the results go to ``out.npz``.  Only numpy is imported here: the parent test
+computes the oracle's side.
+"""
+import ctypes
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+class MeshDesc(ctypes.Structure):
+    _fields_ = [("n_elem", ctypes.c_int32), ("n_var", ctypes.c_int32),
+                ("degree", ctypes.c_void_p), ("corners", ctypes.c_void_p),
+                ("n_face", ctypes.c_int32), ("faces", ctypes.c_void_p),
+                ("n_fv", ctypes.c_int32), ("metric_degree", ctypes.c_int32),
+                ("gamma", ctypes.c_double), ("kappa", ctypes.c_double * 2), ("R", ctypes.c_double * 2)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("volume_flux", ctypes.c_int32), ("face_flux_dg", ctypes.c_int32),
+                ("face_flux_fv", ctypes.c_int32), ("ind_vars", ctypes.c_int32),
+                ("ind_T", ctypes.c_double), ("ind_dT", ctypes.c_double)]
+
+
+def ptr(a):
+    return ctypes.c_void_p(a.ctypes.data) if a is not None else None
+
+
+def main(src, dst):
+    z = dict(np.load(src, allow_pickle=False))
+    lib = ctypes.CDLL(os.path.join(HERE, "_build", "libdgfv_cpu.so"))
+    lib.dgfv_last_error.restype = ctypes.c_char_p
+    P = ctypes.c_void_p
+
+    def check(st, what):
+        if st != 0:
+            raise RuntimeError(f"{what}: status {st}: {lib.dgfv_last_error().decode()}")
+
+    degree = np.ascontiguousarray(z["degree"], dtype=np.int8)
+    corners = np.ascontiguousarray(z["corners"], dtype=np.float64)
+    faces = np.ascontiguousarray(z["faces"], dtype=np.int32)
+    K = degree.shape[0]
+    desc = MeshDesc(K, int(z["n_var"]), ptr(degree), ptr(corners), faces.shape[0], ptr(faces),
+                    int(z["n_fv"]), int(z["metric_degree"]), float(z["gamma"]),
+                    (ctypes.c_double * 2)(*z["kappa"]), (ctypes.c_double * 2)(*z["R"]))
+    h = P()
+    check(lib.dgfv_mesh_create(ctypes.byref(desc), ctypes.byref(h)), "dgfv_mesh_create")
+    n_node = ctypes.c_int64()
+    check(lib.dgfv_mesh_info(h, ctypes.byref(n_node), None), "dgfv_mesh_info")
+    pr = z["params"]
+    prm = Params(int(pr[0]), int(pr[1]), int(pr[2]), int(pr[3]), float(pr[4]), float(pr[5]))
+    if "launch_mode" in z:
+        check(lib.dgfv_set_launch_mode(h, int(z["launch_mode"])), "launch mode")
+    u = np.ascontiguousarray(z["u"], dtype=np.float64)
+    alpha = np.ascontiguousarray(z["alpha"], dtype=np.float64) if "alpha" in z else None
+    out = {}
+    for call in [str(c) for c in z["calls"]]:
+        print(f"[cpu_hip] {call}", flush=True)
+        if call == "rhs":
+            r = np.empty_like(u)
+            check(lib.dg_rhs(h, ctypes.byref(prm), ptr(u), ptr(alpha), ptr(r), None), "dg_rhs")
+            out["rhs"] = r
+        elif call == "vjp":
+            w = np.ascontiguousarray(z["w"], dtype=np.float64)
+            g = np.empty_like(w)
+            check(lib.dg_rhs_vjp(h, ctypes.byref(prm), ptr(u), ptr(alpha), ptr(w), ptr(g),
+                                 ctypes.c_int(w.shape[0]), None), "dg_rhs_vjp")
+            out["vjp"] = g
+        elif call == "rk_step":
+            uu = u.copy()
+            k = np.empty_like(u)
+            check(lib.dg_rk_step(h, ctypes.byref(prm), ctypes.c_double(float(z["dt"])), ptr(uu), ptr(k),
+                                 ptr(alpha), None), "dg_rk_step")
+            out["rk_step"] = uu
+        elif call == "indicator":
+            a = np.empty(K)
+            ind = np.empty(K)
+            check(lib.dg_indicator(h, ctypes.byref(prm), ptr(u), ptr(a), ptr(ind), None), "dg_indicator")
+            out["alpha"], out["ind"] = a, ind
+        elif call == "coords":
+            xyz = np.empty((3, n_node.value))
+            check(lib.dgfv_mesh_node_coords(h, ptr(xyz)), "coords")
+            out["coords"] = xyz
+        else:
+            raise ValueError(call)
+    lib.dgfv_mesh_destroy(h)
+    np.savez(dst, **out)
+    print("[cpu_hip] done", flush=True)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1], sys.argv[2])

@@ -1,0 +1,109 @@
+"""The library's kernels and host code run on the CPU, against the oracle.
+
+The HIP sources are built with g++ against a CPU stand-in of the HIP runtime
+(``tests/cpu_hip``): every GPU thread is a fiber, wavefront operations act on
+64-lane wavefronts and stop the run when a shuffle reads a thread that has
+returned or the lanes of one wavefront split between a wavefront operation and
+a workgroup barrier; device allocations sit flush against inaccessible guard
+regions (after the end, then before the start) and start as NaN; everything
+runs under AddressSanitizer and UndefinedBehaviorSanitizer.  This is where new
+kernels and host code are checked before a GPU run, and where the adjoint of
+FV-blended elements and degree jumps, which stays off on the GPU (it faulted
+the GPU once, with no cause shown), is exercised.
+"""
+import types
+
+import numpy as np
+import pytest
+import torch
+
+import cpu_emu
+from gpu_common import oracle_spread, rel_err
+from oracle import lsrk, problem
+from paper_2502_19342_amd import workloads as W
+
+from oracle_cases import curved_mixed, seeded_alpha, smooth_state
+
+T = torch.float64
+
+
+def _case(wl, prim, noise=0.0, seed=0):
+    mesh, gas, f = problem.build(wl)
+    u = problem.initial_state(mesh, gas, prim)
+    if noise:
+        rng = np.random.default_rng(seed)
+        u = u * (1.0 + noise * torch.as_tensor(rng.standard_normal(tuple(u.shape))))
+    c = types.SimpleNamespace(wl=wl, mesh=mesh, gas=gas, f=f, u=u, alpha=torch.zeros(mesh.K, dtype=T))
+    c.oracle_rhs = lambda: c.f(c.u, c.alpha)
+    return c
+
+
+def _tol(c, base=1e-12):
+    return base if not bool((c.alpha > 0).any()) else max(base, 4.0 * oracle_spread(c))
+
+
+def test_cpu_build_c1_rhs_and_rk_step():
+    wl = W.make_workload("C1")
+    c = _case(wl, wl.prim)
+    dt = lsrk.timestep(c.mesh, c.gas, c.u, 0.5)
+    out = cpu_emu.run(wl, c.u.numpy(), ["rhs", "rk_step", "coords"], alpha=c.alpha.numpy(), dt=dt)
+    assert rel_err(torch.as_tensor(out["rhs"]), c.f(c.u, c.alpha)) <= 1e-12
+    ref = lsrk.step(lambda v: c.f(v, c.alpha), c.u, dt)
+    assert rel_err(torch.as_tensor(out["rk_step"]), ref) <= 1e-12
+    assert np.abs(out["coords"] - c.mesh.node_coords().numpy()).max() <= 1e-14
+
+
+@pytest.mark.parametrize("n_var", [5, 6])
+def test_cpu_build_per_element_metrics(n_var):
+    # metric_degree 0 on a curved, scrambled mesh with degrees 1..7 side by side
+    flux = {} if n_var == 5 else dict(volume_flux=W.VOL_PIROZZOLI, face_dg=W.RIEMANN_LLF)
+    wl = curved_mixed(n=3, nmin=1, nmax=7, n_var=n_var, scramble=5, metric_degree=0, n_fv=8, **flux)
+    c = _case(wl, smooth_state(73, n_var), noise=1e-3, seed=2)
+    c.alpha = seeded_alpha(c.mesh.K, 11, values=(0.0, 0.0, 0.35, 1.0))
+    fs = _case(wl, lambda x: W.freestream(x, n_var))
+    out = cpu_emu.run(wl, c.u.numpy(), ["rhs"], alpha=c.alpha.numpy())
+    assert rel_err(torch.as_tensor(out["rhs"]), c.f(c.u, c.alpha)) <= _tol(c)
+    out = cpu_emu.run(wl, fs.u.numpy(), ["rhs"], alpha=np.zeros(c.mesh.K))
+    from test_oracle_rhs import term_scale
+    assert np.abs(out["rhs"]).max() <= 1e-13 * term_scale(fs.mesh, fs.gas, fs.f.params, fs.u)
+
+
+def _oracle_vjp(c, w):
+    uu = c.u.clone().requires_grad_(True)
+    (g,) = torch.autograd.grad((c.f(uu, c.alpha) * w).sum(), uu)
+    return g
+
+
+def _vjp_tol(c, w, g_ref):
+    gen = torch.Generator().manual_seed(1)
+    worst = 0.0
+    for _ in range(2):
+        up = c.u * (1.0 + 2.0 ** -52 * torch.randn(tuple(c.u.shape), generator=gen, dtype=T))
+        worst = max(worst, rel_err(_oracle_vjp(types.SimpleNamespace(u=up, f=c.f, alpha=c.alpha), w), g_ref))
+    return max(1e-12, 4.0 * worst)
+
+
+@pytest.mark.parametrize("guard", ["end", "start"])
+def test_cpu_build_adjoint_blended_mixed_degree(guard):
+    # the case that faulted the GPU: 3^3, degrees 1..4, N_FV = 5, scrambled frames,
+    # alpha in {0, 0.4, 1}
+    wl = curved_mixed(n=3, nmin=1, nmax=4, scramble=23, metric_degree=1, n_fv=5)
+    c = _case(wl, smooth_state(83), noise=1e-3, seed=7)
+    c.alpha = seeded_alpha(c.mesh.K, 24, values=(0.0, 0.0, 0.4, 1.0))
+    w = torch.as_tensor(W.cotangents(84, tuple(c.u.shape)), dtype=T)
+    ws = torch.stack([w, torch.as_tensor(W.cotangents(85, tuple(c.u.shape)), dtype=T)])
+    out = cpu_emu.run(wl, c.u.numpy(), ["vjp"], alpha=c.alpha.numpy(), w=ws.numpy(), guard=guard)
+    for b in range(2):
+        g_ref = _oracle_vjp(c, ws[b])
+        assert rel_err(torch.as_tensor(out["vjp"][b]), g_ref) <= _vjp_tol(c, ws[b], g_ref)
+
+
+def test_cpu_build_adjoint_two_species_blended():
+    wl = curved_mixed(n=3, nmin=2, nmax=4, n_var=6, scramble=25, volume_flux=W.VOL_PIROZZOLI,
+                      face_dg=W.RIEMANN_LLF, n_fv=6)
+    c = _case(wl, smooth_state(85, n_var=6), noise=1e-3, seed=8)
+    c.alpha = seeded_alpha(c.mesh.K, 26, values=(0.0, 0.5, 1.0))
+    w = torch.as_tensor(W.cotangents(86, tuple(c.u.shape)), dtype=T)
+    out = cpu_emu.run(wl, c.u.numpy(), ["vjp"], alpha=c.alpha.numpy(), w=w.numpy()[None])
+    g_ref = _oracle_vjp(c, w)
+    assert rel_err(torch.as_tensor(out["vjp"][0]), g_ref) <= _vjp_tol(c, w, g_ref)
