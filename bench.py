@@ -67,13 +67,13 @@ def blend_mask(ind: np.ndarray, fraction: float, seed: int) -> np.ndarray:
 def initial_state_device(gm, wl, dgfv, torch, chunk=1 << 23):
     """Sample the workload's primitive state at the library's nodes, chunk by chunk, on the device."""
     xyz = gm.node_coords()
-    u = torch.empty((wl.n_var, gm.n_node), dtype=torch.float64, device="cuda")
+    w = torch.empty((wl.n_var, gm.n_node), dtype=torch.float64, device="cuda")
     for a in range(0, gm.n_node, chunk):
         b = min(gm.n_node, a + chunk)
-        w = wl.prim(np.ascontiguousarray(xyz[:, a:b].T))[: wl.n_var]
-        c = dgfv.prim_to_cons(w, wl.n_var, wl.gamma, wl.kappa, wl.R)
-        u[:, a:b] = torch.from_numpy(np.ascontiguousarray(c)).to("cuda")
+        w[:, a:b] = torch.from_numpy(np.ascontiguousarray(wl.prim(np.ascontiguousarray(xyz[:, a:b].T))[: wl.n_var]))
     del xyz
+    u = dgfv.prim_to_cons(gm, w)                 # on the device, with the mesh's gas
+    del w
     return u
 
 

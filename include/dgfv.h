@@ -222,6 +222,31 @@ dgfv_status dg_rhs_vjp(const dgfv_mesh* mesh, const dgfv_params* params, const d
                        void* stream);
 
 /*
+ * Reverse of one Runge-Kutta stage (Section 3.3) with alpha frozen.  The
+ * forward stage s maps (u_{s-1}, k_{s-1}) to k_s = A_s k_{s-1} + dt R(u_{s-1}),
+ * u_s = u_{s-1} + B_s k_s.  Given the cotangents ubar of u_s and kbar of k_s,
+ * this call replaces them, in place, by those of u_{s-1} and k_{s-1}:
+ *     kt = kbar + B_s ubar;  ubar <- ubar + dt (dR/du (u_{s-1}))^T kt;  kbar <- A_s kt
+ * (kbar <- 0 at stage 1), with the coefficients of dg_rk_stage.  u_stage_d is
+ * u_{s-1}, the state the forward stage read.  All three are [n_var][n_node]
+ * and must not overlap; alpha_d as for dg_rhs_vjp.  The first call on a mesh
+ * allocates one state-sized buffer, kept by the mesh (synchronous).
+ * A multi-step adjoint stores the state at each step start, recomputes the
+ * stage inputs with dg_rk_stage and calls this for stages 5..1.
+ */
+dgfv_status dg_rk_stage_vjp(const dgfv_mesh* mesh, const dgfv_params* params, int stage, double dt,
+                            const double* u_stage_d, double* ubar_d, double* kbar_d, const double* alpha_d,
+                            void* stream);
+
+/*
+ * Primitive to conservative variables (Section 2, eq. eos; mixing rules of
+ * eq. mix_R_kappa and eq. mix_cp_cv for two species) with the mesh's gas:
+ * w_d = (rho, v1, v2, v3, p[, Y1]) -> u_d = (rho, rho v, rho e[, rho Y1]),
+ * rho e = p / (kappa - 1) + rho |v|^2 / 2.  Both [n_var][n_node], distinct.
+ */
+dgfv_status dgfv_prim_to_cons(const dgfv_mesh* mesh, const double* w_d, double* u_d, void* stream);
+
+/*
  * Kernel timing with HIP events (measurement support, not part of the method).
  * dgfv_profile_enable(mesh, 1) clears the counters and makes every later call
  * on the mesh record an event pair around each phase below, on the stream the

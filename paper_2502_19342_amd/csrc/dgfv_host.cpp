@@ -131,6 +131,9 @@ struct dgfv_mesh {
   hipEvent_t flag_ev = nullptr;
   mutable bool flag_pending = false;
 
+  // state-sized buffer of dg_rk_stage_vjp, allocated by its first call
+  mutable double* stage_g = nullptr;
+
   // kernel timing (mutable: recording does not change the mesh)
   mutable bool profile = false;
   mutable std::array<std::vector<std::pair<hipEvent_t, hipEvent_t>>, DGFV_KERNEL_COUNT> ev;
@@ -156,6 +159,7 @@ struct dgfv_mesh {
         (void)hipEventDestroy(pr.second);
       }
     for (void* p : allocations) (void)hipFree(p);
+    if (stage_g) (void)hipFree(stage_g);
   }
   template <class T>
   T* keep(T* p) {
@@ -627,6 +631,57 @@ dgfv_status guarded(const dgfv_mesh* m, hipStream_t s, F&& call) {
   if (dgfv_status st = state_seen(m, s)) return st;
   if (dgfv_status st = call()) return st;
   return state_post(m, s);
+}
+
+// Which adjoint paths run (see dg_rhs_vjp).
+dgfv_status vjp_paths_enabled(const dgfv_mesh* m, const double* alpha) {
+#ifndef DGFV_CPU_ADJOINT_ALL_PATHS
+  // The adjoint of FV-blended elements and of degree-jump faces faulted the GPU
+  // once with no cause found: the same kernels run clean and exact in the CPU
+  // build of the library (every thread a fiber with wavefront semantics,
+  // guarded allocations, AddressSanitizer), which alone defines the macro
+  // above.  On the GPU those paths stay off until a cause is shown.
+  if (alpha) return fail(DGFV_ERR_UNSUPPORTED, "dg_rhs_vjp: only alpha = NULL (pure DG) is enabled");
+  int degrees = 0;
+  for (int N = 1; N <= MAXN; ++N) degrees += !m->bucket[N].empty();
+  if (degrees > 1) return fail(DGFV_ERR_UNSUPPORTED, "dg_rhs_vjp: meshes with degree jumps are not enabled");
+#else
+  (void)m;
+  (void)alpha;
+#endif
+  return DGFV_OK;
+}
+
+// g_b = (dR/du)^T w_b for b < batch, enqueued on s (throws HipError).
+void enqueue_vjp(const dgfv_mesh* m, const ParamsDev& p, const double* u, const double* alpha, const double* w,
+                 double* g, int batch, hipStream_t s) {
+  const MeshView& v = m->view;
+  const size_t plane = (size_t)m->nvar * m->n_node;
+  Timed t(m, DGFV_KERNEL_VJP, s);
+  if (alpha) {
+    hip_check(launch_blend_list(v, alpha, s), "blended list launch");
+    for (int N = 1; N <= MAXN; ++N)
+      if (!m->bucket[N].empty())
+        hip_check(ops_for(N).fv_means(v, (int)m->bucket[N].size(), 1, u, s), "fv_means launch");
+  }
+  for (int b = 0; b < batch; ++b) {
+    const double* wb = w + b * plane;
+    double* gb = g + b * plane;
+    for (int N = 1; N <= MAXN; ++N)
+      if (!m->bucket[N].empty())
+        hip_check(ops_for(N).vjp_volume(v, p, m->d_bucket[N], (int)m->bucket[N].size(), u, alpha, wb, gb, s),
+                  "vjp_volume launch");
+    if (alpha)
+      for (int N = 1; N <= MAXN; ++N)
+        if (!m->bucket[N].empty())
+          hip_check(ops_for(N).vjp_fv(v, p, m->d_bucket[N], (int)m->bucket[N].size(), alpha, wb, s),
+                    "vjp_fv launch");
+    hip_check(launch_faces_vjp(v, p, u, alpha, s), "face vjp launch");
+    for (int N = 1; N <= MAXN; ++N)
+      if (!m->bucket[N].empty())
+        hip_check(ops_for(N).vjp_gather(v, m->d_bucket[N], (int)m->bucket[N].size(), alpha, gb, s),
+                  "vjp_gather launch");
+  }
 }
 
 }  // namespace
@@ -1129,52 +1184,44 @@ dgfv_status dg_rhs_vjp(const dgfv_mesh* m, const dgfv_params* prm, const double*
   if (batch < 1) return fail(DGFV_ERR_ARG, "batch must be positive");
   if (g == w || g == u) return fail(DGFV_ERR_ARG, "g must not overlap u or w");
   if (dgfv_status st = check_params(m, prm)) return st;
-#ifndef DGFV_CPU_ADJOINT_ALL_PATHS
-  // The adjoint of FV-blended elements and of degree-jump faces faulted the GPU
-  // once with no cause found: the same kernels run clean and exact in the CPU
-  // build of the library (every thread a fiber with wavefront semantics,
-  // guarded allocations, AddressSanitizer), which alone defines the macro
-  // above.  On the GPU those paths stay off until a cause is shown.
-  if (alpha) return fail(DGFV_ERR_UNSUPPORTED, "dg_rhs_vjp: only alpha = NULL (pure DG) is enabled");
-  {
-    int degrees = 0;
-    for (int N = 1; N <= MAXN; ++N) degrees += !m->bucket[N].empty();
-    if (degrees > 1) return fail(DGFV_ERR_UNSUPPORTED, "dg_rhs_vjp: meshes with degree jumps are not enabled");
-  }
-#endif
-  const ParamsDev p = to_dev(prm);
-  const MeshView& v = m->view;
-  hipStream_t s = (hipStream_t)stream;
-  const size_t plane = (size_t)m->nvar * m->n_node;
+  if (dgfv_status st = vjp_paths_enabled(m, alpha)) return st;
   try {
-    Timed t(m, DGFV_KERNEL_VJP, s);
-    if (alpha) {
-      hip_check(launch_blend_list(v, alpha, s), "blended list launch");
-      for (int N = 1; N <= MAXN; ++N)
-        if (!m->bucket[N].empty())
-          hip_check(ops_for(N).fv_means(v, (int)m->bucket[N].size(), 1, u, s), "fv_means launch");
-    }
-    for (int b = 0; b < batch; ++b) {
-      const double* wb = w + b * plane;
-      double* gb = g + b * plane;
-      for (int N = 1; N <= MAXN; ++N)
-        if (!m->bucket[N].empty())
-          hip_check(ops_for(N).vjp_volume(v, p, m->d_bucket[N], (int)m->bucket[N].size(), u, alpha, wb, gb, s),
-                    "vjp_volume launch");
-      if (alpha)
-        for (int N = 1; N <= MAXN; ++N)
-          if (!m->bucket[N].empty())
-            hip_check(ops_for(N).vjp_fv(v, p, m->d_bucket[N], (int)m->bucket[N].size(), alpha, wb, s),
-                      "vjp_fv launch");
-      hip_check(launch_faces_vjp(v, p, u, alpha, s), "face vjp launch");
-      for (int N = 1; N <= MAXN; ++N)
-        if (!m->bucket[N].empty())
-          hip_check(ops_for(N).vjp_gather(v, m->d_bucket[N], (int)m->bucket[N].size(), alpha, gb, s),
-                    "vjp_gather launch");
-    }
+    enqueue_vjp(m, to_dev(prm), u, alpha, w, g, batch, (hipStream_t)stream);
   } catch (const HipError& e) {
     return fail(DGFV_ERR_HIP, e.what());
   }
+  return DGFV_OK;
+}
+
+dgfv_status dg_rk_stage_vjp(const dgfv_mesh* m, const dgfv_params* prm, int stage, double dt,
+                            const double* u_stage, double* ubar, double* kbar, const double* alpha,
+                            void* stream) {
+  if (!m || !u_stage || !ubar || !kbar) return fail(DGFV_ERR_ARG, "NULL argument");
+  if (stage < 1 || stage > 5) return fail(DGFV_ERR_ARG, "stage must be 1..5");
+  if (!std::isfinite(dt)) return fail(DGFV_ERR_ARG, "dt must be finite");
+  if (ubar == kbar || ubar == u_stage || kbar == u_stage)
+    return fail(DGFV_ERR_ARG, "u_stage, ubar and kbar must not overlap");
+  if (dgfv_status st = check_params(m, prm)) return st;
+  if (dgfv_status st = vjp_paths_enabled(m, alpha)) return st;
+  hipStream_t s = (hipStream_t)stream;
+  try {
+    if (!m->stage_g) m->stage_g = dev_alloc<double>((size_t)m->nvar * m->n_node);
+    const MeshView& v = m->view;
+    hip_check(launch_rk_adjoint_pre(v, RK_B[stage - 1], ubar, kbar, s), "rk adjoint launch");
+    enqueue_vjp(m, to_dev(prm), u_stage, alpha, kbar, m->stage_g, 1, s);
+    hip_check(launch_rk_adjoint_post(v, dt, RK_A[stage - 1], m->stage_g, ubar, kbar, s), "rk adjoint launch");
+  } catch (const HipError& e) {
+    const std::string msg = e.what();
+    return fail(msg.find("out of memory") != std::string::npos ? DGFV_ERR_OOM : DGFV_ERR_HIP, msg);
+  }
+  return DGFV_OK;
+}
+
+dgfv_status dgfv_prim_to_cons(const dgfv_mesh* m, const double* w, double* u, void* stream) {
+  if (!m || !w || !u) return fail(DGFV_ERR_ARG, "NULL argument");
+  if (w == u) return fail(DGFV_ERR_ARG, "w and u must not overlap");
+  if (hipError_t e = launch_prim_to_cons(m->view, w, u, (hipStream_t)stream))
+    return fail(DGFV_ERR_HIP, std::string("prim_to_cons launch: ") + hipGetErrorString(e));
   return DGFV_OK;
 }
 

@@ -158,4 +158,10 @@ hipError_t launch_face_class(const MeshView& m, const ParamsDev& p, const double
 hipError_t launch_faces_vjp(const MeshView& m, const ParamsDev& p, const double* u, const double* alpha,
                             hipStream_t s);
 
+// Pointwise state kernels (dgfv_state.hip).
+hipError_t launch_prim_to_cons(const MeshView& m, const double* w, double* u, hipStream_t s);
+hipError_t launch_rk_adjoint_pre(const MeshView& m, double B, const double* ubar, double* kbar, hipStream_t s);
+hipError_t launch_rk_adjoint_post(const MeshView& m, double dt, double A, const double* g, double* ubar,
+                                  double* kbar, hipStream_t s);
+
 }  // namespace dgfv

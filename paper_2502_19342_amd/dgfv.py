@@ -41,7 +41,8 @@ class _Params(ctypes.Structure):
 
 
 EXPORTED = ("dgfv_mesh_create", "dgfv_mesh_destroy", "dgfv_mesh_info", "dgfv_mesh_node_coords",
-            "dg_indicator", "dg_rhs", "dg_rk_stage", "dg_rk_step", "dg_rhs_vjp", "dgfv_set_launch_mode", "dgfv_autotune",
+            "dg_indicator", "dg_rhs", "dg_rk_stage", "dg_rk_step", "dg_rhs_vjp", "dg_rk_stage_vjp",
+            "dgfv_prim_to_cons", "dgfv_set_launch_mode", "dgfv_autotune",
             "dgfv_set_element_shape", "dgfv_check_state",
             "dgfv_profile_enable", "dgfv_profile_read", "dgfv_last_error")
 KERNEL_ELEMENT, KERNEL_FACE, KERNEL_FV_MEANS, KERNEL_FV_RESIDUAL, KERNEL_INDICATOR, KERNEL_VJP, KERNEL_FV_FACE = range(7)
@@ -63,6 +64,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dg_rk_stage.argtypes = [P, ctypes.POINTER(_Params), c_int, c_double, P, P, P, P]
     lib.dg_rk_step.argtypes = [P, ctypes.POINTER(_Params), c_double, P, P, P, P]
     lib.dg_rhs_vjp.argtypes = [P, ctypes.POINTER(_Params), P, P, P, P, c_int, P]
+    lib.dg_rk_stage_vjp.argtypes = [P, ctypes.POINTER(_Params), c_int, c_double, P, P, P, P, P]
+    lib.dgfv_prim_to_cons.argtypes = [P, P, P, P]
     lib.dgfv_set_launch_mode.argtypes = [P, c_int]
     lib.dgfv_set_element_shape.argtypes = [P, c_int, c_int]
     lib.dgfv_autotune.argtypes = [P, ctypes.POINTER(_Params), P, P, ctypes.POINTER(ctypes.c_double), P]
@@ -272,21 +275,12 @@ def rhs_vjp(mesh: Mesh, params: Params, u: torch.Tensor, alpha: torch.Tensor | N
     return out[0] if squeeze else out
 
 
-def prim_to_cons(w: np.ndarray, n_var: int, gamma: float = 1.4, kappa=(1.4, 1.4), R=(287.0, 287.0)) -> np.ndarray:
-    """Primitive (rho, v1, v2, v3, p[, Y1]) -> conservative variables, host arrays (input preparation)."""
-    rho, v, p = w[0], w[1:4], w[4]
-    if n_var == 6:
-        Y = w[5]
-        cv = [R[j] / (kappa[j] - 1.0) for j in range(2)]
-        cp = [kappa[j] * cv[j] for j in range(2)]
-        kap = (Y * cp[0] + (1 - Y) * cp[1]) / (Y * cv[0] + (1 - Y) * cv[1])
-    else:
-        kap = gamma
-    E = p / (kap - 1.0) + 0.5 * rho * (v * v).sum(0)
-    comps = [rho, rho * v[0], rho * v[1], rho * v[2], E]
-    if n_var == 6:
-        comps.append(rho * w[5])
-    return np.stack(comps)
+def prim_to_cons(mesh: Mesh, w: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Primitive ``(rho, v1, v2, v3, p[, Y1])`` -> conservative state on the device (``dgfv_prim_to_cons``)."""
+    if out is None:
+        out = torch.empty_like(w)
+    _check(_lib.dgfv_prim_to_cons(mesh._h, mesh._state(w, "w"), mesh._state(out, "out"), _stream(stream)))
+    return out
 
 
 # ---------------------------------------------------------------------------
@@ -309,21 +303,23 @@ class RHSFunction(torch.autograd.Function):
         return g, None, None, None
 
 
+def rk_stage_vjp(mesh: Mesh, params: Params, stage: int, dt: float, u_stage: torch.Tensor, ubar: torch.Tensor,
+                 kbar: torch.Tensor, alpha: torch.Tensor | None = None, stream=None) -> None:
+    """In-place reverse of Runge-Kutta stage ``stage`` (``dg_rk_stage_vjp``)."""
+    _check(_lib.dg_rk_stage_vjp(mesh._h, ctypes.byref(params.c()), int(stage), float(dt),
+                                mesh._state(u_stage, "u_stage"), mesh._state(ubar, "ubar"),
+                                mesh._state(kbar, "kbar"), mesh._alpha(alpha), _stream(stream)))
+
+
 def rk_step_vjp(mesh: Mesh, params: Params, dt: float, u0: torch.Tensor, ubar: torch.Tensor,
                 alpha: torch.Tensor | None = None, stream=None) -> torch.Tensor:
-    """Cotangent of the state at the start of one 2N RK step, given that of its end.
+    """Cotangent of the state at the start of one RK step, given that of its end.
 
-    The five stage inputs are recomputed from ``u0`` (k starts at zero since
-    A_1 = 0).  Per stage s = 5..1, with k_s = A_s k_{s-1} + dt R(u_{s-1}) and
-    u_s = u_{s-1} + B_s k_s:  kbar += B_s ubar;  ubar += dt (dR/du)^T kbar;
-    kbar = A_s kbar.
+    The stage inputs are recomputed from ``u0`` with ``dg_rk_stage``, then
+    ``dg_rk_stage_vjp`` runs stages 5..1 (the cotangent of k starts at zero:
+    nothing after the step reads its k).
     """
-    A = [0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
-         -3550918686646.0 / 2091501179385.0, -1275806237668.0 / 842570457699.0]
-    B = [1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
-         1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
-         2277821191437.0 / 14882151754819.0]
-    stages = [u0.clone()]
+    stages = [u0]
     u = u0.clone()
     k = torch.empty_like(u)
     for s in range(1, 5):
@@ -332,9 +328,7 @@ def rk_step_vjp(mesh: Mesh, params: Params, dt: float, u0: torch.Tensor, ubar: t
     ub = ubar.clone()
     kb = torch.zeros_like(ub)
     for s in range(5, 0, -1):
-        kb.add_(ub, alpha=B[s - 1])
-        ub.add_(rhs_vjp(mesh, params, stages[s - 1], alpha, kb, stream=stream), alpha=dt)
-        kb.mul_(A[s - 1])
+        rk_stage_vjp(mesh, params, s, dt, stages[s - 1], ub, kb, alpha, stream)
     return ub
 
 

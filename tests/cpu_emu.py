@@ -17,8 +17,9 @@ def _builder():
     return mod
 
 
-def run(wl, u, calls, alpha=None, w=None, dt=None, launch_mode=None, timeout=900, guard="end"):
-    """Mesh of workload ``wl``; ``calls`` in rhs, vjp, rk_step, indicator, coords."""
+def run(wl, u, calls, alpha=None, w=None, dt=None, launch_mode=None, timeout=900, guard="end", **extra):
+    """Mesh of workload ``wl``; ``calls`` in rhs, vjp, rk_step, stage_vjp, prim_to_cons,
+    indicator, coords (``extra`` arrays, e.g. stage, ubar, kbar, go to the child as they are)."""
     cpu_build = _builder()
     cpu_build.build()
     m = wl.mesh
@@ -36,6 +37,8 @@ def run(wl, u, calls, alpha=None, w=None, dt=None, launch_mode=None, timeout=900
         z["dt"] = float(dt)
     if launch_mode is not None:
         z["launch_mode"] = int(launch_mode)
+    for key, val in extra.items():
+        z[key] = np.asarray(val)
     with tempfile.TemporaryDirectory() as td:
         src, dst = os.path.join(td, "in.npz"), os.path.join(td, "out.npz")
         np.savez(src, **z)

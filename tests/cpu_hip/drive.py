@@ -83,6 +83,17 @@ def main(src, dst):
             ind = np.empty(K)
             check(lib.dg_indicator(h, ctypes.byref(prm), ptr(u), ptr(a), ptr(ind), None), "dg_indicator")
             out["alpha"], out["ind"] = a, ind
+        elif call == "stage_vjp":
+            ub = np.ascontiguousarray(z["ubar"], dtype=np.float64).copy()
+            kb = np.ascontiguousarray(z["kbar"], dtype=np.float64).copy()
+            check(lib.dg_rk_stage_vjp(h, ctypes.byref(prm), ctypes.c_int(int(z["stage"])),
+                                      ctypes.c_double(float(z["dt"])), ptr(u), ptr(ub), ptr(kb), ptr(alpha),
+                                      None), "dg_rk_stage_vjp")
+            out["ubar"], out["kbar"] = ub, kb
+        elif call == "prim_to_cons":
+            cu = np.empty_like(u)
+            check(lib.dgfv_prim_to_cons(h, ptr(u), ptr(cu), None), "dgfv_prim_to_cons")
+            out["cons"] = cu
         elif call == "coords":
             xyz = np.empty((3, n_node.value))
             check(lib.dgfv_mesh_node_coords(h, ptr(xyz)), "coords")

@@ -107,3 +107,30 @@ def test_cpu_build_adjoint_two_species_blended():
     out = cpu_emu.run(wl, c.u.numpy(), ["vjp"], alpha=c.alpha.numpy(), w=w.numpy()[None])
     g_ref = _oracle_vjp(c, w)
     assert rel_err(torch.as_tensor(out["vjp"][0]), g_ref) <= _vjp_tol(c, w, g_ref)
+
+
+def test_cpu_build_rk_stage_vjp_and_prim_to_cons():
+    # reverse of one RK stage on a blended mixed-degree mesh, against autograd
+    # through the oracle's stage; and the device primitive -> conservative map
+    wl = curved_mixed(n=3, nmin=2, nmax=4, scramble=37, n_fv=5)
+    c = _case(wl, smooth_state(103), noise=1e-3, seed=13)
+    c.alpha = seeded_alpha(c.mesh.K, 27, values=(0.0, 0.0, 0.5, 1.0))
+    dt = lsrk.timestep(c.mesh, c.gas, c.u, 0.5, c.alpha)
+    stage = 3
+    k0 = 0.1 * torch.as_tensor(W.cotangents(104, tuple(c.u.shape)), dtype=T)
+    ubar = torch.as_tensor(W.cotangents(105, tuple(c.u.shape)), dtype=T)
+    kbar = torch.as_tensor(W.cotangents(106, tuple(c.u.shape)), dtype=T)
+    uu = c.u.clone().requires_grad_(True)
+    kk = k0.clone().requires_grad_(True)
+    ks = lsrk.A_F64[stage - 1] * kk + dt * c.f(uu, c.alpha)
+    us = uu + lsrk.B_F64[stage - 1] * ks
+    gu, gk = torch.autograd.grad((us * ubar).sum() + (ks * kbar).sum(), (uu, kk))
+    out = cpu_emu.run(wl, c.u.numpy(), ["stage_vjp"], alpha=c.alpha.numpy(), dt=dt, stage=stage,
+                      ubar=ubar.numpy(), kbar=kbar.numpy())
+    tol = _vjp_tol(c, kbar + lsrk.B_F64[stage - 1] * ubar, gu)
+    assert rel_err(torch.as_tensor(out["ubar"]), gu) <= tol
+    assert rel_err(torch.as_tensor(out["kbar"]), gk) <= 1e-14
+    from oracle.physics import prim_to_cons
+    w = torch.as_tensor(np.asarray(smooth_state(107)(c.mesh.node_coords().numpy().T)), dtype=T)
+    out = cpu_emu.run(wl, w.numpy(), ["prim_to_cons"])
+    assert rel_err(torch.as_tensor(out["cons"]), prim_to_cons(w, c.gas)) <= 1e-15

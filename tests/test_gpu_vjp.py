@@ -111,9 +111,9 @@ def test_vjp_against_central_differences_c4():
     gm = dgfv.Mesh.from_workload(wl)
     prm = dgfv.params_of(wl)
     xyz = gm.node_coords()
-    u0 = dgfv.prim_to_cons(wl.prim(xyz.T), 5, wl.gamma)
-    u0 = u0 + W.noise(wl.seed, u0.shape, wl.noise)
-    u = torch.as_tensor(u0).to("cuda").contiguous()
+    wp = torch.as_tensor(np.asarray(wl.prim(xyz.T))[:5]).to("cuda").contiguous()
+    u = dgfv.prim_to_cons(gm, wp)
+    u = (u + torch.as_tensor(W.noise(wl.seed, tuple(u.shape), wl.noise)).to("cuda")).contiguous()
     w = torch.as_tensor(W.cotangents(41, tuple(u.shape))).to("cuda").contiguous()
     g = dgfv.rhs_vjp(gm, prm, u, None, w)
     rng = np.random.default_rng(42)
@@ -150,6 +150,43 @@ def test_checkpointed_rollout_matches_oracle():
     (out * c.gpu(w)).sum().backward()
     assert rel_err(out.detach().cpu(), x.detach()) <= 1e-10
     assert rel_err(ug.grad.cpu(), g_ref) <= 1e-10
+
+
+@pytest.mark.parametrize("stage", [1, 2, 3, 4, 5])
+def test_rk_stage_vjp_matches_oracle(stage):
+    # reverse of k_s = A_s k + dt R(u), u_s = u + B_s k_s: autograd through one oracle stage
+    announce(f"rk stage vjp s={stage}")
+    from paper_2502_19342_amd import dgfv
+    wl = curved_mixed(n=2, nmin=3, nmax=3, scramble=35)
+    c = Case(wl, prim=smooth_state(97), noise=1e-3, seed=12)
+    dt = lsrk.timestep(c.mesh, c.gas, c.u, 0.5)
+    k0 = 0.1 * cot(c, 98)
+    ubar, kbar = cot(c, 99), cot(c, 100)
+    uu = c.u.clone().requires_grad_(True)
+    kk = k0.clone().requires_grad_(True)
+    ks = lsrk.A_F64[stage - 1] * kk + dt * c.f(uu, c.alpha)
+    us = uu + lsrk.B_F64[stage - 1] * ks
+    gu, gk = torch.autograd.grad((us * ubar).sum() + (ks * kbar).sum(), (uu, kk))
+    ub, kb = c.gpu(ubar), c.gpu(kbar)
+    dgfv.rk_stage_vjp(c.gmesh, c.params, stage, dt, c.gpu(c.u), ub, kb, None)
+    torch.cuda.synchronize()
+    assert rel_err(ub.cpu(), gu) <= 1e-12
+    if stage == 1:
+        assert bool((kb == 0).all())
+    else:
+        assert rel_err(kb.cpu(), gk) <= 1e-14
+
+
+@pytest.mark.parametrize("n_var", [5, 6])
+def test_prim_to_cons_on_device(n_var):
+    announce(f"prim_to_cons n_var={n_var}")
+    from oracle.physics import prim_to_cons
+    from paper_2502_19342_amd import dgfv
+    wl = curved_mixed(n=2, nmin=2, nmax=3, n_var=n_var)
+    c = Case(wl, prim=smooth_state(101, n_var))
+    w = torch.as_tensor(np.asarray(smooth_state(102, n_var)(c.mesh.node_coords().numpy().T)), dtype=T)
+    u = dgfv.prim_to_cons(c.gmesh, c.gpu(w)).cpu()
+    assert rel_err(u, prim_to_cons(w, c.gas)) <= 1e-15
 
 
 def test_rhs_function_autograd():
