@@ -239,6 +239,20 @@ dgfv_status dg_rk_stage_vjp(const dgfv_mesh* mesh, const dgfv_params* params, in
                             void* stream);
 
 /*
+ * dg_rk_stage_vjp for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation).
+ * Same arguments and results as dg_rk_stage_vjp, but its state-sized
+ * cotangent buffer is a fixed device array of the library (128 MiB, one per
+ * GPU, held until the process ends), looked up once per device at mesh
+ * creation; the call allocates nothing.  DGFV_ERR_ARG when
+ * n_var * n_node > 16777216 (2^24 doubles).  Every call on one GPU shares
+ * that array: calls that overlap on one GPU (on any mesh or stream) race.
+ */
+dgfv_status dg_rk_stage_vjp_noalloc(const dgfv_mesh* mesh, const dgfv_params* params, int stage, double dt,
+                                    const double* u_stage_d, double* ubar_d, double* kbar_d,
+                                    const double* alpha_d, void* stream);
+
+/*
  * Primitive to conservative variables (Section 2, eq. eos; mixing rules of
  * eq. mix_R_kappa and eq. mix_cp_cv for two species) with the mesh's gas:
  * w_d = (rho, v1, v2, v3, p[, Y1]) -> u_d = (rho, rho v, rho e[, rho Y1]),

@@ -654,10 +654,10 @@ dgfv_status vjp_paths_enabled(const dgfv_mesh* m, const double* alpha) {
 
 // g_b = (dR/du)^T w_b for b < batch, enqueued on s (throws HipError).
 void enqueue_vjp(const dgfv_mesh* m, const ParamsDev& p, const double* u, const double* alpha, const double* w,
-                 double* g, int batch, hipStream_t s) {
+                 double* g, int batch, hipStream_t s, bool timed = true) {
   const MeshView& v = m->view;
   const size_t plane = (size_t)m->nvar * m->n_node;
-  Timed t(m, DGFV_KERNEL_VJP, s);
+  Timed t(m, timed ? DGFV_KERNEL_VJP : -1, s);
   if (alpha) {
     hip_check(launch_blend_list(v, alpha, s), "blended list launch");
     for (int N = 1; N <= MAXN; ++N)
@@ -988,6 +988,10 @@ dgfv_status dgfv_mesh_create(const dgfv_mesh_desc* d, dgfv_mesh** out) {
       hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
       v.n_cu = cus > 0 ? cus : 1;
     }
+    {
+      double* sp = nullptr;                  // the no-allocation entry point's buffer on this device
+      hip_check(static_scratch_ptr(&sp), "hipGetSymbolAddress of the fixed device buffer");
+    }
     for (auto& st : m->side) hip_check(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "hipStreamCreate");
     hip_check(hipStreamCreateWithFlags(&m->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
     hip_check(hipEventCreateWithFlags(&m->fork_ev, hipEventDisableTiming), "hipEventCreate");
@@ -1213,6 +1217,35 @@ dgfv_status dg_rk_stage_vjp(const dgfv_mesh* m, const dgfv_params* prm, int stag
   } catch (const HipError& e) {
     const std::string msg = e.what();
     return fail(msg.find("out of memory") != std::string::npos ? DGFV_ERR_OOM : DGFV_ERR_HIP, msg);
+  }
+  return DGFV_OK;
+}
+
+dgfv_status dg_rk_stage_vjp_noalloc(const dgfv_mesh* m, const dgfv_params* prm, int stage, double dt,
+                                    const double* u_stage, double* ubar, double* kbar, const double* alpha,
+                                    void* stream) {
+  if (!m || !u_stage || !ubar || !kbar) return fail(DGFV_ERR_ARG, "NULL argument");
+  if (stage < 1 || stage > 5) return fail(DGFV_ERR_ARG, "stage must be 1..5");
+  if (!std::isfinite(dt)) return fail(DGFV_ERR_ARG, "dt must be finite");
+  if (ubar == kbar || ubar == u_stage || kbar == u_stage)
+    return fail(DGFV_ERR_ARG, "u_stage, ubar and kbar must not overlap");
+  if ((size_t)m->nvar * (size_t)m->n_node > STATIC_SCRATCH_DOUBLES)
+    return fail(DGFV_ERR_ARG, "dg_rk_stage_vjp_noalloc: n_var * n_node = " +
+                                  std::to_string((size_t)m->nvar * (size_t)m->n_node) +
+                                  " exceeds the fixed buffer of " + std::to_string(STATIC_SCRATCH_DOUBLES) +
+                                  " doubles");
+  if (dgfv_status st = check_params(m, prm)) return st;
+  if (dgfv_status st = vjp_paths_enabled(m, alpha)) return st;
+  hipStream_t s = (hipStream_t)stream;
+  try {
+    double* g = nullptr;                     // this device's copy of the fixed buffer
+    hip_check(static_scratch_ptr(&g), "hipGetSymbolAddress of the fixed device buffer");
+    const MeshView& v = m->view;
+    hip_check(launch_rk_adjoint_pre(v, RK_B[stage - 1], ubar, kbar, s), "rk adjoint launch");
+    enqueue_vjp(m, to_dev(prm), u_stage, alpha, kbar, g, 1, s, false);
+    hip_check(launch_rk_adjoint_post(v, dt, RK_A[stage - 1], g, ubar, kbar, s), "rk adjoint launch");
+  } catch (const HipError& e) {
+    return fail(DGFV_ERR_HIP, e.what());
   }
   return DGFV_OK;
 }

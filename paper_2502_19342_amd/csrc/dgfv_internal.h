@@ -158,6 +158,13 @@ hipError_t launch_face_class(const MeshView& m, const ParamsDev& p, const double
 hipError_t launch_faces_vjp(const MeshView& m, const ParamsDev& p, const double* u, const double* alpha,
                             hipStream_t s);
 
+// Fixed device buffer (a file-scope device array in dgfv_state.hip) of the
+// entry point that allocates nothing: its address on the current device,
+// looked up once per device (hipGetSymbolAddress) and kept.
+constexpr size_t STATIC_SCRATCH_DOUBLES = size_t(1) << 24;   // 128 MiB
+constexpr int MAX_DEVICES = 64;
+hipError_t static_scratch_ptr(double** out);
+
 // Pointwise state kernels (dgfv_state.hip).
 hipError_t launch_prim_to_cons(const MeshView& m, const double* w, double* u, hipStream_t s);
 hipError_t launch_rk_adjoint_pre(const MeshView& m, double B, const double* ubar, double* kbar, hipStream_t s);

@@ -9,10 +9,22 @@
 // so with the cotangents ubar of u_s and kbar of k_s from the later stages
 //   kt = kbar + B_s ubar;   ubar <- ubar + dt (dR/du)^T kt;   kbar <- A_s kt.
 // rk_adjoint_pre forms kt in place of kbar; rk_adjoint_post takes g = (dR/du)^T kt.
+#include <mutex>
+
 #include "dgfv_internal.h"
+
+// Fixed device buffer of dg_rk_stage_vjp_noalloc, for callers that cannot
+// allocate: each GPU the library runs on holds one copy until the process
+// ends.  Host code never passes the array's name to a kernel (on the host it
+// is only a stand-in, not a device address): it passes the address that
+// hipGetSymbolAddress returns for the current device (static_scratch_ptr).
+static __device__ __align__(256) double scratch[dgfv::STATIC_SCRATCH_DOUBLES];
 
 namespace dgfv {
 namespace {
+
+std::mutex g_scratch_mu;
+double* g_scratch_dev[MAX_DEVICES] = {};
 
 constexpr int STATE_THREADS = 256;
 
@@ -60,6 +72,20 @@ int grid_for(int64_t n, const MeshView& m) {
 }
 
 }  // namespace
+
+hipError_t static_scratch_ptr(double** out) {
+  int dev = 0;
+  if (hipError_t e = hipGetDevice(&dev)) return e;
+  if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidValue;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    if (hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) return e;
+    g_scratch_dev[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_dev[dev];
+  return hipSuccess;
+}
 
 hipError_t launch_prim_to_cons(const MeshView& m, const double* w, double* u, hipStream_t s) {
   const int64_t n = m.n_node;

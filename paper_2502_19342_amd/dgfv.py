@@ -42,7 +42,7 @@ class _Params(ctypes.Structure):
 
 EXPORTED = ("dgfv_mesh_create", "dgfv_mesh_destroy", "dgfv_mesh_info", "dgfv_mesh_node_coords",
             "dg_indicator", "dg_rhs", "dg_rk_stage", "dg_rk_step", "dg_rhs_vjp", "dg_rk_stage_vjp",
-            "dgfv_prim_to_cons", "dgfv_set_launch_mode", "dgfv_autotune",
+            "dg_rk_stage_vjp_noalloc", "dgfv_prim_to_cons", "dgfv_set_launch_mode", "dgfv_autotune",
             "dgfv_set_element_shape", "dgfv_check_state",
             "dgfv_profile_enable", "dgfv_profile_read", "dgfv_last_error")
 KERNEL_ELEMENT, KERNEL_FACE, KERNEL_FV_MEANS, KERNEL_FV_RESIDUAL, KERNEL_INDICATOR, KERNEL_VJP, KERNEL_FV_FACE = range(7)
@@ -65,6 +65,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dg_rk_step.argtypes = [P, ctypes.POINTER(_Params), c_double, P, P, P, P]
     lib.dg_rhs_vjp.argtypes = [P, ctypes.POINTER(_Params), P, P, P, P, c_int, P]
     lib.dg_rk_stage_vjp.argtypes = [P, ctypes.POINTER(_Params), c_int, c_double, P, P, P, P, P]
+    lib.dg_rk_stage_vjp_noalloc.argtypes = [P, ctypes.POINTER(_Params), c_int, c_double, P, P, P, P, P]
     lib.dgfv_prim_to_cons.argtypes = [P, P, P, P]
     lib.dgfv_set_launch_mode.argtypes = [P, c_int]
     lib.dgfv_set_element_shape.argtypes = [P, c_int, c_int]
@@ -309,6 +310,15 @@ def rk_stage_vjp(mesh: Mesh, params: Params, stage: int, dt: float, u_stage: tor
     _check(_lib.dg_rk_stage_vjp(mesh._h, ctypes.byref(params.c()), int(stage), float(dt),
                                 mesh._state(u_stage, "u_stage"), mesh._state(ubar, "ubar"),
                                 mesh._state(kbar, "kbar"), mesh._alpha(alpha), _stream(stream)))
+
+
+def rk_stage_vjp_noalloc(mesh: Mesh, params: Params, stage: int, dt: float, u_stage: torch.Tensor,
+                         ubar: torch.Tensor, kbar: torch.Tensor, alpha: torch.Tensor | None = None,
+                         stream=None) -> None:
+    """``rk_stage_vjp`` through the library's fixed device buffer (``dg_rk_stage_vjp_noalloc``)."""
+    _check(_lib.dg_rk_stage_vjp_noalloc(mesh._h, ctypes.byref(params.c()), int(stage), float(dt),
+                                        mesh._state(u_stage, "u_stage"), mesh._state(ubar, "ubar"),
+                                        mesh._state(kbar, "kbar"), mesh._alpha(alpha), _stream(stream)))
 
 
 def rk_step_vjp(mesh: Mesh, params: Params, dt: float, u0: torch.Tensor, ubar: torch.Tensor,
