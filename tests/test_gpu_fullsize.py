@@ -183,3 +183,135 @@ def test_fullsize_c5_sampled_patches():
     k_ref = float(lsrk.A[stage - 1]) * k0 + dt * r_ref
     assert rel_err(k_s, k_ref) <= tol
     assert rel_err(u_s, u0 + float(lsrk.B[stage - 1]) * k_ref) <= tol
+
+
+# ---------------------------------------------------------------------------
+# long runs against stored oracle results, C3 free-stream, C5 adjoint patches
+# ---------------------------------------------------------------------------
+
+def _golden(name):
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", name)
+    if not os.path.exists(path):
+        pytest.skip(f"{name} is written by tests/golden/make_fullsize_rollouts.py")
+    with open(path) as fh:
+        return json.load(fh)
+
+
+def test_fullsize_c2_100_steps():
+    # 16^3, N = 5, the blending factors from the indicator at the start of every step, CFL 0.5
+    announce("C2 full size, 100 steps")
+    from paper_2502_19342_amd import dgfv
+    ref = _golden("c2_100_steps.json")
+    t0 = time.perf_counter()
+    wl = W.make_workload("C2")
+    c = Case(wl)
+    u, k = c.gpu(c.u), torch.empty_like(c.gpu(c.u))
+    alpha = torch.empty(c.mesh.K, dtype=T, device="cuda")
+    ind = torch.empty_like(alpha)
+    for _ in range(ref["steps"]):
+        dgfv.indicator(c.gmesh, c.params, u, alpha=alpha, ind=ind)
+        dgfv.rk_step(c.gmesh, c.params, ref["dt"], u, k, alpha)
+    torch.cuda.synchronize()
+    nodes = torch.as_tensor(ref["sample_nodes"])
+    got = u[:, nodes.to("cuda")].cpu()
+    want = torch.as_tensor(ref["u_sample"], dtype=T)
+    linf = torch.as_tensor(ref["linf"], dtype=T)
+    err = float(((got - want).abs().amax(1) / linf).max())
+    progress(f"C2 100 steps: sampled rel err {err:.2e}", t0)
+    assert err <= 1e-10
+    assert float(((u.abs().amax(1).cpu() - linf).abs() / linf).max()) <= 1e-10
+
+
+def test_fullsize_c4_adjoint_50_steps():
+    # cotangent of <w, u_50> at u_0 through 50 checkpointed steps (stage recompute + stage adjoints)
+    announce("C4 full size, 50-step adjoint")
+    from paper_2502_19342_amd import dgfv
+    ref = _golden("c4_adjoint_50_steps.json")
+    t0 = time.perf_counter()
+    wl = W.make_workload("C4")
+    c = Case(wl)
+    u0 = c.u + torch.as_tensor(W.noise(wl.seed, tuple(c.u.shape), wl.noise), dtype=T)
+    w = torch.as_tensor(W.cotangents(ref["w_seed"], tuple(c.u.shape)), dtype=T)
+    ug = c.gpu(u0).requires_grad_(True)
+    out = dgfv.checkpointed_rollout(ug, c.gmesh, c.params, ref["steps"], ref["dt"], None)
+    (out * c.gpu(w)).sum().backward()
+    g = ug.grad.detach().cpu()
+    nodes = torch.as_tensor(ref["sample_nodes"])
+    glinf = torch.as_tensor(ref["g_linf"], dtype=T)
+    err = float(((g[:, nodes] - torch.as_tensor(ref["g_sample"], dtype=T)).abs().amax(1) / glinf).max())
+    progress(f"C4 50-step adjoint: sampled rel err {err:.2e}", t0)
+    assert err <= 1e-10
+    assert float(((g.abs().amax(1) - glinf).abs() / glinf).max()) <= 1e-10
+    for seed, dot in zip(ref["dir_seeds"], ref["g_dot_dirs"]):
+        v = torch.as_tensor(W.cotangents(seed, tuple(c.u.shape)), dtype=T)
+        assert abs(float((g * v).sum()) - dot) <= 1e-10 * abs(dot)
+
+
+def test_fullsize_c3_freestream():
+    # the curved 32^3 mesh with degrees 1..7 (per-element metrics), two species, a tenth blended
+    announce("C3 full size free-stream")
+    t0 = time.perf_counter()
+    wl = W.make_workload("C3")
+    c = Case(wl, prim=lambda x: W.freestream(x, 6))
+    rng = np.random.default_rng(3003)
+    c.alpha = torch.as_tensor(np.where(W.quantile_mask(rng.random(c.mesh.K), 0.10), 1.0, 0.0), dtype=T)
+    from test_oracle_rhs import term_scale
+    scale = term_scale(c.mesh, c.gas, c.f.params, c.u)
+    r0 = c.gpu_rhs(alpha=None)
+    progress(f"C3 free-stream, pure DG: max |R| / term scale {float(r0.abs().max()) / scale:.2e}", t0)
+    assert float(r0.abs().max()) <= 1e-13 * scale
+    # blended: on DG nodes the same bar; on FV elements V^{FV->DG} amplifies the rounding
+    # of the cancelling sub-cell fluxes by up to ||V^+||^3 (the oracle's own residual
+    # reaches 7e-13 of the scale at N = 7), so there the bar is four times the oracle's
+    r = c.gpu_rhs()
+    r_ora = c.oracle_rhs()
+    fv_node = torch.repeat_interleave(c.alpha > 0, torch.as_tensor(np.diff(c.mesh.offset)))
+    progress(f"C3 free-stream, blended: DG nodes {float(r[:, ~fv_node].abs().max()) / scale:.2e}, "
+             f"FV nodes {float(r[:, fv_node].abs().max()) / scale:.2e} (oracle "
+             f"{float(r_ora[:, fv_node].abs().max()) / scale:.2e})", t0)
+    assert float(r[:, ~fv_node].abs().max()) <= 1e-13 * scale
+    assert float(r[:, fv_node].abs().max()) <= max(1e-13 * scale, 4.0 * float(r_ora[:, fv_node].abs().max()))
+
+
+def test_fullsize_c5_vjp_sampled_patches():
+    # dg_rhs_vjp over the whole 64^3 N = 7 mesh (pure DG); the cotangent at a sampled
+    # element depends on w on it and its face neighbours only, so autograd through
+    # the oracle on the patch is exact there
+    announce("C5 full size vjp, sampled patches")
+    from paper_2502_19342_amd import dgfv
+    t0 = time.perf_counter()
+    wl = W.make_workload("C5")
+    spec = wl.mesh
+    K = spec.n_elem
+    off = spec.elem_offset()
+    u = c5_state(wl)
+    rng = np.random.default_rng(5006)
+    centres = np.unique(np.concatenate([rng.choice(K, size=8, replace=False),
+                                        np.array([0, K - 1, spec.n - 1, K - spec.n])]))
+    gm = dgfv.Mesh.from_workload(wl)
+    prm = dgfv.params_of(wl)
+    ud = u.to("cuda")
+    wd = torch.empty_like(ud)
+    wd.copy_(torch.as_tensor(W.cotangents(5007, tuple(u.shape)), dtype=T))
+    g = dgfv.rhs_vjp(gm, prm, ud, None, wd)
+    torch.cuda.synchronize()
+    idx = node_index(off, centres)
+    g_s = g[:, torch.as_tensor(idx, device="cuda")].cpu()
+    elems, local, pspec = patch(spec, centres)
+    pidx = torch.as_tensor(node_index(off, elems), device="cuda")
+    w_p = wd[:, pidx].cpu()
+    del g, ud, wd
+    progress("C5 vjp on the GPU", t0)
+    pwl = W.Workload(name="C5-patch", mesh=pspec, n_var=wl.n_var, prim=wl.prim, volume_flux=wl.volume_flux,
+                     face_flux_dg=wl.face_flux_dg, face_flux_fv=wl.face_flux_fv, n_fv=wl.n_fv,
+                     metric_degree=wl.metric_degree, gamma=wl.gamma, kappa=wl.kappa, R=wl.R)
+    mesh = OracleMesh(pspec, pwl.n_fv, pwl.metric_degree)
+    f = Rhs(mesh, problem.gas_of(pwl), problem.params_of(pwl))
+    up = u[:, torch.as_tensor(node_index(off, elems))].clone().requires_grad_(True)
+    (gp,) = torch.autograd.grad((f(up, torch.zeros(len(elems), dtype=T)) * w_p).sum(), up)
+    lidx = torch.as_tensor(node_index(pspec.elem_offset(), [local[int(e)] for e in centres]))
+    g_ref = gp[:, lidx]
+    progress(f"C5 vjp patch of {len(elems)} elements: rel err {rel_err(g_s, g_ref):.2e}", t0)
+    assert rel_err(g_s, g_ref) <= 1e-12
