@@ -117,12 +117,14 @@ def cpu_baseline(cfg: str, n: int, seed: int):
     """Time the CPU oracle (as it stands) on a small mesh of the same configuration."""
     import torch
 
-    from oracle import indicator, lsrk, problem
+    from oracle import indicator, limiter, lsrk, problem
     from paper_2502_19342_amd import workloads as W
 
     wl = W.make_workload(cfg, n=n)
     mesh, gas, f = problem.build(wl)
     u = problem.initial_state(mesh, gas, wl.prim)
+    if wl.limiter:
+        u = limiter.limit(mesh, gas, u, indicator.indicator(mesh, gas, u, wl.ind_T, wl.ind_dT, wl.ind_vars)[1])[0]
     alpha = torch.zeros(mesh.K, dtype=torch.float64)
     if wl.blend_fraction:
         alpha[torch.as_tensor(blend_mask(np.zeros(mesh.K), wl.blend_fraction, seed))] = 1.0
@@ -138,6 +140,8 @@ def cpu_baseline(cfg: str, n: int, seed: int):
             if not wl.blend_fraction:
                 alpha = a_ind
         u, k = lsrk.stage(lambda v: f(v, alpha), u, k, reps % 5, dt)
+        if wl.limiter:
+            u = limiter.limit(mesh, gas, u, alpha)[0]
         reps += 1
         el = time.perf_counter() - t0
         if el > 12.0 or reps >= 50:
@@ -242,6 +246,10 @@ def main():
     prm = dgfv.params_of(wl)
     u = initial_state_device(gm, wl, dgfv, torch)
     k = torch.zeros_like(u)
+    if wl.limiter:                               # positivity limiter: the initial state, then every stage
+        a0, _ = dgfv.indicator(gm, prm, u)
+        dgfv.positivity_limiter(gm, prm, u, a0)
+        gm.positivity_limiter(True)
     n_dof = gm.n_node
     degs, cnts = np.unique(wl.mesh.degree, return_counts=True)
     n_by_deg = {int(d): int(c) for d, c in zip(degs, cnts)}

@@ -159,6 +159,29 @@ dgfv_status dg_rk_step(const dgfv_mesh* mesh, const dgfv_params* params, double 
                        double* k_d, const double* alpha_d, void* stream);
 
 /*
+ * Positivity-preserving limiter of Zhang and Shu (Section 3.5), one species.
+ * Per element, with the mean ubar = sum w J u / sum w J (which it keeps), every
+ * point value becomes ubar + theta (u_P - ubar): first the density alone, with
+ * the largest theta_rho <= 1 that keeps rho_P >= eps at every point, then all
+ * variables with the largest theta_p <= 1 that keeps p_P >= eps (the exact
+ * root of a quadratic per point).  eps = 1e-10 rhobar for the density and
+ * 1e-10 p(ubar) for the pressure.  The points are the LGL nodes and, on
+ * elements with alpha > 0 (alpha_d may be NULL), the J-weighted sub-cell means
+ * that the FV operator evaluates.  u_d is updated in place; an element within
+ * the bounds is not written.  theta_d (nullable, [n_elem]) receives
+ * min(theta_rho, theta_p), or -1 where the mean itself has rho <= 0 or p <= 0
+ * (left as it is).  DGFV_ERR_UNSUPPORTED for two species.
+ */
+dgfv_status dg_positivity_limiter(const dgfv_mesh* mesh, const dgfv_params* params, double* u_d,
+                                  const double* alpha_d, double* theta_d, void* stream);
+
+/*
+ * With enable != 0, dg_rk_stage and dg_rk_step apply dg_positivity_limiter to
+ * u after every stage (with the stage's alpha; cached graphs are dropped).
+ */
+dgfv_status dgfv_set_positivity_limiter(dgfv_mesh* mesh, int enable);
+
+/*
  * Non-physical states (failure detection, not part of the method).  The
  * element kernels of dg_rhs, dg_rk_stage and dg_rk_step set a flag of the mesh
  * when a node of the state they read has rho <= 0, p <= 0 or a NaN in either

@@ -1176,6 +1176,154 @@ vjp_fv_gather_kernel(MeshView m, const int32_t* __restrict__ elist, int count,
 }
 
 // ---------------------------------------------------------------------------
+// positivity-preserving limiter of Zhang and Shu (Section 3.5), one element per
+// workgroup, single species.  With the element mean ubar = sum w J u / sum w J,
+// each point value becomes ubar + theta (u_P - ubar): first the density alone
+// with theta_rho = min(1, min_P (rhobar - eps) / (rhobar - rho_P)) over points
+// with rho_P < eps, then every variable with theta_p = min_P t_P, t_P the root
+// in (0, 1) of p(ubar + t (u~_P - ubar)) = eps (rho p / (gamma - 1) is a
+// quadratic in t) over points whose pressure is below eps after step 1.
+// eps = 1e-10 rhobar for density and 1e-10 p(ubar) for pressure (a fixed 1e-13 lies
+// below the rounding of E - |m|^2 / (2 rho) when E is of order one).
+// Points: the LGL nodes, and on blended elements the J-weighted sub-cell means
+// in m.ubar (written for the current state before this kernel).  theta_out[e]
+// receives min(theta_rho, theta_p), or -1 when the mean itself has rho <= 0 or
+// p <= 0 (left unchanged).  An element within the bounds is not written.
+// Reductions: wave shuffles, then LDS across the workgroup's waves.
+// ---------------------------------------------------------------------------
+template <int N>
+constexpr int lim_threads() { return (N + 1) * (N + 1) * (N + 1) > 64 ? 256 : 64; }
+constexpr double LIM_EPS_REL = 1e-10;
+
+template <int T_>
+__device__ __forceinline__ double block_reduce(double v, bool is_min, double* sRed) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const double o = __shfl(v, lane ^ off);
+    v = is_min ? (o < v ? o : v) : v + o;
+  }
+  if constexpr (T_ > 64) {
+    __syncthreads();                           // sRed free from the previous reduction
+    if (lane == 0) sRed[wave] = v;
+    __syncthreads();
+    v = sRed[0];
+#pragma unroll
+    for (int w = 1; w < T_ / 64; ++w) v = is_min ? (sRed[w] < v ? sRed[w] : v) : v + sRed[w];
+  }
+  return v;
+}
+
+__device__ __forceinline__ double lim_pressure(const double* w, double gamma) {
+  return (gamma - 1.0) * (w[4] - 0.5 * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]) / w[0]);
+}
+
+// root in (0, 1) of p(ub + t d) = eps for a point below eps (the mean above it)
+__device__ __forceinline__ double lim_root(const double* ub, const double* d, double eps, double gamma) {
+  const double g1 = 1.0 / (gamma - 1.0);
+  const double a = d[0] * d[4] - 0.5 * (d[1] * d[1] + d[2] * d[2] + d[3] * d[3]);
+  const double b = ub[0] * d[4] + ub[4] * d[0] - (ub[1] * d[1] + ub[2] * d[2] + ub[3] * d[3]) - eps * g1 * d[0];
+  const double c = ub[0] * ub[4] - 0.5 * (ub[1] * ub[1] + ub[2] * ub[2] + ub[3] * ub[3]) - eps * g1 * ub[0];
+  if (a == 0.0) {
+    const double t = -c / b;
+    return t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+  }
+  double disc = b * b - 4.0 * a * c;
+  if (disc < 0.0) disc = 0.0;
+  const double q = -0.5 * (b + (b >= 0.0 ? 1.0 : -1.0) * sqrt(disc));
+  const double r1 = q / a;
+  const double r2 = q != 0.0 ? c / q : 2.0;
+  if (r2 >= 0.0 && r2 <= 1.0) return r2;
+  if (r1 >= 0.0 && r1 <= 1.0) return r1;
+  return 0.0;
+}
+
+template <int N>
+__global__ void __launch_bounds__(lim_threads<N>())
+limiter_kernel(MeshView m, const int32_t* __restrict__ elist, int count, double* __restrict__ u,
+               const double* __restrict__ alpha, double* __restrict__ theta_out) {
+  constexpr int NP = N + 1, NP3 = NP * NP * NP, TH = lim_threads<N>();
+  __shared__ double sw[NP];
+  __shared__ double sRed[TH / 64];
+  const int idx = blockIdx.x;
+  if (idx >= count) return;
+  const int e = elist[idx];
+  const int64_t base = m.elem_offset[e];
+  const int t0 = threadIdx.x;
+  if (t0 < NP) sw[t0] = m.ops[m.tab.w[N] + t0];
+  __syncthreads();
+  const double gamma = m.gas.gamma;
+  // element mean of the conserved variables
+  double s[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int t = t0; t < NP3; t += TH) {
+    const int i = t % NP, j = (t / NP) % NP, k = t / (NP * NP);
+    const double wJ = sw[i] * sw[j] * sw[k] * m.metric[9 * m.n_node + base + t];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) s[v] += wJ * u[v * m.n_node + base + t];
+    s[5] += wJ;
+  }
+  double ub[5];
+  const double vol = block_reduce<TH>(s[5], false, sRed);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) ub[v] = block_reduce<TH>(s[v], false, sRed) / vol;
+  const double pb = lim_pressure(ub, gamma);
+  if (!(ub[0] > 0.0) || !(pb > 0.0)) {
+    if (theta_out && t0 == 0) theta_out[e] = -1.0;
+    return;
+  }
+  const double eps_r = LIM_EPS_REL * ub[0];
+  const double eps_p = LIM_EPS_REL * pb;
+  const bool sub = alpha && alpha[e] > 0.0;
+  const int S3 = m.n_fv * m.n_fv * m.n_fv;
+  const int npts = NP3 + (sub ? S3 : 0);
+  const double* ubar_e = m.ubar + (size_t)e * 5 * S3;
+  auto point = [&](int t, double* w) {
+    if (t < NP3) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) w[v] = u[v * m.n_node + base + t];
+    } else {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) w[v] = ubar_e[v * S3 + (t - NP3)];
+    }
+  };
+  // step 1: density
+  double th = 1.0;
+  for (int t = t0; t < npts; t += TH) {
+    double w[5];
+    point(t, w);
+    if (w[0] < eps_r) {
+      const double r = (ub[0] - eps_r) / (ub[0] - w[0]);
+      th = r < th ? r : th;
+    }
+  }
+  const double th_r = block_reduce<TH>(th, true, sRed);
+  // step 2: pressure of the density-limited points
+  th = 1.0;
+  for (int t = t0; t < npts; t += TH) {
+    double w[5];
+    point(t, w);
+    w[0] = ub[0] + th_r * (w[0] - ub[0]);
+    if (lim_pressure(w, gamma) < eps_p) {
+      double d[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) d[v] = w[v] - ub[v];
+      const double r = lim_root(ub, d, eps_p, gamma);
+      th = r < th ? r : th;
+    }
+  }
+  const double th_p = block_reduce<TH>(th, true, sRed);
+  if (theta_out && t0 == 0) theta_out[e] = th_r < th_p ? th_r : th_p;
+  if (!(th_r < 1.0) && !(th_p < 1.0)) return;
+  for (int t = t0; t < NP3; t += TH) {
+    double w[5];
+    point(t, w);
+    w[0] = ub[0] + th_r * (w[0] - ub[0]);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) u[v * m.n_node + base + t] = ub[v] + th_p * (w[v] - ub[v]);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // launchers for this degree
 // ---------------------------------------------------------------------------
 template <int NV, class FLUX, int V>
@@ -1303,6 +1451,15 @@ hipError_t indicator(const MeshView& m, const ParamsDev& p, const int32_t* elist
   return hipGetLastError();
 }
 
+hipError_t limiter(const MeshView& m, const int32_t* elist, int count, double* u, const double* alpha,
+                   double* theta, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  if (m.nvar != 5) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((limiter_kernel<kN>), dim3(count), dim3(lim_threads<kN>()), 0, s, m, elist, count, u, alpha,
+                     theta);
+  return hipGetLastError();
+}
+
 template <int NV, class FLUX>
 hipError_t launch_vjp_volume_t(const MeshView& m, const int32_t* elist, int count, const double* u,
                                const double* alpha, const double* w, double* g, hipStream_t s) {
@@ -1361,7 +1518,7 @@ hipError_t vjp_gather(const MeshView& m, const int32_t* elist, int count, const 
 DegreeOps DGFV_CAT(degree_ops_, DGFV_N)() {
   return DegreeOps{&per_degree::element,    &per_degree::fv_means, &per_degree::fv_residual,
                    &per_degree::indicator,  &per_degree::vjp_volume, &per_degree::vjp_fv,
-                   &per_degree::vjp_gather, &per_degree::fv_normals, elem_variants(kN)};
+                   &per_degree::vjp_gather, &per_degree::fv_normals, &per_degree::limiter, elem_variants(kN)};
 }
 
 }  // namespace dgfv

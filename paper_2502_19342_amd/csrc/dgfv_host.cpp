@@ -120,6 +120,7 @@ struct dgfv_mesh {
   };
   static constexpr size_t GRAPH_CACHE = 16;
   int launch_mode = DGFV_LAUNCH_BRANCHES;
+  bool limiter_on = false;                      // positivity limiter after every RK stage
   std::array<int, MAXN + 1> elem_variant{};    // element-kernel tile shape per degree (autotuned)
   hipStream_t cap_stream = nullptr;
   mutable std::vector<std::pair<GraphKey, hipGraphExec_t>> graph_cache;
@@ -479,6 +480,23 @@ std::vector<int> degrees_present(const dgfv_mesh* m) {
   return d;
 }
 
+// Positivity limiter on u (one species): with alpha, the sub-cell means of the
+// blended elements of the current u first (the blended list must be current).
+void enqueue_limiter(const dgfv_mesh* m, double* u, const double* alpha, double* theta, hipStream_t s,
+                     bool build_list) {
+  const MeshView& v = m->view;
+  if (alpha) {
+    if (build_list) hip_check(launch_blend_list(v, alpha, s), "blended list launch");
+    for (int N = 1; N <= MAXN; ++N)
+      if (!m->bucket[N].empty())
+        hip_check(ops_for(N).fv_means(v, (int)m->bucket[N].size(), 1, u, s), "fv_means launch");
+  }
+  for (int N = 1; N <= MAXN; ++N)
+    if (!m->bucket[N].empty())
+      hip_check(ops_for(N).limiter(v, m->d_bucket[N], (int)m->bucket[N].size(), u, alpha, theta, s),
+                "limiter launch");
+}
+
 // Enqueue one evaluation: stage 0 -> ut = R(u); stage 1..5 -> RK stage on (u, k).
 // Phases: blended list + sub-cell means, face fluxes, FV residuals, element
 // kernels (volume, lift, blend, RK update); the per-degree (per face class)
@@ -525,6 +543,7 @@ void enqueue_rhs_impl(const dgfv_mesh* m, const ParamsDev& p, const double* u, c
                 "element launch");
     });
   }
+  if (stage > 0 && m->limiter_on) enqueue_limiter(m, const_cast<double*>(u), alpha, nullptr, s, false);
 }
 
 dgfv_status enqueue_rhs(const dgfv_mesh* m, const dgfv_params* prm, const double* u,
@@ -545,8 +564,9 @@ dgfv_status run_stages(const dgfv_mesh* m, const dgfv_params* prm, int kind, int
   try {
     if (m->launch_mode != DGFV_LAUNCH_GRAPH || m->profile) {
       const ParamsDev p = to_dev(prm);
+      const bool tr = !m->limiter_on;          // the limiter changes u after the traces are written
       for (int st = first; st <= last; ++st)
-        enqueue_rhs_impl(m, p, u, alpha, nullptr, k, st, dt, s, st > first, st < last);
+        enqueue_rhs_impl(m, p, u, alpha, nullptr, k, st, dt, s, tr && st > first, tr && st < last);
       return DGFV_OK;
     }
     dgfv_mesh::GraphKey key;
@@ -571,8 +591,9 @@ dgfv_status run_stages(const dgfv_mesh* m, const dgfv_params* prm, int kind, int
       hipGraph_t graph = nullptr;
       hip_check(hipStreamBeginCapture(m->cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
       try {
+        const bool tr = !m->limiter_on;
         for (int st = first; st <= last; ++st)
-          enqueue_rhs_impl(m, p, u, alpha, nullptr, k, st, dt, m->cap_stream, st > first, st < last);
+          enqueue_rhs_impl(m, p, u, alpha, nullptr, k, st, dt, m->cap_stream, tr && st > first, tr && st < last);
       } catch (...) {
         (void)hipStreamEndCapture(m->cap_stream, &graph);
         if (graph) (void)hipGraphDestroy(graph);
@@ -1142,6 +1163,27 @@ dgfv_status dgfv_set_element_shape(dgfv_mesh* m, int degree, int shape) {
   if (shape < 0 || shape >= ops_for(degree).element_variants)
     return fail(DGFV_ERR_ARG, "no such element-kernel shape at this degree");
   m->elem_variant[degree] = shape;
+  m->drop_graphs();
+  return DGFV_OK;
+}
+
+dgfv_status dg_positivity_limiter(const dgfv_mesh* m, const dgfv_params* prm, double* u, const double* alpha,
+                                  double* theta, void* stream) {
+  if (!m || !u) return fail(DGFV_ERR_ARG, "NULL argument");
+  if (dgfv_status st = check_params(m, prm)) return st;
+  if (m->nvar != 5) return fail(DGFV_ERR_UNSUPPORTED, "the positivity limiter is single-species only");
+  try {
+    enqueue_limiter(m, u, alpha, theta, (hipStream_t)stream, true);
+  } catch (const HipError& e) {
+    return fail(DGFV_ERR_HIP, e.what());
+  }
+  return DGFV_OK;
+}
+
+dgfv_status dgfv_set_positivity_limiter(dgfv_mesh* m, int enable) {
+  if (!m) return fail(DGFV_ERR_ARG, "mesh is NULL");
+  if (enable && m->nvar != 5) return fail(DGFV_ERR_UNSUPPORTED, "the positivity limiter is single-species only");
+  m->limiter_on = enable != 0;
   m->drop_graphs();
   return DGFV_OK;
 }

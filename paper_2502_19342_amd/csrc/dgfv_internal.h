@@ -119,6 +119,9 @@ struct DegreeOps {
                            double* g, hipStream_t s);
   // setup: sub-face normals of the FV sub-cell grid (geometry only)
   hipError_t (*fv_normals)(const MeshView& m, const int32_t* elist, int count, hipStream_t s);
+  // positivity limiter (one species); sub-cell points of blended elements from m.ubar
+  hipError_t (*limiter)(const MeshView& m, const int32_t* elist, int count, double* u, const double* alpha,
+                        double* theta, hipStream_t s);
   int element_variants;   // tile shapes of the element kernel at this degree
 };
 DegreeOps degree_ops_1();

@@ -42,7 +42,8 @@ class _Params(ctypes.Structure):
 
 EXPORTED = ("dgfv_mesh_create", "dgfv_mesh_destroy", "dgfv_mesh_info", "dgfv_mesh_node_coords",
             "dg_indicator", "dg_rhs", "dg_rk_stage", "dg_rk_step", "dg_rhs_vjp", "dg_rk_stage_vjp",
-            "dg_rk_stage_vjp_noalloc", "dgfv_prim_to_cons", "dgfv_set_launch_mode", "dgfv_autotune",
+            "dg_rk_stage_vjp_noalloc", "dgfv_prim_to_cons", "dg_positivity_limiter",
+            "dgfv_set_positivity_limiter", "dgfv_set_launch_mode", "dgfv_autotune",
             "dgfv_set_element_shape", "dgfv_check_state",
             "dgfv_profile_enable", "dgfv_profile_read", "dgfv_last_error")
 KERNEL_ELEMENT, KERNEL_FACE, KERNEL_FV_MEANS, KERNEL_FV_RESIDUAL, KERNEL_INDICATOR, KERNEL_VJP, KERNEL_FV_FACE = range(7)
@@ -67,6 +68,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dg_rk_stage_vjp.argtypes = [P, ctypes.POINTER(_Params), c_int, c_double, P, P, P, P, P]
     lib.dg_rk_stage_vjp_noalloc.argtypes = [P, ctypes.POINTER(_Params), c_int, c_double, P, P, P, P, P]
     lib.dgfv_prim_to_cons.argtypes = [P, P, P, P]
+    lib.dg_positivity_limiter.argtypes = [P, ctypes.POINTER(_Params), P, P, P, P]
+    lib.dgfv_set_positivity_limiter.argtypes = [P, c_int]
     lib.dgfv_set_launch_mode.argtypes = [P, c_int]
     lib.dgfv_set_element_shape.argtypes = [P, c_int, c_int]
     lib.dgfv_autotune.argtypes = [P, ctypes.POINTER(_Params), P, P, ctypes.POINTER(ctypes.c_double), P]
@@ -171,6 +174,10 @@ class Mesh:
         """Element-kernel tile shape of one degree by hand (``dgfv_set_element_shape``)."""
         _check(_lib.dgfv_set_element_shape(self._h, int(degree), int(shape)))
 
+    def positivity_limiter(self, enable: bool = True) -> None:
+        """Apply the positivity limiter after every RK stage (``dgfv_set_positivity_limiter``)."""
+        _check(_lib.dgfv_set_positivity_limiter(self._h, int(enable)))
+
     def graphs(self, enable: bool = True) -> None:
         """Capture and replay RK steps and stages as hipGraphs, or go back to branch launches."""
         self.launch_mode(LAUNCH_GRAPH if enable else LAUNCH_BRANCHES)
@@ -235,6 +242,14 @@ def rk_step(mesh: Mesh, params: Params, dt: float, u: torch.Tensor, k: torch.Ten
     """In-place five-stage 2N Runge-Kutta step (``dg_rk_step``)."""
     _check(_lib.dg_rk_step(mesh._h, ctypes.byref(params.c()), float(dt), mesh._state(u, "u"),
                            mesh._state(k, "k"), mesh._alpha(alpha), _stream(stream)))
+
+
+def positivity_limiter(mesh: Mesh, params: Params, u: torch.Tensor, alpha: torch.Tensor | None = None,
+                       theta: torch.Tensor | None = None, stream=None) -> torch.Tensor | None:
+    """In-place Zhang-Shu limiter of ``u`` (``dg_positivity_limiter``); returns ``theta`` if given."""
+    _check(_lib.dg_positivity_limiter(mesh._h, ctypes.byref(params.c()), mesh._state(u, "u"), mesh._alpha(alpha),
+                                      mesh._alpha(theta), _stream(stream)))
+    return theta
 
 
 def check_state(mesh: Mesh, stream=None) -> None:

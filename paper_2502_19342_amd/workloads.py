@@ -406,6 +406,7 @@ class Workload:
     seed: int = 0
     noise: float = 0.0
     blend_fraction: float | None = None
+    limiter: bool = False        # positivity limiter after every Runge-Kutta stage
 
 
 def make_workload(name: str, n: int | None = None, scramble_seed: int | None = None) -> Workload:
@@ -419,11 +420,11 @@ def make_workload(name: str, n: int | None = None, scramble_seed: int | None = N
     if name == "C2":
         n = n or 16
         mesh = structured_mesh(n, (0, 0, 0), (1, 1, 1), 5, scramble_seed=scramble_seed)
-        # the front is a tanh of width 0.32/n (0.02 at 16^3): without a positivity
-        # limiter a sharp jump gives negative sub-cell means of the degree-5 interpolant
-        return Workload("C2", mesh, 5, smoothed_blast(0.32 / n), VOL_RANOCHA, RIEMANN_ROE_HH,
+        # the configured jump; the positivity limiter keeps density and pressure
+        # positive at the nodes and at the sub-cell means of blended elements
+        return Workload("C2", mesh, 5, blast_wave, VOL_RANOCHA, RIEMANN_ROE_HH,
                         RIEMANN_LLF, n_fv=6, metric_degree=1, steps=100, seed=2,
-                        ind_T=2.5, ind_dT=0.5)
+                        ind_T=2.5, ind_dT=0.5, limiter=True)
     if name == "C3":
         n = n or 32
         mesh = structured_mesh(n, (0, 0, 0), (1, 1, 1), degree_field(3, 1, 7),

@@ -90,6 +90,12 @@ def main(src, dst):
                                       ctypes.c_double(float(z["dt"])), ptr(u), ptr(ub), ptr(kb), ptr(alpha),
                                       None), "dg_rk_stage_vjp")
             out["ubar"], out["kbar"] = ub, kb
+        elif call == "limiter":
+            ul = u.copy()
+            th = np.empty(K)
+            check(lib.dg_positivity_limiter(h, ctypes.byref(prm), ptr(ul), ptr(alpha), ptr(th), None),
+                  "dg_positivity_limiter")
+            out["limited"], out["theta"] = ul, th
         elif call == "prim_to_cons":
             cu = np.empty_like(u)
             check(lib.dgfv_prim_to_cons(h, ptr(u), ptr(cu), None), "dgfv_prim_to_cons")

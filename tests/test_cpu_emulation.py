@@ -134,3 +134,19 @@ def test_cpu_build_rk_stage_vjp_and_prim_to_cons():
     w = torch.as_tensor(np.asarray(smooth_state(107)(c.mesh.node_coords().numpy().T)), dtype=T)
     out = cpu_emu.run(wl, w.numpy(), ["prim_to_cons"])
     assert rel_err(torch.as_tensor(out["cons"]), prim_to_cons(w, c.gas)) <= 1e-15
+
+
+def test_cpu_build_positivity_limiter():
+    # the HIP limiter kernel (wave-shuffle reductions) against the oracle's limiter
+    from oracle import limiter
+    from test_oracle_limiter import _spoil
+    wl = curved_mixed(n=3, nmin=2, nmax=5, scramble=9, metric_degree=0, n_fv=6)
+    c = _case(wl, smooth_state(3))
+    u = _spoil(c.mesh, c.u, 11)
+    alpha = seeded_alpha(c.mesh.K, 5, values=(0.0, 1.0))
+    ref, n_lim, _ = limiter.limit(c.mesh, c.gas, u, alpha)
+    out = cpu_emu.run(wl, u.numpy(), ["limiter"], alpha=alpha.numpy())
+    assert rel_err(torch.as_tensor(out["limited"]), ref) <= 1e-12
+    changed = [e for e in range(c.mesh.K) if not torch.equal(u[:, c.mesh.offset[e]:c.mesh.offset[e + 1]],
+                                                             ref[:, c.mesh.offset[e]:c.mesh.offset[e + 1]])]
+    assert sorted(np.nonzero(out["theta"] < 1.0)[0].tolist()) == changed and len(changed) == n_lim

@@ -170,28 +170,58 @@ def test_c1_ten_rk_steps():
 
 
 def test_blast_hundred_rk_steps():
-    # C2 at 4^3: 100 LSRK steps, the indicator recomputed at the start of every step on
-    # each side (<= 1e-10).  CFL 0.125 makes the 100 steps span the physical time of
-    # 100 CFL-0.5 steps at 16^3 (no positivity limiter is part of this path).
-    announce("C2 small 100 steps, indicator every step")
+    # C2 at 4^3 with its jump: 100 LSRK steps, the indicator recomputed at the start of
+    # every step and the positivity limiter (Section 3.5) on the initial state and after
+    # every stage, on each side (<= 1e-10).  CFL 0.125 makes the 100 steps span the
+    # physical time of 100 CFL-0.5 steps at 16^3.
+    announce("C2 small 100 steps, indicator every step, positivity limiter")
     from paper_2502_19342_amd import dgfv
+    from oracle import limiter
     from oracle.indicator import indicator as ora_ind
     wl = W.make_workload("C2", n=4)
     c = Case(wl)
+    _, a0 = ora_ind(c.mesh, c.gas, c.u, wl.ind_T, wl.ind_dT, wl.ind_vars)
+    u0, n0, _ = limiter.limit(c.mesh, c.gas, c.u, a0)
     ones = torch.ones(c.mesh.K, dtype=T)
-    dt = lsrk.timestep(c.mesh, c.gas, c.u, wl.cfl * 4 / 16, ones)
-    u = c.u.clone()
+    dt = lsrk.timestep(c.mesh, c.gas, u0, wl.cfl * 4 / 16, ones)
+    u, k = u0.clone(), torch.zeros_like(u0)
+    limited = n0
     for _ in range(100):
         _, a = ora_ind(c.mesh, c.gas, u, wl.ind_T, wl.ind_dT, wl.ind_vars)
-        u = lsrk.step(lambda v: c.f(v, a), u, dt)
-    ug = c.gpu(c.u)
-    k = torch.empty_like(ug)
+        for st in range(5):
+            u, k = lsrk.stage(lambda v: c.f(v, a), u, k, st, dt)
+            u, n, _ = limiter.limit(c.mesh, c.gas, u, a)
+            limited += n
+    assert limited > 0                                   # the limiter acts on this run
+    ug = c.gpu(u0)
+    kg = torch.empty_like(ug)
+    c.gmesh.positivity_limiter(True)
     for _ in range(100):
         ag, _ = dgfv.indicator(c.gmesh, c.params, ug)
-        dgfv.rk_step(c.gmesh, c.params, dt, ug, k, ag)
+        dgfv.rk_step(c.gmesh, c.params, dt, ug, kg, ag)
     torch.cuda.synchronize()
     assert torch.isfinite(u).all()
     assert rel_err(ug.cpu(), u) <= STEP_TOL
+
+
+def test_positivity_limiter_on_gpu():
+    # the limiter kernel against the oracle on a state with negative density and pressure
+    # at some nodes (blended elements also check their sub-cell means)
+    announce("positivity limiter")
+    from paper_2502_19342_amd import dgfv
+    from oracle import limiter
+    from test_oracle_limiter import _spoil
+    wl = curved_mixed(n=3, nmin=2, nmax=5, scramble=9, metric_degree=0, n_fv=6)
+    c = Case(wl, prim=smooth_state(3))
+    u = _spoil(c.mesh, c.u, 11)
+    alpha = seeded_alpha(c.mesh.K, 5, values=(0.0, 1.0))
+    ref, n_lim, _ = limiter.limit(c.mesh, c.gas, u, alpha)
+    ug = c.gpu(u)
+    theta = torch.empty(c.mesh.K, dtype=T, device="cuda")
+    dgfv.positivity_limiter(c.gmesh, c.params, ug, c.gpu(alpha), theta)
+    torch.cuda.synchronize()
+    assert rel_err(ug.cpu(), ref) <= 1e-12
+    assert int((theta < 1.0).sum()) == n_lim > 0
 
 
 @pytest.mark.parametrize("scramble", [None, 41])
