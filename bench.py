@@ -48,6 +48,8 @@ def parse():
                     help="serial launches, concurrent degree-bucket branches, or replayed hipGraphs")
     ap.add_argument("--cpu-sample-n", type=int, default=8, help="elements per direction of the oracle sample")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward timing ratio")
+    ap.add_argument("--face-fusion", default="off", choices=["on", "off"],
+                    help="element kernels of degree 6, 7 evaluate their conforming DG faces (default off)")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="before the steps, one plain device copy of this many GiB (counter calibration)")
     return ap.parse_args()
@@ -77,27 +79,39 @@ def initial_state_device(gm, wl, dgfv, torch, chunk=1 << 23):
     return u
 
 
-def element_kernel_bytes(wl, degree: np.ndarray, alpha: np.ndarray, stage: int) -> float:
+def element_kernel_bytes(wl, degree: np.ndarray, alpha: np.ndarray, stage: int, fused: bool) -> float:
     """Algorithmic HBM bytes of one element-kernel launch (all buckets of one stage of an RK step).
 
     Per node: u read + write, k read (not at stage 1) + write; per blended node
     (alpha > 0) the FV residual (nvar).  Except on pure FV elements (alpha = 1
     at degrees with one element per workgroup, N >= 6, whose DG part is not
-    evaluated): per node the 9 metric terms and J, per element the 6 (N+1)^2
-    nvar side fluxes.  Stages 1..4 also write the new state of sides 0 and 1
-    (2 (N+1)^2 nvar per element of degree >= 6) for the next stage's face fluxes.
+    evaluated): per node the 9 metric terms and J, and per side (N+1)^2 nvar
+    side fluxes, or, where the kernel evaluates the face flux itself (fused
+    stages 1..4: degree >= 6, both elements pure DG of the same degree), the
+    neighbour's trace and the face normals, (N+1)^2 (nvar + 3).  The stage
+    before an in-place stage (all of 1..4 unfused, stage 4 fused) also writes
+    the new state of sides 0 and 1 (2 (N+1)^2 nvar per element of degree >= 6).
     """
     nv = wl.n_var
-    npe = (degree.astype(np.int64) + 1) ** 3
-    fv_only = (alpha >= 1.0) & (degree >= 6)
+    deg = degree.astype(np.int64)
+    npe = (deg + 1) ** 3
+    n2 = (deg + 1) ** 2
+    fv_only = (alpha >= 1.0) & (deg >= 6)
     dg = ~fv_only
     per_node = 8 * (2 * nv + (nv if stage > 1 else 0) + nv)
     total = per_node * npe.sum()
     total += 8 * 10 * npe[dg].sum()
-    total += 8 * 6 * ((degree[dg].astype(np.int64) + 1) ** 2).sum() * nv
     total += 8 * nv * npe[alpha > 0].sum()
-    if stage < 5:
-        total += 8 * 2 * ((degree[degree >= 6].astype(np.int64) + 1) ** 2).sum() * nv
+    fuse_stage = fused and stage < 5
+    faces = np.asarray(wl.mesh.faces)
+    eL, eR = faces[:, 0], faces[:, 2]
+    pure = ~(alpha > 0)
+    fused_face = fuse_stage & (deg[eL] == deg[eR]) & (deg[eL] >= 6) & pure[eL] & pure[eR]
+    # every face is seen from both sides; a side of a pure FV element reads nothing
+    for e_side in (eL, eR):
+        total += 8 * (n2[e_side] * np.where(fused_face, nv + 3, nv))[dg[e_side]].sum()
+    if (stage < 5 and not fused) or (fused and stage == 4):
+        total += 8 * 2 * n2[deg >= 6].sum() * nv
     return float(total)
 
 
@@ -282,6 +296,7 @@ def main():
 
     gm.launch_mode({"serial": dgfv.LAUNCH_SERIAL, "branches": dgfv.LAUNCH_BRANCHES,
                     "graph": dgfv.LAUNCH_GRAPH}[args.launch])
+    gm.face_fusion(args.face_fusion == "on")
     if args.copy_gib > 0:
         n = int(args.copy_gib * (1 << 30)) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -333,7 +348,8 @@ def main():
     el_ms, el_n = kt["element"]
     avg_el_s = el_ms / el_n / 1e3
     alpha_h = alpha.cpu().numpy()
-    byts = np.mean([element_kernel_bytes(wl, np.asarray(wl.mesh.degree), alpha_h, s) for s in range(1, 6)])
+    fused = args.face_fusion == "on" and bool((np.asarray(wl.mesh.degree) >= 6).any())
+    byts = np.mean([element_kernel_bytes(wl, np.asarray(wl.mesh.degree), alpha_h, s, fused) for s in range(1, 6)])
     achieved = byts / avg_el_s / 1e9
     stage_b = stage_bytes(wl, np.asarray(wl.mesh.degree))
     rec = {
@@ -357,13 +373,15 @@ def main():
             "n_elem": wl.mesh.n_elem, "n_dof": n_dof, "n_var": wl.n_var,
             "volume_flux": ["ranocha", "pirozzoli", "central"][wl.volume_flux],
             "launch": args.launch,
+            "face_fusion": args.face_fusion,
             "autotune_ms": {str(N): [round(a, 4), round(b, 4)] for N, (a, b) in tune.items()},
             "blended_fraction": float(mask.mean()),
             "blended_fraction_last_step": float((alpha_h > 0).mean()),
         },
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": counter_traffic(args.config),
-                     "kernel": "element_kernel (volume + lift + blend + RK update)",
+                     "kernel": "element_kernel (volume + lift + blend + RK update"
+                               + (", conforming face fluxes of degrees 6, 7 at stages 1..4)" if fused else ")"),
                      "bytes_per_launch": byts, "avg_launch_ms": 1e3 * avg_el_s},
         "stage_roofline": {"bound": "hbm", "achieved": stage_b / (el / stages) / 1e9, "peak": PEAK_HBM_GBS,
                            "unit": "GB/s", "frac": stage_b / (el / stages) / 1e9 / PEAK_HBM_GBS,

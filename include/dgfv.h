@@ -216,6 +216,27 @@ enum { DGFV_LAUNCH_SERIAL = 0, DGFV_LAUNCH_BRANCHES = 1, DGFV_LAUNCH_GRAPH = 2 }
 dgfv_status dgfv_set_launch_mode(dgfv_mesh* mesh, int mode);
 
 /*
+ * Fused face fluxes (not part of the method; off by default).  Elements of
+ * degree 6 and 7 evaluate the Riemann flux (eq. conv_flux) of each face they
+ * share with a pure DG element of the same degree themselves, with the same
+ * operands and operations as the face kernel, instead of reading it from the
+ * side buffer the face kernel fills: one launch and one round trip of the
+ * side fluxes less.  The element then reads its neighbour's state while the
+ * launch runs, so no launch may write the state it reads: dg_rhs fuses
+ * always; dg_rk_step alternates its stages between u and a second state
+ * buffer owned by the mesh (n_var x n_node doubles, allocated by the first
+ * such call, never while the stream is captured; without it the stages run in
+ * place, unfused), and runs the fifth stage in place and unfused; dg_rk_stage
+ * never fuses.  Results are those of the unfused path to rounding (the
+ * compiler may contract the flux's products and sums differently in the two
+ * kernels).  Changing the setting drops the mesh's cached graphs.  On the
+ * 64^3 N=7 shear-layer workload the fused stages take as long as the separate
+ * kernels: the element kernel gains the face flux on its critical path, and
+ * the FV faces lose the conforming face kernel they overlapped with.
+ */
+dgfv_status dgfv_set_face_fusion(dgfv_mesh* mesh, int enable);
+
+/*
  * Autotuning (not part of the method).  The element kernel has two tile
  * shapes at degrees N <= 5: about 512 or about 256 lanes per workgroup (the
  * number of elements per workgroup).  dgfv_autotune evaluates the RHS once on

@@ -42,9 +42,9 @@ constexpr int elem_variants(int N) { return (N + 1) * (N + 1) * (N + 1) >= 256 ?
 // ---------------------------------------------------------------------------
 template <int N, int NV, class FLUX, int EPB>
 __global__ void __launch_bounds__(EPB * Geo<N>::NP3)
-element_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const double* u,
-               const double* __restrict__ alpha, double* __restrict__ ut, double* k, int stage,
-               double dt, double A, double B, bool write_trace) {
+element_kernel(MeshView m, ParamsDev prm, const int32_t* __restrict__ elist, int count, const double* u,
+               double* uout, const double* __restrict__ alpha, double* __restrict__ ut, double* k, int stage,
+               double dt, double A, double B, int flags) {
   using G = Geo<N>;
   constexpr int NP = G::NP, NP2 = G::NP2, NP3 = G::NP3;
   constexpr int NA = FLUX::NA;
@@ -90,13 +90,65 @@ element_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const d
   for (int v = 0; v < NV; ++v) uo[v] = u[v * m.n_node + base];
   const double al = alpha ? alpha[e] : 0.0;
   const double* fs = m.fside + m.side_off[e];
+  const bool write_trace = flags & ELEM_WRITE_TRACE;
+  // Fused faces (one element per workgroup): lane t < 6 (N+1)^2 takes point
+  // t mod (N+1)^2 of side t / (N+1)^2 on the face's left grid.  A face shared
+  // with a pure DG element of the same degree gets its Riemann flux here, with
+  // exactly the operands and operations of the conforming face kernel (the
+  // right element stores the negated flux, re-indexed through the orientation);
+  // the other sides (degree jumps, FV faces) take the point's value from the
+  // side buffer, written by the face kernels.  The neighbour's state is read
+  // from u, which no workgroup of this launch writes (stage 0, or uout != u).
+  constexpr bool CAN_FUSE = STAGE_SIDES;
+  const bool fuse = CAN_FUSE && (flags & ELEM_FUSE_FACES);
   double sv[SIDE_PER];
+  double fv[NV];
+  int fdst = -1;                           // this lane's point in sSide (fused), or none
   if constexpr (STAGE_SIDES) {
-    if (al < 1.0) {        // a pure FV element needs no side fluxes
+    if (al < 1.0 && !fuse) {        // a pure FV element needs no side fluxes
 #pragma unroll
       for (int r = 0; r < SIDE_PER; ++r) {
         const int q = tid + r * NP3;
         sv[r] = q < NSIDE ? fs[q] : 0.0;
+      }
+    }
+    // (the side record and the operands are loaded whatever this element's
+    // alpha, so that they do not wait for it)
+    if (CAN_FUSE && fuse && tid < 6 * NP2) {
+      const int s = tid / NP2, r = tid - s * NP2;
+      const SideRec sr = m.side_rec[6 * (int64_t)e + s];
+      const int sL = sr.code & 7, sR = (sr.code >> 3) & 7, o = (sr.code >> 6) & 7;
+      const bool own_left = (sr.code >> 9) & 1, same_degree = (sr.code >> 10) & 1;
+      const int p = r % NP, q = r / NP;
+      int pp, qq;
+      orient_map(o, p, q, NP, pp, qq);
+      const double an = alpha ? alpha[sr.nbr] : 0.0;
+      double uL[NV], uR[NV], n0 = 0.0, n1 = 0.0, n2 = 0.0;
+      if (same_degree) {                   // both elements have (N+1)^3 nodes: in range
+        const double* srcL = u + sr.baseL + side_node(sL, p, q, NP);
+        const double* srcR = u + sr.baseR + side_node(sR, pp, qq, NP);
+        const double* nrm = m.face_norm + sr.nrm;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          uL[v] = srcL[v * m.n_node];
+          uR[v] = srcR[v * m.n_node];
+        }
+        n0 = nrm[r];
+        n1 = nrm[NP2 + r];
+        n2 = nrm[2 * NP2 + r];
+      }
+      if (!(al < 1.0)) {
+        // a pure FV element takes no side fluxes
+      } else if (same_degree && !(al > 0.0) && !(an > 0.0)) {
+        double F[NV];
+        riemann<NV>(prm.face_flux_dg, prm.volume_flux, uL, uR, n0, n1, n2, m.gas, F);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) fv[v] = own_left ? F[v] : -F[v];
+        fdst = s * NV * NP2 + (own_left ? q * NP + p : qq * NP + pp);
+      } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) fv[v] = fs[(s * NV + v) * NP2 + r];
+        fdst = s * NV * NP2 + r;
       }
     }
   }
@@ -113,7 +165,7 @@ element_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const d
 #pragma unroll
       for (int v = 0; v < NV; ++v) ut[v * m.n_node + base] = R[v];
     } else {
-      double* uw = const_cast<double*>(u);
+      double* uw = uout;
       double* tr = nullptr;
       if (TRACE && write_trace && (i == 0 || i == N))
         tr = m.trace + m.side_off[e] / 3 + ((i == 0 ? 0 : 1) * NV) * NP2 + kk * NP + j;
@@ -155,10 +207,17 @@ element_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const d
     for (int a = 0; a < NA; ++a) sAux[slot][a][node] = r[a];
   }
   if constexpr (STAGE_SIDES) {
+    if (fuse) {
+      if (fdst >= 0) {
 #pragma unroll
-    for (int r = 0; r < SIDE_PER; ++r) {
-      const int q = tid + r * NP3;
-      if (q < NSIDE) sSide[q] = sv[r];
+        for (int v = 0; v < NV; ++v) sSide[fdst + v * NP2] = fv[v];
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < SIDE_PER; ++r) {
+        const int q = tid + r * NP3;
+        if (q < NSIDE) sSide[q] = sv[r];
+      }
     }
   }
   const double invJ = 1.0 / m.metric[9 * m.n_node + base];
@@ -1327,38 +1386,41 @@ limiter_kernel(MeshView m, const int32_t* __restrict__ elist, int count, double*
 // launchers for this degree
 // ---------------------------------------------------------------------------
 template <int NV, class FLUX, int V>
-static hipError_t launch_elem_v(const MeshView& m, const int32_t* elist, int count, const double* u,
-                                const double* alpha, double* ut, double* k, int stage, double dt,
-                                double A, double B, bool tr, hipStream_t s) {
+static hipError_t launch_elem_v(const MeshView& m, const ParamsDev& p, const int32_t* elist, int count,
+                                const double* u, double* uout, const double* alpha, double* ut, double* k,
+                                int stage, double dt, double A, double B, int flags, hipStream_t s) {
   constexpr int EPB = elem_epb<kN, V>();
   const int blocks = (count + EPB - 1) / EPB;
-  hipLaunchKernelGGL((element_kernel<kN, NV, FLUX, EPB>), dim3(blocks), dim3(EPB * Geo<kN>::NP3), 0, s, m,
-                     elist, count, u, alpha, ut, k, stage, dt, A, B, tr);
+  hipLaunchKernelGGL((element_kernel<kN, NV, FLUX, EPB>), dim3(blocks), dim3(EPB * Geo<kN>::NP3), 0, s, m, p,
+                     elist, count, u, uout, alpha, ut, k, stage, dt, A, B, flags);
   return hipGetLastError();
 }
 
 template <int NV, class FLUX>
-static hipError_t launch_elem_t(const MeshView& m, const int32_t* elist, int count, const double* u,
-                                const double* alpha, double* ut, double* k, int stage, double dt,
-                                double A, double B, int variant, bool tr, hipStream_t s) {
+static hipError_t launch_elem_t(const MeshView& m, const ParamsDev& p, const int32_t* elist, int count,
+                                const double* u, double* uout, const double* alpha, double* ut, double* k,
+                                int stage, double dt, double A, double B, int variant, int flags, hipStream_t s) {
   if (variant == 1 && elem_variants(kN) > 1)
-    return launch_elem_v<NV, FLUX, 1>(m, elist, count, u, alpha, ut, k, stage, dt, A, B, tr, s);
-  return launch_elem_v<NV, FLUX, 0>(m, elist, count, u, alpha, ut, k, stage, dt, A, B, tr, s);
+    return launch_elem_v<NV, FLUX, 1>(m, p, elist, count, u, uout, alpha, ut, k, stage, dt, A, B, flags, s);
+  return launch_elem_v<NV, FLUX, 0>(m, p, elist, count, u, uout, alpha, ut, k, stage, dt, A, B, flags, s);
 }
 
 namespace per_degree {
 hipError_t element(const MeshView& m, const ParamsDev& p, const int32_t* elist, int count,
-                   const double* u, const double* alpha, double* ut, double* k, int stage,
-                   double dt, double A, double B, int variant, bool tr, hipStream_t s) {
+                   const double* u, double* uout, const double* alpha, double* ut, double* k, int stage,
+                   double dt, double A, double B, int variant, int flags, hipStream_t s) {
   if (count == 0) return hipSuccess;
+  // fused faces read the neighbours' state from u: nothing of this launch may write it
+  if ((flags & ELEM_FUSE_FACES) && (kN < FUSE_MIN_N || (stage > 0 && uout == u) || !m.side_rec))
+    return hipErrorInvalidValue;
   const int v = variant;
   if (m.nvar == 5) {
-    if (p.volume_flux == 0) return launch_elem_t<5, FluxRanocha>(m, elist, count, u, alpha, ut, k, stage, dt, A, B, v, tr, s);
-    if (p.volume_flux == 1) return launch_elem_t<5, FluxPirozzoli>(m, elist, count, u, alpha, ut, k, stage, dt, A, B, v, tr, s);
-    return launch_elem_t<5, FluxCentral>(m, elist, count, u, alpha, ut, k, stage, dt, A, B, v, tr, s);
+    if (p.volume_flux == 0) return launch_elem_t<5, FluxRanocha>(m, p, elist, count, u, uout, alpha, ut, k, stage, dt, A, B, v, flags, s);
+    if (p.volume_flux == 1) return launch_elem_t<5, FluxPirozzoli>(m, p, elist, count, u, uout, alpha, ut, k, stage, dt, A, B, v, flags, s);
+    return launch_elem_t<5, FluxCentral>(m, p, elist, count, u, uout, alpha, ut, k, stage, dt, A, B, v, flags, s);
   }
-  if (p.volume_flux == 1) return launch_elem_t<6, FluxPirozzoli>(m, elist, count, u, alpha, ut, k, stage, dt, A, B, v, tr, s);
-  return launch_elem_t<6, FluxCentral>(m, elist, count, u, alpha, ut, k, stage, dt, A, B, v, tr, s);
+  if (p.volume_flux == 1) return launch_elem_t<6, FluxPirozzoli>(m, p, elist, count, u, uout, alpha, ut, k, stage, dt, A, B, v, flags, s);
+  return launch_elem_t<6, FluxCentral>(m, p, elist, count, u, uout, alpha, ut, k, stage, dt, A, B, v, flags, s);
 }
 
 // fv_means is persistent: as many workgroups as fit on the device at once (at

@@ -467,8 +467,10 @@ face_mixed_kernel(MeshView m, ParamsDev prm, const int32_t* __restrict__ flist, 
 
 // FV faces: one workgroup per entry of the blended-element list of the call
 // (a grid of K, the workgroups past the list leaving at once); each blended
-// element processes the faces it owns (the left element owns a
-// face when it is blended, otherwise the right one).
+// element processes the faces it owns (the left element owns a face when it is
+// blended, otherwise the right one), so that the element's sub-cell means are
+// read through one L2.  (Persistent workgroups over (element, side) pairs ran
+// twice as long.)
 
 template <int NV>
 __global__ void __launch_bounds__(FACE_THREADS)

@@ -109,12 +109,12 @@ struct dgfv_mesh {
 
   // hipGraph cache of dg_rk_step / dg_rk_stage, keyed on the full argument set
   struct GraphKey {
-    int kind, stage;
+    int kind, stage, fuse;
     const void *u, *k, *alpha;
     double dt;
     dgfv_params prm;
     bool operator==(const GraphKey& o) const {
-      return kind == o.kind && stage == o.stage && u == o.u && k == o.k && alpha == o.alpha &&
+      return kind == o.kind && stage == o.stage && fuse == o.fuse && u == o.u && k == o.k && alpha == o.alpha &&
              std::memcmp(&dt, &o.dt, sizeof dt) == 0 && std::memcmp(&prm, &o.prm, sizeof prm) == 0;
     }
   };
@@ -134,6 +134,13 @@ struct dgfv_mesh {
 
   // state-sized buffer of dg_rk_stage_vjp, allocated by its first call
   mutable double* stage_g = nullptr;
+
+  // fused face fluxes (element kernels of degree >= FUSE_MIN_N evaluate the
+  // conforming DG faces themselves), off unless asked for; the RK stages of one
+  // dg_rk_step then alternate between u and u_alt (state-sized, allocated by
+  // the first such call), so that no launch writes the state it reads
+  bool fuse_faces = false;
+  mutable double* u_alt = nullptr;
 
   // kernel timing (mutable: recording does not change the mesh)
   mutable bool profile = false;
@@ -161,6 +168,7 @@ struct dgfv_mesh {
       }
     for (void* p : allocations) (void)hipFree(p);
     if (stage_g) (void)hipFree(stage_g);
+    if (u_alt) (void)hipFree(u_alt);
   }
   template <class T>
   T* keep(T* p) {
@@ -396,6 +404,19 @@ std::vector<double> transpose(const std::vector<double>& a, int r, int c) {
   return t;
 }
 
+// Position b of the list gets element (b mod 8)-th chunk, entry b div 8: with
+// C = 8q + r, chunk x holds q + (x < r) consecutive entries of `sorted`.
+std::vector<int32_t> xcd_order(const std::vector<int32_t>& sorted) {
+  constexpr int XCD = 8;
+  const size_t C = sorted.size(), q = C / XCD, r = C % XCD;
+  std::vector<int32_t> out(C);
+  for (size_t b = 0; b < C; ++b) {
+    const size_t x = b % XCD, j = b / XCD;
+    out[b] = sorted[x * q + std::min(x, r) + j];
+  }
+  return out;
+}
+
 int side_node_h(int s, int p, int q, int n) {
   const int last = (s & 1) ? n - 1 : 0;
   switch (s >> 1) {
@@ -504,9 +525,13 @@ void enqueue_limiter(const dgfv_mesh* m, double* u, const double* alpha, double*
 // trace_in: the conforming faces read sides 0 and 1 from m->view.trace, which
 // the previous stage of the same step wrote (trace_out) from the state it left
 // in u; only dg_rk_step sets them, as within one call nothing else writes u.
-void enqueue_rhs_impl(const dgfv_mesh* m, const ParamsDev& p, const double* u, const double* alpha,
-                      double* ut, double* k, int stage, double dt, hipStream_t s, bool trace_in = false,
-                      bool trace_out = false) {
+// uout: where a stage puts the new state (u itself for an in-place stage).
+// fuse: the element kernels of degree >= FUSE_MIN_N evaluate their conforming
+// DG faces themselves (stage 0, or uout != u), and those face classes are not
+// launched.
+void enqueue_rhs_impl(const dgfv_mesh* m, const ParamsDev& p, const double* u, double* uout,
+                      const double* alpha, double* ut, double* k, int stage, double dt, hipStream_t s,
+                      bool trace_in = false, bool trace_out = false, bool fuse = false) {
   const MeshView& v = m->view;
   const double A = stage > 0 ? RK_A[stage - 1] : 0.0;
   const double B = stage > 0 ? RK_B[stage - 1] : 0.0;
@@ -523,7 +548,7 @@ void enqueue_rhs_impl(const dgfv_mesh* m, const ParamsDev& p, const double* u, c
     Timed t(m, DGFV_KERNEL_FACE, s);
     std::vector<int> classes;
     for (int c = 1; c < FACE_CLASS_COUNT; ++c)
-      if (face_class_present(v, alpha, c)) classes.push_back(c);
+      if (face_class_present(v, alpha, c) && !(fuse && c >= FUSE_MIN_N && c <= MAXN)) classes.push_back(c);
     fork_join(m, s, classes, [&](int c, hipStream_t ss) {
       Timed tf(m, c == FACE_CLASS_FV ? DGFV_KERNEL_FV_FACE : -1, ss);
       hip_check(launch_face_class(v, p, u, alpha, c, trace_in, ss), "face launch");
@@ -538,19 +563,57 @@ void enqueue_rhs_impl(const dgfv_mesh* m, const ParamsDev& p, const double* u, c
   {
     Timed t(m, DGFV_KERNEL_ELEMENT, s);
     fork_join(m, s, degs, [&](int N, hipStream_t ss) {
-      hip_check(ops_for(N).element(v, p, m->d_bucket[N], (int)m->bucket[N].size(), u, alpha, ut, k, stage,
-                                   dt, A, B, m->elem_variant[N], trace_out, ss),
+      const int flags = (trace_out ? ELEM_WRITE_TRACE : 0) | (fuse && N >= FUSE_MIN_N ? ELEM_FUSE_FACES : 0);
+      hip_check(ops_for(N).element(v, p, m->d_bucket[N], (int)m->bucket[N].size(), u, uout, alpha, ut, k,
+                                   stage, dt, A, B, m->elem_variant[N], flags, ss),
                 "element launch");
     });
   }
-  if (stage > 0 && m->limiter_on) enqueue_limiter(m, const_cast<double*>(u), alpha, nullptr, s, false);
+  if (stage > 0 && m->limiter_on) enqueue_limiter(m, uout, alpha, nullptr, s, false);
 }
+
+bool has_fused_degree(const dgfv_mesh* m) {
+  for (int N = FUSE_MIN_N; N <= MAXN; ++N)
+    if (!m->bucket[N].empty()) return true;
+  return false;
+}
+
+// Stages first..last, each reading one state buffer and writing another where
+// faces are fused: the stages alternate between u and m->u_alt, and the last
+// one, whose result must be in u, runs in place without fusion when its input
+// is u.  Traces go from a stage to a following in-place stage.
+void enqueue_stages(const dgfv_mesh* m, const ParamsDev& p, int first, int last, double dt, double* u, double* k,
+                    const double* alpha, hipStream_t s, bool fuse) {
+  const bool tr = !m->limiter_on;              // the limiter changes u after the traces are written
+  double* cur = u;
+  for (int st = first; st <= last; ++st) {
+    double* out = u;
+    bool fused = false;
+    if (fuse) {
+      if (st < last) {
+        out = cur == u ? m->u_alt : u;
+        fused = true;
+      } else if (cur != u) {
+        fused = true;                          // from u_alt back into u
+      }
+    }
+    const bool next_in_place = st < last && !(fuse && (st + 1 < last || out != u));
+    const bool prev_wrote = st > first && !fused && (!fuse || cur == u);
+    enqueue_rhs_impl(m, p, cur, out, alpha, nullptr, k, st, dt, s, tr && prev_wrote, tr && next_in_place, fused);
+    cur = out;
+  }
+}
+
+// Whether stages first..last of a call on stream s alternate state buffers;
+// allocates the second buffer when needed (never while s is captured).
+bool use_fused_stages(const dgfv_mesh* m, int first, int last, hipStream_t s);
 
 dgfv_status enqueue_rhs(const dgfv_mesh* m, const dgfv_params* prm, const double* u,
                         const double* alpha, double* ut, double* k, int stage, double dt,
                         hipStream_t s) {
   try {
-    enqueue_rhs_impl(m, to_dev(prm), u, alpha, ut, k, stage, dt, s);
+    const bool fuse = stage == 0 && m->fuse_faces && has_fused_degree(m);
+    enqueue_rhs_impl(m, to_dev(prm), u, const_cast<double*>(u), alpha, ut, k, stage, dt, s, false, false, fuse);
   } catch (const HipError& e) {
     return fail(DGFV_ERR_HIP, e.what());
   }
@@ -562,17 +625,16 @@ dgfv_status enqueue_rhs(const dgfv_mesh* m, const dgfv_params* prm, const double
 dgfv_status run_stages(const dgfv_mesh* m, const dgfv_params* prm, int kind, int first, int last, double dt,
                        double* u, double* k, const double* alpha, hipStream_t s) {
   try {
+    const bool fuse = use_fused_stages(m, first, last, s);
     if (m->launch_mode != DGFV_LAUNCH_GRAPH || m->profile) {
-      const ParamsDev p = to_dev(prm);
-      const bool tr = !m->limiter_on;          // the limiter changes u after the traces are written
-      for (int st = first; st <= last; ++st)
-        enqueue_rhs_impl(m, p, u, alpha, nullptr, k, st, dt, s, tr && st > first, tr && st < last);
+      enqueue_stages(m, to_dev(prm), first, last, dt, u, k, alpha, s, fuse);
       return DGFV_OK;
     }
     dgfv_mesh::GraphKey key;
     std::memset(&key, 0, sizeof key);             // padding too: the key is compared bytewise in part
     key.kind = kind;
     key.stage = first;
+    key.fuse = fuse;
     key.u = u;
     key.k = k;
     key.alpha = alpha;
@@ -591,9 +653,7 @@ dgfv_status run_stages(const dgfv_mesh* m, const dgfv_params* prm, int kind, int
       hipGraph_t graph = nullptr;
       hip_check(hipStreamBeginCapture(m->cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
       try {
-        const bool tr = !m->limiter_on;
-        for (int st = first; st <= last; ++st)
-          enqueue_rhs_impl(m, p, u, alpha, nullptr, k, st, dt, m->cap_stream, tr && st > first, tr && st < last);
+        enqueue_stages(m, p, first, last, dt, u, k, alpha, m->cap_stream, fuse);
       } catch (...) {
         (void)hipStreamEndCapture(m->cap_stream, &graph);
         if (graph) (void)hipGraphDestroy(graph);
@@ -619,6 +679,20 @@ dgfv_status run_stages(const dgfv_mesh* m, const dgfv_params* prm, int kind, int
 bool capturing(hipStream_t s) {
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   return hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone;
+}
+
+bool use_fused_stages(const dgfv_mesh* m, int first, int last, hipStream_t s) {
+  if (!m->fuse_faces || last <= first || !has_fused_degree(m)) return false;
+  if (!m->u_alt) {
+    if (capturing(s)) return false;
+    double* p = nullptr;
+    if (hipMalloc((void**)&p, sizeof(double) * (size_t)m->nvar * (size_t)m->n_node) != hipSuccess) {
+      (void)hipGetLastError();                // out of memory: the stages run in place
+      return false;
+    }
+    m->u_alt = p;
+  }
+  return true;
 }
 
 // A non-physical state seen by an earlier call whose flag copy has landed:
@@ -911,7 +985,14 @@ dgfv_status dgfv_mesh_create(const dgfv_mesh_desc* d, dgfv_mesh** out) {
     }
 
     // ---- buckets -----------------------------------------------------------
+    // Workgroups go to the eight XCDs (each with its own L2) in turn by
+    // workgroup index.  A bucket is listed so that XCD x takes the x-th eighth of
+    // the bucket's elements in ascending order: elements adjacent in the mesh
+    // order (neighbours along xi_1 and, a row later, xi_2 on a structured mesh)
+    // then run on one XCD close together, and the faces they share are read
+    // through the same L2.
     for (int e = 0; e < m->K; ++e) m->bucket[m->degree[e]].push_back(e);
+    for (int N = 1; N <= MAXN; ++N) m->bucket[N] = xcd_order(m->bucket[N]);
 
     // ---- device ------------------------------------------------------------
     MeshView& v = m->view;
@@ -982,6 +1063,21 @@ dgfv_status dgfv_mesh_create(const dgfv_mesh_desc* d, dgfv_mesh** out) {
       v.face_mixed = mixed.empty() ? nullptr : m->keep(dev_upload(mixed));
       v.face_mixed_count = (int)mixed.size();
       v.elem_face = m->keep(dev_upload(elem_face));
+      std::vector<SideRec> srec((size_t)m->K * 6);
+      for (int e = 0; e < m->K; ++e)
+        for (int sd = 0; sd < 6; ++sd) {
+          const int f = elem_face[(size_t)e * 6 + sd];
+          const int32_t* fc = d->faces + 5 * (size_t)f;
+          SideRec& r = srec[(size_t)e * 6 + sd];
+          const bool left = fc[0] == e && fc[1] == sd;
+          r.baseL = m->offset[fc[0]];
+          r.baseR = m->offset[fc[2]];
+          r.nrm = fnorm_off[f];
+          r.nbr = left ? fc[2] : fc[0];
+          r.code = fc[1] | (fc[3] << 3) | (fc[4] << 6) | ((left ? 1 : 0) << 9) |
+                   ((m->degree[fc[0]] == m->degree[fc[2]] ? 1 : 0) << 10);
+        }
+      v.side_rec = m->keep(dev_upload(srec));
     }
     // blended-element work list: buckets concatenated in ascending degree
     {
@@ -1112,8 +1208,8 @@ dgfv_status dgfv_autotune(dgfv_mesh* m, const dgfv_params* prm, const double* u,
     hip_check(hipEventCreate(&e0), "hipEventCreate");
     hip_check(hipEventCreate(&e1), "hipEventCreate");
     const ParamsDev p = to_dev(prm);
-    // one full evaluation fills the side-flux and FV buffers that the element kernel reads
-    enqueue_rhs_impl(m, p, u, alpha, scratch, nullptr, 0, 0.0, s);
+    // one full evaluation (faces not fused) fills the side-flux and FV buffers that the element kernel reads
+    enqueue_rhs_impl(m, p, u, const_cast<double*>(u), alpha, scratch, nullptr, 0, 0.0, s);
     const MeshView& v = m->view;
     constexpr int REPS = 5;
     for (int N = 1; N <= MAXN; ++N) {
@@ -1123,11 +1219,13 @@ dgfv_status dgfv_autotune(dgfv_mesh* m, const dgfv_params* prm, const double* u,
       double best = 0.0;
       int choice = 0;
       for (int var = 0; var < ops.element_variants; ++var) {
-        hip_check(ops.element(v, p, m->d_bucket[N], cnt, u, alpha, scratch, nullptr, 0, 0.0, 0.0, 0.0, var, false, s),
+        hip_check(ops.element(v, p, m->d_bucket[N], cnt, u, const_cast<double*>(u), alpha, scratch, nullptr, 0, 0.0,
+                              0.0, 0.0, var, 0, s),
                   "element launch");
         hip_check(hipEventRecord(e0, s), "hipEventRecord");
         for (int r = 0; r < REPS; ++r)
-          hip_check(ops.element(v, p, m->d_bucket[N], cnt, u, alpha, scratch, nullptr, 0, 0.0, 0.0, 0.0, var, false, s),
+          hip_check(ops.element(v, p, m->d_bucket[N], cnt, u, const_cast<double*>(u), alpha, scratch, nullptr, 0, 0.0,
+                              0.0, 0.0, var, 0, s),
                     "element launch");
         hip_check(hipEventRecord(e1, s), "hipEventRecord");
         hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
@@ -1184,6 +1282,13 @@ dgfv_status dgfv_set_positivity_limiter(dgfv_mesh* m, int enable) {
   if (!m) return fail(DGFV_ERR_ARG, "mesh is NULL");
   if (enable && m->nvar != 5) return fail(DGFV_ERR_UNSUPPORTED, "the positivity limiter is single-species only");
   m->limiter_on = enable != 0;
+  m->drop_graphs();
+  return DGFV_OK;
+}
+
+dgfv_status dgfv_set_face_fusion(dgfv_mesh* m, int enable) {
+  if (!m) return fail(DGFV_ERR_ARG, "mesh is NULL");
+  m->fuse_faces = enable != 0;
   m->drop_graphs();
   return DGFV_OK;
 }

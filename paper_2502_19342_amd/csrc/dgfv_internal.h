@@ -51,6 +51,18 @@ struct alignas(16) ConfRec {
   int32_t pad;
 };
 
+// One element side as the element kernel sees it when it evaluates the face
+// flux itself: the face's two elements (left one first, as in the face
+// table), the normals of the face, and
+// code = left side | right side << 3 | orientation << 6 | (this element is the
+// face's left one) << 9 | (both elements have the same degree) << 10.
+struct alignas(16) SideRec {
+  int64_t baseL, baseR;   // elem_offset of the left and right elements
+  int64_t nrm;            // face_norm_off of the face
+  int32_t nbr;            // the other element of the face
+  int32_t code;
+};
+
 // Everything a kernel needs to address the mesh (device pointers).
 struct MeshView {
   int K, nvar, n_fv, n_face;
@@ -72,6 +84,7 @@ struct MeshView {
   double* ubar_bar;             // adjoint of the sub-cell means, [K][nvar][NFV^3]
   double* fvnorm;               // sub-face normals of internal planes, [K][3][3][(NFV-1) NFV^2]
   const int32_t* elem_face;     // [K][6] face of each element side
+  const SideRec* side_rec;      // [K][6] the same sides as records (element kernels of degree >= FUSE_MIN_N)
   const int32_t* face_conf[MAXN + 1];   // faces with NL = NR = N
   const ConfRec* face_conf_rec[MAXN + 1];   // the same lists as records
   int face_conf_count[MAXN + 1];
@@ -95,13 +108,22 @@ struct MeshView {
 // ---- launchers (defined in the .hip translation units) ----------------------
 // Per-degree launchers; each acts on one degree bucket: `count` elements listed
 // in `elist` (device).  stage 0 writes ut = R(u); stage 1..5 performs the RK
-// stage with coefficients (A, B) on u (in place) and k.
+// stage with coefficients (A, B) on k and writes the new state to uout (u
+// itself when uout is u).
+// Element-kernel flags:
+//  ELEM_WRITE_TRACE  also store the new state of sides 0 and 1 in m.trace;
+//  ELEM_FUSE_FACES   (degrees >= FUSE_MIN_N) evaluate the Riemann flux of every
+//                    conforming face between two pure DG elements in the element
+//                    kernel, from u, which the launch must not write: stage 0,
+//                    or uout != u.  The face kernels then skip that degree's
+//                    conforming class.
+constexpr int ELEM_WRITE_TRACE = 1, ELEM_FUSE_FACES = 2;
+constexpr int FUSE_MIN_N = 6;    // one element per workgroup from here on
 struct DegreeOps {
   // element kernel in tile shape `variant` (0 .. element_variants - 1)
-  // With write_trace the kernel also stores the new state of sides 0 and 1 in m.trace.
   hipError_t (*element)(const MeshView& m, const ParamsDev& p, const int32_t* elist, int count,
-                        const double* u, const double* alpha, double* ut, double* k, int stage,
-                        double dt, double A, double B, int variant, bool write_trace, hipStream_t s);
+                        const double* u, double* uout, const double* alpha, double* ut, double* k, int stage,
+                        double dt, double A, double B, int variant, int flags, hipStream_t s);
   // FV kernels walk this degree's range of the blended-element list (m.blend_list,
   // m.blend_start); `count` bounds the range size.  fv_means runs persistent
   // workgroups, a 1/share part of the device (share = concurrent degree branches)

@@ -43,7 +43,7 @@ class _Params(ctypes.Structure):
 EXPORTED = ("dgfv_mesh_create", "dgfv_mesh_destroy", "dgfv_mesh_info", "dgfv_mesh_node_coords",
             "dg_indicator", "dg_rhs", "dg_rk_stage", "dg_rk_step", "dg_rhs_vjp", "dg_rk_stage_vjp",
             "dg_rk_stage_vjp_noalloc", "dgfv_prim_to_cons", "dg_positivity_limiter",
-            "dgfv_set_positivity_limiter", "dgfv_set_launch_mode", "dgfv_autotune",
+            "dgfv_set_positivity_limiter", "dgfv_set_launch_mode", "dgfv_set_face_fusion", "dgfv_autotune",
             "dgfv_set_element_shape", "dgfv_check_state",
             "dgfv_profile_enable", "dgfv_profile_read", "dgfv_last_error")
 KERNEL_ELEMENT, KERNEL_FACE, KERNEL_FV_MEANS, KERNEL_FV_RESIDUAL, KERNEL_INDICATOR, KERNEL_VJP, KERNEL_FV_FACE = range(7)
@@ -71,6 +71,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dg_positivity_limiter.argtypes = [P, ctypes.POINTER(_Params), P, P, P, P]
     lib.dgfv_set_positivity_limiter.argtypes = [P, c_int]
     lib.dgfv_set_launch_mode.argtypes = [P, c_int]
+    lib.dgfv_set_face_fusion.argtypes = [P, c_int]
     lib.dgfv_set_element_shape.argtypes = [P, c_int, c_int]
     lib.dgfv_autotune.argtypes = [P, ctypes.POINTER(_Params), P, P, ctypes.POINTER(ctypes.c_double), P]
     lib.dgfv_profile_enable.argtypes = [P, c_int]
@@ -177,6 +178,10 @@ class Mesh:
     def positivity_limiter(self, enable: bool = True) -> None:
         """Apply the positivity limiter after every RK stage (``dgfv_set_positivity_limiter``)."""
         _check(_lib.dgfv_set_positivity_limiter(self._h, int(enable)))
+
+    def face_fusion(self, enable: bool = True) -> None:
+        """Element kernels of degree 6, 7 evaluate their conforming DG faces (``dgfv_set_face_fusion``)."""
+        _check(_lib.dgfv_set_face_fusion(self._h, int(enable)))
 
     def graphs(self, enable: bool = True) -> None:
         """Capture and replay RK steps and stages as hipGraphs, or go back to branch launches."""

@@ -62,7 +62,21 @@ def main(src, dst):
     out = {}
     for call in [str(c) for c in z["calls"]]:
         print(f"[cpu_hip] {call}", flush=True)
-        if call == "rhs":
+        if call in ("fusion_off", "fusion_on"):
+            check(lib.dgfv_set_face_fusion(h, int(call == "fusion_on")), call)
+        elif call == "rhs_unfused":
+            r = np.empty_like(u)
+            check(lib.dgfv_set_face_fusion(h, 0), "fusion off")
+            check(lib.dg_rhs(h, ctypes.byref(prm), ptr(u), ptr(alpha), ptr(r), None), "dg_rhs")
+            out["rhs_unfused"] = r
+        elif call == "rk_step_unfused":
+            uu = u.copy()
+            k = np.empty_like(u)
+            check(lib.dgfv_set_face_fusion(h, 0), "fusion off")
+            check(lib.dg_rk_step(h, ctypes.byref(prm), ctypes.c_double(float(z["dt"])), ptr(uu), ptr(k),
+                                 ptr(alpha), None), "dg_rk_step")
+            out["rk_step_unfused"] = uu
+        elif call == "rhs":
             r = np.empty_like(u)
             check(lib.dg_rhs(h, ctypes.byref(prm), ptr(u), ptr(alpha), ptr(r), None), "dg_rhs")
             out["rhs"] = r

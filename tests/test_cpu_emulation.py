@@ -68,6 +68,26 @@ def test_cpu_build_per_element_metrics(n_var):
     assert np.abs(out["rhs"]).max() <= 1e-13 * term_scale(fs.mesh, fs.gas, fs.f.params, fs.u)
 
 
+@pytest.mark.parametrize("n_var", [5, 6])
+def test_cpu_build_fused_faces(n_var):
+    # degrees 5..7 side by side, curved and scrambled, blended elements: the
+    # element kernels of degree 6 and 7 evaluate their conforming DG faces
+    # themselves (dg_rhs; dg_rk_step over two state buffers), with results
+    # equal bit for bit to the separate face kernels' and close to the oracle's
+    flux = {} if n_var == 5 else dict(volume_flux=W.VOL_PIROZZOLI, face_dg=W.RIEMANN_LLF)
+    wl = curved_mixed(n=3, nmin=5, nmax=7, n_var=n_var, scramble=7, metric_degree=0, n_fv=8, **flux)
+    c = _case(wl, smooth_state(41, n_var), noise=1e-3, seed=5)
+    c.alpha = seeded_alpha(c.mesh.K, 13, values=(0.0, 0.0, 0.0, 0.4, 1.0))
+    dt = lsrk.timestep(c.mesh, c.gas, c.u, 0.3)
+    out = cpu_emu.run(wl, c.u.numpy(), ["fusion_on", "rhs", "rk_step", "rhs_unfused", "rk_step_unfused"],
+                      alpha=c.alpha.numpy(), dt=dt)
+    assert np.array_equal(out["rhs"], out["rhs_unfused"])
+    assert np.array_equal(out["rk_step"], out["rk_step_unfused"])
+    assert rel_err(torch.as_tensor(out["rhs"]), c.f(c.u, c.alpha)) <= _tol(c)
+    ref = lsrk.step(lambda v: c.f(v, c.alpha), c.u, dt)
+    assert rel_err(torch.as_tensor(out["rk_step"]), ref) <= _tol(c)
+
+
 def _oracle_vjp(c, w):
     uu = c.u.clone().requires_grad_(True)
     (g,) = torch.autograd.grad((c.f(uu, c.alpha) * w).sum(), uu)
