@@ -216,6 +216,45 @@ enum { DGFV_LAUNCH_SERIAL = 0, DGFV_LAUNCH_BRANCHES = 1, DGFV_LAUNCH_GRAPH = 2 }
 dgfv_status dgfv_set_launch_mode(dgfv_mesh* mesh, int mode);
 
 /*
+ * FV-stored elements (Section 3.1.2, eq. semidiscrete_fv; Section 3.2).
+ * An element with fv_d[e] > 0 carries, instead of its nodal DG state, the
+ * means of N_FV^3 equidistant reference sub-cells (N_FV = the mesh's n_fv, up
+ * to 8: any N_FV >= N + 1 of the paper's range up to 2 N_max + 1 that fits,
+ * e.g. 2N+1 for N <= 3):
+ *   ufv_d: [n_elem][n_var][N_FV^3] device doubles, sub-cell (s1, s2, s3) at
+ *          (s3 N_FV + s2) N_FV + s1; read and written only on FV elements;
+ *   fv_d:  [n_elem] device doubles, > 0 on FV elements, 0 on DG elements.
+ * The means are J-weighted, ufv = V3(J u) / V3(J).  Their rate is minus the sum
+ * of the six sub-face fluxes over h^3 V3(J) (h = 2 / N_FV), each flux taken
+ * between states reconstructed to the sub-face: per reference direction the
+ * slope of a sub-cell's primitive variables (rho, v, p[, Y1]) is the minmod of
+ * its backward and forward differences, and across an element side the
+ * neighbour is the adjacent sub-cell mean of an FV element or the DG
+ * element's nodal trace mapped with V^{DG->FV} in both face directions
+ * (fig. h_coupling); a DG side's own value on such a face is that mapped
+ * trace, and it receives the flux through V^{FV->DG} / h^2.  Faces between two
+ * DG elements, and the DG elements, are as in dg_rhs with alpha = 0; the
+ * nodal slots of FV elements are neither read nor written.
+ *   dg_rhs_fv:      ut_d = R(u) on DG elements, utfv_d = R(ufv) on FV elements;
+ *   dg_rk_stage_fv: stage s of dg_rk_stage on (u, k) and on (ufv, kfv);
+ *   dg_switch_fv:   converts the elements whose flag goes from fv_old_d to
+ *                   fv_new_d: DG -> FV ufv = V3(J u) / V3(J); FV -> DG
+ *                   u = V3^+(ufv V3(J)) / J (the least-squares nodal state
+ *                   with those sub-cell contents; exact inverse for
+ *                   N_FV = N + 1).  Other elements are untouched.
+ * The first call allocates the mesh's ghost-layer buffer (n_elem 6 n_var N_FV^2
+ * doubles) and V3(J) (n_elem N_FV^3): DGFV_ERR_ARG while the stream is
+ * captured, DGFV_ERR_OOM when the memory is short.  No positivity limiter and
+ * no graphs on this path.
+ */
+dgfv_status dg_rhs_fv(const dgfv_mesh* mesh, const dgfv_params* params, const double* u_d, const double* ufv_d,
+                      const double* fv_d, double* ut_d, double* utfv_d, void* stream);
+dgfv_status dg_rk_stage_fv(const dgfv_mesh* mesh, const dgfv_params* params, int stage, double dt, double* u_d,
+                           double* k_d, double* ufv_d, double* kfv_d, const double* fv_d, void* stream);
+dgfv_status dg_switch_fv(const dgfv_mesh* mesh, double* u_d, double* ufv_d, const double* fv_old_d,
+                         const double* fv_new_d, void* stream);
+
+/*
  * Fused face fluxes (not part of the method; off by default).  Elements of
  * degree 6 and 7 evaluate the Riemann flux (eq. conv_flux) of each face they
  * share with a pure DG element of the same degree themselves, with the same

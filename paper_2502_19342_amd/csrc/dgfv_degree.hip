@@ -40,7 +40,7 @@ constexpr int elem_variants(int N) { return (N + 1) * (N + 1) * (N + 1) >= 256 ?
 // ---------------------------------------------------------------------------
 // element kernel
 // ---------------------------------------------------------------------------
-template <int N, int NV, class FLUX, int EPB>
+template <int N, int NV, class FLUX, int EPB, bool FUSE>
 __global__ void __launch_bounds__(EPB * Geo<N>::NP3)
 element_kernel(MeshView m, ParamsDev prm, const int32_t* __restrict__ elist, int count, const double* u,
                double* uout, const double* __restrict__ alpha, double* __restrict__ ut, double* k, int stage,
@@ -70,7 +70,7 @@ element_kernel(MeshView m, ParamsDev prm, const int32_t* __restrict__ elist, int
   const int slot = tid / NP3;
   const int node = tid - slot * NP3;
   const int idx = blockIdx.x * EPB + slot;
-  const bool active = idx < count;          // inactive lanes mirror element 0 and write nothing
+  const bool in_range = idx < count;        // lanes past the list mirror element 0 and write nothing
 
   // The two-point fluxes are linear in the metric direction: they are evaluated
   // with the sum Ja_i + Ja_m instead of the mean, so the weights are D_im
@@ -81,7 +81,7 @@ element_kernel(MeshView m, ParamsDev prm, const int32_t* __restrict__ elist, int
   // with one element per workgroup the element index is wave-uniform: kept in
   // a scalar register, its per-element records (offsets, alpha, side block)
   // are scalar loads held in scalar registers for the whole kernel
-  int e = elist[active ? idx : 0];
+  int e = elist[in_range ? idx : 0];
   if constexpr (EPB == 1) e = __builtin_amdgcn_readfirstlane(e);
   const int64_t base = m.elem_offset[e] + node;
   const double inv_w0 = 1.0 / m.ops[m.tab.w[N]];    // lift weight, loaded early
@@ -89,6 +89,14 @@ element_kernel(MeshView m, ParamsDev prm, const int32_t* __restrict__ elist, int
 #pragma unroll
   for (int v = 0; v < NV; ++v) uo[v] = u[v * m.n_node + base];
   const double al = alpha ? alpha[e] : 0.0;
+  // An FV-stored element (ELEM_SKIP_FV, alpha >= 1) is left alone: its lanes
+  // compute on its unused nodal slot and write nothing (one element per
+  // workgroup: the whole workgroup leaves before the first barrier).
+  const bool skip_fv = (flags & ELEM_SKIP_FV) && al >= 1.0;
+  if constexpr (EPB == 1) {
+    if (skip_fv) return;
+  }
+  const bool active = in_range && !skip_fv;
   const double* fs = m.fside + m.side_off[e];
   const bool write_trace = flags & ELEM_WRITE_TRACE;
   // Fused faces (one element per workgroup): lane t < 6 (N+1)^2 takes point
@@ -99,8 +107,9 @@ element_kernel(MeshView m, ParamsDev prm, const int32_t* __restrict__ elist, int
   // the other sides (degree jumps, FV faces) take the point's value from the
   // side buffer, written by the face kernels.  The neighbour's state is read
   // from u, which no workgroup of this launch writes (stage 0, or uout != u).
-  constexpr bool CAN_FUSE = STAGE_SIDES;
-  const bool fuse = CAN_FUSE && (flags & ELEM_FUSE_FACES);
+  // (a separate instantiation: the unfused kernel carries none of this code)
+  constexpr bool CAN_FUSE = STAGE_SIDES && FUSE;
+  constexpr bool fuse = CAN_FUSE;
   double sv[SIDE_PER];
   double fv[NV];
   int fdst = -1;                           // this lane's point in sSide (fused), or none
@@ -200,7 +209,7 @@ element_kernel(MeshView m, ParamsDev prm, const int32_t* __restrict__ elist, int
   }
   {
     const Prim q = cons2prim<NV>(uo, m.gas);
-    if (!(q.rho > 0.0) || !(q.p > 0.0)) m.state_flag[0] = 1;     // rho <= 0, p <= 0 or NaN
+    if (active && (!(q.rho > 0.0) || !(q.p > 0.0))) m.state_flag[0] = 1;   // rho <= 0, p <= 0 or NaN
     double r[NA];
     FLUX::template make<NV>(q, r);
 #pragma unroll
@@ -1383,6 +1392,132 @@ limiter_kernel(MeshView m, const int32_t* __restrict__ elist, int count, double*
 }
 
 // ---------------------------------------------------------------------------
+// FV-stored elements (Sections 3.1.2 and 3.2): the sub-cell means of J, set up
+// once, and the switch of an element between its nodal DG state and its
+// sub-cell means.
+// ---------------------------------------------------------------------------
+constexpr int FVS_THREADS = 512;
+
+// Tensor map A (x) A (x) A (A: NOUT x NIN, row-major) of F fields on LDS:
+// in: a[F][NIN^3] (c fastest) -> out: b[F][NOUT^3]; a is overwritten.  One
+// one-dimensional contraction per pass, each thread holding one input line
+// in registers and forming every output along the contracted axis.
+template <int NIN, int NOUT, int F, int TH>
+__device__ void map3(const double* __restrict__ A, double* a, double* b) {
+  const int t = threadIdx.x;
+  for (int r = t; r < F * NIN * NIN; r += TH) {                // axis 0: [f][k][j][c] -> [f][k][j][s0]
+    double x[NIN];
+#pragma unroll
+    for (int c = 0; c < NIN; ++c) x[c] = a[r * NIN + c];
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) {
+      double acc = 0.0;
+#pragma unroll
+      for (int c = 0; c < NIN; ++c) acc += A[o * NIN + c] * x[c];
+      b[r * NOUT + o] = acc;
+    }
+  }
+  __syncthreads();
+  for (int r = t; r < F * NIN * NOUT; r += TH) {               // axis 1: [f][k][c][s0] -> [f][k][s1][s0]
+    const int s0 = r % NOUT, kf = r / NOUT;
+    double x[NIN];
+#pragma unroll
+    for (int c = 0; c < NIN; ++c) x[c] = b[(kf * NIN + c) * NOUT + s0];
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) {
+      double acc = 0.0;
+#pragma unroll
+      for (int c = 0; c < NIN; ++c) acc += A[o * NIN + c] * x[c];
+      a[(kf * NOUT + o) * NOUT + s0] = acc;
+    }
+  }
+  __syncthreads();
+  for (int r = t; r < F * NOUT * NOUT; r += TH) {              // axis 2: [f][c][s1][s0] -> [f][s2][s1][s0]
+    const int s01 = r % (NOUT * NOUT), f = r / (NOUT * NOUT);
+    double x[NIN];
+#pragma unroll
+    for (int c = 0; c < NIN; ++c) x[c] = a[(f * NIN + c) * NOUT * NOUT + s01];
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) {
+      double acc = 0.0;
+#pragma unroll
+      for (int c = 0; c < NIN; ++c) acc += A[o * NIN + c] * x[c];
+      b[(f * NOUT + o) * NOUT * NOUT + s01] = acc;
+    }
+  }
+  __syncthreads();
+}
+
+// m.fvjbar[e] = V3(J) for the elements of one bucket, one element per workgroup.
+template <int N, int NFV>
+__global__ void __launch_bounds__(FVS_THREADS)
+fv_jbar_kernel(MeshView m, const int32_t* __restrict__ elist, int count) {
+  constexpr int NP = N + 1, NP3 = NP * NP * NP, S3 = NFV * NFV * NFV;
+  constexpr int BIG = NP3 > S3 ? NP3 : S3;
+  __shared__ double a[BIG], b[BIG];
+  __shared__ double sV[NFV * NP];
+  if ((int)blockIdx.x >= count) return;
+  const int t = threadIdx.x;
+  const int e = elist[blockIdx.x];
+  const int64_t base = m.elem_offset[e];
+  if (t < NFV * NP) sV[t] = m.ops[m.tab.dg2fv[N] + t];
+  for (int r = t; r < NP3; r += FVS_THREADS) a[r] = m.metric[9 * m.n_node + base + r];
+  __syncthreads();
+  map3<NP, NFV, 1, FVS_THREADS>(sV, a, b);
+  for (int r = t; r < S3; r += FVS_THREADS) m.fvjbar[(size_t)e * S3 + r] = b[r];
+}
+
+// Switch of the bucket's elements whose flag changes (fv > 0: FV-stored).
+//   DG -> FV: ufv = V3(J u) / V3(J)         (J-weighted sub-cell means)
+//   FV -> DG: u = V3^+(ufv V3(J)) / J       (least-squares nodal state with those contents)
+template <int N, int NFV, int NV>
+__global__ void __launch_bounds__(FVS_THREADS)
+fv_switch_kernel(MeshView m, const int32_t* __restrict__ elist, int count, double* __restrict__ u,
+                 double* __restrict__ ufv, const double* __restrict__ fv_old, const double* __restrict__ fv_new) {
+  constexpr int NP = N + 1, NP3 = NP * NP * NP, S3 = NFV * NFV * NFV;
+  constexpr int BIG = (NV + 1) * (NP3 > S3 ? NP3 : S3);
+  __shared__ double a[BIG], b[BIG];
+  __shared__ double sA[NFV * NP];
+  if ((int)blockIdx.x >= count) return;
+  const int t = threadIdx.x;
+  const int e = elist[blockIdx.x];
+  const bool was_fv = fv_old[e] > 0.0, is_fv = fv_new[e] > 0.0;
+  if (was_fv == is_fv) return;                    // uniform over the workgroup
+  const int64_t base = m.elem_offset[e];
+  double* ue = ufv + (size_t)e * NV * S3;
+  if (is_fv) {
+    if (t < NFV * NP) sA[t] = m.ops[m.tab.dg2fv[N] + t];
+    for (int r = t; r < NP3; r += FVS_THREADS) {
+      const double J = m.metric[9 * m.n_node + base + r];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) a[v * NP3 + r] = J * u[v * m.n_node + base + r];
+      a[NV * NP3 + r] = J;
+    }
+    __syncthreads();
+    map3<NP, NFV, NV + 1, FVS_THREADS>(sA, a, b);
+    for (int r = t; r < S3; r += FVS_THREADS) {
+      const double ivol = 1.0 / b[NV * S3 + r];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) ue[v * S3 + r] = b[v * S3 + r] * ivol;
+    }
+  } else {
+    if (t < NFV * NP) sA[t] = m.ops[m.tab.fv2dg[N] + t];
+    for (int r = t; r < S3; r += FVS_THREADS) {
+      const double jb = m.fvjbar[(size_t)e * S3 + r];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) a[v * S3 + r] = ue[v * S3 + r] * jb;
+    }
+    __syncthreads();
+    map3<NFV, NP, NV, FVS_THREADS>(sA, a, b);
+    for (int r = t; r < NP3; r += FVS_THREADS) {
+      const double iJ = 1.0 / m.metric[9 * m.n_node + base + r];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) u[v * m.n_node + base + r] = b[v * NP3 + r] * iJ;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // launchers for this degree
 // ---------------------------------------------------------------------------
 template <int NV, class FLUX, int V>
@@ -1391,8 +1526,15 @@ static hipError_t launch_elem_v(const MeshView& m, const ParamsDev& p, const int
                                 int stage, double dt, double A, double B, int flags, hipStream_t s) {
   constexpr int EPB = elem_epb<kN, V>();
   const int blocks = (count + EPB - 1) / EPB;
-  hipLaunchKernelGGL((element_kernel<kN, NV, FLUX, EPB>), dim3(blocks), dim3(EPB * Geo<kN>::NP3), 0, s, m, p,
-                     elist, count, u, uout, alpha, ut, k, stage, dt, A, B, flags);
+  if constexpr (EPB == 1) {
+    if (flags & ELEM_FUSE_FACES) {
+      hipLaunchKernelGGL((element_kernel<kN, NV, FLUX, EPB, true>), dim3(blocks), dim3(EPB * Geo<kN>::NP3), 0, s, m,
+                         p, elist, count, u, uout, alpha, ut, k, stage, dt, A, B, flags);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((element_kernel<kN, NV, FLUX, EPB, false>), dim3(blocks), dim3(EPB * Geo<kN>::NP3), 0, s, m,
+                     p, elist, count, u, uout, alpha, ut, k, stage, dt, A, B, flags);
   return hipGetLastError();
 }
 
@@ -1513,6 +1655,59 @@ hipError_t indicator(const MeshView& m, const ParamsDev& p, const int32_t* elist
   return hipGetLastError();
 }
 
+template <int NFV>
+hipError_t fv_jbar_t(const MeshView& m, const int32_t* elist, int count, hipStream_t s) {
+  if constexpr (NFV >= kN + 1) {
+    hipLaunchKernelGGL((fv_jbar_kernel<kN, NFV>), dim3(count), dim3(FVS_THREADS), 0, s, m, elist, count);
+    return hipGetLastError();
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t fv_jbar(const MeshView& m, const int32_t* elist, int count, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  switch (m.n_fv) {
+    case 2: return fv_jbar_t<2>(m, elist, count, s);
+    case 3: return fv_jbar_t<3>(m, elist, count, s);
+    case 4: return fv_jbar_t<4>(m, elist, count, s);
+    case 5: return fv_jbar_t<5>(m, elist, count, s);
+    case 6: return fv_jbar_t<6>(m, elist, count, s);
+    case 7: return fv_jbar_t<7>(m, elist, count, s);
+    case 8: return fv_jbar_t<8>(m, elist, count, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int NFV>
+hipError_t fv_switch_t(const MeshView& m, const int32_t* elist, int count, double* u, double* ufv,
+                       const double* fv_old, const double* fv_new, hipStream_t s) {
+  if constexpr (NFV >= kN + 1) {
+    if (m.nvar == 5)
+      hipLaunchKernelGGL((fv_switch_kernel<kN, NFV, 5>), dim3(count), dim3(FVS_THREADS), 0, s, m, elist, count, u,
+                         ufv, fv_old, fv_new);
+    else
+      hipLaunchKernelGGL((fv_switch_kernel<kN, NFV, 6>), dim3(count), dim3(FVS_THREADS), 0, s, m, elist, count, u,
+                         ufv, fv_old, fv_new);
+    return hipGetLastError();
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t fv_switch(const MeshView& m, const int32_t* elist, int count, double* u, double* ufv,
+                     const double* fv_old, const double* fv_new, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  switch (m.n_fv) {
+    case 2: return fv_switch_t<2>(m, elist, count, u, ufv, fv_old, fv_new, s);
+    case 3: return fv_switch_t<3>(m, elist, count, u, ufv, fv_old, fv_new, s);
+    case 4: return fv_switch_t<4>(m, elist, count, u, ufv, fv_old, fv_new, s);
+    case 5: return fv_switch_t<5>(m, elist, count, u, ufv, fv_old, fv_new, s);
+    case 6: return fv_switch_t<6>(m, elist, count, u, ufv, fv_old, fv_new, s);
+    case 7: return fv_switch_t<7>(m, elist, count, u, ufv, fv_old, fv_new, s);
+    case 8: return fv_switch_t<8>(m, elist, count, u, ufv, fv_old, fv_new, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 hipError_t limiter(const MeshView& m, const int32_t* elist, int count, double* u, const double* alpha,
                    double* theta, hipStream_t s) {
   if (count == 0) return hipSuccess;
@@ -1580,7 +1775,8 @@ hipError_t vjp_gather(const MeshView& m, const int32_t* elist, int count, const 
 DegreeOps DGFV_CAT(degree_ops_, DGFV_N)() {
   return DegreeOps{&per_degree::element,    &per_degree::fv_means, &per_degree::fv_residual,
                    &per_degree::indicator,  &per_degree::vjp_volume, &per_degree::vjp_fv,
-                   &per_degree::vjp_gather, &per_degree::fv_normals, &per_degree::limiter, elem_variants(kN)};
+                   &per_degree::vjp_gather, &per_degree::fv_normals, &per_degree::limiter,
+                   &per_degree::fv_jbar,    &per_degree::fv_switch,  elem_variants(kN)};
 }
 
 }  // namespace dgfv

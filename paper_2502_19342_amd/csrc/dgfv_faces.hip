@@ -488,6 +488,176 @@ face_fv_kernel(MeshView m, ParamsDev prm, const double* __restrict__ u, const do
   }
 }
 
+// ---------------------------------------------------------------------------
+// Faces with an FV-stored side (Sections 3.1.2 and 3.2, fig. h_coupling).
+// Each side's value on the sub-face grid: an FV side's boundary sub-cell mean
+// reconstructed to the face, w_b + minmod(w_b - w_i, w_g - w_b) / 2 on the
+// primitives (w_i the next sub-cell inwards, w_g the state across the face);
+// a DG side's nodal trace mapped with V^{DG->FV} in both face directions.
+// The state across the face (the other side's boundary sub-cell mean, or the
+// mapped DG trace) goes to m.fvghost for the FV element's own slopes.  One
+// Riemann flux per sub-face goes to m.fvside of FV sides and, through
+// V^{FV->DG} / h^2, to m.fside of a DG side.
+// ---------------------------------------------------------------------------
+template <int NV>
+__device__ void face_body_fvs(const MeshView& m, const ParamsDev& prm, const double* __restrict__ u,
+                              const double* __restrict__ ufv, const double* __restrict__ fv, int f, double* B0,
+                              double* B1, double* B2, double* B3, double* B4, double* B5, double* sN, double* sNF) {
+  static_assert(GRID == FACE_THREADS, "one point per lane");
+  const int32_t* fc = m.faces + 5 * f;
+  const int eL = fc[0], sideL = fc[1], eR = fc[2], sideR = fc[3], o = fc[4];
+  const int NL = m.degree[eL], NR = m.degree[eR];
+  const int M = NL > NR ? NL : NR;
+  const int nL = NL + 1, nR = NR + 1, nM = M + 1, nn = nM * nM;
+  const bool fL = fv[eL] > 0.0, fR = fv[eR] > 0.0;
+  const double* nrm = m.face_norm + m.face_norm_off[f];
+  const int nF = m.n_fv, n2F = nF * nF, S3 = n2F * nF;
+  const double h = 2.0 / nF;
+  const int t = threadIdx.x;
+  {
+    // one point of each grid per lane, every load issued before the first store
+    auto source = [&](int e, int side, bool is_fv, int n, bool right, const double*& s0, const double*& s1,
+                      int64_t& vs) {
+      const int tc = t < n * n ? t : 0;            // in-range index for idle lanes
+      int p = tc % n, q = tc / n;
+      if (right) orient_map(o, p, q, n, p, q);
+      if (is_fv) {
+        const double* ub = ufv + (size_t)e * NV * S3;
+        const int b0 = side_node(side, p, q, n);
+        const int step = (side >> 1) == 0 ? 1 : ((side >> 1) == 1 ? n : n * n);
+        s0 = ub + b0;
+        s1 = ub + ((side & 1) ? b0 - step : b0 + step);      // the next sub-cell inwards
+        vs = S3;
+      } else {
+        s0 = u + m.elem_offset[e] + side_node(side, p, q, n);
+        s1 = s0;
+        vs = m.n_node;
+      }
+    };
+    const int nl = fL ? nF : nL, nr = fR ? nF : nR;
+    const double *aL0, *aL1, *aR0, *aR1;
+    int64_t vL, vR;
+    source(eL, sideL, fL, nl, false, aL0, aL1, vL);
+    source(eR, sideR, fR, nr, true, aR0, aR1, vR);
+    const int tn = t < nn ? t : 0;
+    double xl[NV], xr[NV], yl[NV], yr[NV], xn[3];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      xl[v] = aL0[v * vL];
+      xr[v] = aR0[v * vR];
+      yl[v] = aL1[v * vL];
+      yr[v] = aR1[v * vR];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) xn[c] = nrm[c * nn + tn];
+    if (t < nl * nl)
+      for (int v = 0; v < NV; ++v) B0[v * GRID + t] = xl[v];
+    if (t < nr * nr)
+      for (int v = 0; v < NV; ++v) B1[v * GRID + t] = xr[v];
+    if (fL && t < n2F)
+      for (int v = 0; v < NV; ++v) B4[v * GRID + t] = yl[v];
+    if (fR && t < n2F)
+      for (int v = 0; v < NV; ++v) B5[v * GRID + t] = yr[v];
+    if (t < nn)
+      for (int c = 0; c < 3; ++c) sN[c * GRID + t] = xn[c];
+  }
+  wave_sync();
+  // normals to the sub-face grid (B2 as scratch); at most one side is DG, and
+  // its trace follows, with the buffers the FV side leaves free as scratch
+  const double* LF = B0;
+  const double* RF = B1;
+  map2d_sep_to<3>(sN, B2, sNF, m.ops + m.tab.dg2fv[M], nF, nM);
+  wave_sync();
+  if (!fL) { map2d_sep_to<NV>(B0, B3, B2, m.ops + m.tab.dg2fv[NL], nF, nL); LF = B2; }
+  if (!fR) { map2d_sep_to<NV>(B1, B2, B3, m.ops + m.tab.dg2fv[NR], nF, nR); RF = B3; }
+  wave_sync();
+  double* F = LF == B2 ? B0 : B2;
+  double* fvL = m.fvside + (size_t)eL * 6 * NV * n2F;
+  double* fvR = m.fvside + (size_t)eR * 6 * NV * n2F;
+  double* ghL = m.fvghost + (size_t)eL * 6 * NV * n2F;
+  double* ghR = m.fvghost + (size_t)eR * 6 * NV * n2F;
+  const double a = h * h;
+  for (int tt = t; tt < n2F; tt += blockDim.x) {
+    double cL[NV], cR[NV], vL[NV], vR[NV], Fl[NV];
+    for (int v = 0; v < NV; ++v) {
+      cL[v] = LF[v * GRID + tt];
+      cR[v] = RF[v * GRID + tt];
+      vL[v] = cL[v];
+      vR[v] = cR[v];
+    }
+    auto reconstruct = [&](const double* cb, const double* ci, const double* cg, double* out) {
+      double wb[NV], wi[NV], wg[NV], wf[NV];
+      cons_to_w<NV>(cb, m.gas, wb);
+      cons_to_w<NV>(ci, m.gas, wi);
+      cons_to_w<NV>(cg, m.gas, wg);
+      for (int v = 0; v < NV; ++v) wf[v] = wb[v] + 0.5 * minmod(wb[v] - wi[v], wg[v] - wb[v]);
+      w_to_cons<NV>(wf, m.gas, out);
+    };
+    if (fL) {
+      double ci[NV];
+      for (int v = 0; v < NV; ++v) ci[v] = B4[v * GRID + tt];
+      reconstruct(cL, ci, cR, vL);
+    }
+    if (fR) {
+      double ci[NV];
+      for (int v = 0; v < NV; ++v) ci[v] = B5[v * GRID + tt];
+      reconstruct(cR, ci, cL, vR);
+    }
+    riemann<NV>(prm.face_flux_fv, prm.volume_flux, vL, vR, a * sNF[tt], a * sNF[GRID + tt],
+                a * sNF[2 * GRID + tt], m.gas, Fl);
+    for (int v = 0; v < NV; ++v) F[v * GRID + tt] = Fl[v];
+    const int p = tt % nF, q = tt / nF;
+    if (fL)
+      for (int v = 0; v < NV; ++v) {
+        fvL[(sideL * NV + v) * n2F + q * nF + p] = Fl[v];
+        ghL[(sideL * NV + v) * n2F + q * nF + p] = cR[v];
+      }
+    if (fR) {
+      int pp, qq;
+      orient_map(o, p, q, nF, pp, qq);
+      for (int v = 0; v < NV; ++v) {
+        fvR[(sideR * NV + v) * n2F + qq * nF + pp] = -Fl[v];
+        ghR[(sideR * NV + v) * n2F + qq * nF + pp] = cL[v];
+      }
+    }
+  }
+  wave_sync();
+  // a DG side receives V^{FV->DG} F / h^2 (two passes through a buffer other than F)
+  const double ih2 = 1.0 / (h * h);
+  double* Tt = F == B0 ? B1 : B0;
+  if (!fL) {
+    map2d_pass1<NV>(F, Tt, m.ops + m.tab.fv2dg[NL], nL, nF);
+    wave_sync();
+    map2d_pass2_side<NV>(m.fside + m.side_off[eL], Tt, m.ops + m.tab.fv2dg[NL], nL, nF, sideL, o, false, ih2);
+  }
+  if (!fR) {
+    map2d_pass1<NV>(F, Tt, m.ops + m.tab.fv2dg[NR], nR, nF);
+    wave_sync();
+    map2d_pass2_side<NV>(m.fside + m.side_off[eR], Tt, m.ops + m.tab.fv2dg[NR], nR, nF, sideR, o, true, -ih2);
+  }
+}
+
+// One workgroup per FV-stored element of the call's list (a grid of K, the
+// workgroups past the list leaving at once), over the faces it owns (the left
+// element owns a face when it is FV-stored, otherwise the right one).
+template <int NV>
+__global__ void __launch_bounds__(FACE_THREADS)
+face_fvs_kernel(MeshView m, ParamsDev prm, const double* __restrict__ u, const double* __restrict__ ufv,
+                const double* __restrict__ fv) {
+  __shared__ double B0[NV * GRID], B1[NV * GRID], B2[NV * GRID], B3[NV * GRID], B4[NV * GRID], B5[NV * GRID];
+  __shared__ double sN[3 * GRID], sNF[3 * GRID];
+  if ((int)blockIdx.x >= m.blend_start[MAXN + 1]) return;
+  const int e = m.blend_list[blockIdx.x];
+  for (int side = 0; side < 6; ++side) {
+    const int f = m.elem_face[6 * e + side];
+    const int32_t* fc = m.faces + 5 * f;
+    const bool left = fc[0] == e && fc[1] == side;
+    if (!left && fv[fc[0]] > 0.0) continue;          // the FV-stored left element owns it
+    face_body_fvs<NV>(m, prm, u, ufv, fv, f, B0, B1, B2, B3, B4, B5, sN, sNF);
+    wave_sync();
+  }
+}
+
 // Gather side data [NV][n*n] from a side block (`right` re-indexes onto the left grid).
 template <int NV>
 __device__ void gather_side(const double* blk, int side, int o, bool right, int n, double* dst) {
@@ -770,6 +940,16 @@ static hipError_t launch_face_class_t(const MeshView& m, const ParamsDev& p, con
     return hipGetLastError();
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_face_fv_stored(const MeshView& m, const ParamsDev& p, const double* u, const double* ufv,
+                                 const double* fv, hipStream_t s) {
+  if (m.n_face == 0) return hipSuccess;
+  if (m.nvar == 5)
+    hipLaunchKernelGGL((face_fvs_kernel<5>), dim3(m.K), dim3(FACE_THREADS), 0, s, m, p, u, ufv, fv);
+  else
+    hipLaunchKernelGGL((face_fvs_kernel<6>), dim3(m.K), dim3(FACE_THREADS), 0, s, m, p, u, ufv, fv);
+  return hipGetLastError();
 }
 
 bool face_class_present(const MeshView& m, const double* alpha, int cls) {

@@ -36,6 +36,8 @@ void hip_check(hipError_t e, const char* what) {
   if (e != hipSuccess) throw HipError(std::string(what) + ": " + hipGetErrorString(e));
 }
 
+bool msg_oom(const HipError& e) { return std::string(e.what()).find("out of memory") != std::string::npos; }
+
 template <class T>
 T* dev_upload(const std::vector<T>& h) {
   T* d = nullptr;
@@ -142,6 +144,11 @@ struct dgfv_mesh {
   bool fuse_faces = false;
   mutable double* u_alt = nullptr;
 
+  // FV-stored elements: ghost layers [K][6][nvar][N_FV^2] and V3(J) [K][N_FV^3],
+  // made by the first call that has FV-stored elements
+  mutable double* fvghost = nullptr;
+  mutable double* fvjbar = nullptr;
+
   // kernel timing (mutable: recording does not change the mesh)
   mutable bool profile = false;
   mutable std::array<std::vector<std::pair<hipEvent_t, hipEvent_t>>, DGFV_KERNEL_COUNT> ev;
@@ -169,6 +176,8 @@ struct dgfv_mesh {
     for (void* p : allocations) (void)hipFree(p);
     if (stage_g) (void)hipFree(stage_g);
     if (u_alt) (void)hipFree(u_alt);
+    if (fvghost) (void)hipFree(fvghost);
+    if (fvjbar) (void)hipFree(fvjbar);
   }
   template <class T>
   T* keep(T* p) {
@@ -570,6 +579,75 @@ void enqueue_rhs_impl(const dgfv_mesh* m, const ParamsDev& p, const double* u, d
     });
   }
   if (stage > 0 && m->limiter_on) enqueue_limiter(m, uout, alpha, nullptr, s, false);
+}
+
+// The mesh view with the FV-stored elements' buffers.
+MeshView fvs_view(const dgfv_mesh* m) {
+  MeshView v = m->view;
+  v.fvghost = m->fvghost;
+  v.fvjbar = m->fvjbar;
+  return v;
+}
+
+// The FV-stored elements' buffers and V3(J), once (enqueued on s).
+void ensure_fv_stored(const dgfv_mesh* m, hipStream_t s) {
+  if (m->fvghost) return;
+  const size_t nf = (size_t)m->n_fv;
+  double* g = dev_alloc<double>((size_t)m->K * 6 * m->nvar * nf * nf);
+  double* j = nullptr;
+  try {
+    j = dev_alloc<double>((size_t)m->K * nf * nf * nf);
+  } catch (...) {
+    (void)hipFree(g);
+    throw;
+  }
+  m->fvghost = g;
+  m->fvjbar = j;
+  const MeshView v = fvs_view(m);
+  for (int N = 1; N <= MAXN; ++N)
+    if (!m->bucket[N].empty())
+      hip_check(ops_for(N).fv_jbar(v, m->d_bucket[N], (int)m->bucket[N].size(), s), "fv_jbar launch");
+}
+
+// One evaluation with FV-stored elements (fv[e] > 0): stage 0 -> ut = R(u) on
+// DG elements and utfv = R(ufv) on FV elements; stage 1..5 -> the RK stage on
+// (u, k) and (ufv, kfv).  Phases: the FV-element list; the DG faces (both
+// sides DG) and the faces with an FV side; the FV elements' rates; the DG
+// element kernels, which leave the FV elements alone.
+void enqueue_rhs_fvs(const dgfv_mesh* m, const ParamsDev& p, double* u, double* ufv, const double* fv, double* ut,
+                     double* utfv, double* k, double* kfv, int stage, double dt, hipStream_t s) {
+  ensure_fv_stored(m, s);
+  const MeshView v = fvs_view(m);
+  const double A = stage > 0 ? RK_A[stage - 1] : 0.0;
+  const double B = stage > 0 ? RK_B[stage - 1] : 0.0;
+  const std::vector<int> degs = degrees_present(m);
+  hip_check(launch_blend_list(v, fv, s), "FV element list launch");
+  {
+    Timed t(m, DGFV_KERNEL_FACE, s);
+    std::vector<int> classes;
+    for (int c = 1; c < FACE_CLASS_COUNT; ++c)
+      if (c != FACE_CLASS_FV && face_class_present(v, fv, c)) classes.push_back(c);
+    classes.push_back(FACE_CLASS_FV);
+    fork_join(m, s, classes, [&](int c, hipStream_t ss) {
+      Timed tf(m, c == FACE_CLASS_FV ? DGFV_KERNEL_FV_FACE : -1, ss);
+      if (c == FACE_CLASS_FV)
+        hip_check(launch_face_fv_stored(v, p, u, ufv, fv, ss), "FV-stored face launch");
+      else
+        hip_check(launch_face_class(v, p, u, fv, c, false, ss), "face launch");
+    });
+  }
+  {
+    Timed t(m, DGFV_KERNEL_FV_RESIDUAL, s);
+    hip_check(launch_fv_stored(v, p, ufv, kfv, utfv, stage, dt, A, B, s), "FV-stored element launch");
+  }
+  {
+    Timed t(m, DGFV_KERNEL_ELEMENT, s);
+    fork_join(m, s, degs, [&](int N, hipStream_t ss) {
+      hip_check(ops_for(N).element(v, p, m->d_bucket[N], (int)m->bucket[N].size(), u, u, fv, ut, k, stage, dt,
+                                   A, B, m->elem_variant[N], ELEM_SKIP_FV, ss),
+                "element launch");
+    });
+  }
 }
 
 bool has_fused_degree(const dgfv_mesh* m) {
@@ -1274,6 +1352,61 @@ dgfv_status dg_positivity_limiter(const dgfv_mesh* m, const dgfv_params* prm, do
     enqueue_limiter(m, u, alpha, theta, (hipStream_t)stream, true);
   } catch (const HipError& e) {
     return fail(DGFV_ERR_HIP, e.what());
+  }
+  return DGFV_OK;
+}
+
+dgfv_status dg_rhs_fv(const dgfv_mesh* m, const dgfv_params* prm, const double* u, const double* ufv,
+                      const double* fv, double* ut, double* utfv, void* stream) {
+  if (!m || !u || !ufv || !fv || !ut || !utfv) return fail(DGFV_ERR_ARG, "NULL argument");
+  if (u == ut || ufv == utfv) return fail(DGFV_ERR_ARG, "inputs and outputs must not overlap");
+  if (dgfv_status st = check_params(m, prm)) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if (!m->fvghost && capturing(s)) return fail(DGFV_ERR_ARG, "the first call with FV-stored elements allocates: not under capture");
+  return guarded(m, s, [&] {
+    try {
+      enqueue_rhs_fvs(m, to_dev(prm), const_cast<double*>(u), const_cast<double*>(ufv), fv, ut, utfv, nullptr,
+                      nullptr, 0, 0.0, s);
+    } catch (const HipError& e) {
+      return fail(msg_oom(e) ? DGFV_ERR_OOM : DGFV_ERR_HIP, e.what());
+    }
+    return DGFV_OK;
+  });
+}
+
+dgfv_status dg_rk_stage_fv(const dgfv_mesh* m, const dgfv_params* prm, int stage, double dt, double* u, double* k,
+                           double* ufv, double* kfv, const double* fv, void* stream) {
+  if (!m || !u || !k || !ufv || !kfv || !fv) return fail(DGFV_ERR_ARG, "NULL argument");
+  if (stage < 1 || stage > 5) return fail(DGFV_ERR_ARG, "stage must be 1..5");
+  if (!std::isfinite(dt)) return fail(DGFV_ERR_ARG, "dt must be finite");
+  if (u == k || ufv == kfv) return fail(DGFV_ERR_ARG, "states and registers must not overlap");
+  if (dgfv_status st = check_params(m, prm)) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if (!m->fvghost && capturing(s)) return fail(DGFV_ERR_ARG, "the first call with FV-stored elements allocates: not under capture");
+  return guarded(m, s, [&] {
+    try {
+      enqueue_rhs_fvs(m, to_dev(prm), u, ufv, fv, nullptr, nullptr, k, kfv, stage, dt, s);
+    } catch (const HipError& e) {
+      return fail(msg_oom(e) ? DGFV_ERR_OOM : DGFV_ERR_HIP, e.what());
+    }
+    return DGFV_OK;
+  });
+}
+
+dgfv_status dg_switch_fv(const dgfv_mesh* m, double* u, double* ufv, const double* fv_old, const double* fv_new,
+                         void* stream) {
+  if (!m || !u || !ufv || !fv_old || !fv_new) return fail(DGFV_ERR_ARG, "NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  if (!m->fvghost && capturing(s)) return fail(DGFV_ERR_ARG, "the first call with FV-stored elements allocates: not under capture");
+  try {
+    ensure_fv_stored(m, s);
+    const MeshView v = fvs_view(m);
+    for (int N = 1; N <= MAXN; ++N)
+      if (!m->bucket[N].empty())
+        hip_check(ops_for(N).fv_switch(v, m->d_bucket[N], (int)m->bucket[N].size(), u, ufv, fv_old, fv_new, s),
+                  "fv_switch launch");
+  } catch (const HipError& e) {
+    return fail(msg_oom(e) ? DGFV_ERR_OOM : DGFV_ERR_HIP, e.what());
   }
   return DGFV_OK;
 }

@@ -83,6 +83,10 @@ struct MeshView {
   double* rfv;                  // FV residual in nodal form, [nvar][n_node]
   double* ubar_bar;             // adjoint of the sub-cell means, [K][nvar][NFV^3]
   double* fvnorm;               // sub-face normals of internal planes, [K][3][3][(NFV-1) NFV^2]
+  // FV-stored elements (allocated by the first call that has them):
+  double* fvghost;              // per FV element side the state across it on the sub-face grid,
+                                // [K][6][nvar][NFV^2], written by the FV face kernel
+  double* fvjbar;               // sub-cell means of J, V3(J), [K][NFV^3]
   const int32_t* elem_face;     // [K][6] face of each element side
   const SideRec* side_rec;      // [K][6] the same sides as records (element kernels of degree >= FUSE_MIN_N)
   const int32_t* face_conf[MAXN + 1];   // faces with NL = NR = N
@@ -117,7 +121,9 @@ struct MeshView {
 //                    kernel, from u, which the launch must not write: stage 0,
 //                    or uout != u.  The face kernels then skip that degree's
 //                    conforming class.
-constexpr int ELEM_WRITE_TRACE = 1, ELEM_FUSE_FACES = 2;
+//  ELEM_SKIP_FV      elements with alpha >= 1 are FV-stored: the kernel leaves
+//                    them alone (no reads of their side blocks, no writes).
+constexpr int ELEM_WRITE_TRACE = 1, ELEM_FUSE_FACES = 2, ELEM_SKIP_FV = 4;
 constexpr int FUSE_MIN_N = 6;    // one element per workgroup from here on
 struct DegreeOps {
   // element kernel in tile shape `variant` (0 .. element_variants - 1)
@@ -144,6 +150,12 @@ struct DegreeOps {
   // positivity limiter (one species); sub-cell points of blended elements from m.ubar
   hipError_t (*limiter)(const MeshView& m, const int32_t* elist, int count, double* u, const double* alpha,
                         double* theta, hipStream_t s);
+  // FV-stored elements: m.fvjbar = V3(J) of this bucket (setup), and the switch
+  // of the elements whose flag changes: DG -> FV ufv = V3(J u) / V3(J),
+  // FV -> DG u = V3^+(ufv V3(J)) / J
+  hipError_t (*fv_jbar)(const MeshView& m, const int32_t* elist, int count, hipStream_t s);
+  hipError_t (*fv_switch)(const MeshView& m, const int32_t* elist, int count, double* u, double* ufv,
+                          const double* fv_old, const double* fv_new, hipStream_t s);
   int element_variants;   // tile shapes of the element kernel at this degree
 };
 DegreeOps degree_ops_1();
@@ -182,6 +194,17 @@ hipError_t launch_face_class(const MeshView& m, const ParamsDev& p, const double
 
 hipError_t launch_faces_vjp(const MeshView& m, const ParamsDev& p, const double* u, const double* alpha,
                             hipStream_t s);
+
+// FV-stored elements (flag fv[e] > 0; the blended-element list of the call holds
+// them).  Faces with an FV side: minmod-reconstructed sub-face states, one
+// Riemann flux per sub-face into m.fvside (FV sides) and, through
+// V^{FV->DG} / h^2, m.fside (DG sides); the ghost layers into m.fvghost.
+hipError_t launch_face_fv_stored(const MeshView& m, const ParamsDev& p, const double* u, const double* ufv,
+                                 const double* fv, hipStream_t s);
+// Rates of the FV elements' means: stage 0 writes utfv = R; stage s updates
+// kfv <- A kfv + dt R, ufv <- ufv + B kfv.
+hipError_t launch_fv_stored(const MeshView& m, const ParamsDev& p, double* ufv, double* kfv, double* utfv,
+                            int stage, double dt, double A, double B, hipStream_t s);
 
 // Fixed device buffer (a file-scope device array in dgfv_state.hip) of the
 // entry point that allocates nothing: its address on the current device,

@@ -51,6 +51,36 @@ __device__ __forceinline__ PrimT<S> cons2prim(const S* u, const GasDev& g) {
   return q;
 }
 
+// Primitive vector w = (rho, v1, v2, v3, p[, Y1]) of a conservative state, and back.
+template <int NV>
+__device__ __forceinline__ void cons_to_w(const double* u, const GasDev& g, double* w) {
+  const PrimT<double> q = cons2prim<NV>(u, g);
+  w[0] = q.rho;
+  w[1] = q.v1;
+  w[2] = q.v2;
+  w[3] = q.v3;
+  w[4] = q.p;
+  if constexpr (NV == 6) w[5] = q.Y;
+}
+
+template <int NV>
+__device__ __forceinline__ void w_to_cons(const double* w, const GasDev& g, double* u) {
+  double kap = g.gamma;
+  if constexpr (NV == 6) kap = kappa_mix(w[5], g);
+  u[0] = w[0];
+  u[1] = w[0] * w[1];
+  u[2] = w[0] * w[2];
+  u[3] = w[0] * w[3];
+  u[4] = w[4] / (kap - 1.0) + 0.5 * w[0] * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]);
+  if constexpr (NV == 6) u[5] = w[0] * w[5];
+}
+
+// minmod(a, b): the argument of smaller magnitude where both have one sign, else 0.
+__device__ __forceinline__ double minmod(double a, double b) {
+  if (!(a * b > 0.0)) return 0.0;
+  return a > 0.0 ? (a < b ? a : b) : (a > b ? a : b);
+}
+
 // Physical flux F(u) . a
 template <int NV, class S>
 __device__ __forceinline__ void euler_flux(const PrimT<S>& q, double a1, double a2, double a3, S* f) {

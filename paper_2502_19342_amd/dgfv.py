@@ -44,7 +44,7 @@ EXPORTED = ("dgfv_mesh_create", "dgfv_mesh_destroy", "dgfv_mesh_info", "dgfv_mes
             "dg_indicator", "dg_rhs", "dg_rk_stage", "dg_rk_step", "dg_rhs_vjp", "dg_rk_stage_vjp",
             "dg_rk_stage_vjp_noalloc", "dgfv_prim_to_cons", "dg_positivity_limiter",
             "dgfv_set_positivity_limiter", "dgfv_set_launch_mode", "dgfv_set_face_fusion", "dgfv_autotune",
-            "dgfv_set_element_shape", "dgfv_check_state",
+            "dgfv_set_element_shape", "dgfv_check_state", "dg_rhs_fv", "dg_rk_stage_fv", "dg_switch_fv",
             "dgfv_profile_enable", "dgfv_profile_read", "dgfv_last_error")
 KERNEL_ELEMENT, KERNEL_FACE, KERNEL_FV_MEANS, KERNEL_FV_RESIDUAL, KERNEL_INDICATOR, KERNEL_VJP, KERNEL_FV_FACE = range(7)
 LAUNCH_SERIAL, LAUNCH_BRANCHES, LAUNCH_GRAPH = range(3)
@@ -72,6 +72,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dgfv_set_positivity_limiter.argtypes = [P, c_int]
     lib.dgfv_set_launch_mode.argtypes = [P, c_int]
     lib.dgfv_set_face_fusion.argtypes = [P, c_int]
+    lib.dg_rhs_fv.argtypes = [P, ctypes.POINTER(_Params), P, P, P, P, P, P]
+    lib.dg_rk_stage_fv.argtypes = [P, ctypes.POINTER(_Params), c_int, c_double, P, P, P, P, P, P]
+    lib.dg_switch_fv.argtypes = [P, P, P, P, P, P]
     lib.dgfv_set_element_shape.argtypes = [P, c_int, c_int]
     lib.dgfv_autotune.argtypes = [P, ctypes.POINTER(_Params), P, P, ctypes.POINTER(ctypes.c_double), P]
     lib.dgfv_profile_enable.argtypes = [P, c_int]
@@ -212,6 +215,14 @@ class Mesh:
             raise ValueError(f"{name} must be contiguous with shape {shape}")
         return t.data_ptr()
 
+    def _fv_state(self, t: torch.Tensor, name: str) -> int:
+        shape = (self.n_elem, self.n_var, self.n_fv ** 3)
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
+            raise TypeError(f"{name} must be a float64 CUDA/HIP tensor")
+        if tuple(t.shape) != shape or not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous with shape {shape}")
+        return t.data_ptr()
+
     def _alpha(self, a) -> int | None:
         if a is None:
             return None
@@ -247,6 +258,36 @@ def rk_step(mesh: Mesh, params: Params, dt: float, u: torch.Tensor, k: torch.Ten
     """In-place five-stage 2N Runge-Kutta step (``dg_rk_step``)."""
     _check(_lib.dg_rk_step(mesh._h, ctypes.byref(params.c()), float(dt), mesh._state(u, "u"),
                            mesh._state(k, "k"), mesh._alpha(alpha), _stream(stream)))
+
+
+def rhs_fv(mesh: Mesh, params: Params, u: torch.Tensor, ufv: torch.Tensor, fv: torch.Tensor, out=None,
+           out_fv=None, stream=None):
+    """Rates with FV-stored elements (``dg_rhs_fv``): ``(R on DG elements, R of the FV elements' means)``."""
+    out = torch.empty_like(u) if out is None else out
+    out_fv = torch.empty_like(ufv) if out_fv is None else out_fv
+    _check(_lib.dg_rhs_fv(mesh._h, ctypes.byref(params.c()), mesh._state(u, "u"), mesh._fv_state(ufv, "ufv"),
+                          mesh._alpha(fv), mesh._state(out, "out"), mesh._fv_state(out_fv, "out_fv"),
+                          _stream(stream)))
+    return out, out_fv
+
+
+def rk_stage_fv(mesh: Mesh, params: Params, stage: int, dt: float, u, k, ufv, kfv, fv, stream=None) -> None:
+    """In-place RK stage of (u, k) and (ufv, kfv) with FV-stored elements (``dg_rk_stage_fv``)."""
+    _check(_lib.dg_rk_stage_fv(mesh._h, ctypes.byref(params.c()), int(stage), float(dt), mesh._state(u, "u"),
+                               mesh._state(k, "k"), mesh._fv_state(ufv, "ufv"), mesh._fv_state(kfv, "kfv"),
+                               mesh._alpha(fv), _stream(stream)))
+
+
+def rk_step_fv(mesh: Mesh, params: Params, dt: float, u, k, ufv, kfv, fv, stream=None) -> None:
+    """The five stages of ``dg_rk_stage_fv`` in turn."""
+    for s in range(1, 6):
+        rk_stage_fv(mesh, params, s, dt, u, k, ufv, kfv, fv, stream)
+
+
+def switch_fv(mesh: Mesh, u, ufv, fv_old, fv_new, stream=None) -> None:
+    """Convert the elements whose FV flag changes (``dg_switch_fv``), in place."""
+    _check(_lib.dg_switch_fv(mesh._h, mesh._state(u, "u"), mesh._fv_state(ufv, "ufv"), mesh._alpha(fv_old),
+                             mesh._alpha(fv_new), _stream(stream)))
 
 
 def positivity_limiter(mesh: Mesh, params: Params, u: torch.Tensor, alpha: torch.Tensor | None = None,

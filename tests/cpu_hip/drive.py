@@ -76,6 +76,27 @@ def main(src, dst):
             check(lib.dg_rk_step(h, ctypes.byref(prm), ctypes.c_double(float(z["dt"])), ptr(uu), ptr(k),
                                  ptr(alpha), None), "dg_rk_step")
             out["rk_step_unfused"] = uu
+        elif call == "rhs_fv":
+            ufv = np.ascontiguousarray(z["ufv"], dtype=np.float64)
+            fvf = np.ascontiguousarray(z["fv"], dtype=np.float64)
+            r, rf = np.empty_like(u), np.empty_like(ufv)
+            check(lib.dg_rhs_fv(h, ctypes.byref(prm), ptr(u), ptr(ufv), ptr(fvf), ptr(r), ptr(rf), None), "dg_rhs_fv")
+            out["rhs_fv_dg"], out["rhs_fv_fv"] = r, rf
+        elif call == "rk_step_fv":
+            uu = u.copy()
+            uf = np.ascontiguousarray(z["ufv"], dtype=np.float64).copy()
+            fvf = np.ascontiguousarray(z["fv"], dtype=np.float64)
+            k, kf = np.empty_like(uu), np.empty_like(uf)
+            for st in range(1, 6):
+                check(lib.dg_rk_stage_fv(h, ctypes.byref(prm), ctypes.c_int(st), ctypes.c_double(float(z["dt"])),
+                                         ptr(uu), ptr(k), ptr(uf), ptr(kf), ptr(fvf), None), "dg_rk_stage_fv")
+            out["step_fv_dg"], out["step_fv_fv"] = uu, uf
+        elif call == "switch_fv":
+            uu = u.copy()
+            uf = np.ascontiguousarray(z["ufv"], dtype=np.float64).copy()
+            check(lib.dg_switch_fv(h, ptr(uu), ptr(uf), ptr(np.ascontiguousarray(z["fv"], dtype=np.float64)),
+                                   ptr(np.ascontiguousarray(z["fv_new"], dtype=np.float64)), None), "dg_switch_fv")
+            out["switch_dg"], out["switch_fv"] = uu, uf
         elif call == "rhs":
             r = np.empty_like(u)
             check(lib.dg_rhs(h, ctypes.byref(prm), ptr(u), ptr(alpha), ptr(r), None), "dg_rhs")

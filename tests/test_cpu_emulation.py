@@ -170,3 +170,58 @@ def test_cpu_build_positivity_limiter():
     changed = [e for e in range(c.mesh.K) if not torch.equal(u[:, c.mesh.offset[e]:c.mesh.offset[e + 1]],
                                                              ref[:, c.mesh.offset[e]:c.mesh.offset[e + 1]])]
     assert sorted(np.nonzero(out["theta"] < 1.0)[0].tolist()) == changed and len(changed) == n_lim
+
+
+def _fv_stored_case(n_var, seed=7):
+    from oracle import native_fv
+    flux = {} if n_var == 5 else dict(volume_flux=W.VOL_PIROZZOLI, face_dg=W.RIEMANN_LLF)
+    wl = curved_mixed(n=3, nmin=2, nmax=4, n_var=n_var, scramble=19, metric_degree=0, n_fv=5, **flux)
+    c = _case(wl, smooth_state(83, n_var), noise=1e-3, seed=seed)
+    rng = np.random.default_rng(seed)
+    flag = rng.random(c.mesh.K) < 0.4
+    nf = wl.n_fv
+    ufv = torch.zeros(c.mesh.K, n_var, nf, nf, nf, dtype=T)
+    fvel = np.nonzero(flag)[0]
+    ufv[torch.as_tensor(fvel)] = native_fv.dg_to_fv(c.mesh, c.u, fvel)
+    ufv = ufv * (1.0 + 2e-2 * torch.as_tensor(rng.standard_normal(tuple(ufv.shape))))
+    return wl, c, flag, ufv
+
+
+@pytest.mark.parametrize("n_var", [5, 6])
+def test_cpu_build_fv_stored_elements(n_var):
+    # FV-stored elements (N_FV = 5 = 2N + 1 at N = 2) beside DG elements of degrees 2..4:
+    # rates, five RK stages and the switch against the oracle
+    from oracle import lsrk, native_fv, problem
+    wl, c, flag, ufv = _fv_stored_case(n_var)
+    K, nf = c.mesh.K, wl.n_fv
+    native = native_fv.NativeRhs(c.mesh, c.gas, problem.params_of(wl))
+    R, Rfv = native(c.u, ufv, flag)
+    fv = flag.astype(np.float64)
+    fv_new = (np.random.default_rng(5).random(K) < 0.5).astype(np.float64)
+    dt = 0.2 * lsrk.timestep(c.mesh, c.gas, c.u, 0.5, torch.as_tensor(fv))
+    out = cpu_emu.run(wl, c.u.numpy(), ["rhs_fv", "rk_step_fv", "switch_fv"], dt=dt,
+                      ufv=ufv.reshape(K, n_var, -1).numpy(), fv=fv, fv_new=fv_new)
+    dg = np.repeat(~flag, [int(c.mesh.offset[e + 1] - c.mesh.offset[e]) for e in range(K)])
+    got_dg = torch.as_tensor(out["rhs_fv_dg"])[:, torch.as_tensor(dg)]
+    assert rel_err(got_dg, R[:, torch.as_tensor(dg)]) <= 1e-11
+    sel = torch.as_tensor(flag)
+    got_fv = torch.as_tensor(out["rhs_fv_fv"]).reshape(K, n_var, -1)[sel].transpose(0, 1).reshape(n_var, -1)
+    assert rel_err(got_fv, Rfv[sel].transpose(0, 1).reshape(n_var, -1)) <= 1e-11
+    # five stages
+    u, uf = c.u.clone(), ufv.clone()
+    k, kf = torch.zeros_like(u), torch.zeros_like(uf)
+    for s in range(5):
+        u, uf, k, kf = native_fv.stage(lambda a, b: native(a, b, flag), u, uf, k, kf, s, dt,
+                                       lsrk.A_F64, lsrk.B_F64)
+    got = torch.as_tensor(out["step_fv_dg"])[:, torch.as_tensor(dg)]
+    assert rel_err(got, u[:, torch.as_tensor(dg)]) <= 1e-11
+    got = torch.as_tensor(out["step_fv_fv"]).reshape(K, n_var, -1)[sel].transpose(0, 1).reshape(n_var, -1)
+    assert rel_err(got, uf[sel].transpose(0, 1).reshape(n_var, -1)) <= 1e-11
+    # switch
+    su, sf = native_fv.switch(c.mesh, c.u, ufv, flag, fv_new > 0)
+    new = fv_new > 0
+    dgn = np.repeat(~new, [int(c.mesh.offset[e + 1] - c.mesh.offset[e]) for e in range(K)])
+    assert rel_err(torch.as_tensor(out["switch_dg"])[:, torch.as_tensor(dgn)], su[:, torch.as_tensor(dgn)]) <= 1e-12
+    seln = torch.as_tensor(new)
+    got = torch.as_tensor(out["switch_fv"]).reshape(K, n_var, -1)[seln].transpose(0, 1).reshape(n_var, -1)
+    assert rel_err(got, sf[seln].transpose(0, 1).reshape(n_var, -1)) <= 1e-12

@@ -1,0 +1,133 @@
+"""FV-stored elements on the GPU against the oracle (Sections 3.1.2 and 3.2).
+
+Rates of the DG elements and of the FV elements' minmod-reconstructed
+sub-cell means, RK steps of the pair, and the switch between the two
+representations, on curved scrambled meshes of mixed degree with N_FV = 2N+1
+at the lowest degree, one and two species; the degenerate cases (no FV
+element: dg_rhs; every element FV) as well.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import lsrk, native_fv, problem
+from paper_2502_19342_amd import workloads as W
+
+from gpu_common import announce, rel_err
+from oracle_cases import curved_mixed, smooth_state
+
+pytestmark = pytest.mark.gpu
+T = torch.float64
+
+
+def _case(n_var=5, n=4, nmin=2, nmax=4, n_fv=5, frac=0.4, seed=7, scramble=19):
+    from paper_2502_19342_amd import dgfv
+    flux = {} if n_var == 5 else dict(volume_flux=W.VOL_PIROZZOLI, face_dg=W.RIEMANN_LLF)
+    wl = curved_mixed(n=n, nmin=nmin, nmax=nmax, n_var=n_var, scramble=scramble, metric_degree=0, n_fv=n_fv,
+                      **flux)
+    mesh, gas, _ = problem.build(wl)
+    u = problem.initial_state(mesh, gas, smooth_state(83, n_var))
+    rng = np.random.default_rng(seed)
+    u = u * (1.0 + 1e-3 * torch.as_tensor(rng.standard_normal(tuple(u.shape))))
+    flag = rng.random(mesh.K) < frac
+    ufv = torch.zeros(mesh.K, n_var, n_fv, n_fv, n_fv, dtype=T)
+    fvel = np.nonzero(flag)[0]
+    if len(fvel):
+        ufv[torch.as_tensor(fvel)] = native_fv.dg_to_fv(mesh, u, fvel)
+    ufv = ufv * (1.0 + 2e-2 * torch.as_tensor(rng.standard_normal(tuple(ufv.shape))))
+    gm = dgfv.Mesh.from_workload(wl)
+    return wl, mesh, gas, u, ufv, flag, gm, dgfv.params_of(wl)
+
+
+def _dg_cols(mesh, flag):
+    return torch.as_tensor(np.repeat(~flag, np.diff(mesh.offset)))
+
+
+def _fv_rows(x, flag, n_var):
+    K = x.shape[0]
+    return x.reshape(K, n_var, -1)[torch.as_tensor(flag)].transpose(0, 1).reshape(n_var, -1)
+
+
+def _gpu(t):
+    return t.to("cuda").contiguous()
+
+
+@pytest.mark.parametrize("n_var", [5, 6])
+def test_fv_stored_rates(n_var):
+    announce(f"FV-stored rates n_var={n_var}")
+    from paper_2502_19342_amd import dgfv
+    wl, mesh, gas, u, ufv, flag, gm, prm = _case(n_var)
+    K, nf = mesh.K, wl.n_fv
+    R, Rfv = native_fv.NativeRhs(mesh, gas, problem.params_of(wl))(u, ufv, flag)
+    fv = _gpu(torch.as_tensor(flag, dtype=T))
+    r, rf = dgfv.rhs_fv(gm, prm, _gpu(u), _gpu(ufv.reshape(K, n_var, -1)), fv)
+    torch.cuda.synchronize()
+    dg = _dg_cols(mesh, flag)
+    e1 = rel_err(r.cpu()[:, dg], R[:, dg])
+    e2 = rel_err(_fv_rows(rf.cpu(), flag, n_var), _fv_rows(Rfv, flag, n_var))
+    print(f"[fv-stored] rates: DG {e1:.3e}, FV {e2:.3e}", flush=True)
+    assert e1 <= 1e-11 and e2 <= 1e-11
+
+
+def test_fv_stored_rk_steps():
+    announce("FV-stored 10 RK steps")
+    from paper_2502_19342_amd import dgfv
+    wl, mesh, gas, u, ufv, flag, gm, prm = _case()
+    K, n_var = mesh.K, 5
+    native = native_fv.NativeRhs(mesh, gas, problem.params_of(wl))
+    dt = 0.2 * lsrk.timestep(mesh, gas, u, 0.5, torch.as_tensor(flag, dtype=T))
+    fv = _gpu(torch.as_tensor(flag, dtype=T))
+    ug, ufg = _gpu(u), _gpu(ufv.reshape(K, n_var, -1))
+    k = torch.full_like(ug, float("nan"))           # stage 1 must not read the registers
+    kf = torch.full_like(ufg, float("nan"))
+    uo, ufo = u.clone(), ufv.clone()
+    for _ in range(10):
+        dgfv.rk_step_fv(gm, prm, dt, ug, k, ufg, kf, fv)
+        ko, kfo = torch.zeros_like(uo), torch.zeros_like(ufo)
+        for s in range(5):
+            uo, ufo, ko, kfo = native_fv.stage(lambda a, b: native(a, b, flag), uo, ufo, ko, kfo, s, dt,
+                                               lsrk.A_F64, lsrk.B_F64)
+    torch.cuda.synchronize()
+    dg = _dg_cols(mesh, flag)
+    e1 = rel_err(ug.cpu()[:, dg], uo[:, dg])
+    e2 = rel_err(_fv_rows(ufg.cpu(), flag, n_var), _fv_rows(ufo, flag, n_var))
+    print(f"[fv-stored] 10 steps: DG {e1:.3e}, FV {e2:.3e}", flush=True)
+    assert e1 <= 1e-10 and e2 <= 1e-10
+
+
+def test_fv_stored_switch():
+    announce("FV-stored switch")
+    from paper_2502_19342_amd import dgfv
+    wl, mesh, gas, u, ufv, flag, gm, prm = _case(n=3, nmin=3, nmax=3, n_fv=7)     # N_FV = 2N + 1
+    K, n_var = mesh.K, 5
+    new = np.random.default_rng(11).random(K) < 0.5
+    su, sf = native_fv.switch(mesh, u, ufv, flag, new)
+    ug, ufg = _gpu(u), _gpu(ufv.reshape(K, n_var, -1))
+    f_old, f_new = _gpu(torch.as_tensor(flag, dtype=T)), _gpu(torch.as_tensor(new, dtype=T))
+    dgfv.switch_fv(gm, ug, ufg, f_old, f_new)
+    torch.cuda.synchronize()
+    dg = _dg_cols(mesh, new)
+    assert rel_err(ug.cpu()[:, dg], su[:, dg]) <= 1e-12
+    assert rel_err(_fv_rows(ufg.cpu(), new, n_var), _fv_rows(sf, new, n_var)) <= 1e-12
+    # back again: the DG states return (V^+ V = I for N_FV >= N + 1)
+    dgfv.switch_fv(gm, ug, ufg, f_new, f_old)
+    torch.cuda.synchronize()
+    keep = torch.as_tensor(np.repeat(~flag & new, np.diff(mesh.offset)))
+    assert rel_err(ug.cpu()[:, keep], u[:, keep]) <= 1e-12
+
+
+def test_fv_stored_degenerate_cases():
+    announce("FV-stored: none and all")
+    from paper_2502_19342_amd import dgfv
+    wl, mesh, gas, u, ufv, flag, gm, prm = _case(frac=0.0)
+    K, n_var = mesh.K, 5
+    fv0 = torch.zeros(K, dtype=T, device="cuda")
+    r, _ = dgfv.rhs_fv(gm, prm, _gpu(u), _gpu(ufv.reshape(K, n_var, -1)), fv0)
+    r_dg = dgfv.rhs(gm, prm, _gpu(u), None)
+    torch.cuda.synchronize()
+    assert torch.equal(r, r_dg)                      # no FV element: the DG path itself
+    wl, mesh, gas, u, ufv, flag, gm, prm = _case(frac=1.0, seed=9)
+    R, Rfv = native_fv.NativeRhs(mesh, gas, problem.params_of(wl))(u, ufv, flag)
+    _, rf = dgfv.rhs_fv(gm, prm, _gpu(u), _gpu(ufv.reshape(K, n_var, -1)), torch.ones(K, dtype=T, device="cuda"))
+    torch.cuda.synchronize()
+    assert rel_err(_fv_rows(rf.cpu(), flag, n_var), _fv_rows(Rfv, flag, n_var)) <= 1e-11
