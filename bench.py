@@ -48,6 +48,8 @@ def parse():
                     help="serial launches, concurrent degree-bucket branches, or replayed hipGraphs")
     ap.add_argument("--cpu-sample-n", type=int, default=8, help="elements per direction of the oracle sample")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward timing ratio")
+    ap.add_argument("--cpu-table", action="store_true",
+                    help="only time the CPU oracle on every configuration (1 thread and all threads) and exit")
     ap.add_argument("--face-fusion", default="off", choices=["on", "off"],
                     help="element kernels of degree 6, 7 evaluate their conforming DG faces (default off)")
     ap.add_argument("--copy-gib", type=float, default=0.0,
@@ -127,7 +129,7 @@ def stage_bytes(wl, degree: np.ndarray) -> float:
     return float(8 * ((N + 1) ** 3 * (4 * nv + 10) + 6 * (N + 1) ** 2 * nv).sum())
 
 
-def cpu_baseline(cfg: str, n: int, seed: int):
+def cpu_baseline(cfg: str, n: int, seed: int, budget_s: float = 12.0, max_stages: int = 50):
     """Time the CPU oracle (as it stands) on a small mesh of the same configuration."""
     import torch
 
@@ -158,12 +160,41 @@ def cpu_baseline(cfg: str, n: int, seed: int):
             u = limiter.limit(mesh, gas, u, alpha)[0]
         reps += 1
         el = time.perf_counter() - t0
-        if el > 12.0 or reps >= 50:
+        if el > budget_s or reps >= max_stages:
             break
     return {"value": mesh.n_node * reps / el, "unit": "DOF-updates/s", "cores": torch.get_num_threads(),
             "kind": "oracle",
             "sample": f"{reps} RK stages of the same configuration on {n}^3 elements ({mesh.n_node} DOFs), "
                       f"with the indicator once per 5 stages, {el:.1f} s"}
+
+
+def cpu_table(n: int, reps: int = 5):
+    """The oracle's rate on every configuration at one thread and at all threads (median of `reps`)."""
+    import statistics
+
+    import torch
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    all_threads = torch.get_num_threads()
+    rows = []
+    for cfg in ("C1", "C2", "C3", "C4", "C5"):
+        for th in (1, all_threads):
+            torch.set_num_threads(th)
+            vals = [cpu_baseline(cfg, n, 0, budget_s=2.0, max_stages=25) for _ in range(reps)]
+            rate = statistics.median(v["value"] for v in vals)
+            rows.append({"config": cfg, "threads": th, "median_dof_updates_per_s": rate,
+                         "runs": [round(v["value"], 1) for v in vals], "sample": vals[0]["sample"]})
+            print(f"[cpu-table] {cfg} threads={th}: {rate:.4g} DOF-updates/s", file=sys.stderr, flush=True)
+    torch.set_num_threads(all_threads)
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "torch_threads_all": all_threads,
+            "n": n, "reps": reps, "rows": rows}
 
 
 def counter_traffic(cfg: str):
@@ -246,6 +277,9 @@ def main():
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: the benchmark measures one GPU; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
+    if args.cpu_table:
+        print(json.dumps(cpu_table(args.cpu_sample_n if args.cpu_sample_n != 8 else 4)), flush=True)
+        return
     import torch
 
     from paper_2502_19342_amd import dgfv
