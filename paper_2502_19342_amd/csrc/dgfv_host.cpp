@@ -413,19 +413,6 @@ std::vector<double> transpose(const std::vector<double>& a, int r, int c) {
   return t;
 }
 
-// Position b of the list gets element (b mod 8)-th chunk, entry b div 8: with
-// C = 8q + r, chunk x holds q + (x < r) consecutive entries of `sorted`.
-std::vector<int32_t> xcd_order(const std::vector<int32_t>& sorted) {
-  constexpr int XCD = 8;
-  const size_t C = sorted.size(), q = C / XCD, r = C % XCD;
-  std::vector<int32_t> out(C);
-  for (size_t b = 0; b < C; ++b) {
-    const size_t x = b % XCD, j = b / XCD;
-    out[b] = sorted[x * q + std::min(x, r) + j];
-  }
-  return out;
-}
-
 int side_node_h(int s, int p, int q, int n) {
   const int last = (s & 1) ? n - 1 : 0;
   switch (s >> 1) {
@@ -1063,14 +1050,7 @@ dgfv_status dgfv_mesh_create(const dgfv_mesh_desc* d, dgfv_mesh** out) {
     }
 
     // ---- buckets -----------------------------------------------------------
-    // Workgroups go to the eight XCDs (each with its own L2) in turn by
-    // workgroup index.  A bucket is listed so that XCD x takes the x-th eighth of
-    // the bucket's elements in ascending order: elements adjacent in the mesh
-    // order (neighbours along xi_1 and, a row later, xi_2 on a structured mesh)
-    // then run on one XCD close together, and the faces they share are read
-    // through the same L2.
     for (int e = 0; e < m->K; ++e) m->bucket[m->degree[e]].push_back(e);
-    for (int N = 1; N <= MAXN; ++N) m->bucket[N] = xcd_order(m->bucket[N]);
 
     // ---- device ------------------------------------------------------------
     MeshView& v = m->view;
