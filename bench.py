@@ -48,6 +48,8 @@ def parse():
                     help="serial launches, concurrent degree-bucket branches, or replayed hipGraphs")
     ap.add_argument("--cpu-sample-n", type=int, default=8, help="elements per direction of the oracle sample")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward timing ratio")
+    ap.add_argument("--fv-stored", action="store_true",
+                    help="the blended elements carry sub-cell means (FV-stored elements) instead")
     ap.add_argument("--cpu-table", action="store_true",
                     help="only time the CPU oracle on every configuration (1 thread and all threads) and exit")
     ap.add_argument("--face-fusion", default="off", choices=["on", "off"],
@@ -81,7 +83,8 @@ def initial_state_device(gm, wl, dgfv, torch, chunk=1 << 23):
     return u
 
 
-def element_kernel_bytes(wl, degree: np.ndarray, alpha: np.ndarray, stage: int, fused: bool) -> float:
+def element_kernel_bytes(wl, degree: np.ndarray, alpha: np.ndarray, stage: int, fused: bool,
+                         keep: np.ndarray | None = None, traces: bool = True) -> float:
     """Algorithmic HBM bytes of one element-kernel launch (all buckets of one stage of an RK step).
 
     Per node: u read + write, k read (not at stage 1) + write; per blended node
@@ -93,13 +96,16 @@ def element_kernel_bytes(wl, degree: np.ndarray, alpha: np.ndarray, stage: int, 
     neighbour's trace and the face normals, (N+1)^2 (nvar + 3).  The stage
     before an in-place stage (all of 1..4 unfused, stage 4 fused) also writes
     the new state of sides 0 and 1 (2 (N+1)^2 nvar per element of degree >= 6).
+    ``keep`` selects the elements the kernels process (FV-stored elements are not),
+    ``traces`` whether the stages write the traces (not on the FV-stored path).
     """
     nv = wl.n_var
     deg = degree.astype(np.int64)
-    npe = (deg + 1) ** 3
+    keep = np.ones(len(deg), dtype=bool) if keep is None else keep
+    npe = np.where(keep, (deg + 1) ** 3, 0)
     n2 = (deg + 1) ** 2
     fv_only = (alpha >= 1.0) & (deg >= 6)
-    dg = ~fv_only
+    dg = ~fv_only & keep
     per_node = 8 * (2 * nv + (nv if stage > 1 else 0) + nv)
     total = per_node * npe.sum()
     total += 8 * 10 * npe[dg].sum()
@@ -112,9 +118,28 @@ def element_kernel_bytes(wl, degree: np.ndarray, alpha: np.ndarray, stage: int, 
     # every face is seen from both sides; a side of a pure FV element reads nothing
     for e_side in (eL, eR):
         total += 8 * (n2[e_side] * np.where(fused_face, nv + 3, nv))[dg[e_side]].sum()
-    if (stage < 5 and not fused) or (fused and stage == 4):
+    if traces and ((stage < 5 and not fused) or (fused and stage == 4)):
         total += 8 * 2 * n2[deg >= 6].sum() * nv
     return float(total)
+
+
+def fv_stored_roofline(wl, fv: np.ndarray, kt: dict) -> dict:
+    """HBM roofline of the FV-stored elements' kernel (means, reconstruction, fluxes, RK update).
+
+    Per FV element and stage: the means and the RK register read and written
+    (4 nvar N_FV^3; the register is not read at stage 1, averaged in), the
+    ghost layers and side fluxes of the six sides (12 nvar N_FV^2), the
+    internal sub-face normals (9 (N_FV - 1) N_FV^2) and V3(J) (N_FV^3).
+    """
+    nv, nf = wl.n_var, wl.n_fv
+    n_fv = int((fv > 0).sum())
+    per = 8 * ((3 * nv + 0.8 * nv) * nf ** 3 + 12 * nv * nf ** 2 + 9 * (nf - 1) * nf ** 2 + nf ** 3)
+    ms, n = kt["fv_residual"]
+    avg_ms = ms / max(1, n)
+    achieved = per * n_fv / (avg_ms / 1e3) / 1e9 if avg_ms > 0 else 0.0
+    return {"bound": "hbm", "kernel": "fv_stored_kernel", "elements": n_fv, "bytes_per_launch": per * n_fv,
+            "avg_launch_ms": avg_ms, "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBS}
 
 
 def stage_bytes(wl, degree: np.ndarray) -> float:
@@ -346,9 +371,21 @@ def main():
         step_prm, step_alpha = prm, alpha
     step_ind = torch.empty_like(alpha)
 
-    def step():
-        dgfv.indicator(gm, step_prm, u, alpha=step_alpha, ind=step_ind)
-        dgfv.rk_step(gm, prm, dt, u, k, alpha)
+    if args.fv_stored:
+        # the blended elements carry sub-cell means instead (Section 3.1.2): switched
+        # once from the DG state, then advanced by the FV-stored path every stage
+        fv = (alpha > 0).to(torch.float64).contiguous()
+        ufv = torch.zeros(wl.mesh.n_elem, wl.n_var, wl.n_fv ** 3, dtype=torch.float64, device="cuda")
+        kfv = torch.zeros_like(ufv)
+        dgfv.switch_fv(gm, u, ufv, torch.zeros_like(fv), fv)
+
+        def step():
+            dgfv.indicator(gm, step_prm, u, alpha=step_alpha, ind=step_ind)
+            dgfv.rk_step_fv(gm, prm, dt, u, k, ufv, kfv, fv)
+    else:
+        def step():
+            dgfv.indicator(gm, step_prm, u, alpha=step_alpha, ind=step_ind)
+            dgfv.rk_step(gm, prm, dt, u, k, alpha)
 
     for _ in range(args.warmup):
         step()
@@ -372,10 +409,15 @@ def main():
           (("element", dgfv.KERNEL_ELEMENT), ("face", dgfv.KERNEL_FACE), ("fv_means", dgfv.KERNEL_FV_MEANS),
            ("fv_face", dgfv.KERNEL_FV_FACE), ("fv_residual", dgfv.KERNEL_FV_RESIDUAL))}
     gm.profile(False)
-    if not torch.isfinite(u).all():
+    if args.fv_stored:
+        dg_mask = torch.repeat_interleave(fv == 0, torch.as_tensor(np.diff(gm.elem_offset), device="cuda"))
+        finite = bool(torch.isfinite(u[:, dg_mask]).all()) and bool(torch.isfinite(ufv[fv > 0]).all())
+    else:
+        finite = bool(torch.isfinite(u).all())
+    if not finite:
         print("bench.py: non-finite state after the timed steps", file=sys.stderr)
         sys.exit(1)
-    adjoint = None if args.no_adjoint else adjoint_ratio(gm, prm, u, dgfv, torch)
+    adjoint = None if (args.no_adjoint or args.fv_stored) else adjoint_ratio(gm, prm, u, dgfv, torch)
 
     stages = 5 * args.steps
     value = n_dof * stages / el
@@ -383,7 +425,14 @@ def main():
     avg_el_s = el_ms / el_n / 1e3
     alpha_h = alpha.cpu().numpy()
     fused = args.face_fusion == "on" and bool((np.asarray(wl.mesh.degree) >= 6).any())
-    byts = np.mean([element_kernel_bytes(wl, np.asarray(wl.mesh.degree), alpha_h, s, fused) for s in range(1, 6)])
+    if args.fv_stored:
+        # the element kernels see only the DG elements (alpha 0 there)
+        keep = alpha_h <= 0
+        byts = np.mean([element_kernel_bytes(wl, np.asarray(wl.mesh.degree), np.zeros_like(alpha_h), s, False,
+                                             keep, traces=False) for s in range(1, 6)])
+    else:
+        byts = np.mean([element_kernel_bytes(wl, np.asarray(wl.mesh.degree), alpha_h, s, fused)
+                        for s in range(1, 6)])
     achieved = byts / avg_el_s / 1e9
     stage_b = stage_bytes(wl, np.asarray(wl.mesh.degree))
     rec = {
@@ -408,6 +457,7 @@ def main():
             "volume_flux": ["ranocha", "pirozzoli", "central"][wl.volume_flux],
             "launch": args.launch,
             "face_fusion": args.face_fusion,
+            "fv_stored": bool(args.fv_stored),
             "autotune_ms": {str(N): [round(a, 4), round(b, 4)] for N, (a, b) in tune.items()},
             "blended_fraction": float(mask.mean()),
             "blended_fraction_last_step": float((alpha_h > 0).mean()),
@@ -427,6 +477,7 @@ def main():
         "kernel_ms_source": "live events over the timed steps" if live else "profiled steps after the timed region",
         "kernel_ms_note": "phases in order: fv_means, face, fv_residual, element; fv_face lies inside face "
                           "(beside the DG face fluxes outside --launch serial)",
+        "fv_stored": fv_stored_roofline(wl, alpha_h, kt) if args.fv_stored else None,
         "indicator_ms": indicator_ms,
         "indicator_note": "one dg_indicator call over all elements (variables p and rho), timed alone; "
                           "every timed step includes one call",

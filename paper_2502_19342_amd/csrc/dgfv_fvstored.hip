@@ -18,16 +18,20 @@ namespace {
 constexpr int FVS_THREADS = 512;
 
 // One workgroup per entry of the call's FV-element list (a grid of K, the
-// workgroups past the list leaving at once), one thread per sub-cell.
+// workgroups past the list leaving at once), one thread per sub-cell.  The
+// thread of sub-cell c evaluates the internal face c + 1/2 along each
+// direction: its left state from c's slope, its right state from the slope of
+// c + 1, which the thread forms itself from the primitives in LDS (the same
+// arithmetic as c + 1's own), so that the states need no LDS round trip.
+// 4 waves per SIMD: two workgroups per CU at N_FV = 8.
 template <int NFV, int NV>
-__global__ void __launch_bounds__(FVS_THREADS)
+__global__ void __launch_bounds__(FVS_THREADS, 4)
 fv_stored_kernel(MeshView m, ParamsDev prm, double* __restrict__ ufv, double* __restrict__ kfv,
                  double* __restrict__ utfv, int stage, double dt, double A, double B) {
   constexpr int S2 = NFV * NFV, S3 = S2 * NFV, NIF = (NFV - 1) * S2, NSD = 6 * NV * S2;
   static_assert(S3 <= FVS_THREADS, "one thread per sub-cell");
   __shared__ double sW[NV * S3];      // primitives of the means
-  __shared__ double sP[NV * S3];      // value at the + face of each sub-cell, then the fluxes
-  __shared__ double sM[NV * S3];      // value at the - face
+  __shared__ double sL[NV * S3];      // flux through each sub-cell's + face
   __shared__ double sG[NSD];          // primitives across the six sides
   __shared__ double sF[NSD];          // the six sides' outward fluxes
   if ((int)blockIdx.x >= m.blend_start[MAXN + 1]) return;
@@ -68,11 +72,13 @@ fv_stored_kernel(MeshView m, ParamsDev prm, double* __restrict__ ufv, double* __
 #pragma unroll
     for (int v = 0; v < NV; ++v) sG[(side * NV + v) * S2 + i] = w[v];
   }
-  double wc[NV];
-  cons_to_w<NV>(um, m.gas, wc);
-  if (active) {
+  {
+    double wc[NV];
+    cons_to_w<NV>(um, m.gas, wc);
+    if (active) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) sW[v * S3 + c] = wc[v];
+      for (int v = 0; v < NV; ++v) sW[v * S3 + c] = wc[v];
+    }
   }
   __syncthreads();
   double dC[NV];
@@ -84,45 +90,38 @@ fv_stored_kernel(MeshView m, ParamsDev prm, double* __restrict__ ufv, double* __
     const int stride = d == 0 ? 1 : (d == 1 ? NFV : S2);
     const int ta = d == 2 ? s1 : s2, tb = d == 0 ? s1 : s0;
     const int fidx = ta * NFV + tb;                       // face-grid index on the two sides
-    if (active) {
+    const int glo = ((2 * d) * NV) * S2 + fidx, ghi = ((2 * d + 1) * NV) * S2 + fidx;
+    if (active && sd < NFV - 1) {                         // the internal face at this sub-cell's + side
+      double ul[NV], ur[NV];
+      {
+        double wl[NV], wr[NV];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const double lo = sd > 0 ? sW[v * S3 + c - stride] : sG[((2 * d) * NV + v) * S2 + fidx];
-        const double hi = sd < NFV - 1 ? sW[v * S3 + c + stride] : sG[((2 * d + 1) * NV + v) * S2 + fidx];
-        const double sig = minmod(wc[v] - lo, hi - wc[v]);
-        sP[v * S3 + c] = wc[v] + 0.5 * sig;
-        sM[v * S3 + c] = wc[v] - 0.5 * sig;
+        for (int v = 0; v < NV; ++v) {
+          const double w0 = sW[v * S3 + c];
+          const double wm = sd > 0 ? sW[v * S3 + c - stride] : sG[glo + v * S2];
+          const double w1 = sW[v * S3 + c + stride];
+          const double w2 = sd + 2 < NFV ? sW[v * S3 + c + 2 * stride] : sG[ghi + v * S2];
+          wl[v] = w0 + 0.5 * minmod(w0 - wm, w1 - w0);
+          wr[v] = w1 - 0.5 * minmod(w1 - w0, w2 - w1);
+        }
+        w_to_cons<NV>(wl, m.gas, ul);
+        w_to_cons<NV>(wr, m.gas, ur);
       }
-    }
-    __syncthreads();
-    double Fl[NV];
-    const bool face = active && sd < NFV - 1;             // the internal face at this sub-cell's + side
-    if (face) {
-      double wl[NV], wr[NV], ul[NV], ur[NV];
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        wl[v] = sP[v * S3 + c];
-        wr[v] = sM[v * S3 + c + stride];
-      }
-      w_to_cons<NV>(wl, m.gas, ul);
-      w_to_cons<NV>(wr, m.gas, ur);
+      double Fl[NV];
       riemann<NV>(prm.face_flux_fv, prm.volume_flux, ul, ur, nd[d][0], nd[d][1], nd[d][2], m.gas, Fl);
-    }
-    __syncthreads();                                      // every thread is done with sP and sM
-    if (face) {
 #pragma unroll
-      for (int v = 0; v < NV; ++v) sP[v * S3 + c] = Fl[v];
+      for (int v = 0; v < NV; ++v) sL[v * S3 + c] = Fl[v];
     }
     __syncthreads();
     if (active) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        const double hi = sd < NFV - 1 ? sP[v * S3 + c] : sF[((2 * d + 1) * NV + v) * S2 + fidx];
-        const double lo = sd > 0 ? sP[v * S3 + c - stride] : -sF[((2 * d) * NV + v) * S2 + fidx];
+        const double hi = sd < NFV - 1 ? sL[v * S3 + c] : sF[((2 * d + 1) * NV + v) * S2 + fidx];
+        const double lo = sd > 0 ? sL[v * S3 + c - stride] : -sF[((2 * d) * NV + v) * S2 + fidx];
         dC[v] -= hi - lo;
       }
     }
-    __syncthreads();                                      // sP is rewritten by the next direction
+    __syncthreads();                                      // sL is rewritten by the next direction
   }
   if (!active) return;
   const double scale = 1.0 / (h * h * h * jb);
