@@ -502,7 +502,7 @@ face_fv_kernel(MeshView m, ParamsDev prm, const double* __restrict__ u, const do
 template <int NV>
 __device__ void face_body_fvs(const MeshView& m, const ParamsDev& prm, const double* __restrict__ u,
                               const double* __restrict__ ufv, const double* __restrict__ fv, int f, double* B0,
-                              double* B1, double* B2, double* B3, double* B4, double* B5, double* sN, double* sNF) {
+                              double* B1, double* B2, double* B3, double* sN, double* sNF) {
   static_assert(GRID == FACE_THREADS, "one point per lane");
   const int32_t* fc = m.faces + 5 * f;
   const int eL = fc[0], sideL = fc[1], eR = fc[2], sideR = fc[3], o = fc[4];
@@ -514,6 +514,9 @@ __device__ void face_body_fvs(const MeshView& m, const ParamsDev& prm, const dou
   const int nF = m.n_fv, n2F = nF * nF, S3 = n2F * nF;
   const double h = 2.0 / nF;
   const int t = threadIdx.x;
+  // the next sub-cell inwards of an FV side stays in this lane's registers: the
+  // lane of sub-face t reconstructs sub-face t only
+  double yl[NV], yr[NV];
   {
     // one point of each grid per lane, every load issued before the first store
     auto source = [&](int e, int side, bool is_fv, int n, bool right, const double*& s0, const double*& s1,
@@ -540,7 +543,7 @@ __device__ void face_body_fvs(const MeshView& m, const ParamsDev& prm, const dou
     source(eL, sideL, fL, nl, false, aL0, aL1, vL);
     source(eR, sideR, fR, nr, true, aR0, aR1, vR);
     const int tn = t < nn ? t : 0;
-    double xl[NV], xr[NV], yl[NV], yr[NV], xn[3];
+    double xl[NV], xr[NV], xn[3];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       xl[v] = aL0[v * vL];
@@ -554,10 +557,6 @@ __device__ void face_body_fvs(const MeshView& m, const ParamsDev& prm, const dou
       for (int v = 0; v < NV; ++v) B0[v * GRID + t] = xl[v];
     if (t < nr * nr)
       for (int v = 0; v < NV; ++v) B1[v * GRID + t] = xr[v];
-    if (fL && t < n2F)
-      for (int v = 0; v < NV; ++v) B4[v * GRID + t] = yl[v];
-    if (fR && t < n2F)
-      for (int v = 0; v < NV; ++v) B5[v * GRID + t] = yr[v];
     if (t < nn)
       for (int c = 0; c < 3; ++c) sN[c * GRID + t] = xn[c];
   }
@@ -577,7 +576,8 @@ __device__ void face_body_fvs(const MeshView& m, const ParamsDev& prm, const dou
   double* ghL = m.fvghost + (size_t)eL * 6 * NV * n2F;
   double* ghR = m.fvghost + (size_t)eR * 6 * NV * n2F;
   const double a = h * h;
-  for (int tt = t; tt < n2F; tt += blockDim.x) {
+  if (t < n2F) {
+    const int tt = t;
     double cL[NV], cR[NV], vL[NV], vR[NV], Fl[NV];
     for (int v = 0; v < NV; ++v) {
       cL[v] = LF[v * GRID + tt];
@@ -593,16 +593,8 @@ __device__ void face_body_fvs(const MeshView& m, const ParamsDev& prm, const dou
       for (int v = 0; v < NV; ++v) wf[v] = wb[v] + 0.5 * minmod(wb[v] - wi[v], wg[v] - wb[v]);
       w_to_cons<NV>(wf, m.gas, out);
     };
-    if (fL) {
-      double ci[NV];
-      for (int v = 0; v < NV; ++v) ci[v] = B4[v * GRID + tt];
-      reconstruct(cL, ci, cR, vL);
-    }
-    if (fR) {
-      double ci[NV];
-      for (int v = 0; v < NV; ++v) ci[v] = B5[v * GRID + tt];
-      reconstruct(cR, ci, cL, vR);
-    }
+    if (fL) reconstruct(cL, yl, cR, vL);
+    if (fR) reconstruct(cR, yr, cL, vR);
     riemann<NV>(prm.face_flux_fv, prm.volume_flux, vL, vR, a * sNF[tt], a * sNF[GRID + tt],
                 a * sNF[2 * GRID + tt], m.gas, Fl);
     for (int v = 0; v < NV; ++v) F[v * GRID + tt] = Fl[v];
@@ -644,8 +636,7 @@ template <int NV>
 __global__ void __launch_bounds__(FACE_THREADS)
 face_fvs_kernel(MeshView m, ParamsDev prm, const double* __restrict__ u, const double* __restrict__ ufv,
                 const double* __restrict__ fv) {
-  __shared__ double B0[NV * GRID], B1[NV * GRID], B2[NV * GRID], B3[NV * GRID], B4[NV * GRID], B5[NV * GRID];
-  __shared__ double sN[3 * GRID], sNF[3 * GRID];
+  __shared__ double B0[NV * GRID], B1[NV * GRID], B2[NV * GRID], B3[NV * GRID], sN[3 * GRID], sNF[3 * GRID];
   if ((int)blockIdx.x >= m.blend_start[MAXN + 1]) return;
   const int e = m.blend_list[blockIdx.x];
   for (int side = 0; side < 6; ++side) {
@@ -653,7 +644,7 @@ face_fvs_kernel(MeshView m, ParamsDev prm, const double* __restrict__ u, const d
     const int32_t* fc = m.faces + 5 * f;
     const bool left = fc[0] == e && fc[1] == side;
     if (!left && fv[fc[0]] > 0.0) continue;          // the FV-stored left element owns it
-    face_body_fvs<NV>(m, prm, u, ufv, fv, f, B0, B1, B2, B3, B4, B5, sN, sNF);
+    face_body_fvs<NV>(m, prm, u, ufv, fv, f, B0, B1, B2, B3, sN, sNF);
     wave_sync();
   }
 }
