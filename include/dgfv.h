@@ -237,6 +237,9 @@ dgfv_status dgfv_set_launch_mode(dgfv_mesh* mesh, int mode);
  * nodal slots of FV elements are neither read nor written.
  *   dg_rhs_fv:      ut_d = R(u) on DG elements, utfv_d = R(ufv) on FV elements;
  *   dg_rk_stage_fv: stage s of dg_rk_stage on (u, k) and on (ufv, kfv);
+ *   dg_rk_step_fv:  the five stages in turn (between them the DG faces read the
+ *                   xi_1 sides from traces the previous stage wrote, as in
+ *                   dg_rk_step);
  *   dg_switch_fv:   converts the elements whose flag goes from fv_old_d to
  *                   fv_new_d: DG -> FV ufv = V3(J u) / V3(J); FV -> DG
  *                   u = V3^+(ufv V3(J)) / J (the least-squares nodal state
@@ -251,6 +254,8 @@ dgfv_status dg_rhs_fv(const dgfv_mesh* mesh, const dgfv_params* params, const do
                       const double* fv_d, double* ut_d, double* utfv_d, void* stream);
 dgfv_status dg_rk_stage_fv(const dgfv_mesh* mesh, const dgfv_params* params, int stage, double dt, double* u_d,
                            double* k_d, double* ufv_d, double* kfv_d, const double* fv_d, void* stream);
+dgfv_status dg_rk_step_fv(const dgfv_mesh* mesh, const dgfv_params* params, double dt, double* u_d, double* k_d,
+                          double* ufv_d, double* kfv_d, const double* fv_d, void* stream);
 dgfv_status dg_switch_fv(const dgfv_mesh* mesh, double* u_d, double* ufv_d, const double* fv_old_d,
                          const double* fv_new_d, void* stream);
 

@@ -601,8 +601,10 @@ void ensure_fv_stored(const dgfv_mesh* m, hipStream_t s) {
 // (u, k) and (ufv, kfv).  Phases: the FV-element list; the DG faces (both
 // sides DG) and the faces with an FV side; the FV elements' rates; the DG
 // element kernels, which leave the FV elements alone.
+// trace_in / trace_out as in enqueue_rhs_impl (dg_rk_step_fv between its stages).
 void enqueue_rhs_fvs(const dgfv_mesh* m, const ParamsDev& p, double* u, double* ufv, const double* fv, double* ut,
-                     double* utfv, double* k, double* kfv, int stage, double dt, hipStream_t s) {
+                     double* utfv, double* k, double* kfv, int stage, double dt, hipStream_t s,
+                     bool trace_in = false, bool trace_out = false) {
   ensure_fv_stored(m, s);
   const MeshView v = fvs_view(m);
   const double A = stage > 0 ? RK_A[stage - 1] : 0.0;
@@ -620,7 +622,7 @@ void enqueue_rhs_fvs(const dgfv_mesh* m, const ParamsDev& p, double* u, double* 
       if (c == FACE_CLASS_FV)
         hip_check(launch_face_fv_stored(v, p, u, ufv, fv, ss), "FV-stored face launch");
       else
-        hip_check(launch_face_class(v, p, u, fv, c, false, ss), "face launch");
+        hip_check(launch_face_class(v, p, u, fv, c, trace_in, ss), "face launch");
     });
   }
   {
@@ -630,8 +632,9 @@ void enqueue_rhs_fvs(const dgfv_mesh* m, const ParamsDev& p, double* u, double* 
   {
     Timed t(m, DGFV_KERNEL_ELEMENT, s);
     fork_join(m, s, degs, [&](int N, hipStream_t ss) {
+      const int flags = ELEM_SKIP_FV | (trace_out ? ELEM_WRITE_TRACE : 0);
       hip_check(ops_for(N).element(v, p, m->d_bucket[N], (int)m->bucket[N].size(), u, u, fv, ut, k, stage, dt,
-                                   A, B, m->elem_variant[N], ELEM_SKIP_FV, ss),
+                                   A, B, m->elem_variant[N], flags, ss),
                 "element launch");
     });
   }
@@ -1366,6 +1369,28 @@ dgfv_status dg_rk_stage_fv(const dgfv_mesh* m, const dgfv_params* prm, int stage
   return guarded(m, s, [&] {
     try {
       enqueue_rhs_fvs(m, to_dev(prm), u, ufv, fv, nullptr, nullptr, k, kfv, stage, dt, s);
+    } catch (const HipError& e) {
+      return fail(msg_oom(e) ? DGFV_ERR_OOM : DGFV_ERR_HIP, e.what());
+    }
+    return DGFV_OK;
+  });
+}
+
+dgfv_status dg_rk_step_fv(const dgfv_mesh* m, const dgfv_params* prm, double dt, double* u, double* k, double* ufv,
+                          double* kfv, const double* fv, void* stream) {
+  if (!m || !u || !k || !ufv || !kfv || !fv) return fail(DGFV_ERR_ARG, "NULL argument");
+  if (!std::isfinite(dt)) return fail(DGFV_ERR_ARG, "dt must be finite");
+  if (u == k || ufv == kfv) return fail(DGFV_ERR_ARG, "states and registers must not overlap");
+  if (dgfv_status st = check_params(m, prm)) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if (!m->fvghost && capturing(s)) return fail(DGFV_ERR_ARG, "the first call with FV-stored elements allocates: not under capture");
+  return guarded(m, s, [&] {
+    try {
+      const ParamsDev p = to_dev(prm);
+      // between its own stages nothing else writes u: the DG faces read sides 0 and 1
+      // from the traces the previous stage wrote
+      for (int st = 1; st <= 5; ++st)
+        enqueue_rhs_fvs(m, p, u, ufv, fv, nullptr, nullptr, k, kfv, st, dt, s, st > 1, st < 5);
     } catch (const HipError& e) {
       return fail(msg_oom(e) ? DGFV_ERR_OOM : DGFV_ERR_HIP, e.what());
     }

@@ -44,7 +44,8 @@ EXPORTED = ("dgfv_mesh_create", "dgfv_mesh_destroy", "dgfv_mesh_info", "dgfv_mes
             "dg_indicator", "dg_rhs", "dg_rk_stage", "dg_rk_step", "dg_rhs_vjp", "dg_rk_stage_vjp",
             "dg_rk_stage_vjp_noalloc", "dgfv_prim_to_cons", "dg_positivity_limiter",
             "dgfv_set_positivity_limiter", "dgfv_set_launch_mode", "dgfv_set_face_fusion", "dgfv_autotune",
-            "dgfv_set_element_shape", "dgfv_check_state", "dg_rhs_fv", "dg_rk_stage_fv", "dg_switch_fv",
+            "dgfv_set_element_shape", "dgfv_check_state", "dg_rhs_fv", "dg_rk_stage_fv", "dg_rk_step_fv",
+            "dg_switch_fv",
             "dgfv_profile_enable", "dgfv_profile_read", "dgfv_last_error")
 KERNEL_ELEMENT, KERNEL_FACE, KERNEL_FV_MEANS, KERNEL_FV_RESIDUAL, KERNEL_INDICATOR, KERNEL_VJP, KERNEL_FV_FACE = range(7)
 LAUNCH_SERIAL, LAUNCH_BRANCHES, LAUNCH_GRAPH = range(3)
@@ -74,6 +75,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dgfv_set_face_fusion.argtypes = [P, c_int]
     lib.dg_rhs_fv.argtypes = [P, ctypes.POINTER(_Params), P, P, P, P, P, P]
     lib.dg_rk_stage_fv.argtypes = [P, ctypes.POINTER(_Params), c_int, c_double, P, P, P, P, P, P]
+    lib.dg_rk_step_fv.argtypes = [P, ctypes.POINTER(_Params), c_double, P, P, P, P, P, P]
     lib.dg_switch_fv.argtypes = [P, P, P, P, P, P]
     lib.dgfv_set_element_shape.argtypes = [P, c_int, c_int]
     lib.dgfv_autotune.argtypes = [P, ctypes.POINTER(_Params), P, P, ctypes.POINTER(ctypes.c_double), P]
@@ -279,9 +281,10 @@ def rk_stage_fv(mesh: Mesh, params: Params, stage: int, dt: float, u, k, ufv, kf
 
 
 def rk_step_fv(mesh: Mesh, params: Params, dt: float, u, k, ufv, kfv, fv, stream=None) -> None:
-    """The five stages of ``dg_rk_stage_fv`` in turn."""
-    for s in range(1, 6):
-        rk_stage_fv(mesh, params, s, dt, u, k, ufv, kfv, fv, stream)
+    """In-place five-stage RK step of (u, k) and (ufv, kfv) (``dg_rk_step_fv``)."""
+    _check(_lib.dg_rk_step_fv(mesh._h, ctypes.byref(params.c()), float(dt), mesh._state(u, "u"), mesh._state(k, "k"),
+                              mesh._fv_state(ufv, "ufv"), mesh._fv_state(kfv, "kfv"), mesh._alpha(fv),
+                              _stream(stream)))
 
 
 def switch_fv(mesh: Mesh, u, ufv, fv_old, fv_new, stream=None) -> None:

@@ -91,6 +91,14 @@ def main(src, dst):
                 check(lib.dg_rk_stage_fv(h, ctypes.byref(prm), ctypes.c_int(st), ctypes.c_double(float(z["dt"])),
                                          ptr(uu), ptr(k), ptr(uf), ptr(kf), ptr(fvf), None), "dg_rk_stage_fv")
             out["step_fv_dg"], out["step_fv_fv"] = uu, uf
+        elif call == "rk_step_fv_one_call":
+            uu = u.copy()
+            uf = np.ascontiguousarray(z["ufv"], dtype=np.float64).copy()
+            fvf = np.ascontiguousarray(z["fv"], dtype=np.float64)
+            k, kf = np.empty_like(uu), np.empty_like(uf)
+            check(lib.dg_rk_step_fv(h, ctypes.byref(prm), ctypes.c_double(float(z["dt"])), ptr(uu), ptr(k), ptr(uf),
+                                    ptr(kf), ptr(fvf), None), "dg_rk_step_fv")
+            out["step1_fv_dg"], out["step1_fv_fv"] = uu, uf
         elif call == "switch_fv":
             uu = u.copy()
             uf = np.ascontiguousarray(z["ufv"], dtype=np.float64).copy()

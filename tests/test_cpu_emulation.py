@@ -225,3 +225,25 @@ def test_cpu_build_fv_stored_elements(n_var):
     seln = torch.as_tensor(new)
     got = torch.as_tensor(out["switch_fv"]).reshape(K, n_var, -1)[seln].transpose(0, 1).reshape(n_var, -1)
     assert rel_err(got, sf[seln].transpose(0, 1).reshape(n_var, -1)) <= 1e-12
+
+
+def test_cpu_build_fv_stored_step_with_traces():
+    # degrees 6 and 7 (their DG faces read the xi_1 sides from traces between the
+    # stages of dg_rk_step_fv): the one-call step equals five stage calls bit for bit
+    from oracle import lsrk
+    wl = curved_mixed(n=2, nmin=6, nmax=7, n_var=5, scramble=3, metric_degree=0, n_fv=8)
+    c = _case(wl, smooth_state(29, 5), noise=1e-3, seed=4)
+    rng = np.random.default_rng(4)
+    flag = rng.random(c.mesh.K) < 0.3
+    flag[0] = True
+    from oracle import native_fv
+    nf = wl.n_fv
+    ufv = torch.zeros(c.mesh.K, 5, nf, nf, nf, dtype=T)
+    fvel = np.nonzero(flag)[0]
+    ufv[torch.as_tensor(fvel)] = native_fv.dg_to_fv(c.mesh, c.u, fvel)
+    dt = 0.2 * lsrk.timestep(c.mesh, c.gas, c.u, 0.5, torch.as_tensor(flag, dtype=T))
+    out = cpu_emu.run(wl, c.u.numpy(), ["rk_step_fv", "rk_step_fv_one_call"], dt=dt,
+                      ufv=ufv.reshape(c.mesh.K, 5, -1).numpy(), fv=flag.astype(np.float64))
+    dg = np.repeat(~flag, np.diff(c.mesh.offset))
+    assert np.array_equal(out["step1_fv_dg"][:, dg], out["step_fv_dg"][:, dg])
+    assert np.array_equal(out["step1_fv_fv"][flag], out["step_fv_fv"][flag])

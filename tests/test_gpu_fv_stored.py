@@ -131,3 +131,32 @@ def test_fv_stored_degenerate_cases():
     _, rf = dgfv.rhs_fv(gm, prm, _gpu(u), _gpu(ufv.reshape(K, n_var, -1)), torch.ones(K, dtype=T, device="cuda"))
     torch.cuda.synchronize()
     assert rel_err(_fv_rows(rf.cpu(), flag, n_var), _fv_rows(Rfv, flag, n_var)) <= 1e-11
+
+
+def test_fv_stored_step_with_traces_equals_stages():
+    # degrees 6 and 7: between the stages of dg_rk_step_fv the DG faces read the
+    # xi_1 sides from traces; five dg_rk_stage_fv calls read them from u
+    announce("FV-stored step with traces, N=6,7")
+    from paper_2502_19342_amd import dgfv
+    wl, mesh, gas, u, ufv, flag, gm, prm = _case(n=3, nmin=6, nmax=7, n_fv=8, frac=0.3, seed=5)
+    K, n_var = mesh.K, 5
+    native = native_fv.NativeRhs(mesh, gas, problem.params_of(wl))
+    dt = 0.2 * lsrk.timestep(mesh, gas, u, 0.5, torch.as_tensor(flag, dtype=T))
+    fv = _gpu(torch.as_tensor(flag, dtype=T))
+    a_u, a_f = _gpu(u), _gpu(ufv.reshape(K, n_var, -1))
+    b_u, b_f = a_u.clone(), a_f.clone()
+    k, kf = torch.zeros_like(a_u), torch.zeros_like(a_f)
+    dgfv.rk_step_fv(gm, prm, dt, a_u, k, a_f, kf, fv)
+    for s in range(1, 6):
+        dgfv.rk_stage_fv(gm, prm, s, dt, b_u, k, b_f, kf, fv)
+    torch.cuda.synchronize()
+    dg = _dg_cols(mesh, flag)
+    assert torch.equal(a_u[:, dg.cuda()], b_u[:, dg.cuda()])
+    assert torch.equal(a_f[torch.as_tensor(flag).cuda()], b_f[torch.as_tensor(flag).cuda()])
+    uo, ufo = u.clone(), ufv.clone()
+    ko, kfo = torch.zeros_like(uo), torch.zeros_like(ufo)
+    for s in range(5):
+        uo, ufo, ko, kfo = native_fv.stage(lambda x, y: native(x, y, flag), uo, ufo, ko, kfo, s, dt,
+                                           lsrk.A_F64, lsrk.B_F64)
+    assert rel_err(a_u.cpu()[:, dg], uo[:, dg]) <= 1e-11
+    assert rel_err(_fv_rows(a_f.cpu(), flag, n_var), _fv_rows(ufo, flag, n_var)) <= 1e-11
