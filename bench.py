@@ -48,6 +48,9 @@ def parse():
                     help="serial launches, concurrent degree-bucket branches, or replayed hipGraphs")
     ap.add_argument("--cpu-sample-n", type=int, default=8, help="elements per direction of the oracle sample")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward timing ratio")
+    ap.add_argument("--p-adapt", action="store_true",
+                    help="after the timed steps, one p-adaptation (degree decision on I(rho), the mesh of the new "
+                         "degrees, the state transfer) and steps on the new mesh, timed")
     ap.add_argument("--fv-stored", action="store_true",
                     help="the blended elements carry sub-cell means (FV-stored elements) instead")
     ap.add_argument("--cpu-table", action="store_true",
@@ -140,6 +143,49 @@ def fv_stored_roofline(wl, fv: np.ndarray, kt: dict) -> dict:
     return {"bound": "hbm", "kernel": "fv_stored_kernel", "elements": n_fv, "bytes_per_launch": per * n_fv,
             "avg_launch_ms": avg_ms, "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": achieved / PEAK_HBM_GBS}
+
+
+def p_adapt_timing(gm, prm, u, alpha, dt, dgfv, torch, steps: int = 5) -> dict:
+    """One p-adaptation of the state after the timed steps, timed by parts.
+
+    Thresholds at the 30 % and 70 % quantiles of I(rho), so that about a third of
+    the elements move each way; degrees within 1..7.  Then `steps` RK steps on
+    the new mesh (first one untimed: graph capture, autotune-free).
+    """
+    t0 = time.perf_counter()
+    ind = torch.empty(gm.n_elem, dtype=torch.float64, device="cuda")
+    tmp = torch.empty_like(ind)
+    p_rho = dgfv.Params(prm.volume_flux, prm.face_flux_dg, prm.face_flux_fv, 2, 0.0, 1.0)
+    dgfv.indicator(gm, p_rho, u, alpha=tmp, ind=ind)
+    I = ind.cpu().numpy()
+    t_ref, t_coarse = float(np.quantile(I, 0.3)), float(np.quantile(I, 0.7))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    new = dgfv.p_degrees(gm, prm, u, t_ref, t_coarse, 1, 7)
+    t2 = time.perf_counter()
+    gm2 = gm.redegree(new)
+    t3 = time.perf_counter()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    u2 = dgfv.transfer_degree(gm, gm2, u)
+    b.record()
+    b.synchronize()
+    transfer_ms = a.elapsed_time(b)
+    k2 = torch.zeros_like(u2)
+    a2 = torch.zeros(gm2.n_elem, dtype=torch.float64, device="cuda") if alpha is not None else None
+    dgfv.rk_step(gm2, prm, dt, u2, k2, a2)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    for _ in range(steps):
+        dgfv.rk_step(gm2, prm, dt, u2, k2, a2)
+    torch.cuda.synchronize()
+    t5 = time.perf_counter()
+    return {"raised": int((new > gm.degree).sum()), "lowered": int((new < gm.degree).sum()),
+            "decision_ms": 1e3 * (t2 - t1), "mesh_build_s": t3 - t2, "transfer_ms": transfer_ms,
+            "dofs_before": int(gm.n_node), "dofs_after": int(gm2.n_node),
+            "dof_updates_per_s_after": gm2.n_node * 5 * steps / (t5 - t4),
+            "thresholds": [t_ref, t_coarse], "note": "mesh_build_s is host work (metrics in long double); "
+            "the decision waits for the indicator and copies I to the host"}
 
 
 def stage_bytes(wl, degree: np.ndarray) -> float:
@@ -418,6 +464,7 @@ def main():
         print("bench.py: non-finite state after the timed steps", file=sys.stderr)
         sys.exit(1)
     adjoint = None if (args.no_adjoint or args.fv_stored) else adjoint_ratio(gm, prm, u, dgfv, torch)
+    padapt = p_adapt_timing(gm, prm, u, alpha, dt, dgfv, torch) if args.p_adapt else None
 
     stages = 5 * args.steps
     value = n_dof * stages / el
@@ -478,6 +525,7 @@ def main():
         "kernel_ms_note": "phases in order: fv_means, face, fv_residual, element; fv_face lies inside face "
                           "(beside the DG face fluxes outside --launch serial)",
         "fv_stored": fv_stored_roofline(wl, alpha_h, kt) if args.fv_stored else None,
+        "p_adapt": padapt,
         "indicator_ms": indicator_ms,
         "indicator_note": "one dg_indicator call over all elements (variables p and rho), timed alone; "
                           "every timed step includes one call",

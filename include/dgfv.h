@@ -260,6 +260,33 @@ dgfv_status dg_switch_fv(const dgfv_mesh* mesh, double* u_d, double* ufv_d, cons
                          const double* fv_new_d, void* stream);
 
 /*
+ * Dynamic p-adaptation (Section 3.4: I_p-adapt = I(rho); Section 3.2: the maps
+ * between ansatz degrees).
+ * dg_p_degrees: the modal decay indicator of the density (as dg_indicator with
+ *   the density selected, whatever params->ind_vars) decides each element's next
+ *   degree: I < t_refine raises N by one, I > t_coarsen lowers it by one,
+ *   clamped to [n_min, n_max] (t_refine < t_coarsen; I = +inf coarsens).
+ *   degree_out: host int8 [n_elem].  Synchronous: the call waits for the
+ *   indicator on `stream` (DGFV_ERR_ARG while the stream is captured).
+ * The caller then builds the mesh of the new degrees with dgfv_mesh_create (the
+ *   same corners, faces and constants; a mesh-wide metric degree above the new
+ *   lowest degree must come down): the new mesh has its own degree buckets, work
+ *   lists and graph cache.
+ * dg_transfer_degree: u_to_d (layout of mesh `to`) from u_from_d (layout of mesh
+ *   `from`), element by element along each reference direction: interpolation
+ *   V^{N->M} to a higher degree (exact), the modal L2 truncation V^{M->N} to a
+ *   lower one (keeps the Legendre modes up to the lower degree), the identity
+ *   where the degree stays; on the conservative state.  Constants are kept
+ *   exactly, and on affine elements every element's content.  The meshes must
+ *   have the same n_elem and n_var.  The first transfer into a mesh uploads the
+ *   maps (32 KB; DGFV_ERR_ARG while the stream is captured).
+ */
+dgfv_status dg_p_degrees(const dgfv_mesh* mesh, const dgfv_params* params, const double* u_d, double t_refine,
+                         double t_coarsen, int n_min, int n_max, int8_t* degree_out, void* stream);
+dgfv_status dg_transfer_degree(const dgfv_mesh* from, const dgfv_mesh* to, const double* u_from_d, double* u_to_d,
+                               void* stream);
+
+/*
  * Fused face fluxes (not part of the method; off by default).  Elements of
  * degree 6 and 7 evaluate the Riemann flux (eq. conv_flux) of each face they
  * share with a pure DG element of the same degree themselves, with the same

@@ -149,6 +149,11 @@ struct dgfv_mesh {
   mutable double* fvghost = nullptr;
   mutable double* fvjbar = nullptr;
 
+  // p-adaptation: the maps between degrees (made by the first transfer into this
+  // mesh) and the indicator values of the degree decision
+  mutable double* pmap = nullptr;
+  mutable double* pind = nullptr;
+
   // kernel timing (mutable: recording does not change the mesh)
   mutable bool profile = false;
   mutable std::array<std::vector<std::pair<hipEvent_t, hipEvent_t>>, DGFV_KERNEL_COUNT> ev;
@@ -178,6 +183,8 @@ struct dgfv_mesh {
     if (u_alt) (void)hipFree(u_alt);
     if (fvghost) (void)hipFree(fvghost);
     if (fvjbar) (void)hipFree(fvjbar);
+    if (pmap) (void)hipFree(pmap);
+    if (pind) (void)hipFree(pind);
   }
   template <class T>
   T* keep(T* p) {
@@ -1220,6 +1227,72 @@ dgfv_status dg_indicator(const dgfv_mesh* m, const dgfv_params* prm, const doubl
                   "indicator launch");
   } catch (const HipError& e) {
     return fail(DGFV_ERR_HIP, e.what());
+  }
+  return DGFV_OK;
+}
+
+dgfv_status dg_p_degrees(const dgfv_mesh* m, const dgfv_params* prm, const double* u, double t_refine,
+                         double t_coarsen, int n_min, int n_max, int8_t* degree_out, void* stream) {
+  if (!m || !u || !degree_out) return fail(DGFV_ERR_ARG, "NULL argument");
+  if (dgfv_status st = check_params(m, prm)) return st;
+  if (n_min < 1 || n_max > MAXN || n_min > n_max) return fail(DGFV_ERR_ARG, "need 1 <= n_min <= n_max <= 7");
+  if (!(t_refine < t_coarsen)) return fail(DGFV_ERR_ARG, "need t_refine < t_coarsen");
+  hipStream_t s = (hipStream_t)stream;
+  if (capturing(s)) return fail(DGFV_ERR_ARG, "dg_p_degrees waits for its result: not under capture");
+  try {
+    if (!m->pind) m->pind = dev_alloc<double>(2 * (size_t)m->K);      // alpha scratch, then I
+    ParamsDev p = to_dev(prm);
+    p.ind_vars = 2;                                                   // I_p-adapt = I(rho)
+    p.ind_T = 0.0;
+    p.ind_dT = 1.0;
+    for (int N = 1; N <= MAXN; ++N)
+      if (!m->bucket[N].empty())
+        hip_check(ops_for(N).indicator(m->view, p, m->d_bucket[N], (int)m->bucket[N].size(), u, m->pind,
+                                       m->pind + m->K, s),
+                  "indicator launch");
+    std::vector<double> I(m->K);
+    hip_check(hipMemcpyAsync(I.data(), m->pind + m->K, sizeof(double) * m->K, hipMemcpyDeviceToHost, s), "copy");
+    hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    for (int e = 0; e < m->K; ++e) {
+      int N = m->degree[e];
+      if (I[e] < t_refine) N = std::min(N + 1, n_max);
+      else if (I[e] > t_coarsen) N = std::max(N - 1, n_min);
+      degree_out[e] = (int8_t)N;
+    }
+  } catch (const HipError& e) {
+    return fail(msg_oom(e) ? DGFV_ERR_OOM : DGFV_ERR_HIP, e.what());
+  }
+  return DGFV_OK;
+}
+
+dgfv_status dg_transfer_degree(const dgfv_mesh* from, const dgfv_mesh* to, const double* u_from, double* u_to,
+                               void* stream) {
+  if (!from || !to || !u_from || !u_to) return fail(DGFV_ERR_ARG, "NULL argument");
+  if (from->K != to->K || from->nvar != to->nvar) return fail(DGFV_ERR_ARG, "the meshes differ in n_elem or n_var");
+  if (u_from == u_to) return fail(DGFV_ERR_ARG, "u_from and u_to must not overlap");
+  hipStream_t s = (hipStream_t)stream;
+  try {
+    if (!to->pmap) {
+      if (capturing(s)) return fail(DGFV_ERR_ARG, "the first transfer into a mesh allocates: not under capture");
+      constexpr int TM = MAXN + 1;
+      std::vector<double> tab((size_t)TM * TM * TM * TM, 0.0);
+      for (int Nf = 1; Nf <= MAXN; ++Nf)
+        for (int Nt = 1; Nt <= MAXN; ++Nt) {
+          std::vector<double> A;
+          if (Nt > Nf) A = op_interp(Nf, Nt);
+          else if (Nt < Nf) A = op_project(Nf, Nt);
+          else {
+            A.assign((size_t)(Nf + 1) * (Nf + 1), 0.0);
+            for (int i = 0; i <= Nf; ++i) A[(size_t)i * (Nf + 1) + i] = 1.0;
+          }
+          std::copy(A.begin(), A.end(), tab.begin() + ((size_t)Nf * TM + Nt) * TM * TM);
+        }
+      double* d = dev_upload(tab);
+      to->pmap = d;
+    }
+    hip_check(launch_transfer(from->view, to->view, u_from, u_to, to->pmap, s), "transfer launch");
+  } catch (const HipError& e) {
+    return fail(msg_oom(e) ? DGFV_ERR_OOM : DGFV_ERR_HIP, e.what());
   }
   return DGFV_OK;
 }

@@ -213,6 +213,11 @@ constexpr size_t STATIC_SCRATCH_DOUBLES = size_t(1) << 24;   // 128 MiB
 constexpr int MAX_DEVICES = 64;
 hipError_t static_scratch_ptr(double** out);
 
+// p-adaptation: every element's state from its degree in `from` to its degree in
+// `to` (same elements), with table[(Nf * 8 + Nt) * 64 ...] the (Nt+1) x (Nf+1) map.
+hipError_t launch_transfer(const MeshView& from, const MeshView& to, const double* u_from, double* u_to,
+                           const double* table, hipStream_t s);
+
 // Pointwise state kernels (dgfv_state.hip).
 hipError_t launch_prim_to_cons(const MeshView& m, const double* w, double* u, hipStream_t s);
 hipError_t launch_rk_adjoint_pre(const MeshView& m, double B, const double* ubar, double* kbar, hipStream_t s);

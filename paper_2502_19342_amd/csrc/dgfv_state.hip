@@ -65,6 +65,62 @@ rk_adjoint_post_kernel(int64_t n, double dt, double A, const double* __restrict_
   }
 }
 
+// p-adaptation (Section 3.2): an element's state from degree Nf to degree Nt by
+// the 1D map table[Nf][Nt] ((Nt+1) x (Nf+1), interpolation up, modal
+// truncation down, identity otherwise) along each reference direction; one
+// element per 512-lane workgroup, the three one-dimensional passes through LDS.
+constexpr int TRANSFER_THREADS = 512;
+constexpr int TMAX = MAXN + 1;
+
+template <int NV>
+__global__ void __launch_bounds__(TRANSFER_THREADS)
+transfer_kernel(int K, const double* __restrict__ u_from, const int64_t* __restrict__ off_from,
+                const int8_t* __restrict__ deg_from, int64_t n_from, double* __restrict__ u_to,
+                const int64_t* __restrict__ off_to, const int8_t* __restrict__ deg_to, int64_t n_to,
+                const double* __restrict__ table) {
+  __shared__ double a[NV * TMAX * TMAX * TMAX], b[NV * TMAX * TMAX * TMAX];
+  __shared__ double A[TMAX * TMAX];
+  const int e = blockIdx.x;
+  if (e >= K) return;
+  const int t = threadIdx.x;
+  const int Nf = deg_from[e], Nt = deg_to[e];
+  const int ni = Nf + 1, no = Nt + 1;
+  const int ni3 = ni * ni * ni;
+  if (t < no * ni) A[t] = table[(Nf * TMAX + Nt) * TMAX * TMAX + t];
+  const int64_t bf = off_from[e], bt = off_to[e];
+  for (int r = t; r < ni3; r += TRANSFER_THREADS)
+    for (int v = 0; v < NV; ++v) a[v * ni3 + r] = u_from[v * n_from + bf + r];
+  __syncthreads();
+  // axis 0: [f][k][j][c] -> [f][k][j][o]
+  for (int r = t; r < NV * ni * ni; r += TRANSFER_THREADS)
+    for (int o = 0; o < no; ++o) {
+      double acc = 0.0;
+      for (int c = 0; c < ni; ++c) acc += A[o * ni + c] * a[r * ni + c];
+      b[r * no + o] = acc;
+    }
+  __syncthreads();
+  // axis 1: [f][k][c][o0] -> [f][k][o1][o0]
+  for (int r = t; r < NV * ni * no; r += TRANSFER_THREADS) {
+    const int o0 = r % no, kf = r / no;
+    for (int o = 0; o < no; ++o) {
+      double acc = 0.0;
+      for (int c = 0; c < ni; ++c) acc += A[o * ni + c] * b[(kf * ni + c) * no + o0];
+      a[(kf * no + o) * no + o0] = acc;
+    }
+  }
+  __syncthreads();
+  // axis 2: [f][c][o1][o0] -> [f][o2][o1][o0], written to the new layout
+  const int no2 = no * no;
+  for (int r = t; r < NV * no2; r += TRANSFER_THREADS) {
+    const int o01 = r % no2, f = r / no2;
+    for (int o = 0; o < no; ++o) {
+      double acc = 0.0;
+      for (int c = 0; c < ni; ++c) acc += A[o * ni + c] * a[(f * ni + c) * no2 + o01];
+      u_to[f * n_to + bt + o * no2 + o01] = acc;
+    }
+  }
+}
+
 int grid_for(int64_t n, const MeshView& m) {
   const int64_t want = (n + STATE_THREADS - 1) / STATE_THREADS;
   const int64_t cap = (int64_t)m.n_cu * 32;       // grid-stride beyond this
@@ -93,6 +149,18 @@ hipError_t launch_prim_to_cons(const MeshView& m, const double* w, double* u, hi
     hipLaunchKernelGGL((prim_to_cons_kernel<5>), dim3(grid_for(n, m)), dim3(STATE_THREADS), 0, s, n, m.gas, w, u);
   else
     hipLaunchKernelGGL((prim_to_cons_kernel<6>), dim3(grid_for(n, m)), dim3(STATE_THREADS), 0, s, n, m.gas, w, u);
+  return hipGetLastError();
+}
+
+hipError_t launch_transfer(const MeshView& from, const MeshView& to, const double* u_from, double* u_to,
+                           const double* table, hipStream_t s) {
+  if (from.K == 0) return hipSuccess;
+  if (from.nvar == 5)
+    hipLaunchKernelGGL(transfer_kernel<5>, dim3(from.K), dim3(TRANSFER_THREADS), 0, s, from.K, u_from,
+                       from.elem_offset, from.degree, from.n_node, u_to, to.elem_offset, to.degree, to.n_node, table);
+  else
+    hipLaunchKernelGGL(transfer_kernel<6>, dim3(from.K), dim3(TRANSFER_THREADS), 0, s, from.K, u_from,
+                       from.elem_offset, from.degree, from.n_node, u_to, to.elem_offset, to.degree, to.n_node, table);
   return hipGetLastError();
 }
 

@@ -45,7 +45,7 @@ EXPORTED = ("dgfv_mesh_create", "dgfv_mesh_destroy", "dgfv_mesh_info", "dgfv_mes
             "dg_rk_stage_vjp_noalloc", "dgfv_prim_to_cons", "dg_positivity_limiter",
             "dgfv_set_positivity_limiter", "dgfv_set_launch_mode", "dgfv_set_face_fusion", "dgfv_autotune",
             "dgfv_set_element_shape", "dgfv_check_state", "dg_rhs_fv", "dg_rk_stage_fv", "dg_rk_step_fv",
-            "dg_switch_fv",
+            "dg_switch_fv", "dg_p_degrees", "dg_transfer_degree",
             "dgfv_profile_enable", "dgfv_profile_read", "dgfv_last_error")
 KERNEL_ELEMENT, KERNEL_FACE, KERNEL_FV_MEANS, KERNEL_FV_RESIDUAL, KERNEL_INDICATOR, KERNEL_VJP, KERNEL_FV_FACE = range(7)
 LAUNCH_SERIAL, LAUNCH_BRANCHES, LAUNCH_GRAPH = range(3)
@@ -77,6 +77,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dg_rk_stage_fv.argtypes = [P, ctypes.POINTER(_Params), c_int, c_double, P, P, P, P, P, P]
     lib.dg_rk_step_fv.argtypes = [P, ctypes.POINTER(_Params), c_double, P, P, P, P, P, P]
     lib.dg_switch_fv.argtypes = [P, P, P, P, P, P]
+    lib.dg_p_degrees.argtypes = [P, ctypes.POINTER(_Params), P, c_double, c_double, c_int, c_int,
+                                 ctypes.POINTER(ctypes.c_int8), P]
+    lib.dg_transfer_degree.argtypes = [P, P, P, P, P]
     lib.dgfv_set_element_shape.argtypes = [P, c_int, c_int]
     lib.dgfv_autotune.argtypes = [P, ctypes.POINTER(_Params), P, P, ctypes.POINTER(ctypes.c_double), P]
     lib.dgfv_profile_enable.argtypes = [P, c_int]
@@ -128,6 +131,8 @@ class Mesh:
         self.n_elem = K
         self.n_var = int(n_var)
         self.n_fv = int(n_fv if n_fv is not None else int(self.degree.max()) + 1)
+        self._args = dict(n_var=self.n_var, n_fv=self.n_fv, metric_degree=int(metric_degree), gamma=float(gamma),
+                          kappa=tuple(kappa), R=tuple(R))
         desc = _MeshDesc(K, self.n_var, self.degree.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)),
                          self.corners.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                          self.faces.shape[0], self.faces.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
@@ -160,6 +165,14 @@ class Mesh:
         if h is not None and h.value:
             _lib.dgfv_mesh_destroy(h)
             self._h = None
+
+    def redegree(self, degree) -> "Mesh":
+        """The mesh of the same elements at new degrees (a mesh-wide metric degree
+        above the new lowest degree comes down to it)."""
+        kw = dict(self._args)
+        if kw["metric_degree"] > 0:
+            kw["metric_degree"] = min(kw["metric_degree"], int(np.min(degree)))
+        return Mesh(degree, self.corners, self.faces, **kw)
 
     def launch_mode(self, mode: int) -> None:
         """LAUNCH_SERIAL, LAUNCH_BRANCHES (default) or LAUNCH_GRAPH (``dgfv_set_launch_mode``)."""
@@ -291,6 +304,26 @@ def switch_fv(mesh: Mesh, u, ufv, fv_old, fv_new, stream=None) -> None:
     """Convert the elements whose FV flag changes (``dg_switch_fv``), in place."""
     _check(_lib.dg_switch_fv(mesh._h, mesh._state(u, "u"), mesh._fv_state(ufv, "ufv"), mesh._alpha(fv_old),
                              mesh._alpha(fv_new), _stream(stream)))
+
+
+def p_degrees(mesh: Mesh, params: Params, u: torch.Tensor, t_refine: float, t_coarsen: float, n_min: int,
+              n_max: int, stream=None) -> np.ndarray:
+    """Next degree of every element from I(rho) (``dg_p_degrees``; waits for the result)."""
+    out = np.zeros(mesh.n_elem, dtype=np.int8)
+    _check(_lib.dg_p_degrees(mesh._h, ctypes.byref(params.c()), mesh._state(u, "u"), float(t_refine),
+                             float(t_coarsen), int(n_min), int(n_max),
+                             out.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)), _stream(stream)))
+    return out
+
+
+def transfer_degree(mesh_from: Mesh, mesh_to: Mesh, u: torch.Tensor, out: torch.Tensor | None = None,
+                    stream=None) -> torch.Tensor:
+    """The state on ``mesh_to`` from the state on ``mesh_from`` (``dg_transfer_degree``)."""
+    if out is None:
+        out = torch.empty(mesh_to.n_var, mesh_to.n_node, dtype=torch.float64, device=u.device)
+    _check(_lib.dg_transfer_degree(mesh_from._h, mesh_to._h, mesh_from._state(u, "u"), mesh_to._state(out, "out"),
+                                   _stream(stream)))
+    return out
 
 
 def positivity_limiter(mesh: Mesh, params: Params, u: torch.Tensor, alpha: torch.Tensor | None = None,

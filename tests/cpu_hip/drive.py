@@ -99,6 +99,26 @@ def main(src, dst):
             check(lib.dg_rk_step_fv(h, ctypes.byref(prm), ctypes.c_double(float(z["dt"])), ptr(uu), ptr(k), ptr(uf),
                                     ptr(kf), ptr(fvf), None), "dg_rk_step_fv")
             out["step1_fv_dg"], out["step1_fv_fv"] = uu, uf
+        elif call == "p_degrees":
+            nd = np.zeros(K, dtype=np.int8)
+            th = z["p_thresholds"]
+            check(lib.dg_p_degrees(h, ctypes.byref(prm), ptr(u), ctypes.c_double(float(th[0])),
+                                   ctypes.c_double(float(th[1])), ctypes.c_int(int(th[2])), ctypes.c_int(int(th[3])),
+                                   ptr(nd), None), "dg_p_degrees")
+            out["p_degrees"] = nd
+        elif call == "transfer":
+            deg2 = np.ascontiguousarray(z["degree_to"], dtype=np.int8)
+            desc2 = MeshDesc(K, int(z["n_var"]), ptr(deg2), ptr(corners), faces.shape[0], ptr(faces),
+                             int(z["n_fv"]), int(z["metric_degree_to"]), float(z["gamma"]),
+                             (ctypes.c_double * 2)(*z["kappa"]), (ctypes.c_double * 2)(*z["R"]))
+            h2 = P()
+            check(lib.dgfv_mesh_create(ctypes.byref(desc2), ctypes.byref(h2)), "dgfv_mesh_create (new degrees)")
+            n2 = ctypes.c_int64()
+            check(lib.dgfv_mesh_info(h2, ctypes.byref(n2), None), "dgfv_mesh_info")
+            u2 = np.empty((u.shape[0], n2.value))
+            check(lib.dg_transfer_degree(h, h2, ptr(u), ptr(u2), None), "dg_transfer_degree")
+            lib.dgfv_mesh_destroy(h2)
+            out["transfer"] = u2
         elif call == "switch_fv":
             uu = u.copy()
             uf = np.ascontiguousarray(z["ufv"], dtype=np.float64).copy()

@@ -247,3 +247,23 @@ def test_cpu_build_fv_stored_step_with_traces():
     dg = np.repeat(~flag, np.diff(c.mesh.offset))
     assert np.array_equal(out["step1_fv_dg"][:, dg], out["step_fv_dg"][:, dg])
     assert np.array_equal(out["step1_fv_fv"][flag], out["step_fv_fv"][flag])
+
+
+def test_cpu_build_p_adaptation():
+    # the degree decision from I(rho) and the transfer to the new degrees, against the oracle
+    import dataclasses
+    from oracle import p_adapt
+    from oracle.geometry import OracleMesh
+    wl = curved_mixed(n=3, nmin=2, nmax=5, scramble=7, metric_degree=0, n_fv=8)
+    c = _case(wl, smooth_state(31, 5), noise=1e-2, seed=6)
+    from oracle.indicator import indicator
+    I, _ = indicator(c.mesh, c.gas, c.u, 0.0, 1.0, ind_vars=2)
+    t_ref, t_coarse = float(np.quantile(I.numpy(), 0.3)), float(np.quantile(I.numpy(), 0.7))
+    want = p_adapt.degrees(c.mesh, c.gas, c.u, t_ref, t_coarse, 1, 7)
+    assert (want > c.mesh.degree).any() and (want < c.mesh.degree).any()
+    m2 = OracleMesh(dataclasses.replace(c.mesh.spec, degree=want.astype(np.int8)), c.mesh.n_fv, 0)
+    u2 = p_adapt.transfer(c.mesh, m2, c.u)
+    out = cpu_emu.run(wl, c.u.numpy(), ["p_degrees", "transfer"], p_thresholds=np.array([t_ref, t_coarse, 1, 7]),
+                      degree_to=want, metric_degree_to=0)
+    assert np.array_equal(out["p_degrees"].astype(np.int64), want)
+    assert rel_err(torch.as_tensor(out["transfer"]), u2) <= 1e-13
