@@ -13,4 +13,8 @@ Modules:
     indicator  modal decay indicator and blending ramp
     lsrk       five-stage fourth-order 2N Runge-Kutta and the CFL time step
     problem    assembly of a workload into oracle objects
+    limiter    positivity-preserving limiter of Zhang and Shu
+    native_fv  FV-stored elements: minmod-reconstructed sub-cell means, switching
+    p_adapt    degree decision from I(rho) and the state maps between degrees
+    viscous    viscous multi-species fluxes and BR1 lifting
 """

@@ -7,6 +7,7 @@ import torch
 from .geometry import OracleMesh
 from .physics import Gas, prim_to_cons
 from .rhs import Params, Rhs
+from .viscous import Transport, ViscousRhs
 
 T = torch.float64
 
@@ -19,10 +20,18 @@ def params_of(wl) -> Params:
     return Params(wl.volume_flux, wl.face_flux_dg, wl.face_flux_fv)
 
 
+def transport_of(wl) -> Transport:
+    return Transport(mu=tuple(wl.mu), Pr=tuple(wl.Pr), D=tuple(wl.D))
+
+
 def build(wl):
+    """Mesh, gas and ``R(u, alpha)``; with the viscous terms when the workload has any."""
     mesh = OracleMesh(wl.mesh, wl.n_fv, wl.metric_degree)
     gas = gas_of(wl)
-    return mesh, gas, Rhs(mesh, gas, params_of(wl))
+    f = Rhs(mesh, gas, params_of(wl))
+    if getattr(wl, "viscous", False):
+        f = ViscousRhs(f, mesh, gas, transport_of(wl))
+    return mesh, gas, f
 
 
 def initial_state(mesh: OracleMesh, gas: Gas, prim_fn) -> torch.Tensor:

@@ -407,6 +407,15 @@ class Workload:
     noise: float = 0.0
     blend_fraction: float | None = None
     limiter: bool = False        # positivity limiter after every Runge-Kutta stage
+    # viscous terms (species 1 first; one species uses index 0): dynamic viscosity,
+    # Prandtl number, diffusion coefficient; all zero mu and D: inviscid
+    mu: tuple = (0.0, 0.0)
+    Pr: tuple = (0.72, 0.72)
+    D: tuple = (0.0, 0.0)
+
+    @property
+    def viscous(self) -> bool:
+        return any(x != 0.0 for x in tuple(self.mu) + tuple(self.D))
 
 
 def make_workload(name: str, n: int | None = None, scramble_seed: int | None = None) -> Workload:
