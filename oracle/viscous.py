@@ -26,9 +26,10 @@ summation-by-parts property of the collocated operators:
 * viscous rate: ``R^v = -(1/J) sum_d [ sum_m D_im Ft^d_m + (F^v* - Ft^d) / w
   at the ends, with outward sign ]`` with ``Ft^d = sum_x Ja^d_x F^v_x`` and
   the face flux ``F^v* = (F^v(u^-, g^-) + F^v(u^+, g^+)) / 2 . n s``
-  (eq. visc_flux), formed on the higher degree of the face with the left
-  side's outward normal, the lower side receiving the projection, as the
-  convective flux.
+  (eq. visc_flux), formed as the convective flux: both sides' traces of
+  ``u`` and ``g`` interpolated to the higher degree of the face, the fluxes
+  evaluated there with the left side's outward normal, the lower side
+  receiving the projection.
 
 Readings where the paper is silent or garbled:
 
@@ -249,20 +250,27 @@ def viscous_rhs(mesh: OracleMesh, gas: Gas, tr: Transport, u: torch.Tensor,
         Fv[N] = viscous_flux(Uv, Gv, gas, tr).transpose(1, 2)  # [3(x), E, nvar, n, n, n]
 
     side = {N: [[None] * 6 for _ in range(len(g_.elems))] for N, g_ in mesh.groups.items()}
+    G5 = {N: Gd[N].reshape(len(grp.elems), 3, nvar, N + 1, N + 1, N + 1) for N, grp in mesh.groups.items()}
     for (NL, NR, sL, sR, o), eL, eR in _face_groups(mesh):
         slL = torch.as_tensor(mesh.slot[eL], dtype=torch.long)
         slR = torch.as_tensor(mesh.slot[eR], dtype=torch.long)
-        fL = face_slice(Fv[NL][:, slL], sL)                    # [3, F, nvar, n, n]
-        fR = to_left(face_slice(Fv[NR][:, slR], sR), o)
+        uL = face_slice(U[NL][slL], sL)                        # [F, nvar, n, n]
+        uR = to_left(face_slice(U[NR][slR], sR), o)
+        gL = face_slice(G5[NL][slL], sL)                       # [F, 3, nvar, n, n]
+        gR = to_left(face_slice(G5[NR][slR], sR), o)
         nvec = mesh.groups[NL].outward_normal(sL)[slL]         # [F, 3, nL, nL]
         M = max(NL, NR)
-        # the physical fluxes of each side's state and gradient, brought to degree M
+        # as for the convective flux: both sides' traces (state and gradient)
+        # on degree M, the fluxes evaluated there
         if NL < M:
             VL = _t(ops1d.interp(NL, M))
-            fL, nvec = apply2(VL, fL), apply2(VL, nvec)
+            uL, gL, nvec = apply2(VL, uL), apply2(VL, gL), apply2(VL, nvec)
         if NR < M:
-            fR = apply2(_t(ops1d.interp(NR, M)), fR)
-        Fs = sum(0.5 * (fL[x] + fR[x]) * nvec[:, x][:, None] for x in range(3))   # [F, nvar, M+1, M+1]
+            VR = _t(ops1d.interp(NR, M))
+            uR, gR = apply2(VR, uR), apply2(VR, gR)
+        fL = viscous_flux(uL.transpose(0, 1), gL.permute(1, 2, 0, 3, 4), gas, tr)   # [3, nvar, F, M+1, M+1]
+        fR = viscous_flux(uR.transpose(0, 1), gR.permute(1, 2, 0, 3, 4), gas, tr)
+        Fs = sum(0.5 * (fL[x] + fR[x]) * nvec[:, x] for x in range(3)).transpose(0, 1)   # [F, nvar, M+1, M+1]
         FL = apply2(_t(ops1d.project(M, NL)), Fs) if NL < M else Fs
         FR = apply2(_t(ops1d.project(M, NR)), Fs) if NR < M else Fs
         FR = -to_right(FR, o)
