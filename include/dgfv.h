@@ -308,6 +308,47 @@ dgfv_status dg_transfer_degree(const dgfv_mesh* from, const dgfv_mesh* to, const
 dgfv_status dgfv_set_face_fusion(dgfv_mesh* mesh, int enable);
 
 /*
+ * Viscous multi-species Navier-Stokes terms (Section 2, eq. visc_stress,
+ * eq. fourier_law, eq. enthalpy_flux, eq. fickian_law, eq. mix_lambda_mu;
+ * Section 3.1.1, eq. lift_weak, eq. semidiscrete_lift, eq. lift_flux,
+ * eq. visc_flux; Section 3.2.2 for degree jumps).
+ *
+ * dgfv_set_transport sets constant species transport coefficients and turns
+ * the viscous terms on for every later dg_rhs, dg_rk_stage and dg_rk_step on
+ * the mesh (tr = NULL turns them off).  Index 0 is the species weighted by Y1
+ * (the only one for n_var = 5), index 1 the other: mixture mu and Pr mix
+ * linearly in Y, lambda = mu c_p / Pr; D are the Fickian diffusivities, with
+ * the mass-conserving correction (the species fluxes sum to zero).  One
+ * species takes its temperature from p / rho with a unit gas constant, which
+ * cancels in the heat flux.  The first call allocates 3 n_var n_node doubles
+ * (the lifted gradient), n_var n_node (the viscous rate) and one side buffer
+ * (synchronous; DGFV_ERR_OOM when they do not fit); changing the setting
+ * drops the mesh's cached graphs.  mu, D >= 0 and Pr > 0, finite, else
+ * DGFV_ERR_ARG.
+ *
+ * The rate becomes R = (1 - alpha) R^c_DG + alpha R^c_FV + R^v: the BR1
+ * operator R^v acts on every element, the sub-cell blending on the
+ * convective part.  R^v: the conservative state is lifted to its gradient g
+ * (the face value u* = (u^- + u^+)/2 formed on the lower degree of a degree
+ * jump and interpolated to the higher side); the viscous fluxes of (u, g)
+ * meet at each face in their arithmetic mean on the higher degree, the lower
+ * side receiving the projection.  Face fusion is off while the viscous terms
+ * are on; the FV-stored calls (dg_rhs_fv and its stages) and the adjoint
+ * return DGFV_ERR_UNSUPPORTED.
+ *
+ * dg_lift writes the lifted gradient of u_d alone, g_d [3][n_var][n_node]
+ * (d u_v / d x_x at component x * n_var + v), for inspection; DGFV_ERR_ARG
+ * when no transport coefficients are set.  Enqueued on `stream`.
+ */
+typedef struct {
+  double mu[2];            /* dynamic viscosities      */
+  double Pr[2];            /* Prandtl numbers          */
+  double D[2];             /* diffusion coefficients   */
+} dgfv_transport;
+dgfv_status dgfv_set_transport(dgfv_mesh* mesh, const dgfv_transport* tr);
+dgfv_status dg_lift(const dgfv_mesh* mesh, const double* u_d, double* g_d, void* stream);
+
+/*
  * Autotuning (not part of the method).  The element kernel has two tile
  * shapes at degrees N <= 5: about 512 or about 256 lanes per workgroup (the
  * number of elements per workgroup).  dgfv_autotune evaluates the RHS once on
@@ -391,7 +432,8 @@ enum { DGFV_KERNEL_ELEMENT = 0,     /* volume + lift + blend (+ RK update), all 
        DGFV_KERNEL_INDICATOR = 4,
        DGFV_KERNEL_VJP = 5,
        DGFV_KERNEL_FV_FACE = 6,     /* fluxes of the faces with a blended side                   */
-       DGFV_KERNEL_COUNT = 7 };
+       DGFV_KERNEL_VISCOUS = 7,     /* viscous terms: lifting, viscous face fluxes and rates     */
+       DGFV_KERNEL_COUNT = 8 };
 dgfv_status dgfv_profile_enable(dgfv_mesh* mesh, int enable);
 dgfv_status dgfv_profile_read(dgfv_mesh* mesh, int kernel, double* total_ms, int64_t* launches);
 

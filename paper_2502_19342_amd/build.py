@@ -34,6 +34,8 @@ def _jobs():
     for n in range(1, 8):
         jobs.append((["-x", "hip", os.path.join(CSRC, "dgfv_degree.hip"), f"-DDGFV_N={n}"] + DEVICE_ONLY,
                      os.path.join(OUT_DIR, f"dgfv_degree_{n}.o")))
+        jobs.append((["-x", "hip", os.path.join(CSRC, "dgfv_viscous.hip"), f"-DDGFV_N={n}"] + DEVICE_ONLY,
+                     os.path.join(OUT_DIR, f"dgfv_viscous_{n}.o")))
     for name in ("dgfv_faces", "dgfv_lists", "dgfv_state", "dgfv_fvstored"):
         jobs.append((["-x", "hip", os.path.join(CSRC, name + ".hip")] + DEVICE_ONLY,
                      os.path.join(OUT_DIR, name + ".o")))

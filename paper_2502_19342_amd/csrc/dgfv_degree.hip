@@ -201,6 +201,7 @@ element_kernel(MeshView m, ParamsDev prm, const int32_t* __restrict__ elist, int
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         R[v] = m.rfv[v * m.n_node + base];
+        if (m.rvisc) R[v] += m.rvisc[v * m.n_node + base];
         k_old[v] = stage > 1 ? k[v * m.n_node + base] : 0.0;
       }
       store(R, k_old);
@@ -426,6 +427,10 @@ element_kernel(MeshView m, ParamsDev prm, const int32_t* __restrict__ elist, int
   if (al > 0.0) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) R[v] = (1.0 - al) * R[v] + al * m.rfv[v * m.n_node + base];
+  }
+  if (m.rvisc) {                           // viscous rate of every element, outside the blend
+#pragma unroll
+    for (int v = 0; v < NV; ++v) R[v] += m.rvisc[v * m.n_node + base];
   }
   store(R, k_old);
 }

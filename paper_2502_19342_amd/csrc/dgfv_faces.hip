@@ -861,6 +861,199 @@ face_vjp_conforming_kernel(MeshView m, ParamsDev prm, const int32_t* __restrict_
   }
 }
 
+// ---------------------------------------------------------------------------
+// Viscous face terms (Section 3.1.1, eq. lift_flux and eq. visc_flux; Section
+// 3.2.2 for degree jumps).  Both write m.vside, the side layout of fside.
+//  lift:    u* = (u^- + u^+) / 2 at every node of both sides; at a degree jump
+//           the higher side's trace is projected to the lower degree, u* is
+//           formed there and the higher side receives its interpolation.
+//  viscous: F^v* = (F^v(u^-, g^-) + F^v(u^+, g^+)) / 2 . n s with the face
+//           normal (left outward) on the higher degree; the left side receives
+//           +F^v*, the right side -F^v*, the lower side of a degree jump its
+//           projection.
+// Same-degree faces: one lane per face node, several faces per workgroup
+// (per-degree face lists); degree jumps: one face per one-wavefront workgroup.
+// ---------------------------------------------------------------------------
+template <int N, int NV>
+__global__ void __launch_bounds__(CONF_THREADS)
+lift_face_conf_kernel(MeshView m, const int32_t* __restrict__ flist, int fcount, const double* __restrict__ u) {
+  constexpr int NP = N + 1, NP2 = NP * NP, FPB = CONF_THREADS / NP2;
+  const int t = threadIdx.x;
+  const int slot = t / NP2, r = t - slot * NP2;
+  if (slot >= FPB) return;
+  const int fi = blockIdx.x * FPB + slot;
+  if (fi >= fcount) return;
+  const int32_t* fc = m.faces + 5 * flist[fi];
+  const int eL = fc[0], sideL = fc[1], eR = fc[2], sideR = fc[3], o = fc[4];
+  const int p = r % NP, q = r / NP;
+  int pp, qq;
+  orient_map(o, p, q, NP, pp, qq);
+  const int64_t gL = m.elem_offset[eL] + side_node(sideL, p, q, NP);
+  const int64_t gR = m.elem_offset[eR] + side_node(sideR, pp, qq, NP);
+  double* bL = m.vside + m.side_off[eL];
+  double* bR = m.vside + m.side_off[eR];
+  double us[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) us[v] = 0.5 * (u[v * m.n_node + gL] + u[v * m.n_node + gR]);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    bL[(sideL * NV + v) * NP2 + q * NP + p] = us[v];
+    bR[(sideR * NV + v) * NP2 + qq * NP + pp] = us[v];
+  }
+}
+
+template <int NV>
+__global__ void __launch_bounds__(FACE_THREADS)
+lift_face_mixed_kernel(MeshView m, const double* __restrict__ u) {
+  __shared__ double B0[NV * GRID];
+  __shared__ double B1[NV * GRID];
+  __shared__ double B2[NV * GRID];
+  __shared__ double B3[NV * GRID];
+  const int fi = blockIdx.x;
+  if (fi >= m.face_mixed_count) return;
+  const int32_t* fc = m.faces + 5 * m.face_mixed[fi];
+  const int eL = fc[0], sideL = fc[1], eR = fc[2], sideR = fc[3], o = fc[4];
+  const int NL = m.degree[eL], NR = m.degree[eR];
+  const bool left_low = NL < NR;
+  const int lo = left_low ? NL : NR, hi = left_low ? NR : NL;
+  const int nlo = lo + 1, nhi = hi + 1;
+  gather_trace<NV>(m, u, eL, sideL, o, false, NL + 1, B0);
+  gather_trace<NV>(m, u, eR, sideR, o, true, NR + 1, B1);
+  wave_sync();
+  const double* H = left_low ? B1 : B0;
+  const double* L = left_low ? B0 : B1;
+  map2d_sep_to<NV>(H, B3, B2, m.ops + m.tab.project[hi][lo], nlo, nhi);   // higher trace on the lower degree
+  wave_sync();
+  for (int t = threadIdx.x; t < nlo * nlo; t += blockDim.x)
+    for (int v = 0; v < NV; ++v) B2[v * GRID + t] = 0.5 * (B2[v * GRID + t] + L[v * GRID + t]);
+  wave_sync();
+  double* bL = m.vside + m.side_off[eL];
+  double* bR = m.vside + m.side_off[eR];
+  if (left_low) {
+    write_side<NV>(bL, B2, sideL, o, false, nlo, 1.0);
+    map2d_sep_side<NV>(bR, B2, B3, m.ops + m.tab.interp[lo][hi], nhi, nlo, sideR, o, true, 1.0);
+  } else {
+    write_side<NV>(bR, B2, sideR, o, true, nlo, 1.0);
+    map2d_sep_side<NV>(bL, B2, B3, m.ops + m.tab.interp[lo][hi], nhi, nlo, sideL, o, false, 1.0);
+  }
+}
+
+template <int N, int NV>
+__global__ void __launch_bounds__(CONF_THREADS)
+visc_face_conf_kernel(MeshView m, const int32_t* __restrict__ flist, int fcount, const double* __restrict__ u) {
+  constexpr int NP = N + 1, NP2 = NP * NP, FPB = CONF_THREADS / NP2;
+  const int t = threadIdx.x;
+  const int slot = t / NP2, r = t - slot * NP2;
+  if (slot >= FPB) return;
+  const int fi = blockIdx.x * FPB + slot;
+  if (fi >= fcount) return;
+  const int f = flist[fi];
+  const int32_t* fc = m.faces + 5 * f;
+  const int eL = fc[0], sideL = fc[1], eR = fc[2], sideR = fc[3], o = fc[4];
+  const int p = r % NP, q = r / NP;
+  int pp, qq;
+  orient_map(o, p, q, NP, pp, qq);
+  const int64_t gL = m.elem_offset[eL] + side_node(sideL, p, q, NP);
+  const int64_t gR = m.elem_offset[eR] + side_node(sideR, pp, qq, NP);
+  const double* nrm = m.face_norm + m.face_norm_off[f];
+  double F[NV];
+  {
+    double uL[NV], uR[NV], gL_[3][NV], gR_[3][NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      uL[v] = u[v * m.n_node + gL];
+      uR[v] = u[v * m.n_node + gR];
+    }
+#pragma unroll
+    for (int x = 0; x < 3; ++x)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        gL_[x][v] = m.grad[(x * NV + v) * m.n_node + gL];
+        gR_[x][v] = m.grad[(x * NV + v) * m.n_node + gR];
+      }
+    const double n0 = nrm[r], n1 = nrm[NP2 + r], n2 = nrm[2 * NP2 + r];
+    double f[3][NV];
+    viscous_flux<NV>(uL, gL_, m.gas, m.visc, f);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) F[v] = f[0][v] * n0 + f[1][v] * n1 + f[2][v] * n2;
+    viscous_flux<NV>(uR, gR_, m.gas, m.visc, f);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) F[v] = 0.5 * (F[v] + (f[0][v] * n0 + f[1][v] * n1 + f[2][v] * n2));
+  }
+  double* bL = m.vside + m.side_off[eL];
+  double* bR = m.vside + m.side_off[eR];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    bL[(sideL * NV + v) * NP2 + q * NP + p] = F[v];
+    bR[(sideR * NV + v) * NP2 + qq * NP + pp] = -F[v];
+  }
+}
+
+template <int NV>
+__global__ void __launch_bounds__(FACE_THREADS)
+visc_face_mixed_kernel(MeshView m, const double* __restrict__ u) {
+  constexpr int NW = 4 * NV;          // fields per face point: u, then g_x for x = 0, 1, 2
+  __shared__ double SL[NW * GRID];
+  __shared__ double SR[NW * GRID];
+  __shared__ double ST[NW * GRID];
+  __shared__ double SM[NW * GRID];
+  const int fi = blockIdx.x;
+  if (fi >= m.face_mixed_count) return;
+  const int f = m.face_mixed[fi];
+  const int32_t* fc = m.faces + 5 * f;
+  const int eL = fc[0], sideL = fc[1], eR = fc[2], sideR = fc[3], o = fc[4];
+  const int NL = m.degree[eL], NR = m.degree[eR];
+  const bool left_low = NL < NR;
+  const int lo = left_low ? NL : NR, M = left_low ? NR : NL;
+  const int nlo = lo + 1, nM = M + 1, n2 = nM * nM;
+  gather_trace<NV>(m, u, eL, sideL, o, false, NL + 1, SL);
+  gather_trace<NV>(m, u, eR, sideR, o, true, NR + 1, SR);
+  for (int x = 0; x < 3; ++x) {
+    gather_trace<NV>(m, m.grad + (size_t)x * NV * m.n_node, eL, sideL, o, false, NL + 1, SL + (1 + x) * NV * GRID);
+    gather_trace<NV>(m, m.grad + (size_t)x * NV * m.n_node, eR, sideR, o, true, NR + 1, SR + (1 + x) * NV * GRID);
+  }
+  wave_sync();
+  map2d_sep_to<NW>(left_low ? SL : SR, ST, SM, m.ops + m.tab.interp[lo][M], nM, nlo);   // lower side on degree M
+  wave_sync();
+  const double* A = left_low ? SM : SL;
+  const double* B = left_low ? SR : SM;
+  const double* nrm = m.face_norm + m.face_norm_off[f];
+  double* bL = m.vside + m.side_off[eL];
+  double* bR = m.vside + m.side_off[eR];
+  double* Fb = ST;                    // the flux on the degree-M grid, for the projection
+  for (int t = threadIdx.x; t < n2; t += blockDim.x) {
+    double ua[NV], ub[NV], ga[3][NV], gb[3][NV], fa[3][NV], fb[3][NV], F[NV];
+    for (int v = 0; v < NV; ++v) {
+      ua[v] = A[v * GRID + t];
+      ub[v] = B[v * GRID + t];
+      for (int x = 0; x < 3; ++x) {
+        ga[x][v] = A[((1 + x) * NV + v) * GRID + t];
+        gb[x][v] = B[((1 + x) * NV + v) * GRID + t];
+      }
+    }
+    viscous_flux<NV>(ua, ga, m.gas, m.visc, fa);
+    viscous_flux<NV>(ub, gb, m.gas, m.visc, fb);
+    const double n0 = nrm[t], n1 = nrm[n2 + t], n2v = nrm[2 * n2 + t];
+    for (int v = 0; v < NV; ++v) {
+      F[v] = 0.5 * ((fa[0][v] * n0 + fa[1][v] * n1 + fa[2][v] * n2v) + (fb[0][v] * n0 + fb[1][v] * n1 + fb[2][v] * n2v));
+      Fb[v * GRID + t] = F[v];
+    }
+    const int p = t % nM, q = t / nM;
+    if (left_low) {
+      int pp, qq;
+      orient_map(o, p, q, nM, pp, qq);
+      for (int v = 0; v < NV; ++v) bR[(sideR * NV + v) * n2 + qq * nM + pp] = -F[v];
+    } else {
+      for (int v = 0; v < NV; ++v) bL[(sideL * NV + v) * n2 + q * nM + p] = F[v];
+    }
+  }
+  wave_sync();
+  if (left_low)
+    map2d_sep_side<NV>(bL, Fb, SL, m.ops + m.tab.project[M][lo], nlo, nM, sideL, o, false, 1.0);
+  else
+    map2d_sep_side<NV>(bR, Fb, SR, m.ops + m.tab.project[M][lo], nlo, nM, sideR, o, true, -1.0);
+}
+
 }  // namespace
 
 template <int NV>
@@ -955,6 +1148,43 @@ hipError_t launch_face_class(const MeshView& m, const ParamsDev& p, const double
   if (m.n_face == 0) return hipSuccess;
   return m.nvar == 5 ? launch_face_class_t<5>(m, p, u, alpha, cls, read_trace, s)
                      : launch_face_class_t<6>(m, p, u, alpha, cls, read_trace, s);
+}
+
+template <int NV, bool LIFT>
+static hipError_t launch_visc_faces_t(const MeshView& m, const double* u, hipStream_t s) {
+  for (int N = 1; N <= MAXN; ++N) {
+    const int cnt = m.face_conf_count[N];
+    if (cnt == 0) continue;
+    const int np2 = (N + 1) * (N + 1), fpb = CONF_THREADS / np2;
+    const dim3 grid((cnt + fpb - 1) / fpb), block(CONF_THREADS);
+    const int32_t* fl = m.face_conf[N];
+#define DGFV_VF(n)                                                                                        \
+  case n:                                                                                                 \
+    if constexpr (LIFT) hipLaunchKernelGGL((lift_face_conf_kernel<n, NV>), grid, block, 0, s, m, fl, cnt, u); \
+    else hipLaunchKernelGGL((visc_face_conf_kernel<n, NV>), grid, block, 0, s, m, fl, cnt, u);            \
+    break;
+    switch (N) {
+      DGFV_VF(1) DGFV_VF(2) DGFV_VF(3) DGFV_VF(4) DGFV_VF(5) DGFV_VF(6) DGFV_VF(7)
+    }
+#undef DGFV_VF
+    if (hipError_t e = hipGetLastError()) return e;
+  }
+  if (m.face_mixed_count > 0) {
+    if constexpr (LIFT)
+      hipLaunchKernelGGL((lift_face_mixed_kernel<NV>), dim3(m.face_mixed_count), dim3(FACE_THREADS), 0, s, m, u);
+    else
+      hipLaunchKernelGGL((visc_face_mixed_kernel<NV>), dim3(m.face_mixed_count), dim3(FACE_THREADS), 0, s, m, u);
+    if (hipError_t e = hipGetLastError()) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_lift_faces(const MeshView& m, const double* u, hipStream_t s) {
+  return m.nvar == 5 ? launch_visc_faces_t<5, true>(m, u, s) : launch_visc_faces_t<6, true>(m, u, s);
+}
+
+hipError_t launch_visc_faces(const MeshView& m, const double* u, hipStream_t s) {
+  return m.nvar == 5 ? launch_visc_faces_t<5, false>(m, u, s) : launch_visc_faces_t<6, false>(m, u, s);
 }
 
 }  // namespace dgfv

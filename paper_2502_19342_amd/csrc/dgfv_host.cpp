@@ -90,6 +90,18 @@ DegreeOps ops_for(int N) {
   }
 }
 
+ViscousOps viscous_ops_for(int N) {
+  switch (N) {
+    case 1: return viscous_ops_1();
+    case 2: return viscous_ops_2();
+    case 3: return viscous_ops_3();
+    case 4: return viscous_ops_4();
+    case 5: return viscous_ops_5();
+    case 6: return viscous_ops_6();
+    default: return viscous_ops_7();
+  }
+}
+
 }  // namespace
 
 struct dgfv_mesh {
@@ -154,6 +166,13 @@ struct dgfv_mesh {
   mutable double* pmap = nullptr;
   mutable double* pind = nullptr;
 
+  // viscous terms: on once transport coefficients are set; the lifted gradient,
+  // the face values / viscous face fluxes per side and the viscous rate live
+  // in view.grad, view.vside and rvisc
+  bool viscous = false;
+  double* rvisc = nullptr;
+  size_t side_total = 0;                        // doubles of one side buffer (fside, vside)
+
   // kernel timing (mutable: recording does not change the mesh)
   mutable bool profile = false;
   mutable std::array<std::vector<std::pair<hipEvent_t, hipEvent_t>>, DGFV_KERNEL_COUNT> ev;
@@ -185,6 +204,9 @@ struct dgfv_mesh {
     if (fvjbar) (void)hipFree(fvjbar);
     if (pmap) (void)hipFree(pmap);
     if (pind) (void)hipFree(pind);
+    if (view.grad) (void)hipFree(view.grad);
+    if (view.vside) (void)hipFree(view.vside);
+    if (rvisc) (void)hipFree(rvisc);
   }
   template <class T>
   T* keep(T* p) {
@@ -532,6 +554,23 @@ void enqueue_limiter(const dgfv_mesh* m, double* u, const double* alpha, double*
 // fuse: the element kernels of degree >= FUSE_MIN_N evaluate their conforming
 // DG faces themselves (stage 0, or uout != u), and those face classes are not
 // launched.
+// Viscous rate of u into m->rvisc (Section 3.1.1, Section 3.2.2): the BR1 face
+// values, the lifted gradient, the viscous face fluxes, the volume terms.
+void enqueue_viscous(const dgfv_mesh* m, const double* u, hipStream_t s) {
+  const MeshView& v = m->view;
+  const std::vector<int> degs = degrees_present(m);
+  Timed t(m, DGFV_KERNEL_VISCOUS, s);
+  hip_check(launch_lift_faces(v, u, s), "lift face launch");
+  fork_join(m, s, degs, [&](int N, hipStream_t ss) {
+    hip_check(viscous_ops_for(N).lift(v, m->d_bucket[N], (int)m->bucket[N].size(), u, ss), "lift launch");
+  });
+  hip_check(launch_visc_faces(v, u, s), "viscous face launch");
+  fork_join(m, s, degs, [&](int N, hipStream_t ss) {
+    hip_check(viscous_ops_for(N).volume(v, m->d_bucket[N], (int)m->bucket[N].size(), u, m->rvisc, ss),
+              "viscous volume launch");
+  });
+}
+
 void enqueue_rhs_impl(const dgfv_mesh* m, const ParamsDev& p, const double* u, double* uout,
                       const double* alpha, double* ut, double* k, int stage, double dt, hipStream_t s,
                       bool trace_in = false, bool trace_out = false, bool fuse = false) {
@@ -539,6 +578,7 @@ void enqueue_rhs_impl(const dgfv_mesh* m, const ParamsDev& p, const double* u, d
   const double A = stage > 0 ? RK_A[stage - 1] : 0.0;
   const double B = stage > 0 ? RK_B[stage - 1] : 0.0;
   const std::vector<int> degs = degrees_present(m);
+  if (m->viscous) enqueue_viscous(m, u, s);
   if (alpha) {
     Timed t(m, DGFV_KERNEL_FV_MEANS, s);
     hip_check(launch_blend_list(v, alpha, s), "blended list launch");
@@ -565,9 +605,11 @@ void enqueue_rhs_impl(const dgfv_mesh* m, const ParamsDev& p, const double* u, d
   }
   {
     Timed t(m, DGFV_KERNEL_ELEMENT, s);
+    MeshView ve = v;
+    if (m->viscous) ve.rvisc = m->rvisc;
     fork_join(m, s, degs, [&](int N, hipStream_t ss) {
       const int flags = (trace_out ? ELEM_WRITE_TRACE : 0) | (fuse && N >= FUSE_MIN_N ? ELEM_FUSE_FACES : 0);
-      hip_check(ops_for(N).element(v, p, m->d_bucket[N], (int)m->bucket[N].size(), u, uout, alpha, ut, k,
+      hip_check(ops_for(N).element(ve, p, m->d_bucket[N], (int)m->bucket[N].size(), u, uout, alpha, ut, k,
                                    stage, dt, A, B, m->elem_variant[N], flags, ss),
                 "element launch");
     });
@@ -687,7 +729,7 @@ dgfv_status enqueue_rhs(const dgfv_mesh* m, const dgfv_params* prm, const double
                         const double* alpha, double* ut, double* k, int stage, double dt,
                         hipStream_t s) {
   try {
-    const bool fuse = stage == 0 && m->fuse_faces && has_fused_degree(m);
+    const bool fuse = stage == 0 && m->fuse_faces && !m->viscous && has_fused_degree(m);
     enqueue_rhs_impl(m, to_dev(prm), u, const_cast<double*>(u), alpha, ut, k, stage, dt, s, false, false, fuse);
   } catch (const HipError& e) {
     return fail(DGFV_ERR_HIP, e.what());
@@ -757,7 +799,7 @@ bool capturing(hipStream_t s) {
 }
 
 bool use_fused_stages(const dgfv_mesh* m, int first, int last, hipStream_t s) {
-  if (!m->fuse_faces || last <= first || !has_fused_degree(m)) return false;
+  if (!m->fuse_faces || m->viscous || last <= first || !has_fused_degree(m)) return false;
   if (!m->u_alt) {
     if (capturing(s)) return false;
     double* p = nullptr;
@@ -805,6 +847,7 @@ dgfv_status guarded(const dgfv_mesh* m, hipStream_t s, F&& call) {
 
 // Which adjoint paths run (see dg_rhs_vjp).
 dgfv_status vjp_paths_enabled(const dgfv_mesh* m, const double* alpha) {
+  if (m->viscous) return fail(DGFV_ERR_UNSUPPORTED, "dg_rhs_vjp: the adjoint of the viscous terms is not built");
 #ifndef DGFV_CPU_ADJOINT_ALL_PATHS
   // The adjoint of FV-blended elements and of degree-jump faces faulted the GPU
   // once with no cause found: the same kernels run clean and exact in the CPU
@@ -1078,6 +1121,7 @@ dgfv_status dgfv_mesh_create(const dgfv_mesh_desc* d, dgfv_mesh** out) {
     v.face_norm = m->keep(dev_upload(fnorm));
     v.side_off = m->keep(dev_upload(side_off));
     v.fside = m->keep(dev_alloc<double>(stot));
+    m->side_total = (size_t)stot;
     v.trace = m->keep(dev_alloc<double>(stot / 3));    // sides 0 and 1 of every element
     v.fvside = m->keep(dev_alloc<double>((size_t)m->K * 6 * m->nvar * NFV * NFV));
     v.ubar = m->keep(dev_alloc<double>((size_t)m->K * m->nvar * NFV * NFV * NFV));
@@ -1417,6 +1461,7 @@ dgfv_status dg_rhs_fv(const dgfv_mesh* m, const dgfv_params* prm, const double* 
   if (!m || !u || !ufv || !fv || !ut || !utfv) return fail(DGFV_ERR_ARG, "NULL argument");
   if (u == ut || ufv == utfv) return fail(DGFV_ERR_ARG, "inputs and outputs must not overlap");
   if (dgfv_status st = check_params(m, prm)) return st;
+  if (m->viscous) return fail(DGFV_ERR_UNSUPPORTED, "FV-stored elements with viscous terms are not built");
   hipStream_t s = (hipStream_t)stream;
   if (!m->fvghost && capturing(s)) return fail(DGFV_ERR_ARG, "the first call with FV-stored elements allocates: not under capture");
   return guarded(m, s, [&] {
@@ -1437,6 +1482,7 @@ dgfv_status dg_rk_stage_fv(const dgfv_mesh* m, const dgfv_params* prm, int stage
   if (!std::isfinite(dt)) return fail(DGFV_ERR_ARG, "dt must be finite");
   if (u == k || ufv == kfv) return fail(DGFV_ERR_ARG, "states and registers must not overlap");
   if (dgfv_status st = check_params(m, prm)) return st;
+  if (m->viscous) return fail(DGFV_ERR_UNSUPPORTED, "FV-stored elements with viscous terms are not built");
   hipStream_t s = (hipStream_t)stream;
   if (!m->fvghost && capturing(s)) return fail(DGFV_ERR_ARG, "the first call with FV-stored elements allocates: not under capture");
   return guarded(m, s, [&] {
@@ -1455,6 +1501,7 @@ dgfv_status dg_rk_step_fv(const dgfv_mesh* m, const dgfv_params* prm, double dt,
   if (!std::isfinite(dt)) return fail(DGFV_ERR_ARG, "dt must be finite");
   if (u == k || ufv == kfv) return fail(DGFV_ERR_ARG, "states and registers must not overlap");
   if (dgfv_status st = check_params(m, prm)) return st;
+  if (m->viscous) return fail(DGFV_ERR_UNSUPPORTED, "FV-stored elements with viscous terms are not built");
   hipStream_t s = (hipStream_t)stream;
   if (!m->fvghost && capturing(s)) return fail(DGFV_ERR_ARG, "the first call with FV-stored elements allocates: not under capture");
   return guarded(m, s, [&] {
@@ -1494,6 +1541,58 @@ dgfv_status dgfv_set_positivity_limiter(dgfv_mesh* m, int enable) {
   if (enable && m->nvar != 5) return fail(DGFV_ERR_UNSUPPORTED, "the positivity limiter is single-species only");
   m->limiter_on = enable != 0;
   m->drop_graphs();
+  return DGFV_OK;
+}
+
+dgfv_status dgfv_set_transport(dgfv_mesh* m, const dgfv_transport* tr) {
+  if (!m) return fail(DGFV_ERR_ARG, "mesh is NULL");
+  if (!tr) {
+    m->viscous = false;
+    m->drop_graphs();
+    return DGFV_OK;
+  }
+  for (int j = 0; j < 2; ++j) {
+    if (!(tr->mu[j] >= 0.0) || !(tr->D[j] >= 0.0) || !(tr->Pr[j] > 0.0) || !std::isfinite(tr->mu[j]) ||
+        !std::isfinite(tr->D[j]) || !std::isfinite(tr->Pr[j]))
+      return fail(DGFV_ERR_ARG, "dgfv_set_transport: mu, D >= 0 and Pr > 0, finite");
+  }
+  if (!m->view.grad) {
+    double* g = nullptr;
+    double* vs = nullptr;
+    double* rv = nullptr;
+    const size_t plane = (size_t)m->nvar * (size_t)m->n_node;
+    if (hipMalloc((void**)&g, sizeof(double) * 3 * plane) != hipSuccess ||
+        hipMalloc((void**)&vs, sizeof(double) * m->side_total) != hipSuccess ||
+        hipMalloc((void**)&rv, sizeof(double) * plane) != hipSuccess) {
+      (void)hipGetLastError();
+      if (g) (void)hipFree(g);
+      if (vs) (void)hipFree(vs);
+      return fail(DGFV_ERR_OOM, "dgfv_set_transport: device memory for the viscous terms");
+    }
+    m->view.grad = g;
+    m->view.vside = vs;
+    m->rvisc = rv;
+  }
+  m->view.visc = ViscDev{tr->mu[0], tr->mu[1], tr->Pr[0], tr->Pr[1], tr->D[0], tr->D[1]};
+  m->viscous = true;
+  m->drop_graphs();
+  return DGFV_OK;
+}
+
+dgfv_status dg_lift(const dgfv_mesh* m, const double* u, double* g, void* stream) {
+  if (!m || !u || !g) return fail(DGFV_ERR_ARG, "NULL argument");
+  if (!m->viscous) return fail(DGFV_ERR_ARG, "dg_lift: no transport coefficients set (dgfv_set_transport)");
+  const hipStream_t s = (hipStream_t)stream;
+  try {
+    MeshView v = m->view;
+    v.grad = g;                                // the lift kernels write the caller's buffer
+    hip_check(launch_lift_faces(v, u, s), "lift face launch");
+    for (int N = 1; N <= MAXN; ++N)
+      if (!m->bucket[N].empty())
+        hip_check(viscous_ops_for(N).lift(v, m->d_bucket[N], (int)m->bucket[N].size(), u, s), "lift launch");
+  } catch (const HipError& e) {
+    return fail(DGFV_ERR_HIP, e.what());
+  }
   return DGFV_OK;
 }
 

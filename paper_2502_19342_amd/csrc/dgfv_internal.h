@@ -33,6 +33,12 @@ struct GasDev {
   double cp0, cv0, cp1, cv1;  // two species (Y1 weights species 0)
 };
 
+// Constant species transport coefficients of the viscous terms (species 1,
+// weighted by Y1, first; one species uses mu0, Pr0).
+struct ViscDev {
+  double mu0, mu1, Pr0, Pr1, D0, D1;
+};
+
 struct ParamsDev {
   int volume_flux, face_flux_dg, face_flux_fv;
   int ind_vars;
@@ -107,6 +113,12 @@ struct MeshView {
   const double* ops;            // operator tables
   OpTables tab;
   GasDev gas;
+  // viscous terms (allocated when transport coefficients are set)
+  ViscDev visc;
+  double* grad;                 // BR1-lifted gradient of u, [3][nvar][n_node]
+  double* vside;                // per element side: the BR1 face value u*, then the viscous
+                                // face flux (outward), same layout as fside
+  const double* rvisc;          // viscous rate [nvar][n_node] that the element kernel adds, or null
 };
 
 // ---- launchers (defined in the .hip translation units) ----------------------
@@ -158,6 +170,23 @@ struct DegreeOps {
                           const double* fv_old, const double* fv_new, hipStream_t s);
   int element_variants;   // tile shapes of the element kernel at this degree
 };
+// Per-degree launchers of the viscous terms (dgfv_viscous.hip), over the
+// degree bucket `elist[0 .. count)`:
+//  lift    m.grad = BR1-lifted gradient of u, from the face values in m.vside
+//  volume  rv = -(1/J) [viscous volume term + viscous face fluxes of m.vside]
+struct ViscousOps {
+  hipError_t (*lift)(const MeshView& m, const int32_t* elist, int count, const double* u, hipStream_t s);
+  hipError_t (*volume)(const MeshView& m, const int32_t* elist, int count, const double* u, double* rv,
+                       hipStream_t s);
+};
+ViscousOps viscous_ops_1();
+ViscousOps viscous_ops_2();
+ViscousOps viscous_ops_3();
+ViscousOps viscous_ops_4();
+ViscousOps viscous_ops_5();
+ViscousOps viscous_ops_6();
+ViscousOps viscous_ops_7();
+
 DegreeOps degree_ops_1();
 DegreeOps degree_ops_2();
 DegreeOps degree_ops_3();
@@ -192,6 +221,12 @@ bool face_class_present(const MeshView& m, const double* alpha, int cls);
 hipError_t launch_face_class(const MeshView& m, const ParamsDev& p, const double* u, const double* alpha,
                              int cls, bool read_trace, hipStream_t s);
 
+// Viscous face terms of all faces (dgfv_faces.hip): the BR1 face value u* of
+// every element side into m.vside, formed on the lower degree of a degree
+// jump; then the arithmetic-mean viscous flux from u and m.grad on the higher
+// degree, each side receiving its outward part at its own degree.
+hipError_t launch_lift_faces(const MeshView& m, const double* u, hipStream_t s);
+hipError_t launch_visc_faces(const MeshView& m, const double* u, hipStream_t s);
 hipError_t launch_faces_vjp(const MeshView& m, const ParamsDev& p, const double* u, const double* alpha,
                             hipStream_t s);
 

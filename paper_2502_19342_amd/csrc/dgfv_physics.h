@@ -628,4 +628,69 @@ __device__ __forceinline__ int side_node(int s, int p, int q, int n) {
   }
 }
 
+// Viscous fluxes F^v_x (x = 0, 1, 2) at one point from the state u and its
+// gradient gr[x][v] = d u_v / d x_x (Section 2): with the flux on the
+// left-hand side, F^v_x = -(0, tau_x., (tau v)_x - q_h,x - q_d,x, -J_1,x),
+// tau = mu (grad v + grad v^T - 2/3 div v I), q_h = -lambda grad T, and for
+// two species J_1 = -rho grad Y1 (D_1 Y2 + D_2 Y1) = -J_2 (Fick's law with
+// the mass-conserving correction) and q_d = (c_p,1 - c_p,2) T J_1.  Velocity,
+// temperature and mass-fraction gradients follow from grad u by the chain
+// rule.  One species: T = (gamma - 1) e_int with unit gas constant, which
+// cancels in lambda grad T = mu c_p grad T / Pr.
+template <int NV>
+__device__ __forceinline__ void viscous_flux(const double (&u)[NV], const double (&gr)[3][NV], const GasDev& gas,
+                                             const ViscDev& tr, double (&f)[3][NV]) {
+  const double ir = 1.0 / u[0];
+  const double w[3] = {u[1] * ir, u[2] * ir, u[3] * ir};
+  const double es = u[4] * ir;
+  const double eint = es - 0.5 * (w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+  double gw[3][3];                         // gw[x][i] = d v_i / d x_x
+#pragma unroll
+  for (int x = 0; x < 3; ++x)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) gw[x][i] = (gr[x][1 + i] - w[i] * gr[x][0]) * ir;
+  double cv, cp, mu, Pr, Y = 0.0, dcv = 0.0, dcp = 0.0, Dm = 0.0;
+  if constexpr (NV == 6) {
+    Y = u[5] * ir;
+    const double Y2 = 1.0 - Y;
+    cv = Y * gas.cv0 + Y2 * gas.cv1;
+    cp = Y * gas.cp0 + Y2 * gas.cp1;
+    mu = Y * tr.mu0 + Y2 * tr.mu1;
+    Pr = Y * tr.Pr0 + Y2 * tr.Pr1;
+    dcv = gas.cv0 - gas.cv1;
+    dcp = gas.cp0 - gas.cp1;
+    Dm = tr.D0 * Y2 + tr.D1 * Y;
+  } else {
+    cv = 1.0 / (gas.gamma - 1.0);
+    cp = gas.gamma * cv;
+    mu = tr.mu0;
+    Pr = tr.Pr0;
+  }
+  const double T = eint / cv;
+  const double lam = mu * cp / Pr;
+  const double div3 = (2.0 / 3.0) * (gw[0][0] + gw[1][1] + gw[2][2]);
+#pragma unroll
+  for (int x = 0; x < 3; ++x) {
+    double tau[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) tau[i] = mu * (gw[x][i] + gw[i][x] - (i == x ? div3 : 0.0));
+    const double geint = (gr[x][4] - es * gr[x][0]) * ir - (w[0] * gw[x][0] + w[1] * gw[x][1] + w[2] * gw[x][2]);
+    double gT, qd = 0.0;
+    if constexpr (NV == 6) {
+      const double gY = (gr[x][5] - Y * gr[x][0]) * ir;
+      gT = (geint - T * dcv * gY) / cv;
+      const double J1 = -u[0] * gY * Dm;
+      qd = dcp * T * J1;
+      f[x][5] = J1;
+    } else {
+      gT = geint / cv;
+    }
+    f[x][0] = 0.0;
+    f[x][1] = -tau[0];
+    f[x][2] = -tau[1];
+    f[x][3] = -tau[2];
+    f[x][4] = -(tau[0] * w[0] + tau[1] * w[1] + tau[2] * w[2]) - lam * gT + qd;
+  }
+}
+
 }  // namespace dgfv

@@ -40,14 +40,19 @@ class _Params(ctypes.Structure):
                 ("ind_T", ctypes.c_double), ("ind_dT", ctypes.c_double)]
 
 
+class _Transport(ctypes.Structure):
+    _fields_ = [("mu", ctypes.c_double * 2), ("Pr", ctypes.c_double * 2), ("D", ctypes.c_double * 2)]
+
+
 EXPORTED = ("dgfv_mesh_create", "dgfv_mesh_destroy", "dgfv_mesh_info", "dgfv_mesh_node_coords",
             "dg_indicator", "dg_rhs", "dg_rk_stage", "dg_rk_step", "dg_rhs_vjp", "dg_rk_stage_vjp",
             "dg_rk_stage_vjp_noalloc", "dgfv_prim_to_cons", "dg_positivity_limiter",
             "dgfv_set_positivity_limiter", "dgfv_set_launch_mode", "dgfv_set_face_fusion", "dgfv_autotune",
             "dgfv_set_element_shape", "dgfv_check_state", "dg_rhs_fv", "dg_rk_stage_fv", "dg_rk_step_fv",
-            "dg_switch_fv", "dg_p_degrees", "dg_transfer_degree",
+            "dg_switch_fv", "dg_p_degrees", "dg_transfer_degree", "dgfv_set_transport", "dg_lift",
             "dgfv_profile_enable", "dgfv_profile_read", "dgfv_last_error")
-KERNEL_ELEMENT, KERNEL_FACE, KERNEL_FV_MEANS, KERNEL_FV_RESIDUAL, KERNEL_INDICATOR, KERNEL_VJP, KERNEL_FV_FACE = range(7)
+(KERNEL_ELEMENT, KERNEL_FACE, KERNEL_FV_MEANS, KERNEL_FV_RESIDUAL, KERNEL_INDICATOR, KERNEL_VJP, KERNEL_FV_FACE,
+ KERNEL_VISCOUS) = range(8)
 LAUNCH_SERIAL, LAUNCH_BRANCHES, LAUNCH_GRAPH = range(3)
 
 
@@ -81,6 +86,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                  ctypes.POINTER(ctypes.c_int8), P]
     lib.dg_transfer_degree.argtypes = [P, P, P, P, P]
     lib.dgfv_set_element_shape.argtypes = [P, c_int, c_int]
+    lib.dgfv_set_transport.argtypes = [P, ctypes.POINTER(_Transport)]
+    lib.dg_lift.argtypes = [P, P, P, P]
     lib.dgfv_autotune.argtypes = [P, ctypes.POINTER(_Params), P, P, ctypes.POINTER(ctypes.c_double), P]
     lib.dgfv_profile_enable.argtypes = [P, c_int]
     lib.dgfv_profile_read.argtypes = [P, c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
@@ -157,8 +164,21 @@ class Mesh:
     @classmethod
     def from_workload(cls, wl) -> "Mesh":
         m = wl.mesh
-        return cls(m.degree, m.corners, m.faces, wl.n_var, wl.n_fv, wl.metric_degree, wl.gamma,
+        mesh = cls(m.degree, m.corners, m.faces, wl.n_var, wl.n_fv, wl.metric_degree, wl.gamma,
                    tuple(wl.kappa), tuple(wl.R))
+        if getattr(wl, "viscous", False):
+            mesh.transport(wl.mu, wl.Pr, wl.D)
+        return mesh
+
+    def transport(self, mu=None, Pr=(0.72, 0.72), D=(0.0, 0.0)) -> None:
+        """Viscous terms with these species coefficients, or off with ``mu=None`` (``dgfv_set_transport``)."""
+        if mu is None:
+            _check(_lib.dgfv_set_transport(self._h, None))
+            self._transport = None
+            return
+        tr = _Transport((ctypes.c_double * 2)(*mu), (ctypes.c_double * 2)(*Pr), (ctypes.c_double * 2)(*D))
+        _check(_lib.dgfv_set_transport(self._h, ctypes.byref(tr)))
+        self._transport = (tuple(mu), tuple(Pr), tuple(D))
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -172,7 +192,10 @@ class Mesh:
         kw = dict(self._args)
         if kw["metric_degree"] > 0:
             kw["metric_degree"] = min(kw["metric_degree"], int(np.min(degree)))
-        return Mesh(degree, self.corners, self.faces, **kw)
+        out = Mesh(degree, self.corners, self.faces, **kw)
+        if getattr(self, "_transport", None) is not None:
+            out.transport(*self._transport)
+        return out
 
     def launch_mode(self, mode: int) -> None:
         """LAUNCH_SERIAL, LAUNCH_BRANCHES (default) or LAUNCH_GRAPH (``dgfv_set_launch_mode``)."""
@@ -258,6 +281,17 @@ def rhs(mesh: Mesh, params: Params, u: torch.Tensor, alpha: torch.Tensor | None 
         out = torch.empty_like(u)
     _check(_lib.dg_rhs(mesh._h, ctypes.byref(params.c()), mesh._state(u, "u"), mesh._alpha(alpha),
                        mesh._state(out, "out"), _stream(stream)))
+    return out
+
+
+def lift(mesh: Mesh, u: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """BR1-lifted gradient ``[3, n_var, n_node]`` of ``u`` (``dg_lift``; viscous meshes)."""
+    if out is None:
+        out = torch.empty((3,) + tuple(u.shape), dtype=u.dtype, device=u.device)
+    if (tuple(out.shape) != (3,) + tuple(u.shape) or not out.is_contiguous() or out.dtype != torch.float64
+            or not out.is_cuda):
+        raise ValueError("out must be a contiguous float64 [3, n_var, n_node] tensor")
+    _check(_lib.dg_lift(mesh._h, mesh._state(u, "u"), ctypes.c_void_p(out.data_ptr()), _stream(stream)))
     return out
 
 

@@ -27,6 +27,8 @@ FLAGS = ["-std=c++17", "-O1", "-g", "-fPIC", "-fno-omit-frame-pointer", "-fsanit
 def _jobs():
     jobs = [(["-x", "c++", os.path.join(CSRC, "dgfv_degree.hip"), f"-DDGFV_N={n}"],
              os.path.join(OUT, f"degree_{n}.o")) for n in range(1, 8)]
+    jobs += [(["-x", "c++", os.path.join(CSRC, "dgfv_viscous.hip"), f"-DDGFV_N={n}"],
+              os.path.join(OUT, f"viscous_{n}.o")) for n in range(1, 8)]
     for name in ("dgfv_faces.hip", "dgfv_lists.hip", "dgfv_state.hip", "dgfv_fvstored.hip"):
         jobs.append((["-x", "c++", os.path.join(CSRC, name)], os.path.join(OUT, name.replace(".hip", ".o"))))
     for name in ("dgfv_host.cpp", "dgfv_ops1d.cpp"):

@@ -57,6 +57,9 @@ def main(src, dst):
     prm = Params(int(pr[0]), int(pr[1]), int(pr[2]), int(pr[3]), float(pr[4]), float(pr[5]))
     if "launch_mode" in z:
         check(lib.dgfv_set_launch_mode(h, int(z["launch_mode"])), "launch mode")
+    if "transport" in z:                       # mu[2], Pr[2], D[2]
+        tr = (ctypes.c_double * 6)(*[float(x) for x in z["transport"]])
+        check(lib.dgfv_set_transport(h, tr), "dgfv_set_transport")
     u = np.ascontiguousarray(z["u"], dtype=np.float64)
     alpha = np.ascontiguousarray(z["alpha"], dtype=np.float64) if "alpha" in z else None
     out = {}
@@ -125,6 +128,10 @@ def main(src, dst):
             check(lib.dg_switch_fv(h, ptr(uu), ptr(uf), ptr(np.ascontiguousarray(z["fv"], dtype=np.float64)),
                                    ptr(np.ascontiguousarray(z["fv_new"], dtype=np.float64)), None), "dg_switch_fv")
             out["switch_dg"], out["switch_fv"] = uu, uf
+        elif call == "lift":
+            g = np.empty((3,) + u.shape)
+            check(lib.dg_lift(h, ptr(u), ptr(g), None), "dg_lift")
+            out["lift"] = g
         elif call == "rhs":
             r = np.empty_like(u)
             check(lib.dg_rhs(h, ctypes.byref(prm), ptr(u), ptr(alpha), ptr(r), None), "dg_rhs")

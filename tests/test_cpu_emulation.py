@@ -267,3 +267,22 @@ def test_cpu_build_p_adaptation():
                       degree_to=want, metric_degree_to=0)
     assert np.array_equal(out["p_degrees"].astype(np.int64), want)
     assert rel_err(torch.as_tensor(out["transfer"]), u2) <= 1e-13
+
+
+@pytest.mark.parametrize("n_var", [5, 6])
+def test_cpu_build_viscous(n_var):
+    # BR1 lifting, viscous rates with degree jumps and blended elements, one RK step
+    import dataclasses
+    from oracle import viscous
+    flux = {} if n_var == 5 else dict(volume_flux=W.VOL_PIROZZOLI, face_dg=W.RIEMANN_LLF)
+    wl = curved_mixed(n=3, nmin=1, nmax=4, n_var=n_var, scramble=17, metric_degree=0, n_fv=5, **flux)
+    wl = dataclasses.replace(wl, mu=(0.02, 0.03), Pr=(0.7, 0.9), D=(0.01, 0.04))
+    c = _case(wl, smooth_state(47, n_var), noise=1e-3, seed=5)
+    c.alpha = seeded_alpha(c.mesh.K, 48, values=(0.0, 0.0, 0.4, 1.0))
+    dt = 0.2 * lsrk.timestep(c.mesh, c.gas, c.u, 0.5, c.alpha)
+    out = cpu_emu.run(wl, c.u.numpy(), ["lift", "rhs", "rk_step"], alpha=c.alpha.numpy(), dt=dt)
+    g = viscous.lift(c.mesh, c.u)
+    assert rel_err(torch.as_tensor(out["lift"]).reshape(3 * n_var, -1), g.reshape(3 * n_var, -1)) <= 1e-12
+    assert rel_err(torch.as_tensor(out["rhs"]), c.oracle_rhs()) <= _tol(c)
+    want = lsrk.step(lambda v: c.f(v, c.alpha), c.u, dt)
+    assert rel_err(torch.as_tensor(out["rk_step"]), want) <= 1e-11
