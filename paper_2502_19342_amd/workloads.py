@@ -280,6 +280,21 @@ def density_wave_exact(x, t):
     return np.stack([rho, one, one, one, one], axis=0)
 
 
+def taylor_green(mach: float = 0.1, gamma: float = 1.4):
+    """Taylor-Green vortex on the unit-period box (k = 2 pi): rho = 1,
+    v = (sin kx cos ky cos kz, -cos kx sin ky cos kz, 0),
+    p = 1/(gamma Ma^2) + (cos 2kx + cos 2ky)(cos 2kz + 2)/16."""
+    k = 2 * np.pi
+
+    def f(x):
+        sx, sy, sz = (np.sin(k * x[..., d]) for d in range(3))
+        cx, cy, cz = (np.cos(k * x[..., d]) for d in range(3))
+        p = 1.0 / (gamma * mach ** 2) + (np.cos(2 * k * x[..., 0]) + np.cos(2 * k * x[..., 1])) \
+            * (np.cos(2 * k * x[..., 2]) + 2.0) / 16.0
+        return np.stack([np.ones_like(p), sx * cy * cz, -cx * sy * cz, np.zeros_like(p), p], axis=0)
+    return f
+
+
 def freestream(x, n_var: int = 5):
     """Uniform state rho = 1, v = (1,1,1), p = 1 (and Y1 = 0.5)."""
     one = np.ones(x.shape[:-1])
@@ -458,6 +473,14 @@ def make_workload(name: str, n: int | None = None, scramble_seed: int | None = N
         return Workload("C5", mesh, 5, kelvin_helmholtz(5), VOL_RANOCHA, RIEMANN_ROE_HH,
                         RIEMANN_LLF, n_fv=8, metric_degree=1, seed=5,
                         ind_T=2.0, ind_dT=1.0, blend_fraction=0.10)
+    if name == "TGV":
+        # viscous Taylor-Green vortex, Re = 1600 on the length 1/(2 pi), Ma = 0.1, Pr = 0.71;
+        # smooth, so every element is DG (no blending)
+        n = n or 64
+        mesh = structured_mesh(n, (0, 0, 0), (1, 1, 1), 7, scramble_seed=scramble_seed)
+        return Workload("TGV", mesh, 5, taylor_green(0.1), VOL_RANOCHA, RIEMANN_ROE_HH,
+                        RIEMANN_LLF, n_fv=8, metric_degree=1, seed=6,
+                        ind_T=-1.0, ind_dT=0.5, mu=(1.0 / (1600.0 * 2 * np.pi), 0.0), Pr=(0.71, 0.71))
     raise KeyError(name)
 
 
