@@ -41,7 +41,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="C5", choices=["C1", "C2", "C3", "C4", "C5"])
+    ap.add_argument("--config", default="C5", choices=["C1", "C2", "C3", "C4", "C5", "TGV"],
+                    help="workload; TGV is the viscous Taylor-Green vortex (64^3, N=7)")
     ap.add_argument("--n", type=int, default=None, help="elements per direction (default: the config's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch", default="branches", choices=["serial", "branches", "graph"],
@@ -268,6 +269,27 @@ def cpu_table(n: int, reps: int = 5):
             "n": n, "reps": reps, "rows": rows}
 
 
+def viscous_bytes(wl, degree: np.ndarray) -> dict:
+    """Algorithmic HBM bytes of the viscous kernels of one RK stage, per kernel.
+
+    Each kernel reads its inputs once and writes its outputs once (n_e nodes and
+    S_e = 6 (N_e + 1)^2 side nodes of element e, nvar variables, 10 geometry
+    terms per node, 3 face-normal components per face node = 1.5 per side node):
+      lift faces:   u at every side node, u* per side node          nvar S + nvar S
+      lift:         u, geometry, u* of the sides; g = grad u         (nvar + 10 + 3 nvar) n + nvar S
+      visc faces:   u, g at every side node, normals; F^v* per side  (4 nvar + 1.5) S + nvar S
+      visc volume:  u, g, geometry, F^v* of the sides; R^v           (5 nvar + 10) n + nvar S
+      element:      R^v read once more                               nvar n
+    """
+    N = degree.astype(np.int64)
+    nv = wl.n_var
+    n = float(((N + 1) ** 3).sum())
+    S = float((6 * (N + 1) ** 2).sum())
+    parts = {"lift_faces": 2 * nv * S, "lift": (4 * nv + 10) * n + nv * S,
+             "visc_faces": (5 * nv + 1.5) * S, "visc": (5 * nv + 10) * n + nv * S, "element_extra": nv * n}
+    return {k: 8.0 * v for k, v in parts.items()}
+
+
 def counter_traffic(cfg: str):
     """HBM bytes per element-kernel launch from the committed rocprofv3 counter runs.
 
@@ -453,7 +475,8 @@ def main():
         torch.cuda.synchronize()
     kt = {name: gm.kernel_time(kid) for name, kid in
           (("element", dgfv.KERNEL_ELEMENT), ("face", dgfv.KERNEL_FACE), ("fv_means", dgfv.KERNEL_FV_MEANS),
-           ("fv_face", dgfv.KERNEL_FV_FACE), ("fv_residual", dgfv.KERNEL_FV_RESIDUAL))}
+           ("fv_face", dgfv.KERNEL_FV_FACE), ("fv_residual", dgfv.KERNEL_FV_RESIDUAL),
+           ("viscous", dgfv.KERNEL_VISCOUS))}
     gm.profile(False)
     if args.fv_stored:
         dg_mask = torch.repeat_interleave(fv == 0, torch.as_tensor(np.diff(gm.elem_offset), device="cuda"))
@@ -463,7 +486,7 @@ def main():
     if not finite:
         print("bench.py: non-finite state after the timed steps", file=sys.stderr)
         sys.exit(1)
-    adjoint = None if (args.no_adjoint or args.fv_stored) else adjoint_ratio(gm, prm, u, dgfv, torch)
+    adjoint = None if (args.no_adjoint or args.fv_stored or wl.viscous) else adjoint_ratio(gm, prm, u, dgfv, torch)
     padapt = p_adapt_timing(gm, prm, u, alpha, dt, dgfv, torch) if args.p_adapt else None
 
     stages = 5 * args.steps
@@ -482,6 +505,17 @@ def main():
                         for s in range(1, 6)])
     achieved = byts / avg_el_s / 1e9
     stage_b = stage_bytes(wl, np.asarray(wl.mesh.degree))
+    visc = None
+    if wl.viscous:
+        vb = viscous_bytes(wl, np.asarray(wl.mesh.degree))
+        v_ms = kt["viscous"][0] / max(1, kt["viscous"][1])
+        v_b = sum(b for k_, b in vb.items() if k_ != "element_extra")
+        visc = {"bytes_per_stage": vb, "viscous_phase_ms": v_ms,
+                "viscous_phase_frac": v_b / (v_ms / 1e3) / 1e9 / PEAK_HBM_GBS,
+                "mu": list(wl.mu), "Pr": list(wl.Pr), "D": list(wl.D),
+                "note": "viscous phase = lift faces, lift, viscous faces, viscous volume (one event pair); "
+                        "the stage roofline adds these bytes to the convective stage's"}
+        stage_b += sum(vb.values())
     rec = {
         "metric": METRIC,
         "value": value,
@@ -498,6 +532,7 @@ def main():
         "config": {
             "workload": f"{args.config}: {wl.mesh.n}^3 periodic hexahedra, degrees "
                         f"{sorted(n_by_deg)}, {n_dof} DOFs x {wl.n_var} variables, "
+                        + ("viscous (BR1), " if wl.viscous else "") +
                         f"{100 * mask.mean():.1f}% of elements FV-blended (N_FV={wl.n_fv}), "
                         f"5-stage 2N RK steps",
             "n_elem": wl.mesh.n_elem, "n_dof": n_dof, "n_var": wl.n_var,
@@ -519,12 +554,14 @@ def main():
                            "bytes_per_stage": stage_b, "ms_per_stage": 1e3 * el / stages,
                            "definition": "algorithmic bytes of one RK stage (read u, k, 10 geometry terms per "
                                          "node; write u, k; read each neighbour trace once) over the measured "
-                                         "time per stage, indicator included"},
+                                         "time per stage, indicator included; a viscous workload adds the "
+                                         "viscous kernels' bytes (the viscous section)"},
         "kernel_ms_per_stage": {kname: v[0] / max(1, v[1]) for kname, v in kt.items()},
         "kernel_ms_source": "live events over the timed steps" if live else "profiled steps after the timed region",
         "kernel_ms_note": "phases in order: fv_means, face, fv_residual, element; fv_face lies inside face "
                           "(beside the DG face fluxes outside --launch serial)",
         "fv_stored": fv_stored_roofline(wl, alpha_h, kt) if args.fv_stored else None,
+        "viscous": visc,
         "p_adapt": padapt,
         "indicator_ms": indicator_ms,
         "indicator_note": "one dg_indicator call over all elements (variables p and rho), timed alone; "
