@@ -272,21 +272,34 @@ def cpu_table(n: int, reps: int = 5):
 def viscous_bytes(wl, degree: np.ndarray) -> dict:
     """Algorithmic HBM bytes of the viscous kernels of one RK stage, per kernel.
 
-    Each kernel reads its inputs once and writes its outputs once (n_e nodes and
-    S_e = 6 (N_e + 1)^2 side nodes of element e, nvar variables, 10 geometry
-    terms per node, 3 face-normal components per face node = 1.5 per side node):
-      lift faces:   u at every side node, u* per side node          nvar S + nvar S
-      lift:         u, geometry, u* of the sides; g = grad u         (nvar + 10 + 3 nvar) n + nvar S
-      visc faces:   u, g at every side node, normals; F^v* per side  (4 nvar + 1.5) S + nvar S
-      visc volume:  u, g, geometry, F^v* of the sides; R^v           (5 nvar + 10) n + nvar S
-      element:      R^v read once more                               nvar n
+    Each kernel reads its inputs once and writes its outputs once: n nodes,
+    nvar variables, 10 geometry terms per node; side nodes S_same on faces
+    between elements of one degree (formed inside the lift and viscous
+    kernels) and S_jump on degree jumps (face kernels), 3 normal components
+    per side node where a kernel forms a same-degree face, 1.5 per side node
+    where a face kernel does:
+      lift faces:  u traces, u* per side                       2 nvar S_jump
+      lift:        u, geometry, g = grad u; the neighbour's u
+                   and the half flux F^v . n_L per same-degree
+                   side node, with the normal; u* at jumps      (4 nvar + 10) n + (2 nvar + 3) S_same + nvar S_jump
+      visc faces:  u, g traces, normals; F^v* per side          (5 nvar + 1.5) S_jump
+      visc volume: u, g, geometry, R^v; the neighbour's half
+                   flux with the normal; F^v* at jumps          (5 nvar + 10) n + (nvar + 3) S_same + nvar S_jump
+      element:     R^v read once more                           nvar n
     """
     N = degree.astype(np.int64)
     nv = wl.n_var
     n = float(((N + 1) ** 3).sum())
-    S = float((6 * (N + 1) ** 2).sum())
-    parts = {"lift_faces": 2 * nv * S, "lift": (4 * nv + 10) * n + nv * S,
-             "visc_faces": (5 * nv + 1.5) * S, "visc": (5 * nv + 10) * n + nv * S, "element_extra": nv * n}
+    faces = np.asarray(wl.mesh.faces)
+    NL, NR = N[faces[:, 0]], N[faces[:, 2]]
+    same = NL == NR
+    S_same = float((2 * (NL[same] + 1) ** 2).sum())
+    S_jump = float(((NL[~same] + 1) ** 2 + (NR[~same] + 1) ** 2).sum())
+    parts = {"lift_faces": 2 * nv * S_jump,
+             "lift": (4 * nv + 10) * n + (2 * nv + 3) * S_same + nv * S_jump,
+             "visc_faces": (5 * nv + 1.5) * S_jump,
+             "visc": (5 * nv + 10) * n + (nv + 3) * S_same + nv * S_jump,
+             "element_extra": nv * n}
     return {k: 8.0 * v for k, v in parts.items()}
 
 
@@ -513,8 +526,9 @@ def main():
         visc = {"bytes_per_stage": vb, "viscous_phase_ms": v_ms,
                 "viscous_phase_frac": v_b / (v_ms / 1e3) / 1e9 / PEAK_HBM_GBS,
                 "mu": list(wl.mu), "Pr": list(wl.Pr), "D": list(wl.D),
-                "note": "viscous phase = lift faces, lift, viscous faces, viscous volume (one event pair); "
-                        "the stage roofline adds these bytes to the convective stage's"}
+                "note": "viscous phase = degree-jump lift faces, lift, degree-jump viscous faces, viscous "
+                        "volume (one event pair); the stage roofline adds these bytes to the convective "
+                        "stage's"}
         stage_b += sum(vb.values())
     rec = {
         "metric": METRIC,

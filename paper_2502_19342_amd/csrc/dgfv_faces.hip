@@ -862,46 +862,18 @@ face_vjp_conforming_kernel(MeshView m, ParamsDev prm, const int32_t* __restrict_
 }
 
 // ---------------------------------------------------------------------------
-// Viscous face terms (Section 3.1.1, eq. lift_flux and eq. visc_flux; Section
-// 3.2.2 for degree jumps).  Both write m.vside, the side layout of fside.
-//  lift:    u* = (u^- + u^+) / 2 at every node of both sides; at a degree jump
-//           the higher side's trace is projected to the lower degree, u* is
-//           formed there and the higher side receives its interpolation.
-//  viscous: F^v* = (F^v(u^-, g^-) + F^v(u^+, g^+)) / 2 . n s with the face
-//           normal (left outward) on the higher degree; the left side receives
-//           +F^v*, the right side -F^v*, the lower side of a degree jump its
-//           projection.
-// Same-degree faces: one lane per face node, several faces per workgroup
-// (per-degree face lists); degree jumps: one face per one-wavefront workgroup.
+// Viscous face terms at degree jumps (Section 3.1.1, eq. lift_flux and
+// eq. visc_flux; Section 3.2.2), one face per one-wavefront workgroup; both
+// write m.vside, the side layout of fside.  Same-degree faces are formed by
+// the per-degree lift and viscous kernels themselves.
+//  lift:    u* = (u^- + u^+) / 2: the higher side's trace projected to the
+//           lower degree, u* formed there, the higher side receiving its
+//           interpolation.
+//  viscous: F^v* = (F^v(u^-, g^-) + F^v(u^+, g^+)) / 2 . n s with both
+//           sides' traces of u and g on the higher degree and the face normal
+//           (left outward) there; the left side receives +F^v*, the right
+//           side -F^v*, the lower side its projection.
 // ---------------------------------------------------------------------------
-template <int N, int NV>
-__global__ void __launch_bounds__(CONF_THREADS)
-lift_face_conf_kernel(MeshView m, const int32_t* __restrict__ flist, int fcount, const double* __restrict__ u) {
-  constexpr int NP = N + 1, NP2 = NP * NP, FPB = CONF_THREADS / NP2;
-  const int t = threadIdx.x;
-  const int slot = t / NP2, r = t - slot * NP2;
-  if (slot >= FPB) return;
-  const int fi = blockIdx.x * FPB + slot;
-  if (fi >= fcount) return;
-  const int32_t* fc = m.faces + 5 * flist[fi];
-  const int eL = fc[0], sideL = fc[1], eR = fc[2], sideR = fc[3], o = fc[4];
-  const int p = r % NP, q = r / NP;
-  int pp, qq;
-  orient_map(o, p, q, NP, pp, qq);
-  const int64_t gL = m.elem_offset[eL] + side_node(sideL, p, q, NP);
-  const int64_t gR = m.elem_offset[eR] + side_node(sideR, pp, qq, NP);
-  double* bL = m.vside + m.side_off[eL];
-  double* bR = m.vside + m.side_off[eR];
-  double us[NV];
-#pragma unroll
-  for (int v = 0; v < NV; ++v) us[v] = 0.5 * (u[v * m.n_node + gL] + u[v * m.n_node + gR]);
-#pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    bL[(sideL * NV + v) * NP2 + q * NP + p] = us[v];
-    bR[(sideR * NV + v) * NP2 + qq * NP + pp] = us[v];
-  }
-}
-
 template <int NV>
 __global__ void __launch_bounds__(FACE_THREADS)
 lift_face_mixed_kernel(MeshView m, const double* __restrict__ u) {
@@ -935,57 +907,6 @@ lift_face_mixed_kernel(MeshView m, const double* __restrict__ u) {
   } else {
     write_side<NV>(bR, B2, sideR, o, true, nlo, 1.0);
     map2d_sep_side<NV>(bL, B2, B3, m.ops + m.tab.interp[lo][hi], nhi, nlo, sideL, o, false, 1.0);
-  }
-}
-
-template <int N, int NV>
-__global__ void __launch_bounds__(CONF_THREADS)
-visc_face_conf_kernel(MeshView m, const int32_t* __restrict__ flist, int fcount, const double* __restrict__ u) {
-  constexpr int NP = N + 1, NP2 = NP * NP, FPB = CONF_THREADS / NP2;
-  const int t = threadIdx.x;
-  const int slot = t / NP2, r = t - slot * NP2;
-  if (slot >= FPB) return;
-  const int fi = blockIdx.x * FPB + slot;
-  if (fi >= fcount) return;
-  const int f = flist[fi];
-  const int32_t* fc = m.faces + 5 * f;
-  const int eL = fc[0], sideL = fc[1], eR = fc[2], sideR = fc[3], o = fc[4];
-  const int p = r % NP, q = r / NP;
-  int pp, qq;
-  orient_map(o, p, q, NP, pp, qq);
-  const int64_t gL = m.elem_offset[eL] + side_node(sideL, p, q, NP);
-  const int64_t gR = m.elem_offset[eR] + side_node(sideR, pp, qq, NP);
-  const double* nrm = m.face_norm + m.face_norm_off[f];
-  double F[NV];
-  {
-    double uL[NV], uR[NV], gL_[3][NV], gR_[3][NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      uL[v] = u[v * m.n_node + gL];
-      uR[v] = u[v * m.n_node + gR];
-    }
-#pragma unroll
-    for (int x = 0; x < 3; ++x)
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        gL_[x][v] = m.grad[(x * NV + v) * m.n_node + gL];
-        gR_[x][v] = m.grad[(x * NV + v) * m.n_node + gR];
-      }
-    const double n0 = nrm[r], n1 = nrm[NP2 + r], n2 = nrm[2 * NP2 + r];
-    double f[3][NV];
-    viscous_flux<NV>(uL, gL_, m.gas, m.visc, f);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) F[v] = f[0][v] * n0 + f[1][v] * n1 + f[2][v] * n2;
-    viscous_flux<NV>(uR, gR_, m.gas, m.visc, f);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) F[v] = 0.5 * (F[v] + (f[0][v] * n0 + f[1][v] * n1 + f[2][v] * n2));
-  }
-  double* bL = m.vside + m.side_off[eL];
-  double* bR = m.vside + m.side_off[eR];
-#pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    bL[(sideL * NV + v) * NP2 + q * NP + p] = F[v];
-    bR[(sideR * NV + v) * NP2 + qq * NP + pp] = -F[v];
   }
 }
 
@@ -1152,31 +1073,12 @@ hipError_t launch_face_class(const MeshView& m, const ParamsDev& p, const double
 
 template <int NV, bool LIFT>
 static hipError_t launch_visc_faces_t(const MeshView& m, const double* u, hipStream_t s) {
-  for (int N = 1; N <= MAXN; ++N) {
-    const int cnt = m.face_conf_count[N];
-    if (cnt == 0) continue;
-    const int np2 = (N + 1) * (N + 1), fpb = CONF_THREADS / np2;
-    const dim3 grid((cnt + fpb - 1) / fpb), block(CONF_THREADS);
-    const int32_t* fl = m.face_conf[N];
-#define DGFV_VF(n)                                                                                        \
-  case n:                                                                                                 \
-    if constexpr (LIFT) hipLaunchKernelGGL((lift_face_conf_kernel<n, NV>), grid, block, 0, s, m, fl, cnt, u); \
-    else hipLaunchKernelGGL((visc_face_conf_kernel<n, NV>), grid, block, 0, s, m, fl, cnt, u);            \
-    break;
-    switch (N) {
-      DGFV_VF(1) DGFV_VF(2) DGFV_VF(3) DGFV_VF(4) DGFV_VF(5) DGFV_VF(6) DGFV_VF(7)
-    }
-#undef DGFV_VF
-    if (hipError_t e = hipGetLastError()) return e;
-  }
-  if (m.face_mixed_count > 0) {
-    if constexpr (LIFT)
-      hipLaunchKernelGGL((lift_face_mixed_kernel<NV>), dim3(m.face_mixed_count), dim3(FACE_THREADS), 0, s, m, u);
-    else
-      hipLaunchKernelGGL((visc_face_mixed_kernel<NV>), dim3(m.face_mixed_count), dim3(FACE_THREADS), 0, s, m, u);
-    if (hipError_t e = hipGetLastError()) return e;
-  }
-  return hipSuccess;
+  if (m.face_mixed_count == 0) return hipSuccess;
+  if constexpr (LIFT)
+    hipLaunchKernelGGL((lift_face_mixed_kernel<NV>), dim3(m.face_mixed_count), dim3(FACE_THREADS), 0, s, m, u);
+  else
+    hipLaunchKernelGGL((visc_face_mixed_kernel<NV>), dim3(m.face_mixed_count), dim3(FACE_THREADS), 0, s, m, u);
+  return hipGetLastError();
 }
 
 hipError_t launch_lift_faces(const MeshView& m, const double* u, hipStream_t s) {

@@ -116,8 +116,10 @@ struct MeshView {
   // viscous terms (allocated when transport coefficients are set)
   ViscDev visc;
   double* grad;                 // BR1-lifted gradient of u, [3][nvar][n_node]
-  double* vside;                // per element side: the BR1 face value u*, then the viscous
-                                // face flux (outward), same layout as fside
+  double* vside;                // per element side, the layout of fside: at a degree jump the
+                                // BR1 face value u*, then the outward viscous face flux; at a
+                                // same-degree face the side's viscous flux . n_L (the face's
+                                // left outward normal), which the neighbour's viscous kernel reads
   const double* rvisc;          // viscous rate [nvar][n_node] that the element kernel adds, or null
 };
 
@@ -221,10 +223,11 @@ bool face_class_present(const MeshView& m, const double* alpha, int cls);
 hipError_t launch_face_class(const MeshView& m, const ParamsDev& p, const double* u, const double* alpha,
                              int cls, bool read_trace, hipStream_t s);
 
-// Viscous face terms of all faces (dgfv_faces.hip): the BR1 face value u* of
-// every element side into m.vside, formed on the lower degree of a degree
-// jump; then the arithmetic-mean viscous flux from u and m.grad on the higher
-// degree, each side receiving its outward part at its own degree.
+// Viscous face terms of the degree-jump faces (dgfv_faces.hip): the BR1 face
+// value u* of both sides into m.vside, formed on the lower degree; then the
+// arithmetic-mean viscous flux from u and m.grad on the higher degree, each
+// side receiving its outward part at its own degree.  The per-degree lift and
+// viscous kernels form the same-degree faces themselves.
 hipError_t launch_lift_faces(const MeshView& m, const double* u, hipStream_t s);
 hipError_t launch_visc_faces(const MeshView& m, const double* u, hipStream_t s);
 hipError_t launch_faces_vjp(const MeshView& m, const ParamsDev& p, const double* u, const double* alpha,

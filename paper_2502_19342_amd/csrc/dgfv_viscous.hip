@@ -7,14 +7,21 @@
 //                 physical direction x,
 //                   g_x = (1/J) sum_d [ sum_m D_im (Ja^d_x u)_m
 //                                       +- Ja^d_x (u* - u) / w_0 on the sides ],
-//                 the strong form on LGL nodes, with u* the face value the lift
-//                 face kernel left in m.vside and the element's own
-//                 contravariant vectors at its boundary nodes.
+//                 the strong form on LGL nodes with the element's own
+//                 contravariant vectors at its boundary nodes.  On a side
+//                 shared with an element of the same degree the node forms
+//                 u* = (u + u_nbr) / 2 itself from the neighbour's matching
+//                 node; at a degree jump u* comes from m.vside.  Its boundary
+//                 nodes then leave the viscous flux of (u, g) dotted with the
+//                 face's left outward normal in m.vside for each same-degree
+//                 side: half of that face's viscous flux.
 //  visc_kernel    viscous rate: F^v_x from (u, g) at each node, the
 //                 contravariant fluxes Ft^d = sum_x Ja^d_x F^v_x, and
 //                   R^v = -(1/J) sum_d [ sum_m D_im Ft^d_m
 //                                        + (F^v*_out - (+-Ft^d)) / w_0 on the sides ],
-//                 with the outward face fluxes F^v*_out of m.vside.
+//                 with F^v* . n_L = (F^v_own . n_L + the neighbour's half) / 2 at
+//                 a same-degree side and the outward flux of m.vside at a
+//                 degree jump.
 //
 // Both run one element per NP^3 lanes, several elements per workgroup at low
 // degree; the partners of a node along each line are read from LDS.
@@ -37,7 +44,46 @@ struct VGeo {
   static constexpr int EPB = NP3 >= 256 ? 1 : 256 / NP3;
 };
 
-// Adds side s's term at this node (if the node lies on it) to acc.
+// Left-grid point (p, q) of a face whose right side holds (pp, qq): the
+// inverse of orient_map.
+__device__ __forceinline__ void orient_inverse(int o, int pp, int qq, int n, int& p, int& q) {
+  const int a = (o & 1) ? n - 1 - pp : pp;
+  const int b = (o & 2) ? n - 1 - qq : qq;
+  p = (o & 4) ? b : a;
+  q = (o & 4) ? a : b;
+}
+
+// The point (a, b) of an element's side seen from the face: the neighbour's
+// node, the neighbour's side and its face-grid index there, and the index of
+// the point on the face's left grid (where the face normals are stored).
+struct FacePoint {
+  int64_t nbr_node;
+  int nbr_side, nbr_fidx, left_fidx;
+};
+template <int N>
+__device__ __forceinline__ FacePoint face_point(const SideRec& sr, int a, int b) {
+  constexpr int NP = N + 1;
+  const int sL = sr.code & 7, sR = (sr.code >> 3) & 7, o = (sr.code >> 6) & 7;
+  FacePoint fp;
+  if ((sr.code >> 9) & 1) {              // this element is the face's left side
+    int pp, qq;
+    orient_map(o, a, b, NP, pp, qq);
+    fp.nbr_node = sr.baseR + side_node(sR, pp, qq, NP);
+    fp.nbr_side = sR;
+    fp.nbr_fidx = qq * NP + pp;
+    fp.left_fidx = b * NP + a;
+  } else {
+    int p, q;
+    orient_inverse(o, a, b, NP, p, q);
+    fp.nbr_node = sr.baseL + side_node(sL, p, q, NP);
+    fp.nbr_side = sL;
+    fp.nbr_fidx = q * NP + p;
+    fp.left_fidx = fp.nbr_fidx;
+  }
+  return fp;
+}
+
+// Calls f(side, face-grid index) for each side this node lies on.
 template <int N, class F>
 __device__ __forceinline__ void for_sides(int i, int j, int k, F&& f) {
   if (i == 0) f(0, k * (N + 1) + j);
@@ -108,13 +154,21 @@ lift_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const doub
   }
   // sides: +- Ja^d_x (u* - u) / w_0, outward sign by side parity
   const double inv_w0 = 1.0 / m.ops[m.tab.w[N]];
-  const double* us = m.vside + m.side_off[e];
+  double* vs = m.vside + m.side_off[e];
+  const SideRec* srs = m.side_rec + 6 * (int64_t)e;
   for_sides<N>(i, j, k, [&](int s, int fidx) {
     const int d = s >> 1;
     const double sg = (s & 1) ? inv_w0 : -inv_w0;
+    const SideRec sr = srs[s];
     double jump[NV];
+    if ((sr.code >> 10) & 1) {             // same degree: u* from the neighbour's matching node
+      const FacePoint fp = face_point<N>(sr, fidx % NP, fidx / NP);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) jump[v] = us[(s * NV + v) * NP2 + fidx] - ui[v];
+      for (int v = 0; v < NV; ++v) jump[v] = 0.5 * (u[v * m.n_node + fp.nbr_node] - ui[v]);
+    } else {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) jump[v] = vs[(s * NV + v) * NP2 + fidx] - ui[v];
+    }
 #pragma unroll
     for (int x = 0; x < 3; ++x) {
       const double c = sg * ja[3 * d + x];
@@ -126,7 +180,24 @@ lift_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const doub
 #pragma unroll
   for (int x = 0; x < 3; ++x)
 #pragma unroll
-    for (int v = 0; v < NV; ++v) m.grad[(x * NV + v) * m.n_node + base] = acc[x][v] * invJ;
+    for (int v = 0; v < NV; ++v) {
+      acc[x][v] *= invJ;
+      m.grad[(x * NV + v) * m.n_node + base] = acc[x][v];
+    }
+  // half fluxes of the same-degree sides: F^v(u, g) . n_L
+  if (i == 0 || i == N || j == 0 || j == N || k == 0 || k == N) {
+    double f[3][NV];
+    viscous_flux<NV>(ui, acc, m.gas, m.visc, f);
+    for_sides<N>(i, j, k, [&](int s, int fidx) {
+      const SideRec sr = srs[s];
+      if (!((sr.code >> 10) & 1)) return;
+      const FacePoint fp = face_point<N>(sr, fidx % NP, fidx / NP);
+      const double* nrm = m.face_norm + sr.nrm;
+      const double n0 = nrm[fp.left_fidx], n1 = nrm[NP2 + fp.left_fidx], n2 = nrm[2 * NP2 + fp.left_fidx];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) vs[(s * NV + v) * NP2 + fidx] = f[0][v] * n0 + f[1][v] * n1 + f[2][v] * n2;
+    });
+  }
 }
 
 template <int N, int NV>
@@ -144,11 +215,11 @@ visc_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const doub
   for (int t = tid; t < NP * NP; t += blockDim.x) sD[t] = m.ops[m.tab.D[N] + t];
   int e = 0;
   int64_t base = 0;
-  double Ft[3][NV];
+  double Ft[3][NV], f[3][NV];
   if (active) {
     e = elist[idx];
     base = m.elem_offset[e] + node;
-    double ui[NV], gr[3][NV], f[3][NV];
+    double ui[NV], gr[3][NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) ui[v] = u[v * m.n_node + base];
 #pragma unroll
@@ -188,11 +259,26 @@ visc_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const doub
   }
   const double inv_w0 = 1.0 / m.ops[m.tab.w[N]];
   const double* fs = m.vside + m.side_off[e];
+  const SideRec* srs = m.side_rec + 6 * (int64_t)e;
   for_sides<N>(i, j, k, [&](int s, int fidx) {
     const int d = s >> 1;
     const double sg = (s & 1) ? 1.0 : -1.0;
+    const SideRec sr = srs[s];
+    double Fo[NV];
+    if ((sr.code >> 10) & 1) {             // same degree: (own . n_L + the neighbour's half) / 2, outward
+      const FacePoint fp = face_point<N>(sr, fidx % NP, fidx / NP);
+      const double* nrm = m.face_norm + sr.nrm;
+      const double n0 = nrm[fp.left_fidx], n1 = nrm[NP2 + fp.left_fidx], n2 = nrm[2 * NP2 + fp.left_fidx];
+      const double* hn = m.vside + m.side_off[sr.nbr] + fp.nbr_side * NV * NP2 + fp.nbr_fidx;
+      const double so = ((sr.code >> 9) & 1) ? 0.5 : -0.5;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) acc[v] += (fs[(s * NV + v) * NP2 + fidx] - sg * Ft[d][v]) * inv_w0;
+      for (int v = 0; v < NV; ++v) Fo[v] = so * ((f[0][v] * n0 + f[1][v] * n1 + f[2][v] * n2) + hn[v * NP2]);
+    } else {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Fo[v] = fs[(s * NV + v) * NP2 + fidx];
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] += (Fo[v] - sg * Ft[d][v]) * inv_w0;
   });
   const double invJ = 1.0 / m.metric[9 * m.n_node + base];
 #pragma unroll
