@@ -14,6 +14,15 @@ The convective time step of Section 3.3 is taken with ``alpha_RK = 1`` and the
 element signal speed ``lambda_e = max_nodes sum_d (|v . Ja^d| + c |Ja^d|) / J``,
 ``dt = CFL min_e 2 / ((2 N_e + 1) lambda_e)``; blended elements also limit it by
 ``CFL h_FV / lambda_e`` with ``h_FV = 2 / N_FV``.
+
+With viscous terms the parabolic step of Section 3.3 joins it,
+``dt = 1 / (1 / (CFL dt^c) + 1 / (CFL^v dt^v))``, with ``beta_RK = 1``, the
+element's parabolic rate ``lambda^v_e = max_nodes delta^v sum_d |Ja^d|^2 / J^2``
+(the reference length 2 squared stands for ``dx^2``) and
+``dt^v = min_e 4 / ((2 N_e + 1) lambda^v_e)``, blended elements also limiting
+it by ``h_FV^2 / lambda^v_e``.  Readings: ``(2N + 1)`` to the first power, as
+printed; ``delta^v = max(4/3 mu / rho, kappa mu / (Pr rho), D_1, D_2)`` at each
+node, the largest of the momentum, heat and species diffusivities.
 """
 from __future__ import annotations
 
@@ -71,21 +80,42 @@ def step(rhs_fn, u: torch.Tensor, dt: float):
     return u
 
 
-def timestep(mesh: OracleMesh, gas: Gas, u: torch.Tensor, cfl: float, alpha=None) -> float:
-    best = float("inf")
+def timestep(mesh: OracleMesh, gas: Gas, u: torch.Tensor, cfl: float, alpha=None, transport=None,
+             cfl_v: float = 1.0) -> float:
+    """The time step (module docstring); ``transport`` (an ``oracle.viscous.Transport``) adds the parabolic one."""
+    best, best_v = float("inf"), float("inf")
     for N, g in mesh.groups.items():
         U = mesh.gather(u, N).transpose(0, 1)
         q = to_prim(U, gas)
         c = sound_speed(q)
         lam = torch.zeros_like(q.rho)
+        metric2 = torch.zeros_like(q.rho)
         for d in range(3):
             a = g.Ja[:, d].transpose(0, 1)                     # [3, E, ...]
             lam = lam + ((q.v * a).sum(0).abs() + c * torch.sqrt((a * a).sum(0)))
+            metric2 = metric2 + (a * a).sum(0)
         lam = (lam / g.J).amax(dim=(1, 2, 3))                  # [E]
         dtg = 2.0 / ((2 * N + 1) * lam)
-        if alpha is not None:
-            al = torch.as_tensor(alpha)[g.elems]
+        al = torch.as_tensor(alpha)[g.elems] if alpha is not None else None
+        if al is not None:
             dfv = (2.0 / mesh.n_fv) / lam
             dtg = torch.where(al > 0, torch.minimum(dtg, dfv), dtg)
         best = min(best, float(dtg.min()))
-    return cfl * best
+        if transport is not None:
+            if gas.nvar == 6:
+                Y = q.Y
+                mu = Y * transport.mu[0] + (1.0 - Y) * transport.mu[1]
+                Pr = Y * transport.Pr[0] + (1.0 - Y) * transport.Pr[1]
+                dmax = max(transport.D[0], transport.D[1])
+            else:
+                mu, Pr, dmax = transport.mu[0], transport.Pr[0], 0.0
+            delta = torch.maximum(torch.maximum((4.0 / 3.0) * mu / q.rho, q.kappa * mu / (Pr * q.rho)),
+                                  torch.full_like(q.rho, dmax))
+            lam_v = (delta * metric2 / (g.J * g.J)).amax(dim=(1, 2, 3))
+            dtv = 4.0 / ((2 * N + 1) * lam_v)
+            if al is not None:
+                dtv = torch.where(al > 0, torch.minimum(dtv, (2.0 / mesh.n_fv) ** 2 / lam_v), dtv)
+            best_v = min(best_v, float(dtv.min()))
+    if transport is None:
+        return cfl * best
+    return 1.0 / (1.0 / (cfl * best) + 1.0 / (cfl_v * best_v))

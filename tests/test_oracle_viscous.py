@@ -359,3 +359,53 @@ def test_species_wave_rate():
         R = viscous.viscous_rhs(mesh, gas, viscous.Transport(mu=(0.0, 0.0), D=(D, D)), u)
         return R[5], -D * eps * k ** 2 * torch.sin(k * x[2]), R[:5]          # d(rho Y1)/dt = rho D Y1''
     _converges(_errors(run, D * eps * k ** 2), 5e-4)
+
+
+# ---------------------------------------------------------------------------
+# the time step
+# ---------------------------------------------------------------------------
+def test_parabolic_time_step_on_an_affine_box():
+    # uniform state at rest on n^3 cubes of side h: |Ja^d|^2 / J^2 sums to 12 / h^2,
+    # so dt^v = h^2 / (3 (2N + 1) delta) with delta = max(4/3, gamma / Pr) mu / rho
+    from oracle import lsrk
+    n, N = 4, 3
+    wl, mesh, gas = _mesh(n, N, N, scramble=3)
+    h = 1.0 / n
+    rho, p = 1.3, 0.9
+    u = physics.prim_to_cons(torch.tensor([rho, 0.0, 0.0, 0.0, p], dtype=T)[:, None].expand(5, mesh.n_node), gas)
+    c = float(np.sqrt(1.4 * p / rho))
+    dtc = 2.0 / ((2 * N + 1) * 3 * c * 2.0 / h)            # |Ja^d| / J = 2 / h per direction
+    assert abs(lsrk.timestep(mesh, gas, u, 0.7) - 0.7 * dtc) <= 1e-13 * dtc
+    for mu, Pr in ((0.01, 0.72), (0.3, 2.0)):
+        delta = max(4.0 / 3.0, 1.4 / Pr) * mu / rho
+        dtv = h * h / (3 * (2 * N + 1) * delta)
+        got = lsrk.timestep(mesh, gas, u, 0.7, transport=viscous.Transport(mu=(mu, 0.0), Pr=(Pr, Pr)), cfl_v=0.4)
+        want = 1.0 / (1.0 / (0.7 * dtc) + 1.0 / (0.4 * dtv))
+        assert abs(got - want) <= 1e-13 * want
+    # vanishing viscosity leaves the convective step; blended elements take the sub-cell spacing
+    got = lsrk.timestep(mesh, gas, u, 0.7, transport=viscous.Transport(mu=(1e-300, 0.0)))
+    assert abs(got - 0.7 * dtc) <= 1e-13 * dtc
+    alpha = torch.zeros(mesh.K, dtype=T)
+    alpha[5] = 0.5
+    mu = 0.05
+    delta = max(4.0 / 3.0, 1.4 / 0.72) * mu / rho
+    dtv_fv = (2.0 / mesh.n_fv) ** 2 / (delta * 12 / h ** 2)
+    dtc_fv = (2.0 / mesh.n_fv) / (3 * c * 2.0 / h)
+    got = lsrk.timestep(mesh, gas, u, 0.7, alpha=alpha, transport=viscous.Transport(mu=(mu, 0.0)), cfl_v=0.4)
+    want = 1.0 / (1.0 / (0.7 * min(dtc, dtc_fv)) + 1.0 / (0.4 * min(h * h / (3 * (2 * N + 1) * delta), dtv_fv)))
+    assert abs(got - want) <= 1e-13 * want
+
+
+def test_parabolic_time_step_uses_the_largest_diffusivity():
+    from oracle import lsrk
+    wl, mesh, gas = _mesh(3, 2, 2, scramble=None, n_var=6)
+    gas = physics.Gas(nvar=6, kappa=(1.4, 1.4), R=(1.0, 1.0))
+    w = torch.tensor([1.0, 0.0, 0.0, 0.0, 1.0, 0.5], dtype=T)[:, None].expand(6, mesh.n_node)
+    u = physics.prim_to_cons(w, gas)
+    small = lsrk.timestep(mesh, gas, u, 1.0, transport=viscous.Transport(mu=(1e-3, 1e-3), D=(0.0, 0.0)))
+    big = lsrk.timestep(mesh, gas, u, 1.0, transport=viscous.Transport(mu=(1e-3, 1e-3), D=(0.0, 5.0)))
+    h, N = 1.0 / 3, 2
+    dtc = 2.0 / ((2 * N + 1) * 3 * np.sqrt(1.4) * 2.0 / h)
+    dtv = h * h / (3 * (2 * N + 1) * 5.0)
+    assert big < small
+    assert abs(big - 1.0 / (1.0 / dtc + 1.0 / dtv)) <= 1e-13 * big
