@@ -349,6 +349,30 @@ dgfv_status dgfv_set_transport(dgfv_mesh* mesh, const dgfv_transport* tr);
 dgfv_status dg_lift(const dgfv_mesh* mesh, const double* u_d, double* g_d, void* stream);
 
 /*
+ * Time step of Section 3.3 for u_d (and the blending factors alpha_d, or
+ * NULL), with alpha_RK = beta_RK = 1: the convective step
+ *   dt^c = min_e 2 / ((2 N_e + 1) lambda^c_e),
+ *   lambda^c_e = max over e's nodes of sum_d (|v . Ja^d| + c |Ja^d|) / J,
+ * a blended element (alpha > 0) also bounded by h_FV / lambda^c_e with the
+ * sub-cell spacing h_FV = 2 / N_FV; with viscous terms (dgfv_set_transport)
+ * the parabolic step
+ *   dt^v = min_e 4 / ((2 N_e + 1) lambda^v_e),
+ *   lambda^v_e = max over e's nodes of delta sum_d |Ja^d|^2 / J^2,
+ *   delta = max(4/3 mu / rho, kappa mu / (Pr rho), D_1, D_2),
+ * a blended element also bounded by h_FV^2 / lambda^v_e, and the two join as
+ *   *dt = 1 / (1 / (cfl dt^c) + 1 / (cfl_v dt^v));
+ * without viscous terms *dt = cfl dt^c (cfl_v unused).  The reference length
+ * 2 (squared) stands for the element size, (2N + 1) enters to the first power
+ * as printed.  Synchronous: waits for `stream` and copies two doubles; the
+ * first call allocates 2 n_elem + 2 doubles; not while the stream is
+ * captured (DGFV_ERR_ARG).  cfl (and cfl_v when viscous) positive and finite,
+ * else DGFV_ERR_ARG; DGFV_ERR_STATE if the state gives no positive finite step
+ * (rho <= 0, p <= 0 or NaN somewhere).
+ */
+dgfv_status dg_timestep(const dgfv_mesh* mesh, const double* u_d, const double* alpha_d, double cfl,
+                        double cfl_v, double* dt, void* stream);
+
+/*
  * Autotuning (not part of the method).  The element kernel has two tile
  * shapes at degrees N <= 5: about 512 or about 256 lanes per workgroup (the
  * number of elements per workgroup).  dgfv_autotune evaluates the RHS once on

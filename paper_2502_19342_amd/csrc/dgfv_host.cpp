@@ -173,6 +173,9 @@ struct dgfv_mesh {
   double* rvisc = nullptr;
   size_t side_total = 0;                        // doubles of one side buffer (fside, vside)
 
+  // dg_timestep: per-element steps [2][K] and the two minima (made by its first call)
+  mutable double* dt_buf = nullptr;
+
   // kernel timing (mutable: recording does not change the mesh)
   mutable bool profile = false;
   mutable std::array<std::vector<std::pair<hipEvent_t, hipEvent_t>>, DGFV_KERNEL_COUNT> ev;
@@ -207,6 +210,7 @@ struct dgfv_mesh {
     if (view.grad) (void)hipFree(view.grad);
     if (view.vside) (void)hipFree(view.vside);
     if (rvisc) (void)hipFree(rvisc);
+    if (dt_buf) (void)hipFree(dt_buf);
   }
   template <class T>
   T* keep(T* p) {
@@ -1576,6 +1580,36 @@ dgfv_status dgfv_set_transport(dgfv_mesh* m, const dgfv_transport* tr) {
   m->view.visc = ViscDev{tr->mu[0], tr->mu[1], tr->Pr[0], tr->Pr[1], tr->D[0], tr->D[1]};
   m->viscous = true;
   m->drop_graphs();
+  return DGFV_OK;
+}
+
+dgfv_status dg_timestep(const dgfv_mesh* m, const double* u, const double* alpha, double cfl, double cfl_v,
+                        double* dt, void* stream) {
+  if (!m || !u || !dt) return fail(DGFV_ERR_ARG, "NULL argument");
+  if (!(cfl > 0.0) || !std::isfinite(cfl)) return fail(DGFV_ERR_ARG, "dg_timestep: cfl must be positive and finite");
+  if (m->viscous && (!(cfl_v > 0.0) || !std::isfinite(cfl_v)))
+    return fail(DGFV_ERR_ARG, "dg_timestep: cfl_v must be positive and finite");
+  const hipStream_t s = (hipStream_t)stream;
+  if (capturing(s)) return fail(DGFV_ERR_ARG, "dg_timestep waits for its result: not under capture");
+  try {
+    if (!m->dt_buf) m->dt_buf = dev_alloc<double>(2 * (size_t)m->K + 2);
+    const MeshView& v = m->view;
+    for (int N = 1; N <= MAXN; ++N)
+      if (!m->bucket[N].empty())
+        hip_check(viscous_ops_for(N).timestep(v, m->d_bucket[N], (int)m->bucket[N].size(), u, alpha,
+                                              m->viscous ? 1 : 0, m->dt_buf, s),
+                  "timestep launch");
+    hip_check(launch_min_pairs(m->dt_buf, m->K, m->dt_buf + 2 * (size_t)m->K, s), "minimum launch");
+    double h[2] = {0.0, 0.0};
+    hip_check(hipMemcpyAsync(h, m->dt_buf + 2 * (size_t)m->K, sizeof h, hipMemcpyDeviceToHost, s), "copy");
+    hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    const double out = m->viscous ? 1.0 / (1.0 / (cfl * h[0]) + 1.0 / (cfl_v * h[1])) : cfl * h[0];
+    if (!(out > 0.0) || !std::isfinite(out))
+      return fail(DGFV_ERR_STATE, "dg_timestep: no positive finite time step (non-physical state)");
+    *dt = out;
+  } catch (const HipError& e) {
+    return fail(msg_oom(e) ? DGFV_ERR_OOM : DGFV_ERR_HIP, e.what());
+  }
   return DGFV_OK;
 }
 

@@ -180,6 +180,9 @@ struct ViscousOps {
   hipError_t (*lift)(const MeshView& m, const int32_t* elist, int count, const double* u, hipStream_t s);
   hipError_t (*volume)(const MeshView& m, const int32_t* elist, int count, const double* u, double* rv,
                        hipStream_t s);
+  // time step per element: dt_e[e] convective, dt_e[K + e] parabolic (0 unless viscous)
+  hipError_t (*timestep)(const MeshView& m, const int32_t* elist, int count, const double* u,
+                         const double* alpha, int viscous, double* dt_e, hipStream_t s);
 };
 ViscousOps viscous_ops_1();
 ViscousOps viscous_ops_2();
@@ -257,6 +260,8 @@ hipError_t launch_transfer(const MeshView& from, const MeshView& to, const doubl
                            const double* table, hipStream_t s);
 
 // Pointwise state kernels (dgfv_state.hip).
+// out[0] = min of dt_e[0 .. K), out[1] = min of dt_e[K .. 2K) (one workgroup).
+hipError_t launch_min_pairs(const double* dt_e, int K, double* out, hipStream_t s);
 hipError_t launch_prim_to_cons(const MeshView& m, const double* w, double* u, hipStream_t s);
 hipError_t launch_rk_adjoint_pre(const MeshView& m, double B, const double* ubar, double* kbar, hipStream_t s);
 hipError_t launch_rk_adjoint_post(const MeshView& m, double dt, double A, const double* g, double* ubar,

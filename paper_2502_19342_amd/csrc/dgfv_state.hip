@@ -9,6 +9,7 @@
 // so with the cotangents ubar of u_s and kbar of k_s from the later stages
 //   kt = kbar + B_s ubar;   ubar <- ubar + dt (dR/du)^T kt;   kbar <- A_s kt.
 // rk_adjoint_pre forms kt in place of kbar; rk_adjoint_post takes g = (dR/du)^T kt.
+#include <cmath>
 #include <mutex>
 
 #include "dgfv_internal.h"
@@ -141,6 +142,41 @@ hipError_t static_scratch_ptr(double** out) {
   }
   *out = g_scratch_dev[dev];
   return hipSuccess;
+}
+
+// Minimum of each half of dt_e (the per-element convective and parabolic time
+// steps), one workgroup: a strided pass per lane, then the lanes' minima
+// combined with unsigned 64-bit atomics in LDS on the bit patterns (order-
+// preserving for non-negative doubles; a NaN outranks every number, and
+// comes through as the maximum, never as the minimum: the lanes keep it
+// apart so that the host sees it).
+constexpr int MIN_THREADS = 1024;
+__global__ void __launch_bounds__(MIN_THREADS) min_pairs_kernel(const double* __restrict__ dt_e, int K,
+                                                                double* __restrict__ out) {
+  __shared__ unsigned long long sMin[2];
+  __shared__ int sNan;
+  if (threadIdx.x < 2) sMin[threadIdx.x] = ~0ull;
+  if (threadIdx.x == 0) sNan = 0;
+  __syncthreads();
+  for (int h = 0; h < 2; ++h) {
+    double best = INFINITY;
+    bool nan = false;
+    for (int e = threadIdx.x; e < K; e += blockDim.x) {
+      const double x = dt_e[(size_t)h * K + e];
+      if (x != x) nan = true;
+      else best = fmin(best, x);
+    }
+    if (nan) sNan = 1;
+    atomicMin(&sMin[h], (unsigned long long)__double_as_longlong(best));
+  }
+  __syncthreads();
+  if (threadIdx.x < 2)
+    out[threadIdx.x] = sNan ? NAN : __longlong_as_double((long long)sMin[threadIdx.x]);
+}
+
+hipError_t launch_min_pairs(const double* dt_e, int K, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(min_pairs_kernel, dim3(1), dim3(MIN_THREADS), 0, s, dt_e, K, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_prim_to_cons(const MeshView& m, const double* w, double* u, hipStream_t s) {

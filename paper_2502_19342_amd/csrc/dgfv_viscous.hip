@@ -285,6 +285,82 @@ visc_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const doub
   for (int v = 0; v < NV; ++v) rv[v * m.n_node + base] = -acc[v] * invJ;
 }
 
+// Time step of Section 3.3, per element: the convective signal speed
+// lambda^c = max_nodes sum_d (|v . Ja^d| + c |Ja^d|) / J and, with viscous
+// terms, the parabolic rate lambda^v = max_nodes delta^v sum_d |Ja^d|^2 / J^2
+// with delta^v = max(4/3 mu / rho, kappa mu / (Pr rho), D_1, D_2); then
+// dt^c_e = 2 / ((2N + 1) lambda^c), dt^v_e = 4 / ((2N + 1) lambda^v), a blended
+// element also bounded by the sub-cell spacing h_FV = 2 / N_FV (h_FV /
+// lambda^c, h_FV^2 / lambda^v).  The maxima over an element's nodes use
+// unsigned 64-bit atomics in LDS on the bit patterns (order-preserving for
+// non-negative doubles; a NaN outranks every number and comes through).
+template <int N, int NV>
+__global__ void __launch_bounds__(VGeo<N>::EPB * VGeo<N>::NP3)
+timestep_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const double* __restrict__ u,
+                const double* __restrict__ alpha, int viscous, double* __restrict__ dt_e) {
+  using G = VGeo<N>;
+  constexpr int NP3 = G::NP3, EPB = G::EPB;
+  __shared__ unsigned long long sMax[EPB][2];
+  const int tid = threadIdx.x;
+  const int slot = tid / NP3, node = tid - slot * NP3;
+  const int idx = blockIdx.x * EPB + slot;
+  const bool active = idx < count;
+  if (node < 2) sMax[slot][node] = 0ull;
+  __syncthreads();
+  int e = 0;
+  if (active) {
+    e = elist[idx];
+    const int64_t base = m.elem_offset[e] + node;
+    double uo[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) uo[v] = u[v * m.n_node + base];
+    const Prim q = cons2prim<NV>(uo, m.gas);
+    const double c = sqrt(q.kap * q.p / q.rho);
+    const double iJ = 1.0 / m.metric[9 * m.n_node + base];
+    double lc = 0.0, a2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double a0 = m.metric[(3 * d) * m.n_node + base];
+      const double a1 = m.metric[(3 * d + 1) * m.n_node + base];
+      const double a2d = m.metric[(3 * d + 2) * m.n_node + base];
+      const double nn = a0 * a0 + a1 * a1 + a2d * a2d;
+      lc += fabs(q.v1 * a0 + q.v2 * a1 + q.v3 * a2d) + c * sqrt(nn);
+      a2 += nn;
+    }
+    lc *= iJ;
+    atomicMax(&sMax[slot][0], (unsigned long long)__double_as_longlong(lc));
+    if (viscous) {
+      double mu, Pr, dmax = 0.0;
+      if constexpr (NV == 6) {
+        mu = q.Y * m.visc.mu0 + (1.0 - q.Y) * m.visc.mu1;
+        Pr = q.Y * m.visc.Pr0 + (1.0 - q.Y) * m.visc.Pr1;
+        dmax = fmax(m.visc.D0, m.visc.D1);
+      } else {
+        mu = m.visc.mu0;
+        Pr = m.visc.Pr0;
+      }
+      const double delta = fmax(fmax((4.0 / 3.0) * mu / q.rho, q.kap * mu / (Pr * q.rho)), dmax);
+      const double lv = delta * a2 * iJ * iJ;
+      atomicMax(&sMax[slot][1], (unsigned long long)__double_as_longlong(lv));
+    }
+  }
+  __syncthreads();
+  if (!active || node != 0) return;
+  const double lc = __longlong_as_double((long long)sMax[slot][0]);
+  const double lv = __longlong_as_double((long long)sMax[slot][1]);
+  const bool blended = alpha && alpha[e] > 0.0;
+  const double hfv = 2.0 / m.n_fv;
+  double dc = 2.0 / ((2 * N + 1) * lc);
+  if (blended) dc = fmin(dc, hfv / lc);
+  double dv = 0.0;
+  if (viscous) {
+    dv = 4.0 / ((2 * N + 1) * lv);
+    if (blended) dv = fmin(dv, hfv * hfv / lv);
+  }
+  dt_e[e] = dc;
+  dt_e[m.K + e] = dv;
+}
+
 namespace per_degree {
 hipError_t lift(const MeshView& m, const int32_t* elist, int count, const double* u, hipStream_t s) {
   using G = VGeo<kN>;
@@ -308,11 +384,26 @@ hipError_t volume(const MeshView& m, const int32_t* elist, int count, const doub
     hipLaunchKernelGGL((visc_kernel<kN, 6>), dim3(blocks), dim3(G::EPB * G::NP3), 0, s, m, elist, count, u, rv);
   return hipGetLastError();
 }
+hipError_t timestep(const MeshView& m, const int32_t* elist, int count, const double* u, const double* alpha,
+                    int viscous, double* dt_e, hipStream_t s) {
+  using G = VGeo<kN>;
+  if (count <= 0) return hipSuccess;
+  const int blocks = (count + G::EPB - 1) / G::EPB;
+  if (m.nvar == 5)
+    hipLaunchKernelGGL((timestep_kernel<kN, 5>), dim3(blocks), dim3(G::EPB * G::NP3), 0, s, m, elist, count, u,
+                       alpha, viscous, dt_e);
+  else
+    hipLaunchKernelGGL((timestep_kernel<kN, 6>), dim3(blocks), dim3(G::EPB * G::NP3), 0, s, m, elist, count, u,
+                       alpha, viscous, dt_e);
+  return hipGetLastError();
+}
 }  // namespace per_degree
 }  // namespace
 
 #define DGFV_CAT2(a, b) a##b
 #define DGFV_CAT(a, b) DGFV_CAT2(a, b)
-ViscousOps DGFV_CAT(viscous_ops_, DGFV_N)() { return ViscousOps{&per_degree::lift, &per_degree::volume}; }
+ViscousOps DGFV_CAT(viscous_ops_, DGFV_N)() {
+  return ViscousOps{&per_degree::lift, &per_degree::volume, &per_degree::timestep};
+}
 
 }  // namespace dgfv

@@ -49,7 +49,7 @@ EXPORTED = ("dgfv_mesh_create", "dgfv_mesh_destroy", "dgfv_mesh_info", "dgfv_mes
             "dg_rk_stage_vjp_noalloc", "dgfv_prim_to_cons", "dg_positivity_limiter",
             "dgfv_set_positivity_limiter", "dgfv_set_launch_mode", "dgfv_set_face_fusion", "dgfv_autotune",
             "dgfv_set_element_shape", "dgfv_check_state", "dg_rhs_fv", "dg_rk_stage_fv", "dg_rk_step_fv",
-            "dg_switch_fv", "dg_p_degrees", "dg_transfer_degree", "dgfv_set_transport", "dg_lift",
+            "dg_switch_fv", "dg_p_degrees", "dg_transfer_degree", "dgfv_set_transport", "dg_lift", "dg_timestep",
             "dgfv_profile_enable", "dgfv_profile_read", "dgfv_last_error")
 (KERNEL_ELEMENT, KERNEL_FACE, KERNEL_FV_MEANS, KERNEL_FV_RESIDUAL, KERNEL_INDICATOR, KERNEL_VJP, KERNEL_FV_FACE,
  KERNEL_VISCOUS) = range(8)
@@ -88,6 +88,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dgfv_set_element_shape.argtypes = [P, c_int, c_int]
     lib.dgfv_set_transport.argtypes = [P, ctypes.POINTER(_Transport)]
     lib.dg_lift.argtypes = [P, P, P, P]
+    lib.dg_timestep.argtypes = [P, P, P, c_double, c_double, ctypes.POINTER(ctypes.c_double), P]
     lib.dgfv_autotune.argtypes = [P, ctypes.POINTER(_Params), P, P, ctypes.POINTER(ctypes.c_double), P]
     lib.dgfv_profile_enable.argtypes = [P, c_int]
     lib.dgfv_profile_read.argtypes = [P, c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
@@ -293,6 +294,15 @@ def lift(mesh: Mesh, u: torch.Tensor, out: torch.Tensor | None = None, stream=No
         raise ValueError("out must be a contiguous float64 [3, n_var, n_node] tensor")
     _check(_lib.dg_lift(mesh._h, mesh._state(u, "u"), ctypes.c_void_p(out.data_ptr()), _stream(stream)))
     return out
+
+
+def timestep(mesh: Mesh, u: torch.Tensor, alpha: torch.Tensor | None = None, cfl: float = 0.5,
+             cfl_v: float = 0.5, stream=None) -> float:
+    """Time step of the state: convective, joined with the parabolic one on viscous meshes (``dg_timestep``)."""
+    out = ctypes.c_double()
+    _check(_lib.dg_timestep(mesh._h, mesh._state(u, "u"), mesh._alpha(alpha), float(cfl), float(cfl_v),
+                            ctypes.byref(out), _stream(stream)))
+    return out.value
 
 
 def rk_stage(mesh: Mesh, params: Params, stage: int, dt: float, u: torch.Tensor, k: torch.Tensor,

@@ -128,6 +128,12 @@ def main(src, dst):
             check(lib.dg_switch_fv(h, ptr(uu), ptr(uf), ptr(np.ascontiguousarray(z["fv"], dtype=np.float64)),
                                    ptr(np.ascontiguousarray(z["fv_new"], dtype=np.float64)), None), "dg_switch_fv")
             out["switch_dg"], out["switch_fv"] = uu, uf
+        elif call == "timestep":
+            cf = z["cfl"]
+            dt = ctypes.c_double()
+            check(lib.dg_timestep(h, ptr(u), ptr(alpha), ctypes.c_double(float(cf[0])), ctypes.c_double(float(cf[1])),
+                                  ctypes.byref(dt), None), "dg_timestep")
+            out["timestep"] = np.array([dt.value])
         elif call == "lift":
             g = np.empty((3,) + u.shape)
             check(lib.dg_lift(h, ptr(u), ptr(g), None), "dg_lift")

@@ -82,6 +82,27 @@ inline unsigned long long __ballot(int pred) { return cpu_hip::ballot(pred); }
 inline int __popcll(unsigned long long x) { return __builtin_popcountll(x); }
 inline int __builtin_amdgcn_readfirstlane(int v) { return cpu_hip::readfirstlane(v); }
 inline double __builtin_amdgcn_rcp(double x) { return 1.0 / x; }
+// the fibers of a workgroup never run at the same time: a plain read-modify-write is atomic
+inline unsigned long long atomicMax(unsigned long long* p, unsigned long long v) {
+  const unsigned long long o = *p;
+  if (v > o) *p = v;
+  return o;
+}
+inline unsigned long long atomicMin(unsigned long long* p, unsigned long long v) {
+  const unsigned long long o = *p;
+  if (v < o) *p = v;
+  return o;
+}
+inline long long __double_as_longlong(double x) {
+  long long r;
+  __builtin_memcpy(&r, &x, sizeof r);
+  return r;
+}
+inline double __longlong_as_double(long long x) {
+  double r;
+  __builtin_memcpy(&r, &x, sizeof r);
+  return r;
+}
 #define __builtin_amdgcn_fence(order, scope) ((void)0)
 inline void __builtin_amdgcn_wave_barrier() { cpu_hip::wave_barrier(); }
 

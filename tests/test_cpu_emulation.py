@@ -286,3 +286,18 @@ def test_cpu_build_viscous(n_var):
     assert rel_err(torch.as_tensor(out["rhs"]), c.oracle_rhs()) <= _tol(c)
     want = lsrk.step(lambda v: c.f(v, c.alpha), c.u, dt)
     assert rel_err(torch.as_tensor(out["rk_step"]), want) <= 1e-11
+
+
+@pytest.mark.parametrize("n_var,viscous", [(5, True), (6, True), (5, False)])
+def test_cpu_build_timestep(n_var, viscous):
+    # the convective and parabolic time steps over degrees 1..4 with blended elements
+    import dataclasses
+    from oracle import problem as P
+    wl = curved_mixed(n=3, nmin=1, nmax=4, n_var=n_var, scramble=29, metric_degree=0, n_fv=5)
+    if viscous:
+        wl = dataclasses.replace(wl, mu=(0.02, 0.05), Pr=(0.7, 0.6), D=(0.01, 0.2))
+    c = _case(wl, smooth_state(53, n_var), noise=1e-3, seed=6)
+    c.alpha = seeded_alpha(c.mesh.K, 54, values=(0.0, 0.0, 0.4, 1.0))
+    out = cpu_emu.run(wl, c.u.numpy(), ["timestep"], alpha=c.alpha.numpy(), cfl=np.array([0.6, 0.3]))
+    want = lsrk.timestep(c.mesh, c.gas, c.u, 0.6, c.alpha, P.transport_of(wl) if viscous else None, 0.3)
+    assert abs(float(out["timestep"][0]) - want) <= 1e-13 * want

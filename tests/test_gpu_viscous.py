@@ -93,6 +93,25 @@ def test_viscous_switch_and_unsupported_calls():
     assert torch.equal(r_again, r_visc)
 
 
+@pytest.mark.parametrize("n_var,viscous", [(5, True), (6, True), (6, False)])
+def test_timestep_on_gpu(n_var, viscous):
+    announce(f"time step n_var={n_var} viscous={viscous}")
+    from oracle import problem
+    from paper_2502_19342_amd import dgfv
+    wl = _wl(n_var, scramble=29)
+    if not viscous:
+        wl = dataclasses.replace(wl, mu=(0.0, 0.0), D=(0.0, 0.0))
+    c = Case(wl, prim=smooth_state(69, n_var), noise=1e-3, seed=7)
+    c.alpha = seeded_alpha(c.mesh.K, 70, values=(0.0, 0.0, 0.4, 1.0))
+    got = dgfv.timestep(c.gmesh, c.gpu(c.u), c.gpu(c.alpha), 0.6, 0.3)
+    want = lsrk.timestep(c.mesh, c.gas, c.u, 0.6, c.alpha, problem.transport_of(wl) if viscous else None, 0.3)
+    assert abs(got - want) <= 1e-13 * want
+    bad = c.u.clone()
+    bad[0, 7] = -1.0                                           # negative density: no time step
+    with pytest.raises(dgfv.DgfvError):
+        dgfv.timestep(c.gmesh, c.gpu(bad), None, 0.6, 0.3)
+
+
 def _exact_viscous_rate(wl, x: np.ndarray, gas) -> torch.Tensor:
     """-div F^v of the exact initial state at points x [P, 3] (autograd, float64)."""
     xt = torch.as_tensor(x, dtype=T).requires_grad_(True)
