@@ -275,16 +275,15 @@ def viscous_bytes(wl, degree: np.ndarray) -> dict:
     Each kernel reads its inputs once and writes its outputs once: n nodes,
     nvar variables, 10 geometry terms per node; side nodes S_same on faces
     between elements of one degree (formed inside the lift and viscous
-    kernels) and S_jump on degree jumps (face kernels), 3 normal components
-    per side node where a kernel forms a same-degree face, 1.5 per side node
-    where a face kernel does:
+    kernels) and S_jump on degree jumps (face kernels), 1.5 normal
+    components per side node where a face kernel forms a flux:
       lift faces:  u traces, u* per side                       2 nvar S_jump
       lift:        u, geometry, g = grad u; the neighbour's u
-                   and the half flux F^v . n_L per same-degree
-                   side node, with the normal; u* at jumps      (4 nvar + 10) n + (2 nvar + 3) S_same + nvar S_jump
+                   and the outward half flux F^v . n per
+                   same-degree side node; u* at jumps           (4 nvar + 10) n + 2 nvar S_same + nvar S_jump
       visc faces:  u, g traces, normals; F^v* per side          (5 nvar + 1.5) S_jump
-      visc volume: u, g, geometry, R^v; the neighbour's half
-                   flux with the normal; F^v* at jumps          (5 nvar + 10) n + (nvar + 3) S_same + nvar S_jump
+      visc volume: u, g, geometry, R^v; both halves of each
+                   same-degree face flux; F^v* at jumps          (5 nvar + 10) n + 2 nvar S_same + nvar S_jump
       element:     R^v read once more                           nvar n
     """
     N = degree.astype(np.int64)
@@ -296,9 +295,9 @@ def viscous_bytes(wl, degree: np.ndarray) -> dict:
     S_same = float((2 * (NL[same] + 1) ** 2).sum())
     S_jump = float(((NL[~same] + 1) ** 2 + (NR[~same] + 1) ** 2).sum())
     parts = {"lift_faces": 2 * nv * S_jump,
-             "lift": (4 * nv + 10) * n + (2 * nv + 3) * S_same + nv * S_jump,
+             "lift": (4 * nv + 10) * n + 2 * nv * S_same + nv * S_jump,
              "visc_faces": (5 * nv + 1.5) * S_jump,
-             "visc": (5 * nv + 10) * n + (nv + 3) * S_same + nv * S_jump,
+             "visc": (5 * nv + 10) * n + 2 * nv * S_same + nv * S_jump,
              "element_extra": nv * n}
     return {k: 8.0 * v for k, v in parts.items()}
 

@@ -118,8 +118,8 @@ struct MeshView {
   double* grad;                 // BR1-lifted gradient of u, [3][nvar][n_node]
   double* vside;                // per element side, the layout of fside: at a degree jump the
                                 // BR1 face value u*, then the outward viscous face flux; at a
-                                // same-degree face the side's viscous flux . n_L (the face's
-                                // left outward normal), which the neighbour's viscous kernel reads
+                                // same-degree face the side's own viscous flux . its outward
+                                // contravariant vector, which the neighbour's viscous kernel reads
   const double* rvisc;          // viscous rate [nvar][n_node] that the element kernel adds, or null
 };
 

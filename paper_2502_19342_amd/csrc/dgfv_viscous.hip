@@ -13,15 +13,17 @@
 //                 u* = (u + u_nbr) / 2 itself from the neighbour's matching
 //                 node; at a degree jump u* comes from m.vside.  Its boundary
 //                 nodes then leave the viscous flux of (u, g) dotted with the
-//                 face's left outward normal in m.vside for each same-degree
-//                 side: half of that face's viscous flux.
+//                 element's own outward contravariant vector in m.vside for
+//                 each same-degree side: half of that face's viscous flux.
 //  visc_kernel    viscous rate: F^v_x from (u, g) at each node, the
 //                 contravariant fluxes Ft^d = sum_x Ja^d_x F^v_x, and
 //                   R^v = -(1/J) sum_d [ sum_m D_im Ft^d_m
 //                                        + (F^v*_out - (+-Ft^d)) / w_0 on the sides ],
-//                 with F^v* . n_L = (F^v_own . n_L + the neighbour's half) / 2 at
-//                 a same-degree side and the outward flux of m.vside at a
-//                 degree jump.
+//                 with the outward F^v* = (own half - the neighbour's half) / 2
+//                 at a same-degree side (both outward, left in m.vside by
+//                 the lift kernel; the two sides' contravariant vectors at a
+//                 face agree up to rounding) and the outward flux of m.vside
+//                 at a degree jump.
 //
 // Both run one element per NP^3 lanes, several elements per workgroup at low
 // degree; the partners of a node along each line are read from LDS.
@@ -54,11 +56,10 @@ __device__ __forceinline__ void orient_inverse(int o, int pp, int qq, int n, int
 }
 
 // The point (a, b) of an element's side seen from the face: the neighbour's
-// node, the neighbour's side and its face-grid index there, and the index of
-// the point on the face's left grid (where the face normals are stored).
+// node, the neighbour's side and its face-grid index there.
 struct FacePoint {
   int64_t nbr_node;
-  int nbr_side, nbr_fidx, left_fidx;
+  int nbr_side, nbr_fidx;
 };
 template <int N>
 __device__ __forceinline__ FacePoint face_point(const SideRec& sr, int a, int b) {
@@ -71,14 +72,12 @@ __device__ __forceinline__ FacePoint face_point(const SideRec& sr, int a, int b)
     fp.nbr_node = sr.baseR + side_node(sR, pp, qq, NP);
     fp.nbr_side = sR;
     fp.nbr_fidx = qq * NP + pp;
-    fp.left_fidx = b * NP + a;
   } else {
     int p, q;
     orient_inverse(o, a, b, NP, p, q);
     fp.nbr_node = sr.baseL + side_node(sL, p, q, NP);
     fp.nbr_side = sL;
     fp.nbr_fidx = q * NP + p;
-    fp.left_fidx = fp.nbr_fidx;
   }
   return fp;
 }
@@ -102,11 +101,33 @@ lift_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const doub
   __shared__ double sD[NP * NP];
   __shared__ double sU[EPB][NV][NP3];
   __shared__ double sJa[EPB][9][NP3];
+  __shared__ double sSt[EPB][6][NV][NP2];    // per side point: the neighbour's u (same degree) or u*
   const int tid = threadIdx.x;
   const int slot = tid / NP3, node = tid - slot * NP3;
   const int idx = blockIdx.x * EPB + slot;
   const bool active = idx < count;
   for (int t = tid; t < NP * NP; t += blockDim.x) sD[t] = m.ops[m.tab.D[N] + t];
+  // side points first, so that their dependent loads (side record, then the
+  // neighbour's node) overlap the element's own loads and the volume sums
+  for (int r = tid; r < EPB * 6 * NP2; r += blockDim.x) {
+    const int sl = r / (6 * NP2), rr = r - sl * 6 * NP2, sd = rr / NP2, fidx = rr - sd * NP2;
+    const int ix = blockIdx.x * EPB + sl;
+    if (ix >= count) continue;
+    const int e2 = elist[ix];
+    const SideRec sr = m.side_rec[6 * (int64_t)e2 + sd];
+    double x[NV];
+    if ((sr.code >> 10) & 1) {
+      const FacePoint fp = face_point<N>(sr, fidx % NP, fidx / NP);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) x[v] = u[v * m.n_node + fp.nbr_node];
+    } else {
+      const double* vs2 = m.vside + m.side_off[e2] + sd * NV * NP2 + fidx;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) x[v] = vs2[v * NP2];
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sSt[sl][sd][v][fidx] = x[v];
+  }
   int e = 0;
   int64_t base = 0;
   double ui[NV], ja[9];
@@ -161,13 +182,12 @@ lift_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const doub
     const double sg = (s & 1) ? inv_w0 : -inv_w0;
     const SideRec sr = srs[s];
     double jump[NV];
-    if ((sr.code >> 10) & 1) {             // same degree: u* from the neighbour's matching node
-      const FacePoint fp = face_point<N>(sr, fidx % NP, fidx / NP);
+    if ((sr.code >> 10) & 1) {             // same degree: u* = (u + u_nbr) / 2
 #pragma unroll
-      for (int v = 0; v < NV; ++v) jump[v] = 0.5 * (u[v * m.n_node + fp.nbr_node] - ui[v]);
+      for (int v = 0; v < NV; ++v) jump[v] = 0.5 * (sSt[slot][s][v][fidx] - ui[v]);
     } else {
 #pragma unroll
-      for (int v = 0; v < NV; ++v) jump[v] = vs[(s * NV + v) * NP2 + fidx] - ui[v];
+      for (int v = 0; v < NV; ++v) jump[v] = sSt[slot][s][v][fidx] - ui[v];
     }
 #pragma unroll
     for (int x = 0; x < 3; ++x) {
@@ -184,16 +204,17 @@ lift_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const doub
       acc[x][v] *= invJ;
       m.grad[(x * NV + v) * m.n_node + base] = acc[x][v];
     }
-  // half fluxes of the same-degree sides: F^v(u, g) . n_L
+  // half fluxes of the same-degree sides: F^v(u, g) . n with the element's own
+  // outward contravariant vector, which the face shares (up to rounding) with
+  // the neighbour's, reversed
   if (i == 0 || i == N || j == 0 || j == N || k == 0 || k == N) {
     double f[3][NV];
     viscous_flux<NV>(ui, acc, m.gas, m.visc, f);
     for_sides<N>(i, j, k, [&](int s, int fidx) {
-      const SideRec sr = srs[s];
-      if (!((sr.code >> 10) & 1)) return;
-      const FacePoint fp = face_point<N>(sr, fidx % NP, fidx / NP);
-      const double* nrm = m.face_norm + sr.nrm;
-      const double n0 = nrm[fp.left_fidx], n1 = nrm[NP2 + fp.left_fidx], n2 = nrm[2 * NP2 + fp.left_fidx];
+      if (!((srs[s].code >> 10) & 1)) return;
+      const int d = s >> 1;
+      const double sg = (s & 1) ? 1.0 : -1.0;
+      const double n0 = sg * ja[3 * d], n1 = sg * ja[3 * d + 1], n2 = sg * ja[3 * d + 2];
 #pragma unroll
       for (int v = 0; v < NV; ++v) vs[(s * NV + v) * NP2 + fidx] = f[0][v] * n0 + f[1][v] * n1 + f[2][v] * n2;
     });
@@ -208,18 +229,41 @@ visc_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const doub
   constexpr int NP = G::NP, NP2 = G::NP2, NP3 = G::NP3, EPB = G::EPB;
   __shared__ double sD[NP * NP];
   __shared__ double sF[EPB][3][NV][NP3];
+  __shared__ double sFo[EPB][6][NV][NP2];    // per side point: the outward viscous face flux
   const int tid = threadIdx.x;
   const int slot = tid / NP3, node = tid - slot * NP3;
   const int idx = blockIdx.x * EPB + slot;
   const bool active = idx < count;
   for (int t = tid; t < NP * NP; t += blockDim.x) sD[t] = m.ops[m.tab.D[N] + t];
+  // side points first: a same-degree side takes half the difference of its own
+  // outward half flux and the neighbour's (both from the lift kernel); a
+  // degree jump takes the face kernel's flux
+  for (int r = tid; r < EPB * 6 * NP2; r += blockDim.x) {
+    const int sl = r / (6 * NP2), rr = r - sl * 6 * NP2, sd = rr / NP2, fidx = rr - sd * NP2;
+    const int ix = blockIdx.x * EPB + sl;
+    if (ix >= count) continue;
+    const int e2 = elist[ix];
+    const SideRec sr = m.side_rec[6 * (int64_t)e2 + sd];
+    const double* own = m.vside + m.side_off[e2] + sd * NV * NP2 + fidx;
+    double x[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) x[v] = own[v * NP2];
+    if ((sr.code >> 10) & 1) {
+      const FacePoint fp = face_point<N>(sr, fidx % NP, fidx / NP);
+      const double* hn = m.vside + m.side_off[sr.nbr] + fp.nbr_side * NV * NP2 + fp.nbr_fidx;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) x[v] = 0.5 * (x[v] - hn[v * NP2]);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sFo[sl][sd][v][fidx] = x[v];
+  }
   int e = 0;
   int64_t base = 0;
-  double Ft[3][NV], f[3][NV];
+  double Ft[3][NV];
   if (active) {
     e = elist[idx];
     base = m.elem_offset[e] + node;
-    double ui[NV], gr[3][NV];
+    double ui[NV], gr[3][NV], f[3][NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) ui[v] = u[v * m.n_node + base];
 #pragma unroll
@@ -258,27 +302,11 @@ visc_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const doub
     }
   }
   const double inv_w0 = 1.0 / m.ops[m.tab.w[N]];
-  const double* fs = m.vside + m.side_off[e];
-  const SideRec* srs = m.side_rec + 6 * (int64_t)e;
   for_sides<N>(i, j, k, [&](int s, int fidx) {
     const int d = s >> 1;
     const double sg = (s & 1) ? 1.0 : -1.0;
-    const SideRec sr = srs[s];
-    double Fo[NV];
-    if ((sr.code >> 10) & 1) {             // same degree: (own . n_L + the neighbour's half) / 2, outward
-      const FacePoint fp = face_point<N>(sr, fidx % NP, fidx / NP);
-      const double* nrm = m.face_norm + sr.nrm;
-      const double n0 = nrm[fp.left_fidx], n1 = nrm[NP2 + fp.left_fidx], n2 = nrm[2 * NP2 + fp.left_fidx];
-      const double* hn = m.vside + m.side_off[sr.nbr] + fp.nbr_side * NV * NP2 + fp.nbr_fidx;
-      const double so = ((sr.code >> 9) & 1) ? 0.5 : -0.5;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) Fo[v] = so * ((f[0][v] * n0 + f[1][v] * n1 + f[2][v] * n2) + hn[v * NP2]);
-    } else {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) Fo[v] = fs[(s * NV + v) * NP2 + fidx];
-    }
-#pragma unroll
-    for (int v = 0; v < NV; ++v) acc[v] += (Fo[v] - sg * Ft[d][v]) * inv_w0;
+    for (int v = 0; v < NV; ++v) acc[v] += (sFo[slot][s][v][fidx] - sg * Ft[d][v]) * inv_w0;
   });
   const double invJ = 1.0 / m.metric[9 * m.n_node + base];
 #pragma unroll
