@@ -560,13 +560,14 @@ void enqueue_limiter(const dgfv_mesh* m, double* u, const double* alpha, double*
 // launched.
 // Viscous rate of u into m->rvisc (Section 3.1.1, Section 3.2.2): the BR1 face
 // values, the lifted gradient, the viscous face fluxes, the volume terms.
-void enqueue_viscous(const dgfv_mesh* m, const double* u, hipStream_t s) {
+void enqueue_viscous(const dgfv_mesh* m, const double* u, hipStream_t s, bool trace_in) {
   const MeshView& v = m->view;
   const std::vector<int> degs = degrees_present(m);
   Timed t(m, DGFV_KERNEL_VISCOUS, s);
   hip_check(launch_lift_faces(v, u, s), "lift face launch");
   fork_join(m, s, degs, [&](int N, hipStream_t ss) {
-    hip_check(viscous_ops_for(N).lift(v, m->d_bucket[N], (int)m->bucket[N].size(), u, ss), "lift launch");
+    hip_check(viscous_ops_for(N).lift(v, m->d_bucket[N], (int)m->bucket[N].size(), u, trace_in, ss),
+              "lift launch");
   });
   hip_check(launch_visc_faces(v, u, s), "viscous face launch");
   fork_join(m, s, degs, [&](int N, hipStream_t ss) {
@@ -582,7 +583,7 @@ void enqueue_rhs_impl(const dgfv_mesh* m, const ParamsDev& p, const double* u, d
   const double A = stage > 0 ? RK_A[stage - 1] : 0.0;
   const double B = stage > 0 ? RK_B[stage - 1] : 0.0;
   const std::vector<int> degs = degrees_present(m);
-  if (m->viscous) enqueue_viscous(m, u, s);
+  if (m->viscous) enqueue_viscous(m, u, s, trace_in);
   if (alpha) {
     Timed t(m, DGFV_KERNEL_FV_MEANS, s);
     hip_check(launch_blend_list(v, alpha, s), "blended list launch");
@@ -1623,7 +1624,8 @@ dgfv_status dg_lift(const dgfv_mesh* m, const double* u, double* g, void* stream
     hip_check(launch_lift_faces(v, u, s), "lift face launch");
     for (int N = 1; N <= MAXN; ++N)
       if (!m->bucket[N].empty())
-        hip_check(viscous_ops_for(N).lift(v, m->d_bucket[N], (int)m->bucket[N].size(), u, s), "lift launch");
+        hip_check(viscous_ops_for(N).lift(v, m->d_bucket[N], (int)m->bucket[N].size(), u, false, s),
+                  "lift launch");
   } catch (const HipError& e) {
     return fail(DGFV_ERR_HIP, e.what());
   }

@@ -177,7 +177,10 @@ struct DegreeOps {
 //  lift    m.grad = BR1-lifted gradient of u, from the face values in m.vside
 //  volume  rv = -(1/J) [viscous volume term + viscous face fluxes of m.vside]
 struct ViscousOps {
-  hipError_t (*lift)(const MeshView& m, const int32_t* elist, int count, const double* u, hipStream_t s);
+  // trace_in: the neighbours' sides 0 and 1 come from m.trace (written by the
+  // previous RK stage's element kernels, degrees >= TRACE_MIN_N)
+  hipError_t (*lift)(const MeshView& m, const int32_t* elist, int count, const double* u, bool trace_in,
+                     hipStream_t s);
   hipError_t (*volume)(const MeshView& m, const int32_t* elist, int count, const double* u, double* rv,
                        hipStream_t s);
   // time step per element: dt_e[e] convective, dt_e[K + e] parabolic (0 unless viscous)

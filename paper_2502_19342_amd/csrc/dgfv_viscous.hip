@@ -11,7 +11,9 @@
 //                 contravariant vectors at its boundary nodes.  On a side
 //                 shared with an element of the same degree the node forms
 //                 u* = (u + u_nbr) / 2 itself from the neighbour's matching
-//                 node; at a degree jump u* comes from m.vside.  Its boundary
+//                 node (the neighbour's xi_1 ends from the traces of the
+//                 previous RK stage where it wrote them); at a degree jump u*
+//                 comes from m.vside.  Its boundary
 //                 nodes then leave the viscous flux of (u, g) dotted with the
 //                 element's own outward contravariant vector in m.vside for
 //                 each same-degree side: half of that face's viscous flux.
@@ -95,7 +97,8 @@ __device__ __forceinline__ void for_sides(int i, int j, int k, F&& f) {
 
 template <int N, int NV>
 __global__ void __launch_bounds__(VGeo<N>::EPB * VGeo<N>::NP3)
-lift_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const double* __restrict__ u) {
+lift_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const double* __restrict__ u,
+            const double* __restrict__ trace) {
   using G = VGeo<N>;
   constexpr int NP = G::NP, NP2 = G::NP2, NP3 = G::NP3, EPB = G::EPB;
   __shared__ double sD[NP * NP];
@@ -118,8 +121,14 @@ lift_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const doub
     double x[NV];
     if ((sr.code >> 10) & 1) {
       const FacePoint fp = face_point<N>(sr, fidx % NP, fidx / NP);
+      if (trace && fp.nbr_side < 2) {      // the neighbour's xi_1 ends, contiguous in the traces
+        const double* t = trace + m.side_off[sr.nbr] / 3 + fp.nbr_side * NV * NP2 + fp.nbr_fidx;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) x[v] = u[v * m.n_node + fp.nbr_node];
+        for (int v = 0; v < NV; ++v) x[v] = t[v * NP2];
+      } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) x[v] = u[v * m.n_node + fp.nbr_node];
+      }
     } else {
       const double* vs2 = m.vside + m.side_off[e2] + sd * NV * NP2 + fidx;
 #pragma unroll
@@ -390,14 +399,16 @@ timestep_kernel(MeshView m, const int32_t* __restrict__ elist, int count, const 
 }
 
 namespace per_degree {
-hipError_t lift(const MeshView& m, const int32_t* elist, int count, const double* u, hipStream_t s) {
+hipError_t lift(const MeshView& m, const int32_t* elist, int count, const double* u, bool trace_in,
+                hipStream_t s) {
   using G = VGeo<kN>;
   if (count <= 0) return hipSuccess;
   const int blocks = (count + G::EPB - 1) / G::EPB;
+  const double* tr = trace_in && kN >= TRACE_MIN_N ? m.trace : nullptr;
   if (m.nvar == 5)
-    hipLaunchKernelGGL((lift_kernel<kN, 5>), dim3(blocks), dim3(G::EPB * G::NP3), 0, s, m, elist, count, u);
+    hipLaunchKernelGGL((lift_kernel<kN, 5>), dim3(blocks), dim3(G::EPB * G::NP3), 0, s, m, elist, count, u, tr);
   else
-    hipLaunchKernelGGL((lift_kernel<kN, 6>), dim3(blocks), dim3(G::EPB * G::NP3), 0, s, m, elist, count, u);
+    hipLaunchKernelGGL((lift_kernel<kN, 6>), dim3(blocks), dim3(G::EPB * G::NP3), 0, s, m, elist, count, u, tr);
   return hipGetLastError();
 }
 

@@ -154,6 +154,13 @@ def main(src, dst):
             check(lib.dg_rk_step(h, ctypes.byref(prm), ctypes.c_double(float(z["dt"])), ptr(uu), ptr(k),
                                  ptr(alpha), None), "dg_rk_step")
             out["rk_step"] = uu
+        elif call == "rk_stages":               # five dg_rk_stage calls: no traces between them
+            uu = u.copy()
+            k = np.empty_like(u)
+            for st in range(1, 6):
+                check(lib.dg_rk_stage(h, ctypes.byref(prm), ctypes.c_int(st), ctypes.c_double(float(z["dt"])),
+                                      ptr(uu), ptr(k), ptr(alpha), None), "dg_rk_stage")
+            out["rk_stages"] = uu
         elif call == "indicator":
             a = np.empty(K)
             ind = np.empty(K)

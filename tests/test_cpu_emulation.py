@@ -301,3 +301,17 @@ def test_cpu_build_timestep(n_var, viscous):
     out = cpu_emu.run(wl, c.u.numpy(), ["timestep"], alpha=c.alpha.numpy(), cfl=np.array([0.6, 0.3]))
     want = lsrk.timestep(c.mesh, c.gas, c.u, 0.6, c.alpha, P.transport_of(wl) if viscous else None, 0.3)
     assert abs(float(out["timestep"][0]) - want) <= 1e-13 * want
+
+
+def test_cpu_build_viscous_step_with_traces():
+    # degrees 6 and 7: dg_rk_step's lift reads the neighbours' xi_1 sides from the
+    # stage traces; five dg_rk_stage calls read u; both equal, and match the oracle
+    import dataclasses
+    wl = curved_mixed(n=2, nmin=6, nmax=7, scramble=31, metric_degree=0, n_fv=8)
+    wl = dataclasses.replace(wl, mu=(0.02, 0.03), Pr=(0.7, 0.9))
+    c = _case(wl, smooth_state(71, 5), noise=1e-3, seed=8)
+    dt = 0.3 * lsrk.timestep(c.mesh, c.gas, c.u, 0.5)
+    out = cpu_emu.run(wl, c.u.numpy(), ["rk_step", "rk_stages"], dt=dt)
+    assert np.array_equal(out["rk_step"], out["rk_stages"])
+    want = lsrk.step(lambda v: c.f(v, c.alpha), c.u, dt)
+    assert rel_err(torch.as_tensor(out["rk_step"]), want) <= 1e-11

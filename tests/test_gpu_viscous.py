@@ -68,6 +68,24 @@ def test_viscous_rk_steps_with_graphs():
     assert err <= 1e-10
 
 
+def test_viscous_step_with_traces_equals_stages():
+    # degrees 6 and 7: between the stages of dg_rk_step the lift kernel reads the
+    # neighbours' xi_1 sides from the traces; five dg_rk_stage calls read them from u
+    announce("viscous step with traces, N=6,7")
+    from paper_2502_19342_amd import dgfv
+    c = Case(_wl(5, n=3, nmin=6, nmax=7, scramble=31, n_fv=8), prim=smooth_state(71), noise=1e-3, seed=8)
+    dt = 0.3 * lsrk.timestep(c.mesh, c.gas, c.u, 0.5)
+    a, b = c.gpu(c.u), c.gpu(c.u)
+    ka, kb = torch.zeros_like(a), torch.zeros_like(b)
+    dgfv.rk_step(c.gmesh, c.params, dt, a, ka, None)
+    for st in range(1, 6):
+        dgfv.rk_stage(c.gmesh, c.params, st, dt, b, kb, None)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    uo = lsrk.step(lambda v: c.f(v, c.alpha), c.u, dt)
+    assert rel_err(a.cpu(), uo) <= 1e-11
+
+
 def test_viscous_switch_and_unsupported_calls():
     announce("viscous on/off, unsupported calls")
     from paper_2502_19342_amd import dgfv
