@@ -255,6 +255,9 @@ class OracleMesh:
         self.offset = spec.elem_offset()
         self.n_node = int(self.offset[-1])
         self.faces = np.asarray(spec.faces, dtype=np.int64)
+        self.mortars = np.asarray(getattr(spec, "mortars", np.zeros((0, 15))), dtype=np.int64).reshape(-1, 15)
+        if len(self.mortars) and self.NJ == 0:
+            raise ValueError("meshes with mortars take a mesh-wide metric degree (metric_degree >= 1)")
 
     # ---- flat <-> grouped state ----------------------------------------
     def gather(self, u: torch.Tensor, N: int) -> torch.Tensor:

@@ -243,3 +243,64 @@ def face_interp(N: int, NFV: int) -> np.ndarray:
     x, _ = lgl_mp(N)
     h = mp.mpf(2) / NFV
     return _f64([_lagrange_row(x, -1 + q * h) for q in range(NFV + 1)])
+
+
+# ---------------------------------------------------------------------------
+# mortars (Section 3.2.3): a big side and its two halves along one direction
+# ---------------------------------------------------------------------------
+@functools.lru_cache(maxsize=None)
+def mortar_interp(N: int, k: int) -> np.ndarray:
+    """``M_{0k}[i, j] = l_j((s_i + 2k - 1) / 2)``: the big side's degree-N polynomial at the
+    degree-N nodes ``s_i`` of its half ``k`` (0: [-1, 0], 1: [0, 1]) in the half's own coordinate."""
+    x, _ = lgl_mp(N)
+    return _f64([_lagrange_row(x, (t + 2 * k - 1) / 2) for t in x])
+
+
+@functools.lru_cache(maxsize=None)
+def mortar_project(N: int, k: int) -> np.ndarray:
+    """``M_{k0}``: the big side's share of a degree-N polynomial ``F_k`` given on half ``k``.
+
+    The big side's flux is the L2 projection onto degree N over [-1, 1] of the
+    function that equals ``2 F_k`` on half k (the half's surface element is half
+    the big side's, so its flux per unit of its own length is half), zero on the
+    other half: with Legendre polynomials ``L_j``,
+    ``c_j = (2j + 1)/2 int_{-1}^{1} F_k(s) L_j((s + 2k - 1)/2) ds``,
+    ``F_0(xi_i) = sum_j c_j L_j(xi_i)``.  Summed over both halves this projects
+    the piecewise flux; it keeps ``sum_i w_i F_0`` equal to the halves' sums,
+    and ``(M_{00} M_{00} + M_{10} M_{01}) / 2`` (projection after interpolation
+    to each half) is the identity: a big-side polynomial comes back.
+    """
+    x, _ = lgl_mp(N)
+    n = N + 1
+    gx, gw = _gauss_legendre(n + 1)                  # exact for the degree-2N integrands
+    C = [[mp.mpf(0)] * n for _ in range(n)]          # C[j][l] = (2j+1)/2 int l_l(s) L_j(...) ds
+    for s, w in zip(gx, gw):
+        lrow = _lagrange_row(x, s)
+        t = (s + 2 * k - 1) / 2
+        for j in range(n):
+            pj, _ = _legendre(j, t)
+            f = mp.mpf(2 * j + 1) / 2 * w * pj
+            for l in range(n):
+                C[j][l] += f * lrow[l]
+    rows = []
+    for xi in x:
+        Lrow = [_legendre(j, xi)[0] for j in range(n)]
+        rows.append([sum(Lrow[j] * C[j][l] for j in range(n)) for l in range(n)])
+    return _f64(rows)
+
+
+def _gauss_legendre(m: int):
+    """Nodes and weights of the m-point Gauss-Legendre rule (Newton on P_m)."""
+    xs, ws = [], []
+    for i in range(1, m + 1):
+        z = mp.cos(mp.pi * (i - mp.mpf(1) / 4) / (m + mp.mpf(1) / 2))
+        for _ in range(100):
+            p, dp = _legendre(m, z)
+            dz = p / dp
+            z -= dz
+            if abs(dz) < mp.mpf(10) ** (-35):
+                break
+        p, dp = _legendre(m, z)
+        xs.append(z)
+        ws.append(2 / ((1 - z * z) * dp * dp))
+    return xs, ws

@@ -28,6 +28,14 @@ Interfaces (Section 3.2.1):
   of blended sides directly and the DG surface terms of both sides through
   ``V^{FV->DG}``.
 
+Non-conforming faces (Section 3.2.3, mortar types 1-3, DG sides): see
+``Rhs._mortar_fluxes``; the big side's flux is the sum over its halves or
+quarters of ``M_{k0}`` applied to their fluxes (``ops1d.mortar_project``).
+Readings: the small side's own normal (reversed) carries the flux, so the
+big side's share needs no surface-element factor (``M_{k0}`` is the L2
+projection of twice the half's flux per direction of the split); elements at a
+mortar must be pure DG (the FV mortar variants ``M^FV`` are not built).
+
 FV part (eq. semidiscrete_fv, first order): sub-cell contents
 ``C = h^3 V3(J u)`` and volumes ``h^3 V3(J)`` give the means
 ``ubar = C / vol``; each sub-cell face carries a Riemann flux with normal
@@ -217,6 +225,13 @@ class Rhs:
                     Ffv[NL][a][sL] = Fs[r]
                     Ffv[NR][b][sR] = FsR[r]
 
+        if len(m.mortars):
+            touched = np.unique(np.concatenate([m.mortars[:, 0], m.mortars[:, 3:7].reshape(-1)]))
+            touched = touched[touched >= 0]
+            if (alpha_np[touched] > 0).any():
+                raise NotImplementedError("FV-blended elements at mortars (the FV mortar variants) are not built")
+            self._mortar_fluxes(U, Fdg)
+
         out = {}
         for N, g in m.groups.items():
             n = N + 1
@@ -238,6 +253,57 @@ class Rhs:
         return m.scatter(out, nvar)
 
     # ------------------------------------------------------------------
+    def _mortar_fluxes(self, U, Fdg):
+        """Side fluxes of the non-conforming faces (Section 3.2.3, its five steps, DG sides).
+
+        For each small side k of a big side: the big side's trace interpolated to
+        the virtual small side (``M_{0k}`` along the split directions, at the big
+        side's degree N_0); the small side's trace brought onto that grid by the
+        orientation; both, and the small side's normal (its outward one reversed,
+        so that it carries the small side's surface element), on the common
+        degree ``max(N_0, N_k)``; the Riemann flux there; the small side receives
+        its projection to N_k, reversed; the big side receives the projection to
+        N_0 mapped with ``M_{k0}`` along the split directions, summed over k.
+        """
+        m, gas, prm = self.mesh, self.gas, self.params
+        deg = m.degree
+        for row in m.mortars.tolist():
+            e0, s0, mt = row[0], row[1], row[2]
+            N0 = int(deg[e0])
+            sl0 = int(m.slot[e0])
+            u0 = face_slice(U[N0][sl0:sl0 + 1], s0)[0]           # [nvar, n0, n0] on the big side's grid
+            F0 = torch.zeros_like(u0)
+            nsub = 4 if mt == 3 else 2
+            for k in range(nsub):
+                ek, sk, ok = row[3 + k], row[7 + k], row[11 + k]
+                kp, kq = (k, None) if mt == 1 else ((None, k) if mt == 2 else (k % 2, k // 2))
+                uv = u0
+                if kp is not None:
+                    uv = apply_axis(_t(ops1d.mortar_interp(N0, kp)), uv, 0)
+                if kq is not None:
+                    uv = apply_axis(_t(ops1d.mortar_interp(N0, kq)), uv, 1)
+                Nk = int(deg[ek])
+                slk = int(m.slot[ek])
+                gk = m.groups[Nk]
+                tk = to_left(face_slice(U[Nk][slk:slk + 1], sk), ok)[0]
+                nk = -to_left(gk.outward_normal(sk)[slk:slk + 1], ok)[0]
+                M = max(N0, Nk)
+                if N0 < M:
+                    uv = apply2(_t(ops1d.interp(N0, M)), uv)
+                if Nk < M:
+                    Vk = _t(ops1d.interp(Nk, M))
+                    tk, nk = apply2(Vk, tk), apply2(Vk, nk)
+                F = riemann(prm.face_flux_dg, uv, tk, nk, gas, prm.volume_flux)   # [nvar, M+1, M+1]
+                Fs = apply2(_t(ops1d.project(M, Nk)), F) if Nk < M else F
+                Fdg[Nk][slk][sk] = -to_right(Fs[None], ok)[0]
+                Fb = apply2(_t(ops1d.project(M, N0)), F) if N0 < M else F
+                if kp is not None:
+                    Fb = apply_axis(_t(ops1d.mortar_project(N0, kp)), Fb, 0)
+                if kq is not None:
+                    Fb = apply_axis(_t(ops1d.mortar_project(N0, kq)), Fb, 1)
+                F0 = F0 + Fb
+            Fdg[N0][sl0][s0] = F0
+
     @staticmethod
     def _lift(side, E, nvar, n, w0):
         """Place each side's outward flux on its boundary nodes, divided by the end weight."""

@@ -49,6 +49,9 @@ class MeshSpec:
     faces: np.ndarray           # [F, 5] int32 (eL, sideL, eR, sideR, orient)
     degree: np.ndarray          # [K] int8
     rotation: np.ndarray = field(default=None)  # [K] int, index into ROTATIONS
+    # non-conforming faces, one row per big side (see mortar_mesh):
+    # (big element, big side, type, small elements[4], small sides[4], orientations[4])
+    mortars: np.ndarray = field(default_factory=lambda: np.zeros((0, 15), dtype=np.int32))
 
     @property
     def n_elem(self) -> int:
@@ -200,6 +203,156 @@ def structured_mesh(n: int, lo, hi, degree, displacement=None,
     else:
         deg = np.full(K, int(degree), dtype=np.int8)
     return MeshSpec(n=n, lo=lo, hi=hi, corners=corners, faces=faces, degree=deg, rotation=rot)
+
+
+def mortar_mesh(n: int, refine: str = "yz", degree=3, scramble_seed: int | None = None,
+                amp: float = 0.0) -> MeshSpec:
+    """Periodic unit box, coarse for x < 1/2 and refined for x > 1/2: a 2:1 non-conforming interface
+    at x = 1/2 and at x = 0 (= 1).
+
+    Coarse cells have side h = 1/n (n even, >= 4); fine cells halve h in the
+    directions of ``refine`` ("y": each coarse face meets two fine faces,
+    mortar type 1 or 2 depending on the big side's frame; "yz": four, type 3).
+    ``degree``: an int, or a pair (coarse, fine), or a callable of the centres.
+    ``scramble_seed`` rotates each element's local frame; ``amp`` displaces the
+    vertices by ``amp prod_d sin 2 pi (x_d + 1/8)`` (box units, non-zero on the
+    interfaces), the fine vertices hanging on a
+    coarse face then placed on that face's bilinear surface, so that the small
+    faces tile the big one exactly (with a metric degree of at least 2 the
+    face-normal polynomials are exact and a small side's normal is the
+    restriction of the big side's).
+
+    Mortar rows: ``(big element, big side, type, e_0..e_3, s_0..s_3, o_0..o_3)``
+    (unused entries -1).  Type 1 splits the big side's face grid along ``p``
+    into halves k = 0, 1 (p in [-1, 0], [0, 1]); type 2 along ``q``; type 3 both,
+    k = kp + 2 kq.  ``o_k`` maps the half's face grid, with ``p``, ``q`` along
+    the big side's, to the small side's grid as a face orientation does (the
+    big side as the left one).
+    """
+    if n < 4 or n % 2:
+        raise ValueError("need an even n >= 4 (below it the periodic corner keys of two faces coincide)")
+    if refine not in ("y", "yz"):
+        raise ValueError("refine is 'y' or 'yz'")
+    Lt = 2 * n                                           # lattice points per direction (unit h/2)
+    cells = []                                           # (lattice min corner, lattice size)
+    for iz in range(n):
+        for iy in range(n):
+            for ix in range(n // 2):
+                cells.append(((2 * ix, 2 * iy, 2 * iz), (2, 2, 2)))
+    fy = 1 if "y" in refine else 2
+    fz = 1 if "z" in refine else 2
+    for iz in range(0, Lt, fz):
+        for iy in range(0, Lt, fy):
+            for ix in range(n, Lt, 2):
+                cells.append(((ix, iy, iz), (2, fy, fz)))
+    K = len(cells)
+    cmin = np.array([c[0] for c in cells], dtype=np.int64)
+    csz = np.array([c[1] for c in cells], dtype=np.int64)
+    rng = np.random.default_rng(scramble_seed) if scramble_seed is not None else None
+    rot = np.zeros(K, dtype=np.int64) if rng is None else rng.integers(0, 24, size=K)
+    bits = np.array([[(c >> d) & 1 for d in range(3)] for c in range(8)], dtype=np.int64)
+
+    def corner_lattice(e, xi):                           # local reference corner (+-1) -> lattice point
+        off = (ROTATIONS[rot[e]] @ xi + 1) // 2
+        return cmin[e] + off * csz[e]
+
+    # vertex positions: displaced lattice points; hanging ones on the coarse faces' bilinear surfaces
+    h2 = 0.5 / n
+
+    def disp(pt):
+        x = pt * h2
+        if amp:                                          # phase 1/8: non-zero on the interfaces x = 0, 1/2
+            w = np.prod(np.sin(2 * np.pi * (x + 0.125)))
+            x = x + amp * w
+        return x
+
+    def vertex(pt):
+        pt = np.asarray(pt, dtype=np.int64)
+        hang = (pt[0] % Lt in (0, n)) and (pt[1] % 2 or pt[2] % 2)
+        if not hang:
+            return disp(pt)
+        ys = [pt[1]] if pt[1] % 2 == 0 else [pt[1] - 1, pt[1] + 1]
+        zs = [pt[2]] if pt[2] % 2 == 0 else [pt[2] - 1, pt[2] + 1]
+        return np.mean([disp(np.array([pt[0], y, z])) for y in ys for z in zs], axis=0)
+
+    corners = np.zeros((K, 8, 3))
+    for e in range(K):
+        for c in range(8):
+            corners[e, c] = vertex(corner_lattice(e, 2 * bits[c] - 1))
+
+    def key(pt):
+        return tuple(int(v) % Lt for v in pt)
+
+    def side_corners(e, side):                           # lattice corner of (p, q) in {0,1}^2
+        return {(p, q): corner_lattice(e, _local_face_corner(side, p, q)) for p in (0, 1) for q in (0, 1)}
+
+    sides = {}                                           # corner-key set -> the sides that have it
+    for e in range(K):
+        for sd in range(6):
+            sc = side_corners(e, sd)
+            sides.setdefault(frozenset(key(v) for v in sc.values()), []).append(
+                (e, sd, {key(v): pq for pq, v in sc.items()}))
+
+    def orientation(big_keys, small):                    # big_keys[(a, b)] -> key; small: (e, s, key -> (p', q'))
+        for o in range(8):
+            if all(small[2].get(big_keys[(a, b)]) == orient_map(o, a, b, 2) for a in (0, 1) for b in (0, 1)):
+                return o
+        raise RuntimeError("mortar orientation not found")
+
+    faces, mortars, done = [], [], set()
+    for e in range(K):
+        for sd in range(6):
+            if (e, sd) in done:
+                continue
+            sc = side_corners(e, sd)
+            ks = frozenset(key(v) for v in sc.values())
+            other = [v for v in sides[ks] if (v[0], v[1]) != (e, sd)]
+            if other:
+                f, sf, kmap = other[0]
+                o = orientation({pq: key(v) for pq, v in sc.items()}, other[0])
+                faces.append((e, sd, f, sf, o))
+                done.update({(e, sd), (f, sf)})
+                continue
+            # a big side: find its halves or quarters among the other sides
+            P = {pq: v.astype(np.float64) for pq, v in sc.items()}
+
+            def at(u, v):                                # bilinear lattice point of the big face, (u, v) in [0,1]^2
+                x = (1 - u) * (1 - v) * P[(0, 0)] + u * (1 - v) * P[(1, 0)] + (1 - u) * v * P[(0, 1)] + u * v * P[(1, 1)]
+                return np.rint(x).astype(np.int64)
+            found = None
+            for mtype, parts in ((3, [(kp, kq) for kq in (0, 1) for kp in (0, 1)]), (1, [(0, None), (1, None)]),
+                                 (2, [(None, 0), (None, 1)])):
+                subs = []
+                for kp, kq in parts:
+                    up = (0.0, 0.5) if kp == 0 else ((0.5, 1.0) if kp == 1 else (0.0, 1.0))
+                    vq = (0.0, 0.5) if kq == 0 else ((0.5, 1.0) if kq == 1 else (0.0, 1.0))
+                    bk = {(a, b): key(at(up[a], vq[b])) for a in (0, 1) for b in (0, 1)}
+                    cand = sides.get(frozenset(bk.values()), [])
+                    if len(cand) != 1:
+                        break
+                    sm = cand[0]
+                    subs.append((sm, orientation(bk, sm)))
+                else:
+                    found = (mtype, subs)
+                    break
+            if found is None:
+                raise RuntimeError(f"side {sd} of element {e} has no partner")
+            mtype, subs = found
+            row = [e, sd, mtype] + [-1] * 12
+            for k, (sm, o) in enumerate(subs):
+                row[3 + k], row[7 + k], row[11 + k] = sm[0], sm[1], o
+                done.add((sm[0], sm[1]))
+            mortars.append(row)
+            done.add((e, sd))
+    centres = corners.mean(axis=1)
+    if callable(degree):
+        deg = np.asarray(degree(centres), dtype=np.int8)
+    elif isinstance(degree, tuple):
+        deg = np.where(centres[:, 0] < 0.5, degree[0], degree[1]).astype(np.int8)
+    else:
+        deg = np.full(K, int(degree), dtype=np.int8)
+    return MeshSpec(n=n, lo=np.zeros(3), hi=np.ones(3), corners=corners, faces=np.asarray(faces, dtype=np.int32),
+                    degree=deg, rotation=rot, mortars=np.asarray(mortars, dtype=np.int32).reshape(-1, 15))
 
 
 def sine_displacement(lo, hi, amp: float):
