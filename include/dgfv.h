@@ -74,8 +74,20 @@ enum { DGFV_RIEMANN_ROE_HH = 0, /* Roe with the Harten-Hyman entropy fix, 1 spec
  * reference direction, q along the higher one.  `orient` maps the left
  * side's (p, q) on an n x n grid to the right side's (p', q'): (a, b) = (q, p)
  * if bit 2 is set, else (p, q); then p' = n-1-a if bit 0, else a; q' = n-1-b
- * if bit 1, else b.  Every element side must appear in exactly one face
- * (periodic, conforming meshes).
+ * if bit 1, else b.  Every element side must appear in exactly one face or
+ * mortar (periodic meshes).
+ * Mortars (non-conforming faces, Section 3.2.3, fig. mortarTypes): row
+ * {e0, s0, type, e_0..e_3, s_0..s_3, o_0..o_3} gives a big side (element e0,
+ * side s0) and its small sides.  Type 1 splits the big side's face grid along
+ * p into halves k = 0 (p in [-1, 0]) and 1; type 2 along q; type 3 both, into
+ * quarters k = kp + 2 kq.  o_k maps the half's (or quarter's) face grid, p and
+ * q along the big side's, to the small side's grid as `orient` does for a
+ * face with the big side on the left; unused entries are -1.  The big side's
+ * flux follows the paper's five steps for DG sides (see dg_rhs).  Meshes with
+ * mortars need metric_degree >= 1 (>= 2 on curved elements, where the face
+ * normals of a small side must be the restriction of the big side's); they
+ * take alpha = NULL (the FV mortar variants are not built) and no viscous
+ * terms, FV-stored elements, face fusion or adjoint (DGFV_ERR_UNSUPPORTED).
  * Metrics Ja^d are formed in the conservative curl form (Section 3.1.1):
  *  - metric_degree >= 1 (at most min N_e): on the degree-metric_degree nodes,
  *    interpolated to each element's degree;
@@ -99,6 +111,8 @@ typedef struct {
   double gamma;            /* ratio of specific heats, n_var = 5        */
   double kappa[2];         /* species heat-capacity ratios, n_var = 6   */
   double R[2];             /* species gas constants, n_var = 6          */
+  int32_t n_mortar;        /* non-conforming faces (0: a conforming mesh) */
+  const int32_t* mortars;  /* [n_mortar][15], see below, or NULL        */
 } dgfv_mesh_desc;
 
 typedef struct {
@@ -110,7 +124,16 @@ typedef struct {
   double ind_dT;           /* blending ramp half-width (> 0)                       */
 } dgfv_params;
 
-/* Build the device geometry of a mesh (synchronous; allocates device memory). */
+/* Build the device geometry of a mesh (synchronous; allocates device memory).
+ * Mortar faces: for each small side k of a big side of degree N0, the big
+ * trace is interpolated to the half (quarter) k, M_0k(xi) = l_j((xi + 2k - 1)/2)
+ * along the split directions; it and the small side's trace (degree N_k) go to
+ * the common degree max(N0, N_k); the Riemann flux of the DG faces is taken
+ * there with the small side's outward normal reversed; the small side
+ * receives its projection to N_k, reversed; the big side receives the
+ * projection to N0 mapped with M_k0, the L2 projection of twice the half's
+ * flux per split direction (the half's surface element is half the big
+ * side's), summed over k. */
 dgfv_status dgfv_mesh_create(const dgfv_mesh_desc* desc, dgfv_mesh** out);
 void dgfv_mesh_destroy(dgfv_mesh* mesh);
 

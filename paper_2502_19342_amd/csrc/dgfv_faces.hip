@@ -975,6 +975,134 @@ visc_face_mixed_kernel(MeshView m, const double* __restrict__ u) {
     map2d_sep_side<NV>(bR, Fb, SR, m.ops + m.tab.project[M][lo], nlo, nM, sideR, o, true, -1.0);
 }
 
+// dst[f][qq][pp] = sum_q Aq[qq][q] sum_p Ap[pp][p] src[f][q][p] on an n x n face
+// grid, a null matrix standing for the identity; T aliases neither src nor
+// dst; one wave_sync inside, the caller synchronises around the call.
+template <int NF>
+__device__ void map2d_pq(const double* src, double* T, double* dst, const double* Ap, const double* Aq, int n) {
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+    const int pp = t % n, q = t / n;
+    if (Ap) {
+      double a[MAXN + 1];
+      load_row(Ap, n, pp, a);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) T[f * GRID + t] = dot_row(a, src + f * GRID + q * n, 1, n);
+    } else {
+#pragma unroll
+      for (int f = 0; f < NF; ++f) T[f * GRID + t] = src[f * GRID + t];
+    }
+  }
+  wave_sync();
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+    const int pp = t % n, qq = t / n;
+    if (Aq) {
+      double a[MAXN + 1];
+      load_row(Aq, n, qq, a);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) dst[f * GRID + t] = dot_row(a, T + f * GRID + pp, n, n);
+    } else {
+#pragma unroll
+      for (int f = 0; f < NF; ++f) dst[f * GRID + t] = T[f * GRID + t];
+    }
+  }
+}
+
+// Non-conforming faces (Section 3.2.3, the five steps for DG sides), one
+// mortar per one-wavefront workgroup.  For each small side k: (1) the big
+// side's trace interpolated to half (quarter) k with M_0k along the split
+// directions; (2) it, the small side's trace on the half's grid (orientation
+// o_k) and the small side's outward normal reversed, on the common degree
+// max(N0, N_k); (3) the DG Riemann flux there; (4) the small side receives its
+// projection to N_k, reversed, and the big side's share is projected to N0;
+// (5) that share is mapped with M_k0 along the split directions and summed
+// into the big side's flux.
+template <int NV>
+__global__ void __launch_bounds__(FACE_THREADS)
+face_mortar_kernel(MeshView m, ParamsDev prm, const double* __restrict__ u) {
+  __shared__ double sB[NV * GRID];    // big side's trace
+  __shared__ double sA[NV * GRID];    // big side's flux, summed over its small sides
+  __shared__ double sV[NV * GRID];    // the half's data from the big side (degree N0)
+  __shared__ double sS[NV * GRID];    // small side's trace on the half's grid (degree N_k)
+  __shared__ double sN[3 * GRID];     // small side's normal, reversed
+  __shared__ double sVM[NV * GRID];   // the three on the common degree
+  __shared__ double sSM[NV * GRID];
+  __shared__ double sNM[3 * GRID];
+  __shared__ double sF[NV * GRID];    // flux on the common degree
+  __shared__ double sT[NV * GRID];    // scratch of the two-pass maps
+  __shared__ double sT2[NV * GRID];
+  const int qm = blockIdx.x;
+  if (qm >= m.n_mortar) return;
+  const int32_t* mr = m.mortars + 15 * qm;
+  const int e0 = mr[0], s0 = mr[1], mt = mr[2];
+  const int N0 = m.degree[e0], n0 = N0 + 1;
+  const int nsub = mt == 3 ? 4 : 2;
+  gather_trace<NV>(m, u, e0, s0, 0, false, n0, sB);
+  for (int t = threadIdx.x; t < n0 * n0; t += blockDim.x)
+    for (int v = 0; v < NV; ++v) sA[v * GRID + t] = 0.0;
+  wave_sync();
+  for (int k = 0; k < nsub; ++k) {
+    const int ek = mr[3 + k], sk = mr[7 + k], ok = mr[11 + k];
+    const int kp = mt == 1 ? k : (mt == 2 ? -1 : (k & 1));
+    const int kq = mt == 1 ? -1 : (mt == 2 ? k : (k >> 1));
+    map2d_pq<NV>(sB, sT, sV, kp >= 0 ? m.ops + m.tab.mortar_interp[N0][kp] : nullptr,
+                 kq >= 0 ? m.ops + m.tab.mortar_interp[N0][kq] : nullptr, n0);
+    const int Nk = m.degree[ek], nk = Nk + 1;
+    gather_trace<NV>(m, u, ek, sk, ok, true, nk, sS);
+    gather_trace<3>(m, m.metric + (size_t)3 * (sk >> 1) * m.n_node, ek, sk, ok, true, nk, sN);
+    wave_sync();
+    const double rev = (sk & 1) ? -1.0 : 1.0;       // minus the outward sign of side sk
+    for (int t = threadIdx.x; t < nk * nk; t += blockDim.x)
+      for (int c = 0; c < 3; ++c) sN[c * GRID + t] *= rev;
+    wave_sync();
+    const int M = N0 > Nk ? N0 : Nk, nM = M + 1;
+    const double* VV = sV;
+    const double* SS = sS;
+    const double* NN = sN;
+    if (N0 < M) {
+      map2d_sep_to<NV>(sV, sT, sVM, m.ops + m.tab.interp[N0][M], nM, n0);
+      VV = sVM;
+      wave_sync();
+    }
+    if (Nk < M) {
+      map2d_sep_to<NV>(sS, sT, sSM, m.ops + m.tab.interp[Nk][M], nM, nk);
+      wave_sync();
+      map2d_sep_to<3>(sN, sT, sNM, m.ops + m.tab.interp[Nk][M], nM, nk);
+      SS = sSM;
+      NN = sNM;
+      wave_sync();
+    }
+    for (int t = threadIdx.x; t < nM * nM; t += blockDim.x) {
+      double uL[NV], uR[NV], F[NV];
+      for (int v = 0; v < NV; ++v) {
+        uL[v] = VV[v * GRID + t];
+        uR[v] = SS[v * GRID + t];
+      }
+      riemann<NV>(prm.face_flux_dg, prm.volume_flux, uL, uR, NN[t], NN[GRID + t], NN[2 * GRID + t], m.gas, F);
+      for (int v = 0; v < NV; ++v) sF[v * GRID + t] = F[v];
+    }
+    wave_sync();
+    double* bk = m.fside + m.side_off[ek];
+    if (Nk < M)
+      map2d_sep_side<NV>(bk, sF, sT, m.ops + m.tab.project[M][Nk], nk, nM, sk, ok, true, -1.0);
+    else
+      write_side<NV>(bk, sF, sk, ok, true, nk, -1.0);
+    wave_sync();
+    const double* FB = sF;
+    if (N0 < M) {
+      map2d_sep_to<NV>(sF, sT, sT2, m.ops + m.tab.project[M][N0], n0, nM);
+      FB = sT2;
+      wave_sync();
+    }
+    map2d_pq<NV>(FB, sT, sV, kp >= 0 ? m.ops + m.tab.mortar_proj[N0][kp] : nullptr,
+                 kq >= 0 ? m.ops + m.tab.mortar_proj[N0][kq] : nullptr, n0);
+    wave_sync();
+    for (int t = threadIdx.x; t < n0 * n0; t += blockDim.x)
+      for (int v = 0; v < NV; ++v) sA[v * GRID + t] += sV[v * GRID + t];
+    wave_sync();
+  }
+  write_side<NV>(m.fside + m.side_off[e0], sA, s0, 0, false, n0, 1.0);
+}
+
 }  // namespace
 
 template <int NV>
@@ -1089,4 +1217,14 @@ hipError_t launch_visc_faces(const MeshView& m, const double* u, hipStream_t s) 
   return m.nvar == 5 ? launch_visc_faces_t<5, false>(m, u, s) : launch_visc_faces_t<6, false>(m, u, s);
 }
 
+hipError_t launch_face_mortars(const MeshView& m, const ParamsDev& p, const double* u, hipStream_t s) {
+  if (m.n_mortar == 0) return hipSuccess;
+  if (m.nvar == 5)
+    hipLaunchKernelGGL((face_mortar_kernel<5>), dim3(m.n_mortar), dim3(FACE_THREADS), 0, s, m, p, u);
+  else
+    hipLaunchKernelGGL((face_mortar_kernel<6>), dim3(m.n_mortar), dim3(FACE_THREADS), 0, s, m, p, u);
+  return hipGetLastError();
+}
+
 }  // namespace dgfv
+

@@ -171,6 +171,7 @@ struct dgfv_mesh {
   // in view.grad, view.vside and rvisc
   bool viscous = false;
   double* rvisc = nullptr;
+  int n_mortar = 0;                             // non-conforming faces
   size_t side_total = 0;                        // doubles of one side buffer (fside, vside)
 
   // dg_timestep: per-element steps [2][K] and the two minima (made by its first call)
@@ -455,6 +456,13 @@ int side_node_h(int s, int p, int q, int n) {
   }
 }
 
+// Meshes with mortars take pure DG elements only (the FV mortar variants are not built).
+dgfv_status mortar_alpha(const dgfv_mesh* m, const double* alpha) {
+  if (m->n_mortar > 0 && alpha)
+    return fail(DGFV_ERR_UNSUPPORTED, "meshes with mortars take alpha = NULL (the FV mortar variants are not built)");
+  return DGFV_OK;
+}
+
 dgfv_status check_params(const dgfv_mesh* m, const dgfv_params* p) {
   if (!p) return fail(DGFV_ERR_ARG, "params is NULL");
   if (p->volume_flux < 0 || p->volume_flux > 2) return fail(DGFV_ERR_ARG, "volume_flux out of range");
@@ -601,6 +609,7 @@ void enqueue_rhs_impl(const dgfv_mesh* m, const ParamsDev& p, const double* u, d
       Timed tf(m, c == FACE_CLASS_FV ? DGFV_KERNEL_FV_FACE : -1, ss);
       hip_check(launch_face_class(v, p, u, alpha, c, trace_in, ss), "face launch");
     });
+    if (m->n_mortar > 0) hip_check(launch_face_mortars(v, p, u, s), "mortar launch");
   }
   if (alpha) {
     Timed t(m, DGFV_KERNEL_FV_RESIDUAL, s);
@@ -853,6 +862,7 @@ dgfv_status guarded(const dgfv_mesh* m, hipStream_t s, F&& call) {
 // Which adjoint paths run (see dg_rhs_vjp).
 dgfv_status vjp_paths_enabled(const dgfv_mesh* m, const double* alpha) {
   if (m->viscous) return fail(DGFV_ERR_UNSUPPORTED, "dg_rhs_vjp: the adjoint of the viscous terms is not built");
+  if (m->n_mortar > 0) return fail(DGFV_ERR_UNSUPPORTED, "dg_rhs_vjp: the adjoint of mortar faces is not built");
 #ifndef DGFV_CPU_ADJOINT_ALL_PATHS
   // The adjoint of FV-blended elements and of degree-jump faces faulted the GPU
   // once with no cause found: the same kernels run clean and exact in the CPU
@@ -938,19 +948,43 @@ dgfv_status dgfv_mesh_create(const dgfv_mesh_desc* d, dgfv_mesh** out) {
     return fail(DGFV_ERR_ARG, "metric_degree must be 0 (per element) or in 1..min(degree)");
   if (d->n_fv < nmax + 1 || d->n_fv > MAXFV)
     return fail(DGFV_ERR_UNSUPPORTED, "n_fv must be in max(degree)+1 .. 8");
-  if (d->n_face != 3 * d->n_elem)
-    return fail(DGFV_ERR_ARG, "a closed conforming hexahedral mesh has 3 faces per element");
+  if (d->n_face < 0 || d->n_mortar < 0 || (d->n_mortar > 0 && !d->mortars))
+    return fail(DGFV_ERR_ARG, "face or mortar count out of range");
+  if (d->n_mortar > 0 && d->metric_degree == 0)
+    return fail(DGFV_ERR_UNSUPPORTED, "meshes with mortars take a mesh-wide metric degree (metric_degree >= 1)");
   {
     std::vector<uint8_t> seen((size_t)d->n_elem * 6, 0);
+    auto mark = [&](int e, int s) {
+      if (e < 0 || e >= d->n_elem || s < 0 || s > 5) return 1;
+      return seen[(size_t)e * 6 + s]++ ? 2 : 0;
+    };
     for (int f = 0; f < d->n_face; ++f) {
       const int32_t* fc = d->faces + 5 * f;
       for (int side = 0; side < 2; ++side) {
-        const int e = fc[2 * side], s = fc[2 * side + 1];
-        if (e < 0 || e >= d->n_elem || s < 0 || s > 5) return fail(DGFV_ERR_ARG, "face entry out of range");
-        if (seen[(size_t)e * 6 + s]++) return fail(DGFV_ERR_ARG, "element side used by two faces");
+        const int r = mark(fc[2 * side], fc[2 * side + 1]);
+        if (r == 1) return fail(DGFV_ERR_ARG, "face entry out of range");
+        if (r == 2) return fail(DGFV_ERR_ARG, "element side used twice");
       }
       if (fc[4] < 0 || fc[4] > 7) return fail(DGFV_ERR_ARG, "orientation code out of range");
     }
+    for (int q = 0; q < d->n_mortar; ++q) {
+      const int32_t* mr = d->mortars + 15 * q;
+      if (mr[2] < 1 || mr[2] > 3) return fail(DGFV_ERR_ARG, "mortar type must be 1, 2 or 3");
+      const int nsub = mr[2] == 3 ? 4 : 2;
+      int r = mark(mr[0], mr[1]);
+      for (int k = 0; k < 4 && r == 0; ++k) {
+        if (k < nsub) {
+          r = mark(mr[3 + k], mr[7 + k]);
+          if (r == 0 && (mr[11 + k] < 0 || mr[11 + k] > 7)) r = 1;
+        } else if (mr[3 + k] != -1 || mr[7 + k] != -1 || mr[11 + k] != -1) {
+          r = 1;
+        }
+      }
+      if (r == 1) return fail(DGFV_ERR_ARG, "mortar entry out of range");
+      if (r == 2) return fail(DGFV_ERR_ARG, "element side used twice");
+    }
+    for (uint8_t c : seen)
+      if (c != 1) return fail(DGFV_ERR_ARG, "every element side must belong to exactly one face or mortar");
   }
   if (d->n_var == 5 && !(d->gamma > 1.0)) return fail(DGFV_ERR_ARG, "gamma must exceed 1");
   if (d->n_var == 6 && !(d->kappa[0] > 1.0 && d->kappa[1] > 1.0 && d->R[0] > 0 && d->R[1] > 0))
@@ -963,6 +997,7 @@ dgfv_status dgfv_mesh_create(const dgfv_mesh_desc* d, dgfv_mesh** out) {
     m->n_fv = d->n_fv;
     m->NJ = d->metric_degree;
     m->F = d->n_face;
+    m->n_mortar = d->n_mortar;
     m->degree.assign(d->degree, d->degree + d->n_elem);
     m->offset.resize(m->K + 1);
     m->offset[0] = 0;
@@ -994,6 +1029,11 @@ dgfv_status dgfv_mesh_create(const dgfv_mesh_desc* d, dgfv_mesh** out) {
       tab.dg2fvT[N] = push(transpose(op_dg2fv(N, NFV), NFV, N + 1));
       tab.fv2dgT[N] = push(transpose(op_fv2dg(N, NFV), N + 1, NFV));
       tab.face_interp[N] = push(op_face_interp(N, NFV));
+      if (d->n_mortar > 0)
+        for (int k = 0; k < 2; ++k) {
+          tab.mortar_interp[N][k] = push(op_mortar_interp(N, k));
+          tab.mortar_proj[N][k] = push(op_mortar_project(N, k));
+        }
       for (int M = N + 1; M <= MAXN; ++M) {
         if (!present[M]) continue;
         tab.interp[N][M] = push(op_interp(N, M));
@@ -1184,8 +1224,15 @@ dgfv_status dgfv_mesh_create(const dgfv_mesh_desc* d, dgfv_mesh** out) {
       for (int e = 0; e < m->K; ++e)
         for (int sd = 0; sd < 6; ++sd) {
           const int f = elem_face[(size_t)e * 6 + sd];
-          const int32_t* fc = d->faces + 5 * (size_t)f;
           SideRec& r = srec[(size_t)e * 6 + sd];
+          if (f < 0) {                      // a mortar side: no neighbour of its own
+            r.baseL = r.baseR = m->offset[e];
+            r.nrm = 0;
+            r.nbr = e;
+            r.code = sd | (sd << 3) | (1 << 9) | (1 << 11);
+            continue;
+          }
+          const int32_t* fc = d->faces + 5 * (size_t)f;
           const bool left = fc[0] == e && fc[1] == sd;
           r.baseL = m->offset[fc[0]];
           r.baseR = m->offset[fc[2]];
@@ -1195,6 +1242,11 @@ dgfv_status dgfv_mesh_create(const dgfv_mesh_desc* d, dgfv_mesh** out) {
                    ((m->degree[fc[0]] == m->degree[fc[2]] ? 1 : 0) << 10);
         }
       v.side_rec = m->keep(dev_upload(srec));
+      if (d->n_mortar > 0) {
+        std::vector<int32_t> mort(d->mortars, d->mortars + 15 * (size_t)d->n_mortar);
+        v.mortars = m->keep(dev_upload(mort));
+      }
+      v.n_mortar = d->n_mortar;
     }
     // blended-element work list: buckets concatenated in ascending degree
     {
@@ -1351,6 +1403,7 @@ dgfv_status dg_rhs(const dgfv_mesh* m, const dgfv_params* prm, const double* u, 
   if (!m || !u || !ut) return fail(DGFV_ERR_ARG, "NULL argument");
   if (u == ut) return fail(DGFV_ERR_ARG, "u and ut must not overlap");
   if (dgfv_status st = check_params(m, prm)) return st;
+  if (dgfv_status st = mortar_alpha(m, alpha)) return st;
   hipStream_t s = (hipStream_t)stream;
   return guarded(m, s, [&] { return enqueue_rhs(m, prm, u, alpha, ut, nullptr, 0, 0.0, s); });
 }
@@ -1362,6 +1415,7 @@ dgfv_status dg_rk_stage(const dgfv_mesh* m, const dgfv_params* prm, int stage, d
   if (!std::isfinite(dt)) return fail(DGFV_ERR_ARG, "dt must be finite");
   if (u == k) return fail(DGFV_ERR_ARG, "u and k must not overlap");
   if (dgfv_status st = check_params(m, prm)) return st;
+  if (dgfv_status st = mortar_alpha(m, alpha)) return st;
   hipStream_t s = (hipStream_t)stream;
   return guarded(m, s, [&] { return run_stages(m, prm, 0, stage, stage, dt, u, k, alpha, s); });
 }
@@ -1372,6 +1426,7 @@ dgfv_status dg_rk_step(const dgfv_mesh* m, const dgfv_params* prm, double dt, do
   if (!std::isfinite(dt)) return fail(DGFV_ERR_ARG, "dt must be finite");
   if (u == k) return fail(DGFV_ERR_ARG, "u and k must not overlap");
   if (dgfv_status st = check_params(m, prm)) return st;
+  if (dgfv_status st = mortar_alpha(m, alpha)) return st;
   hipStream_t s = (hipStream_t)stream;
   return guarded(m, s, [&] { return run_stages(m, prm, 1, 1, 5, dt, u, k, alpha, s); });
 }
@@ -1380,6 +1435,7 @@ dgfv_status dgfv_autotune(dgfv_mesh* m, const dgfv_params* prm, const double* u,
                           double* ms_out, void* stream) {
   if (!m || !u) return fail(DGFV_ERR_ARG, "NULL argument");
   if (dgfv_status st = check_params(m, prm)) return st;
+  if (dgfv_status st = mortar_alpha(m, alpha)) return st;
   if (ms_out) std::fill(ms_out, ms_out + 2 * (MAXN + 1), 0.0);
   hipStream_t s = (hipStream_t)stream;
   double* scratch = nullptr;
@@ -1467,6 +1523,7 @@ dgfv_status dg_rhs_fv(const dgfv_mesh* m, const dgfv_params* prm, const double* 
   if (u == ut || ufv == utfv) return fail(DGFV_ERR_ARG, "inputs and outputs must not overlap");
   if (dgfv_status st = check_params(m, prm)) return st;
   if (m->viscous) return fail(DGFV_ERR_UNSUPPORTED, "FV-stored elements with viscous terms are not built");
+  if (m->n_mortar > 0) return fail(DGFV_ERR_UNSUPPORTED, "FV-stored elements on meshes with mortars are not built");
   hipStream_t s = (hipStream_t)stream;
   if (!m->fvghost && capturing(s)) return fail(DGFV_ERR_ARG, "the first call with FV-stored elements allocates: not under capture");
   return guarded(m, s, [&] {
@@ -1488,6 +1545,7 @@ dgfv_status dg_rk_stage_fv(const dgfv_mesh* m, const dgfv_params* prm, int stage
   if (u == k || ufv == kfv) return fail(DGFV_ERR_ARG, "states and registers must not overlap");
   if (dgfv_status st = check_params(m, prm)) return st;
   if (m->viscous) return fail(DGFV_ERR_UNSUPPORTED, "FV-stored elements with viscous terms are not built");
+  if (m->n_mortar > 0) return fail(DGFV_ERR_UNSUPPORTED, "FV-stored elements on meshes with mortars are not built");
   hipStream_t s = (hipStream_t)stream;
   if (!m->fvghost && capturing(s)) return fail(DGFV_ERR_ARG, "the first call with FV-stored elements allocates: not under capture");
   return guarded(m, s, [&] {
@@ -1507,6 +1565,7 @@ dgfv_status dg_rk_step_fv(const dgfv_mesh* m, const dgfv_params* prm, double dt,
   if (u == k || ufv == kfv) return fail(DGFV_ERR_ARG, "states and registers must not overlap");
   if (dgfv_status st = check_params(m, prm)) return st;
   if (m->viscous) return fail(DGFV_ERR_UNSUPPORTED, "FV-stored elements with viscous terms are not built");
+  if (m->n_mortar > 0) return fail(DGFV_ERR_UNSUPPORTED, "FV-stored elements on meshes with mortars are not built");
   hipStream_t s = (hipStream_t)stream;
   if (!m->fvghost && capturing(s)) return fail(DGFV_ERR_ARG, "the first call with FV-stored elements allocates: not under capture");
   return guarded(m, s, [&] {
@@ -1551,6 +1610,7 @@ dgfv_status dgfv_set_positivity_limiter(dgfv_mesh* m, int enable) {
 
 dgfv_status dgfv_set_transport(dgfv_mesh* m, const dgfv_transport* tr) {
   if (!m) return fail(DGFV_ERR_ARG, "mesh is NULL");
+  if (tr && m->n_mortar > 0) return fail(DGFV_ERR_UNSUPPORTED, "viscous terms on meshes with mortars are not built");
   if (!tr) {
     m->viscous = false;
     m->drop_graphs();
@@ -1634,6 +1694,7 @@ dgfv_status dg_lift(const dgfv_mesh* m, const double* u, double* g, void* stream
 
 dgfv_status dgfv_set_face_fusion(dgfv_mesh* m, int enable) {
   if (!m) return fail(DGFV_ERR_ARG, "mesh is NULL");
+  if (enable && m->n_mortar > 0) return fail(DGFV_ERR_UNSUPPORTED, "face fusion on meshes with mortars is not built");
   m->fuse_faces = enable != 0;
   m->drop_graphs();
   return DGFV_OK;

@@ -26,6 +26,9 @@ struct OpTables {
   int projectT[MAXN + 1][MAXN + 1];   // [M][N]: (M+1) x (N+1)
   int dg2fvT[MAXN + 1];               // (N+1) x NFV
   int fv2dgT[MAXN + 1];               // NFV x (N+1)
+  // mortars: [N][k] for half k of a degree-N big side, (N+1) x (N+1) each
+  int mortar_interp[MAXN + 1][2];     // big side -> the nodes of half k
+  int mortar_proj[MAXN + 1][2];       // half k's flux -> the big side
 };
 
 struct GasDev {
@@ -61,7 +64,8 @@ struct alignas(16) ConfRec {
 // flux itself: the face's two elements (left one first, as in the face
 // table), the normals of the face, and
 // code = left side | right side << 3 | orientation << 6 | (this element is the
-// face's left one) << 9 | (both elements have the same degree) << 10.
+// face's left one) << 9 | (both elements have the same degree) << 10 | (the
+// side belongs to a mortar: no face record, nbr = the element itself) << 11.
 struct alignas(16) SideRec {
   int64_t baseL, baseR;   // elem_offset of the left and right elements
   int64_t nrm;            // face_norm_off of the face
@@ -113,6 +117,10 @@ struct MeshView {
   const double* ops;            // operator tables
   OpTables tab;
   GasDev gas;
+  // non-conforming faces: [n_mortar][15] rows (big element, big side, type,
+  // small elements[4], small sides[4], orientations[4])
+  const int32_t* mortars;
+  int n_mortar;
   // viscous terms (allocated when transport coefficients are set)
   ViscDev visc;
   double* grad;                 // BR1-lifted gradient of u, [3][nvar][n_node]
@@ -236,6 +244,9 @@ hipError_t launch_face_class(const MeshView& m, const ParamsDev& p, const double
 // viscous kernels form the same-degree faces themselves.
 hipError_t launch_lift_faces(const MeshView& m, const double* u, hipStream_t s);
 hipError_t launch_visc_faces(const MeshView& m, const double* u, hipStream_t s);
+// Fluxes of the non-conforming faces into m.fside (dgfv_faces.hip), one mortar
+// per workgroup, after the other face kernels.
+hipError_t launch_face_mortars(const MeshView& m, const ParamsDev& p, const double* u, hipStream_t s);
 hipError_t launch_faces_vjp(const MeshView& m, const ParamsDev& p, const double* u, const double* alpha,
                             hipStream_t s);
 

@@ -248,4 +248,70 @@ std::vector<double> op_face_interp(int N, int NFV) {
   return to_double(I);
 }
 
+// ---- mortars -------------------------------------------------------------
+// Gauss-Legendre rule of m points (Newton on P_m from the cosine guesses).
+static void gauss_legendre(int m, std::vector<LD>& x, std::vector<LD>& w) {
+  const LD pi = 3.141592653589793238462643383279502884L;
+  x.resize(m);
+  w.resize(m);
+  for (int i = 0; i < m; ++i) {
+    LD z = std::cos(pi * (i + 0.75L) / (m + 0.5L));
+    LD p = 0, dp = 1;
+    for (int it = 0; it < 100; ++it) {
+      legendre(m, z, p, dp);
+      const LD dz = p / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-19L) break;
+    }
+    legendre(m, z, p, dp);
+    x[i] = z;
+    w[i] = 2.0L / ((1.0L - z * z) * dp * dp);
+  }
+}
+
+// The big side's nodal polynomial at the nodes of half k, in the half's own
+// coordinate s: xi = (s + 2k - 1) / 2.
+std::vector<double> op_mortar_interp(int N, int k) {
+  const auto x = lgl_nodes(N);
+  const int n = N + 1;
+  std::vector<LD> A((size_t)n * n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) A[(size_t)i * n + j] = lagrange(x, j, (x[i] + 2 * k - 1) * 0.5L);
+  return to_double(A);
+}
+
+// The big side's share of a flux F_k given (per unit of the half's own length)
+// at the degree-N nodes of half k: the L2 projection over [-1, 1] of the
+// function 2 F_k on half k, 0 elsewhere, as the solution of the mass-matrix
+// system  Mass F_0 = B F_k  with  Mass_ij = int l_i l_j dxi  and
+// B_il = int_half 2 l_i(xi) l_l(s(xi)) dxi = int_{-1}^{1} l_i((s + 2k - 1)/2) l_l(s) ds,
+// both by an (N+2)-point Gauss rule (exact for the degree-2N integrands).
+std::vector<double> op_mortar_project(int N, int k) {
+  const auto x = lgl_nodes(N);
+  const int n = N + 1;
+  std::vector<LD> g, gw;
+  gauss_legendre(n + 1, g, gw);
+  std::vector<LD> mass((size_t)n * n, 0.0L), B((size_t)n * n, 0.0L);
+  for (size_t q = 0; q < g.size(); ++q) {
+    const LD t = (g[q] + 2 * k - 1) * 0.5L;
+    for (int i = 0; i < n; ++i) {
+      const LD li = lagrange(x, i, g[q]), lit = lagrange(x, i, t);
+      for (int j = 0; j < n; ++j) {
+        const LD lj = lagrange(x, j, g[q]);
+        mass[(size_t)i * n + j] += gw[q] * li * lj;
+        B[(size_t)i * n + j] += gw[q] * lit * lj;
+      }
+    }
+  }
+  const auto Mi = inverse(mass, n);
+  std::vector<LD> P((size_t)n * n, 0.0L);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      LD acc = 0.0L;
+      for (int l = 0; l < n; ++l) acc += Mi[(size_t)i * n + l] * B[(size_t)l * n + j];
+      P[(size_t)i * n + j] = acc;
+    }
+  return to_double(P);
+}
+
 }  // namespace dgfv

@@ -19,5 +19,8 @@ std::vector<double> op_project(int M, int N);       // (N+1) x (M+1), M > N
 std::vector<double> op_dg2fv(int N, int NFV);       // NFV x (N+1)
 std::vector<double> op_fv2dg(int N, int NFV);       // (N+1) x NFV
 std::vector<double> op_face_interp(int N, int NFV); // (NFV+1) x (N+1)
+// mortars (Section 3.2.3): half k = 0 ([-1, 0]) or 1 ([0, 1]) of a big side of degree N
+std::vector<double> op_mortar_interp(int N, int k);   // (N+1) x (N+1): big side -> nodes of half k
+std::vector<double> op_mortar_project(int N, int k);  // (N+1) x (N+1): half k's flux -> big side
 
 }  // namespace dgfv

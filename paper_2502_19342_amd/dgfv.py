@@ -31,7 +31,8 @@ class _MeshDesc(ctypes.Structure):
                 ("degree", ctypes.POINTER(ctypes.c_int8)), ("corners", ctypes.POINTER(ctypes.c_double)),
                 ("n_face", ctypes.c_int32), ("faces", ctypes.POINTER(ctypes.c_int32)),
                 ("n_fv", ctypes.c_int32), ("metric_degree", ctypes.c_int32),
-                ("gamma", ctypes.c_double), ("kappa", ctypes.c_double * 2), ("R", ctypes.c_double * 2)]
+                ("gamma", ctypes.c_double), ("kappa", ctypes.c_double * 2), ("R", ctypes.c_double * 2),
+                ("n_mortar", ctypes.c_int32), ("mortars", ctypes.POINTER(ctypes.c_int32))]
 
 
 class _Params(ctypes.Structure):
@@ -126,13 +127,16 @@ def params_of(wl) -> Params:
 
 
 class Mesh:
-    """Device geometry of a conforming hexahedral mesh (owns the library handle)."""
+    """Device geometry of a hexahedral mesh (owns the library handle); ``mortars`` lists its
+    non-conforming faces ([M, 15] rows, ``workloads.mortar_mesh``), if any."""
 
     def __init__(self, degree, corners, faces, n_var=5, n_fv=None, metric_degree=1, gamma=1.4,
-                 kappa=(1.4, 1.4), R=(287.0, 287.0)):
+                 kappa=(1.4, 1.4), R=(287.0, 287.0), mortars=None):
         self.degree = np.ascontiguousarray(degree, dtype=np.int8)
         self.corners = np.ascontiguousarray(corners, dtype=np.float64)
         self.faces = np.ascontiguousarray(faces, dtype=np.int32)
+        self.mortars = np.ascontiguousarray(np.zeros((0, 15)) if mortars is None else mortars,
+                                            dtype=np.int32).reshape(-1, 15)
         K = self.degree.shape[0]
         if self.corners.shape != (K, 8, 3) or self.faces.ndim != 2 or self.faces.shape[1] != 5:
             raise ValueError("corners must be [K,8,3] and faces [F,5]")
@@ -140,12 +144,13 @@ class Mesh:
         self.n_var = int(n_var)
         self.n_fv = int(n_fv if n_fv is not None else int(self.degree.max()) + 1)
         self._args = dict(n_var=self.n_var, n_fv=self.n_fv, metric_degree=int(metric_degree), gamma=float(gamma),
-                          kappa=tuple(kappa), R=tuple(R))
+                          kappa=tuple(kappa), R=tuple(R), mortars=self.mortars)
         desc = _MeshDesc(K, self.n_var, self.degree.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)),
                          self.corners.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                          self.faces.shape[0], self.faces.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                          self.n_fv, int(metric_degree), float(gamma),
-                         (ctypes.c_double * 2)(*kappa), (ctypes.c_double * 2)(*R))
+                         (ctypes.c_double * 2)(*kappa), (ctypes.c_double * 2)(*R), self.mortars.shape[0],
+                         self.mortars.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if len(self.mortars) else None)
         h = ctypes.c_void_p()
         _check(_lib.dgfv_mesh_create(ctypes.byref(desc), ctypes.byref(h)))
         self._h = h
@@ -166,7 +171,7 @@ class Mesh:
     def from_workload(cls, wl) -> "Mesh":
         m = wl.mesh
         mesh = cls(m.degree, m.corners, m.faces, wl.n_var, wl.n_fv, wl.metric_degree, wl.gamma,
-                   tuple(wl.kappa), tuple(wl.R))
+                   tuple(wl.kappa), tuple(wl.R), getattr(m, "mortars", None))
         if getattr(wl, "viscous", False):
             mesh.transport(wl.mu, wl.Pr, wl.D)
         return mesh

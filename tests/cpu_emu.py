@@ -29,6 +29,8 @@ def run(wl, u, calls, alpha=None, w=None, dt=None, launch_mode=None, timeout=900
              params=np.array([wl.volume_flux, wl.face_flux_dg, wl.face_flux_fv, wl.ind_vars, wl.ind_T,
                               wl.ind_dT], dtype=np.float64),
              u=np.asarray(u, dtype=np.float64), calls=np.array(calls))
+    if len(getattr(m, "mortars", [])):
+        z["mortars"] = np.asarray(m.mortars, dtype=np.int32)
     if getattr(wl, "viscous", False):
         z["transport"] = np.asarray(tuple(wl.mu) + tuple(wl.Pr) + tuple(wl.D), dtype=np.float64)
     if alpha is not None:

@@ -19,7 +19,8 @@ class MeshDesc(ctypes.Structure):
                 ("degree", ctypes.c_void_p), ("corners", ctypes.c_void_p),
                 ("n_face", ctypes.c_int32), ("faces", ctypes.c_void_p),
                 ("n_fv", ctypes.c_int32), ("metric_degree", ctypes.c_int32),
-                ("gamma", ctypes.c_double), ("kappa", ctypes.c_double * 2), ("R", ctypes.c_double * 2)]
+                ("gamma", ctypes.c_double), ("kappa", ctypes.c_double * 2), ("R", ctypes.c_double * 2),
+                ("n_mortar", ctypes.c_int32), ("mortars", ctypes.c_void_p)]
 
 
 class Params(ctypes.Structure):
@@ -46,9 +47,11 @@ def main(src, dst):
     corners = np.ascontiguousarray(z["corners"], dtype=np.float64)
     faces = np.ascontiguousarray(z["faces"], dtype=np.int32)
     K = degree.shape[0]
+    mortars = np.ascontiguousarray(z["mortars"], dtype=np.int32).reshape(-1, 15) if "mortars" in z else None
     desc = MeshDesc(K, int(z["n_var"]), ptr(degree), ptr(corners), faces.shape[0], ptr(faces),
                     int(z["n_fv"]), int(z["metric_degree"]), float(z["gamma"]),
-                    (ctypes.c_double * 2)(*z["kappa"]), (ctypes.c_double * 2)(*z["R"]))
+                    (ctypes.c_double * 2)(*z["kappa"]), (ctypes.c_double * 2)(*z["R"]),
+                    0 if mortars is None else mortars.shape[0], ptr(mortars) if mortars is not None and len(mortars) else None)
     h = P()
     check(lib.dgfv_mesh_create(ctypes.byref(desc), ctypes.byref(h)), "dgfv_mesh_create")
     n_node = ctypes.c_int64()

@@ -315,3 +315,21 @@ def test_cpu_build_viscous_step_with_traces():
     assert np.array_equal(out["rk_step"], out["rk_stages"])
     want = lsrk.step(lambda v: c.f(v, c.alpha), c.u, dt)
     assert rel_err(torch.as_tensor(out["rk_step"]), want) <= 1e-11
+
+
+@pytest.mark.parametrize("refine,degree,scramble,amp,n_var", [("y", (4, 2), 7, 0.05, 5), ("yz", (2, 4), 5, 0.0, 5),
+                                                              ("yz", (3, 3), 9, 0.05, 6)])
+def test_cpu_build_mortars(refine, degree, scramble, amp, n_var):
+    # non-conforming faces of types 1/2 and 3 with degree jumps across them, scrambled frames,
+    # curved watertight elements: the RHS and one RK step against the oracle
+    mesh = W.mortar_mesh(4, refine, degree, scramble_seed=scramble, amp=amp)
+    kw = {} if n_var == 5 else dict(kappa=W.GAS_AIR_H2["kappa"], R=W.GAS_AIR_H2["R"])
+    flux = (W.VOL_RANOCHA, W.RIEMANN_ROE_HH) if n_var == 5 else (W.VOL_PIROZZOLI, W.RIEMANN_LLF)
+    wl = W.Workload("mortar", mesh, n_var, W.density_wave, flux[0], flux[1], W.RIEMANN_LLF, n_fv=8,
+                    metric_degree=2 if amp else 1, **kw)
+    c = _case(wl, smooth_state(57, n_var), noise=1e-3, seed=9)
+    dt = 0.3 * lsrk.timestep(c.mesh, c.gas, c.u, 0.5)
+    out = cpu_emu.run(wl, c.u.numpy(), ["rhs", "rk_step"], dt=dt)
+    assert rel_err(torch.as_tensor(out["rhs"]), c.oracle_rhs()) <= 1e-12
+    want = lsrk.step(lambda v: c.f(v, c.alpha), c.u, dt)
+    assert rel_err(torch.as_tensor(out["rk_step"]), want) <= 1e-11

@@ -1,0 +1,87 @@
+"""Non-conforming (mortar) faces on the GPU against the oracle (Section 3.2.3).
+
+Mortar meshes of types 1/2 (refinement in y) and 3 (in y and z), scrambled
+element frames, degree jumps across the mortars, curved watertight elements,
+one and two species: the RHS, free-stream preservation, ten RK steps under
+graph replay, and the calls that reject mortar meshes.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import lsrk
+from paper_2502_19342_amd import workloads as W
+
+from gpu_common import Case, announce, rel_err
+from oracle_cases import smooth_state
+
+pytestmark = pytest.mark.gpu
+T = torch.float64
+
+
+def _wl(refine, degree, scramble, amp, n_var=5, n=4):
+    mesh = W.mortar_mesh(n, refine, degree, scramble_seed=scramble, amp=amp)
+    kw = {} if n_var == 5 else dict(kappa=W.GAS_AIR_H2["kappa"], R=W.GAS_AIR_H2["R"])
+    flux = (W.VOL_RANOCHA, W.RIEMANN_ROE_HH) if n_var == 5 else (W.VOL_PIROZZOLI, W.RIEMANN_LLF)
+    return W.Workload("mortar", mesh, n_var, W.density_wave, flux[0], flux[1], W.RIEMANN_LLF, n_fv=8,
+                      metric_degree=2 if amp else 1, **kw)
+
+
+CASES = [("y", (4, 2), 7, 0.05, 5), ("y", 3, None, 0.0, 5), ("yz", (2, 4), 5, 0.0, 5), ("yz", (3, 3), 9, 0.05, 6),
+         ("yz", (7, 6), 11, 0.05, 5)]
+
+
+@pytest.mark.parametrize("refine,degree,scramble,amp,n_var", CASES)
+def test_mortar_rhs_on_gpu(refine, degree, scramble, amp, n_var):
+    announce(f"mortar rhs {refine} {degree} {scramble} {amp} {n_var}")
+    c = Case(_wl(refine, degree, scramble, amp, n_var), prim=smooth_state(57, n_var), noise=1e-3, seed=9)
+    err = rel_err(c.gpu_rhs(alpha=None), c.oracle_rhs())
+    print(f"[mortar] rhs rel err {err:.3e}", flush=True)
+    assert err <= 1e-12
+
+
+@pytest.mark.parametrize("refine,amp", [("y", 0.05), ("yz", 0.05)])
+def test_mortar_freestream_on_gpu(refine, amp):
+    announce(f"mortar free-stream {refine}")
+    c = Case(_wl(refine, (4, 3), 13, amp), prim=lambda x: W.freestream(x, 5))
+    ref = Case(_wl(refine, (4, 3), 13, amp), prim=smooth_state(3))
+    scale = float(ref.oracle_rhs().abs().max())
+    # metric degree 2 (curved) carries rounding of about 5e-13 of the rate's scale
+    assert float(c.gpu_rhs(alpha=None).abs().max()) <= 1e-11 * scale
+
+
+def test_mortar_rk_steps_with_graphs():
+    announce("mortar 10 RK steps, graph replays")
+    from paper_2502_19342_amd import dgfv
+    c = Case(_wl("yz", (3, 4), 15, 0.05), prim=smooth_state(59), noise=1e-3, seed=10)
+    dt = 0.3 * lsrk.timestep(c.mesh, c.gas, c.u, 0.5)
+    c.gmesh.graphs(True)
+    ug = c.gpu(c.u)
+    k = torch.zeros_like(ug)
+    uo = c.u.clone()
+    for _ in range(10):
+        dgfv.rk_step(c.gmesh, c.params, dt, ug, k, None)
+        uo = lsrk.step(lambda v: c.f(v, c.alpha), uo, dt)
+    torch.cuda.synchronize()
+    err = rel_err(ug.cpu(), uo)
+    print(f"[mortar] 10 steps rel err {err:.3e}", flush=True)
+    assert err <= 1e-10
+
+
+def test_mortar_unsupported_calls():
+    announce("mortar: unsupported calls")
+    from paper_2502_19342_amd import dgfv
+    c = Case(_wl("y", 3, None, 0.0), prim=smooth_state(61), noise=1e-3, seed=11)
+    u = c.gpu(c.u)
+    K = c.mesh.K
+    with pytest.raises(dgfv.DgfvError):
+        dgfv.rhs(c.gmesh, c.params, u, torch.zeros(K, dtype=T, device="cuda"))
+    with pytest.raises(dgfv.DgfvError):
+        c.gmesh.transport((0.01, 0.0))
+    with pytest.raises(dgfv.DgfvError):
+        c.gmesh.face_fusion(True)
+    with pytest.raises(dgfv.DgfvError):
+        dgfv.rhs_vjp(c.gmesh, c.params, u, None, torch.ones_like(u))
+    r = dgfv.rhs(c.gmesh, c.params, u)                # the mesh still works
+    torch.cuda.synchronize()
+    assert rel_err(r.cpu(), c.oracle_rhs()) <= 1e-12
