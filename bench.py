@@ -41,8 +41,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="C5", choices=["C1", "C2", "C3", "C4", "C5", "TGV"],
-                    help="workload; TGV is the viscous Taylor-Green vortex (64^3, N=7)")
+    ap.add_argument("--config", default="C5", choices=["C1", "C2", "C3", "C4", "C5", "TGV", "M3"],
+                    help="workload; TGV is the viscous Taylor-Green vortex (64^3, N=7), M3 the mesh with "
+                         "type-3 mortars (24^3 coarse cells, the fine half refined in y and z, N=7)")
     ap.add_argument("--n", type=int, default=None, help="elements per direction (default: the config's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch", default="branches", choices=["serial", "branches", "graph"],
@@ -426,7 +427,11 @@ def main():
     ev1.record()
     torch.cuda.synchronize()
     indicator_ms = ev0.elapsed_time(ev1)
-    tune = gm.autotune(prm, u, alpha)            # element-kernel tile shape per degree
+    mortars = len(wl.mesh.mortars) > 0
+    if mortars:                                  # pure DG: the FV mortar variants are not built
+        alpha = torch.zeros_like(alpha)
+        mask = np.zeros(wl.mesh.n_elem, dtype=bool)
+    tune = gm.autotune(prm, u, None if mortars else alpha)   # element-kernel tile shape per degree
     dt = 1e-5
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup
@@ -448,7 +453,7 @@ def main():
     if blend_frac:
         step_prm, step_alpha = ind_prm_t, torch.empty_like(alpha)
     else:
-        step_prm, step_alpha = prm, alpha
+        step_prm, step_alpha = prm, (torch.empty_like(alpha) if mortars else alpha)
     step_ind = torch.empty_like(alpha)
 
     if args.fv_stored:
@@ -465,7 +470,7 @@ def main():
     else:
         def step():
             dgfv.indicator(gm, step_prm, u, alpha=step_alpha, ind=step_ind)
-            dgfv.rk_step(gm, prm, dt, u, k, alpha)
+            dgfv.rk_step(gm, prm, dt, u, k, None if mortars else alpha)
 
     for _ in range(args.warmup):
         step()
@@ -498,7 +503,8 @@ def main():
     if not finite:
         print("bench.py: non-finite state after the timed steps", file=sys.stderr)
         sys.exit(1)
-    adjoint = None if (args.no_adjoint or args.fv_stored or wl.viscous) else adjoint_ratio(gm, prm, u, dgfv, torch)
+    adjoint = None if (args.no_adjoint or args.fv_stored or wl.viscous or mortars) else \
+        adjoint_ratio(gm, prm, u, dgfv, torch)
     padapt = p_adapt_timing(gm, prm, u, alpha, dt, dgfv, torch) if args.p_adapt else None
 
     stages = 5 * args.steps
@@ -545,7 +551,9 @@ def main():
         "config": {
             "workload": f"{args.config}: {wl.mesh.n}^3 periodic hexahedra, degrees "
                         f"{sorted(n_by_deg)}, {n_dof} DOFs x {wl.n_var} variables, "
-                        + ("viscous (BR1), " if wl.viscous else "") +
+                        + ("viscous (BR1), " if wl.viscous else "")
+                        + (f"{len(wl.mesh.mortars)} mortars (types "
+                           f"{sorted(set(wl.mesh.mortars[:, 2].tolist()))}), " if mortars else "") +
                         f"{100 * mask.mean():.1f}% of elements FV-blended (N_FV={wl.n_fv}), "
                         f"5-stage 2N RK steps",
             "n_elem": wl.mesh.n_elem, "n_dof": n_dof, "n_var": wl.n_var,
