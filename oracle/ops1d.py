@@ -304,3 +304,29 @@ def _gauss_legendre(m: int):
         xs.append(z)
         ws.append(2 / ((1 - z * z) * dp * dp))
     return xs, ws
+
+
+def _overlap_half(NFV: int, k: int) -> np.ndarray:
+    """[j, i] = length of the overlap of sub-face j of half k with sub-face i of the big side,
+    over the length of sub-face j (both on the big side's axis, in units of its sub-faces)."""
+    A = np.zeros((NFV, NFV))
+    for j in range(NFV):
+        lo = (j + k * NFV) / 2.0
+        hi = lo + 0.5
+        for i in range(NFV):
+            A[j, i] = max(0.0, min(hi, i + 1.0) - max(lo, float(i))) / 0.5
+    return A
+
+
+@functools.lru_cache(maxsize=None)
+def mortar_fv_interp(NFV: int, k: int) -> np.ndarray:
+    """``M^FV_{0k}``: the mean of the big side's piecewise-constant sub-face data over each
+    sub-face of half k (a copy when N_FV is even: every sub-face of the half lies in one of the big side's)."""
+    return _overlap_half(NFV, k)
+
+
+@functools.lru_cache(maxsize=None)
+def mortar_fv_project(NFV: int, k: int) -> np.ndarray:
+    """``M^FV_{k0}``: sub-face fluxes of half k (integrated over its sub-faces) summed into the
+    big side's sub-faces, each by the fraction of it that lies there."""
+    return _overlap_half(NFV, k).T.copy()

@@ -33,8 +33,10 @@ Non-conforming faces (Section 3.2.3, mortar types 1-3, DG sides): see
 quarters of ``M_{k0}`` applied to their fluxes (``ops1d.mortar_project``).
 Readings: the small side's own normal (reversed) carries the flux, so the
 big side's share needs no surface-element factor (``M_{k0}`` is the L2
-projection of twice the half's flux per direction of the split); elements at a
-mortar must be pure DG (the FV mortar variants ``M^FV`` are not built).
+projection of twice the half's flux per direction of the split); the FV
+variants (a blended side at a mortar) take the flux on the small side's
+sub-face grid, with ``M^FV_{0k}`` and ``M^FV_{k0}`` the overlap maps between
+the big side's sub-faces and those of its halves.
 
 FV part (eq. semidiscrete_fv, first order): sub-cell contents
 ``C = h^3 V3(J u)`` and volumes ``h^3 V3(J)`` give the means
@@ -226,11 +228,7 @@ class Rhs:
                     Ffv[NR][b][sR] = FsR[r]
 
         if len(m.mortars):
-            touched = np.unique(np.concatenate([m.mortars[:, 0], m.mortars[:, 3:7].reshape(-1)]))
-            touched = touched[touched >= 0]
-            if (alpha_np[touched] > 0).any():
-                raise NotImplementedError("FV-blended elements at mortars (the FV mortar variants) are not built")
-            self._mortar_fluxes(U, Fdg)
+            self._mortar_fluxes(U, Fdg, Ffv, ubar, alpha_np)
 
         out = {}
         for N, g in m.groups.items():
@@ -253,26 +251,42 @@ class Rhs:
         return m.scatter(out, nvar)
 
     # ------------------------------------------------------------------
-    def _mortar_fluxes(self, U, Fdg):
-        """Side fluxes of the non-conforming faces (Section 3.2.3, its five steps, DG sides).
+    def _mortar_fluxes(self, U, Fdg, Ffv, ubar, alpha_np):
+        """Side fluxes of the non-conforming faces (Section 3.2.3, its five steps).
 
-        For each small side k of a big side: the big side's trace interpolated to
-        the virtual small side (``M_{0k}`` along the split directions, at the big
-        side's degree N_0); the small side's trace brought onto that grid by the
-        orientation; both, and the small side's normal (its outward one reversed,
-        so that it carries the small side's surface element), on the common
-        degree ``max(N_0, N_k)``; the Riemann flux there; the small side receives
-        its projection to N_k, reversed; the big side receives the projection to
-        N_0 mapped with ``M_{k0}`` along the split directions, summed over k.
+        For each small side k of a big side, when both are DG: the big side's
+        trace interpolated to the virtual small side (``M_{0k}`` along the split
+        directions, at the big side's degree N_0); the small side's trace brought
+        onto that grid by the orientation; both, and the small side's normal (its
+        outward one reversed, so that it carries the small side's surface
+        element), on the common degree ``max(N_0, N_k)``; the Riemann flux there;
+        the small side receives its projection to N_k, reversed; the big side
+        receives the projection to N_0 mapped with ``M_{k0}`` along the split
+        directions, summed over k.
+
+        When either is FV-blended (the FV variants): the flux is taken on the
+        small side's ``N_FV^2`` sub-face grid, as at a conforming FV face, from
+        the big side's boundary sub-cell means mapped with ``M^FV_{0k}`` (or its
+        DG virtual side through ``V^{DG->FV}``) and the small side's sub-cell
+        means (or ``V^{DG->FV}`` of its trace), with the sub-face means of the
+        reversed normal times ``h_FV^2``; the small side takes it reversed, its
+        DG part through ``V^{FV->DG}`` over ``h_FV^2``; the big side's DG part
+        takes ``V^{FV->DG}`` of it at N_0 over ``h_FV^2`` mapped with ``M_{k0}``,
+        a blended big side's FV part the sub-face fluxes summed with ``M^FV_{k0}``.
         """
         m, gas, prm = self.mesh, self.gas, self.params
         deg = m.degree
+        NFV = m.n_fv
+        h2 = (2.0 / NFV) ** 2
         for row in m.mortars.tolist():
             e0, s0, mt = row[0], row[1], row[2]
             N0 = int(deg[e0])
             sl0 = int(m.slot[e0])
+            a0 = alpha_np[e0] > 0
             u0 = face_slice(U[N0][sl0:sl0 + 1], s0)[0]           # [nvar, n0, n0] on the big side's grid
             F0 = torch.zeros_like(u0)
+            F0fv = torch.zeros(u0.shape[0], NFV, NFV, dtype=T) if a0 else None
+            b0 = face_slice(ubar[N0][sl0:sl0 + 1], s0)[0] if a0 else None   # boundary sub-cell means
             nsub = 4 if mt == 3 else 2
             for k in range(nsub):
                 ek, sk, ok = row[3 + k], row[7 + k], row[11 + k]
@@ -287,6 +301,36 @@ class Rhs:
                 gk = m.groups[Nk]
                 tk = to_left(face_slice(U[Nk][slk:slk + 1], sk), ok)[0]
                 nk = -to_left(gk.outward_normal(sk)[slk:slk + 1], ok)[0]
+                ak = alpha_np[ek] > 0
+                if a0 or ak:
+                    if a0:
+                        vf = b0
+                        if kp is not None:
+                            vf = apply_axis(_t(ops1d.mortar_fv_interp(NFV, kp)), vf, 0)
+                        if kq is not None:
+                            vf = apply_axis(_t(ops1d.mortar_fv_interp(NFV, kq)), vf, 1)
+                    else:
+                        vf = apply2(_t(ops1d.dg2fv(N0, NFV)), uv)
+                    Vk = _t(ops1d.dg2fv(Nk, NFV))
+                    sf = to_left(face_slice(ubar[Nk][slk:slk + 1], sk), ok)[0] if ak else apply2(Vk, tk)
+                    Fs = riemann(prm.face_flux_fv, vf, sf, h2 * apply2(Vk, nk), gas, prm.volume_flux)
+                    Fdg[Nk][slk][sk] = -to_right(apply2(_t(ops1d.fv2dg(Nk, NFV)), Fs)[None] / h2, ok)[0]
+                    if ak:
+                        Ffv[Nk][slk][sk] = -to_right(Fs[None], ok)[0]
+                    Fb = apply2(_t(ops1d.fv2dg(N0, NFV)), Fs) / h2
+                    if kp is not None:
+                        Fb = apply_axis(_t(ops1d.mortar_project(N0, kp)), Fb, 0)
+                    if kq is not None:
+                        Fb = apply_axis(_t(ops1d.mortar_project(N0, kq)), Fb, 1)
+                    F0 = F0 + Fb
+                    if a0:
+                        Fv = Fs
+                        if kp is not None:
+                            Fv = apply_axis(_t(ops1d.mortar_fv_project(NFV, kp)), Fv, 0)
+                        if kq is not None:
+                            Fv = apply_axis(_t(ops1d.mortar_fv_project(NFV, kq)), Fv, 1)
+                        F0fv = F0fv + Fv
+                    continue
                 M = max(N0, Nk)
                 if N0 < M:
                     uv = apply2(_t(ops1d.interp(N0, M)), uv)
@@ -303,6 +347,8 @@ class Rhs:
                     Fb = apply_axis(_t(ops1d.mortar_project(N0, kq)), Fb, 1)
                 F0 = F0 + Fb
             Fdg[N0][sl0][s0] = F0
+            if a0:
+                Ffv[N0][sl0][s0] = F0fv
 
     @staticmethod
     def _lift(side, E, nvar, n, w0):

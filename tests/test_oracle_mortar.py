@@ -128,3 +128,35 @@ def test_mortar_rate_converges_to_the_exact_divergence(refine, scramble):
         want = _exact_rate(mesh.node_coords().numpy().T, gas, _prim)
         errs.append(float(((R - want).abs().amax(1) / want.abs().amax(1)).max()))
     assert errs[1] < 2e-3 and errs[1] < errs[0] / 20, errs
+
+
+@pytest.mark.parametrize("NFV", [5, 6, 8])
+def test_mortar_fv_maps(NFV):
+    # the half's sub-faces copy (or, for odd N_FV, average) the big side's; the big side's
+    # sub-faces sum the halves' fluxes by overlap: columns of M^FV_k0 sum to one, and
+    # projecting the copies of both halves gives twice the big side's data
+    S = sum(ops1d.mortar_fv_project(NFV, k) @ ops1d.mortar_fv_interp(NFV, k) for k in (0, 1))
+    assert np.abs(S - 2 * np.eye(NFV)).max() <= 1e-15 or NFV % 2
+    for k in (0, 1):
+        assert np.abs(ops1d.mortar_fv_project(NFV, k).sum(0) - 1).max() <= 1e-15
+        assert np.abs(ops1d.mortar_fv_interp(NFV, k).sum(1) - 1).max() <= 1e-15
+
+
+@pytest.mark.parametrize("refine,degree,scramble,amp,n_fv", [("y", (4, 3), 7, 0.05, 8), ("yz", (3, 2), 5, 0.0, 5),
+                                                             ("yz", (2, 4), 9, 0.05, 6)])
+def test_mortar_blended_freestream_and_conservation(refine, degree, scramble, amp, n_fv):
+    # FV-blended elements at mortars (the FV variants): a constant state stays, every variable is
+    # conserved, with blending factors 0, 0.4 and 1 on both sides of the mortars
+    mesh = W.mortar_mesh(4, refine, degree, scramble_seed=scramble, amp=amp)
+    wl = W.Workload("mortar", mesh, 5, W.density_wave, W.VOL_RANOCHA, W.RIEMANN_ROE_HH, W.RIEMANN_LLF,
+                    n_fv=n_fv, metric_degree=2 if amp else 1)
+    om, gas, f = problem.build(wl)
+    alpha = torch.as_tensor(np.random.default_rng(scramble).choice([0.0, 0.4, 1.0], size=om.K), dtype=T)
+    touched = set(mesh.mortars[:, 0].tolist()) | set(mesh.mortars[:, 3:7].reshape(-1).tolist())
+    assert any(alpha[e] > 0 for e in touched if e >= 0)
+    u = problem.initial_state(om, gas, lambda x: W.freestream(x, 5))
+    scale = float(f(problem.initial_state(om, gas, smooth_state(3)), alpha).abs().max())
+    assert float(f(u, alpha).abs().max()) <= (1e-12 if amp == 0 else 1e-11) * scale
+    R = f(problem.initial_state(om, gas, smooth_state(5)), alpha)
+    wJ = om.weights_flat() * om.jacobian_flat()
+    assert float(((R * wJ).sum(1).abs() / (R.abs() * wJ).sum(1))[1:].max()) <= 1e-13
