@@ -428,10 +428,11 @@ def main():
     torch.cuda.synchronize()
     indicator_ms = ev0.elapsed_time(ev1)
     mortars = len(wl.mesh.mortars) > 0
-    if mortars:                                  # pure DG: the FV mortar variants are not built
-        alpha = torch.zeros_like(alpha)
-        mask = np.zeros(wl.mesh.n_elem, dtype=bool)
-    tune = gm.autotune(prm, u, None if mortars else alpha)   # element-kernel tile shape per degree
+    if mortars:                                  # mortars that take the FV variants
+        mrows = wl.mesh.mortars
+        mside = np.concatenate([mrows[:, :1], mrows[:, 3:7]], axis=1)
+        mortar_fv = int((np.where(mside >= 0, mask[np.maximum(mside, 0)], False)).any(axis=1).sum())
+    tune = gm.autotune(prm, u, alpha)            # element-kernel tile shape per degree
     dt = 1e-5
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup
@@ -453,7 +454,7 @@ def main():
     if blend_frac:
         step_prm, step_alpha = ind_prm_t, torch.empty_like(alpha)
     else:
-        step_prm, step_alpha = prm, (torch.empty_like(alpha) if mortars else alpha)
+        step_prm, step_alpha = prm, alpha
     step_ind = torch.empty_like(alpha)
 
     if args.fv_stored:
@@ -470,7 +471,7 @@ def main():
     else:
         def step():
             dgfv.indicator(gm, step_prm, u, alpha=step_alpha, ind=step_ind)
-            dgfv.rk_step(gm, prm, dt, u, k, None if mortars else alpha)
+            dgfv.rk_step(gm, prm, dt, u, k, alpha)
 
     for _ in range(args.warmup):
         step()
@@ -553,7 +554,8 @@ def main():
                         f"{sorted(n_by_deg)}, {n_dof} DOFs x {wl.n_var} variables, "
                         + ("viscous (BR1), " if wl.viscous else "")
                         + (f"{len(wl.mesh.mortars)} mortars (types "
-                           f"{sorted(set(wl.mesh.mortars[:, 2].tolist()))}), " if mortars else "") +
+                           f"{sorted(set(wl.mesh.mortars[:, 2].tolist()))}, {mortar_fv} with a blended "
+                           f"side), " if mortars else "") +
                         f"{100 * mask.mean():.1f}% of elements FV-blended (N_FV={wl.n_fv}), "
                         f"5-stage 2N RK steps",
             "n_elem": wl.mesh.n_elem, "n_dof": n_dof, "n_var": wl.n_var,

@@ -83,11 +83,12 @@ enum { DGFV_RIEMANN_ROE_HH = 0, /* Roe with the Harten-Hyman entropy fix, 1 spec
  * quarters k = kp + 2 kq.  o_k maps the half's (or quarter's) face grid, p and
  * q along the big side's, to the small side's grid as `orient` does for a
  * face with the big side on the left; unused entries are -1.  The big side's
- * flux follows the paper's five steps for DG sides (see dg_rhs).  Meshes with
+ * flux follows the paper's five steps for DG sides, and their FV variants
+ * where either side is blended (see dgfv_mesh_create).  Meshes with
  * mortars need metric_degree >= 1 (>= 2 on curved elements, where the face
  * normals of a small side must be the restriction of the big side's); they
- * take alpha = NULL (the FV mortar variants are not built) and no viscous
- * terms, FV-stored elements, face fusion or adjoint (DGFV_ERR_UNSUPPORTED).
+ * take no viscous terms, FV-stored elements, face fusion or adjoint
+ * (DGFV_ERR_UNSUPPORTED).
  * Metrics Ja^d are formed in the conservative curl form (Section 3.1.1):
  *  - metric_degree >= 1 (at most min N_e): on the degree-metric_degree nodes,
  *    interpolated to each element's degree;
@@ -133,7 +134,15 @@ typedef struct {
  * receives its projection to N_k, reversed; the big side receives the
  * projection to N0 mapped with M_k0, the L2 projection of twice the half's
  * flux per split direction (the half's surface element is half the big
- * side's), summed over k. */
+ * side's), summed over k.  Where either side is blended (alpha > 0, the FV
+ * variants) the flux is taken on the small side's N_FV^2 sub-face grid
+ * instead, with the FV Riemann flux: the big side's boundary sub-cell means
+ * averaged over each sub-face of the half by overlap (a DG big side: its
+ * half's trace through V^{DG->FV}), the small side's boundary sub-cell means
+ * (or V^{DG->FV} of its trace), and h^2 V^{DG->FV} of the reversed normal.
+ * The small side receives it reversed (its DG part through V^{FV->DG} / h^2);
+ * the big side's DG part receives V^{FV->DG} of it / h^2 mapped with M_k0,
+ * a blended big side's FV part the sub-face fluxes summed by overlap. */
 dgfv_status dgfv_mesh_create(const dgfv_mesh_desc* desc, dgfv_mesh** out);
 void dgfv_mesh_destroy(dgfv_mesh* mesh);
 

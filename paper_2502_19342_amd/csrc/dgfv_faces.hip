@@ -480,6 +480,7 @@ face_fv_kernel(MeshView m, ParamsDev prm, const double* __restrict__ u, const do
   const int e = m.blend_list[blockIdx.x];
   for (int side = 0; side < 6; ++side) {
     const int f = m.elem_face[6 * e + side];
+    if (f < 0) continue;                            // a mortar side: the mortar kernel's
     const int32_t* fc = m.faces + 5 * f;
     const bool left = fc[0] == e && fc[1] == side;
     if (!left && alpha[fc[0]] > 0.0) continue;      // the blended left element owns it
@@ -641,6 +642,7 @@ face_fvs_kernel(MeshView m, ParamsDev prm, const double* __restrict__ u, const d
   const int e = m.blend_list[blockIdx.x];
   for (int side = 0; side < 6; ++side) {
     const int f = m.elem_face[6 * e + side];
+    if (f < 0) continue;                             // no mortars with FV-stored elements
     const int32_t* fc = m.faces + 5 * f;
     const bool left = fc[0] == e && fc[1] == side;
     if (!left && fv[fc[0]] > 0.0) continue;          // the FV-stored left element owns it
@@ -1007,27 +1009,35 @@ __device__ void map2d_pq(const double* src, double* T, double* dst, const double
   }
 }
 
-// Non-conforming faces (Section 3.2.3, the five steps for DG sides), one
-// mortar per one-wavefront workgroup.  For each small side k: (1) the big
-// side's trace interpolated to half (quarter) k with M_0k along the split
-// directions; (2) it, the small side's trace on the half's grid (orientation
-// o_k) and the small side's outward normal reversed, on the common degree
-// max(N0, N_k); (3) the DG Riemann flux there; (4) the small side receives its
-// projection to N_k, reversed, and the big side's share is projected to N0;
-// (5) that share is mapped with M_k0 along the split directions and summed
-// into the big side's flux.
+// Non-conforming faces (Section 3.2.3), one mortar per one-wavefront
+// workgroup.  For each small side k, when both sides are pure DG (the five
+// steps): (1) the big side's trace interpolated to half (quarter) k with M_0k
+// along the split directions; (2) it, the small side's trace on the half's
+// grid (orientation o_k) and the small side's outward normal reversed, on the
+// common degree max(N0, N_k); (3) the DG Riemann flux there; (4) the small
+// side receives its projection to N_k, reversed, and the big side's share is
+// projected to N0; (5) that share is mapped with M_k0 along the split
+// directions and summed into the big side's flux.
+// When either side is blended (the FV variants) the flux is taken on the small
+// side's N_FV^2 sub-face grid: the big side's boundary sub-cell means mapped
+// with M^FV_0k (a DG big side: its half's data of step 1 through V^{DG->FV}),
+// the small side's boundary sub-cell means (a DG small side: V^{DG->FV} of its
+// trace), and h^2 V^{DG->FV} of the reversed normal.  The small side takes the
+// flux reversed (its FV part directly, its DG part through V^{FV->DG} / h^2);
+// the big side's DG part takes V^{FV->DG} of it at N0 / h^2 mapped with M_k0,
+// a blended big side's FV part the sub-face fluxes summed with M^FV_k0.
 template <int NV>
 __global__ void __launch_bounds__(FACE_THREADS)
-face_mortar_kernel(MeshView m, ParamsDev prm, const double* __restrict__ u) {
-  __shared__ double sB[NV * GRID];    // big side's trace
+face_mortar_kernel(MeshView m, ParamsDev prm, const double* __restrict__ u, const double* __restrict__ alpha) {
+  __shared__ double sB[NV * GRID];    // big side's trace (its boundary sub-cell means if blended)
   __shared__ double sA[NV * GRID];    // big side's flux, summed over its small sides
-  __shared__ double sV[NV * GRID];    // the half's data from the big side (degree N0)
-  __shared__ double sS[NV * GRID];    // small side's trace on the half's grid (degree N_k)
+  __shared__ double sV[NV * GRID];    // the half's data from the big side
+  __shared__ double sS[NV * GRID];    // small side's trace (or boundary sub-cell means) on the half's grid
   __shared__ double sN[3 * GRID];     // small side's normal, reversed
-  __shared__ double sVM[NV * GRID];   // the three on the common degree
-  __shared__ double sSM[NV * GRID];
-  __shared__ double sNM[3 * GRID];
-  __shared__ double sF[NV * GRID];    // flux on the common degree
+  __shared__ double sVM[NV * GRID];   // the three on the common degree or the sub-face grid; a blended
+  __shared__ double sSM[NV * GRID];   // big side's FV flux sum lives in sVM (its half's data then
+  __shared__ double sNM[3 * GRID];    // come straight from the sub-cell means, in sV)
+  __shared__ double sF[NV * GRID];    // flux on the common degree or the sub-face grid
   __shared__ double sT[NV * GRID];    // scratch of the two-pass maps
   __shared__ double sT2[NV * GRID];
   const int qm = blockIdx.x;
@@ -1036,7 +1046,17 @@ face_mortar_kernel(MeshView m, ParamsDev prm, const double* __restrict__ u) {
   const int e0 = mr[0], s0 = mr[1], mt = mr[2];
   const int N0 = m.degree[e0], n0 = N0 + 1;
   const int nsub = mt == 3 ? 4 : 2;
-  gather_trace<NV>(m, u, e0, s0, 0, false, n0, sB);
+  const bool a0 = alpha && alpha[e0] > 0.0;
+  const int nF = m.n_fv, n2F = nF * nF;
+  const double h2 = (2.0 / nF) * (2.0 / nF);
+  double* sAF = sVM;
+  if (a0) {
+    gather_subcells<NV>(m, e0, s0, 0, false, sB);
+    for (int t = threadIdx.x; t < n2F; t += blockDim.x)
+      for (int v = 0; v < NV; ++v) sAF[v * GRID + t] = 0.0;
+  } else {
+    gather_trace<NV>(m, u, e0, s0, 0, false, n0, sB);
+  }
   for (int t = threadIdx.x; t < n0 * n0; t += blockDim.x)
     for (int v = 0; v < NV; ++v) sA[v * GRID + t] = 0.0;
   wave_sync();
@@ -1044,16 +1064,72 @@ face_mortar_kernel(MeshView m, ParamsDev prm, const double* __restrict__ u) {
     const int ek = mr[3 + k], sk = mr[7 + k], ok = mr[11 + k];
     const int kp = mt == 1 ? k : (mt == 2 ? -1 : (k & 1));
     const int kq = mt == 1 ? -1 : (mt == 2 ? k : (k >> 1));
-    map2d_pq<NV>(sB, sT, sV, kp >= 0 ? m.ops + m.tab.mortar_interp[N0][kp] : nullptr,
-                 kq >= 0 ? m.ops + m.tab.mortar_interp[N0][kq] : nullptr, n0);
+    const bool ak = alpha && alpha[ek] > 0.0;
+    if (a0)
+      map2d_pq<NV>(sB, sT, sV, kp >= 0 ? m.ops + m.tab.mortar_fv_interp[kp] : nullptr,
+                   kq >= 0 ? m.ops + m.tab.mortar_fv_interp[kq] : nullptr, nF);
+    else
+      map2d_pq<NV>(sB, sT, sV, kp >= 0 ? m.ops + m.tab.mortar_interp[N0][kp] : nullptr,
+                   kq >= 0 ? m.ops + m.tab.mortar_interp[N0][kq] : nullptr, n0);
     const int Nk = m.degree[ek], nk = Nk + 1;
-    gather_trace<NV>(m, u, ek, sk, ok, true, nk, sS);
+    if (ak)
+      gather_subcells<NV>(m, ek, sk, ok, true, sS);
+    else
+      gather_trace<NV>(m, u, ek, sk, ok, true, nk, sS);
     gather_trace<3>(m, m.metric + (size_t)3 * (sk >> 1) * m.n_node, ek, sk, ok, true, nk, sN);
     wave_sync();
     const double rev = (sk & 1) ? -1.0 : 1.0;       // minus the outward sign of side sk
     for (int t = threadIdx.x; t < nk * nk; t += blockDim.x)
       for (int c = 0; c < 3; ++c) sN[c * GRID + t] *= rev;
     wave_sync();
+    double* bk = m.fside + m.side_off[ek];
+    if (a0 || ak) {
+      const double* VV = sV;
+      const double* SS = sS;
+      if (!a0) {
+        map2d_sep_to<NV>(sV, sT, sVM, m.ops + m.tab.dg2fv[N0], nF, n0);
+        VV = sVM;
+        wave_sync();
+      }
+      if (!ak) {
+        map2d_sep_to<NV>(sS, sT, sSM, m.ops + m.tab.dg2fv[Nk], nF, nk);
+        SS = sSM;
+        wave_sync();
+      }
+      map2d_sep_to<3>(sN, sT, sNM, m.ops + m.tab.dg2fv[Nk], nF, nk);
+      wave_sync();
+      for (int t = threadIdx.x; t < n2F; t += blockDim.x) {
+        double uL[NV], uR[NV], F[NV];
+        for (int v = 0; v < NV; ++v) {
+          uL[v] = VV[v * GRID + t];
+          uR[v] = SS[v * GRID + t];
+        }
+        riemann<NV>(prm.face_flux_fv, prm.volume_flux, uL, uR, h2 * sNM[t], h2 * sNM[GRID + t],
+                    h2 * sNM[2 * GRID + t], m.gas, F);
+        for (int v = 0; v < NV; ++v) sF[v * GRID + t] = F[v];
+      }
+      wave_sync();
+      map2d_sep_side<NV>(bk, sF, sT, m.ops + m.tab.fv2dg[Nk], nk, nF, sk, ok, true, -1.0 / h2);
+      if (ak) write_side<NV>(m.fvside + (size_t)ek * 6 * NV * n2F, sF, sk, ok, true, nF, -1.0);
+      wave_sync();
+      map2d_sep_to<NV>(sF, sT, sT2, m.ops + m.tab.fv2dg[N0], n0, nF);
+      wave_sync();
+      map2d_pq<NV>(sT2, sT, sV, kp >= 0 ? m.ops + m.tab.mortar_proj[N0][kp] : nullptr,
+                   kq >= 0 ? m.ops + m.tab.mortar_proj[N0][kq] : nullptr, n0);
+      wave_sync();
+      const double ih2 = 1.0 / h2;
+      for (int t = threadIdx.x; t < n0 * n0; t += blockDim.x)
+        for (int v = 0; v < NV; ++v) sA[v * GRID + t] += ih2 * sV[v * GRID + t];
+      if (a0) {
+        map2d_pq<NV>(sF, sT2, sS, kp >= 0 ? m.ops + m.tab.mortar_fv_proj[kp] : nullptr,
+                     kq >= 0 ? m.ops + m.tab.mortar_fv_proj[kq] : nullptr, nF);
+        wave_sync();
+        for (int t = threadIdx.x; t < n2F; t += blockDim.x)
+          for (int v = 0; v < NV; ++v) sAF[v * GRID + t] += sS[v * GRID + t];
+      }
+      wave_sync();
+      continue;
+    }
     const int M = N0 > Nk ? N0 : Nk, nM = M + 1;
     const double* VV = sV;
     const double* SS = sS;
@@ -1081,7 +1157,6 @@ face_mortar_kernel(MeshView m, ParamsDev prm, const double* __restrict__ u) {
       for (int v = 0; v < NV; ++v) sF[v * GRID + t] = F[v];
     }
     wave_sync();
-    double* bk = m.fside + m.side_off[ek];
     if (Nk < M)
       map2d_sep_side<NV>(bk, sF, sT, m.ops + m.tab.project[M][Nk], nk, nM, sk, ok, true, -1.0);
     else
@@ -1101,6 +1176,7 @@ face_mortar_kernel(MeshView m, ParamsDev prm, const double* __restrict__ u) {
     wave_sync();
   }
   write_side<NV>(m.fside + m.side_off[e0], sA, s0, 0, false, n0, 1.0);
+  if (a0) write_side<NV>(m.fvside + (size_t)e0 * 6 * NV * n2F, sAF, s0, 0, false, nF, 1.0);
 }
 
 }  // namespace
@@ -1217,12 +1293,13 @@ hipError_t launch_visc_faces(const MeshView& m, const double* u, hipStream_t s) 
   return m.nvar == 5 ? launch_visc_faces_t<5, false>(m, u, s) : launch_visc_faces_t<6, false>(m, u, s);
 }
 
-hipError_t launch_face_mortars(const MeshView& m, const ParamsDev& p, const double* u, hipStream_t s) {
+hipError_t launch_face_mortars(const MeshView& m, const ParamsDev& p, const double* u, const double* alpha,
+                               hipStream_t s) {
   if (m.n_mortar == 0) return hipSuccess;
   if (m.nvar == 5)
-    hipLaunchKernelGGL((face_mortar_kernel<5>), dim3(m.n_mortar), dim3(FACE_THREADS), 0, s, m, p, u);
+    hipLaunchKernelGGL((face_mortar_kernel<5>), dim3(m.n_mortar), dim3(FACE_THREADS), 0, s, m, p, u, alpha);
   else
-    hipLaunchKernelGGL((face_mortar_kernel<6>), dim3(m.n_mortar), dim3(FACE_THREADS), 0, s, m, p, u);
+    hipLaunchKernelGGL((face_mortar_kernel<6>), dim3(m.n_mortar), dim3(FACE_THREADS), 0, s, m, p, u, alpha);
   return hipGetLastError();
 }
 

@@ -456,13 +456,6 @@ int side_node_h(int s, int p, int q, int n) {
   }
 }
 
-// Meshes with mortars take pure DG elements only (the FV mortar variants are not built).
-dgfv_status mortar_alpha(const dgfv_mesh* m, const double* alpha) {
-  if (m->n_mortar > 0 && alpha)
-    return fail(DGFV_ERR_UNSUPPORTED, "meshes with mortars take alpha = NULL (the FV mortar variants are not built)");
-  return DGFV_OK;
-}
-
 dgfv_status check_params(const dgfv_mesh* m, const dgfv_params* p) {
   if (!p) return fail(DGFV_ERR_ARG, "params is NULL");
   if (p->volume_flux < 0 || p->volume_flux > 2) return fail(DGFV_ERR_ARG, "volume_flux out of range");
@@ -609,7 +602,7 @@ void enqueue_rhs_impl(const dgfv_mesh* m, const ParamsDev& p, const double* u, d
       Timed tf(m, c == FACE_CLASS_FV ? DGFV_KERNEL_FV_FACE : -1, ss);
       hip_check(launch_face_class(v, p, u, alpha, c, trace_in, ss), "face launch");
     });
-    if (m->n_mortar > 0) hip_check(launch_face_mortars(v, p, u, s), "mortar launch");
+    if (m->n_mortar > 0) hip_check(launch_face_mortars(v, p, u, alpha, s), "mortar launch");
   }
   if (alpha) {
     Timed t(m, DGFV_KERNEL_FV_RESIDUAL, s);
@@ -1034,6 +1027,11 @@ dgfv_status dgfv_mesh_create(const dgfv_mesh_desc* d, dgfv_mesh** out) {
           tab.mortar_interp[N][k] = push(op_mortar_interp(N, k));
           tab.mortar_proj[N][k] = push(op_mortar_project(N, k));
         }
+      if (d->n_mortar > 0 && tab.mortar_fv_interp[0] < 0)
+        for (int k = 0; k < 2; ++k) {
+          tab.mortar_fv_interp[k] = push(op_mortar_fv_interp(NFV, k));
+          tab.mortar_fv_proj[k] = push(op_mortar_fv_project(NFV, k));
+        }
       for (int M = N + 1; M <= MAXN; ++M) {
         if (!present[M]) continue;
         tab.interp[N][M] = push(op_interp(N, M));
@@ -1403,7 +1401,6 @@ dgfv_status dg_rhs(const dgfv_mesh* m, const dgfv_params* prm, const double* u, 
   if (!m || !u || !ut) return fail(DGFV_ERR_ARG, "NULL argument");
   if (u == ut) return fail(DGFV_ERR_ARG, "u and ut must not overlap");
   if (dgfv_status st = check_params(m, prm)) return st;
-  if (dgfv_status st = mortar_alpha(m, alpha)) return st;
   hipStream_t s = (hipStream_t)stream;
   return guarded(m, s, [&] { return enqueue_rhs(m, prm, u, alpha, ut, nullptr, 0, 0.0, s); });
 }
@@ -1415,7 +1412,6 @@ dgfv_status dg_rk_stage(const dgfv_mesh* m, const dgfv_params* prm, int stage, d
   if (!std::isfinite(dt)) return fail(DGFV_ERR_ARG, "dt must be finite");
   if (u == k) return fail(DGFV_ERR_ARG, "u and k must not overlap");
   if (dgfv_status st = check_params(m, prm)) return st;
-  if (dgfv_status st = mortar_alpha(m, alpha)) return st;
   hipStream_t s = (hipStream_t)stream;
   return guarded(m, s, [&] { return run_stages(m, prm, 0, stage, stage, dt, u, k, alpha, s); });
 }
@@ -1426,7 +1422,6 @@ dgfv_status dg_rk_step(const dgfv_mesh* m, const dgfv_params* prm, double dt, do
   if (!std::isfinite(dt)) return fail(DGFV_ERR_ARG, "dt must be finite");
   if (u == k) return fail(DGFV_ERR_ARG, "u and k must not overlap");
   if (dgfv_status st = check_params(m, prm)) return st;
-  if (dgfv_status st = mortar_alpha(m, alpha)) return st;
   hipStream_t s = (hipStream_t)stream;
   return guarded(m, s, [&] { return run_stages(m, prm, 1, 1, 5, dt, u, k, alpha, s); });
 }
@@ -1435,7 +1430,6 @@ dgfv_status dgfv_autotune(dgfv_mesh* m, const dgfv_params* prm, const double* u,
                           double* ms_out, void* stream) {
   if (!m || !u) return fail(DGFV_ERR_ARG, "NULL argument");
   if (dgfv_status st = check_params(m, prm)) return st;
-  if (dgfv_status st = mortar_alpha(m, alpha)) return st;
   if (ms_out) std::fill(ms_out, ms_out + 2 * (MAXN + 1), 0.0);
   hipStream_t s = (hipStream_t)stream;
   double* scratch = nullptr;

@@ -29,6 +29,8 @@ struct OpTables {
   // mortars: [N][k] for half k of a degree-N big side, (N+1) x (N+1) each
   int mortar_interp[MAXN + 1][2];     // big side -> the nodes of half k
   int mortar_proj[MAXN + 1][2];       // half k's flux -> the big side
+  int mortar_fv_interp[2];            // NFV x NFV: the big side's sub-faces -> those of half k
+  int mortar_fv_proj[2];              // NFV x NFV: half k's sub-face fluxes -> the big side's
 };
 
 struct GasDev {
@@ -244,9 +246,11 @@ hipError_t launch_face_class(const MeshView& m, const ParamsDev& p, const double
 // viscous kernels form the same-degree faces themselves.
 hipError_t launch_lift_faces(const MeshView& m, const double* u, hipStream_t s);
 hipError_t launch_visc_faces(const MeshView& m, const double* u, hipStream_t s);
-// Fluxes of the non-conforming faces into m.fside (dgfv_faces.hip), one mortar
-// per workgroup, after the other face kernels.
-hipError_t launch_face_mortars(const MeshView& m, const ParamsDev& p, const double* u, hipStream_t s);
+// Fluxes of the non-conforming faces into m.fside, and into m.fvside for the
+// FV parts of blended sides (dgfv_faces.hip), one mortar per workgroup, after
+// the other face kernels.
+hipError_t launch_face_mortars(const MeshView& m, const ParamsDev& p, const double* u, const double* alpha,
+                               hipStream_t s);
 hipError_t launch_faces_vjp(const MeshView& m, const ParamsDev& p, const double* u, const double* alpha,
                             hipStream_t s);
 

@@ -14,6 +14,7 @@
 //  * face_interp: l_j at the N_FV + 1 sub-cell interfaces.
 #include "dgfv_ops1d.h"
 
+#include <algorithm>
 #include <cmath>
 #include <stdexcept>
 
@@ -314,4 +315,29 @@ std::vector<double> op_mortar_project(int N, int k) {
   return to_double(P);
 }
 
+// Sub-face j of half k spans [(j + k NFV)/2, (j + 1 + k NFV)/2) in units of the big side's
+// sub-faces; A[j][i] is the share of that span lying in big sub-face i (twice the overlap).
+static std::vector<LD> fv_half_overlap(int NFV, int k) {
+  std::vector<LD> A((size_t)NFV * NFV, 0.0L);
+  for (int j = 0; j < NFV; ++j) {
+    const LD lo = 0.5L * (j + k * NFV), hi = lo + 0.5L;
+    for (int i = 0; i < NFV; ++i) {
+      const LD ov = std::min(hi, (LD)(i + 1)) - std::max(lo, (LD)i);
+      A[(size_t)j * NFV + i] = ov > 0 ? 2.0L * ov : 0.0L;
+    }
+  }
+  return A;
+}
+
+std::vector<double> op_mortar_fv_interp(int NFV, int k) { return to_double(fv_half_overlap(NFV, k)); }
+
+std::vector<double> op_mortar_fv_project(int NFV, int k) {
+  const auto A = fv_half_overlap(NFV, k);
+  std::vector<LD> P((size_t)NFV * NFV);
+  for (int i = 0; i < NFV; ++i)
+    for (int j = 0; j < NFV; ++j) P[(size_t)i * NFV + j] = A[(size_t)j * NFV + i];
+  return to_double(P);
+}
+
 }  // namespace dgfv
+

@@ -22,5 +22,8 @@ std::vector<double> op_face_interp(int N, int NFV); // (NFV+1) x (N+1)
 // mortars (Section 3.2.3): half k = 0 ([-1, 0]) or 1 ([0, 1]) of a big side of degree N
 std::vector<double> op_mortar_interp(int N, int k);   // (N+1) x (N+1): big side -> nodes of half k
 std::vector<double> op_mortar_project(int N, int k);  // (N+1) x (N+1): half k's flux -> big side
+// their sub-cell variants on N_FV equal sub-faces per direction, by overlap
+std::vector<double> op_mortar_fv_interp(int NFV, int k);   // NFV x NFV: big side -> sub-faces of half k (means)
+std::vector<double> op_mortar_fv_project(int NFV, int k);  // NFV x NFV: half k's sub-face fluxes -> big side
 
 }  // namespace dgfv

@@ -628,11 +628,12 @@ def make_workload(name: str, n: int | None = None, scramble_seed: int | None = N
                         ind_T=2.0, ind_dT=1.0, blend_fraction=0.10)
     if name == "M3":
         # non-conforming: coarse for x < 1/2, halved in y and z beyond (type-3 mortars
-        # at x = 1/2 and x = 0), N = 7, pure DG (the FV mortar variants are not built)
+        # at x = 1/2 and x = 0), N = 7, a tenth of the elements blended as in C5 (the
+        # FV variants of the mortars where a blended element meets one)
         n = n or 24
         mesh = mortar_mesh(n, "yz", 7, scramble_seed=scramble_seed)
         return Workload("M3", mesh, 5, density_wave, VOL_RANOCHA, RIEMANN_ROE_HH, RIEMANN_LLF,
-                        n_fv=8, metric_degree=1, seed=7, ind_T=-1.0, ind_dT=0.5)
+                        n_fv=8, metric_degree=1, seed=7, ind_T=-1.0, ind_dT=0.5, blend_fraction=0.10)
     if name == "TGV":
         # viscous Taylor-Green vortex, Re = 1600 on the length 1/(2 pi), Ma = 0.1, Pr = 0.71;
         # smooth, so every element is DG (no blending)

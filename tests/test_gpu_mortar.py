@@ -2,9 +2,12 @@
 
 Mortar meshes of types 1/2 (refinement in y) and 3 (in y and z), scrambled
 element frames, degree jumps across the mortars, curved watertight elements,
-one and two species: the RHS, free-stream preservation, ten RK steps under
-graph replay, and the calls that reject mortar meshes.
+one and two species, pure DG and blended (the FV variants): the RHS,
+free-stream preservation, ten RK steps under graph replay, and the calls that
+reject mortar meshes.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -12,8 +15,8 @@ import torch
 from oracle import lsrk
 from paper_2502_19342_amd import workloads as W
 
-from gpu_common import Case, announce, rel_err
-from oracle_cases import smooth_state
+from gpu_common import Case, announce, rel_err, rhs_tol
+from oracle_cases import seeded_alpha, smooth_state
 
 pytestmark = pytest.mark.gpu
 T = torch.float64
@@ -75,9 +78,10 @@ def test_mortar_unsupported_calls():
     u = c.gpu(c.u)
     K = c.mesh.K
     with pytest.raises(dgfv.DgfvError):
-        dgfv.rhs(c.gmesh, c.params, u, torch.zeros(K, dtype=T, device="cuda"))
-    with pytest.raises(dgfv.DgfvError):
         c.gmesh.transport((0.01, 0.0))
+    with pytest.raises(dgfv.DgfvError):
+        dgfv.rhs_fv(c.gmesh, c.params, u, torch.zeros(K, 5, 8 ** 3, dtype=T, device="cuda"),
+                    torch.zeros(K, dtype=T, device="cuda"))
     with pytest.raises(dgfv.DgfvError):
         c.gmesh.face_fusion(True)
     with pytest.raises(dgfv.DgfvError):
@@ -85,3 +89,37 @@ def test_mortar_unsupported_calls():
     r = dgfv.rhs(c.gmesh, c.params, u)                # the mesh still works
     torch.cuda.synchronize()
     assert rel_err(r.cpu(), c.oracle_rhs()) <= 1e-12
+
+
+@pytest.mark.parametrize("refine,degree,scramble,amp,n_fv,n_var", [("y", (4, 3), 7, 0.05, 8, 5),
+                                                                   ("yz", (3, 2), 5, 0.0, 5, 5),
+                                                                   ("yz", (7, 6), 11, 0.05, 8, 6)])
+def test_mortar_blended_rhs_on_gpu(refine, degree, scramble, amp, n_fv, n_var):
+    # the FV variants: blending factors 0, 0.4 and 1 on both sides of the mortars
+    announce(f"mortar blended rhs {refine} {degree} {scramble} {amp} {n_fv} {n_var}")
+    wl = dataclasses.replace(_wl(refine, degree, scramble, amp, n_var), n_fv=n_fv)
+    c = Case(wl, prim=smooth_state(73, n_var), noise=1e-3, seed=12)
+    c.alpha = seeded_alpha(c.mesh.K, scramble, values=(0.0, 0.4, 1.0))
+    err = rel_err(c.gpu_rhs(), c.oracle_rhs())
+    print(f"[mortar] blended rhs rel err {err:.3e}", flush=True)
+    assert err <= rhs_tol(c)
+
+
+def test_mortar_blended_rk_steps_with_graphs():
+    announce("mortar blended 10 RK steps, graph replays")
+    from paper_2502_19342_amd import dgfv
+    c = Case(_wl("yz", (3, 4), 15, 0.05), prim=smooth_state(75), noise=1e-3, seed=13)
+    c.alpha = seeded_alpha(c.mesh.K, 76, values=(0.0, 0.0, 0.4, 1.0))
+    dt = 0.3 * lsrk.timestep(c.mesh, c.gas, c.u, 0.5, c.alpha)
+    c.gmesh.graphs(True)
+    ug = c.gpu(c.u)
+    k = torch.zeros_like(ug)
+    a = c.gpu(c.alpha)
+    uo = c.u.clone()
+    for _ in range(10):
+        dgfv.rk_step(c.gmesh, c.params, dt, ug, k, a)
+        uo = lsrk.step(lambda v: c.f(v, c.alpha), uo, dt)
+    torch.cuda.synchronize()
+    err = rel_err(ug.cpu(), uo)
+    print(f"[mortar] blended 10 steps rel err {err:.3e}", flush=True)
+    assert err <= 1e-10
