@@ -160,3 +160,32 @@ def test_mortar_blended_freestream_and_conservation(refine, degree, scramble, am
     R = f(problem.initial_state(om, gas, smooth_state(5)), alpha)
     wJ = om.weights_flat() * om.jacobian_flat()
     assert float(((R * wJ).sum(1).abs() / (R.abs() * wJ).sum(1))[1:].max()) <= 1e-13
+
+
+@pytest.mark.parametrize("refine,degree,amp,n_fv,seed", [("y", (4, 3), 0.05, 8, 7), ("yz", (3, 2), 0.0, 5, 5)])
+def test_mortar_rate_is_frame_invariant(refine, degree, amp, n_fv, seed):
+    # the same physical mesh, state and blending with every element's local frame rotated:
+    # the rate at each physical node is the same (the orientation maps of the DG and FV
+    # variants, the sub-face grids of both sides, the reversed normals)
+    rates, coords = [], []
+    alpha = None
+    for scramble in (None, seed):
+        mesh = W.mortar_mesh(4, refine, degree, scramble_seed=scramble, amp=amp)
+        wl = W.Workload("mortar", mesh, 5, W.density_wave, W.VOL_RANOCHA, W.RIEMANN_ROE_HH, W.RIEMANN_LLF,
+                        n_fv=n_fv, metric_degree=2 if amp else 1)
+        om, gas, f = problem.build(wl)
+        if alpha is None:
+            alpha = torch.as_tensor(np.random.default_rng(seed).choice([0.0, 0.4, 1.0], size=om.K), dtype=T)
+        rates.append(f(problem.initial_state(om, gas, smooth_state(9)), alpha))
+        coords.append((om.node_coords().numpy(), om.offset))
+    scale = rates[0].abs().amax(1, keepdim=True)
+    worst = 0.0
+    for e in range(len(coords[0][1]) - 1):
+        cols = []
+        for (x, off) in coords:
+            xe = np.round(x[:, off[e]:off[e + 1]], 9)
+            cols.append(off[e] + np.lexsort(xe[::-1]))
+        a, b = rates[0][:, cols[0]], rates[1][:, cols[1]]
+        assert np.allclose(coords[0][0][:, cols[0]], coords[1][0][:, cols[1]], atol=1e-12)
+        worst = max(worst, float(((a - b).abs() / scale).max()))
+    assert worst <= 1e-12, worst
