@@ -598,11 +598,18 @@ void enqueue_rhs_impl(const dgfv_mesh* m, const ParamsDev& p, const double* u, d
     std::vector<int> classes;
     for (int c = 1; c < FACE_CLASS_COUNT; ++c)
       if (face_class_present(v, alpha, c) && !(fuse && c >= FUSE_MIN_N && c <= MAXN)) classes.push_back(c);
+    // the mortars write only mortar sides, which no other face class touches: one more branch
+    constexpr int MORTARS = FACE_CLASS_COUNT;
+    if (m->n_mortar > 0) classes.push_back(MORTARS);
+    static_assert(FACE_CLASS_COUNT >= MAXN + 3, "a side stream for every face class and the mortars");
     fork_join(m, s, classes, [&](int c, hipStream_t ss) {
+      if (c == MORTARS) {
+        hip_check(launch_face_mortars(v, p, u, alpha, ss), "mortar launch");
+        return;
+      }
       Timed tf(m, c == FACE_CLASS_FV ? DGFV_KERNEL_FV_FACE : -1, ss);
       hip_check(launch_face_class(v, p, u, alpha, c, trace_in, ss), "face launch");
     });
-    if (m->n_mortar > 0) hip_check(launch_face_mortars(v, p, u, alpha, s), "mortar launch");
   }
   if (alpha) {
     Timed t(m, DGFV_KERNEL_FV_RESIDUAL, s);

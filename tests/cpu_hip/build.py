@@ -8,6 +8,7 @@ libasan preloaded (``asan_env()``).
 """
 from __future__ import annotations
 
+import fcntl
 import os
 import subprocess
 import sys
@@ -43,13 +44,28 @@ def _sources():
     return srcs
 
 
+def _fresh() -> bool:
+    if not os.path.exists(LIB):
+        return False
+    t = os.path.getmtime(LIB)
+    return all(os.path.getmtime(s) <= t for s in _sources())
+
+
 def build(force: bool = False) -> str:
-    """Compile (when a source is newer than the library) and return the library path."""
-    if not force and os.path.exists(LIB):
-        t = os.path.getmtime(LIB)
-        if all(os.path.getmtime(s) <= t for s in _sources()):
-            return LIB
+    """Compile (when a source is newer than the library) and return the library path.
+
+    Test processes running side by side take turns through a lock file."""
+    if not force and _fresh():
+        return LIB
     os.makedirs(OUT, exist_ok=True)
+    with open(os.path.join(OUT, ".lock"), "w") as lk:
+        fcntl.flock(lk, fcntl.LOCK_EX)
+        if not force and _fresh():
+            return LIB
+        return _compile()
+
+
+def _compile() -> str:
 
     def run(job):
         args, obj = job
