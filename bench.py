@@ -581,8 +581,11 @@ def main():
                                          "viscous kernels' bytes (the viscous section)"},
         "kernel_ms_per_stage": {kname: v[0] / max(1, v[1]) for kname, v in kt.items()},
         "kernel_ms_source": "live events over the timed steps" if live else "profiled steps after the timed region",
-        "kernel_ms_note": "phases in order: fv_means, face, fv_residual, element; fv_face lies inside face "
-                          "(beside the DG face fluxes outside --launch serial)",
+        "kernel_ms_note": "phases in order: face, element; the face phase runs the DG face classes beside "
+                          "the FV chain (fv_means, fv_face, fv_residual in order; with --fv-stored fv_face "
+                          "then fv_residual), so those lie inside face (one after another with --launch "
+                          "serial); on a mesh with mortars fv_means comes before the face phase, the mortars "
+                          "and the FV faces are branches of it, and fv_residual follows it",
         "fv_stored": fv_stored_roofline(wl, alpha_h, kt) if args.fv_stored else None,
         "viscous": visc,
         "p_adapt": padapt,

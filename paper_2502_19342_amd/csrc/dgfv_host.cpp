@@ -585,38 +585,58 @@ void enqueue_rhs_impl(const dgfv_mesh* m, const ParamsDev& p, const double* u, d
   const double B = stage > 0 ? RK_B[stage - 1] : 0.0;
   const std::vector<int> degs = degrees_present(m);
   if (m->viscous) enqueue_viscous(m, u, s, trace_in);
-  if (alpha) {
-    Timed t(m, DGFV_KERNEL_FV_MEANS, s);
-    hip_check(launch_blend_list(v, alpha, s), "blended list launch");
-    const int share = m->launch_mode == DGFV_LAUNCH_SERIAL ? 1 : (int)degs.size();
-    fork_join(m, s, degs, [&](int N, hipStream_t ss) {
+  // The face phase as concurrent branches, one per DG face class (conforming
+  // per degree, degree jumps), which read neither the sub-cell means nor the
+  // blended-element list (they test alpha per face) and write only sides of
+  // DG/DG faces.  On a conforming mesh the FV work is one more branch, in
+  // order: the list, the means, the FV faces, the FV residual (which needs
+  // only the FV faces' sub-face fluxes).  With mortars, whose blended sides
+  // read the means and whose sub-face fluxes the FV residual needs, the list
+  // and the means come first, the FV faces and the mortars are branches of
+  // their own, and the FV residual follows the join.
+  std::vector<int> classes;
+  for (int c = 1; c < FACE_CLASS_COUNT; ++c)
+    if (c != FACE_CLASS_FV && face_class_present(v, alpha, c) && !(fuse && c >= FUSE_MIN_N && c <= MAXN))
+      classes.push_back(c);
+  constexpr int FV_CHAIN = FACE_CLASS_FV, MORTARS = FACE_CLASS_COUNT;
+  static_assert(FACE_CLASS_COUNT >= MAXN + 3, "a side stream for every DG face class, the FV work and the mortars");
+  const bool mortars = m->n_mortar > 0;
+  auto fv_means = [&](hipStream_t ss, int share) {
+    Timed tm(m, DGFV_KERNEL_FV_MEANS, ss);
+    hip_check(launch_blend_list(v, alpha, ss), "blended list launch");
+    for (int N : degs)
       hip_check(ops_for(N).fv_means(v, (int)m->bucket[N].size(), share, u, ss), "fv_means launch");
-    });
-  }
+  };
+  auto fv_residual = [&](hipStream_t ss) {
+    Timed tr(m, DGFV_KERNEL_FV_RESIDUAL, ss);
+    for (int N : degs)
+      hip_check(ops_for(N).fv_residual(v, p, (int)m->bucket[N].size(), ss), "fv_residual launch");
+  };
+  auto fv_faces = [&](hipStream_t ss) {
+    if (!face_class_present(v, alpha, FACE_CLASS_FV)) return;
+    Timed tf(m, DGFV_KERNEL_FV_FACE, ss);
+    hip_check(launch_face_class(v, p, u, alpha, FACE_CLASS_FV, trace_in, ss), "face launch");
+  };
+  if (alpha && mortars) fv_means(s, 1);
   {
     Timed t(m, DGFV_KERNEL_FACE, s);
-    std::vector<int> classes;
-    for (int c = 1; c < FACE_CLASS_COUNT; ++c)
-      if (face_class_present(v, alpha, c) && !(fuse && c >= FUSE_MIN_N && c <= MAXN)) classes.push_back(c);
-    // the mortars write only mortar sides, which no other face class touches: one more branch
-    constexpr int MORTARS = FACE_CLASS_COUNT;
-    if (m->n_mortar > 0) classes.push_back(MORTARS);
-    static_assert(FACE_CLASS_COUNT >= MAXN + 3, "a side stream for every face class and the mortars");
+    if (alpha) classes.push_back(FV_CHAIN);
+    if (mortars) classes.push_back(MORTARS);
     fork_join(m, s, classes, [&](int c, hipStream_t ss) {
       if (c == MORTARS) {
         hip_check(launch_face_mortars(v, p, u, alpha, ss), "mortar launch");
-        return;
+      } else if (c != FV_CHAIN) {
+        hip_check(launch_face_class(v, p, u, alpha, c, trace_in, ss), "face launch");
+      } else if (mortars) {
+        fv_faces(ss);
+      } else {
+        fv_means(ss, 1);
+        fv_faces(ss);
+        fv_residual(ss);
       }
-      Timed tf(m, c == FACE_CLASS_FV ? DGFV_KERNEL_FV_FACE : -1, ss);
-      hip_check(launch_face_class(v, p, u, alpha, c, trace_in, ss), "face launch");
     });
   }
-  if (alpha) {
-    Timed t(m, DGFV_KERNEL_FV_RESIDUAL, s);
-    fork_join(m, s, degs, [&](int N, hipStream_t ss) {
-      hip_check(ops_for(N).fv_residual(v, p, (int)m->bucket[N].size(), ss), "fv_residual launch");
-    });
-  }
+  if (alpha && mortars) fv_residual(s);
   {
     Timed t(m, DGFV_KERNEL_ELEMENT, s);
     MeshView ve = v;
@@ -662,8 +682,8 @@ void ensure_fv_stored(const dgfv_mesh* m, hipStream_t s) {
 // One evaluation with FV-stored elements (fv[e] > 0): stage 0 -> ut = R(u) on
 // DG elements and utfv = R(ufv) on FV elements; stage 1..5 -> the RK stage on
 // (u, k) and (ufv, kfv).  Phases: the FV-element list; the DG faces (both
-// sides DG) and the faces with an FV side; the FV elements' rates; the DG
-// element kernels, which leave the FV elements alone.
+// sides DG) beside the faces with an FV side followed by the FV elements'
+// rates; the DG element kernels, which leave the FV elements alone.
 // trace_in / trace_out as in enqueue_rhs_impl (dg_rk_step_fv between its stages).
 void enqueue_rhs_fvs(const dgfv_mesh* m, const ParamsDev& p, double* u, double* ufv, const double* fv, double* ut,
                      double* utfv, double* k, double* kfv, int stage, double dt, hipStream_t s,
@@ -680,17 +700,20 @@ void enqueue_rhs_fvs(const dgfv_mesh* m, const ParamsDev& p, double* u, double* 
     for (int c = 1; c < FACE_CLASS_COUNT; ++c)
       if (c != FACE_CLASS_FV && face_class_present(v, fv, c)) classes.push_back(c);
     classes.push_back(FACE_CLASS_FV);
+    // the FV-stored elements' faces and then their rates (and RK update) form one
+    // branch beside the DG face classes, which read neither ufv nor the ghosts
     fork_join(m, s, classes, [&](int c, hipStream_t ss) {
-      Timed tf(m, c == FACE_CLASS_FV ? DGFV_KERNEL_FV_FACE : -1, ss);
-      if (c == FACE_CLASS_FV)
-        hip_check(launch_face_fv_stored(v, p, u, ufv, fv, ss), "FV-stored face launch");
-      else
+      if (c != FACE_CLASS_FV) {
         hip_check(launch_face_class(v, p, u, fv, c, trace_in, ss), "face launch");
+        return;
+      }
+      {
+        Timed tf(m, DGFV_KERNEL_FV_FACE, ss);
+        hip_check(launch_face_fv_stored(v, p, u, ufv, fv, ss), "FV-stored face launch");
+      }
+      Timed tr(m, DGFV_KERNEL_FV_RESIDUAL, ss);
+      hip_check(launch_fv_stored(v, p, ufv, kfv, utfv, stage, dt, A, B, ss), "FV-stored element launch");
     });
-  }
-  {
-    Timed t(m, DGFV_KERNEL_FV_RESIDUAL, s);
-    hip_check(launch_fv_stored(v, p, ufv, kfv, utfv, stage, dt, A, B, s), "FV-stored element launch");
   }
   {
     Timed t(m, DGFV_KERNEL_ELEMENT, s);
