@@ -584,8 +584,9 @@ def main():
         "kernel_ms_note": "phases in order: face, element; the face phase runs the DG face classes beside "
                           "the FV chain (fv_means, fv_face, fv_residual in order; with --fv-stored fv_face "
                           "then fv_residual), so those lie inside face (one after another with --launch "
-                          "serial); on a mesh with mortars fv_means comes before the face phase, the mortars "
-                          "and the FV faces are branches of it, and fv_residual follows it",
+                          "serial); on a mesh with mortars, and in graph replays of a mesh with several degrees, "
+                          "fv_means comes before the face phase, the FV faces (and the mortars) are branches "
+                          "of it, and fv_residual follows it",
         "fv_stored": fv_stored_roofline(wl, alpha_h, kt) if args.fv_stored else None,
         "viscous": visc,
         "p_adapt": padapt,

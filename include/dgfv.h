@@ -484,7 +484,8 @@ dgfv_status dgfv_prim_to_cons(const dgfv_mesh* mesh, const double* w_d, double* 
 enum { DGFV_KERNEL_ELEMENT = 0,     /* volume + lift + blend (+ RK update), all degree buckets   */
        DGFV_KERNEL_FACE = 1,        /* face phase: every interface flux; with alpha on a mesh     */
                                     /* without mortars it holds the FV chain (means, FV faces,    */
-                                    /* FV residuals) as a branch beside the DG face classes       */
+                                    /* FV residuals) as a branch beside the DG face classes,      */
+                                    /* except in graph replays of meshes with several degrees     */
        DGFV_KERNEL_FV_MEANS = 2,    /* blended list + sub-cell means                             */
        DGFV_KERNEL_FV_RESIDUAL = 3, /* FV sub-cell residuals                                     */
        DGFV_KERNEL_INDICATOR = 4,
