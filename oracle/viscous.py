@@ -29,7 +29,17 @@ summation-by-parts property of the collocated operators:
   (eq. visc_flux), formed as the convective flux: both sides' traces of
   ``u`` and ``g`` interpolated to the higher degree of the face, the fluxes
   evaluated there with the left side's outward normal, the lower side
-  receiving the projection.
+  receiving the projection;
+* mortars (Section 3.2.3): both face terms go through the mortar's virtual
+  small sides as the convective flux does.  On half (quarter) k the big
+  side's traces of ``u`` (and ``g``) are interpolated with ``M_0k``; the BR1
+  value is formed there as at a conforming face (on the lower of the two
+  degrees, interpolated up), the small side takes it, and the big side takes
+  the L2 projection of the piecewise values, ``(1/2)^s sum_k M_k0 u*_k`` for
+  ``s`` split directions (``M_k0`` projects twice the half's data per split
+  direction); the viscous flux is the mean of both sides' fluxes on the
+  common degree with the small side's outward normal reversed, the small
+  side receiving it reversed and the big side ``sum_k M_k0`` of it.
 
 Readings where the paper is silent or garbled:
 
@@ -205,7 +215,53 @@ def lift_face_values(mesh: OracleMesh, U: dict) -> dict:
         for r, (a, b) in enumerate(zip(slL.tolist(), slR.tolist())):
             out[NL][a][sL] = usL[r]
             out[NR][b][sR] = usR[r]
+    if len(mesh.mortars):
+        _mortar_lift_values(mesh, U, out)
     return out
+
+
+def _mortar_halves(row):
+    """(small element, side, orientation, split index along p or None, along q or None) per small side."""
+    mt = row[2]
+    nsub = 4 if mt == 3 else 2
+    for k in range(nsub):
+        kp, kq = (k, None) if mt == 1 else ((None, k) if mt == 2 else (k % 2, k // 2))
+        yield row[3 + k], row[7 + k], row[11 + k], kp, kq
+
+
+def _split(A_of, f: torch.Tensor, kp, kq) -> torch.Tensor:
+    """Apply ``A_of(k)`` along p (the last axis) for kp and along q for kq."""
+    if kp is not None:
+        f = apply_axis(_t(A_of(kp)), f, 0)
+    if kq is not None:
+        f = apply_axis(_t(A_of(kq)), f, 1)
+    return f
+
+
+def _mortar_lift_values(mesh: OracleMesh, U: dict, out: dict) -> None:
+    """BR1 values of the mortar sides into ``out`` (module docstring, mortars)."""
+    deg = mesh.degree
+    for row in mesh.mortars.tolist():
+        e0, s0 = row[0], row[1]
+        N0 = int(deg[e0])
+        sl0 = int(mesh.slot[e0])
+        u0 = face_slice(U[N0][sl0:sl0 + 1], s0)[0]            # [nvar, n0, n0], big side's grid
+        big = torch.zeros_like(u0)
+        for ek, sk, ok, kp, kq in _mortar_halves(row):
+            Nk = int(deg[ek])
+            slk = int(mesh.slot[ek])
+            uv = _split(lambda k: ops1d.mortar_interp(N0, k), u0, kp, kq)
+            tk = to_left(face_slice(U[Nk][slk:slk + 1], sk), ok)[0]
+            lo = min(N0, Nk)
+            a = apply2(_t(ops1d.project(N0, lo)), uv) if N0 > lo else uv
+            b = apply2(_t(ops1d.project(Nk, lo)), tk) if Nk > lo else tk
+            us = 0.5 * (a + b)
+            usk = apply2(_t(ops1d.interp(lo, Nk)), us) if Nk > lo else us
+            out[Nk][slk][sk] = to_right(usk[None], ok)[0]
+            us0 = apply2(_t(ops1d.interp(lo, N0)), us) if N0 > lo else us
+            share = 0.5 ** ((kp is not None) + (kq is not None))
+            big = big + share * _split(lambda k: ops1d.mortar_project(N0, k), us0, kp, kq)
+        out[N0][sl0][s0] = big
 
 
 def lift(mesh: OracleMesh, u: torch.Tensor) -> torch.Tensor:
@@ -277,6 +333,8 @@ def viscous_rhs(mesh: OracleMesh, gas: Gas, tr: Transport, u: torch.Tensor,
         for r, (a, b) in enumerate(zip(slL.tolist(), slR.tolist())):
             side[NL][a][sL] = FL[r]
             side[NR][b][sR] = FR[r]
+    if len(mesh.mortars):
+        _mortar_viscous_fluxes(mesh, gas, tr, U, G5, side)
 
     parts = {}
     for N, grp in mesh.groups.items():
@@ -292,6 +350,44 @@ def viscous_rhs(mesh: OracleMesh, gas: Gas, tr: Transport, u: torch.Tensor,
                 _add_on_side(acc, s, (Fs - sign * face_slice(Ft, s)) / w_end)
         parts[N] = -acc / grp.J[:, None]
     return mesh.scatter(parts, nvar)
+
+
+def _mortar_viscous_fluxes(mesh: OracleMesh, gas: Gas, tr: Transport, U: dict, G5: dict, side: dict) -> None:
+    """Outward viscous fluxes of the mortar sides into ``side`` (module docstring, mortars)."""
+    deg = mesh.degree
+
+    def flux_n(uu, gg, nvec):                                  # F^v(u, g) . n on a face grid
+        f = viscous_flux(uu, gg, gas, tr)                      # [3, nvar, n, n]
+        return sum(f[x] * nvec[x] for x in range(3))
+
+    for row in mesh.mortars.tolist():
+        e0, s0 = row[0], row[1]
+        N0 = int(deg[e0])
+        sl0 = int(mesh.slot[e0])
+        u0 = face_slice(U[N0][sl0:sl0 + 1], s0)[0]            # [nvar, n0, n0]
+        g0 = face_slice(G5[N0][sl0:sl0 + 1], s0)[0]           # [3, nvar, n0, n0]
+        big = torch.zeros_like(u0)
+        for ek, sk, ok, kp, kq in _mortar_halves(row):
+            Nk = int(deg[ek])
+            slk = int(mesh.slot[ek])
+            uv = _split(lambda k: ops1d.mortar_interp(N0, k), u0, kp, kq)
+            gv = _split(lambda k: ops1d.mortar_interp(N0, k), g0, kp, kq)
+            tk = to_left(face_slice(U[Nk][slk:slk + 1], sk), ok)[0]
+            gk = to_left(face_slice(G5[Nk][slk:slk + 1], sk), ok)[0]
+            nk = -to_left(mesh.groups[Nk].outward_normal(sk)[slk:slk + 1], ok)[0]
+            M = max(N0, Nk)
+            if N0 < M:
+                V0 = _t(ops1d.interp(N0, M))
+                uv, gv = apply2(V0, uv), apply2(V0, gv)
+            if Nk < M:
+                Vk = _t(ops1d.interp(Nk, M))
+                tk, gk, nk = apply2(Vk, tk), apply2(Vk, gk), apply2(Vk, nk)
+            F = 0.5 * (flux_n(uv, gv, nk) + flux_n(tk, gk, nk))   # [nvar, M+1, M+1], out of the big side
+            Fk = apply2(_t(ops1d.project(M, Nk)), F) if Nk < M else F
+            side[Nk][slk][sk] = -to_right(Fk[None], ok)[0]
+            Fb = apply2(_t(ops1d.project(M, N0)), F) if N0 < M else F
+            big = big + _split(lambda k: ops1d.mortar_project(N0, k), Fb, kp, kq)
+        side[N0][sl0][s0] = big
 
 
 class ViscousRhs:
