@@ -87,8 +87,9 @@ enum { DGFV_RIEMANN_ROE_HH = 0, /* Roe with the Harten-Hyman entropy fix, 1 spec
  * where either side is blended (see dgfv_mesh_create).  Meshes with
  * mortars need metric_degree >= 1 (>= 2 on curved elements, where the face
  * normals of a small side must be the restriction of the big side's); they
- * take no viscous terms, FV-stored elements, face fusion or adjoint
- * (DGFV_ERR_UNSUPPORTED).
+ * take no FV-stored elements, face fusion or adjoint (DGFV_ERR_UNSUPPORTED).
+ * Viscous terms at mortars (see dgfv_set_transport) go through the same
+ * virtual small sides.
  * Metrics Ja^d are formed in the conservative curl form (Section 3.1.1):
  *  - metric_degree >= 1 (at most min N_e): on the degree-metric_degree nodes,
  *    interpolated to each element's degree;
@@ -364,7 +365,12 @@ dgfv_status dgfv_set_face_fusion(dgfv_mesh* mesh, int enable);
  * (the face value u* = (u^- + u^+)/2 formed on the lower degree of a degree
  * jump and interpolated to the higher side); the viscous fluxes of (u, g)
  * meet at each face in their arithmetic mean on the higher degree, the lower
- * side receiving the projection.  Face fusion is off while the viscous terms
+ * side receiving the projection.  At a mortar both terms use its virtual
+ * small sides (Section 3.2.3): on half (quarter) k the big side's traces
+ * mapped with M_0k meet the small side's as at a conforming face (u* on the
+ * lower degree; the fluxes with the small side's normal reversed, on the
+ * higher), and the big side takes (1/2)^s sum_k M_k0 u*_k for its face value
+ * (s split directions) and sum_k M_k0 of the flux.  Face fusion is off while the viscous terms
  * are on; the FV-stored calls (dg_rhs_fv and its stages) and the adjoint
  * return DGFV_ERR_UNSUPPORTED.
  *

@@ -1179,6 +1179,183 @@ face_mortar_kernel(MeshView m, ParamsDev prm, const double* __restrict__ u, cons
   if (a0) write_side<NV>(m.fvside + (size_t)e0 * 6 * NV * n2F, sAF, s0, 0, false, nF, 1.0);
 }
 
+// Viscous terms at the mortars (Sections 3.1.1, 3.2.2 and 3.2.3), one mortar
+// per one-wavefront workgroup, into m.vside of the big side and of each small
+// side, where the lift and viscous kernels read them as at a degree jump.
+// Lift: on half (quarter) k the big side's trace mapped with M_0k and the
+// small side's trace meet on the lower of the two degrees (the higher one
+// projected down); their mean, interpolated up, goes to the small side, and
+// the big side takes (1/2)^s sum_k M_k0 of it (s split directions).
+template <int NV>
+__global__ void __launch_bounds__(FACE_THREADS)
+mortar_lift_kernel(MeshView m, const double* __restrict__ u) {
+  __shared__ double sB[NV * GRID];    // big side's trace
+  __shared__ double sA[NV * GRID];    // big side's face value, summed over its small sides
+  __shared__ double sV[NV * GRID];    // the half's data from the big side
+  __shared__ double sS[NV * GRID];    // small side's trace on the half's grid
+  __shared__ double sW[NV * GRID];    // a trace projected to the lower degree
+  __shared__ double sP[NV * GRID];    // the big side's share of half k
+  __shared__ double sT[NV * GRID];    // scratch of the two-pass maps
+  const int qm = blockIdx.x;
+  if (qm >= m.n_mortar) return;
+  const int32_t* mr = m.mortars + 15 * qm;
+  const int e0 = mr[0], s0 = mr[1], mt = mr[2];
+  const int N0 = m.degree[e0], n0 = N0 + 1;
+  const int nsub = mt == 3 ? 4 : 2;
+  const double share = mt == 3 ? 0.25 : 0.5;
+  gather_trace<NV>(m, u, e0, s0, 0, false, n0, sB);
+  for (int t = threadIdx.x; t < n0 * n0; t += blockDim.x)
+    for (int v = 0; v < NV; ++v) sA[v * GRID + t] = 0.0;
+  wave_sync();
+  for (int k = 0; k < nsub; ++k) {
+    const int ek = mr[3 + k], sk = mr[7 + k], ok = mr[11 + k];
+    const int kp = mt == 1 ? k : (mt == 2 ? -1 : (k & 1));
+    const int kq = mt == 1 ? -1 : (mt == 2 ? k : (k >> 1));
+    map2d_pq<NV>(sB, sT, sV, kp >= 0 ? m.ops + m.tab.mortar_interp[N0][kp] : nullptr,
+                 kq >= 0 ? m.ops + m.tab.mortar_interp[N0][kq] : nullptr, n0);
+    const int Nk = m.degree[ek], nk = Nk + 1;
+    gather_trace<NV>(m, u, ek, sk, ok, true, nk, sS);
+    wave_sync();
+    const int lo = N0 < Nk ? N0 : Nk, nlo = lo + 1;
+    double* X = sV;                   // the mean on the lower degree (in place where possible)
+    const double* Y = sS;
+    if (N0 > lo) {
+      map2d_sep_to<NV>(sV, sT, sW, m.ops + m.tab.project[N0][lo], nlo, n0);
+      X = sW;
+      wave_sync();
+    } else if (Nk > lo) {
+      map2d_sep_to<NV>(sS, sT, sW, m.ops + m.tab.project[Nk][lo], nlo, nk);
+      Y = sW;
+      wave_sync();
+    }
+    for (int t = threadIdx.x; t < nlo * nlo; t += blockDim.x)
+      for (int v = 0; v < NV; ++v) X[v * GRID + t] = 0.5 * (X[v * GRID + t] + Y[v * GRID + t]);
+    wave_sync();
+    double* bk = m.vside + m.side_off[ek];
+    if (Nk > lo)
+      map2d_sep_side<NV>(bk, X, sT, m.ops + m.tab.interp[lo][Nk], nk, nlo, sk, ok, true, 1.0);
+    else
+      write_side<NV>(bk, X, sk, ok, true, nk, 1.0);
+    wave_sync();
+    const double* Z = X;
+    if (N0 > lo) {
+      map2d_sep_to<NV>(X, sT, sS, m.ops + m.tab.interp[lo][N0], n0, nlo);
+      Z = sS;
+      wave_sync();
+    }
+    map2d_pq<NV>(Z, sT, sP, kp >= 0 ? m.ops + m.tab.mortar_proj[N0][kp] : nullptr,
+                 kq >= 0 ? m.ops + m.tab.mortar_proj[N0][kq] : nullptr, n0);
+    wave_sync();
+    for (int t = threadIdx.x; t < n0 * n0; t += blockDim.x)
+      for (int v = 0; v < NV; ++v) sA[v * GRID + t] += share * sP[v * GRID + t];
+    wave_sync();
+  }
+  write_side<NV>(m.vside + m.side_off[e0], sA, s0, 0, false, n0, 1.0);
+}
+
+// Viscous flux: on half (quarter) k the big side's traces of u and g mapped
+// with M_0k, the small side's traces and its outward normal reversed, all on
+// the common degree max(N0, N_k); the mean of the two sides' fluxes there;
+// the small side takes its projection to N_k, reversed, the big side sum_k
+// M_k0 of its projection to N0.
+template <int NV>
+__global__ void __launch_bounds__(FACE_THREADS)
+mortar_visc_kernel(MeshView m, const double* __restrict__ u) {
+  constexpr int NW = 4 * NV;          // fields per face point: u, then g_x for x = 0, 1, 2
+  __shared__ double sB[NW * GRID];    // big side's traces
+  __shared__ double sV[NW * GRID];    // the half's data from the big side
+  __shared__ double sS[NW * GRID];    // small side's traces on the half's grid
+  __shared__ double sM[NW * GRID];    // the side of lower degree on the common degree
+  __shared__ double sT[NW * GRID];    // scratch of the two-pass maps, then the flux
+  __shared__ double sN[3 * GRID];     // small side's normal, reversed
+  __shared__ double sNM[3 * GRID];
+  __shared__ double sA[NV * GRID];    // big side's flux, summed over its small sides
+  const int qm = blockIdx.x;
+  if (qm >= m.n_mortar) return;
+  const int32_t* mr = m.mortars + 15 * qm;
+  const int e0 = mr[0], s0 = mr[1], mt = mr[2];
+  const int N0 = m.degree[e0], n0 = N0 + 1;
+  const int nsub = mt == 3 ? 4 : 2;
+  auto gather_ug = [&](int e, int side, int o, bool right, int n, double* dst) {
+    gather_trace<NV>(m, u, e, side, o, right, n, dst);
+    for (int x = 0; x < 3; ++x)
+      gather_trace<NV>(m, m.grad + (size_t)x * NV * m.n_node, e, side, o, right, n, dst + (1 + x) * NV * GRID);
+  };
+  gather_ug(e0, s0, 0, false, n0, sB);
+  for (int t = threadIdx.x; t < n0 * n0; t += blockDim.x)
+    for (int v = 0; v < NV; ++v) sA[v * GRID + t] = 0.0;
+  wave_sync();
+  for (int k = 0; k < nsub; ++k) {
+    const int ek = mr[3 + k], sk = mr[7 + k], ok = mr[11 + k];
+    const int kp = mt == 1 ? k : (mt == 2 ? -1 : (k & 1));
+    const int kq = mt == 1 ? -1 : (mt == 2 ? k : (k >> 1));
+    map2d_pq<NW>(sB, sT, sV, kp >= 0 ? m.ops + m.tab.mortar_interp[N0][kp] : nullptr,
+                 kq >= 0 ? m.ops + m.tab.mortar_interp[N0][kq] : nullptr, n0);
+    const int Nk = m.degree[ek], nk = Nk + 1;
+    gather_ug(ek, sk, ok, true, nk, sS);
+    gather_trace<3>(m, m.metric + (size_t)3 * (sk >> 1) * m.n_node, ek, sk, ok, true, nk, sN);
+    wave_sync();
+    const double rev = (sk & 1) ? -1.0 : 1.0;       // minus the outward sign of side sk
+    for (int t = threadIdx.x; t < nk * nk; t += blockDim.x)
+      for (int c = 0; c < 3; ++c) sN[c * GRID + t] *= rev;
+    wave_sync();
+    const int M = N0 > Nk ? N0 : Nk, nM = M + 1;
+    const double* A = sV;
+    const double* B = sS;
+    const double* NN = sN;
+    if (N0 < M) {
+      map2d_sep_to<NW>(sV, sT, sM, m.ops + m.tab.interp[N0][M], nM, n0);
+      A = sM;
+      wave_sync();
+    } else if (Nk < M) {
+      map2d_sep_to<NW>(sS, sT, sM, m.ops + m.tab.interp[Nk][M], nM, nk);
+      wave_sync();
+      map2d_sep_to<3>(sN, sT, sNM, m.ops + m.tab.interp[Nk][M], nM, nk);
+      B = sM;
+      NN = sNM;
+      wave_sync();
+    }
+    double* Fb = sT;                  // the flux on the common degree
+    for (int t = threadIdx.x; t < nM * nM; t += blockDim.x) {
+      double ua[NV], ub[NV], ga[3][NV], gb[3][NV], fa[3][NV], fb[3][NV];
+      for (int v = 0; v < NV; ++v) {
+        ua[v] = A[v * GRID + t];
+        ub[v] = B[v * GRID + t];
+        for (int x = 0; x < 3; ++x) {
+          ga[x][v] = A[((1 + x) * NV + v) * GRID + t];
+          gb[x][v] = B[((1 + x) * NV + v) * GRID + t];
+        }
+      }
+      viscous_flux<NV>(ua, ga, m.gas, m.visc, fa);
+      viscous_flux<NV>(ub, gb, m.gas, m.visc, fb);
+      const double c0 = NN[t], c1 = NN[GRID + t], c2 = NN[2 * GRID + t];
+      for (int v = 0; v < NV; ++v)
+        Fb[v * GRID + t] = 0.5 * ((fa[0][v] * c0 + fa[1][v] * c1 + fa[2][v] * c2) +
+                                  (fb[0][v] * c0 + fb[1][v] * c1 + fb[2][v] * c2));
+    }
+    wave_sync();
+    double* bk = m.vside + m.side_off[ek];
+    if (Nk < M)
+      map2d_sep_side<NV>(bk, Fb, sS, m.ops + m.tab.project[M][Nk], nk, nM, sk, ok, true, -1.0);
+    else
+      write_side<NV>(bk, Fb, sk, ok, true, nk, -1.0);
+    wave_sync();
+    const double* FB = Fb;
+    if (N0 < M) {
+      map2d_sep_to<NV>(Fb, sS, sV, m.ops + m.tab.project[M][N0], n0, nM);
+      FB = sV;
+      wave_sync();
+    }
+    map2d_pq<NV>(FB, sS, sM, kp >= 0 ? m.ops + m.tab.mortar_proj[N0][kp] : nullptr,
+                 kq >= 0 ? m.ops + m.tab.mortar_proj[N0][kq] : nullptr, n0);
+    wave_sync();
+    for (int t = threadIdx.x; t < n0 * n0; t += blockDim.x)
+      for (int v = 0; v < NV; ++v) sA[v * GRID + t] += sM[v * GRID + t];
+    wave_sync();
+  }
+  write_side<NV>(m.vside + m.side_off[e0], sA, s0, 0, false, n0, 1.0);
+}
+
 }  // namespace
 
 template <int NV>
@@ -1291,6 +1468,24 @@ hipError_t launch_lift_faces(const MeshView& m, const double* u, hipStream_t s) 
 
 hipError_t launch_visc_faces(const MeshView& m, const double* u, hipStream_t s) {
   return m.nvar == 5 ? launch_visc_faces_t<5, false>(m, u, s) : launch_visc_faces_t<6, false>(m, u, s);
+}
+
+hipError_t launch_mortar_lift(const MeshView& m, const double* u, hipStream_t s) {
+  if (m.n_mortar == 0) return hipSuccess;
+  if (m.nvar == 5)
+    hipLaunchKernelGGL((mortar_lift_kernel<5>), dim3(m.n_mortar), dim3(FACE_THREADS), 0, s, m, u);
+  else
+    hipLaunchKernelGGL((mortar_lift_kernel<6>), dim3(m.n_mortar), dim3(FACE_THREADS), 0, s, m, u);
+  return hipGetLastError();
+}
+
+hipError_t launch_mortar_visc(const MeshView& m, const double* u, hipStream_t s) {
+  if (m.n_mortar == 0) return hipSuccess;
+  if (m.nvar == 5)
+    hipLaunchKernelGGL((mortar_visc_kernel<5>), dim3(m.n_mortar), dim3(FACE_THREADS), 0, s, m, u);
+  else
+    hipLaunchKernelGGL((mortar_visc_kernel<6>), dim3(m.n_mortar), dim3(FACE_THREADS), 0, s, m, u);
+  return hipGetLastError();
 }
 
 hipError_t launch_face_mortars(const MeshView& m, const ParamsDev& p, const double* u, const double* alpha,

@@ -566,11 +566,13 @@ void enqueue_viscous(const dgfv_mesh* m, const double* u, hipStream_t s, bool tr
   const std::vector<int> degs = degrees_present(m);
   Timed t(m, DGFV_KERNEL_VISCOUS, s);
   hip_check(launch_lift_faces(v, u, s), "lift face launch");
+  hip_check(launch_mortar_lift(v, u, s), "mortar lift launch");
   fork_join(m, s, degs, [&](int N, hipStream_t ss) {
     hip_check(viscous_ops_for(N).lift(v, m->d_bucket[N], (int)m->bucket[N].size(), u, trace_in, ss),
               "lift launch");
   });
   hip_check(launch_visc_faces(v, u, s), "viscous face launch");
+  hip_check(launch_mortar_visc(v, u, s), "mortar viscous launch");
   fork_join(m, s, degs, [&](int N, hipStream_t ss) {
     hip_check(viscous_ops_for(N).volume(v, m->d_bucket[N], (int)m->bucket[N].size(), u, m->rvisc, ss),
               "viscous volume launch");
@@ -1646,7 +1648,6 @@ dgfv_status dgfv_set_positivity_limiter(dgfv_mesh* m, int enable) {
 
 dgfv_status dgfv_set_transport(dgfv_mesh* m, const dgfv_transport* tr) {
   if (!m) return fail(DGFV_ERR_ARG, "mesh is NULL");
-  if (tr && m->n_mortar > 0) return fail(DGFV_ERR_UNSUPPORTED, "viscous terms on meshes with mortars are not built");
   if (!tr) {
     m->viscous = false;
     m->drop_graphs();
@@ -1718,6 +1719,7 @@ dgfv_status dg_lift(const dgfv_mesh* m, const double* u, double* g, void* stream
     MeshView v = m->view;
     v.grad = g;                                // the lift kernels write the caller's buffer
     hip_check(launch_lift_faces(v, u, s), "lift face launch");
+  hip_check(launch_mortar_lift(v, u, s), "mortar lift launch");
     for (int N = 1; N <= MAXN; ++N)
       if (!m->bucket[N].empty())
         hip_check(viscous_ops_for(N).lift(v, m->d_bucket[N], (int)m->bucket[N].size(), u, false, s),

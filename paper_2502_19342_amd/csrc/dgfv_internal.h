@@ -251,6 +251,10 @@ hipError_t launch_visc_faces(const MeshView& m, const double* u, hipStream_t s);
 // the other face kernels.
 hipError_t launch_face_mortars(const MeshView& m, const ParamsDev& p, const double* u, const double* alpha,
                                hipStream_t s);
+// Viscous face terms of the mortars into m.vside (dgfv_faces.hip): the BR1
+// values (before the lift kernels) and the viscous fluxes (after them).
+hipError_t launch_mortar_lift(const MeshView& m, const double* u, hipStream_t s);
+hipError_t launch_mortar_visc(const MeshView& m, const double* u, hipStream_t s);
 hipError_t launch_faces_vjp(const MeshView& m, const ParamsDev& p, const double* u, const double* alpha,
                             hipStream_t s);
 

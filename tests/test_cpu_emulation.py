@@ -345,3 +345,19 @@ def test_cpu_build_mortars_blended(refine, degree, scramble, amp, n_fv):
     c.alpha = seeded_alpha(c.mesh.K, scramble, values=(0.0, 0.4, 1.0))
     out = cpu_emu.run(wl, c.u.numpy(), ["rhs"], alpha=c.alpha.numpy())
     assert rel_err(torch.as_tensor(out["rhs"]), c.oracle_rhs()) <= 1e-12
+
+
+@pytest.mark.parametrize("refine,degree,scramble,amp,n_var", [("y", (3, 2), 7, 0.05, 5), ("yz", (2, 3), 5, 0.0, 6)])
+def test_cpu_build_viscous_mortars(refine, degree, scramble, amp, n_var):
+    # viscous terms at mortars: the lifted gradient and the rate against the oracle
+    from oracle import viscous
+    mesh = W.mortar_mesh(4, refine, degree, scramble_seed=scramble, amp=amp)
+    kw = {} if n_var == 5 else dict(kappa=W.GAS_AIR_H2["kappa"], R=W.GAS_AIR_H2["R"])
+    flux = (W.VOL_RANOCHA, W.RIEMANN_ROE_HH) if n_var == 5 else (W.VOL_PIROZZOLI, W.RIEMANN_LLF)
+    wl = W.Workload("mortar", mesh, n_var, W.density_wave, flux[0], flux[1], W.RIEMANN_LLF, n_fv=8,
+                    metric_degree=2 if amp else 1, mu=(0.02, 0.03), Pr=(0.7, 0.9), D=(0.01, 0.04), **kw)
+    c = _case(wl, smooth_state(77, n_var), noise=1e-3, seed=14)
+    out = cpu_emu.run(wl, c.u.numpy(), ["lift", "rhs"])
+    want_g = viscous.lift(c.mesh, c.u)
+    assert rel_err(torch.as_tensor(out["lift"]).reshape(3 * n_var, -1), want_g.reshape(3 * n_var, -1)) <= 1e-12
+    assert rel_err(torch.as_tensor(out["rhs"]), c.oracle_rhs()) <= 1e-12

@@ -2,9 +2,9 @@
 
 Mortar meshes of types 1/2 (refinement in y) and 3 (in y and z), scrambled
 element frames, degree jumps across the mortars, curved watertight elements,
-one and two species, pure DG and blended (the FV variants): the RHS,
-free-stream preservation, ten RK steps under graph replay, and the calls that
-reject mortar meshes.
+one and two species, pure DG and blended (the FV variants), with and without
+the viscous terms: the RHS, the lifted gradient, free-stream preservation,
+RK steps under graph replay, and the calls that reject mortar meshes.
 """
 import dataclasses
 
@@ -78,8 +78,6 @@ def test_mortar_unsupported_calls():
     u = c.gpu(c.u)
     K = c.mesh.K
     with pytest.raises(dgfv.DgfvError):
-        c.gmesh.transport((0.01, 0.0))
-    with pytest.raises(dgfv.DgfvError):
         dgfv.rhs_fv(c.gmesh, c.params, u, torch.zeros(K, 5, 8 ** 3, dtype=T, device="cuda"),
                     torch.zeros(K, dtype=T, device="cuda"))
     with pytest.raises(dgfv.DgfvError):
@@ -122,4 +120,45 @@ def test_mortar_blended_rk_steps_with_graphs():
     torch.cuda.synchronize()
     err = rel_err(ug.cpu(), uo)
     print(f"[mortar] blended 10 steps rel err {err:.3e}", flush=True)
+    assert err <= 1e-10
+
+
+def _vwl(refine, degree, scramble, amp, n_var=5):
+    return dataclasses.replace(_wl(refine, degree, scramble, amp, n_var), mu=(0.02, 0.03), Pr=(0.7, 0.9),
+                               D=(0.01, 0.04))
+
+
+@pytest.mark.parametrize("refine,degree,scramble,amp,n_var", [("y", (4, 2), 7, 0.05, 5), ("yz", (2, 4), 5, 0.0, 6),
+                                                              ("yz", (7, 6), 11, 0.05, 5)])
+def test_mortar_viscous_on_gpu(refine, degree, scramble, amp, n_var):
+    announce(f"mortar viscous {refine} {degree} {scramble} {amp} {n_var}")
+    from oracle import viscous
+    from paper_2502_19342_amd import dgfv
+    c = Case(_vwl(refine, degree, scramble, amp, n_var), prim=smooth_state(79, n_var), noise=1e-3, seed=15)
+    g = dgfv.lift(c.gmesh, c.gpu(c.u))
+    torch.cuda.synchronize()
+    want = viscous.lift(c.mesh, c.u)
+    eg = rel_err(g.cpu().reshape(3 * n_var, -1), want.reshape(3 * n_var, -1))
+    er = rel_err(c.gpu_rhs(alpha=None), c.oracle_rhs())
+    print(f"[mortar] viscous lift rel err {eg:.3e}, rhs rel err {er:.3e}", flush=True)
+    assert eg <= 1e-12 and er <= 1e-12
+
+
+def test_mortar_viscous_blended_rk_steps_with_graphs():
+    announce("mortar viscous blended 10 RK steps, graph replays")
+    from paper_2502_19342_amd import dgfv
+    c = Case(_vwl("yz", (3, 4), 15, 0.05), prim=smooth_state(81), noise=1e-3, seed=16)
+    c.alpha = seeded_alpha(c.mesh.K, 82, values=(0.0, 0.0, 0.4, 1.0))
+    dt = 0.3 * lsrk.timestep(c.mesh, c.gas, c.u, 0.5, c.alpha)
+    c.gmesh.graphs(True)
+    ug = c.gpu(c.u)
+    k = torch.zeros_like(ug)
+    a = c.gpu(c.alpha)
+    uo = c.u.clone()
+    for _ in range(10):
+        dgfv.rk_step(c.gmesh, c.params, dt, ug, k, a)
+        uo = lsrk.step(lambda v: c.f(v, c.alpha), uo, dt)
+    torch.cuda.synchronize()
+    err = rel_err(ug.cpu(), uo)
+    print(f"[mortar] viscous blended 10 steps rel err {err:.3e}", flush=True)
     assert err <= 1e-10
