@@ -41,9 +41,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="C5", choices=["C1", "C2", "C3", "C4", "C5", "TGV", "M3"],
+    ap.add_argument("--config", default="C5", choices=["C1", "C2", "C3", "C4", "C5", "TGV", "M3", "M3V"],
                     help="workload; TGV is the viscous Taylor-Green vortex (64^3, N=7), M3 the mesh with "
-                         "type-3 mortars (24^3 coarse cells, the fine half refined in y and z, N=7)")
+                         "type-3 mortars (24^3 coarse cells, the fine half refined in y and z, N=7), M3V the same with "
+                         "the viscous terms")
     ap.add_argument("--n", type=int, default=None, help="elements per direction (default: the config's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch", default="branches", choices=["serial", "branches", "graph"],
@@ -276,8 +277,9 @@ def viscous_bytes(wl, degree: np.ndarray) -> dict:
     Each kernel reads its inputs once and writes its outputs once: n nodes,
     nvar variables, 10 geometry terms per node; side nodes S_same on faces
     between elements of one degree (formed inside the lift and viscous
-    kernels) and S_jump on degree jumps (face kernels), 1.5 normal
-    components per side node where a face kernel forms a flux:
+    kernels) and S_jump on degree jumps and mortars (face and mortar kernels;
+    a mortar's big side and each small side count), 1.5 normal components
+    per side node where a face kernel forms a flux:
       lift faces:  u traces, u* per side                       2 nvar S_jump
       lift:        u, geometry, g = grad u; the neighbour's u
                    and the outward half flux F^v . n per
@@ -295,6 +297,8 @@ def viscous_bytes(wl, degree: np.ndarray) -> dict:
     same = NL == NR
     S_same = float((2 * (NL[same] + 1) ** 2).sum())
     S_jump = float(((NL[~same] + 1) ** 2 + (NR[~same] + 1) ** 2).sum())
+    for row in np.asarray(wl.mesh.mortars).reshape(-1, 15):
+        S_jump += float((N[row[0]] + 1) ** 2 + sum((N[e] + 1) ** 2 for e in row[3:7] if e >= 0))
     parts = {"lift_faces": 2 * nv * S_jump,
              "lift": (4 * nv + 10) * n + 2 * nv * S_same + nv * S_jump,
              "visc_faces": (5 * nv + 1.5) * S_jump,

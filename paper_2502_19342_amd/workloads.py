@@ -27,6 +27,8 @@ Conventions (the interface format both implementations read):
 """
 from __future__ import annotations
 
+import dataclasses
+
 import itertools
 import math
 from dataclasses import dataclass, field
@@ -634,6 +636,11 @@ def make_workload(name: str, n: int | None = None, scramble_seed: int | None = N
         mesh = mortar_mesh(n, "yz", 7, scramble_seed=scramble_seed)
         return Workload("M3", mesh, 5, density_wave, VOL_RANOCHA, RIEMANN_ROE_HH, RIEMANN_LLF,
                         n_fv=8, metric_degree=1, seed=7, ind_T=-1.0, ind_dT=0.5, blend_fraction=0.10)
+    if name == "M3V":
+        # M3 with the viscous terms (mu = 1e-3, Pr = 0.71): BR1 lifting and viscous
+        # fluxes through the mortars as well
+        return dataclasses.replace(make_workload("M3", n, scramble_seed), name="M3V", mu=(1e-3, 0.0),
+                                   Pr=(0.71, 0.71))
     if name == "TGV":
         # viscous Taylor-Green vortex, Re = 1600 on the length 1/(2 pi), Ma = 0.1, Pr = 0.71;
         # smooth, so every element is DG (no blending)
