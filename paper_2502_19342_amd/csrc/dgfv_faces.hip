@@ -1356,6 +1356,78 @@ mortar_visc_kernel(MeshView m, const double* __restrict__ u) {
   write_side<NV>(m.vside + m.side_off[e0], sA, s0, 0, false, n0, 1.0);
 }
 
+// Adjoint of the mortar fluxes, pure DG, one degree on both sides of each
+// mortar, one mortar per one-wavefront workgroup.  Forward, per small side k:
+// F = F*(M_0k t_0, t_k, n_k) gave the small side -F and the big side M_k0 F.
+// Reverse, with the side-flux cotangents b_k (small side) and A (big side):
+// F_bar = M_k0^T A - b_k, (t_v_bar, t_k_bar) = (dF*/d(t_v, t_k))^T F_bar; the
+// small side's trace cotangent is t_k_bar, the big side's sum_k M_0k^T t_v_bar.
+// In place in m.fside, like the face adjoint kernels (each side belongs to one
+// face or mortar).
+template <int NV>
+__global__ void __launch_bounds__(FACE_THREADS)
+mortar_vjp_kernel(MeshView m, ParamsDev prm, const double* __restrict__ u) {
+  __shared__ double sB[NV * GRID];    // big side's trace
+  __shared__ double sAb[NV * GRID];   // big side's flux cotangent
+  __shared__ double sUb[NV * GRID];   // big side's trace cotangent, summed over its small sides
+  __shared__ double sV[NV * GRID];    // the half's data from the big side, then its cotangent
+  __shared__ double sS[NV * GRID];    // small side's trace on the half's grid
+  __shared__ double sC[NV * GRID];    // small side's flux cotangent, then its trace cotangent
+  __shared__ double sG[NV * GRID];    // M_k0^T A
+  __shared__ double sN[3 * GRID];     // small side's normal, reversed
+  __shared__ double sT[NV * GRID];    // scratch of the two-pass maps
+  __shared__ double sT2[NV * GRID];
+  const int qm = blockIdx.x;
+  if (qm >= m.n_mortar) return;
+  const int32_t* mr = m.mortars + 15 * qm;
+  const int e0 = mr[0], s0 = mr[1], mt = mr[2];
+  const int N = m.degree[e0], n = N + 1;
+  const int nsub = mt == 3 ? 4 : 2;
+  gather_trace<NV>(m, u, e0, s0, 0, false, n, sB);
+  gather_side<NV>(m.fside + m.side_off[e0], s0, 0, false, n, sAb);
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x)
+    for (int v = 0; v < NV; ++v) sUb[v * GRID + t] = 0.0;
+  wave_sync();
+  for (int k = 0; k < nsub; ++k) {
+    const int ek = mr[3 + k], sk = mr[7 + k], ok = mr[11 + k];
+    const int kp = mt == 1 ? k : (mt == 2 ? -1 : (k & 1));
+    const int kq = mt == 1 ? -1 : (mt == 2 ? k : (k >> 1));
+    map2d_pq<NV>(sB, sT, sV, kp >= 0 ? m.ops + m.tab.mortar_interp[N][kp] : nullptr,
+                 kq >= 0 ? m.ops + m.tab.mortar_interp[N][kq] : nullptr, n);
+    map2d_pq<NV>(sAb, sT2, sG, kp >= 0 ? m.ops + m.tab.mortar_projT[N][kp] : nullptr,
+                 kq >= 0 ? m.ops + m.tab.mortar_projT[N][kq] : nullptr, n);
+    double* bk = m.fside + m.side_off[ek];
+    gather_trace<NV>(m, u, ek, sk, ok, true, n, sS);
+    gather_side<NV>(bk, sk, ok, true, n, sC);
+    gather_trace<3>(m, m.metric + (size_t)3 * (sk >> 1) * m.n_node, ek, sk, ok, true, n, sN);
+    wave_sync();
+    const double rev = (sk & 1) ? -1.0 : 1.0;       // minus the outward sign of side sk
+    for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+      double uv[NV], us[NV], Fb[NV], uvb[NV], usb[NV];
+      for (int v = 0; v < NV; ++v) {
+        uv[v] = sV[v * GRID + t];
+        us[v] = sS[v * GRID + t];
+        Fb[v] = sG[v * GRID + t] - sC[v * GRID + t];
+      }
+      riemann_vjp<NV>(prm.face_flux_dg, prm.volume_flux, uv, us, rev * sN[t], rev * sN[GRID + t],
+                      rev * sN[2 * GRID + t], m.gas, Fb, uvb, usb);
+      for (int v = 0; v < NV; ++v) {
+        sV[v * GRID + t] = uvb[v];
+        sC[v * GRID + t] = usb[v];
+      }
+    }
+    wave_sync();
+    write_side<NV>(bk, sC, sk, ok, true, n, 1.0);
+    map2d_pq<NV>(sV, sT, sT2, kp >= 0 ? m.ops + m.tab.mortar_interpT[N][kp] : nullptr,
+                 kq >= 0 ? m.ops + m.tab.mortar_interpT[N][kq] : nullptr, n);
+    wave_sync();
+    for (int t = threadIdx.x; t < n * n; t += blockDim.x)
+      for (int v = 0; v < NV; ++v) sUb[v * GRID + t] += sT2[v * GRID + t];
+    wave_sync();
+  }
+  write_side<NV>(m.fside + m.side_off[e0], sUb, s0, 0, false, n, 1.0);
+}
+
 }  // namespace
 
 template <int NV>
@@ -1468,6 +1540,15 @@ hipError_t launch_lift_faces(const MeshView& m, const double* u, hipStream_t s) 
 
 hipError_t launch_visc_faces(const MeshView& m, const double* u, hipStream_t s) {
   return m.nvar == 5 ? launch_visc_faces_t<5, false>(m, u, s) : launch_visc_faces_t<6, false>(m, u, s);
+}
+
+hipError_t launch_mortars_vjp(const MeshView& m, const ParamsDev& p, const double* u, hipStream_t s) {
+  if (m.n_mortar == 0) return hipSuccess;
+  if (m.nvar == 5)
+    hipLaunchKernelGGL((mortar_vjp_kernel<5>), dim3(m.n_mortar), dim3(FACE_THREADS), 0, s, m, p, u);
+  else
+    hipLaunchKernelGGL((mortar_vjp_kernel<6>), dim3(m.n_mortar), dim3(FACE_THREADS), 0, s, m, p, u);
+  return hipGetLastError();
 }
 
 hipError_t launch_mortar_lift(const MeshView& m, const double* u, hipStream_t s) {

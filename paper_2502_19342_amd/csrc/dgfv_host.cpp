@@ -172,6 +172,7 @@ struct dgfv_mesh {
   bool viscous = false;
   double* rvisc = nullptr;
   int n_mortar = 0;                             // non-conforming faces
+  bool mortar_jump = false;                     // a mortar whose sides differ in degree
   size_t side_total = 0;                        // doubles of one side buffer (fside, vside)
 
   // dg_timestep: per-element steps [2][K] and the two minima (made by its first call)
@@ -899,7 +900,9 @@ dgfv_status guarded(const dgfv_mesh* m, hipStream_t s, F&& call) {
 // Which adjoint paths run (see dg_rhs_vjp).
 dgfv_status vjp_paths_enabled(const dgfv_mesh* m, const double* alpha) {
   if (m->viscous) return fail(DGFV_ERR_UNSUPPORTED, "dg_rhs_vjp: the adjoint of the viscous terms is not built");
-  if (m->n_mortar > 0) return fail(DGFV_ERR_UNSUPPORTED, "dg_rhs_vjp: the adjoint of mortar faces is not built");
+  if (m->n_mortar > 0 && (alpha || m->mortar_jump))
+    return fail(DGFV_ERR_UNSUPPORTED,
+                "dg_rhs_vjp: on meshes with mortars only pure DG (alpha = NULL) without degree jumps across a mortar");
 #ifndef DGFV_CPU_ADJOINT_ALL_PATHS
   // The adjoint of FV-blended elements and of degree-jump faces faulted the GPU
   // once with no cause found: the same kernels run clean and exact in the CPU
@@ -942,6 +945,7 @@ void enqueue_vjp(const dgfv_mesh* m, const ParamsDev& p, const double* u, const 
           hip_check(ops_for(N).vjp_fv(v, p, m->d_bucket[N], (int)m->bucket[N].size(), alpha, wb, s),
                     "vjp_fv launch");
     hip_check(launch_faces_vjp(v, p, u, alpha, s), "face vjp launch");
+    if (m->n_mortar > 0) hip_check(launch_mortars_vjp(v, p, u, s), "mortar vjp launch");
     for (int N = 1; N <= MAXN; ++N)
       if (!m->bucket[N].empty())
         hip_check(ops_for(N).vjp_gather(v, m->d_bucket[N], (int)m->bucket[N].size(), alpha, gb, s),
@@ -1036,6 +1040,11 @@ dgfv_status dgfv_mesh_create(const dgfv_mesh_desc* d, dgfv_mesh** out) {
     m->F = d->n_face;
     m->n_mortar = d->n_mortar;
     m->degree.assign(d->degree, d->degree + d->n_elem);
+    for (int q = 0; q < d->n_mortar; ++q) {
+      const int32_t* mr = d->mortars + 15 * q;
+      for (int k = 0; k < 4; ++k)
+        if (mr[3 + k] >= 0 && d->degree[mr[3 + k]] != d->degree[mr[0]]) m->mortar_jump = true;
+    }
     m->offset.resize(m->K + 1);
     m->offset[0] = 0;
     for (int e = 0; e < m->K; ++e) {
@@ -1070,6 +1079,8 @@ dgfv_status dgfv_mesh_create(const dgfv_mesh_desc* d, dgfv_mesh** out) {
         for (int k = 0; k < 2; ++k) {
           tab.mortar_interp[N][k] = push(op_mortar_interp(N, k));
           tab.mortar_proj[N][k] = push(op_mortar_project(N, k));
+          tab.mortar_interpT[N][k] = push(transpose(op_mortar_interp(N, k), N + 1, N + 1));
+          tab.mortar_projT[N][k] = push(transpose(op_mortar_project(N, k), N + 1, N + 1));
         }
       if (d->n_mortar > 0 && tab.mortar_fv_interp[0] < 0)
         for (int k = 0; k < 2; ++k) {

@@ -29,6 +29,8 @@ struct OpTables {
   // mortars: [N][k] for half k of a degree-N big side, (N+1) x (N+1) each
   int mortar_interp[MAXN + 1][2];     // big side -> the nodes of half k
   int mortar_proj[MAXN + 1][2];       // half k's flux -> the big side
+  int mortar_interpT[MAXN + 1][2];    // their transposes, for the adjoint
+  int mortar_projT[MAXN + 1][2];
   int mortar_fv_interp[2];            // NFV x NFV: the big side's sub-faces -> those of half k
   int mortar_fv_proj[2];              // NFV x NFV: half k's sub-face fluxes -> the big side's
 };
@@ -251,6 +253,10 @@ hipError_t launch_visc_faces(const MeshView& m, const double* u, hipStream_t s);
 // the other face kernels.
 hipError_t launch_face_mortars(const MeshView& m, const ParamsDev& p, const double* u, const double* alpha,
                                hipStream_t s);
+// Adjoint of the mortar fluxes of pure DG meshes of one degree (dgfv_faces.hip):
+// in place in m.fside, the cotangents of the side fluxes of each mortar's sides
+// become those of their nodal traces (as launch_faces_vjp does for the faces).
+hipError_t launch_mortars_vjp(const MeshView& m, const ParamsDev& p, const double* u, hipStream_t s);
 // Viscous face terms of the mortars into m.vside (dgfv_faces.hip): the BR1
 // values (before the lift kernels) and the viscous fluxes (after them).
 hipError_t launch_mortar_lift(const MeshView& m, const double* u, hipStream_t s);

@@ -361,3 +361,18 @@ def test_cpu_build_viscous_mortars(refine, degree, scramble, amp, n_var):
     want_g = viscous.lift(c.mesh, c.u)
     assert rel_err(torch.as_tensor(out["lift"]).reshape(3 * n_var, -1), want_g.reshape(3 * n_var, -1)) <= 1e-12
     assert rel_err(torch.as_tensor(out["rhs"]), c.oracle_rhs()) <= 1e-12
+
+
+@pytest.mark.parametrize("refine,degree,scramble,amp,flux", [("y", 3, 7, 0.05, 0), ("yz", 2, 5, 0.0, 1)])
+def test_cpu_build_mortar_vjp(refine, degree, scramble, amp, flux):
+    # the adjoint through the mortar fluxes (pure DG, one degree): two cotangents
+    # against autograd through the oracle
+    mesh = W.mortar_mesh(4, refine, degree, scramble_seed=scramble, amp=amp)
+    pair = [(W.VOL_RANOCHA, W.RIEMANN_ROE_HH), (W.VOL_PIROZZOLI, W.RIEMANN_LLF)][flux]
+    wl = W.Workload("mortar", mesh, 5, W.density_wave, pair[0], pair[1], W.RIEMANN_LLF, n_fv=8,
+                    metric_degree=2 if amp else 1)
+    c = _case(wl, smooth_state(87), noise=1e-3, seed=17)
+    ws = torch.stack([torch.as_tensor(W.cotangents(s, tuple(c.u.shape)), dtype=T) for s in (88, 89)])
+    out = cpu_emu.run(wl, c.u.numpy(), ["vjp"], w=ws.numpy())
+    for b in range(2):
+        assert rel_err(torch.as_tensor(out["vjp"][b]), _oracle_vjp(c, ws[b])) <= 1e-12

@@ -4,7 +4,8 @@ Mortar meshes of types 1/2 (refinement in y) and 3 (in y and z), scrambled
 element frames, degree jumps across the mortars, curved watertight elements,
 one and two species, pure DG and blended (the FV variants), with and without
 the viscous terms: the RHS, the lifted gradient, free-stream preservation,
-RK steps under graph replay, and the calls that reject mortar meshes.
+RK steps under graph replay, the adjoint (pure DG, one degree), and the calls
+that reject mortar meshes.
 """
 import dataclasses
 
@@ -82,8 +83,11 @@ def test_mortar_unsupported_calls():
                     torch.zeros(K, dtype=T, device="cuda"))
     with pytest.raises(dgfv.DgfvError):
         c.gmesh.face_fusion(True)
-    with pytest.raises(dgfv.DgfvError):
-        dgfv.rhs_vjp(c.gmesh, c.params, u, None, torch.ones_like(u))
+    with pytest.raises(dgfv.DgfvError):                 # the adjoint: pure DG only
+        dgfv.rhs_vjp(c.gmesh, c.params, u, torch.zeros(K, dtype=T, device="cuda"), torch.ones_like(u))
+    cj = Case(_wl("y", (3, 2), None, 0.0), prim=smooth_state(61), noise=1e-3, seed=11)
+    with pytest.raises(dgfv.DgfvError):                 # ... and no degree jump across a mortar
+        dgfv.rhs_vjp(cj.gmesh, cj.params, cj.gpu(cj.u), None, torch.ones_like(cj.gpu(cj.u)))
     r = dgfv.rhs(c.gmesh, c.params, u)                # the mesh still works
     torch.cuda.synchronize()
     assert rel_err(r.cpu(), c.oracle_rhs()) <= 1e-12
@@ -162,3 +166,19 @@ def test_mortar_viscous_blended_rk_steps_with_graphs():
     err = rel_err(ug.cpu(), uo)
     print(f"[mortar] viscous blended 10 steps rel err {err:.3e}", flush=True)
     assert err <= 1e-10
+
+
+@pytest.mark.parametrize("refine,degree,scramble,amp,n_var", [("y", 3, 7, 0.05, 5), ("yz", 4, 5, 0.0, 6),
+                                                              ("yz", 7, 11, 0.05, 5)])
+def test_mortar_vjp_on_gpu(refine, degree, scramble, amp, n_var):
+    announce(f"mortar vjp {refine} {degree} {scramble} {amp} {n_var}")
+    from paper_2502_19342_amd import dgfv
+    c = Case(_wl(refine, degree, scramble, amp, n_var), prim=smooth_state(87, n_var), noise=1e-3, seed=17)
+    w = torch.as_tensor(W.cotangents(88, tuple(c.u.shape)), dtype=T)
+    uu = c.u.clone().requires_grad_(True)
+    (g_ref,) = torch.autograd.grad((c.f(uu, c.alpha) * w).sum(), uu)
+    g = dgfv.rhs_vjp(c.gmesh, c.params, c.gpu(c.u), None, c.gpu(w))
+    torch.cuda.synchronize()
+    err = rel_err(g.cpu(), g_ref)
+    print(f"[mortar] vjp rel err {err:.3e}", flush=True)
+    assert err <= 1e-12
