@@ -508,7 +508,7 @@ def main():
     if not finite:
         print("bench.py: non-finite state after the timed steps", file=sys.stderr)
         sys.exit(1)
-    adjoint = None if (args.no_adjoint or args.fv_stored or wl.viscous or mortars) else \
+    adjoint = None if (args.no_adjoint or args.fv_stored or wl.viscous) else \
         adjoint_ratio(gm, prm, u, dgfv, torch)
     padapt = p_adapt_timing(gm, prm, u, alpha, dt, dgfv, torch) if args.p_adapt else None
 

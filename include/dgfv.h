@@ -87,7 +87,8 @@ enum { DGFV_RIEMANN_ROE_HH = 0, /* Roe with the Harten-Hyman entropy fix, 1 spec
  * where either side is blended (see dgfv_mesh_create).  Meshes with
  * mortars need metric_degree >= 1 (>= 2 on curved elements, where the face
  * normals of a small side must be the restriction of the big side's); they
- * take no FV-stored elements, face fusion or adjoint (DGFV_ERR_UNSUPPORTED).
+ * take no FV-stored elements or face fusion (DGFV_ERR_UNSUPPORTED); the
+ * adjoint takes them pure DG with one degree across each mortar.
  * Viscous terms at mortars (see dgfv_set_transport) go through the same
  * virtual small sides.
  * Metrics Ja^d are formed in the conservative curl form (Section 3.1.1):
@@ -433,7 +434,11 @@ dgfv_status dgfv_set_element_shape(dgfv_mesh* mesh, int degree, int shape);
  *     g_b = (dR/du (u))^T w_b,  b = 0..batch-1,
  * w_d, g_d: [batch][n_var][n_node]; alpha_d as for dg_rhs.  Derivatives at
  * the switches of the Riemann solvers (entropy fix, max) are those of the
- * branch taken.
+ * branch taken.  Built for alpha_d = NULL (pure DG) on meshes of one degree,
+ * mortars included (their fluxes reversed per small side: F_bar = M_k0^T A -
+ * b_k, the Riemann flux's VJP at the half's nodes, M_0k^T back to the big
+ * side); other cases, and meshes with the viscous terms, return
+ * DGFV_ERR_UNSUPPORTED.
  */
 dgfv_status dg_rhs_vjp(const dgfv_mesh* mesh, const dgfv_params* params, const double* u_d,
                        const double* alpha_d, const double* w_d, double* g_d, int batch,
