@@ -35,6 +35,17 @@ Readings where the paper is silent:
   elements);
 * sub-face normals are ``h^2`` times the mean of ``Ja^d`` over the sub-face
   (the same as for blended elements);
+* mortars (Section 3.2.3): where neither side is FV the DG mortar flux; else
+  the FV variant on each small side's sub-face grid, as for blended
+  elements, with the reconstruction above: an FV small side reconstructs
+  from its boundary and next layers with the big side's data on its half as
+  ghost (the big side's boundary means through ``M^FV_0k``, or a DG big
+  side's half trace through ``V^{DG->FV}``); an FV big side's ghost on each
+  of its sub-faces is the mean of the small sides' boundary data over it,
+  ``(1/2)^s sum_k M^FV_k0 c_k``, and its reconstructed face values reach the
+  halves through ``M^FV_0k``; the small side takes the flux reversed, the big
+  side ``sum_k M^FV_k0`` of it (FV) or ``sum_k M_k0`` of its ``V^{FV->DG} /
+  h^2`` (DG);
 * switching: DG -> FV ``ubar = V3(J u) / V3(J)``; FV -> DG
   ``u = V3^+(ubar V3(J)) / J``, the least-squares DG state whose J-weighted
   sub-cell contents are those of ``ubar`` (exactly them for ``N_FV = N + 1``).
@@ -47,7 +58,7 @@ import torch
 from . import ops1d
 from .geometry import OracleMesh, apply3, apply_axis, face_slice, _t
 from .physics import Gas, prim_to_cons, riemann, to_prim
-from .rhs import Params, Rhs, apply2, to_left, to_right, volume_term
+from .rhs import Params, Rhs, apply2, mortar_halves, split_apply, to_left, to_right, volume_term
 
 T = torch.float64
 
@@ -186,6 +197,9 @@ class NativeRhs:
             else:
                 Fdg[eR][sR] = -to_right(apply2(_t(ops1d.fv2dg(NR, NFV)), Fs) / (h * h), o)
 
+        if len(m.mortars):
+            self._mortars(U, ufv, flag, Fdg, Ffv, ghost)
+
         R = {}
         Rfv = torch.zeros_like(ufv)
         for N, g in m.groups.items():
@@ -210,6 +224,75 @@ class NativeRhs:
                     Rfv[e] = self._fv_rate(ufv[e], [ghost[e][sd] for sd in range(6)],
                                            [Ffv[e][sd] for sd in range(6)], [nd[s] for nd in nrm], jb[s])
         return m.scatter(R, nvar), Rfv
+
+    def _mortars(self, U, ufv, flag, Fdg, Ffv, ghost):
+        """Side fluxes (and the FV sides' ghost layers) of the mortars (module docstring, mortars)."""
+        m, gas, prm = self.mesh, self.gas, self.params
+        NFV, h2 = m.n_fv, self.h * self.h
+        deg = m.degree
+        for row in m.mortars.tolist():
+            e0, s0 = row[0], row[1]
+            N0 = int(deg[e0])
+            t0 = face_slice(U[N0][m.slot[e0]], s0)                 # [nvar, n0, n0], the big side's grid
+            share = 0.5 ** (1 + (row[2] == 3))
+            small = []
+            for ek, sk, ok, kp, kq in mortar_halves(row):
+                Nk = int(deg[ek])
+                tk = to_left(face_slice(U[Nk][m.slot[ek]], sk), ok)
+                nk = -to_left(m.groups[Nk].outward_normal(sk)[m.slot[ek]], ok)
+                ck = to_left(layer(ufv[ek], sk, 0), ok) if flag[ek] else apply2(_t(ops1d.dg2fv(Nk, NFV)), tk)
+                small.append((ek, sk, ok, kp, kq, Nk, tk, nk, ck))
+            if flag[e0]:
+                g0 = sum(share * split_apply(lambda k: ops1d.mortar_fv_project(NFV, k), c[8], c[3], c[4])
+                         for c in small)                         # the big side's ghost, its own grid
+                ghost[e0][s0] = g0
+                vb = prim_to_cons(face_value(to_w(layer(ufv[e0], s0, 0), gas), to_w(layer(ufv[e0], s0, 1), gas),
+                                             to_w(g0, gas)), gas)
+                Fbig = torch.zeros(gas.nvar, NFV, NFV, dtype=T)
+            else:
+                Fbig = torch.zeros_like(t0)
+            for ek, sk, ok, kp, kq, Nk, tk, nk, ck in small:
+                uv = split_apply(lambda k: ops1d.mortar_interp(N0, k), t0, kp, kq)
+                if not flag[e0] and not flag[ek]:                 # the DG mortar flux
+                    M = max(N0, Nk)
+                    if N0 < M:
+                        uv = apply2(_t(ops1d.interp(N0, M)), uv)
+                    if Nk < M:
+                        Vk = _t(ops1d.interp(Nk, M))
+                        tk, nk = apply2(Vk, tk), apply2(Vk, nk)
+                    F = riemann(prm.face_flux_dg, uv, tk, nk, gas, prm.volume_flux)
+                    Fs = apply2(_t(ops1d.project(M, Nk)), F) if Nk < M else F
+                    Fdg[ek][sk] = -to_right(Fs[None], ok)[0]
+                    Fb = apply2(_t(ops1d.project(M, N0)), F) if N0 < M else F
+                    Fbig = Fbig + split_apply(lambda k: ops1d.mortar_project(N0, k), Fb, kp, kq)
+                    continue
+                if flag[e0]:
+                    vb_k = split_apply(lambda k: ops1d.mortar_fv_interp(NFV, k), vb, kp, kq)
+                else:
+                    vb_k = apply2(_t(ops1d.dg2fv(N0, NFV)), uv)
+                if flag[ek]:
+                    cg = split_apply(lambda k: ops1d.mortar_fv_interp(NFV, k), layer(ufv[e0], s0, 0), kp, kq) \
+                        if flag[e0] else vb_k
+                    ghost[ek][sk] = to_right(cg[None], ok)[0]
+                    vs = prim_to_cons(face_value(to_w(ck, gas), to_w(to_left(layer(ufv[ek], sk, 1), ok), gas),
+                                                 to_w(cg, gas)), gas)
+                else:
+                    vs = ck
+                Fs = riemann(prm.face_flux_fv, vb_k, vs, h2 * apply2(_t(ops1d.dg2fv(Nk, NFV)), nk), gas,
+                             prm.volume_flux)                      # [nvar, NFV, NFV] on the half's grid
+                if flag[ek]:
+                    Ffv[ek][sk] = -to_right(Fs[None], ok)[0]
+                else:
+                    Fdg[ek][sk] = -to_right((apply2(_t(ops1d.fv2dg(Nk, NFV)), Fs) / h2)[None], ok)[0]
+                if flag[e0]:
+                    Fbig = Fbig + split_apply(lambda k: ops1d.mortar_fv_project(NFV, k), Fs, kp, kq)
+                else:
+                    Fbig = Fbig + split_apply(lambda k: ops1d.mortar_project(N0, k),
+                                              apply2(_t(ops1d.fv2dg(N0, NFV)), Fs) / h2, kp, kq)
+            if flag[e0]:
+                Ffv[e0][s0] = Fbig
+            else:
+                Fdg[e0][s0] = Fbig
 
     def _fv_rate(self, ub, ghosts, sides, nrm, jb):
         """Rate of one FV element's means (eq. semidiscrete_fv with the minmod reconstruction)."""

@@ -130,6 +130,24 @@ def apply2(A: torch.Tensor, f: torch.Tensor) -> torch.Tensor:
     return apply_axis(A, apply_axis(A, f, 0), 1)
 
 
+def mortar_halves(row):
+    """(small element, side, orientation, split index along p or None, along q or None) per small side."""
+    mt = row[2]
+    nsub = 4 if mt == 3 else 2
+    for k in range(nsub):
+        kp, kq = (k, None) if mt == 1 else ((None, k) if mt == 2 else (k % 2, k // 2))
+        yield row[3 + k], row[7 + k], row[11 + k], kp, kq
+
+
+def split_apply(A_of, f: torch.Tensor, kp, kq) -> torch.Tensor:
+    """Apply ``A_of(k)`` along p (the last axis) for kp and along q for kq."""
+    if kp is not None:
+        f = apply_axis(_t(A_of(kp)), f, 0)
+    if kq is not None:
+        f = apply_axis(_t(A_of(kq)), f, 1)
+    return f
+
+
 class Rhs:
     """Evaluates R(u) on one mesh; ``alpha`` is frozen per call."""
 

@@ -70,7 +70,7 @@ import torch
 from . import ops1d
 from .geometry import OracleMesh, apply_axis, face_slice, _t
 from .physics import Gas
-from .rhs import apply2, to_left, to_right
+from .rhs import apply2, mortar_halves, split_apply, to_left, to_right
 
 T = torch.float64
 
@@ -220,24 +220,6 @@ def lift_face_values(mesh: OracleMesh, U: dict) -> dict:
     return out
 
 
-def _mortar_halves(row):
-    """(small element, side, orientation, split index along p or None, along q or None) per small side."""
-    mt = row[2]
-    nsub = 4 if mt == 3 else 2
-    for k in range(nsub):
-        kp, kq = (k, None) if mt == 1 else ((None, k) if mt == 2 else (k % 2, k // 2))
-        yield row[3 + k], row[7 + k], row[11 + k], kp, kq
-
-
-def _split(A_of, f: torch.Tensor, kp, kq) -> torch.Tensor:
-    """Apply ``A_of(k)`` along p (the last axis) for kp and along q for kq."""
-    if kp is not None:
-        f = apply_axis(_t(A_of(kp)), f, 0)
-    if kq is not None:
-        f = apply_axis(_t(A_of(kq)), f, 1)
-    return f
-
-
 def _mortar_lift_values(mesh: OracleMesh, U: dict, out: dict) -> None:
     """BR1 values of the mortar sides into ``out`` (module docstring, mortars)."""
     deg = mesh.degree
@@ -247,10 +229,10 @@ def _mortar_lift_values(mesh: OracleMesh, U: dict, out: dict) -> None:
         sl0 = int(mesh.slot[e0])
         u0 = face_slice(U[N0][sl0:sl0 + 1], s0)[0]            # [nvar, n0, n0], big side's grid
         big = torch.zeros_like(u0)
-        for ek, sk, ok, kp, kq in _mortar_halves(row):
+        for ek, sk, ok, kp, kq in mortar_halves(row):
             Nk = int(deg[ek])
             slk = int(mesh.slot[ek])
-            uv = _split(lambda k: ops1d.mortar_interp(N0, k), u0, kp, kq)
+            uv = split_apply(lambda k: ops1d.mortar_interp(N0, k), u0, kp, kq)
             tk = to_left(face_slice(U[Nk][slk:slk + 1], sk), ok)[0]
             lo = min(N0, Nk)
             a = apply2(_t(ops1d.project(N0, lo)), uv) if N0 > lo else uv
@@ -260,7 +242,7 @@ def _mortar_lift_values(mesh: OracleMesh, U: dict, out: dict) -> None:
             out[Nk][slk][sk] = to_right(usk[None], ok)[0]
             us0 = apply2(_t(ops1d.interp(lo, N0)), us) if N0 > lo else us
             share = 0.5 ** ((kp is not None) + (kq is not None))
-            big = big + share * _split(lambda k: ops1d.mortar_project(N0, k), us0, kp, kq)
+            big = big + share * split_apply(lambda k: ops1d.mortar_project(N0, k), us0, kp, kq)
         out[N0][sl0][s0] = big
 
 
@@ -367,11 +349,11 @@ def _mortar_viscous_fluxes(mesh: OracleMesh, gas: Gas, tr: Transport, U: dict, G
         u0 = face_slice(U[N0][sl0:sl0 + 1], s0)[0]            # [nvar, n0, n0]
         g0 = face_slice(G5[N0][sl0:sl0 + 1], s0)[0]           # [3, nvar, n0, n0]
         big = torch.zeros_like(u0)
-        for ek, sk, ok, kp, kq in _mortar_halves(row):
+        for ek, sk, ok, kp, kq in mortar_halves(row):
             Nk = int(deg[ek])
             slk = int(mesh.slot[ek])
-            uv = _split(lambda k: ops1d.mortar_interp(N0, k), u0, kp, kq)
-            gv = _split(lambda k: ops1d.mortar_interp(N0, k), g0, kp, kq)
+            uv = split_apply(lambda k: ops1d.mortar_interp(N0, k), u0, kp, kq)
+            gv = split_apply(lambda k: ops1d.mortar_interp(N0, k), g0, kp, kq)
             tk = to_left(face_slice(U[Nk][slk:slk + 1], sk), ok)[0]
             gk = to_left(face_slice(G5[Nk][slk:slk + 1], sk), ok)[0]
             nk = -to_left(mesh.groups[Nk].outward_normal(sk)[slk:slk + 1], ok)[0]
@@ -386,7 +368,7 @@ def _mortar_viscous_fluxes(mesh: OracleMesh, gas: Gas, tr: Transport, U: dict, G
             Fk = apply2(_t(ops1d.project(M, Nk)), F) if Nk < M else F
             side[Nk][slk][sk] = -to_right(Fk[None], ok)[0]
             Fb = apply2(_t(ops1d.project(M, N0)), F) if N0 < M else F
-            big = big + _split(lambda k: ops1d.mortar_project(N0, k), Fb, kp, kq)
+            big = big + split_apply(lambda k: ops1d.mortar_project(N0, k), Fb, kp, kq)
         side[N0][sl0][s0] = big
 
 
