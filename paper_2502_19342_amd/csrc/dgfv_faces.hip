@@ -1428,6 +1428,262 @@ mortar_vjp_kernel(MeshView m, ParamsDev prm, const double* __restrict__ u) {
   write_side<NV>(m.fside + m.side_off[e0], sUb, s0, 0, false, n, 1.0);
 }
 
+// Sub-cell layer `depth` (0 at the side) of side `side` of element e's means
+// (ub: [K][NV][n^3]) on the left side's sub-face grid.
+template <int NV>
+__device__ void gather_layer(const double* ub, int e, int side, int depth, int o, bool right, int n, double* dst) {
+  const int S3 = n * n * n;
+  const double* b = ub + (size_t)e * NV * S3;
+  const int step = (side >> 1) == 0 ? 1 : ((side >> 1) == 1 ? n : n * n);
+  const int inward = (side & 1) ? -depth * step : depth * step;
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+    int p = t % n, q = t / n;
+    if (right) orient_map(o, p, q, n, p, q);
+    const int c = side_node(side, p, q, n) + inward;
+    for (int v = 0; v < NV; ++v) dst[v * GRID + t] = b[v * S3 + c];
+  }
+}
+
+// dst = the minmod-reconstructed face value of boundary means cb with the next
+// means ci and the ghost cg (primitives; cb + minmod(cb - ci, cg - cb) / 2).
+template <int NV>
+__device__ void reconstruct_face(const double* cb, const double* ci, const double* cg, const GasDev& gas, int n2,
+                                 double* dst) {
+  for (int t = threadIdx.x; t < n2; t += blockDim.x) {
+    double xb[NV], xi[NV], xg[NV], wb[NV], wi[NV], wg[NV], wf[NV], out[NV];
+    for (int v = 0; v < NV; ++v) {
+      xb[v] = cb[v * GRID + t];
+      xi[v] = ci[v * GRID + t];
+      xg[v] = cg[v * GRID + t];
+    }
+    cons_to_w<NV>(xb, gas, wb);
+    cons_to_w<NV>(xi, gas, wi);
+    cons_to_w<NV>(xg, gas, wg);
+    for (int v = 0; v < NV; ++v) wf[v] = wb[v] + 0.5 * minmod(wb[v] - wi[v], wg[v] - wb[v]);
+    w_to_cons<NV>(wf, gas, out);
+    for (int v = 0; v < NV; ++v) dst[v * GRID + t] = out[v];
+  }
+}
+
+// Mortars with FV-stored elements (fv[e] > 0; Sections 3.1.2, 3.2.3), one
+// mortar per one-wavefront workgroup.  A small side whose half has no
+// FV-stored side takes the DG mortar flux.  Otherwise the flux is taken on the
+// small side's N_FV^2 sub-face grid with the FV Riemann flux, as for blended
+// elements, between minmod-reconstructed values: an FV-stored small side
+// reconstructs from its boundary and next layers with the big side's data on
+// its half as ghost (the big side's boundary means through M^FV_0k, or a DG
+// big side's half trace through V^{DG->FV}); an FV-stored big side's ghost
+// on each of its sub-faces is the mean of the small sides' boundary data
+// over it, (1/2)^s sum_k M^FV_k0 c_k, and its reconstructed face values reach
+// the halves through M^FV_0k.  The small side takes the flux reversed
+// (m.fvside, or m.fside through V^{FV->DG} / h^2); the big side sum_k M^FV_k0
+// of it (m.fvside) or sum_k M_k0 of its V^{FV->DG} / h^2 (m.fside).  The
+// ghosts of FV-stored sides go to m.fvghost.
+template <int NV>
+__global__ void __launch_bounds__(FACE_THREADS)
+mortar_fvs_kernel(MeshView m, ParamsDev prm, const double* __restrict__ u, const double* __restrict__ ufv,
+                  const double* __restrict__ fv) {
+  __shared__ double sB[NV * GRID];    // big side's trace (DG) or boundary means (FV)
+  __shared__ double sI[NV * GRID];    // FV big side: its next layer, then its reconstructed face values
+  __shared__ double sG0[NV * GRID];   // FV big side: its ghost
+  __shared__ double sA[NV * GRID];    // big side's flux, summed over its small sides
+  __shared__ double sV[NV * GRID];    // the big side's data on the half
+  __shared__ double sS[NV * GRID];    // small side's trace or boundary means on the half's grid
+  __shared__ double sSI[NV * GRID];   // FV small side: its next layer
+  __shared__ double sCG[NV * GRID];   // FV small side: its ghost, then its reconstructed values
+  __shared__ double sN[3 * GRID];     // small side's normal, reversed
+  __shared__ double sNM[3 * GRID];    // on the common degree or the sub-face grid
+  __shared__ double sVM[NV * GRID];   // DG data on the common degree or the sub-face grid
+  __shared__ double sSM[NV * GRID];
+  __shared__ double sF[NV * GRID];    // flux
+  __shared__ double sT[NV * GRID];    // scratch of the two-pass maps
+  __shared__ double sT2[NV * GRID];
+  const int qm = blockIdx.x;
+  if (qm >= m.n_mortar) return;
+  const int32_t* mr = m.mortars + 15 * qm;
+  const int e0 = mr[0], s0 = mr[1], mt = mr[2];
+  const int N0 = m.degree[e0], n0 = N0 + 1;
+  const int nsub = mt == 3 ? 4 : 2;
+  const bool a0 = fv[e0] > 0.0;
+  const int nF = m.n_fv, n2F = nF * nF;
+  const double h2 = (2.0 / nF) * (2.0 / nF);
+  const size_t fblk = (size_t)6 * NV * n2F;
+  auto split = [&](int k, int& kp, int& kq) {
+    kp = mt == 1 ? k : (mt == 2 ? -1 : (k & 1));
+    kq = mt == 1 ? -1 : (mt == 2 ? k : (k >> 1));
+  };
+  if (a0) {
+    // the big side's ghost from every small side's boundary data, then its face values
+    gather_layer<NV>(ufv, e0, s0, 0, 0, false, nF, sB);
+    gather_layer<NV>(ufv, e0, s0, 1, 0, false, nF, sI);
+    for (int t = threadIdx.x; t < n2F; t += blockDim.x)
+      for (int v = 0; v < NV; ++v) sG0[v * GRID + t] = 0.0;
+    wave_sync();
+    const double share = mt == 3 ? 0.25 : 0.5;
+    for (int k = 0; k < nsub; ++k) {
+      const int ek = mr[3 + k], sk = mr[7 + k], ok = mr[11 + k];
+      int kp, kq;
+      split(k, kp, kq);
+      const double* C = sS;
+      if (fv[ek] > 0.0) {
+        gather_layer<NV>(ufv, ek, sk, 0, ok, true, nF, sS);
+      } else {
+        const int nk = m.degree[ek] + 1;
+        gather_trace<NV>(m, u, ek, sk, ok, true, nk, sSM);
+        wave_sync();
+        map2d_sep_to<NV>(sSM, sT, sS, m.ops + m.tab.dg2fv[nk - 1], nF, nk);
+      }
+      wave_sync();
+      map2d_pq<NV>(C, sT, sT2, kp >= 0 ? m.ops + m.tab.mortar_fv_proj[kp] : nullptr,
+                   kq >= 0 ? m.ops + m.tab.mortar_fv_proj[kq] : nullptr, nF);
+      wave_sync();
+      for (int t = threadIdx.x; t < n2F; t += blockDim.x)
+        for (int v = 0; v < NV; ++v) sG0[v * GRID + t] += share * sT2[v * GRID + t];
+      wave_sync();
+    }
+    write_side<NV>(m.fvghost + (size_t)e0 * fblk, sG0, s0, 0, false, nF, 1.0);
+    reconstruct_face<NV>(sB, sI, sG0, m.gas, n2F, sI);     // in place: each lane its own point
+    for (int t = threadIdx.x; t < n2F; t += blockDim.x)
+      for (int v = 0; v < NV; ++v) sA[v * GRID + t] = 0.0;
+  } else {
+    gather_trace<NV>(m, u, e0, s0, 0, false, n0, sB);
+    for (int t = threadIdx.x; t < n0 * n0; t += blockDim.x)
+      for (int v = 0; v < NV; ++v) sA[v * GRID + t] = 0.0;
+  }
+  wave_sync();
+  for (int k = 0; k < nsub; ++k) {
+    const int ek = mr[3 + k], sk = mr[7 + k], ok = mr[11 + k];
+    int kp, kq;
+    split(k, kp, kq);
+    const bool ak = fv[ek] > 0.0;
+    const int Nk = m.degree[ek], nk = Nk + 1;
+    double* bk = m.fside + m.side_off[ek];
+    gather_trace<3>(m, m.metric + (size_t)3 * (sk >> 1) * m.n_node, ek, sk, ok, true, nk, sN);
+    if (!a0)
+      map2d_pq<NV>(sB, sT, sV, kp >= 0 ? m.ops + m.tab.mortar_interp[N0][kp] : nullptr,
+                   kq >= 0 ? m.ops + m.tab.mortar_interp[N0][kq] : nullptr, n0);
+    if (ak) {
+      gather_layer<NV>(ufv, ek, sk, 0, ok, true, nF, sS);
+      gather_layer<NV>(ufv, ek, sk, 1, ok, true, nF, sSI);
+    } else {
+      gather_trace<NV>(m, u, ek, sk, ok, true, nk, sS);
+    }
+    wave_sync();
+    const double rev = (sk & 1) ? -1.0 : 1.0;       // minus the outward sign of side sk
+    for (int t = threadIdx.x; t < nk * nk; t += blockDim.x)
+      for (int c = 0; c < 3; ++c) sN[c * GRID + t] *= rev;
+    wave_sync();
+    if (!a0 && !ak) {
+      // the DG mortar flux on the common degree
+      const int M = N0 > Nk ? N0 : Nk, nM = M + 1;
+      const double* VV = sV;
+      const double* SS = sS;
+      const double* NN = sN;
+      if (N0 < M) {
+        map2d_sep_to<NV>(sV, sT, sVM, m.ops + m.tab.interp[N0][M], nM, n0);
+        VV = sVM;
+        wave_sync();
+      }
+      if (Nk < M) {
+        map2d_sep_to<NV>(sS, sT, sSM, m.ops + m.tab.interp[Nk][M], nM, nk);
+        wave_sync();
+        map2d_sep_to<3>(sN, sT, sNM, m.ops + m.tab.interp[Nk][M], nM, nk);
+        SS = sSM;
+        NN = sNM;
+        wave_sync();
+      }
+      for (int t = threadIdx.x; t < nM * nM; t += blockDim.x) {
+        double uL[NV], uR[NV], F[NV];
+        for (int v = 0; v < NV; ++v) {
+          uL[v] = VV[v * GRID + t];
+          uR[v] = SS[v * GRID + t];
+        }
+        riemann<NV>(prm.face_flux_dg, prm.volume_flux, uL, uR, NN[t], NN[GRID + t], NN[2 * GRID + t], m.gas, F);
+        for (int v = 0; v < NV; ++v) sF[v * GRID + t] = F[v];
+      }
+      wave_sync();
+      if (Nk < M)
+        map2d_sep_side<NV>(bk, sF, sT, m.ops + m.tab.project[M][Nk], nk, nM, sk, ok, true, -1.0);
+      else
+        write_side<NV>(bk, sF, sk, ok, true, nk, -1.0);
+      wave_sync();
+      const double* FB = sF;
+      if (N0 < M) {
+        map2d_sep_to<NV>(sF, sT, sT2, m.ops + m.tab.project[M][N0], n0, nM);
+        FB = sT2;
+        wave_sync();
+      }
+      map2d_pq<NV>(FB, sT, sV, kp >= 0 ? m.ops + m.tab.mortar_proj[N0][kp] : nullptr,
+                   kq >= 0 ? m.ops + m.tab.mortar_proj[N0][kq] : nullptr, n0);
+      wave_sync();
+      for (int t = threadIdx.x; t < n0 * n0; t += blockDim.x)
+        for (int v = 0; v < NV; ++v) sA[v * GRID + t] += sV[v * GRID + t];
+      wave_sync();
+      continue;
+    }
+    // the FV variant on the small side's sub-face grid: the big side's value on the half (sVM)
+    if (a0) {
+      map2d_pq<NV>(sI, sT, sVM, kp >= 0 ? m.ops + m.tab.mortar_fv_interp[kp] : nullptr,
+                   kq >= 0 ? m.ops + m.tab.mortar_fv_interp[kq] : nullptr, nF);
+    } else {
+      map2d_sep_to<NV>(sV, sT, sVM, m.ops + m.tab.dg2fv[N0], nF, n0);
+    }
+    wave_sync();
+    // the small side's value (sSM): reconstructed with its ghost, or its mapped trace
+    if (ak) {
+      if (a0)
+        map2d_pq<NV>(sB, sT, sCG, kp >= 0 ? m.ops + m.tab.mortar_fv_interp[kp] : nullptr,
+                     kq >= 0 ? m.ops + m.tab.mortar_fv_interp[kq] : nullptr, nF);
+      else
+        for (int t = threadIdx.x; t < n2F; t += blockDim.x)
+          for (int v = 0; v < NV; ++v) sCG[v * GRID + t] = sVM[v * GRID + t];
+      wave_sync();
+      write_side<NV>(m.fvghost + (size_t)ek * fblk, sCG, sk, ok, true, nF, 1.0);
+      reconstruct_face<NV>(sS, sSI, sCG, m.gas, n2F, sSM);
+    } else {
+      map2d_sep_to<NV>(sS, sT, sSM, m.ops + m.tab.dg2fv[Nk], nF, nk);
+    }
+    map2d_sep_to<3>(sN, sT2, sNM, m.ops + m.tab.dg2fv[Nk], nF, nk);
+    wave_sync();
+    for (int t = threadIdx.x; t < n2F; t += blockDim.x) {
+      double uL[NV], uR[NV], F[NV];
+      for (int v = 0; v < NV; ++v) {
+        uL[v] = sVM[v * GRID + t];
+        uR[v] = sSM[v * GRID + t];
+      }
+      riemann<NV>(prm.face_flux_fv, prm.volume_flux, uL, uR, h2 * sNM[t], h2 * sNM[GRID + t],
+                  h2 * sNM[2 * GRID + t], m.gas, F);
+      for (int v = 0; v < NV; ++v) sF[v * GRID + t] = F[v];
+    }
+    wave_sync();
+    if (ak)
+      write_side<NV>(m.fvside + (size_t)ek * fblk, sF, sk, ok, true, nF, -1.0);
+    else
+      map2d_sep_side<NV>(bk, sF, sT, m.ops + m.tab.fv2dg[Nk], nk, nF, sk, ok, true, -1.0 / h2);
+    wave_sync();
+    if (a0) {
+      map2d_pq<NV>(sF, sT, sT2, kp >= 0 ? m.ops + m.tab.mortar_fv_proj[kp] : nullptr,
+                   kq >= 0 ? m.ops + m.tab.mortar_fv_proj[kq] : nullptr, nF);
+      wave_sync();
+      for (int t = threadIdx.x; t < n2F; t += blockDim.x)
+        for (int v = 0; v < NV; ++v) sA[v * GRID + t] += sT2[v * GRID + t];
+    } else {
+      map2d_sep_to<NV>(sF, sT, sT2, m.ops + m.tab.fv2dg[N0], n0, nF);
+      wave_sync();
+      map2d_pq<NV>(sT2, sT, sV, kp >= 0 ? m.ops + m.tab.mortar_proj[N0][kp] : nullptr,
+                   kq >= 0 ? m.ops + m.tab.mortar_proj[N0][kq] : nullptr, n0);
+      wave_sync();
+      for (int t = threadIdx.x; t < n0 * n0; t += blockDim.x)
+        for (int v = 0; v < NV; ++v) sA[v * GRID + t] += sV[v * GRID + t] / h2;
+    }
+    wave_sync();
+  }
+  if (a0)
+    write_side<NV>(m.fvside + (size_t)e0 * fblk, sA, s0, 0, false, nF, 1.0);
+  else
+    write_side<NV>(m.fside + m.side_off[e0], sA, s0, 0, false, n0, 1.0);
+}
+
 }  // namespace
 
 template <int NV>
@@ -1540,6 +1796,16 @@ hipError_t launch_lift_faces(const MeshView& m, const double* u, hipStream_t s) 
 
 hipError_t launch_visc_faces(const MeshView& m, const double* u, hipStream_t s) {
   return m.nvar == 5 ? launch_visc_faces_t<5, false>(m, u, s) : launch_visc_faces_t<6, false>(m, u, s);
+}
+
+hipError_t launch_mortars_fv_stored(const MeshView& m, const ParamsDev& p, const double* u, const double* ufv,
+                                   const double* fv, hipStream_t s) {
+  if (m.n_mortar == 0) return hipSuccess;
+  if (m.nvar == 5)
+    hipLaunchKernelGGL((mortar_fvs_kernel<5>), dim3(m.n_mortar), dim3(FACE_THREADS), 0, s, m, p, u, ufv, fv);
+  else
+    hipLaunchKernelGGL((mortar_fvs_kernel<6>), dim3(m.n_mortar), dim3(FACE_THREADS), 0, s, m, p, u, ufv, fv);
+  return hipGetLastError();
 }
 
 hipError_t launch_mortars_vjp(const MeshView& m, const ParamsDev& p, const double* u, hipStream_t s) {

@@ -725,6 +725,7 @@ void enqueue_rhs_fvs(const dgfv_mesh* m, const ParamsDev& p, double* u, double* 
       {
         Timed tf(m, DGFV_KERNEL_FV_FACE, ss);
         hip_check(launch_face_fv_stored(v, p, u, ufv, fv, ss), "FV-stored face launch");
+        hip_check(launch_mortars_fv_stored(v, p, u, ufv, fv, ss), "FV-stored mortar launch");
       }
       Timed tr(m, DGFV_KERNEL_FV_RESIDUAL, ss);
       hip_check(launch_fv_stored(v, p, ufv, kfv, utfv, stage, dt, A, B, ss), "FV-stored element launch");
@@ -1572,7 +1573,6 @@ dgfv_status dg_rhs_fv(const dgfv_mesh* m, const dgfv_params* prm, const double* 
   if (u == ut || ufv == utfv) return fail(DGFV_ERR_ARG, "inputs and outputs must not overlap");
   if (dgfv_status st = check_params(m, prm)) return st;
   if (m->viscous) return fail(DGFV_ERR_UNSUPPORTED, "FV-stored elements with viscous terms are not built");
-  if (m->n_mortar > 0) return fail(DGFV_ERR_UNSUPPORTED, "FV-stored elements on meshes with mortars are not built");
   hipStream_t s = (hipStream_t)stream;
   if (!m->fvghost && capturing(s)) return fail(DGFV_ERR_ARG, "the first call with FV-stored elements allocates: not under capture");
   return guarded(m, s, [&] {
@@ -1594,7 +1594,6 @@ dgfv_status dg_rk_stage_fv(const dgfv_mesh* m, const dgfv_params* prm, int stage
   if (u == k || ufv == kfv) return fail(DGFV_ERR_ARG, "states and registers must not overlap");
   if (dgfv_status st = check_params(m, prm)) return st;
   if (m->viscous) return fail(DGFV_ERR_UNSUPPORTED, "FV-stored elements with viscous terms are not built");
-  if (m->n_mortar > 0) return fail(DGFV_ERR_UNSUPPORTED, "FV-stored elements on meshes with mortars are not built");
   hipStream_t s = (hipStream_t)stream;
   if (!m->fvghost && capturing(s)) return fail(DGFV_ERR_ARG, "the first call with FV-stored elements allocates: not under capture");
   return guarded(m, s, [&] {
@@ -1614,7 +1613,6 @@ dgfv_status dg_rk_step_fv(const dgfv_mesh* m, const dgfv_params* prm, double dt,
   if (u == k || ufv == kfv) return fail(DGFV_ERR_ARG, "states and registers must not overlap");
   if (dgfv_status st = check_params(m, prm)) return st;
   if (m->viscous) return fail(DGFV_ERR_UNSUPPORTED, "FV-stored elements with viscous terms are not built");
-  if (m->n_mortar > 0) return fail(DGFV_ERR_UNSUPPORTED, "FV-stored elements on meshes with mortars are not built");
   hipStream_t s = (hipStream_t)stream;
   if (!m->fvghost && capturing(s)) return fail(DGFV_ERR_ARG, "the first call with FV-stored elements allocates: not under capture");
   return guarded(m, s, [&] {

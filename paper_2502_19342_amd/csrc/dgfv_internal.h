@@ -270,6 +270,11 @@ hipError_t launch_faces_vjp(const MeshView& m, const ParamsDev& p, const double*
 // V^{FV->DG} / h^2, m.fside (DG sides); the ghost layers into m.fvghost.
 hipError_t launch_face_fv_stored(const MeshView& m, const ParamsDev& p, const double* u, const double* ufv,
                                  const double* fv, hipStream_t s);
+// The mortars of a mesh with FV-stored elements: the DG mortar flux where a
+// half has no FV-stored side, else the FV variant with the reconstruction
+// (m.fvside, m.fside, m.fvghost).
+hipError_t launch_mortars_fv_stored(const MeshView& m, const ParamsDev& p, const double* u, const double* ufv,
+                                    const double* fv, hipStream_t s);
 // Rates of the FV elements' means: stage 0 writes utfv = R; stage s updates
 // kfv <- A kfv + dt R, ufv <- ufv + B kfv.
 hipError_t launch_fv_stored(const MeshView& m, const ParamsDev& p, double* ufv, double* kfv, double* utfv,

@@ -376,3 +376,27 @@ def test_cpu_build_mortar_vjp(refine, degree, scramble, amp, flux):
     out = cpu_emu.run(wl, c.u.numpy(), ["vjp"], w=ws.numpy())
     for b in range(2):
         assert rel_err(torch.as_tensor(out["vjp"][b]), _oracle_vjp(c, ws[b])) <= 1e-12
+
+
+@pytest.mark.parametrize("refine,degree,scramble,amp,n_fv", [("y", (4, 3), 7, 0.05, 8), ("yz", (3, 2), 5, 0.0, 5)])
+def test_cpu_build_fv_stored_mortars(refine, degree, scramble, amp, n_fv):
+    # FV-stored elements on both sides of mortars: the rates against the oracle
+    from oracle import native_fv, problem
+    mesh = W.mortar_mesh(4, refine, degree, scramble_seed=scramble, amp=amp)
+    wl = W.Workload("mortar", mesh, 5, W.density_wave, W.VOL_RANOCHA, W.RIEMANN_ROE_HH, W.RIEMANN_LLF,
+                    n_fv=n_fv, metric_degree=2 if amp else 1)
+    c = _case(wl, smooth_state(91), noise=1e-3, seed=18)
+    K = c.mesh.K
+    rng = np.random.default_rng(scramble)
+    flag = rng.random(K) < 0.4
+    ufv = torch.zeros(K, 5, n_fv, n_fv, n_fv, dtype=T)
+    fvel = np.nonzero(flag)[0]
+    ufv[torch.as_tensor(fvel)] = native_fv.dg_to_fv(c.mesh, c.u, fvel)
+    ufv = ufv * (1.0 + 2e-2 * torch.as_tensor(rng.standard_normal(tuple(ufv.shape))))
+    R, Rfv = native_fv.NativeRhs(c.mesh, c.gas, problem.params_of(wl))(c.u, ufv, flag)
+    out = cpu_emu.run(wl, c.u.numpy(), ["rhs_fv"], ufv=ufv.reshape(K, 5, -1).numpy(), fv=flag.astype(np.float64))
+    dg = torch.as_tensor(np.repeat(~flag, [int(c.mesh.offset[e + 1] - c.mesh.offset[e]) for e in range(K)]))
+    assert rel_err(torch.as_tensor(out["rhs_fv_dg"])[:, dg], R[:, dg]) <= 1e-11
+    sel = torch.as_tensor(flag)
+    got_fv = torch.as_tensor(out["rhs_fv_fv"]).reshape(K, 5, -1)[sel].transpose(0, 1).reshape(5, -1)
+    assert rel_err(got_fv, Rfv[sel].transpose(0, 1).reshape(5, -1)) <= 1e-11

@@ -4,8 +4,8 @@ Mortar meshes of types 1/2 (refinement in y) and 3 (in y and z), scrambled
 element frames, degree jumps across the mortars, curved watertight elements,
 one and two species, pure DG and blended (the FV variants), with and without
 the viscous terms: the RHS, the lifted gradient, free-stream preservation,
-RK steps under graph replay, the adjoint (pure DG, one degree), and the calls
-that reject mortar meshes.
+RK steps under graph replay, FV-stored elements at the mortars, the adjoint
+(pure DG, one degree), and the calls that reject mortar meshes.
 """
 import dataclasses
 
@@ -78,9 +78,6 @@ def test_mortar_unsupported_calls():
     c = Case(_wl("y", 3, None, 0.0), prim=smooth_state(61), noise=1e-3, seed=11)
     u = c.gpu(c.u)
     K = c.mesh.K
-    with pytest.raises(dgfv.DgfvError):
-        dgfv.rhs_fv(c.gmesh, c.params, u, torch.zeros(K, 5, 8 ** 3, dtype=T, device="cuda"),
-                    torch.zeros(K, dtype=T, device="cuda"))
     with pytest.raises(dgfv.DgfvError):
         c.gmesh.face_fusion(True)
     with pytest.raises(dgfv.DgfvError):                 # the adjoint: pure DG only
@@ -182,3 +179,65 @@ def test_mortar_vjp_on_gpu(refine, degree, scramble, amp, n_var):
     err = rel_err(g.cpu(), g_ref)
     print(f"[mortar] vjp rel err {err:.3e}", flush=True)
     assert err <= 1e-12
+
+
+def _fvs_case(refine, degree, scramble, amp, n_fv, seed):
+    from oracle import native_fv
+    wl = dataclasses.replace(_wl(refine, degree, scramble, amp), n_fv=n_fv)
+    c = Case(wl, prim=smooth_state(91), noise=1e-3, seed=seed)
+    K = c.mesh.K
+    rng = np.random.default_rng(seed)
+    flag = rng.random(K) < 0.4
+    ufv = torch.zeros(K, 5, n_fv, n_fv, n_fv, dtype=T)
+    fvel = np.nonzero(flag)[0]
+    ufv[torch.as_tensor(fvel)] = native_fv.dg_to_fv(c.mesh, c.u, fvel)
+    ufv = ufv * (1.0 + 2e-2 * torch.as_tensor(rng.standard_normal(tuple(ufv.shape))))
+    dg = torch.as_tensor(np.repeat(~flag, [int(c.mesh.offset[e + 1] - c.mesh.offset[e]) for e in range(K)]))
+    return c, flag, ufv, dg
+
+
+@pytest.mark.parametrize("refine,degree,scramble,amp,n_fv", [("y", (4, 3), 7, 0.05, 8), ("yz", (3, 2), 5, 0.0, 5),
+                                                             ("yz", (7, 6), 11, 0.05, 8)])
+def test_mortar_fv_stored_rhs_on_gpu(refine, degree, scramble, amp, n_fv):
+    announce(f"mortar FV-stored rhs {refine} {degree} {scramble} {amp} {n_fv}")
+    from oracle import native_fv, problem
+    from paper_2502_19342_amd import dgfv
+    c, flag, ufv, dg = _fvs_case(refine, degree, scramble, amp, n_fv, 19)
+    K = c.mesh.K
+    R, Rfv = native_fv.NativeRhs(c.mesh, c.gas, problem.params_of(c.wl))(c.u, ufv, flag)
+    r, rf = dgfv.rhs_fv(c.gmesh, c.params, c.gpu(c.u), c.gpu(ufv.reshape(K, 5, -1)),
+                        c.gpu(torch.as_tensor(flag, dtype=T)))
+    torch.cuda.synchronize()
+    sel = torch.as_tensor(flag)
+    e1 = rel_err(r.cpu()[:, dg], R[:, dg])
+    e2 = rel_err(rf.cpu().reshape(K, 5, -1)[sel].transpose(0, 1).reshape(5, -1),
+                 Rfv[sel].transpose(0, 1).reshape(5, -1))
+    print(f"[mortar] FV-stored rhs rel err DG {e1:.3e}, FV {e2:.3e}", flush=True)
+    assert e1 <= 1e-11 and e2 <= 1e-11
+
+
+def test_mortar_fv_stored_rk_steps():
+    announce("mortar FV-stored 10 RK steps")
+    from oracle import native_fv, problem
+    from paper_2502_19342_amd import dgfv
+    c, flag, ufv, dg = _fvs_case("yz", (3, 4), 15, 0.05, 8, 20)
+    K = c.mesh.K
+    native = native_fv.NativeRhs(c.mesh, c.gas, problem.params_of(c.wl))
+    dt = 0.2 * lsrk.timestep(c.mesh, c.gas, c.u, 0.5, torch.as_tensor(flag, dtype=T))
+    fv = c.gpu(torch.as_tensor(flag, dtype=T))
+    ug, ufg = c.gpu(c.u), c.gpu(ufv.reshape(K, 5, -1))
+    k, kf = torch.zeros_like(ug), torch.zeros_like(ufg)
+    uo, ufo = c.u.clone(), ufv.clone()
+    for _ in range(10):
+        dgfv.rk_step_fv(c.gmesh, c.params, dt, ug, k, ufg, kf, fv)
+        ko, kfo = torch.zeros_like(uo), torch.zeros_like(ufo)
+        for s in range(5):
+            uo, ufo, ko, kfo = native_fv.stage(lambda a, b: native(a, b, flag), uo, ufo, ko, kfo, s, dt,
+                                               lsrk.A_F64, lsrk.B_F64)
+    torch.cuda.synchronize()
+    sel = torch.as_tensor(flag)
+    e1 = rel_err(ug.cpu()[:, dg], uo[:, dg])
+    e2 = rel_err(ufg.cpu().reshape(K, 5, -1)[sel].transpose(0, 1).reshape(5, -1),
+                 ufo[sel].transpose(0, 1).reshape(5, -1))
+    print(f"[mortar] FV-stored 10 steps: DG {e1:.3e}, FV {e2:.3e}", flush=True)
+    assert e1 <= 1e-10 and e2 <= 1e-10
