@@ -87,8 +87,9 @@ enum { DGFV_RIEMANN_ROE_HH = 0, /* Roe with the Harten-Hyman entropy fix, 1 spec
  * where either side is blended (see dgfv_mesh_create).  Meshes with
  * mortars need metric_degree >= 1 (>= 2 on curved elements, where the face
  * normals of a small side must be the restriction of the big side's); they
- * take no FV-stored elements or face fusion (DGFV_ERR_UNSUPPORTED); the
- * adjoint takes them pure DG with one degree across each mortar.
+ * take no face fusion (DGFV_ERR_UNSUPPORTED); the adjoint takes them pure
+ * DG with one degree across each mortar.  FV-stored elements at mortars (see
+ * dg_rhs_fv) take the FV variants with the reconstruction.
  * Viscous terms at mortars (see dgfv_set_transport) go through the same
  * virtual small sides.
  * Metrics Ja^d are formed in the conservative curl form (Section 3.1.1):
@@ -268,7 +269,14 @@ dgfv_status dgfv_set_launch_mode(dgfv_mesh* mesh, int mode);
  * (fig. h_coupling); a DG side's own value on such a face is that mapped
  * trace, and it receives the flux through V^{FV->DG} / h^2.  Faces between two
  * DG elements, and the DG elements, are as in dg_rhs with alpha = 0; the
- * nodal slots of FV elements are neither read nor written.
+ * nodal slots of FV elements are neither read nor written.  At a mortar
+ * (Section 3.2.3) a half with an FV side takes the flux on the small side's
+ * sub-face grid: an FV small side's ghost is the big side's data on its half
+ * (boundary means through the overlap map, or the mapped half trace of a DG
+ * big side), an FV big side's ghost on each of its sub-faces the mean of the
+ * small sides' boundary data over it, and its reconstructed values reach the
+ * halves by overlap; the small side takes the flux reversed, the big side the
+ * sub-face fluxes summed by overlap (FV) or M_k0 of their V^{FV->DG} / h^2 (DG).
  *   dg_rhs_fv:      ut_d = R(u) on DG elements, utfv_d = R(ufv) on FV elements;
  *   dg_rk_stage_fv: stage s of dg_rk_stage on (u, k) and on (ufv, kfv);
  *   dg_rk_step_fv:  the five stages in turn (between them the DG faces read the
