@@ -241,3 +241,25 @@ def test_mortar_fv_stored_rk_steps():
                  ufo[sel].transpose(0, 1).reshape(5, -1))
     print(f"[mortar] FV-stored 10 steps: DG {e1:.3e}, FV {e2:.3e}", flush=True)
     assert e1 <= 1e-10 and e2 <= 1e-10
+
+
+@pytest.mark.parametrize("stage", [1, 3, 5])
+def test_mortar_rk_stage_vjp_on_gpu(stage):
+    # the reverse of one RK stage through the mortars: autograd through the oracle's stage
+    announce(f"mortar rk stage vjp s={stage}")
+    from paper_2502_19342_amd import dgfv
+    c = Case(_wl("yz", 3, 13, 0.05), prim=smooth_state(93), noise=1e-3, seed=21)
+    dt = lsrk.timestep(c.mesh, c.gas, c.u, 0.5)
+    cot = lambda s: torch.as_tensor(W.cotangents(s, tuple(c.u.shape)), dtype=T)
+    k0, ubar, kbar = 0.1 * cot(94), cot(95), cot(96)
+    uu = c.u.clone().requires_grad_(True)
+    kk = k0.clone().requires_grad_(True)
+    ks = lsrk.A_F64[stage - 1] * kk + dt * c.f(uu, c.alpha)
+    us = uu + lsrk.B_F64[stage - 1] * ks
+    gu, gk = torch.autograd.grad((us * ubar).sum() + (ks * kbar).sum(), (uu, kk))
+    ub, kb = c.gpu(ubar), c.gpu(kbar)
+    dgfv.rk_stage_vjp(c.gmesh, c.params, stage, dt, c.gpu(c.u), ub, kb, None)
+    torch.cuda.synchronize()
+    assert rel_err(ub.cpu(), gu) <= 1e-12
+    if stage > 1:
+        assert rel_err(kb.cpu(), gk) <= 1e-14
