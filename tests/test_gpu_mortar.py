@@ -263,3 +263,27 @@ def test_mortar_rk_stage_vjp_on_gpu(stage):
     assert rel_err(ub.cpu(), gu) <= 1e-12
     if stage > 1:
         assert rel_err(kb.cpu(), gk) <= 1e-14
+
+
+def test_m3_full_size_rate_is_the_exact_divergence():
+    # the M3 workload at full size (34,560 elements at N = 7, 1,152 type-3 mortars), pure DG:
+    # the density wave is an exact solution, so the rate at every node is the exact
+    # -div F = rho_t (1, 1, 1, 1, 3/2) with rho_t = -3 (0.2 pi) cos 2 pi (x + y + z);
+    # spectral accuracy leaves ~4e-11 of its scale, at the nodes next to the mortars too
+    announce("M3 full size, exact rate")
+    from paper_2502_19342_amd import dgfv
+    wl = W.make_workload("M3")
+    gm = dgfv.Mesh.from_workload(wl)
+    prm = dgfv.params_of(wl)
+    xyz = torch.as_tensor(gm.node_coords(), device="cuda")
+    w = torch.as_tensor(np.asarray(wl.prim(gm.node_coords().T)), device="cuda").contiguous()
+    u = dgfv.prim_to_cons(gm, w)
+    r = dgfv.rhs(gm, prm, u)
+    rho_t = -3.0 * 0.2 * np.pi * torch.cos(2 * np.pi * xyz.sum(0))
+    want = torch.stack([rho_t, rho_t, rho_t, rho_t, 1.5 * rho_t])
+    err = float((r - want).abs().max() / want.abs().max())
+    big = torch.as_tensor(np.unique(np.concatenate([np.arange(gm.elem_offset[e], gm.elem_offset[e + 1])
+                                                    for e in wl.mesh.mortars[:, 0]])), device="cuda")
+    err_m = float((r[:, big] - want[:, big]).abs().max() / want.abs().max())
+    print(f"[mortar] M3 full size: rate rel err {err:.3e} (big sides of mortars {err_m:.3e})", flush=True)
+    assert err <= 1e-9 and err_m <= 1e-9
