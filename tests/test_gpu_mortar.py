@@ -287,3 +287,45 @@ def test_m3_full_size_rate_is_the_exact_divergence():
     err_m = float((r[:, big] - want[:, big]).abs().max() / want.abs().max())
     print(f"[mortar] M3 full size: rate rel err {err:.3e} (big sides of mortars {err_m:.3e})", flush=True)
     assert err <= 1e-9 and err_m <= 1e-9
+
+
+def test_m3v_full_size_viscous_rate():
+    # M3 with the viscous terms at full size: the viscous rate (with minus without
+    # the transport coefficients) at 4096 sampled nodes and at every node of the
+    # mortars' big sides against the exact viscous rate of the density wave (the
+    # heat flux of its temperature field; autograd through the oracle's flux on the
+    # analytic fields)
+    announce("M3V full size, exact viscous rate")
+    from oracle import problem, viscous
+    from paper_2502_19342_amd import dgfv
+    wl = W.make_workload("M3V")
+    gm = dgfv.Mesh.from_workload(wl)
+    prm = dgfv.params_of(wl)
+    xyz = gm.node_coords()
+    w = torch.as_tensor(np.asarray(wl.prim(xyz.T)), device="cuda").contiguous()
+    u = dgfv.prim_to_cons(gm, w)
+    r_v = dgfv.rhs(gm, prm, u)
+    gm.transport(None)
+    r_c = dgfv.rhs(gm, prm, u)
+    torch.cuda.synchronize()
+    big = np.unique(np.concatenate([np.arange(gm.elem_offset[e], gm.elem_offset[e + 1])
+                                    for e in wl.mesh.mortars[:, 0]]))
+    idx = np.unique(np.concatenate([np.random.default_rng(8).choice(gm.n_node, 4096, replace=False),
+                                    big[np.random.default_rng(9).choice(len(big), 4096, replace=False)]]))
+    got = (r_v - r_c)[:, torch.as_tensor(idx, device="cuda")].cpu()
+    gas = problem.gas_of(wl)
+    xt = torch.as_tensor(xyz[:, idx].T, dtype=T).requires_grad_(True)
+    rho = 1.0 + 0.1 * torch.sin(2 * np.pi * xt.sum(1))
+    one = torch.ones_like(rho)
+    from oracle.physics import prim_to_cons
+    uu = prim_to_cons(torch.stack([rho, one, one, one, one]), gas)
+    g = torch.stack([torch.stack([torch.autograd.grad(uu[c].sum(), xt, create_graph=True)[0][:, d]
+                                  for c in range(5)]) for d in range(3)])
+    F = viscous.viscous_flux(uu, g, gas, problem.transport_of(wl))
+    want = torch.zeros(5, len(idx), dtype=T)
+    for c in range(1, 5):
+        for d in range(3):
+            want[c] -= torch.autograd.grad(F[d, c].sum(), xt, retain_graph=True)[0][:, d].detach()
+    err = float((got - want).abs().max() / want.abs().max())
+    print(f"[mortar] M3V full size: viscous rate rel err {err:.3e}", flush=True)
+    assert err <= 1e-8                      # measured 8.7e-10
