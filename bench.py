@@ -586,9 +586,10 @@ def main():
         "kernel_ms_per_stage": {kname: v[0] / max(1, v[1]) for kname, v in kt.items()},
         "kernel_ms_source": "live events over the timed steps" if live else "profiled steps after the timed region",
         "kernel_ms_note": "phases in order: face, element; the face phase runs the DG face classes beside "
-                          "the FV chain (fv_means, fv_face, fv_residual in order; with --fv-stored fv_face "
-                          "then fv_residual), so those lie inside face (one after another with --launch "
-                          "serial); on a mesh with mortars, and in graph replays of a mesh with several degrees, "
+                          "the FV chain (fv_means, fv_face, fv_residual in order), so those lie inside face "
+                          "(one after another with --launch serial); with --fv-stored fv_face (FV-stored "
+                          "faces and mortars) lies inside face and fv_residual (the FV elements' rates) "
+                          "follows it; on a mesh with mortars, and in graph replays of a mesh with several degrees, "
                           "fv_means comes before the face phase, the FV faces (and the mortars) are branches "
                           "of it, and fv_residual follows it",
         "fv_stored": fv_stored_roofline(wl, alpha_h, kt) if args.fv_stored else None,
