@@ -1009,6 +1009,63 @@ __device__ void map2d_pq(const double* src, double* T, double* dst, const double
   }
 }
 
+// One small side's DG mortar flux (steps 2-5 of Section 3.2.3, both sides DG):
+// sV holds the big side's data on the half (degree N0, step 1), sS and sN the
+// small side's trace and reversed normal on the half's grid (degree Nk).  The
+// small side's share goes to m.fside (bk, side sk, orientation ok); the big
+// side's, mapped with M_k0, is added to sA.  sVM, sSM, sNM, sF, sT and sT2 are
+// scratch; sV is overwritten.
+template <int NV>
+__device__ void mortar_dg_half(const MeshView& m, const ParamsDev& prm, int N0, int Nk, double* bk, int sk, int ok,
+                               int kp, int kq, double* sV, double* sS, double* sN, double* sVM, double* sSM,
+                               double* sNM, double* sF, double* sT, double* sT2, double* sA) {
+  const int n0 = N0 + 1, nk = Nk + 1;
+  const int M = N0 > Nk ? N0 : Nk, nM = M + 1;
+  const double* VV = sV;
+  const double* SS = sS;
+  const double* NN = sN;
+  if (N0 < M) {
+    map2d_sep_to<NV>(sV, sT, sVM, m.ops + m.tab.interp[N0][M], nM, n0);
+    VV = sVM;
+    wave_sync();
+  }
+  if (Nk < M) {
+    map2d_sep_to<NV>(sS, sT, sSM, m.ops + m.tab.interp[Nk][M], nM, nk);
+    wave_sync();
+    map2d_sep_to<3>(sN, sT, sNM, m.ops + m.tab.interp[Nk][M], nM, nk);
+    SS = sSM;
+    NN = sNM;
+    wave_sync();
+  }
+  for (int t = threadIdx.x; t < nM * nM; t += blockDim.x) {
+    double uL[NV], uR[NV], F[NV];
+    for (int v = 0; v < NV; ++v) {
+      uL[v] = VV[v * GRID + t];
+      uR[v] = SS[v * GRID + t];
+    }
+    riemann<NV>(prm.face_flux_dg, prm.volume_flux, uL, uR, NN[t], NN[GRID + t], NN[2 * GRID + t], m.gas, F);
+    for (int v = 0; v < NV; ++v) sF[v * GRID + t] = F[v];
+  }
+  wave_sync();
+  if (Nk < M)
+    map2d_sep_side<NV>(bk, sF, sT, m.ops + m.tab.project[M][Nk], nk, nM, sk, ok, true, -1.0);
+  else
+    write_side<NV>(bk, sF, sk, ok, true, nk, -1.0);
+  wave_sync();
+  const double* FB = sF;
+  if (N0 < M) {
+    map2d_sep_to<NV>(sF, sT, sT2, m.ops + m.tab.project[M][N0], n0, nM);
+    FB = sT2;
+    wave_sync();
+  }
+  map2d_pq<NV>(FB, sT, sV, kp >= 0 ? m.ops + m.tab.mortar_proj[N0][kp] : nullptr,
+               kq >= 0 ? m.ops + m.tab.mortar_proj[N0][kq] : nullptr, n0);
+  wave_sync();
+  for (int t = threadIdx.x; t < n0 * n0; t += blockDim.x)
+    for (int v = 0; v < NV; ++v) sA[v * GRID + t] += sV[v * GRID + t];
+  wave_sync();
+}
+
 // Non-conforming faces (Section 3.2.3), one mortar per one-wavefront
 // workgroup.  For each small side k, when both sides are pure DG (the five
 // steps): (1) the big side's trace interpolated to half (quarter) k with M_0k
@@ -1130,50 +1187,7 @@ face_mortar_kernel(MeshView m, ParamsDev prm, const double* __restrict__ u, cons
       wave_sync();
       continue;
     }
-    const int M = N0 > Nk ? N0 : Nk, nM = M + 1;
-    const double* VV = sV;
-    const double* SS = sS;
-    const double* NN = sN;
-    if (N0 < M) {
-      map2d_sep_to<NV>(sV, sT, sVM, m.ops + m.tab.interp[N0][M], nM, n0);
-      VV = sVM;
-      wave_sync();
-    }
-    if (Nk < M) {
-      map2d_sep_to<NV>(sS, sT, sSM, m.ops + m.tab.interp[Nk][M], nM, nk);
-      wave_sync();
-      map2d_sep_to<3>(sN, sT, sNM, m.ops + m.tab.interp[Nk][M], nM, nk);
-      SS = sSM;
-      NN = sNM;
-      wave_sync();
-    }
-    for (int t = threadIdx.x; t < nM * nM; t += blockDim.x) {
-      double uL[NV], uR[NV], F[NV];
-      for (int v = 0; v < NV; ++v) {
-        uL[v] = VV[v * GRID + t];
-        uR[v] = SS[v * GRID + t];
-      }
-      riemann<NV>(prm.face_flux_dg, prm.volume_flux, uL, uR, NN[t], NN[GRID + t], NN[2 * GRID + t], m.gas, F);
-      for (int v = 0; v < NV; ++v) sF[v * GRID + t] = F[v];
-    }
-    wave_sync();
-    if (Nk < M)
-      map2d_sep_side<NV>(bk, sF, sT, m.ops + m.tab.project[M][Nk], nk, nM, sk, ok, true, -1.0);
-    else
-      write_side<NV>(bk, sF, sk, ok, true, nk, -1.0);
-    wave_sync();
-    const double* FB = sF;
-    if (N0 < M) {
-      map2d_sep_to<NV>(sF, sT, sT2, m.ops + m.tab.project[M][N0], n0, nM);
-      FB = sT2;
-      wave_sync();
-    }
-    map2d_pq<NV>(FB, sT, sV, kp >= 0 ? m.ops + m.tab.mortar_proj[N0][kp] : nullptr,
-                 kq >= 0 ? m.ops + m.tab.mortar_proj[N0][kq] : nullptr, n0);
-    wave_sync();
-    for (int t = threadIdx.x; t < n0 * n0; t += blockDim.x)
-      for (int v = 0; v < NV; ++v) sA[v * GRID + t] += sV[v * GRID + t];
-    wave_sync();
+    mortar_dg_half<NV>(m, prm, N0, Nk, bk, sk, ok, kp, kq, sV, sS, sN, sVM, sSM, sNM, sF, sT, sT2, sA);
   }
   write_side<NV>(m.fside + m.side_off[e0], sA, s0, 0, false, n0, 1.0);
   if (a0) write_side<NV>(m.fvside + (size_t)e0 * 6 * NV * n2F, sAF, s0, 0, false, nF, 1.0);
@@ -1573,52 +1587,8 @@ mortar_fvs_kernel(MeshView m, ParamsDev prm, const double* __restrict__ u, const
     for (int t = threadIdx.x; t < nk * nk; t += blockDim.x)
       for (int c = 0; c < 3; ++c) sN[c * GRID + t] *= rev;
     wave_sync();
-    if (!a0 && !ak) {
-      // the DG mortar flux on the common degree
-      const int M = N0 > Nk ? N0 : Nk, nM = M + 1;
-      const double* VV = sV;
-      const double* SS = sS;
-      const double* NN = sN;
-      if (N0 < M) {
-        map2d_sep_to<NV>(sV, sT, sVM, m.ops + m.tab.interp[N0][M], nM, n0);
-        VV = sVM;
-        wave_sync();
-      }
-      if (Nk < M) {
-        map2d_sep_to<NV>(sS, sT, sSM, m.ops + m.tab.interp[Nk][M], nM, nk);
-        wave_sync();
-        map2d_sep_to<3>(sN, sT, sNM, m.ops + m.tab.interp[Nk][M], nM, nk);
-        SS = sSM;
-        NN = sNM;
-        wave_sync();
-      }
-      for (int t = threadIdx.x; t < nM * nM; t += blockDim.x) {
-        double uL[NV], uR[NV], F[NV];
-        for (int v = 0; v < NV; ++v) {
-          uL[v] = VV[v * GRID + t];
-          uR[v] = SS[v * GRID + t];
-        }
-        riemann<NV>(prm.face_flux_dg, prm.volume_flux, uL, uR, NN[t], NN[GRID + t], NN[2 * GRID + t], m.gas, F);
-        for (int v = 0; v < NV; ++v) sF[v * GRID + t] = F[v];
-      }
-      wave_sync();
-      if (Nk < M)
-        map2d_sep_side<NV>(bk, sF, sT, m.ops + m.tab.project[M][Nk], nk, nM, sk, ok, true, -1.0);
-      else
-        write_side<NV>(bk, sF, sk, ok, true, nk, -1.0);
-      wave_sync();
-      const double* FB = sF;
-      if (N0 < M) {
-        map2d_sep_to<NV>(sF, sT, sT2, m.ops + m.tab.project[M][N0], n0, nM);
-        FB = sT2;
-        wave_sync();
-      }
-      map2d_pq<NV>(FB, sT, sV, kp >= 0 ? m.ops + m.tab.mortar_proj[N0][kp] : nullptr,
-                   kq >= 0 ? m.ops + m.tab.mortar_proj[N0][kq] : nullptr, n0);
-      wave_sync();
-      for (int t = threadIdx.x; t < n0 * n0; t += blockDim.x)
-        for (int v = 0; v < NV; ++v) sA[v * GRID + t] += sV[v * GRID + t];
-      wave_sync();
+    if (!a0 && !ak) {                     // the DG mortar flux on the common degree
+      mortar_dg_half<NV>(m, prm, N0, Nk, bk, sk, ok, kp, kq, sV, sS, sN, sVM, sSM, sNM, sF, sT, sT2, sA);
       continue;
     }
     // the FV variant on the small side's sub-face grid: the big side's value on the half (sVM)
