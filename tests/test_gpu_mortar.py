@@ -329,3 +329,30 @@ def test_m3v_full_size_viscous_rate():
     err = float((got - want).abs().max() / want.abs().max())
     print(f"[mortar] M3V full size: viscous rate rel err {err:.3e}", flush=True)
     assert err <= 1e-8                      # measured 8.7e-10
+
+
+def test_mortar_p_adaptation():
+    # p-adaptation on a curved mortar mesh: the degree decision from I(rho), the mesh of
+    # the new degrees (degree jumps across the mortars), the state transfer and the rate
+    # on the new mesh, each against the oracle doing the same
+    announce("mortar p-adaptation")
+    from oracle import p_adapt, problem
+    from paper_2502_19342_amd import dgfv
+    c = Case(_wl("yz", 4, 23, 0.05), prim=smooth_state(97), noise=1e-3, seed=22)
+    from oracle.indicator import indicator
+    I, _ = indicator(c.mesh, c.gas, c.u, 0.0, 1.0, ind_vars=2)               # I(rho), the p-adaptation indicator
+    t_ref, t_coa = float(np.quantile(I.numpy(), 0.3)), float(np.quantile(I.numpy(), 0.7))
+    want_deg = p_adapt.degrees(c.mesh, c.gas, c.u, t_ref, t_coa, 2, 5)
+    ug = c.gpu(c.u)
+    got_deg = dgfv.p_degrees(c.gmesh, c.params, ug, t_ref, t_coa, 2, 5)
+    assert np.array_equal(np.asarray(got_deg), np.asarray(want_deg))
+    assert len(set(np.asarray(got_deg).tolist())) > 1
+    new = c.gmesh.redegree(np.asarray(got_deg))
+    u2 = dgfv.transfer_degree(c.gmesh, new, ug)
+    wl2 = dataclasses.replace(c.wl, mesh=dataclasses.replace(c.wl.mesh, degree=np.asarray(got_deg)))
+    om2, gas2, f2 = problem.build(wl2)
+    uo2 = p_adapt.transfer(c.mesh, om2, c.u)
+    assert rel_err(u2.cpu(), uo2) <= 1e-13
+    r2 = dgfv.rhs(new, c.params, u2)
+    torch.cuda.synchronize()
+    assert rel_err(r2.cpu(), f2(uo2, torch.zeros(om2.K, dtype=T))) <= 1e-12
