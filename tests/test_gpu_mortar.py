@@ -218,11 +218,13 @@ def test_mortar_fv_stored_rhs_on_gpu(refine, degree, scramble, amp, n_fv, n_var)
     assert e1 <= 1e-12 and e2 <= 1e-12                # measured up to 6e-14
 
 
-def test_mortar_fv_stored_rk_steps():
-    announce("mortar FV-stored 10 RK steps")
+@pytest.mark.parametrize("graphs", [False, True])
+def test_mortar_fv_stored_rk_steps(graphs):
+    announce(f"mortar FV-stored 10 RK steps, graphs={graphs}")
     from oracle import native_fv, problem
     from paper_2502_19342_amd import dgfv
     c, flag, ufv, dg = _fvs_case("yz", (3, 4), 15, 0.05, 8, 20)
+    c.gmesh.graphs(graphs)
     K = c.mesh.K
     native = native_fv.NativeRhs(c.mesh, c.gas, problem.params_of(c.wl))
     dt = 0.2 * lsrk.timestep(c.mesh, c.gas, c.u, 0.5, torch.as_tensor(flag, dtype=T))
